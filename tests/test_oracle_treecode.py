@@ -1,0 +1,218 @@
+"""Pins of the oracle's direct sum (eq. N-body) and treecode (Algorithm 2).
+
+Direct sum: exact integer arithmetic on small-integer data, agreement with the
+Neumaier-compensated sum, subsets.  Treecode: exactness for polynomial
+kernels in Q_n (eq. separated_3D), theta = 0 and N <= N0 reduce to the direct
+sum, convergence in n and theta, power-of-two scaling, linearity,
+translation, and soundness of the shared batch MAC.
+"""
+import numpy as np
+import pytest
+
+from paper_1902_02250_amd import inputs
+
+
+def _int_data(n, seed, lo=-3, hi=4):
+    rng = np.random.default_rng(seed)
+    return (rng.integers(lo, hi, (3, n)).astype(np.float64),
+            rng.integers(-5, 6, (3, n)).astype(np.float64))
+
+
+def test_direct_poly_is_exact_on_integers(orc):
+    """Every partial sum is an integer below 2^53, so the FP64 direct sum
+    must equal arbitrary-precision integer arithmetic."""
+    pts, w = _int_data(60, 1)
+    out = orc.direct("poly", pts, pts, w, poly_p=3, poly_c=2.0)
+    P = pts.astype(int)
+    W = w.astype(int)
+    for i in range(60):
+        acc = [0, 0, 0]
+        for j in range(60):
+            v = (2 + sum(P[a, i] * P[a, j] for a in range(3))) ** 3
+            for c in range(3):
+                acc[c] += v * W[c, j]
+        assert out[:, i].tolist() == [float(a) for a in acc]
+
+
+@pytest.mark.parametrize("kernel", ["stokeslet", "rotlet"])
+def test_direct_plain_vs_compensated(orc, kernel):
+    pts, w, _ = inputs.workload("c1", n=3000)
+    a = orc.direct(kernel, pts, pts, w, eps=0.01)
+    b = orc.direct(kernel, pts, pts, w, eps=0.01, compensated=True)
+    assert orc.rel_l2(b, a) < 1e-14
+
+
+def test_direct_subset(orc):
+    pts, w, _ = inputs.workload("c1", n=2000)
+    idx = inputs.sample_indices(2000, 37, 5)
+    a = orc.direct("rotlet", pts, pts, w, eps=0.02)
+    b = orc.direct_subset("rotlet", pts, idx, pts, w, eps=0.02)
+    assert np.array_equal(a[:, idx], b)
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("theta", [0.5, 0.7, 1.0])
+def test_poly_kernel_exact(orc, mode, theta):
+    """P4: (c + x.y)^p with p <= n lies in Q_n in y, so the approximation is
+    exact and the treecode equals the direct sum."""
+    pts = inputs.points("uniform", 3000, 21)
+    w = inputs.weights(3000, 21)
+    d = orc.direct("poly", pts, pts, w, poly_p=4, poly_c=1.5)
+    t, npx, ndr = orc.treecode("poly", pts, pts, w, 0.0, 4, theta, 100, mac_mode=mode,
+                               poly_p=4, poly_c=1.5)
+    assert npx > 0
+    assert orc.rel_l2(d, t) < 1e-12
+    # degree below p is no longer exact
+    t3, _, _ = orc.treecode("poly", pts, pts, w, 0.0, 3, theta, 100, mac_mode=mode,
+                            poly_p=4, poly_c=1.5)
+    assert orc.rel_l2(d, t3) > 1e-8
+
+
+def test_poly_theta_zero_integer_bit_exact(orc):
+    """theta = 0 accepts only clusters of zero radius (all particles on one
+    point, where the approximation is exact); on integer data every partial
+    sum is exact, so the treecode equals the direct sum bit for bit."""
+    pts, w = _int_data(400, 2)
+    d = orc.direct("poly", pts, pts, w, poly_p=2, poly_c=1.0)
+    t, npx, ndr = orc.treecode("poly", pts, pts, w, 0.0, 2, 0.0, 30, poly_p=2, poly_c=1.0)
+    assert npx % 27 == 0 and ndr + npx // 27 <= 400 * 400
+    L = orc.lists(pts, 30, pts, 0.0, 1, 30)
+    T = orc.Tree(pts, 30)
+    assert np.all(T.radius[L["prox_ids"]] == 0.0)
+    assert np.array_equal(d, t)
+
+
+@pytest.mark.parametrize("kernel", ["stokeslet", "rotlet"])
+def test_theta_zero_and_single_leaf_equal_direct(orc, kernel):
+    """P5 and P6."""
+    pts, w, _ = inputs.workload("c1", n=2500)
+    d = orc.direct(kernel, pts, pts, w, eps=0.01)
+    t, npx, ndr = orc.treecode(kernel, pts, pts, w, 0.01, 4, 0.0, 100)
+    assert npx == 0 and ndr == 2500 * 2500
+    assert orc.rel_l2(d, t) < 1e-14
+    t, npx, ndr = orc.treecode(kernel, pts, pts, w, 0.01, 4, 0.9, 2500)
+    assert npx == 0
+    assert orc.rel_l2(d, t) < 1e-14
+
+
+@pytest.mark.parametrize("kernel", ["stokeslet", "rotlet"])
+def test_convergence(orc, kernel):
+    """P7: the error falls as n grows at fixed theta and as theta falls at
+    fixed n (Section 8.1)."""
+    pts, w, _ = inputs.workload("c1", n=6000)
+    d = orc.direct(kernel, pts, pts, w, eps=0.01)
+    errs = []
+    for n in (1, 3, 5, 7):
+        t, _, _ = orc.treecode(kernel, pts, pts, w, 0.01, n, 0.7, 200)
+        errs.append(orc.rel_l2(d, t))
+    assert all(b < a for a, b in zip(errs, errs[1:])), errs
+    assert errs[-1] < 1e-4
+    errs = []
+    for theta in (0.9, 0.7, 0.5):
+        t, _, _ = orc.treecode(kernel, pts, pts, w, 0.01, 4, theta, 200)
+        errs.append(orc.rel_l2(d, t))
+    assert all(b < a for a, b in zip(errs, errs[1:])), errs
+
+
+def test_power_of_two_scaling(orc):
+    """P10: scaling points and eps by 2^m leaves the tree and the lists
+    unchanged and scales the Stokeslet velocity by exactly 2^-m and the
+    rotlet u and w by 2^-2m and 2^-3m."""
+    pts, w, _ = inputs.workload("c1", n=3000)
+    for m in (-3, 5):
+        s = 2.0 ** m
+        T1, T2 = orc.Tree(pts, 200), orc.Tree(s * pts, 200)
+        assert np.array_equal(T1.perm, T2.perm) and np.array_equal(T1.child_first, T2.child_first)
+        L1 = orc.lists(pts, 200, pts, 0.7, 64, 64)
+        L2 = orc.lists(s * pts, 200, s * pts, 0.7, 64, 64)
+        for k in L1:
+            assert np.array_equal(L1[k], L2[k])
+        a, _, _ = orc.treecode("stokeslet", pts, pts, w, 0.01, 5, 0.7, 200)
+        b, _, _ = orc.treecode("stokeslet", s * pts, s * pts, w, 0.01 * s, 5, 0.7, 200)
+        assert np.array_equal(b, a / s)
+        a, _, _ = orc.treecode("rotlet", pts, pts, w, 0.01, 5, 0.7, 200, mac_mode=1)
+        b, _, _ = orc.treecode("rotlet", s * pts, s * pts, w, 0.01 * s, 5, 0.7, 200, mac_mode=1)
+        assert np.array_equal(b[:3], a[:3] / s ** 2)
+        assert np.array_equal(b[3:], a[3:] / s ** 3)
+
+
+def test_linearity(orc):
+    pts, f, _ = inputs.workload("c1", n=3000)
+    g = inputs.weights(3000, 77)
+    a, _, _ = orc.treecode("stokeslet", pts, pts, 0.5 * f + 2.0 * g, 0.01, 5, 0.7, 200)
+    b, _, _ = orc.treecode("stokeslet", pts, pts, f, 0.01, 5, 0.7, 200)
+    c, _, _ = orc.treecode("stokeslet", pts, pts, g, 0.01, 5, 0.7, 200)
+    assert orc.rel_l2(a, 0.5 * b + 2.0 * c) < 1e-13
+
+
+def test_translation(orc):
+    """P12: a shift by a power-of-two-friendly vector keeps the lists, and then
+    the velocities agree to rounding."""
+    pts, w, _ = inputs.workload("c1", n=3000)
+    shift = np.array([[0.25], [-0.5], [0.125]])
+    L1 = orc.lists(pts, 200, pts, 0.7, 64, 64)
+    L2 = orc.lists(pts + shift, 200, pts + shift, 0.7, 64, 64)
+    same = all(np.array_equal(L1[k], L2[k]) for k in L1)
+    a, _, _ = orc.treecode("stokeslet", pts, pts, w, 0.01, 5, 0.7, 200, mac_mode=1)
+    b, _, _ = orc.treecode("stokeslet", pts + shift, pts + shift, w, 0.01, 5, 0.7, 200, mac_mode=1)
+    if same:
+        assert orc.rel_l2(a, b) < 1e-12
+    else:
+        assert orc.rel_l2(a, b) < 1e-4
+
+
+def test_batch_mac_soundness_and_counts(orc):
+    """P13: every cluster accepted for a batch passes the per-target MAC for
+    each target of the batch; one target per batch reproduces mode 0."""
+    src = inputs.points("mixture", 4000, 8)
+    tgt = inputs.points("uniform", 1500, 9)
+    w = inputs.weights(4000, 8)
+    theta = 0.7
+    L = orc.lists(src, 100, tgt, theta, 64, 64)
+    T = orc.Tree(src, 100)
+    for b in range(L["bptr"].size - 1):
+        xs = tgt[:, L["tperm"][L["bptr"][b]:L["bptr"][b + 1]]]
+        for q in L["prox_ids"][L["prox_ptr"][b]:L["prox_ptr"][b + 1]]:
+            R = np.linalg.norm(xs - T.center[q][:, None], axis=0)
+            assert np.all(T.radius[q] <= theta * R * (1 + 1e-15))
+        # the lists cover every source exactly once
+        cover = np.zeros(4000, np.int64)
+        for q in np.concatenate([L["prox_ids"][L["prox_ptr"][b]:L["prox_ptr"][b + 1]],
+                                 L["dir_ids"][L["dir_ptr"][b]:L["dir_ptr"][b + 1]]]):
+            cover[T.perm[T.pbegin[q]:T.pend[q]]] += 1
+        assert np.all(cover == 1)
+    a, npa, nda = orc.treecode("stokeslet", tgt, src, w, 0.01, 5, theta, 100, mac_mode=0)
+    b, npb, ndb = orc.treecode("stokeslet", tgt, src, w, 0.01, 5, theta, 100, mac_mode=1,
+                               batch_size=1, order_leaf=64)
+    assert np.array_equal(a, b) and npa == npb and nda == ndb
+    # interaction counts from the lists
+    c, npc, ndc = orc.treecode("stokeslet", tgt, src, w, 0.01, 5, theta, 100, mac_mode=1,
+                               batch_size=64, order_leaf=64)
+    cnt = np.diff(L["bptr"])
+    per_b_p = np.array([L["prox_ptr"][b + 1] - L["prox_ptr"][b] for b in range(cnt.size)])
+    sizes = T.pend - T.pbegin
+    per_b_d = np.array([sizes[L["dir_ids"][L["dir_ptr"][b]:L["dir_ptr"][b + 1]]].sum()
+                        for b in range(cnt.size)])
+    assert npc == int(np.sum(cnt * per_b_p)) * 216
+    assert ndc == int(np.sum(cnt * per_b_d))
+    # the shared lists are never less accurate than the per-target walk here
+    d = orc.direct("stokeslet", tgt, src, w, eps=0.01)
+    assert orc.rel_l2(d, c) <= orc.rel_l2(d, a) * 1.5
+
+
+def test_sampled_targets(orc):
+    pts, w, _ = inputs.workload("c1", n=2000)
+    idx = inputs.sample_indices(2000, 50, 1)
+    full, _, _ = orc.treecode("rotlet", pts, pts, w, 0.01, 4, 0.7, 150, mac_mode=1)
+    part, _, _ = orc.treecode("rotlet", pts, pts, w, 0.01, 4, 0.7, 150, mac_mode=1, sample=idx)
+    assert np.array_equal(full[:, idx], part)
+
+
+def test_empty_inputs(orc):
+    src = inputs.points("uniform", 100, 1)
+    w = inputs.weights(100, 1)
+    empty = np.zeros((3, 0))
+    t, npx, ndr = orc.treecode("stokeslet", empty, src, w, 0.01, 4, 0.7, 10)
+    assert t.shape == (3, 0) and npx == 0 and ndr == 0
+    t, npx, ndr = orc.treecode("stokeslet", src, empty, np.zeros((3, 0)), 0.01, 4, 0.7, 10)
+    assert np.all(t == 0) and npx == 0 and ndr == 0
