@@ -1,0 +1,204 @@
+#!/usr/bin/env python3
+"""Benchmark of the treecode evaluation phase on one MI355X.
+
+Workload (default): 1,000,000 points i.i.d. uniform in [-1, 1]^3, forces
+uniform in [-1, 1]^3, regularized Stokeslets with eps = 0.005, degree n = 8,
+MAC theta = 0.7, leaf size N0 = 2000, FP32 kernel evaluation with FP64
+per-target accumulation; targets = sources.
+
+One step is the evaluation phase on resident device data: weight gather,
+cluster grids and modified weights (upward pass), the batch interaction lists
+on the device, and the particle-cluster evaluation with the scatter to caller
+order.  The source tree and the target order/batches are built once before
+timing (their build time is reported in "build_ms").
+
+Printed on stdout: one JSON line.  value = kernel evaluations performed per
+second (far-field proxy evaluations plus near-field pair evaluations, summed
+over targets).  Also reported: the relative L2 error against the FP64 direct
+sum on a 10,000-target sample, the per-stage device times from the library's
+HIP events, the roofline of the evaluation kernel and the CPU oracle's rate.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Algorithmic flops per kernel evaluation (FMA = 2, rsqrt = 1), from the
+# formulas of eq. Velocity_1 and eq. MRS_2.
+FLOPS = {"stokeslet": 32, "rotlet": 58}
+# MI355X published vector peaks (TFLOP/s).
+PEAK = {"fp32": 157.3, "fp64": 78.6}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(cfg, src, w, sample_k, precision_label):
+    """The FP64 oracle treecode (tree, Algorithm 1 weights for all sources,
+    batch walk for a target sample) timed on the host cores."""
+    import oracle
+    from paper_1902_02250_amd import inputs
+    oracle._load()
+    idx = inputs.sample_indices(src.shape[1], sample_k, cfg["seed"] + 7)
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    t0 = time.perf_counter()
+    _, npx, ndr = oracle.treecode(cfg["kernel"], src, src, w, cfg["eps"], cfg["degree"],
+                                  cfg["theta"], cfg["leaf"], mac_mode=1, batch_size=64,
+                                  order_leaf=64, sample=idx)
+    dt = time.perf_counter() - t0
+    return {"value": (npx + ndr) / dt, "unit": "interactions/s", "cores": threads,
+            "kind": "oracle",
+            "sample": (f"FP64 oracle treecode from scratch (tree, Algorithm 1 weights for all "
+                       f"{src.shape[1]} sources, shared-batch walk) evaluated for {sample_k} "
+                       f"seeded targets of the same workload: {npx + ndr} kernel evaluations "
+                       f"in {dt:.2f} s on {threads} OpenMP threads"),
+            "seconds": dt}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="c3")
+    ap.add_argument("--n", type=int, default=None, help="override the point count")
+    ap.add_argument("--precision", default="fp32_fp64acc",
+                    choices=["fp64", "fp32_fp64acc", "fp32_kahan"])
+    ap.add_argument("--degree", type=int, default=None)
+    ap.add_argument("--theta", type=float, default=None)
+    ap.add_argument("--batch-size", type=int, default=64)
+    ap.add_argument("--err-sample", type=int, default=10000)
+    ap.add_argument("--cpu-sample", type=int, default=65536)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        msg = ("bench.py measures one GPU only: the treecode path here is built and "
+               "timed on a single MI355X (multi-GPU target sharding is designed, not built); "
+               "run with --gpus 1")
+        print(msg, file=sys.stderr)
+        print(json.dumps({"error": msg, "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+    from paper_1902_02250_amd import bltc, inputs
+
+    bltc.load()
+    cfg = dict(inputs.CONFIGS[args.workload])
+    if args.n:
+        cfg["n"] = args.n
+    if args.degree:
+        cfg["degree"] = args.degree
+    if args.theta is not None:
+        cfg["theta"] = args.theta
+    kernel, eps, degree, theta = cfg["kernel"], cfg["eps"], cfg["degree"], cfg["theta"]
+    n = cfg["n"]
+    log(f"[bench] generating {args.workload}: n={n} {cfg['dist']} {kernel} eps={eps} "
+        f"degree={degree} theta={theta} leaf={cfg['leaf']} precision={args.precision}")
+    src = inputs.points(cfg["dist"], n, cfg["seed"])
+    w = inputs.weights(n, cfg["seed"])
+    dev = torch.device("cuda:0")
+    d_src = torch.from_numpy(src).to(dev)
+    d_w = torch.from_numpy(w).to(dev)
+    torch.cuda.synchronize()
+
+    t0 = time.perf_counter()
+    tree = bltc.Tree(d_src, cfg["leaf"])
+    t1 = time.perf_counter()
+    tg = bltc.Targets(d_src, args.batch_size, args.batch_size)
+    t2 = time.perf_counter()
+    log(f"[bench] tree: {tree.nnodes} clusters, depth {tree.depth} ({(t1 - t0) * 1e3:.0f} ms); "
+        f"targets: {tg.nb} batches ({(t2 - t1) * 1e3:.0f} ms)")
+    out = torch.empty((bltc.ODIM[kernel], n), dtype=torch.float64, device=dev)
+
+    def step():
+        tree.compute_weights(d_w, degree)
+        bltc.evaluate_tree(tree, tg, kernel, eps, degree, theta, precision=args.precision,
+                           out=out)
+
+    for i in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    npx, ndr = bltc.counts(tree, tg, degree, theta)
+    inter = npx + ndr
+    log(f"[bench] warmup done; {inter:.3e} kernel evaluations per step "
+        f"({npx:.3e} far, {ndr:.3e} near)")
+
+    bltc.profile_read(reset=True)
+    bltc.profile_enable(True)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for i in range(args.steps):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    bltc.profile_enable(False)
+    prof = bltc.profile_read(reset=True)
+    ms = e0.elapsed_time(e1) / args.steps
+    log(f"[bench] {args.steps} steps: {ms:.3f} ms/step; stages " +
+        ", ".join(f"{k} {v[0] / max(v[1], 1):.3f} ms" for k, v in prof.items()))
+
+    # accuracy against the FP64 direct sum on a seeded target sample
+    k = min(args.err_sample, n)
+    idx = inputs.sample_indices(n, k, cfg["seed"] + 11)
+    d_idx = torch.from_numpy(idx).to(dev)
+    ref = bltc.direct(d_src, d_src, d_w, kernel, eps, idx=d_idx, precision="fp64")
+    got = out[:, d_idx]
+    err = (torch.linalg.norm(got - ref) / torch.linalg.norm(ref)).item()
+    log(f"[bench] rel L2 error vs FP64 direct on {k} targets: {err:.3e}")
+
+    ev_ms = prof["eval"][0] / max(prof["eval"][1], 1)
+    flops = inter * FLOPS.get(kernel, 32)
+    achieved = flops / (ev_ms * 1e-3) / 1e12
+    pk = PEAK["fp64" if args.precision == "fp64" else "fp32"]
+    roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": pk, "unit": "TFLOP/s",
+            "frac": round(achieved / pk, 4), "traffic": None,
+            "kernel": f"k_p2p ({kernel}, {args.precision}, n={degree})",
+            "per_launch": f"{inter} kernel evaluations x {FLOPS.get(kernel, 32)} flop",
+            "avg_launch_ms": round(ev_ms, 4)}
+
+    res = {
+        "metric": "eval time & interactions/s at N=1e6, rel L2 err vs FP64 direct; "
+                  "learned vs fixed (n,theta)",
+        "value": inter / (ms * 1e-3),
+        "unit": "interactions/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f32",
+        "data": "synthetic",
+        "config": {"workload": (f"{args.workload}: N={n} {cfg['dist']} in [-1,1]^3, {kernel} "
+                                f"eps={eps}, n={degree}, theta={theta}, N0={cfg['leaf']}, "
+                                f"{args.precision}, batch {args.batch_size}"),
+                   "n": n, "kernel": kernel, "eps": eps, "degree": degree, "theta": theta,
+                   "leaf": cfg["leaf"], "precision": args.precision,
+                   "batch_size": args.batch_size},
+        "eval_s": round(ms * 1e-3, 6),
+        "interactions_per_step": inter,
+        "direct_equivalent_per_s": float(n) * n / (ms * 1e-3),
+        "rel_l2_err": err, "err_sample": k,
+        "stage_ms": {s: round(v[0] / max(v[1], 1), 4) for s, v in prof.items()},
+        "build_ms": {"tree": round((t1 - t0) * 1e3, 1), "targets": round((t2 - t1) * 1e3, 1)},
+        "roofline": roof,
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu_baseline:
+        log(f"[bench] CPU oracle baseline on {args.cpu_sample} targets ...")
+        res["cpu_baseline"] = cpu_baseline(cfg, src, w, args.cpu_sample, args.precision)
+        log(f"[bench] CPU oracle: {res['cpu_baseline']['value']:.3e} interactions/s "
+            f"({res['cpu_baseline']['seconds']:.1f} s)")
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,223 @@
+/*
+ * bltc.h - C ABI of the MI355X (gfx950) barycentric Lagrange treecode
+ * (Wang, Krasny and Tlupova, arXiv:1902.02250): the evaluation phase for the
+ * 3D regularized Stokeslet and rotlet kernels.
+ *
+ * What is computed (eq. N-body): for targets x_i and sources y_j with vector
+ * weights f_j,
+ *     u(x_i) = sum_j k(x_i, y_j) f_j,
+ * approximated by the treecode of Algorithm 2: a cluster tree over the
+ * sources (Section 6), modified weights on each cluster's tensor-product grid
+ * of Chebyshev points of the 2nd kind (eq. modified_weights, Algorithm 1),
+ * and a walk under the MAC r/R <= theta (eq. MAC) that uses the far-field
+ * approximation (eq. pc_approximation_3D) for accepted clusters and the
+ * direct sum (eq. pc_interaction_3D) at leaves.  Targets are grouped into
+ * batches of spatially close targets that share one walk (the shared MAC
+ * (r_B + r_C)/R <= theta, which implies the paper's per-target MAC for every
+ * target of the batch); batch_size = 1 is exactly the per-target walk.
+ *
+ * Kernels (Section 7, eq. MRS_kernels):
+ *   BLTC_STOKESLET  f (3) -> u (3):  u = sum f H1 + (f.d) d H2  (eq. Velocity_1)
+ *   BLTC_ROTLET     n (3) -> (u, w) (6): the torque terms of eq. MRS_2,
+ *                   u = sum 1/2 (n x d) Q,  w = sum 1/4 n D1 + 1/4 (n.d) d D2
+ *   BLTC_POLY       f (3) -> u (3): u_c = sum (poly_c + x.y)^poly_p f_c, a
+ *                   polynomial test kernel; FP64 only
+ * with d = x - y and the regularisation eps.  When eps = 0 a pair at zero
+ * distance contributes nothing (the singular self term is dropped,
+ * Section 1); when eps > 0 it is included.  Outputs are for unit viscosity.
+ *
+ * Conventions for every entry point:
+ *   - Point, weight and output arrays are HIP DEVICE pointers unless the
+ *     name or comment says "host".  Points are three separate FP64 arrays
+ *     (x, y, z).  Weights are FP64 [3][n], component-major; outputs are
+ *     FP64 [odim][m], component-major, in the caller's target order
+ *     (odim = 3, or 6 for the rotlet: u rows then w rows).
+ *   - The caller owns every buffer it passes; the library owns its handles
+ *     and the device memory inside them, freed by the matching destroy call.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Work is queued
+ *     on it; calls that must read results back to the host synchronise on it
+ *     and say so.
+ *   - Every call returns a bltc_status.  Arguments are checked before any
+ *     device work is queued; on an error nothing is written to the outputs.
+ *     bltc_last_error() returns a thread-local message for the last failure.
+ *   - Handles are not thread safe; different handles may be used from
+ *     different threads.
+ *   - Sizes: n, m < 2^31; degree 1..12; leaf_max >= 1; batch_size 1..1024;
+ *     0 <= theta <= 1; eps >= 0.  n = 0 or m = 0 is a valid no-op.
+ */
+#ifndef BLTC_H
+#define BLTC_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  BLTC_OK = 0,
+  BLTC_EINVAL = 1,   /* an argument is out of range or a pointer is NULL */
+  BLTC_ENOMEM = 2,   /* a device or host allocation failed */
+  BLTC_EDEVICE = 3,  /* a HIP call failed (message from the runtime) */
+  BLTC_ESTATE = 4,   /* the handle lacks a prerequisite (e.g. no weights) */
+  BLTC_EMODEL = 5    /* a selector model file is missing or malformed */
+} bltc_status;
+
+enum { BLTC_STOKESLET = 0, BLTC_ROTLET = 1, BLTC_POLY = 100 };
+
+enum {
+  BLTC_FP64 = 0,          /* FP64 everywhere */
+  BLTC_FP32_FP64ACC = 1,  /* FP32 kernel evaluation, FP64 per-target sums */
+  BLTC_FP32_KAHAN = 2     /* FP32 kernel evaluation, compensated FP32 sums */
+};
+
+/* Options of an evaluation; bltc_options_default() fills the defaults. */
+typedef struct {
+  int32_t size;        /* sizeof(bltc_options) */
+  int32_t precision;   /* BLTC_FP64 (default) or a mixed mode */
+  int32_t batch_size;  /* targets sharing one walk, default 64 */
+  int32_t order_leaf;  /* leaf size of the tree that orders the targets, default 64 */
+  int32_t poly_p;      /* BLTC_POLY exponent, default 2 */
+  double poly_c;       /* BLTC_POLY constant, default 1 */
+} bltc_options;
+
+typedef struct bltc_tree_s* bltc_tree;       /* sources: tree, weights */
+typedef struct bltc_targets_s* bltc_targets; /* targets: order, batches */
+
+void bltc_options_default(bltc_options* opt);
+const char* bltc_last_error(void);
+const char* bltc_version(void);
+
+/* ---- sources ------------------------------------------------------------
+ * Builds the cluster tree of Section 6 over the n sources (x, y, z) with at
+ * most leaf_max particles per leaf (N0).  Every cluster's box is the tight
+ * box of its particles; a cluster with more than leaf_max particles is
+ * bisected at its box midpoint along every side longer than l_max/sqrt(2)
+ * (l_max its own longest side), giving 8, 4 or 2 children in the order of
+ * the code bx + 2 by + 4 bz; empty children are dropped; a cluster
+ * with l_max = 0 or whose bisection would separate nothing stays a leaf.
+ * Center = box midpoint, radius = half the box diagonal.  The tree is built
+ * on the host from a copy of the coordinates (synchronises on `stream`);
+ * tree-ordered coordinates and the node arrays are kept on the device. */
+int bltc_build_tree(const double* x, const double* y, const double* z,
+                    int64_t n, int64_t leaf_max, void* stream, bltc_tree* out);
+int bltc_tree_destroy(bltc_tree t);
+/* Node count and depth (host values). */
+int bltc_tree_info(bltc_tree t, int64_t* n_nodes, int32_t* depth);
+/* Host copies of the tree (synchronises): perm[n] (tree position -> input
+ * index), box[nn][6] (lo xyz, hi xyz), center[nn][3], radius[nn],
+ * child_first[nn], child_count[nn], pbegin[nn], pend[nn], level[nn].  Any
+ * pointer may be NULL. */
+int bltc_tree_export(bltc_tree t, int64_t* perm, double* box, double* center,
+                     double* radius, int32_t* child_first, int32_t* child_count,
+                     int64_t* pbegin, int64_t* pend, int32_t* level);
+
+/* Upward pass (eq. modified_weights, Algorithm 1): gathers the weights w
+ * (FP64 [3][n], caller order) into tree order and computes, for every
+ * cluster, its Chebyshev grid (degree+1 points per axis mapped to the box)
+ * and modified weights fhat_k = sum_{j in C} L_k1(y_j1) L_k2(y_j2) L_k3(y_j3) f_j,
+ * the Lagrange values taken in barycentric form with the exact-hit rule of
+ * Algorithm 1 (a coordinate equal to a grid point gets the Kronecker delta).
+ * Computed in FP64; kept in FP64 and FP32 for the evaluation.  Calling again
+ * replaces the weights and drops modified weights of other degrees. */
+int bltc_compute_modified_weights(bltc_tree t, const double* w, int32_t degree,
+                                  void* stream);
+/* Host copy of the modified weights of one degree (synchronises):
+ * fhat[nn][3][degree+1][degree+1][degree+1] (k3 fastest) and, if grid is
+ * not NULL, grid[nn][3][degree+1]. */
+int bltc_modified_weights_export(bltc_tree t, int32_t degree, double* fhat,
+                                 double* grid);
+
+/* ---- targets -------------------------------------------------------------
+ * Orders the m targets by a tree built with the same rules and leaf size
+ * order_leaf, then cuts that order into consecutive batches of batch_size
+ * targets; each batch gets its tight box, center and radius like a cluster.
+ * Built on the host (synchronises); the order and batches live on the
+ * device. */
+int bltc_build_targets(const double* x, const double* y, const double* z,
+                       int64_t m, int32_t batch_size, int32_t order_leaf,
+                       void* stream, bltc_targets* out);
+int bltc_targets_destroy(bltc_targets g);
+/* Host copies (synchronises): number of batches, tperm[m] (target position
+ * -> input index), bptr[nb+1], bcenter[nb][3], bradius[nb]. */
+int bltc_targets_export(bltc_targets g, int64_t* nb, int64_t* tperm,
+                        int64_t* bptr, double* bcenter, double* bradius);
+
+/* ---- host-only builders --------------------------------------------------
+ * The same tree and batches built from HOST arrays, with no device work, so
+ * the construction rules can be checked on any machine.  Call with NULL
+ * output arrays to get n_nodes (or nb) first.  Arrays as in
+ * bltc_tree_export / bltc_targets_export. */
+int bltc_host_tree(const double* hx, const double* hy, const double* hz,
+                   int64_t n, int64_t leaf_max, int64_t* n_nodes,
+                   int32_t* depth, int64_t* perm, double* box, double* center,
+                   double* radius, int32_t* child_first, int32_t* child_count,
+                   int64_t* pbegin, int64_t* pend, int32_t* level);
+int bltc_host_batches(const double* hx, const double* hy, const double* hz,
+                      int64_t m, int32_t batch_size, int32_t order_leaf,
+                      int64_t* nb, int64_t* tperm, int64_t* bptr,
+                      double* bcenter, double* bradius);
+
+/* ---- evaluation ----------------------------------------------------------
+ * Walks the tree for every batch under the MAC with parameter theta (device
+ * interaction lists), then evaluates the far field against the Chebyshev
+ * grid points and modified weights of `degree` and the near field against
+ * leaf particles, and writes out[odim][m] in caller order.  The modified
+ * weights of `degree` must have been computed (else BLTC_ESTATE).  The list
+ * sizes are read back once (synchronises on `stream`). */
+int bltc_evaluate_tree(bltc_tree t, bltc_targets g, int32_t kernel, double eps,
+                       int32_t degree, double theta, const bltc_options* opt,
+                       double* out, void* stream);
+
+/* One call: build the source tree (leaf_max), the target batches, the
+ * modified weights of `degree`, evaluate, free everything.  opt may be NULL
+ * (defaults). */
+int bltc_evaluate(const double* tx, const double* ty, const double* tz,
+                  int64_t m, const double* sx, const double* sy,
+                  const double* sz, int64_t n, const double* w, int32_t kernel,
+                  double eps, int32_t degree, double theta, int64_t leaf_max,
+                  const bltc_options* opt, double* out, void* stream);
+
+/* Interaction lists of the batch walk, host copies (synchronises): sizes
+ * first (lists pointers NULL), then contents.  prox_ptr/dir_ptr[nb+1] index
+ * prox_ids/dir_ids (cluster ids in depth-first order, children in order). */
+int bltc_lists_export(bltc_tree t, bltc_targets g, double theta,
+                      int64_t* nb, int64_t* n_prox, int64_t* n_dir,
+                      int64_t* prox_ptr, int32_t* prox_ids, int64_t* dir_ptr,
+                      int32_t* dir_ids);
+/* Kernel evaluations an evaluation performs (synchronises): proxy
+ * evaluations sum over targets of (degree+1)^3 per accepted cluster, direct
+ * ones the leaf sizes of the direct list. */
+int bltc_counts(bltc_tree t, bltc_targets g, int32_t degree, double theta,
+                int64_t* n_proxy_evals, int64_t* n_direct_evals);
+
+/* Direct sum (eq. N-body) on the device for the k targets idx[0:k] (device
+ * int64 indices into the m target arrays, each checked to lie in [0, m),
+ * which copies idx to the host and synchronises; NULL = the first k <= m
+ * targets in order): out[odim][k].  opt->precision BLTC_FP64 or
+ * BLTC_FP32_FP64ACC; opt may be NULL (FP64). */
+int bltc_direct(const double* tx, const double* ty, const double* tz,
+                int64_t m, const int64_t* idx, int64_t k, const double* sx,
+                const double* sy, const double* sz, int64_t n, const double* w,
+                int32_t kernel, double eps, const bltc_options* opt,
+                double* out, void* stream);
+
+/* ---- measurement ---------------------------------------------------------
+ * Stage timing with HIP events recorded on the evaluation stream around each
+ * stage of bltc_compute_modified_weights and bltc_evaluate_tree:
+ *   BLTC_STAGE_PREP    weight gather and cluster grids,
+ *   BLTC_STAGE_UPWARD  modified-weight contraction and its reduction,
+ *   BLTC_STAGE_LISTS   interaction lists (count, scan, read-back, fill),
+ *   BLTC_STAGE_EVAL    the particle-cluster evaluation kernel.
+ * bltc_profile_enable(1) starts recording (process wide, for measurement
+ * runs, not thread safe); bltc_profile_read synchronises on the recorded
+ * events, returns the summed milliseconds and the launch count per stage
+ * (arrays of BLTC_NSTAGES) and, if reset, clears them. */
+enum { BLTC_STAGE_PREP = 0, BLTC_STAGE_UPWARD = 1, BLTC_STAGE_LISTS = 2,
+       BLTC_STAGE_EVAL = 3, BLTC_NSTAGES = 4 };
+int bltc_profile_enable(int32_t on);
+int bltc_profile_read(double* ms, int64_t* launches, int32_t reset);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

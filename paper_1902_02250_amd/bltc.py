@@ -1,0 +1,356 @@
+"""Python binding of libbltc.so (include/bltc.h): argument marshalling only.
+
+Every step of the treecode runs in the library's own HIP kernels; this module
+passes device pointers of torch tensors (float64, contiguous, on the GPU)
+and torch's current HIP stream through ctypes, and turns status codes into
+BltcError.  If the library has not been built, loading raises: there is no
+fallback path.
+
+Point sets are (3, n) float64 tensors (rows x, y, z); weights (3, n); outputs
+(odim, m) with odim = 3 (Stokeslet, polynomial) or 6 (rotlet: u then w).
+"""
+import ctypes
+import os
+import re
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "lib", "libbltc.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "bltc.h")
+
+KERNELS = {"stokeslet": 0, "rotlet": 1, "poly": 100}
+ODIM = {"stokeslet": 3, "rotlet": 6, "poly": 3}
+PRECISIONS = {"fp64": 0, "fp32_fp64acc": 1, "fp32_kahan": 2}
+STATUS = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "ESTATE", 5: "EMODEL"}
+
+_lib = None
+
+
+class BltcError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"bltc {STATUS.get(status, status)}: {message}")
+        self.status = status
+        self.message = message
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("size", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("batch_size", ctypes.c_int32), ("order_leaf", ctypes.c_int32),
+                ("poly_p", ctypes.c_int32), ("poly_c", ctypes.c_double)]
+
+
+def declared_functions():
+    """Names of the functions include/bltc.h declares."""
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:int|void|const char\*)\s+(bltc_\w+)\s*\(", text, re.M)))
+
+
+def load():
+    """Load libbltc.so (raises if it is not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
+                           "or python paper_1902_02250_amd/build.py")
+    L = ctypes.CDLL(LIB_PATH)
+    P, I64, I32, D = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double
+    sig = {
+        "bltc_options_default": (None, [P]),
+        "bltc_last_error": (ctypes.c_char_p, []),
+        "bltc_version": (ctypes.c_char_p, []),
+        "bltc_build_tree": (ctypes.c_int, [P, P, P, I64, I64, P, P]),
+        "bltc_tree_destroy": (ctypes.c_int, [P]),
+        "bltc_tree_info": (ctypes.c_int, [P, P, P]),
+        "bltc_tree_export": (ctypes.c_int, [P] * 10),
+        "bltc_compute_modified_weights": (ctypes.c_int, [P, P, I32, P]),
+        "bltc_modified_weights_export": (ctypes.c_int, [P, I32, P, P]),
+        "bltc_build_targets": (ctypes.c_int, [P, P, P, I64, I32, I32, P, P]),
+        "bltc_targets_destroy": (ctypes.c_int, [P]),
+        "bltc_targets_export": (ctypes.c_int, [P] * 6),
+        "bltc_host_tree": (ctypes.c_int, [P, P, P, I64, I64] + [P] * 11),
+        "bltc_host_batches": (ctypes.c_int, [P, P, P, I64, I32, I32] + [P] * 5),
+        "bltc_evaluate_tree": (ctypes.c_int, [P, P, I32, D, I32, D, P, P, P]),
+        "bltc_evaluate": (ctypes.c_int, [P, P, P, I64, P, P, P, I64, P, I32, D,
+                                         I32, D, I64, P, P, P]),
+        "bltc_lists_export": (ctypes.c_int, [P, P, D] + [P] * 7),
+        "bltc_counts": (ctypes.c_int, [P, P, I32, D, P, P]),
+        "bltc_profile_enable": (ctypes.c_int, [I32]),
+        "bltc_profile_read": (ctypes.c_int, [P, P, I32]),
+        "bltc_direct": (ctypes.c_int, [P, P, P, I64, P, I64, P, P, P, I64, P, I32,
+                                       D, P, P, P]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def _check(rc):
+    if rc != 0:
+        raise BltcError(rc, load().bltc_last_error().decode())
+
+
+def options(precision="fp64", batch_size=64, order_leaf=64, poly_p=2,
+            poly_c=1.0):
+    o = Options()
+    load().bltc_options_default(ctypes.byref(o))
+    o.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    o.batch_size = int(batch_size)
+    o.order_leaf = int(order_leaf)
+    o.poly_p = int(poly_p)
+    o.poly_c = float(poly_c)
+    return o
+
+
+# ---- torch plumbing -------------------------------------------------------------
+def _torch():
+    import torch
+    return torch
+
+
+def _dev(t, name, rows=None):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or not t.is_cuda:
+        raise TypeError(f"{name} must be a float64 CUDA tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if rows is not None and (t.dim() != 2 or t.shape[0] != rows):
+        raise ValueError(f"{name} must have shape ({rows}, n)")
+    return t
+
+
+def _rows(pts, name):
+    _dev(pts, name, 3)
+    n = pts.shape[1]
+    if n == 0:
+        return None, None, None, 0
+    s = pts.stride(0) * 8
+    base = pts.data_ptr()
+    return ctypes.c_void_p(base), ctypes.c_void_p(base + s), ctypes.c_void_p(base + 2 * s), n
+
+
+def _stream():
+    return ctypes.c_void_p(_torch().cuda.current_stream().cuda_stream)
+
+
+def _np(a, dtype):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+def _hp(a):
+    return ctypes.c_void_p(a.ctypes.data) if a is not None and a.size else None
+
+
+# ---- handles ---------------------------------------------------------------------
+class Tree:
+    """Source cluster tree (bltc_build_tree) plus its modified weights."""
+
+    def __init__(self, src, leaf_max):
+        L = load()
+        x, y, z, n = _rows(src, "src")
+        self.n = n
+        self._src = src
+        h = ctypes.c_void_p()
+        _check(L.bltc_build_tree(x, y, z, n, int(leaf_max), _stream(), ctypes.byref(h)))
+        self._h = h
+        nn, dep = ctypes.c_int64(), ctypes.c_int32()
+        _check(L.bltc_tree_info(self._h, ctypes.byref(nn), ctypes.byref(dep)))
+        self.nnodes, self.depth = nn.value, dep.value
+
+    def compute_weights(self, w, degree):
+        _dev(w, "w", 3)
+        if w.shape[1] != self.n:
+            raise ValueError("weights must match the source count")
+        ptr = ctypes.c_void_p(w.data_ptr()) if self.n else None
+        _check(load().bltc_compute_modified_weights(self._h, ptr, int(degree), _stream()))
+        self._w = w
+
+    def export(self):
+        nn = self.nnodes
+        out = dict(perm=np.zeros(self.n, np.int64), box=np.zeros((nn, 6)),
+                   center=np.zeros((nn, 3)), radius=np.zeros(nn),
+                   child_first=np.zeros(nn, np.int32), child_count=np.zeros(nn, np.int32),
+                   pbegin=np.zeros(nn, np.int64), pend=np.zeros(nn, np.int64),
+                   level=np.zeros(nn, np.int32))
+        _check(load().bltc_tree_export(self._h, *[_hp(out[k]) for k in
+               ("perm", "box", "center", "radius", "child_first", "child_count",
+                "pbegin", "pend", "level")]))
+        return out
+
+    def weights_export(self, degree):
+        n1 = degree + 1
+        f = np.zeros((self.nnodes, 3, n1, n1, n1))
+        g = np.zeros((self.nnodes, 3, n1))
+        _check(load().bltc_modified_weights_export(self._h, int(degree), _hp(f), _hp(g)))
+        return f, g
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().bltc_tree_destroy(self._h)
+            self._h = None
+
+    __del__ = close
+
+
+class Targets:
+    """Target order and batches (bltc_build_targets)."""
+
+    def __init__(self, tgt, batch_size=64, order_leaf=64):
+        L = load()
+        x, y, z, m = _rows(tgt, "tgt")
+        self.m = m
+        self.batch_size = batch_size
+        h = ctypes.c_void_p()
+        _check(L.bltc_build_targets(x, y, z, m, int(batch_size), int(order_leaf),
+                                    _stream(), ctypes.byref(h)))
+        self._h = h
+        nb = ctypes.c_int64()
+        _check(L.bltc_targets_export(self._h, ctypes.byref(nb), None, None, None, None))
+        self.nb = nb.value
+
+    def export(self):
+        nb = self.nb
+        out = dict(tperm=np.zeros(self.m, np.int64), bptr=np.zeros(nb + 1, np.int64),
+                   bcenter=np.zeros((nb, 3)), bradius=np.zeros(nb))
+        _check(load().bltc_targets_export(self._h, None, _hp(out["tperm"]), _hp(out["bptr"]),
+                                          _hp(out["bcenter"]), _hp(out["bradius"])))
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().bltc_targets_destroy(self._h)
+            self._h = None
+
+    __del__ = close
+
+
+def evaluate_tree(tree, targets, kernel, eps, degree, theta, precision="fp64",
+                  out=None, poly_p=2, poly_c=1.0):
+    torch = _torch()
+    od = ODIM[kernel]
+    if out is None:
+        out = torch.empty((od, targets.m), dtype=torch.float64, device="cuda")
+    _dev(out, "out", od)
+    o = options(precision, targets.batch_size, 64, poly_p, poly_c)
+    ptr = ctypes.c_void_p(out.data_ptr()) if targets.m else None
+    _check(load().bltc_evaluate_tree(tree._h, targets._h, KERNELS[kernel], float(eps),
+                                     int(degree), float(theta), ctypes.byref(o), ptr,
+                                     _stream()))
+    return out
+
+
+def evaluate(tgt, src, w, kernel, eps, degree, theta, leaf_max, precision="fp64",
+             batch_size=64, order_leaf=64, poly_p=2, poly_c=1.0, out=None):
+    """One call: tree, batches, modified weights and evaluation."""
+    torch = _torch()
+    tx, ty, tz, m = _rows(tgt, "tgt")
+    sx, sy, sz, n = _rows(src, "src")
+    _dev(w, "w", 3)
+    od = ODIM[kernel]
+    if out is None:
+        out = torch.empty((od, m), dtype=torch.float64, device="cuda")
+    _dev(out, "out", od)
+    o = options(precision, batch_size, order_leaf, poly_p, poly_c)
+    _check(load().bltc_evaluate(tx, ty, tz, m, sx, sy, sz, n,
+                                ctypes.c_void_p(w.data_ptr()) if n else None,
+                                KERNELS[kernel], float(eps), int(degree), float(theta),
+                                int(leaf_max), ctypes.byref(o),
+                                ctypes.c_void_p(out.data_ptr()) if m else None, _stream()))
+    return out
+
+
+def lists(tree, targets, theta):
+    L = load()
+    nb, npx, ndr = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    _check(L.bltc_lists_export(tree._h, targets._h, float(theta), ctypes.byref(nb),
+                               ctypes.byref(npx), ctypes.byref(ndr), None, None, None, None))
+    out = dict(prox_ptr=np.zeros(nb.value + 1, np.int64), prox_ids=np.zeros(npx.value, np.int32),
+               dir_ptr=np.zeros(nb.value + 1, np.int64), dir_ids=np.zeros(ndr.value, np.int32))
+    _check(L.bltc_lists_export(tree._h, targets._h, float(theta), None, None, None,
+                               _hp(out["prox_ptr"]), _hp(out["prox_ids"]),
+                               _hp(out["dir_ptr"]), _hp(out["dir_ids"])))
+    return out
+
+
+def counts(tree, targets, degree, theta):
+    a, b = ctypes.c_int64(), ctypes.c_int64()
+    _check(load().bltc_counts(tree._h, targets._h, int(degree), float(theta),
+                              ctypes.byref(a), ctypes.byref(b)))
+    return a.value, b.value
+
+
+def direct(tgt, src, w, kernel, eps, idx=None, precision="fp64", poly_p=2, poly_c=1.0):
+    """Direct sum on the device for the targets idx (int64 CUDA tensor) or all."""
+    torch = _torch()
+    tx, ty, tz, m = _rows(tgt, "tgt")
+    sx, sy, sz, n = _rows(src, "src")
+    _dev(w, "w", 3)
+    if idx is not None:
+        if idx.dtype != torch.int64 or not idx.is_cuda or not idx.is_contiguous():
+            raise TypeError("idx must be a contiguous int64 CUDA tensor")
+        k = idx.numel()
+        ip = ctypes.c_void_p(idx.data_ptr()) if k else None
+    else:
+        k, ip = m, None
+    out = torch.empty((ODIM[kernel], k), dtype=torch.float64, device="cuda")
+    o = options(precision, 64, 64, poly_p, poly_c)
+    _check(load().bltc_direct(tx, ty, tz, m, ip, k, sx, sy, sz, n,
+                              ctypes.c_void_p(w.data_ptr()) if n else None,
+                              KERNELS[kernel], float(eps), ctypes.byref(o),
+                              ctypes.c_void_p(out.data_ptr()) if k else None, _stream()))
+    return out
+
+
+# ---- host-only builders (no device) ------------------------------------------------
+def host_tree(pts, leaf_max):
+    pts = _np(pts, np.float64)
+    L = load()
+    n = pts.shape[1]
+    nn, dep = ctypes.c_int64(), ctypes.c_int32()
+    args = [_hp(pts[0]), _hp(pts[1]), _hp(pts[2]), n, int(leaf_max)]
+    _check(L.bltc_host_tree(*args, ctypes.byref(nn), ctypes.byref(dep), *([None] * 9)))
+    k = nn.value
+    out = dict(perm=np.zeros(n, np.int64), box=np.zeros((k, 6)), center=np.zeros((k, 3)),
+               radius=np.zeros(k), child_first=np.zeros(k, np.int32),
+               child_count=np.zeros(k, np.int32), pbegin=np.zeros(k, np.int64),
+               pend=np.zeros(k, np.int64), level=np.zeros(k, np.int32))
+    _check(L.bltc_host_tree(*args, None, None, *[_hp(out[q]) for q in
+           ("perm", "box", "center", "radius", "child_first", "child_count",
+            "pbegin", "pend", "level")]))
+    out["depth"] = dep.value
+    return out
+
+
+def host_batches(pts, batch_size, order_leaf):
+    pts = _np(pts, np.float64)
+    L = load()
+    m = pts.shape[1]
+    nb = ctypes.c_int64()
+    args = [_hp(pts[0]), _hp(pts[1]), _hp(pts[2]), m, int(batch_size), int(order_leaf)]
+    _check(L.bltc_host_batches(*args, ctypes.byref(nb), None, None, None, None))
+    k = nb.value
+    out = dict(tperm=np.zeros(m, np.int64), bptr=np.zeros(k + 1, np.int64),
+               bcenter=np.zeros((k, 3)), bradius=np.zeros(k))
+    _check(L.bltc_host_batches(*args, None, _hp(out["tperm"]), _hp(out["bptr"]),
+                               _hp(out["bcenter"]), _hp(out["bradius"])))
+    return out
+
+
+# ---- measurement -------------------------------------------------------------------
+STAGES = ("prep", "upward", "lists", "eval")
+
+
+def profile_enable(on=True):
+    _check(load().bltc_profile_enable(1 if on else 0))
+
+
+def profile_read(reset=True):
+    """{stage: (total ms, launches)} from the library's stage events."""
+    ms = np.zeros(len(STAGES))
+    n = np.zeros(len(STAGES), np.int64)
+    _check(load().bltc_profile_read(_hp(ms), _hp(n), 1 if reset else 0))
+    return {s: (float(ms[i]), int(n[i])) for i, s in enumerate(STAGES)}

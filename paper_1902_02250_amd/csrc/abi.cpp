@@ -1,0 +1,825 @@
+// The C ABI of include/bltc.h: argument checks, handle management, host
+// tree building and the sequencing of the device kernels on the caller's
+// stream.  No exception crosses the boundary.
+#include <hip/hip_runtime_api.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "bltc.h"
+#include "internal.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+struct HipError {
+  int code;
+  std::string msg;
+};
+
+// Throws inside the library only; every entry point catches.
+void hipchk(hipError_t e, const char* what) {
+  if (e == hipSuccess) return;
+  const int code = (e == hipErrorOutOfMemory) ? BLTC_ENOMEM : BLTC_EDEVICE;
+  throw HipError{code, std::string(what) + ": " + hipGetErrorString(e)};
+}
+
+template <typename T>
+T* dalloc(size_t count) {
+  void* p = nullptr;
+  hipchk(hipMalloc(&p, sizeof(T) * (count ? count : 1)), "hipMalloc");
+  return static_cast<T*>(p);
+}
+
+template <typename T>
+void dfree(T*& p) {
+  if (p) (void)hipFree((void*)p);
+  p = nullptr;
+}
+
+template <typename T>
+void h2d(T* dst, const T* src, size_t count, hipStream_t s) {
+  if (count)
+    hipchk(hipMemcpyAsync(dst, src, sizeof(T) * count, hipMemcpyHostToDevice, s),
+           "hipMemcpyAsync H2D");
+}
+
+template <typename T>
+void d2h(T* dst, const T* src, size_t count, hipStream_t s) {
+  if (count)
+    hipchk(hipMemcpyAsync(dst, src, sizeof(T) * count, hipMemcpyDeviceToHost, s),
+           "hipMemcpyAsync D2H");
+}
+
+void sync(hipStream_t s) { hipchk(hipStreamSynchronize(s), "hipStreamSynchronize"); }
+
+// True if p points into device (or managed) memory that kernels may read.
+bool device_ptr(const void* p) {
+  if (!p) return false;
+  hipPointerAttribute_t attr;
+  if (hipPointerGetAttributes(&attr, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return attr.type == hipMemoryTypeDevice || attr.type == hipMemoryTypeManaged;
+}
+
+// Copies n doubles from a device (or host) array to the host.
+void fetch(std::vector<double>& dst, const double* src, int64_t n,
+           hipStream_t s) {
+  dst.resize(n);
+  if (n)
+    hipchk(hipMemcpyAsync(dst.data(), src, sizeof(double) * n, hipMemcpyDefault, s),
+           "hipMemcpyAsync");
+}
+
+int odim_of(int kernel) { return kernel == BLTC_ROTLET ? 6 : 3; }
+
+bool valid_kernel(int k) {
+  return k == BLTC_STOKESLET || k == BLTC_ROTLET || k == BLTC_POLY;
+}
+
+int check_points(const double* x, const double* y, const double* z,
+                 int64_t n, const char* what) {
+  if (n < 0 || n > 0x7fffffffLL)
+    return fail(BLTC_EINVAL, std::string(what) + ": count out of range [0, 2^31)");
+  if (n > 0 && (!x || !y || !z))
+    return fail(BLTC_EINVAL, std::string(what) + ": NULL coordinate array");
+  if (n > 0 && (!device_ptr(x) || !device_ptr(y) || !device_ptr(z)))
+    return fail(BLTC_EINVAL, std::string(what) + ": coordinates must be device pointers");
+  return BLTC_OK;
+}
+
+int check_options(const bltc_options* o, int kernel) {
+  if (o->size != (int32_t)sizeof(bltc_options))
+    return fail(BLTC_EINVAL, "bltc_options.size mismatch");
+  if (o->precision < BLTC_FP64 || o->precision > BLTC_FP32_KAHAN)
+    return fail(BLTC_EINVAL, "unknown precision");
+  if (kernel == BLTC_POLY && o->precision != BLTC_FP64)
+    return fail(BLTC_EINVAL, "the polynomial test kernel runs in FP64 only");
+  if (o->batch_size < 1 || o->batch_size > 1024)
+    return fail(BLTC_EINVAL, "batch_size must be in [1, 1024]");
+  if (o->order_leaf < 1) return fail(BLTC_EINVAL, "order_leaf must be >= 1");
+  if (o->poly_p < 0 || o->poly_p > 64) return fail(BLTC_EINVAL, "poly_p must be in [0, 64]");
+  return BLTC_OK;
+}
+
+int check_eval(int kernel, double eps, int degree, double theta) {
+  if (!valid_kernel(kernel)) return fail(BLTC_EINVAL, "unknown kernel");
+  if (!(eps >= 0.0) || !std::isfinite(eps)) return fail(BLTC_EINVAL, "eps must be finite and >= 0");
+  if (degree < 1 || degree > bltc::kMaxDegree)
+    return fail(BLTC_EINVAL, "degree must be in [1, 12]");
+  if (!(theta >= 0.0 && theta <= 1.0)) return fail(BLTC_EINVAL, "theta must be in [0, 1]");
+  return BLTC_OK;
+}
+
+void kernel_scales(int kernel, double* su, double* sw) {
+  const double c = 1.0 / (8.0 * 3.14159265358979323846);
+  if (kernel == BLTC_STOKESLET) { *su = c; *sw = c; }
+  else if (kernel == BLTC_ROTLET) { *su = 0.5 * c; *sw = 0.25 * c; }
+  else { *su = 1.0; *sw = 1.0; }
+}
+
+// ---- stage timing ------------------------------------------------------------
+struct Profiler {
+  bool on = false;
+  struct Mark {
+    int stage;
+    hipEvent_t a, b;
+  };
+  std::vector<Mark> marks;
+  std::vector<hipEvent_t> pool;
+  hipEvent_t get() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e;
+    hipchk(hipEventCreate(&e), "hipEventCreate");
+    return e;
+  }
+};
+Profiler g_prof;
+
+// Records events around one stage on stream s when profiling is on.
+struct StageTimer {
+  int stage;
+  hipStream_t s;
+  hipEvent_t a = nullptr;
+  StageTimer(int st, hipStream_t str) : stage(st), s(str) {
+    if (!g_prof.on) return;
+    a = g_prof.get();
+    hipchk(hipEventRecord(a, s), "hipEventRecord");
+  }
+  void stop() {
+    if (!a) return;
+    hipEvent_t b = g_prof.get();
+    hipchk(hipEventRecord(b, s), "hipEventRecord");
+    g_prof.marks.push_back({stage, a, b});
+    a = nullptr;
+  }
+};
+
+// ---- tree ---------------------------------------------------------------------
+void destroy_degree(bltc_degree_data& d) {
+  dfree(d.grid);
+  dfree(d.fhat64);
+  dfree(d.p2p64);
+  dfree(d.p2p32);
+}
+
+void destroy_tree(bltc_tree t) {
+  if (!t) return;
+  for (auto& kv : t->deg) destroy_degree(kv.second);
+  dfree(t->d_perm); dfree(t->d_y); dfree(t->d_box); dfree(t->d_geo);
+  dfree(t->d_range); dfree(t->d_kids); dfree(t->d_w64); dfree(t->d_w32);
+  dfree(t->d_chunks); dfree(t->d_chunk_ptr); dfree(t->d_partial);
+  delete t;
+}
+
+void build_tree(const double* x, const double* y, const double* z, int64_t n,
+                int64_t leaf_max, hipStream_t s, bltc_tree t) {
+  std::vector<double> hx, hy, hz;
+  fetch(hx, x, n, s);
+  fetch(hy, y, n, s);
+  fetch(hz, z, n, s);
+  sync(s);
+  bltc::build_host_tree(hx.data(), hy.data(), hz.data(), n, leaf_max, t->host);
+  const bltc::HostTree& H = t->host;
+  if (7 * (int64_t)H.depth + 1 > bltc::kStackMax)
+    throw HipError{BLTC_EINVAL, "tree deeper than the list walk supports"};
+  const int64_t nn = H.nnodes();
+  // tree-ordered coordinates
+  std::vector<double> ys(3 * n);
+  for (int64_t i = 0; i < n; ++i) {
+    const int32_t j = H.perm[i];
+    ys[i] = hx[j];
+    ys[n + i] = hy[j];
+    ys[2 * n + i] = hz[j];
+  }
+  std::vector<double4> geo(nn);
+  std::vector<int2> range(nn), kids(nn);
+  for (int64_t q = 0; q < nn; ++q) {
+    geo[q] = make_double4(H.ctr[3 * q], H.ctr[3 * q + 1], H.ctr[3 * q + 2], H.rad[q]);
+    range[q] = make_int2(H.begin[q], H.end[q]);
+    kids[q] = make_int2(H.first[q], H.count[q]);
+  }
+  // upward-pass chunks: consecutive pieces of each cluster's particle range
+  std::vector<int4> chunks;
+  std::vector<int32_t> cptr(nn + 1);
+  for (int64_t q = 0; q < nn; ++q) {
+    cptr[q] = (int32_t)chunks.size();
+    for (int32_t b = H.begin[q]; b < H.end[q]; b += bltc::kUpwardChunk)
+      chunks.push_back(make_int4((int)q, b, std::min(H.end[q], b + bltc::kUpwardChunk), 0));
+  }
+  cptr[nn] = (int32_t)chunks.size();
+  t->nchunks = (int64_t)chunks.size();
+
+  t->d_perm = dalloc<int32_t>(n);
+  t->d_y = dalloc<double>(3 * n);
+  t->d_box = dalloc<double>(6 * nn);
+  t->d_geo = dalloc<double4>(nn);
+  t->d_range = dalloc<int2>(nn);
+  t->d_kids = dalloc<int2>(nn);
+  t->d_chunks = dalloc<int4>(chunks.size());
+  t->d_chunk_ptr = dalloc<int32_t>(nn + 1);
+  h2d(t->d_perm, H.perm.data(), n, s);
+  h2d(t->d_y, ys.data(), 3 * n, s);
+  h2d(t->d_box, H.box.data(), 6 * nn, s);
+  h2d(t->d_geo, geo.data(), nn, s);
+  h2d(t->d_range, range.data(), nn, s);
+  h2d(t->d_kids, kids.data(), nn, s);
+  h2d(t->d_chunks, chunks.data(), chunks.size(), s);
+  h2d(t->d_chunk_ptr, cptr.data(), nn + 1, s);
+  sync(s);   // the host staging vectors go out of scope
+}
+
+// Grid and modified weights of one degree from the stored tree-ordered
+// weights.
+void ensure_degree(bltc_tree t, int degree, hipStream_t s) {
+  if (t->deg.count(degree)) return;
+  const int64_t nn = t->host.nnodes();
+  const int n1 = degree + 1;
+  const int64_t nk = (int64_t)n1 * n1 * n1;
+  bltc_degree_data d;
+  try {
+    d.grid = dalloc<double>(nn * 3 * n1);
+    d.fhat64 = dalloc<double>(nn * 3 * nk);
+    d.p2p64 = dalloc<double>(nn * 3 * nk);
+    d.p2p32 = dalloc<float>(nn * 3 * nk);
+    double tk[bltc::kMaxDegree + 1];
+    bltc::cheb_points(degree, tk);
+    StageTimer prep(BLTC_STAGE_PREP, s);
+    hipchk(bltc::launch_grids(t->d_box, nn, degree, tk, d.grid, s), "grids");
+    prep.stop();
+    const size_t need = (size_t)t->nchunks * 3 * nk;
+    if (need > t->partial_cap) {
+      dfree(t->d_partial);
+      t->d_partial = dalloc<double>(need);
+      t->partial_cap = need;
+    }
+    StageTimer up(BLTC_STAGE_UPWARD, s);
+    hipchk(bltc::launch_upward(t->d_y, t->d_w64, t->n, t->d_chunks,
+                               t->nchunks, d.grid, degree, t->d_partial, s),
+           "upward");
+    hipchk(bltc::launch_upward_reduce(t->d_chunk_ptr, nn, t->d_partial, degree,
+                                      d.fhat64, d.p2p64, d.p2p32, s),
+           "upward reduce");
+    up.stop();
+  } catch (...) {
+    destroy_degree(d);
+    throw;
+  }
+  t->deg[degree] = d;
+}
+
+void set_weights(bltc_tree t, const double* w, hipStream_t s) {
+  for (auto& kv : t->deg) destroy_degree(kv.second);
+  t->deg.clear();
+  if (!t->d_w64) {
+    t->d_w64 = dalloc<double>(3 * t->n);
+    t->d_w32 = dalloc<float>(3 * t->n);
+  }
+  StageTimer prep(BLTC_STAGE_PREP, s);
+  hipchk(bltc::launch_gather_weights(w, t->d_perm, t->n, t->d_w64, t->d_w32, s),
+         "gather weights");
+  prep.stop();
+  t->has_w = true;
+}
+
+// ---- targets -----------------------------------------------------------------
+void destroy_targets(bltc_targets g) {
+  if (!g) return;
+  dfree(g->d_tperm); dfree(g->d_x); dfree(g->d_bptr); dfree(g->d_bgeo);
+  dfree(g->d_cnt); dfree(g->d_ptr); dfree(g->d_flags); dfree(g->d_pids);
+  dfree(g->d_dids);
+  delete g;
+}
+
+void build_targets(const double* x, const double* y, const double* z,
+                   int64_t m, int32_t bs, int32_t leaf, hipStream_t s,
+                   bltc_targets g) {
+  std::vector<double> hx, hy, hz;
+  fetch(hx, x, m, s);
+  fetch(hy, y, m, s);
+  fetch(hz, z, m, s);
+  sync(s);
+  bltc::build_host_batches(hx.data(), hy.data(), hz.data(), m, bs, leaf, g->host);
+  const bltc::HostBatches& B = g->host;
+  g->m = m;
+  g->nb = (int64_t)B.bptr.size() - 1;
+  g->batch_size = bs;
+  g->order_leaf = leaf;
+  std::vector<double> xs(3 * m);
+  for (int64_t i = 0; i < m; ++i) {
+    const int32_t j = B.perm[i];
+    xs[i] = hx[j];
+    xs[m + i] = hy[j];
+    xs[2 * m + i] = hz[j];
+  }
+  const int64_t nb = g->nb;
+  g->d_tperm = dalloc<int32_t>(m);
+  g->d_x = dalloc<double>(3 * m);
+  g->d_bptr = dalloc<int32_t>(nb + 1);
+  g->d_bgeo = dalloc<double4>(nb);
+  g->d_cnt = dalloc<int32_t>(2 * nb);
+  g->d_ptr = dalloc<int32_t>(2 * (nb + 1));
+  g->d_flags = dalloc<int32_t>(4);
+  h2d(g->d_tperm, B.perm.data(), m, s);
+  h2d(g->d_x, xs.data(), 3 * m, s);
+  h2d(g->d_bptr, B.bptr.data(), nb + 1, s);
+  h2d(g->d_bgeo, reinterpret_cast<const double4*>(B.geo.data()), nb, s);
+  const int32_t zero[4] = {0, 0, 0, 0};
+  h2d(g->d_flags, zero, 4, s);
+  sync(s);
+}
+
+// Device interaction lists for (t, g, theta); returns the list sizes.
+void build_lists(bltc_tree t, bltc_targets g, double theta, hipStream_t s,
+                 int64_t* np, int64_t* nd) {
+  const int64_t nb = g->nb;
+  bltc::ListArgs a;
+  a.bgeo = g->d_bgeo;
+  a.nb = nb;
+  a.nodes.geo = t->d_geo;
+  a.nodes.range = t->d_range;
+  a.nodes.kids = t->d_kids;
+  a.nodes.nn = t->host.nnodes();
+  a.theta = theta;
+  a.pcnt = g->d_cnt;
+  a.dcnt = g->d_cnt + nb;
+  a.pptr = g->d_ptr;
+  a.dptr = g->d_ptr + nb + 1;
+  a.pids = nullptr;
+  a.dids = nullptr;
+  a.err = g->d_flags;
+  StageTimer lt(BLTC_STAGE_LISTS, s);
+  hipchk(bltc::launch_lists(a, false, s), "list count");
+  hipchk(bltc::launch_exclusive_scan(a.pcnt, nb, g->d_ptr, g->d_flags + 1, s), "scan");
+  hipchk(bltc::launch_exclusive_scan(a.dcnt, nb, g->d_ptr + nb + 1, g->d_flags + 2, s), "scan");
+  int32_t tot[2], flags[4];
+  d2h(&tot[0], g->d_ptr + nb, 1, s);
+  d2h(&tot[1], g->d_ptr + 2 * nb + 1, 1, s);
+  d2h(flags, g->d_flags, 4, s);
+  sync(s);
+  if (flags[0] || flags[1] || flags[2])
+    throw HipError{BLTC_EDEVICE, "interaction lists overflowed"};
+  if (tot[0] > g->pcap) {
+    dfree(g->d_pids);
+    g->d_pids = dalloc<int32_t>(tot[0]);
+    g->pcap = tot[0];
+  }
+  if (tot[1] > g->dcap) {
+    dfree(g->d_dids);
+    g->d_dids = dalloc<int32_t>(tot[1]);
+    g->dcap = tot[1];
+  }
+  a.pids = g->d_pids;
+  a.dids = g->d_dids;
+  hipchk(bltc::launch_lists(a, true, s), "list fill");
+  lt.stop();
+  *np = tot[0];
+  *nd = tot[1];
+}
+
+void evaluate_tree(bltc_tree t, bltc_targets g, int kernel, double eps,
+                   int degree, double theta, const bltc_options& o,
+                   double* out, hipStream_t s) {
+  if (g->m == 0) return;
+  ensure_degree(t, degree, s);
+  int64_t np = 0, nd = 0;
+  build_lists(t, g, theta, s, &np, &nd);
+  const bltc_degree_data& d = t->deg.at(degree);
+  bltc::P2PArgs a;
+  a.tx = g->d_x;
+  a.m = g->m;
+  a.tperm = g->d_tperm;
+  a.bptr = g->d_bptr;
+  a.bgeo = g->d_bgeo;
+  a.nb = g->nb;
+  a.wpb = (g->batch_size + bltc::kWave - 1) / bltc::kWave;
+  a.pptr = g->d_ptr;
+  a.pids = g->d_pids;
+  a.dptr = g->d_ptr + g->nb + 1;
+  a.dids = g->d_dids;
+  a.range = t->d_range;
+  a.grid = d.grid;
+  a.fhat = o.precision == BLTC_FP64 ? (const void*)d.p2p64 : (const void*)d.p2p32;
+  a.ys = t->d_y;
+  a.w64 = t->d_w64;
+  a.w32 = t->d_w32;
+  a.n = t->n;
+  a.eps = eps;
+  a.poly_p = o.poly_p;
+  a.poly_c = o.poly_c;
+  kernel_scales(kernel, &a.scale_u, &a.scale_w);
+  a.out = out;
+  StageTimer ev(BLTC_STAGE_EVAL, s);
+  hipchk(bltc::launch_p2p(kernel, o.precision, degree, a, s), "p2p");
+  ev.stop();
+}
+
+template <typename F>
+int guarded(F&& f) {
+  try {
+    return f();
+  } catch (const HipError& e) {
+    return fail(e.code, e.msg);
+  } catch (const std::bad_alloc&) {
+    return fail(BLTC_ENOMEM, "host allocation failed");
+  } catch (const std::exception& e) {
+    return fail(BLTC_EDEVICE, e.what());
+  } catch (...) {
+    return fail(BLTC_EDEVICE, "unknown failure");
+  }
+}
+
+}  // namespace
+
+// ============================================================================
+extern "C" {
+
+void bltc_options_default(bltc_options* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof *o);
+  o->size = (int32_t)sizeof(bltc_options);
+  o->precision = BLTC_FP64;
+  o->batch_size = 64;
+  o->order_leaf = 64;
+  o->poly_p = 2;
+  o->poly_c = 1.0;
+}
+
+const char* bltc_last_error(void) { return g_err.c_str(); }
+
+const char* bltc_version(void) { return "bltc 0.1 gfx950"; }
+
+int bltc_build_tree(const double* x, const double* y, const double* z,
+                    int64_t n, int64_t leaf_max, void* stream, bltc_tree* out) {
+  if (!out) return fail(BLTC_EINVAL, "out handle pointer is NULL");
+  *out = nullptr;
+  if (int rc = check_points(x, y, z, n, "sources")) return rc;
+  if (leaf_max < 1) return fail(BLTC_EINVAL, "leaf_max must be >= 1");
+  return guarded([&] {
+    bltc_tree t = new bltc_tree_s;
+    t->n = n;
+    t->leaf_max = leaf_max;
+    try {
+      build_tree(x, y, z, n, leaf_max, (hipStream_t)stream, t);
+    } catch (...) {
+      destroy_tree(t);
+      throw;
+    }
+    *out = t;
+    return (int)BLTC_OK;
+  });
+}
+
+int bltc_tree_destroy(bltc_tree t) {
+  destroy_tree(t);
+  return BLTC_OK;
+}
+
+int bltc_tree_info(bltc_tree t, int64_t* n_nodes, int32_t* depth) {
+  if (!t) return fail(BLTC_EINVAL, "NULL tree");
+  if (n_nodes) *n_nodes = t->host.nnodes();
+  if (depth) *depth = t->host.depth;
+  return BLTC_OK;
+}
+
+int bltc_tree_export(bltc_tree t, int64_t* perm, double* box, double* center,
+                     double* radius, int32_t* child_first, int32_t* child_count,
+                     int64_t* pbegin, int64_t* pend, int32_t* level) {
+  if (!t) return fail(BLTC_EINVAL, "NULL tree");
+  const bltc::HostTree& H = t->host;
+  const int64_t nn = H.nnodes();
+  for (int64_t i = 0; perm && i < t->n; ++i) perm[i] = H.perm[i];
+  for (int64_t q = 0; q < nn; ++q) {
+    if (box) for (int k = 0; k < 6; ++k) box[6 * q + k] = H.box[6 * q + k];
+    if (center) for (int k = 0; k < 3; ++k) center[3 * q + k] = H.ctr[3 * q + k];
+    if (radius) radius[q] = H.rad[q];
+    if (child_first) child_first[q] = H.first[q];
+    if (child_count) child_count[q] = H.count[q];
+    if (pbegin) pbegin[q] = H.begin[q];
+    if (pend) pend[q] = H.end[q];
+    if (level) level[q] = H.level[q];
+  }
+  return BLTC_OK;
+}
+
+int bltc_compute_modified_weights(bltc_tree t, const double* w, int32_t degree,
+                                  void* stream) {
+  if (!t) return fail(BLTC_EINVAL, "NULL tree");
+  if (degree < 1 || degree > bltc::kMaxDegree)
+    return fail(BLTC_EINVAL, "degree must be in [1, 12]");
+  if (t->n > 0 && !device_ptr(w))
+    return fail(BLTC_EINVAL, "weights must be a device pointer");
+  return guarded([&] {
+    hipStream_t s = (hipStream_t)stream;
+    set_weights(t, w, s);
+    ensure_degree(t, degree, s);
+    return (int)BLTC_OK;
+  });
+}
+
+int bltc_modified_weights_export(bltc_tree t, int32_t degree, double* fhat,
+                                 double* grid) {
+  if (!t) return fail(BLTC_EINVAL, "NULL tree");
+  auto it = t->deg.find(degree);
+  if (it == t->deg.end())
+    return fail(BLTC_ESTATE, "modified weights of this degree are not computed");
+  return guarded([&] {
+    const int64_t nn = t->host.nnodes();
+    const int n1 = degree + 1;
+    hipchk(hipDeviceSynchronize(), "hipDeviceSynchronize");
+    if (fhat)
+      hipchk(hipMemcpy(fhat, it->second.fhat64, sizeof(double) * nn * 3 * n1 * n1 * n1,
+                       hipMemcpyDeviceToHost), "hipMemcpy");
+    if (grid)
+      hipchk(hipMemcpy(grid, it->second.grid, sizeof(double) * nn * 3 * n1,
+                       hipMemcpyDeviceToHost), "hipMemcpy");
+    return (int)BLTC_OK;
+  });
+}
+
+int bltc_build_targets(const double* x, const double* y, const double* z,
+                       int64_t m, int32_t batch_size, int32_t order_leaf,
+                       void* stream, bltc_targets* out) {
+  if (!out) return fail(BLTC_EINVAL, "out handle pointer is NULL");
+  *out = nullptr;
+  if (int rc = check_points(x, y, z, m, "targets")) return rc;
+  if (batch_size < 1 || batch_size > 1024)
+    return fail(BLTC_EINVAL, "batch_size must be in [1, 1024]");
+  if (order_leaf < 1) return fail(BLTC_EINVAL, "order_leaf must be >= 1");
+  return guarded([&] {
+    bltc_targets g = new bltc_targets_s;
+    try {
+      build_targets(x, y, z, m, batch_size, order_leaf, (hipStream_t)stream, g);
+    } catch (...) {
+      destroy_targets(g);
+      throw;
+    }
+    *out = g;
+    return (int)BLTC_OK;
+  });
+}
+
+int bltc_targets_destroy(bltc_targets g) {
+  destroy_targets(g);
+  return BLTC_OK;
+}
+
+int bltc_targets_export(bltc_targets g, int64_t* nb, int64_t* tperm,
+                        int64_t* bptr, double* bcenter, double* bradius) {
+  if (!g) return fail(BLTC_EINVAL, "NULL targets");
+  const bltc::HostBatches& B = g->host;
+  if (nb) *nb = g->nb;
+  for (int64_t i = 0; tperm && i < g->m; ++i) tperm[i] = B.perm[i];
+  for (int64_t b = 0; b <= g->nb; ++b) {
+    if (bptr) bptr[b] = B.bptr[b];
+    if (b == g->nb) break;
+    if (bcenter) for (int k = 0; k < 3; ++k) bcenter[3 * b + k] = B.geo[4 * b + k];
+    if (bradius) bradius[b] = B.geo[4 * b + 3];
+  }
+  return BLTC_OK;
+}
+
+int bltc_host_tree(const double* hx, const double* hy, const double* hz,
+                   int64_t n, int64_t leaf_max, int64_t* n_nodes,
+                   int32_t* depth, int64_t* perm, double* box, double* center,
+                   double* radius, int32_t* child_first, int32_t* child_count,
+                   int64_t* pbegin, int64_t* pend, int32_t* level) {
+  if (n < 0 || n > 0x7fffffffLL) return fail(BLTC_EINVAL, "count out of range [0, 2^31)");
+  if (n > 0 && (!hx || !hy || !hz)) return fail(BLTC_EINVAL, "NULL coordinate array");
+  if (leaf_max < 1) return fail(BLTC_EINVAL, "leaf_max must be >= 1");
+  return guarded([&] {
+    bltc_tree_s t;
+    t.n = n;
+    bltc::build_host_tree(hx, hy, hz, n, leaf_max, t.host);
+    if (n_nodes) *n_nodes = t.host.nnodes();
+    if (depth) *depth = t.host.depth;
+    return bltc_tree_export(&t, perm, box, center, radius, child_first,
+                            child_count, pbegin, pend, level);
+  });
+}
+
+int bltc_host_batches(const double* hx, const double* hy, const double* hz,
+                      int64_t m, int32_t batch_size, int32_t order_leaf,
+                      int64_t* nb, int64_t* tperm, int64_t* bptr,
+                      double* bcenter, double* bradius) {
+  if (m < 0 || m > 0x7fffffffLL) return fail(BLTC_EINVAL, "count out of range [0, 2^31)");
+  if (m > 0 && (!hx || !hy || !hz)) return fail(BLTC_EINVAL, "NULL coordinate array");
+  if (batch_size < 1 || batch_size > 1024)
+    return fail(BLTC_EINVAL, "batch_size must be in [1, 1024]");
+  if (order_leaf < 1) return fail(BLTC_EINVAL, "order_leaf must be >= 1");
+  return guarded([&] {
+    bltc_targets_s g;
+    bltc::build_host_batches(hx, hy, hz, m, batch_size, order_leaf, g.host);
+    g.m = m;
+    g.nb = (int64_t)g.host.bptr.size() - 1;
+    return bltc_targets_export(&g, nb, tperm, bptr, bcenter, bradius);
+  });
+}
+
+int bltc_evaluate_tree(bltc_tree t, bltc_targets g, int32_t kernel, double eps,
+                       int32_t degree, double theta, const bltc_options* opt,
+                       double* out, void* stream) {
+  if (!t || !g) return fail(BLTC_EINVAL, "NULL tree or targets");
+  if (int rc = check_eval(kernel, eps, degree, theta)) return rc;
+  bltc_options o;
+  bltc_options_default(&o);
+  if (opt) o = *opt;
+  if (int rc = check_options(&o, kernel)) return rc;
+  if (g->m > 0 && !device_ptr(out)) return fail(BLTC_EINVAL, "out must be a device pointer");
+  if (!t->has_w) return fail(BLTC_ESTATE, "no weights: call bltc_compute_modified_weights first");
+  if (!t->deg.count(degree))
+    return fail(BLTC_ESTATE, "modified weights of this degree are not computed");
+  return guarded([&] {
+    evaluate_tree(t, g, kernel, eps, degree, theta, o, out, (hipStream_t)stream);
+    return (int)BLTC_OK;
+  });
+}
+
+int bltc_evaluate(const double* tx, const double* ty, const double* tz,
+                  int64_t m, const double* sx, const double* sy,
+                  const double* sz, int64_t n, const double* w, int32_t kernel,
+                  double eps, int32_t degree, double theta, int64_t leaf_max,
+                  const bltc_options* opt, double* out, void* stream) {
+  if (int rc = check_points(tx, ty, tz, m, "targets")) return rc;
+  if (int rc = check_points(sx, sy, sz, n, "sources")) return rc;
+  if (int rc = check_eval(kernel, eps, degree, theta)) return rc;
+  if (leaf_max < 1) return fail(BLTC_EINVAL, "leaf_max must be >= 1");
+  bltc_options o;
+  bltc_options_default(&o);
+  if (opt) o = *opt;
+  if (int rc = check_options(&o, kernel)) return rc;
+  if (n > 0 && !device_ptr(w)) return fail(BLTC_EINVAL, "weights must be a device pointer");
+  if (m > 0 && !device_ptr(out)) return fail(BLTC_EINVAL, "out must be a device pointer");
+  if (m == 0) return BLTC_OK;   // nothing to write
+  return guarded([&] {
+    hipStream_t s = (hipStream_t)stream;
+    bltc_tree t = new bltc_tree_s;
+    bltc_targets g = nullptr;
+    try {
+      t->n = n;
+      t->leaf_max = leaf_max;
+      build_tree(sx, sy, sz, n, leaf_max, s, t);
+      g = new bltc_targets_s;
+      build_targets(tx, ty, tz, m, o.batch_size, o.order_leaf, s, g);
+      set_weights(t, w, s);
+      evaluate_tree(t, g, kernel, eps, degree, theta, o, out, s);
+      sync(s);
+    } catch (...) {
+      destroy_targets(g);
+      destroy_tree(t);
+      throw;
+    }
+    destroy_targets(g);
+    destroy_tree(t);
+    return (int)BLTC_OK;
+  });
+}
+
+int bltc_lists_export(bltc_tree t, bltc_targets g, double theta, int64_t* nb,
+                      int64_t* n_prox, int64_t* n_dir, int64_t* prox_ptr,
+                      int32_t* prox_ids, int64_t* dir_ptr, int32_t* dir_ids) {
+  if (!t || !g) return fail(BLTC_EINVAL, "NULL tree or targets");
+  if (!(theta >= 0.0 && theta <= 1.0)) return fail(BLTC_EINVAL, "theta must be in [0, 1]");
+  return guarded([&] {
+    int64_t np = 0, nd = 0;
+    if (g->nb > 0) build_lists(t, g, theta, nullptr, &np, &nd);
+    if (nb) *nb = g->nb;
+    if (n_prox) *n_prox = np;
+    if (n_dir) *n_dir = nd;
+    if (g->nb == 0) {
+      if (prox_ptr) prox_ptr[0] = 0;
+      if (dir_ptr) dir_ptr[0] = 0;
+      return (int)BLTC_OK;
+    }
+    std::vector<int32_t> pp(g->nb + 1), dp(g->nb + 1);
+    d2h(pp.data(), g->d_ptr, g->nb + 1, nullptr);
+    d2h(dp.data(), g->d_ptr + g->nb + 1, g->nb + 1, nullptr);
+    if (prox_ids) d2h(prox_ids, g->d_pids, np, nullptr);
+    if (dir_ids) d2h(dir_ids, g->d_dids, nd, nullptr);
+    sync(nullptr);
+    for (int64_t b = 0; b <= g->nb; ++b) {
+      if (prox_ptr) prox_ptr[b] = pp[b];
+      if (dir_ptr) dir_ptr[b] = dp[b];
+    }
+    return (int)BLTC_OK;
+  });
+}
+
+int bltc_counts(bltc_tree t, bltc_targets g, int32_t degree, double theta,
+                int64_t* n_proxy_evals, int64_t* n_direct_evals) {
+  if (!t || !g) return fail(BLTC_EINVAL, "NULL tree or targets");
+  if (degree < 1 || degree > bltc::kMaxDegree)
+    return fail(BLTC_EINVAL, "degree must be in [1, 12]");
+  if (!(theta >= 0.0 && theta <= 1.0)) return fail(BLTC_EINVAL, "theta must be in [0, 1]");
+  return guarded([&] {
+    int64_t np = 0, nd = 0;
+    if (g->nb > 0) build_lists(t, g, theta, nullptr, &np, &nd);
+    std::vector<int32_t> pp(g->nb + 1), dp(g->nb + 1), pi(np), di(nd);
+    if (g->nb > 0) {
+      d2h(pp.data(), g->d_ptr, g->nb + 1, nullptr);
+      d2h(dp.data(), g->d_ptr + g->nb + 1, g->nb + 1, nullptr);
+      d2h(pi.data(), g->d_pids, np, nullptr);
+      d2h(di.data(), g->d_dids, nd, nullptr);
+      sync(nullptr);
+    }
+    const int64_t nk = (int64_t)(degree + 1) * (degree + 1) * (degree + 1);
+    int64_t cp = 0, cd = 0;
+    const bltc::HostTree& H = t->host;
+    for (int64_t b = 0; b < g->nb; ++b) {
+      const int64_t cnt = g->host.bptr[b + 1] - g->host.bptr[b];
+      cp += cnt * (pp[b + 1] - pp[b]) * nk;
+      int64_t leaf = 0;
+      for (int32_t k = dp[b]; k < dp[b + 1]; ++k) leaf += H.end[di[k]] - H.begin[di[k]];
+      cd += cnt * leaf;
+    }
+    if (n_proxy_evals) *n_proxy_evals = cp;
+    if (n_direct_evals) *n_direct_evals = cd;
+    return (int)BLTC_OK;
+  });
+}
+
+int bltc_direct(const double* tx, const double* ty, const double* tz,
+                int64_t m, const int64_t* idx, int64_t k, const double* sx,
+                const double* sy, const double* sz, int64_t n, const double* w,
+                int32_t kernel, double eps, const bltc_options* opt,
+                double* out, void* stream) {
+  if (int rc = check_points(tx, ty, tz, m, "targets")) return rc;
+  if (k < 0 || k > 0x7fffffffLL) return fail(BLTC_EINVAL, "k out of range [0, 2^31)");
+  if (!idx && k > m) return fail(BLTC_EINVAL, "k exceeds the number of targets");
+  if (int rc = check_points(sx, sy, sz, n, "sources")) return rc;
+  if (!valid_kernel(kernel)) return fail(BLTC_EINVAL, "unknown kernel");
+  if (!(eps >= 0.0) || !std::isfinite(eps)) return fail(BLTC_EINVAL, "eps must be finite and >= 0");
+  bltc_options o;
+  bltc_options_default(&o);
+  if (opt) o = *opt;
+  if (int rc = check_options(&o, kernel)) return rc;
+  if (o.precision != BLTC_FP64 && o.precision != BLTC_FP32_FP64ACC)
+    return fail(BLTC_EINVAL, "direct sum precision must be FP64 or FP32_FP64ACC");
+  if (idx && !device_ptr(idx)) return fail(BLTC_EINVAL, "idx must be a device pointer");
+  if (n > 0 && !device_ptr(w)) return fail(BLTC_EINVAL, "weights must be a device pointer");
+  if (k > 0 && !device_ptr(out)) return fail(BLTC_EINVAL, "out must be a device pointer");
+  return guarded([&] {
+    if (idx && k > 0) {   // every index must address a target
+      std::vector<int64_t> h(k);
+      d2h(h.data(), idx, k, (hipStream_t)stream);
+      sync((hipStream_t)stream);
+      for (int64_t v : h)
+        if (v < 0 || v >= m) throw HipError{BLTC_EINVAL, "idx entry outside [0, m)"};
+    }
+    double su, sw;
+    kernel_scales(kernel, &su, &sw);
+    hipchk(bltc::launch_direct(kernel, o.precision, tx, ty, tz, idx, k, sx, sy,
+                               sz, n, w, eps, o.poly_p, o.poly_c, su, sw, out,
+                               (hipStream_t)stream),
+           "direct");
+    return (int)BLTC_OK;
+  });
+}
+
+int bltc_profile_enable(int32_t on) {
+  g_prof.on = on != 0;
+  return BLTC_OK;
+}
+
+int bltc_profile_read(double* ms, int64_t* launches, int32_t reset) {
+  return guarded([&] {
+    double acc[BLTC_NSTAGES] = {0, 0, 0, 0};
+    int64_t cnt[BLTC_NSTAGES] = {0, 0, 0, 0};
+    for (const auto& mk : g_prof.marks) {
+      hipchk(hipEventSynchronize(mk.b), "hipEventSynchronize");
+      float t = 0.f;
+      hipchk(hipEventElapsedTime(&t, mk.a, mk.b), "hipEventElapsedTime");
+      acc[mk.stage] += t;
+      cnt[mk.stage] += 1;
+    }
+    for (int k = 0; k < BLTC_NSTAGES; ++k) {
+      if (ms) ms[k] = acc[k];
+      if (launches) launches[k] = cnt[k];
+    }
+    if (reset) {
+      for (const auto& mk : g_prof.marks) {
+        g_prof.pool.push_back(mk.a);
+        g_prof.pool.push_back(mk.b);
+      }
+      g_prof.marks.clear();
+    }
+    return (int)BLTC_OK;
+  });
+}
+
+}  // extern "C"

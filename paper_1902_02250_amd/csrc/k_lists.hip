@@ -1,0 +1,80 @@
+// Interaction lists of the batch walk (Algorithm 2 shared by the targets of
+// a batch).  One thread walks the tree for one batch depth first, children
+// in their stored order, with an explicit stack:
+//   MAC holds          -> the cluster goes on the proxy list,
+//   else leaf          -> the cluster goes on the direct list,
+//   else               -> visit the children.
+// The MAC r/R <= theta (eq. MAC) is tested for the whole batch as
+//   R2 > 0  and  (r_B + r_C)^2 <= (theta theta) R2,
+// R2 = dx dx + dy dy + dz dz from the batch center to the cluster center,
+// in FP64 without fused multiply-adds (this file is built with
+// -ffp-contract=off), so the integer lists are reproducible bit for bit.
+// The count pass sizes the lists; the fill pass writes them.
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+
+namespace bltc {
+
+namespace {
+
+template <bool FILL>
+__global__ __launch_bounds__(128) void k_lists(ListArgs a) {
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= a.nb) return;
+  const double4 g = a.bgeo[b];
+  const double th2 = a.theta * a.theta;
+  int32_t stack[kStackMax];
+  int sp = 0;
+  int32_t np = 0, nd = 0;
+  int32_t* pout = nullptr;
+  int32_t* dout = nullptr;
+  if (FILL) {
+    pout = a.pids + a.pptr[b];
+    dout = a.dids + a.dptr[b];
+  }
+  if (a.nodes.nn > 0) stack[sp++] = 0;
+  while (sp > 0) {
+    const int32_t q = stack[--sp];
+    const double4 c = a.nodes.geo[q];
+    const double dx = g.x - c.x;
+    const double dy = g.y - c.y;
+    const double dz = g.z - c.z;
+    const double R2 = dx * dx + dy * dy + dz * dz;
+    const double rr = g.w + c.w;
+    if (R2 > 0.0 && rr * rr <= th2 * R2) {
+      if (FILL) pout[np] = q;
+      ++np;
+      continue;
+    }
+    const int2 kd = a.nodes.kids[q];
+    if (kd.y == 0) {
+      if (FILL) dout[nd] = q;
+      ++nd;
+      continue;
+    }
+    if (sp + kd.y > kStackMax) {   // cannot happen for depth <= 70; guarded
+      *a.err = 1;
+      break;
+    }
+    for (int k = kd.y - 1; k >= 0; --k) stack[sp++] = kd.x + k;
+  }
+  if (!FILL) {
+    a.pcnt[b] = np;
+    a.dcnt[b] = nd;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_lists(const ListArgs& a, bool fill, hipStream_t s) {
+  if (a.nb == 0) return hipSuccess;
+  const unsigned nblk = (unsigned)((a.nb + 127) / 128);
+  if (fill)
+    hipLaunchKernelGGL(k_lists<true>, dim3(nblk), dim3(128), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_lists<false>, dim3(nblk), dim3(128), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace bltc

@@ -1,0 +1,341 @@
+// Particle-cluster evaluation over the batch interaction lists: the hot path.
+//
+// One 64-lane wave evaluates up to 64 targets of one batch (the targets are
+// in tree order, so a batch is a compact group) against the batch's shared
+// lists:
+//   proxy list:  u += sum_k K(x, s_k) fhat_k      (eq. pc_approximation_3D)
+//   direct list: u += sum_{y_j in L} K(x, y_j) f_j (eq. pc_interaction_3D)
+// Every lane handles one target; all lanes walk the same list, so cluster
+// data and sources are wave-uniform: grids and modified weights are read
+// through scalar loads, leaf sources are staged through LDS and read by
+// broadcast.  Consecutive leaves whose particle ranges touch are merged into
+// one run.
+//
+// Far field: the grid is a tensor product, so the per-axis differences
+// x - s_k1, y - s_k2, z - s_k3 are formed once per (target, cluster) in FP64
+// and rounded to FP32; r^2 of a proxy then costs one add.
+// Near field, FP32 modes: the target and the staged sources are rounded to
+// FP32 relative to the batch center (the differences are formed in FP64), so
+// the FP32 difference x - y carries an absolute error of order 1e-7 times
+// the batch size instead of the domain size.
+//
+// Kernel algebra (eq. MRS_kernels with rho^2 = r^2 + eps^2, inv = 1/rho):
+//   8 pi H1 = inv + eps^2 inv^3,          8 pi H2 = inv^3,
+//   8 pi Q  = 2 inv^3 + 3 eps^2 inv^5,
+//   8 pi D1 = 15 eps^4 inv^7 - 3 eps^2 inv^5 - 2 inv^3,
+//   8 pi D2 = 6 inv^5 + 15 eps^2 inv^7,
+// obtained by substituting r^2 = rho^2 - eps^2 in the printed forms; the
+// 1/(8 pi), 1/2 and 1/4 factors are applied once per target at the end.
+//
+// Accumulation: FP64 mode sums in FP64; FP32 modes sum each tile (one
+// cluster's proxies, or up to 64 staged sources) in FP32 and fold the tile
+// into an FP64 accumulator (BLTC_FP32_FP64ACC) or an FP32 compensated pair
+// (BLTC_FP32_KAHAN, Neumaier/Kahan TwoSum).
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+#include "bltc.h"
+#include "internal.h"
+#include "kmath.h"
+
+namespace bltc {
+
+namespace {
+
+// ---- far field ---------------------------------------------------------------
+template <int KERN, int N1, bool ZEPS, typename T, typename F>
+__device__ __forceinline__ void proxies(double x, double y, double z,
+                                        const double* __restrict__ g,
+                                        const F* __restrict__ fh, T e2,
+                                        T* p) {
+  constexpr int OD = Dims<KERN>::OD;
+  T dz[N1], dz2[N1];
+#pragma unroll
+  for (int k = 0; k < N1; ++k) {
+    dz[k] = (T)(z - g[2 * N1 + k]);
+    dz2[k] = dz[k] * dz[k];
+  }
+  for (int k1 = 0; k1 < N1; ++k1) {
+    const T dx = (T)(x - g[k1]);
+    const T dx2e = dx * dx + e2;
+    for (int k2 = 0; k2 < N1; ++k2) {
+      const T dy = (T)(y - g[N1 + k2]);
+      const T dxy2 = dy * dy + dx2e;
+      const F* __restrict__ R = fh + (k1 * N1 + k2) * 3 * N1;
+      if constexpr (KERN == KSTOKES) {
+        T S = 0, ax = 0, ay = 0, az = 0;
+#pragma unroll
+        for (int k3 = 0; k3 < N1; ++k3) {
+          const T fx = (T)R[k3], fy = (T)R[N1 + k3], fz = (T)R[2 * N1 + k3];
+          const T r2 = dxy2 + dz2[k3];
+          const T inv = inv_rho<ZEPS>(r2);
+          const T inv3 = (inv * inv) * inv;
+          const T fd = fz * dz[k3] + (fy * dy + fx * dx);
+          const T h1 = e2 * inv3 + inv;
+          const T s = fd * inv3;
+          ax = fx * h1 + ax;
+          ay = fy * h1 + ay;
+          az = fz * h1 + az;
+          az = dz[k3] * s + az;
+          S += s;
+        }
+        p[0] += dx * S + ax;
+        p[1] += dy * S + ay;
+        p[2] += az;
+      } else {
+        T a[OD];
+#pragma unroll
+        for (int c = 0; c < OD; ++c) a[c] = 0;
+#pragma unroll
+        for (int k3 = 0; k3 < N1; ++k3)
+          pair<KERN, ZEPS, T>(dx, dy, dz[k3], dxy2 + dz2[k3], e2, (T)R[k3],
+                              (T)R[N1 + k3], (T)R[2 * N1 + k3], a);
+#pragma unroll
+        for (int c = 0; c < OD; ++c) p[c] += a[c];
+      }
+    }
+  }
+}
+
+// Polynomial test kernel (FP64): (c + x.s)^p with s the grid point.
+template <int N1>
+__device__ __forceinline__ void proxies_poly(double x, double y, double z,
+                                             const double* __restrict__ g,
+                                             const double* __restrict__ fh,
+                                             int pp, double pc, double* p) {
+  for (int k1 = 0; k1 < N1; ++k1)
+    for (int k2 = 0; k2 < N1; ++k2) {
+      const double* __restrict__ R = fh + (k1 * N1 + k2) * 3 * N1;
+#pragma unroll
+      for (int k3 = 0; k3 < N1; ++k3) {
+        double dot = x * g[k1];
+        dot = dot + y * g[N1 + k2];
+        dot = dot + z * g[2 * N1 + k3];
+        const double base = pc + dot;
+        double v = 1.0;
+        for (int e = 0; e < pp; ++e) v *= base;
+        p[0] += v * R[k3];
+        p[1] += v * R[N1 + k3];
+        p[2] += v * R[2 * N1 + k3];
+      }
+    }
+}
+
+// ---- accumulators --------------------------------------------------------------
+template <int PREC, int OD>
+struct Acc {
+  double s[OD];
+  float hi[OD], lo[OD];
+  __device__ void init() {
+#pragma unroll
+    for (int c = 0; c < OD; ++c) { s[c] = 0.0; hi[c] = 0.f; lo[c] = 0.f; }
+  }
+  template <typename T>
+  __device__ void fold(const T* p) {
+#pragma unroll
+    for (int c = 0; c < OD; ++c) {
+      if (PREC == BLTC_FP32_KAHAN) {
+        const float v = (float)p[c];
+        const float t = hi[c] + v;
+        const float bp = t - hi[c];
+        lo[c] += (hi[c] - (t - bp)) + (v - bp);
+        hi[c] = t;
+      } else {
+        s[c] += (double)p[c];
+      }
+    }
+  }
+  __device__ double get(int c) const {
+    return PREC == BLTC_FP32_KAHAN ? (double)hi[c] + (double)lo[c] : s[c];
+  }
+};
+
+// Blocks are dispatched round robin over the 8 XCDs; give each XCD a
+// contiguous range of batches so neighbouring batches, which share most of
+// their lists, share an L2.
+__device__ __forceinline__ int xcd_block(int blk, int nblk) {
+  const int per = nblk / 8, rem = nblk % 8;
+  const int xcd = blk % 8, idx = blk / 8;
+  return xcd * per + min(xcd, rem) + idx;
+}
+
+template <int KERN, int PREC, int N1, bool ZEPS>
+__global__ __launch_bounds__(64) void k_p2p(
+    const double* __restrict__ tx, int64_t m, const int32_t* __restrict__ tperm,
+    const int32_t* __restrict__ bptr, const double4* __restrict__ bgeo,
+    int nblk, int wpb, const int32_t* __restrict__ pptr,
+    const int32_t* __restrict__ pids, const int32_t* __restrict__ dptr,
+    const int32_t* __restrict__ dids, const int2* __restrict__ range,
+    const double* __restrict__ grid, const float* __restrict__ fh32,
+    const double* __restrict__ fh64, const double* __restrict__ ys,
+    const float* __restrict__ w32, const double* __restrict__ w64, int64_t n,
+    double eps, int poly_p, double poly_c, double su, double sw,
+    double* __restrict__ out) {
+  constexpr int OD = Dims<KERN>::OD;
+  constexpr int NK = N1 * N1 * N1;
+  constexpr bool F64 = PREC == BLTC_FP64;
+  using T = typename std::conditional<F64, double, float>::type;
+  __shared__ T sA[4][64];
+  __shared__ T sB[2][64];
+
+  const int blk = xcd_block(blockIdx.x, nblk);
+  const int b = blk / wpb, wv = blk % wpb;
+  const int t0 = bptr[b] + wv * 64, t1 = bptr[b + 1];
+  if (t0 >= t1) return;
+  const int lane = threadIdx.x;
+  const int ti = t0 + lane;
+  const bool active = ti < t1;
+  const int tc = active ? ti : t0;
+  const double x = tx[tc], y = tx[m + tc], z = tx[2 * m + tc];
+  const double4 cb = bgeo[b];
+  const T e2 = (T)(eps * eps);
+
+  Acc<PREC, OD> acc;
+  acc.init();
+
+  // far field
+  for (int li = pptr[b]; li < pptr[b + 1]; ++li) {
+    const int q = pids[li];
+    const double* __restrict__ g = grid + (int64_t)q * 3 * N1;
+    T p[OD];
+#pragma unroll
+    for (int c = 0; c < OD; ++c) p[c] = 0;
+    if constexpr (KERN == KPOLY)
+      proxies_poly<N1>(x, y, z, g, fh64 + (int64_t)q * 3 * NK, poly_p, poly_c, p);
+    else if constexpr (F64)
+      proxies<KERN, N1, ZEPS, T, double>(x, y, z, g, fh64 + (int64_t)q * 3 * NK, e2, p);
+    else
+      proxies<KERN, N1, ZEPS, T, float>(x, y, z, g, fh32 + (int64_t)q * 3 * NK, e2, p);
+    acc.fold(p);
+  }
+
+  // near field: runs of contiguous leaf particles, staged 64 at a time
+  const T xr = F64 ? (T)x : (T)(x - cb.x);
+  const T yr = F64 ? (T)y : (T)(y - cb.y);
+  const T zr = F64 ? (T)z : (T)(z - cb.z);
+  int li = dptr[b];
+  const int le = dptr[b + 1];
+  while (li < le) {
+    const int2 r0 = range[dids[li]];
+    int rb = r0.x, re = r0.y;
+    ++li;
+    while (li < le) {
+      const int2 r1 = range[dids[li]];
+      if (r1.x != re) break;
+      re = r1.y;
+      ++li;
+    }
+    for (int s0 = rb; s0 < re; s0 += 64) {
+      const int j = s0 + lane;
+      if (j < re) {
+        if constexpr (F64) {
+          sA[0][lane] = (T)ys[j];
+          sA[1][lane] = (T)ys[n + j];
+          sA[2][lane] = (T)ys[2 * n + j];
+          sA[3][lane] = (T)w64[j];
+          sB[0][lane] = (T)w64[n + j];
+          sB[1][lane] = (T)w64[2 * n + j];
+        } else {
+          sA[0][lane] = (T)(ys[j] - cb.x);
+          sA[1][lane] = (T)(ys[n + j] - cb.y);
+          sA[2][lane] = (T)(ys[2 * n + j] - cb.z);
+          sA[3][lane] = (T)w32[j];
+          sB[0][lane] = (T)w32[n + j];
+          sB[1][lane] = (T)w32[2 * n + j];
+        }
+      }
+      __syncthreads();
+      const int cnt = min(64, re - s0);
+      T p[OD];
+#pragma unroll
+      for (int c = 0; c < OD; ++c) p[c] = 0;
+      if constexpr (KERN == KPOLY) {
+        for (int jj = 0; jj < cnt; ++jj) {
+          double dot = x * (double)sA[0][jj];
+          dot = dot + y * (double)sA[1][jj];
+          dot = dot + z * (double)sA[2][jj];
+          const double base = poly_c + dot;
+          double v = 1.0;
+          for (int e = 0; e < poly_p; ++e) v *= base;
+          p[0] += (T)(v * (double)sA[3][jj]);
+          p[1] += (T)(v * (double)sB[0][jj]);
+          p[2] += (T)(v * (double)sB[1][jj]);
+        }
+      } else {
+#pragma unroll 4
+        for (int jj = 0; jj < cnt; ++jj) {
+          const T dx = xr - sA[0][jj];
+          const T dy = yr - sA[1][jj];
+          const T dz = zr - sA[2][jj];
+          const T r2 = dz * dz + (dy * dy + (dx * dx + e2));
+          pair<KERN, ZEPS, T>(dx, dy, dz, r2, e2, sA[3][jj], sB[0][jj],
+                              sB[1][jj], p);
+        }
+      }
+      acc.fold(p);
+      __syncthreads();
+    }
+  }
+
+  if (active) {
+    const int64_t o = tperm[ti];
+#pragma unroll
+    for (int c = 0; c < OD; ++c) out[c * m + o] = acc.get(c) * (c < 3 ? su : sw);
+  }
+}
+
+template <int KERN, int PREC, int N1>
+hipError_t run_p2p(const P2PArgs& a, hipStream_t s) {
+  const int64_t nblk64 = a.nb * (int64_t)a.wpb;
+  if (nblk64 > 0x7fffffff) return hipErrorInvalidValue;
+  const int nblk = (int)nblk64;
+  const bool zeps = a.eps == 0.0;
+  auto go = [&](auto kern) {
+    hipLaunchKernelGGL(kern, dim3(nblk), dim3(64), 0, s, a.tx, a.m, a.tperm,
+                       a.bptr, a.bgeo, nblk, a.wpb, a.pptr, a.pids, a.dptr,
+                       a.dids, a.range, a.grid, (const float*)a.fhat,
+                       (const double*)a.fhat, a.ys, a.w32, a.w64, a.n, a.eps,
+                       a.poly_p, a.poly_c, a.scale_u, a.scale_w, a.out);
+  };
+  if (zeps)
+    go(k_p2p<KERN, PREC, N1, true>);
+  else
+    go(k_p2p<KERN, PREC, N1, false>);
+  return hipGetLastError();
+}
+
+template <int KERN, int PREC>
+hipError_t dispatch_degree(int degree, const P2PArgs& a, hipStream_t s) {
+  switch (degree + 1) {
+#define BLTC_P2P(N) \
+  case N:           \
+    return run_p2p<KERN, PREC, N>(a, s);
+    BLTC_P2P(2) BLTC_P2P(3) BLTC_P2P(4) BLTC_P2P(5) BLTC_P2P(6) BLTC_P2P(7)
+    BLTC_P2P(8) BLTC_P2P(9) BLTC_P2P(10) BLTC_P2P(11) BLTC_P2P(12) BLTC_P2P(13)
+#undef BLTC_P2P
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_p2p(int kernel, int precision, int degree, const P2PArgs& a,
+                      hipStream_t s) {
+  if (a.nb == 0) return hipSuccess;
+  if (kernel == KPOLY) {
+    if (precision != BLTC_FP64) return hipErrorInvalidValue;
+    return dispatch_degree<KPOLY, BLTC_FP64>(degree, a, s);
+  }
+  if (kernel == KSTOKES) {
+    if (precision == BLTC_FP64) return dispatch_degree<KSTOKES, BLTC_FP64>(degree, a, s);
+    if (precision == BLTC_FP32_FP64ACC) return dispatch_degree<KSTOKES, BLTC_FP32_FP64ACC>(degree, a, s);
+    return dispatch_degree<KSTOKES, BLTC_FP32_KAHAN>(degree, a, s);
+  }
+  if (precision == BLTC_FP64) return dispatch_degree<KROT, BLTC_FP64>(degree, a, s);
+  if (precision == BLTC_FP32_FP64ACC) return dispatch_degree<KROT, BLTC_FP32_FP64ACC>(degree, a, s);
+  return dispatch_degree<KROT, BLTC_FP32_KAHAN>(degree, a, s);
+}
+
+}  // namespace bltc

@@ -1,0 +1,250 @@
+"""GPU parity of the HIP path against the CPU oracle (through the C ABI).
+
+Integer work (trees, batches, interaction lists, direct sums on integer data)
+must be bit-exact.  FP64 velocities must agree with the oracle's FP64
+treecode on the same batches to a relative L2 error of 1e-12; FP32 modes to
+the bound derived from FP32 rounding (see MIXED_TOL).  Sizes span several
+tiles, ragged tails and the parameter limits.
+"""
+import numpy as np
+import pytest
+
+from paper_1902_02250_amd import bltc, inputs
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-12
+# FP32 evaluation: every term carries a relative rounding error of a few
+# units of 2^-24 (6e-8) and the differences x - y an absolute error of about
+# 6e-8 times the batch size; summed in FP64 this stays near 1e-7 relative.
+MIXED_TOL = 1e-6
+# eps = 0 (singular kernels): a term's rounding error grows like the FP32
+# error of d divided by r, up to 3x for the r^-3 parts of the rotlet, so the
+# nearest pairs dominate; a tenfold looser bound covers the closest pairs of
+# these small sets.
+SINGULAR_MIXED_TOL = 1e-5
+
+TREE_KEYS = ["perm", "box", "center", "radius", "child_first", "child_count",
+             "pbegin", "pend", "level"]
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available(), "GPU tests need a GPU"
+    bltc.load()
+    return t
+
+
+def _d(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def _gpu_tree(torch, src, w, leaf, degree):
+    T = bltc.Tree(_d(torch, src), leaf)
+    T.compute_weights(_d(torch, w), degree)
+    return T
+
+
+@pytest.mark.parametrize("dist,n,leaf", [("uniform", 8000, 500), ("mixture", 20000, 150),
+                                         ("union", 6001, 9)])
+def test_tree_and_batches_bit_exact(torch, orc, dist, n, leaf):
+    p = inputs.points(dist, n, 31)
+    T = bltc.Tree(_d(torch, p), leaf)
+    a = T.export()
+    R = orc.Tree(p, leaf)
+    assert T.depth == R.depth and T.nnodes == R.nnodes
+    for k in TREE_KEYS:
+        assert np.array_equal(a[k], getattr(R, k)), k
+    for bs, ol in [(64, 64), (100, 40), (1, 64)]:
+        g = bltc.Targets(_d(torch, p), bs, ol).export()
+        ob = orc.batches(p, bs, ol)
+        for x, y in zip([g["tperm"], g["bptr"], g["bcenter"], g["bradius"]], ob):
+            assert np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("degree", [1, 4, 8, 12])
+@pytest.mark.parametrize("dist,n,leaf", [("uniform", 9000, 700), ("mixture", 7000, 60)])
+def test_modified_weights(torch, orc, degree, dist, n, leaf):
+    p = inputs.points(dist, n, 5)
+    w = inputs.weights(n, 5)
+    T = _gpu_tree(torch, p, w, leaf, degree)
+    f, g = T.weights_export(degree)
+    R = orc.Tree(p, leaf)
+    assert np.array_equal(g, R.grids(degree))
+    ref = R.modified_weights(w, degree)
+    for q in range(R.nnodes):
+        scale = np.abs(ref[q]).max()
+        assert np.abs(f[q] - ref[q]).max() <= FP64_TOL * scale, q
+
+
+def test_modified_weights_exact_hits(torch, orc):
+    """Particles on grid points and box faces take the exact-hit branch."""
+    n = 4
+    lo, hi = np.array([-1.0, -0.5, 0.25]), np.array([1.0, 1.5, 2.25])
+    t = orc.cheb_points(n)
+    s = 0.5 * (lo + hi)[:, None] + (0.5 * (hi - lo))[:, None] * t[None, :]
+    rng = np.random.default_rng(2)
+    inner = lo[:, None] + (hi - lo)[:, None] * rng.uniform(size=(3, 200))
+    on_nodes = np.stack([s[0, rng.integers(0, n + 1, 50)], s[1, rng.integers(0, n + 1, 50)],
+                         s[2, rng.integers(0, n + 1, 50)]])
+    p = np.concatenate([lo[:, None], hi[:, None], on_nodes, inner], axis=1)
+    w = inputs.weights(p.shape[1], 9)
+    T = _gpu_tree(torch, p, w, 1000, n)
+    f, _ = T.weights_export(n)
+    ref = orc.Tree(p, 1000).modified_weights(w, n)
+    assert np.abs(f - ref).max() <= FP64_TOL * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("theta", [0.0, 0.3, 0.7, 1.0])
+@pytest.mark.parametrize("bs", [1, 64, 100])
+def test_lists_bit_exact(torch, orc, theta, bs):
+    src = inputs.points("mixture", 12000, 41)
+    tgt = inputs.points("uniform", 3001, 42) * 1.2
+    w = inputs.weights(12000, 41)
+    T = _gpu_tree(torch, src, w, 120, 3)
+    G = bltc.Targets(_d(torch, tgt), bs, 64)
+    L = bltc.lists(T, G, theta)
+    R = orc.lists(src, 120, tgt, theta, bs, 64)
+    for k in ["prox_ptr", "prox_ids", "dir_ptr", "dir_ids"]:
+        assert np.array_equal(L[k], R[k]), k
+
+
+@pytest.mark.parametrize("kernel", ["stokeslet", "rotlet"])
+def test_direct_fp64(torch, orc, kernel):
+    src = inputs.points("uniform", 5003, 3)
+    w = inputs.weights(5003, 3)
+    tgt = inputs.points("mixture", 777, 4)
+    got = bltc.direct(_d(torch, tgt), _d(torch, src), _d(torch, w), kernel, 0.01).cpu().numpy()
+    ref = orc.direct(kernel, tgt, src, w, eps=0.01)
+    assert orc.rel_l2(ref, got) <= FP64_TOL
+    idx = inputs.sample_indices(777, 50, 1)
+    sub = bltc.direct(_d(torch, tgt), _d(torch, src), _d(torch, w), kernel, 0.01,
+                      idx=torch.from_numpy(idx).cuda()).cpu().numpy()
+    assert np.array_equal(sub, got[:, idx])
+    m32 = bltc.direct(_d(torch, tgt), _d(torch, src), _d(torch, w), kernel, 0.01,
+                      precision="fp32_fp64acc").cpu().numpy()
+    assert orc.rel_l2(ref, m32) <= MIXED_TOL
+
+
+def test_direct_poly_integer_bit_exact(torch, orc):
+    rng = np.random.default_rng(8)
+    src = rng.integers(-4, 5, (3, 3000)).astype(np.float64)
+    w = rng.integers(-6, 7, (3, 3000)).astype(np.float64)
+    got = bltc.direct(_d(torch, src), _d(torch, src), _d(torch, w), "poly", 0.0,
+                      poly_p=3, poly_c=2.0).cpu().numpy()
+    ref = orc.direct("poly", src, src, w, poly_p=3, poly_c=2.0)
+    assert np.array_equal(got, ref)
+
+
+def _tree_case(torch, orc, kernel, src, tgt, w, eps, degree, theta, leaf, bs, ol,
+               precision="fp64", **kw):
+    T = _gpu_tree(torch, src, w, leaf, degree)
+    G = bltc.Targets(_d(torch, tgt), bs, ol)
+    got = bltc.evaluate_tree(T, G, kernel, eps, degree, theta, precision=precision,
+                             **kw).cpu().numpy()
+    ref, npx, ndr = orc.treecode(kernel, tgt, src, w, eps, degree, theta, leaf, mac_mode=1,
+                                 batch_size=bs, order_leaf=ol, **kw)
+    cp, cd = bltc.counts(T, G, degree, theta)
+    assert (cp, cd) == (npx, ndr)
+    return got, ref
+
+
+@pytest.mark.parametrize("kernel", ["stokeslet", "rotlet"])
+def test_treecode_fp64_c1(torch, orc, kernel):
+    """The small workload (8000 uniform points, n = 4, theta = 0.7, N0 = 500)."""
+    src, w, cfg = inputs.workload("c1")
+    got, ref = _tree_case(torch, orc, kernel, src, src, w, cfg["eps"], cfg["degree"],
+                          cfg["theta"], cfg["leaf"], 64, 64)
+    assert orc.rel_l2(ref, got) <= FP64_TOL
+
+
+@pytest.mark.parametrize("kernel,degree,theta,bs,ol", [
+    ("stokeslet", 1, 0.9, 100, 30), ("stokeslet", 12, 0.5, 1024, 500),
+    ("rotlet", 7, 0.7, 64, 16), ("stokeslet", 6, 1.0, 1, 64), ("rotlet", 3, 0.0, 64, 64)])
+def test_treecode_fp64_ragged(torch, orc, kernel, degree, theta, bs, ol):
+    src = inputs.points("mixture", 10007, 12)
+    w = inputs.weights(10007, 12)
+    tgt = inputs.points("union", 3001 if bs > 1 else 700, 13) * 1.1
+    got, ref = _tree_case(torch, orc, kernel, src, tgt, w, 0.02, degree, theta, 200, bs, ol)
+    assert orc.rel_l2(ref, got) <= FP64_TOL
+
+
+def test_treecode_poly(torch, orc):
+    """Polynomial kernel: with p <= n the treecode equals the direct sum; on
+    integer data with theta = 0 every sum is exact, so GPU == oracle bit for
+    bit."""
+    src = inputs.points("uniform", 6000, 2)
+    w = inputs.weights(6000, 2)
+    got, ref = _tree_case(torch, orc, "poly", src, src, w, 0.0, 4, 0.7, 150, 64, 64,
+                          poly_p=4, poly_c=1.5)
+    assert orc.rel_l2(ref, got) <= FP64_TOL
+    d = orc.direct("poly", src, src, w, poly_p=4, poly_c=1.5)
+    assert orc.rel_l2(d, got) <= FP64_TOL
+    rng = np.random.default_rng(3)
+    isrc = rng.integers(-3, 4, (3, 2000)).astype(np.float64)
+    iw = rng.integers(-5, 6, (3, 2000)).astype(np.float64)
+    got, ref = _tree_case(torch, orc, "poly", isrc, isrc, iw, 0.0, 2, 0.0, 40, 64, 64,
+                          poly_p=2, poly_c=1.0)
+    assert np.array_equal(got, ref)
+
+
+@pytest.mark.parametrize("precision", ["fp32_fp64acc", "fp32_kahan"])
+@pytest.mark.parametrize("kernel", ["stokeslet", "rotlet"])
+def test_treecode_mixed(torch, orc, precision, kernel):
+    src, w, cfg = inputs.workload("c1", n=20000)
+    got, ref = _tree_case(torch, orc, kernel, src, src, w, 0.005, 6, 0.7, 500, 64, 64,
+                          precision=precision)
+    assert orc.rel_l2(ref, got) <= MIXED_TOL
+
+
+def test_edge_cases(torch, orc):
+    # no targets
+    src, w, _ = inputs.workload("c1", n=500)
+    T = _gpu_tree(torch, src, w, 50, 3)
+    G = bltc.Targets(_d(torch, np.zeros((3, 0))), 64, 64)
+    out = bltc.evaluate_tree(T, G, "stokeslet", 0.01, 3, 0.7)
+    assert out.shape == (3, 0)
+    # no sources: zero velocity
+    T0 = _gpu_tree(torch, np.zeros((3, 0)), np.zeros((3, 0)), 50, 3)
+    G1 = bltc.Targets(_d(torch, src), 64, 64)
+    assert torch.count_nonzero(bltc.evaluate_tree(T0, G1, "rotlet", 0.01, 3, 0.7)).item() == 0
+    # one source; all sources on one point; targets far outside the box
+    far = inputs.points("uniform", 300, 7) * 0.1 + 5.0
+    for s in (src[:, :1], np.repeat(src[:, :1], 40, axis=1), src):
+        ws = w[:, :s.shape[1]]
+        for tg in (far, src):
+            got, ref = _tree_case(torch, orc, "stokeslet", s, tg, ws, 0.01, 5, 0.7, 30, 64, 64)
+            assert orc.rel_l2(ref, got) <= FP64_TOL
+    # eps = 0 with coincident targets and sources: the self term is dropped
+    got, ref = _tree_case(torch, orc, "stokeslet", src, src, w, 0.0, 5, 0.7, 50, 64, 64)
+    assert np.all(np.isfinite(got)) and orc.rel_l2(ref, got) <= FP64_TOL
+    got, ref = _tree_case(torch, orc, "rotlet", src, src, w, 0.0, 5, 0.7, 50, 64, 64,
+                          precision="fp32_fp64acc")
+    assert np.all(np.isfinite(got)) and orc.rel_l2(ref, got) <= SINGULAR_MIXED_TOL
+
+
+def test_one_call_evaluate(torch, orc):
+    src = inputs.points("uniform", 4000, 77)
+    w = inputs.weights(4000, 77)
+    tgt = inputs.points("mixture", 999, 78)
+    got = bltc.evaluate(_d(torch, tgt), _d(torch, src), _d(torch, w), "rotlet", 0.03, 5, 0.8,
+                        300, batch_size=128, order_leaf=32).cpu().numpy()
+    ref, _, _ = orc.treecode("rotlet", tgt, src, w, 0.03, 5, 0.8, 300, mac_mode=1,
+                             batch_size=128, order_leaf=32)
+    assert orc.rel_l2(ref, got) <= FP64_TOL
+
+
+def test_errors_on_device(torch):
+    src, w, _ = inputs.workload("c1", n=500)
+    T = bltc.Tree(_d(torch, src), 50)
+    G = bltc.Targets(_d(torch, src), 64, 64)
+    with pytest.raises(bltc.BltcError) as e:
+        bltc.evaluate_tree(T, G, "stokeslet", 0.01, 3, 0.7)
+    assert e.value.status == 4   # no weights yet
+    T.compute_weights(_d(torch, w), 3)
+    with pytest.raises(bltc.BltcError) as e:
+        bltc.evaluate_tree(T, G, "stokeslet", 0.01, 5, 0.7)
+    assert e.value.status == 4   # degree 5 not computed
+    with pytest.raises(TypeError):
+        bltc.Tree(torch.zeros((3, 10), dtype=torch.float32, device="cuda"), 5)
