@@ -40,6 +40,33 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_p2p_stokeslet_n1e6_hbm_traffic.md")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1902_02250_amd", "csrc", f)
+                  for f in ("k_p2p.hip", "kmath.h")]
+
+
+def measured_traffic(args, cfg):
+    """HBM bytes per launch of the evaluation kernel from the committed
+    rocprofv3 FETCH_SIZE / WRITE_SIZE summary, or None when that summary is
+    for another workload or the kernel sources changed since it was taken."""
+    import hashlib
+    if (args.workload, cfg["n"], cfg["degree"], args.precision, args.batch_size) != \
+            ("c3", 1000000, 8, "fp32_fp64acc", 64) or not os.path.exists(TRAFFIC_FILE):
+        return None
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(f, "rb").read())
+    rec = {}
+    for line in open(TRAFFIC_FILE):
+        if ":" in line and line.split(":")[0] in ("traffic_bytes_per_launch",
+                                                   "kernel_source_sha256"):
+            k, v = line.split(":", 1)
+            rec[k] = v.strip()
+    if rec.get("kernel_source_sha256") != h.hexdigest():
+        return None
+    return float(rec["traffic_bytes_per_launch"])
+
+
 def cpu_baseline(cfg, src, w, sample_k, precision_label):
     """The FP64 oracle treecode (tree, Algorithm 1 weights for all sources,
     batch walk for a target sample) timed on the host cores."""
@@ -51,7 +78,7 @@ def cpu_baseline(cfg, src, w, sample_k, precision_label):
     t0 = time.perf_counter()
     _, npx, ndr = oracle.treecode(cfg["kernel"], src, src, w, cfg["eps"], cfg["degree"],
                                   cfg["theta"], cfg["leaf"], mac_mode=1, batch_size=64,
-                                  order_leaf=64, sample=idx)
+                                  order_leaf=32, group_max=512, sample=idx)
     dt = time.perf_counter() - t0
     return {"value": (npx + ndr) / dt, "unit": "interactions/s", "cores": threads,
             "kind": "oracle",
@@ -74,9 +101,14 @@ def main():
     ap.add_argument("--degree", type=int, default=None)
     ap.add_argument("--theta", type=float, default=None)
     ap.add_argument("--batch-size", type=int, default=64)
+    ap.add_argument("--order-leaf", type=int, default=32)
+    ap.add_argument("--group-max", type=int, default=512)
     ap.add_argument("--err-sample", type=int, default=10000)
     ap.add_argument("--cpu-sample", type=int, default=65536)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="first run one device-to-device copy of MIB MiB, the reference "
+                         "for scaling HBM byte counters")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -92,6 +124,15 @@ def main():
     from paper_1902_02250_amd import bltc, inputs
 
     bltc.load()
+    if args.calibrate_copy > 0:
+        nbytes = args.calibrate_copy << 20
+        a = torch.ones(nbytes, dtype=torch.uint8, device="cuda:0")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"[bench] calibration copy: {nbytes} bytes read and {nbytes} bytes written")
+        del a, b
     cfg = dict(inputs.CONFIGS[args.workload])
     if args.n:
         cfg["n"] = args.n
@@ -113,7 +154,7 @@ def main():
     t0 = time.perf_counter()
     tree = bltc.Tree(d_src, cfg["leaf"])
     t1 = time.perf_counter()
-    tg = bltc.Targets(d_src, args.batch_size, args.batch_size)
+    tg = bltc.Targets(d_src, args.batch_size, args.order_leaf, args.group_max)
     t2 = time.perf_counter()
     log(f"[bench] tree: {tree.nnodes} clusters, depth {tree.depth} ({(t1 - t0) * 1e3:.0f} ms); "
         f"targets: {tg.nb} batches ({(t2 - t1) * 1e3:.0f} ms)")
@@ -162,7 +203,7 @@ def main():
     achieved = flops / (ev_ms * 1e-3) / 1e12
     pk = PEAK["fp64" if args.precision == "fp64" else "fp32"]
     roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": pk, "unit": "TFLOP/s",
-            "frac": round(achieved / pk, 4), "traffic": None,
+            "frac": round(achieved / pk, 4), "traffic": measured_traffic(args, cfg),
             "kernel": f"k_p2p ({kernel}, {args.precision}, n={degree})",
             "per_launch": f"{inter} kernel evaluations x {FLOPS.get(kernel, 32)} flop",
             "avg_launch_ms": round(ev_ms, 4)}
@@ -182,7 +223,8 @@ def main():
                                 f"{args.precision}, batch {args.batch_size}"),
                    "n": n, "kernel": kernel, "eps": eps, "degree": degree, "theta": theta,
                    "leaf": cfg["leaf"], "precision": args.precision,
-                   "batch_size": args.batch_size},
+                   "batch_size": args.batch_size, "order_leaf": args.order_leaf,
+                   "group_max": args.group_max},
         "eval_s": round(ms * 1e-3, 6),
         "interactions_per_step": inter,
         "direct_equivalent_per_s": float(n) * n / (ms * 1e-3),

@@ -43,6 +43,7 @@
  *   - Handles are not thread safe; different handles may be used from
  *     different threads.
  *   - Sizes: n, m < 2^31; degree 1..12; leaf_max >= 1; batch_size 1..1024;
+ *     order_leaf >= 1; group_max >= 1;
  *     0 <= theta <= 1; eps >= 0.  n = 0 or m = 0 is a valid no-op.
  */
 #ifndef BLTC_H
@@ -75,9 +76,10 @@ typedef struct {
   int32_t size;        /* sizeof(bltc_options) */
   int32_t precision;   /* BLTC_FP64 (default) or a mixed mode */
   int32_t batch_size;  /* targets sharing one walk, default 64 */
-  int32_t order_leaf;  /* leaf size of the tree that orders the targets, default 64 */
+  int32_t order_leaf;  /* leaf size of the tree that orders the targets, default 32 */
   int32_t poly_p;      /* BLTC_POLY exponent, default 2 */
   double poly_c;       /* BLTC_POLY constant, default 1 */
+  int64_t group_max;   /* batches never span two target groups, default 512 */
 } bltc_options;
 
 typedef struct bltc_tree_s* bltc_tree;       /* sources: tree, weights */
@@ -129,13 +131,15 @@ int bltc_modified_weights_export(bltc_tree t, int32_t degree, double* fhat,
 
 /* ---- targets -------------------------------------------------------------
  * Orders the m targets by a tree built with the same rules and leaf size
- * order_leaf, then cuts that order into consecutive batches of batch_size
- * targets; each batch gets its tight box, center and radius like a cluster.
- * Built on the host (synchronises); the order and batches live on the
- * device. */
+ * order_leaf.  The maximal nodes of that tree with at most group_max targets
+ * (and any larger degenerate leaf) are the groups; each group is cut into
+ * consecutive batches of batch_size targets, so a batch never spans two
+ * groups and its radius is bounded by its group's.  Each batch gets its
+ * tight box, center and radius like a cluster.  Built on the host
+ * (synchronises); the order and batches live on the device. */
 int bltc_build_targets(const double* x, const double* y, const double* z,
                        int64_t m, int32_t batch_size, int32_t order_leaf,
-                       void* stream, bltc_targets* out);
+                       int64_t group_max, void* stream, bltc_targets* out);
 int bltc_targets_destroy(bltc_targets g);
 /* Host copies (synchronises): number of batches, tperm[m] (target position
  * -> input index), bptr[nb+1], bcenter[nb][3], bradius[nb]. */
@@ -154,8 +158,8 @@ int bltc_host_tree(const double* hx, const double* hy, const double* hz,
                    int64_t* pbegin, int64_t* pend, int32_t* level);
 int bltc_host_batches(const double* hx, const double* hy, const double* hz,
                       int64_t m, int32_t batch_size, int32_t order_leaf,
-                      int64_t* nb, int64_t* tperm, int64_t* bptr,
-                      double* bcenter, double* bradius);
+                      int64_t group_max, int64_t* nb, int64_t* tperm,
+                      int64_t* bptr, double* bcenter, double* bradius);
 
 /* ---- evaluation ----------------------------------------------------------
  * Walks the tree for every batch under the MAC with parameter theta (device

@@ -58,7 +58,7 @@ def _load():
     L.orc_tree_depth.argtypes = [P]
     L.orc_tree_depth.restype = I32
     L.orc_tree_export.argtypes = [P] * 11
-    L.orc_batches.argtypes = [P, P, P, I64, I64, I64, P, P, P, P]
+    L.orc_batches.argtypes = [P, P, P, I64, I64, I64, I64, P, P, P, P]
     L.orc_batches.restype = I64
     L.orc_cheb_points.argtypes = [ctypes.c_int, P]
     L.orc_bary_weights.argtypes = [ctypes.c_int, P]
@@ -69,7 +69,8 @@ def _load():
                                        ctypes.c_int, ctypes.c_int, P]
     L.orc_treecode.argtypes = [P, P, P, P, I64, P, P, P, I64, P, P, I64, P,
                                P, P]
-    L.orc_lists_new.argtypes = [P, P, P, I64, I64, P, P, P, I64, D, I64, I64]
+    L.orc_lists_new.argtypes = [P, P, P, I64, I64, P, P, P, I64, D, I64, I64,
+                                I64]
     L.orc_lists_new.restype = P
     L.orc_lists_sizes.argtypes = [P, P, P, P]
     L.orc_lists_export.argtypes = [P] * 7
@@ -93,7 +94,8 @@ class _Params(ctypes.Structure):
                 ("poly_p", ctypes.c_int), ("poly_c", ctypes.c_double),
                 ("degree", ctypes.c_int), ("theta", ctypes.c_double),
                 ("leaf_max", ctypes.c_int64), ("mac_mode", ctypes.c_int),
-                ("batch_size", ctypes.c_int64), ("order_leaf", ctypes.c_int64)]
+                ("batch_size", ctypes.c_int64), ("order_leaf", ctypes.c_int64),
+                ("group_max", ctypes.c_int64)]
 
 
 # ---- kernels ----------------------------------------------------------------
@@ -196,19 +198,20 @@ class Tree:
             self._h = None
 
 
-def batches(tgt, batch_size, order_leaf):
+def batches(tgt, batch_size, order_leaf, group_max=512):
     """Target batches: (tperm, bptr, bcenter, bradius)."""
     tgt = _c(tgt)
     m = tgt.shape[1]
-    nbmax = (m + batch_size - 1) // batch_size
+    L = _load()
+    args = [_p(tgt[0]), _p(tgt[1]), _p(tgt[2]), m, int(batch_size), int(order_leaf),
+            int(group_max)]
+    nb = L.orc_batches(*args, None, None, None, None)
     tperm = np.zeros(m, np.int64)
-    bptr = np.zeros(nbmax + 1, np.int64)
-    bc = np.zeros((max(nbmax, 1), 3))
-    br = np.zeros(max(nbmax, 1))
-    nb = _load().orc_batches(_p(tgt[0]), _p(tgt[1]), _p(tgt[2]), m,
-                             int(batch_size), int(order_leaf), _p(tperm),
-                             _p(bptr), _p(bc), _p(br))
-    return tperm, bptr[:nb + 1], bc[:nb], br[:nb]
+    bptr = np.zeros(nb + 1, np.int64)
+    bc = np.zeros((max(nb, 1), 3))
+    br = np.zeros(max(nb, 1))
+    L.orc_batches(*args, _p(tperm), _p(bptr), _p(bc), _p(br))
+    return tperm, bptr, bc[:nb], br[:nb]
 
 
 # ---- 1D interpolation -------------------------------------------------------
@@ -240,14 +243,15 @@ def lagrange_product(n, s, t):
 
 # ---- treecode ---------------------------------------------------------------
 def treecode(kernel, tgt, src, w, eps, degree, theta, leaf_max, mac_mode=0,
-             batch_size=64, order_leaf=64, sample=None, poly_p=0, poly_c=0.0):
+             batch_size=64, order_leaf=64, group_max=512, sample=None, poly_p=0,
+             poly_c=0.0):
     """Algorithm 2.  Returns (out (odim, m or len(sample)), n_proxy_evals,
     n_direct_evals)."""
     tgt, src, w = _c(tgt), _c(src), _c(w)
     m, n = tgt.shape[1], src.shape[1]
     prm = _Params(KERNELS[kernel], float(eps), int(poly_p), float(poly_c),
                   int(degree), float(theta), int(leaf_max), int(mac_mode),
-                  int(batch_size), int(order_leaf))
+                  int(batch_size), int(order_leaf), int(group_max))
     if sample is not None:
         sample = _c(sample, np.int64)
         k = sample.size
@@ -264,14 +268,14 @@ def treecode(kernel, tgt, src, w, eps, degree, theta, leaf_max, mac_mode=0,
     return out, npx.value, ndr.value
 
 
-def lists(src, leaf_max, tgt, theta, batch_size, order_leaf):
+def lists(src, leaf_max, tgt, theta, batch_size, order_leaf, group_max=512):
     """Batch-walk interaction lists as a dict of CSR arrays."""
     src, tgt = _c(src), _c(tgt)
     L = _load()
     h = L.orc_lists_new(_p(src[0]), _p(src[1]), _p(src[2]), src.shape[1],
                         int(leaf_max), _p(tgt[0]), _p(tgt[1]), _p(tgt[2]),
                         tgt.shape[1], float(theta), int(batch_size),
-                        int(order_leaf))
+                        int(order_leaf), int(group_max))
     nb, npx, ndr = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
     L.orc_lists_sizes(h, ctypes.byref(nb), ctypes.byref(npx), ctypes.byref(ndr))
     out = dict(tperm=np.zeros(tgt.shape[1], np.int64),

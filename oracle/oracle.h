@@ -76,14 +76,15 @@ void orc_tree_export(const orc_tree* t, int64_t* perm, double* box,
                      int32_t* child_count, int64_t* pbegin, int64_t* pend,
                      int32_t* level, int32_t* parent);
 
-/* Target batches: targets ordered by a tree of leaf size order_leaf, then cut
- * into consecutive chunks of batch_size.  Returns the number of batches and
- * fills tperm[m], bptr[nb+1], bcenter[nb][3], bradius[nb] (arrays sized by
- * the caller: nb <= ceil(m / batch_size)). */
+/* Target batches: targets ordered by a tree of leaf size order_leaf; the
+ * maximal nodes of that tree holding at most group_max targets ("groups")
+ * are cut into consecutive chunks of batch_size.  Returns the number of
+ * batches nb; fills tperm[m], bptr[nb+1], bcenter[nb][3], bradius[nb] (pass
+ * NULL arrays first to get nb). */
 int64_t orc_batches(const double* tx, const double* ty, const double* tz,
                     int64_t m, int64_t batch_size, int64_t order_leaf,
-                    int64_t* tperm, int64_t* bptr, double* bcenter,
-                    double* bradius);
+                    int64_t group_max, int64_t* tperm, int64_t* bptr,
+                    double* bcenter, double* bradius);
 
 /* ---- bary.c ------------------------------------------------------------- */
 /* Chebyshev points of the 2nd kind on [-1,1], descending (eq.
@@ -119,6 +120,7 @@ typedef struct {
                           1: shared batch MAC (r_B + r_C)/R <= theta */
   int64_t batch_size;  /* targets per batch (mode 1) */
   int64_t order_leaf;  /* leaf size of the target ordering tree (mode 1) */
+  int64_t group_max;   /* batches never span two groups of this size (mode 1) */
 } orc_params;
 
 /* Treecode velocities out[odim][m] in input order.  Counts of kernel
@@ -138,7 +140,7 @@ orc_lists* orc_lists_new(const double* sx, const double* sy, const double* sz,
                          int64_t n, int64_t leaf_max,
                          const double* tx, const double* ty, const double* tz,
                          int64_t m, double theta, int64_t batch_size,
-                         int64_t order_leaf);
+                         int64_t order_leaf, int64_t group_max);
 void orc_lists_sizes(const orc_lists* L, int64_t* nb, int64_t* nprox,
                      int64_t* ndir);
 void orc_lists_export(const orc_lists* L, int64_t* tperm, int64_t* bptr,

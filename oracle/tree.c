@@ -177,36 +177,69 @@ void orc_tree_export(const orc_tree* t, int64_t* perm, double* box,
   if (parent) memcpy(parent, t->parent, sizeof(int32_t) * nn);
 }
 
-/* Target batches: tree order of the targets (a tree with leaf size
- * order_leaf), cut into consecutive chunks of batch_size targets.  Each batch
- * gets the tight box of its own targets, its midpoint as center and half its
- * diagonal as radius, by the same formulas as a cluster. */
+/* Target batches: the targets are ordered by a tree with leaf size
+ * order_leaf.  Group nodes are the nodes of that tree holding at most
+ * group_max targets whose parent holds more, together with leaves that are
+ * larger (degenerate leaves); their target ranges tile the order.  Each group,
+ * in order, is cut into consecutive chunks of batch_size targets, so no batch
+ * spans two groups.  Each batch gets the tight box of its own targets, its
+ * midpoint as center and half its diagonal as radius, by the same formulas as
+ * a cluster.  With output arrays NULL only the batch count is returned; bptr
+ * needs nb + 1 entries, bcenter 3 nb, bradius nb. */
+static void collect_groups(const orc_tree* t, int64_t q, int64_t group_max,
+                           int64_t* gb, int64_t* ge, int64_t* ng) {
+  if (t->pend[q] - t->pbegin[q] <= group_max || t->child_count[q] == 0) {
+    gb[*ng] = t->pbegin[q];
+    ge[*ng] = t->pend[q];
+    (*ng)++;
+    return;
+  }
+  for (int32_t c = 0; c < t->child_count[q]; ++c)
+    collect_groups(t, t->child_first[q] + c, group_max, gb, ge, ng);
+}
+
 int64_t orc_batches(const double* tx, const double* ty, const double* tz,
                     int64_t m, int64_t batch_size, int64_t order_leaf,
-                    int64_t* tperm, int64_t* bptr, double* bcenter,
-                    double* bradius) {
+                    int64_t group_max, int64_t* tperm, int64_t* bptr,
+                    double* bcenter, double* bradius) {
+  if (m == 0) {
+    if (bptr) bptr[0] = 0;
+    return 0;
+  }
   orc_tree* t = orc_tree_new(tx, ty, tz, m, order_leaf);
   const double* xyz[3] = {tx, ty, tz};
-  memcpy(tperm, t->perm, sizeof(int64_t) * m);
-  orc_tree_free(t);
-  int64_t nb = (m + batch_size - 1) / batch_size;
-  for (int64_t b = 0; b < nb; ++b) {
-    int64_t s = b * batch_size, e = s + batch_size;
-    if (e > m) e = m;
-    bptr[b] = s;
-    double h[3];
-    for (int a = 0; a < 3; ++a) {
-      double lo = xyz[a][tperm[s]], hi = lo;
-      for (int64_t i = s + 1; i < e; ++i) {
-        double v = xyz[a][tperm[i]];
-        if (v < lo) lo = v;
-        if (v > hi) hi = v;
+  int64_t* gb = malloc(sizeof(int64_t) * t->nn);
+  int64_t* ge = malloc(sizeof(int64_t) * t->nn);
+  int64_t ng = 0;
+  collect_groups(t, 0, group_max, gb, ge, &ng);
+  int64_t nb = 0;
+  for (int64_t g = 0; g < ng; ++g)
+    for (int64_t s = gb[g]; s < ge[g]; s += batch_size) {
+      int64_t e = s + batch_size;
+      if (e > ge[g]) e = ge[g];
+      if (bptr) {
+        bptr[nb] = s;
+        double h[3];
+        for (int a = 0; a < 3; ++a) {
+          double lo = xyz[a][t->perm[s]], hi = lo;
+          for (int64_t i = s + 1; i < e; ++i) {
+            double v = xyz[a][t->perm[i]];
+            if (v < lo) lo = v;
+            if (v > hi) hi = v;
+          }
+          bcenter[3 * nb + a] = 0.5 * (lo + hi);
+          h[a] = 0.5 * (hi - lo);
+        }
+        bradius[nb] = sqrt(h[0] * h[0] + h[1] * h[1] + h[2] * h[2]);
       }
-      bcenter[3 * b + a] = 0.5 * (lo + hi);
-      h[a] = 0.5 * (hi - lo);
+      nb++;
     }
-    bradius[b] = sqrt(h[0] * h[0] + h[1] * h[1] + h[2] * h[2]);
+  if (bptr) {
+    bptr[nb] = m;
+    memcpy(tperm, t->perm, sizeof(int64_t) * m);
   }
-  bptr[nb] = m;
+  free(gb);
+  free(ge);
+  orc_tree_free(t);
   return nb;
 }

@@ -11,7 +11,8 @@
  *   R2 > 0  and  r*r <= (theta*theta)*R2,  R2 = dx*dx + dy*dy + dz*dz,
  * so a cluster whose center coincides with the target is never approximated.
  *
- * mac_mode 1 replaces x by a batch of targets sharing one walk: the batch's
+ * mac_mode 1 replaces x by a batch of targets sharing one walk (batches as
+ * built by orc_batches): the batch's
  * center c_B and radius r_B stand in for x, and the test becomes
  *   R2 > 0  and  (r_B + r)*(r_B + r) <= (theta*theta)*R2.
  * Since |x - y_c| >= R - r_B for every x in the batch, an accepted cluster
@@ -147,14 +148,15 @@ int orc_treecode(const orc_params* p,
   double* br = NULL;
   int64_t* tbatch = NULL;
   if (p->mac_mode == 1 && m > 0) {
-    int64_t nbmax = (m + p->batch_size - 1) / p->batch_size;
+    int64_t nbmax = orc_batches(tx, ty, tz, m, p->batch_size, p->order_leaf,
+                                p->group_max, NULL, NULL, NULL, NULL);
     int64_t* tperm = malloc(sizeof(int64_t) * m);
     int64_t* bptr = malloc(sizeof(int64_t) * (nbmax + 1));
     bc = malloc(sizeof(double) * 3 * nbmax);
     br = malloc(sizeof(double) * nbmax);
     tbatch = malloc(sizeof(int64_t) * m);
     int64_t nb = orc_batches(tx, ty, tz, m, p->batch_size, p->order_leaf,
-                             tperm, bptr, bc, br);
+                             p->group_max, tperm, bptr, bc, br);
     for (int64_t b = 0; b < nb; ++b)
       for (int64_t i = bptr[b]; i < bptr[b + 1]; ++i) tbatch[tperm[i]] = b;
     free(tperm);
@@ -224,7 +226,7 @@ orc_lists* orc_lists_new(const double* sx, const double* sy, const double* sz,
                          int64_t n, int64_t leaf_max,
                          const double* tx, const double* ty, const double* tz,
                          int64_t m, double theta, int64_t batch_size,
-                         int64_t order_leaf) {
+                         int64_t order_leaf, int64_t group_max) {
   orc_params p;
   memset(&p, 0, sizeof p);
   p.kernel = ORC_STOKESLET;
@@ -248,16 +250,15 @@ orc_lists* orc_lists_new(const double* sx, const double* sy, const double* sz,
   orc_tree_free(t);
 
   orc_lists* L = calloc(1, sizeof(orc_lists));
-  int64_t nbmax = m > 0 ? (m + batch_size - 1) / batch_size : 0;
+  int64_t nbmax = orc_batches(tx, ty, tz, m, batch_size, order_leaf, group_max,
+                              NULL, NULL, NULL, NULL);
   L->m = m;
   L->tperm = malloc(sizeof(int64_t) * (m > 0 ? m : 1));
   L->bptr = malloc(sizeof(int64_t) * (nbmax + 1));
   double* bc = malloc(sizeof(double) * 3 * (nbmax > 0 ? nbmax : 1));
   double* br = malloc(sizeof(double) * (nbmax > 0 ? nbmax : 1));
-  L->nb = m > 0 ? orc_batches(tx, ty, tz, m, batch_size, order_leaf, L->tperm,
-                              L->bptr, bc, br)
-                : 0;
-  if (m == 0) L->bptr[0] = 0;
+  L->nb = orc_batches(tx, ty, tz, m, batch_size, order_leaf, group_max,
+                      L->tperm, L->bptr, bc, br);
   L->prox_ptr = malloc(sizeof(int64_t) * (L->nb + 1));
   L->dir_ptr = malloc(sizeof(int64_t) * (L->nb + 1));
   ivec prox = {0}, dir = {0};

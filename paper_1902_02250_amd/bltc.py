@@ -37,7 +37,8 @@ class BltcError(RuntimeError):
 class Options(ctypes.Structure):
     _fields_ = [("size", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("batch_size", ctypes.c_int32), ("order_leaf", ctypes.c_int32),
-                ("poly_p", ctypes.c_int32), ("poly_c", ctypes.c_double)]
+                ("poly_p", ctypes.c_int32), ("poly_c", ctypes.c_double),
+                ("group_max", ctypes.c_int64)]
 
 
 def declared_functions():
@@ -66,11 +67,11 @@ def load():
         "bltc_tree_export": (ctypes.c_int, [P] * 10),
         "bltc_compute_modified_weights": (ctypes.c_int, [P, P, I32, P]),
         "bltc_modified_weights_export": (ctypes.c_int, [P, I32, P, P]),
-        "bltc_build_targets": (ctypes.c_int, [P, P, P, I64, I32, I32, P, P]),
+        "bltc_build_targets": (ctypes.c_int, [P, P, P, I64, I32, I32, I64, P, P]),
         "bltc_targets_destroy": (ctypes.c_int, [P]),
         "bltc_targets_export": (ctypes.c_int, [P] * 6),
         "bltc_host_tree": (ctypes.c_int, [P, P, P, I64, I64] + [P] * 11),
-        "bltc_host_batches": (ctypes.c_int, [P, P, P, I64, I32, I32] + [P] * 5),
+        "bltc_host_batches": (ctypes.c_int, [P, P, P, I64, I32, I32, I64] + [P] * 5),
         "bltc_evaluate_tree": (ctypes.c_int, [P, P, I32, D, I32, D, P, P, P]),
         "bltc_evaluate": (ctypes.c_int, [P, P, P, I64, P, P, P, I64, P, I32, D,
                                          I32, D, I64, P, P, P]),
@@ -94,8 +95,8 @@ def _check(rc):
         raise BltcError(rc, load().bltc_last_error().decode())
 
 
-def options(precision="fp64", batch_size=64, order_leaf=64, poly_p=2,
-            poly_c=1.0):
+def options(precision="fp64", batch_size=64, order_leaf=32, poly_p=2,
+            poly_c=1.0, group_max=512):
     o = Options()
     load().bltc_options_default(ctypes.byref(o))
     o.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
@@ -103,6 +104,7 @@ def options(precision="fp64", batch_size=64, order_leaf=64, poly_p=2,
     o.order_leaf = int(order_leaf)
     o.poly_p = int(poly_p)
     o.poly_c = float(poly_c)
+    o.group_max = int(group_max)
     return o
 
 
@@ -199,14 +201,14 @@ class Tree:
 class Targets:
     """Target order and batches (bltc_build_targets)."""
 
-    def __init__(self, tgt, batch_size=64, order_leaf=64):
+    def __init__(self, tgt, batch_size=64, order_leaf=32, group_max=512):
         L = load()
         x, y, z, m = _rows(tgt, "tgt")
         self.m = m
         self.batch_size = batch_size
         h = ctypes.c_void_p()
         _check(L.bltc_build_targets(x, y, z, m, int(batch_size), int(order_leaf),
-                                    _stream(), ctypes.byref(h)))
+                                    int(group_max), _stream(), ctypes.byref(h)))
         self._h = h
         nb = ctypes.c_int64()
         _check(L.bltc_targets_export(self._h, ctypes.byref(nb), None, None, None, None))
@@ -235,7 +237,7 @@ def evaluate_tree(tree, targets, kernel, eps, degree, theta, precision="fp64",
     if out is None:
         out = torch.empty((od, targets.m), dtype=torch.float64, device="cuda")
     _dev(out, "out", od)
-    o = options(precision, targets.batch_size, 64, poly_p, poly_c)
+    o = options(precision, targets.batch_size, 32, poly_p, poly_c)
     ptr = ctypes.c_void_p(out.data_ptr()) if targets.m else None
     _check(load().bltc_evaluate_tree(tree._h, targets._h, KERNELS[kernel], float(eps),
                                      int(degree), float(theta), ctypes.byref(o), ptr,
@@ -244,7 +246,8 @@ def evaluate_tree(tree, targets, kernel, eps, degree, theta, precision="fp64",
 
 
 def evaluate(tgt, src, w, kernel, eps, degree, theta, leaf_max, precision="fp64",
-             batch_size=64, order_leaf=64, poly_p=2, poly_c=1.0, out=None):
+             batch_size=64, order_leaf=32, group_max=512, poly_p=2, poly_c=1.0,
+             out=None):
     """One call: tree, batches, modified weights and evaluation."""
     torch = _torch()
     tx, ty, tz, m = _rows(tgt, "tgt")
@@ -254,7 +257,7 @@ def evaluate(tgt, src, w, kernel, eps, degree, theta, leaf_max, precision="fp64"
     if out is None:
         out = torch.empty((od, m), dtype=torch.float64, device="cuda")
     _dev(out, "out", od)
-    o = options(precision, batch_size, order_leaf, poly_p, poly_c)
+    o = options(precision, batch_size, order_leaf, poly_p, poly_c, group_max)
     _check(load().bltc_evaluate(tx, ty, tz, m, sx, sy, sz, n,
                                 ctypes.c_void_p(w.data_ptr()) if n else None,
                                 KERNELS[kernel], float(eps), int(degree), float(theta),
@@ -297,7 +300,7 @@ def direct(tgt, src, w, kernel, eps, idx=None, precision="fp64", poly_p=2, poly_
     else:
         k, ip = m, None
     out = torch.empty((ODIM[kernel], k), dtype=torch.float64, device="cuda")
-    o = options(precision, 64, 64, poly_p, poly_c)
+    o = options(precision, 64, 32, poly_p, poly_c)
     _check(load().bltc_direct(tx, ty, tz, m, ip, k, sx, sy, sz, n,
                               ctypes.c_void_p(w.data_ptr()) if n else None,
                               KERNELS[kernel], float(eps), ctypes.byref(o),
@@ -325,12 +328,13 @@ def host_tree(pts, leaf_max):
     return out
 
 
-def host_batches(pts, batch_size, order_leaf):
+def host_batches(pts, batch_size, order_leaf, group_max=512):
     pts = _np(pts, np.float64)
     L = load()
     m = pts.shape[1]
     nb = ctypes.c_int64()
-    args = [_hp(pts[0]), _hp(pts[1]), _hp(pts[2]), m, int(batch_size), int(order_leaf)]
+    args = [_hp(pts[0]), _hp(pts[1]), _hp(pts[2]), m, int(batch_size), int(order_leaf),
+            int(group_max)]
     _check(L.bltc_host_batches(*args, ctypes.byref(nb), None, None, None, None))
     k = nb.value
     out = dict(tperm=np.zeros(m, np.int64), bptr=np.zeros(k + 1, np.int64),

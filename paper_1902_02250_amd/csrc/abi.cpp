@@ -109,6 +109,7 @@ int check_options(const bltc_options* o, int kernel) {
   if (o->batch_size < 1 || o->batch_size > 1024)
     return fail(BLTC_EINVAL, "batch_size must be in [1, 1024]");
   if (o->order_leaf < 1) return fail(BLTC_EINVAL, "order_leaf must be >= 1");
+  if (o->group_max < 1) return fail(BLTC_EINVAL, "group_max must be >= 1");
   if (o->poly_p < 0 || o->poly_p > 64) return fail(BLTC_EINVAL, "poly_p must be in [0, 64]");
   return BLTC_OK;
 }
@@ -307,19 +308,20 @@ void destroy_targets(bltc_targets g) {
 }
 
 void build_targets(const double* x, const double* y, const double* z,
-                   int64_t m, int32_t bs, int32_t leaf, hipStream_t s,
-                   bltc_targets g) {
+                   int64_t m, int32_t bs, int32_t leaf, int64_t gmax,
+                   hipStream_t s, bltc_targets g) {
   std::vector<double> hx, hy, hz;
   fetch(hx, x, m, s);
   fetch(hy, y, m, s);
   fetch(hz, z, m, s);
   sync(s);
-  bltc::build_host_batches(hx.data(), hy.data(), hz.data(), m, bs, leaf, g->host);
+  bltc::build_host_batches(hx.data(), hy.data(), hz.data(), m, bs, leaf, gmax, g->host);
   const bltc::HostBatches& B = g->host;
   g->m = m;
   g->nb = (int64_t)B.bptr.size() - 1;
   g->batch_size = bs;
   g->order_leaf = leaf;
+  g->group_max = gmax;
   std::vector<double> xs(3 * m);
   for (int64_t i = 0; i < m; ++i) {
     const int32_t j = B.perm[i];
@@ -455,7 +457,8 @@ void bltc_options_default(bltc_options* o) {
   o->size = (int32_t)sizeof(bltc_options);
   o->precision = BLTC_FP64;
   o->batch_size = 64;
-  o->order_leaf = 64;
+  o->order_leaf = 32;
+  o->group_max = 512;
   o->poly_p = 2;
   o->poly_c = 1.0;
 }
@@ -554,17 +557,18 @@ int bltc_modified_weights_export(bltc_tree t, int32_t degree, double* fhat,
 
 int bltc_build_targets(const double* x, const double* y, const double* z,
                        int64_t m, int32_t batch_size, int32_t order_leaf,
-                       void* stream, bltc_targets* out) {
+                       int64_t group_max, void* stream, bltc_targets* out) {
   if (!out) return fail(BLTC_EINVAL, "out handle pointer is NULL");
   *out = nullptr;
   if (int rc = check_points(x, y, z, m, "targets")) return rc;
   if (batch_size < 1 || batch_size > 1024)
     return fail(BLTC_EINVAL, "batch_size must be in [1, 1024]");
   if (order_leaf < 1) return fail(BLTC_EINVAL, "order_leaf must be >= 1");
+  if (group_max < 1) return fail(BLTC_EINVAL, "group_max must be >= 1");
   return guarded([&] {
     bltc_targets g = new bltc_targets_s;
     try {
-      build_targets(x, y, z, m, batch_size, order_leaf, (hipStream_t)stream, g);
+      build_targets(x, y, z, m, batch_size, order_leaf, group_max, (hipStream_t)stream, g);
     } catch (...) {
       destroy_targets(g);
       throw;
@@ -615,16 +619,17 @@ int bltc_host_tree(const double* hx, const double* hy, const double* hz,
 
 int bltc_host_batches(const double* hx, const double* hy, const double* hz,
                       int64_t m, int32_t batch_size, int32_t order_leaf,
-                      int64_t* nb, int64_t* tperm, int64_t* bptr,
-                      double* bcenter, double* bradius) {
+                      int64_t group_max, int64_t* nb, int64_t* tperm,
+                      int64_t* bptr, double* bcenter, double* bradius) {
   if (m < 0 || m > 0x7fffffffLL) return fail(BLTC_EINVAL, "count out of range [0, 2^31)");
   if (m > 0 && (!hx || !hy || !hz)) return fail(BLTC_EINVAL, "NULL coordinate array");
   if (batch_size < 1 || batch_size > 1024)
     return fail(BLTC_EINVAL, "batch_size must be in [1, 1024]");
   if (order_leaf < 1) return fail(BLTC_EINVAL, "order_leaf must be >= 1");
+  if (group_max < 1) return fail(BLTC_EINVAL, "group_max must be >= 1");
   return guarded([&] {
     bltc_targets_s g;
-    bltc::build_host_batches(hx, hy, hz, m, batch_size, order_leaf, g.host);
+    bltc::build_host_batches(hx, hy, hz, m, batch_size, order_leaf, group_max, g.host);
     g.m = m;
     g.nb = (int64_t)g.host.bptr.size() - 1;
     return bltc_targets_export(&g, nb, tperm, bptr, bcenter, bradius);
@@ -675,7 +680,7 @@ int bltc_evaluate(const double* tx, const double* ty, const double* tz,
       t->leaf_max = leaf_max;
       build_tree(sx, sy, sz, n, leaf_max, s, t);
       g = new bltc_targets_s;
-      build_targets(tx, ty, tz, m, o.batch_size, o.order_leaf, s, g);
+      build_targets(tx, ty, tz, m, o.batch_size, o.order_leaf, o.group_max, s, g);
       set_weights(t, w, s);
       evaluate_tree(t, g, kernel, eps, degree, theta, o, out, s);
       sync(s);

@@ -31,7 +31,9 @@ struct HostTree {
 void build_host_tree(const double* x, const double* y, const double* z,
                      int64_t n, int64_t leaf_max, HostTree& t);
 
-// Target batches: tree order, then consecutive chunks of batch_size targets.
+// Target batches: tree order (leaf size order_leaf); every group node (a
+// maximal node with at most group_max targets) is cut into consecutive chunks
+// of batch_size, so no batch spans two groups.
 struct HostBatches {
   std::vector<int32_t> perm;     // target position -> input index
   std::vector<int32_t> bptr;     // [nb+1]
@@ -39,7 +41,7 @@ struct HostBatches {
 };
 void build_host_batches(const double* x, const double* y, const double* z,
                         int64_t m, int32_t batch_size, int32_t order_leaf,
-                        HostBatches& b);
+                        int64_t group_max, HostBatches& b);
 
 // Unit Chebyshev points of the 2nd kind, descending.
 void cheb_points(int degree, double* t);
@@ -159,6 +161,7 @@ struct bltc_targets_s {
   int device = 0;
   int64_t m = 0, nb = 0;
   int32_t batch_size = 0, order_leaf = 0;
+  int64_t group_max = 0;
   bltc::HostBatches host;
   int32_t* d_tperm = nullptr;
   double* d_x = nullptr;       // tree-ordered [3][m]

@@ -160,11 +160,46 @@ __device__ __forceinline__ int xcd_block(int blk, int nblk) {
   return xcd * per + min(xcd, rem) + idx;
 }
 
+// Orders this wave's LDS accesses: a wave's LDS instructions execute in
+// program order, so only the compiler must be kept from moving them.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Walks the direct list as maximal runs of contiguous particles.
+struct Runs {
+  const int32_t* __restrict__ ids;
+  const int2* __restrict__ range;
+  int li, le, rb, re;
+  __device__ bool next() {
+    if (li >= le) return false;
+    const int2 r0 = range[ids[li]];
+    rb = r0.x;
+    re = r0.y;
+    ++li;
+    while (li < le) {
+      const int2 r1 = range[ids[li]];
+      if (r1.x != re) break;
+      re = r1.y;
+      ++li;
+    }
+    return true;
+  }
+};
+
+// One wave per work group: a group's slot is held until its slowest wave
+// ends, and batches differ widely in work, so waves are scheduled singly.
+constexpr int kWavesPerBlock = 1;
+
+// Wave gw serves targets
+// [bptr[b] + 64 wv, ...) of batch b = gw / wpb, wv = gw % wpb.
 template <int KERN, int PREC, int N1, bool ZEPS>
-__global__ __launch_bounds__(64) void k_p2p(
+__global__ __launch_bounds__(64 * kWavesPerBlock) void k_p2p(
     const double* __restrict__ tx, int64_t m, const int32_t* __restrict__ tperm,
     const int32_t* __restrict__ bptr, const double4* __restrict__ bgeo,
-    int nblk, int wpb, const int32_t* __restrict__ pptr,
+    int nblk, int nwaves, int wpb, const int32_t* __restrict__ pptr,
     const int32_t* __restrict__ pids, const int32_t* __restrict__ dptr,
     const int32_t* __restrict__ dids, const int2* __restrict__ range,
     const double* __restrict__ grid, const float* __restrict__ fh32,
@@ -176,20 +211,26 @@ __global__ __launch_bounds__(64) void k_p2p(
   constexpr int NK = N1 * N1 * N1;
   constexpr bool F64 = PREC == BLTC_FP64;
   using T = typename std::conditional<F64, double, float>::type;
-  __shared__ T sA[4][64];
-  __shared__ T sB[2][64];
+  __shared__ T sA[kWavesPerBlock][4][64];
+  __shared__ T sB[kWavesPerBlock][2][64];
 
-  const int blk = xcd_block(blockIdx.x, nblk);
-  const int b = blk / wpb, wv = blk % wpb;
+  // the wave index is uniform across the wave; readfirstlane tells the
+  // compiler so, which keeps everything derived from it in scalar registers
+  const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int gw = xcd_block(blockIdx.x, nblk) * kWavesPerBlock + wid;
+  if (gw >= nwaves) return;
+  const int b = gw / wpb, wv = gw % wpb;
   const int t0 = bptr[b] + wv * 64, t1 = bptr[b + 1];
   if (t0 >= t1) return;
-  const int lane = threadIdx.x;
   const int ti = t0 + lane;
   const bool active = ti < t1;
   const int tc = active ? ti : t0;
   const double x = tx[tc], y = tx[m + tc], z = tx[2 * m + tc];
   const double4 cb = bgeo[b];
   const T e2 = (T)(eps * eps);
+  T (*A)[64] = sA[wid];
+  T (*B)[64] = sB[wid];
 
   Acc<PREC, OD> acc;
   acc.init();
@@ -210,72 +251,90 @@ __global__ __launch_bounds__(64) void k_p2p(
     acc.fold(p);
   }
 
-  // near field: runs of contiguous leaf particles, staged 64 at a time
+  // near field: runs of contiguous leaf particles in chunks of 64; the next
+  // chunk's sources are loaded into registers while the current one is
+  // evaluated from LDS
   const T xr = F64 ? (T)x : (T)(x - cb.x);
   const T yr = F64 ? (T)y : (T)(y - cb.y);
   const T zr = F64 ? (T)z : (T)(z - cb.z);
-  int li = dptr[b];
-  const int le = dptr[b + 1];
-  while (li < le) {
-    const int2 r0 = range[dids[li]];
-    int rb = r0.x, re = r0.y;
-    ++li;
-    while (li < le) {
-      const int2 r1 = range[dids[li]];
-      if (r1.x != re) break;
-      re = r1.y;
-      ++li;
-    }
-    for (int s0 = rb; s0 < re; s0 += 64) {
-      const int j = s0 + lane;
-      if (j < re) {
-        if constexpr (F64) {
-          sA[0][lane] = (T)ys[j];
-          sA[1][lane] = (T)ys[n + j];
-          sA[2][lane] = (T)ys[2 * n + j];
-          sA[3][lane] = (T)w64[j];
-          sB[0][lane] = (T)w64[n + j];
-          sB[1][lane] = (T)w64[2 * n + j];
-        } else {
-          sA[0][lane] = (T)(ys[j] - cb.x);
-          sA[1][lane] = (T)(ys[n + j] - cb.y);
-          sA[2][lane] = (T)(ys[2 * n + j] - cb.z);
-          sA[3][lane] = (T)w32[j];
-          sB[0][lane] = (T)w32[n + j];
-          sB[1][lane] = (T)w32[2 * n + j];
-        }
-      }
-      __syncthreads();
-      const int cnt = min(64, re - s0);
-      T p[OD];
-#pragma unroll
-      for (int c = 0; c < OD; ++c) p[c] = 0;
-      if constexpr (KERN == KPOLY) {
-        for (int jj = 0; jj < cnt; ++jj) {
-          double dot = x * (double)sA[0][jj];
-          dot = dot + y * (double)sA[1][jj];
-          dot = dot + z * (double)sA[2][jj];
-          const double base = poly_c + dot;
-          double v = 1.0;
-          for (int e = 0; e < poly_p; ++e) v *= base;
-          p[0] += (T)(v * (double)sA[3][jj]);
-          p[1] += (T)(v * (double)sB[0][jj]);
-          p[2] += (T)(v * (double)sB[1][jj]);
-        }
+  Runs it{dids, range, dptr[b], dptr[b + 1], 0, 0};
+  bool have = it.next();
+  int s0 = it.rb, re = it.re;
+  double py0 = 0, py1 = 0, py2 = 0;   // prefetched source (FP64 position)
+  T pf0 = 0, pf1 = 0, pf2 = 0;        // and weights
+  auto fetch = [&](int start, int end) {
+    const int j = start + lane;
+    if (j < end) {
+      py0 = ys[j];
+      py1 = ys[n + j];
+      py2 = ys[2 * n + j];
+      if constexpr (F64) {
+        pf0 = w64[j];
+        pf1 = w64[n + j];
+        pf2 = w64[2 * n + j];
       } else {
-#pragma unroll 4
-        for (int jj = 0; jj < cnt; ++jj) {
-          const T dx = xr - sA[0][jj];
-          const T dy = yr - sA[1][jj];
-          const T dz = zr - sA[2][jj];
-          const T r2 = dz * dz + (dy * dy + (dx * dx + e2));
-          pair<KERN, ZEPS, T>(dx, dy, dz, r2, e2, sA[3][jj], sB[0][jj],
-                              sB[1][jj], p);
-        }
+        pf0 = w32[j];
+        pf1 = w32[n + j];
+        pf2 = w32[2 * n + j];
       }
-      acc.fold(p);
-      __syncthreads();
     }
+  };
+  if (have) fetch(s0, re);
+  while (have) {
+    const int cnt = min(64, re - s0);
+    if (lane < cnt) {
+      if constexpr (F64) {
+        A[0][lane] = py0;
+        A[1][lane] = py1;
+        A[2][lane] = py2;
+      } else {
+        A[0][lane] = (T)(py0 - cb.x);
+        A[1][lane] = (T)(py1 - cb.y);
+        A[2][lane] = (T)(py2 - cb.z);
+      }
+      A[3][lane] = pf0;
+      B[0][lane] = pf1;
+      B[1][lane] = pf2;
+    }
+    wave_lds_sync();
+    int ns0 = s0 + 64, nre = re;
+    bool nhave = true;
+    if (ns0 >= re) {
+      nhave = it.next();
+      ns0 = it.rb;
+      nre = it.re;
+    }
+    if (nhave) fetch(ns0, nre);
+    T p[OD];
+#pragma unroll
+    for (int c = 0; c < OD; ++c) p[c] = 0;
+    if constexpr (KERN == KPOLY) {
+      for (int jj = 0; jj < cnt; ++jj) {
+        double dot = x * (double)A[0][jj];
+        dot = dot + y * (double)A[1][jj];
+        dot = dot + z * (double)A[2][jj];
+        const double base = poly_c + dot;
+        double v = 1.0;
+        for (int e = 0; e < poly_p; ++e) v *= base;
+        p[0] += (T)(v * (double)A[3][jj]);
+        p[1] += (T)(v * (double)B[0][jj]);
+        p[2] += (T)(v * (double)B[1][jj]);
+      }
+    } else {
+#pragma unroll 8
+      for (int jj = 0; jj < cnt; ++jj) {
+        const T dx = xr - A[0][jj];
+        const T dy = yr - A[1][jj];
+        const T dz = zr - A[2][jj];
+        const T r2 = dz * dz + (dy * dy + (dx * dx + e2));
+        pair<KERN, ZEPS, T>(dx, dy, dz, r2, e2, A[3][jj], B[0][jj], B[1][jj], p);
+      }
+    }
+    acc.fold(p);
+    wave_lds_sync();
+    s0 = ns0;
+    re = nre;
+    have = nhave;
   }
 
   if (active) {
@@ -287,14 +346,15 @@ __global__ __launch_bounds__(64) void k_p2p(
 
 template <int KERN, int PREC, int N1>
 hipError_t run_p2p(const P2PArgs& a, hipStream_t s) {
-  const int64_t nblk64 = a.nb * (int64_t)a.wpb;
-  if (nblk64 > 0x7fffffff) return hipErrorInvalidValue;
-  const int nblk = (int)nblk64;
+  const int64_t nw64 = a.nb * (int64_t)a.wpb;
+  if (nw64 > 0x7fffffff - kWavesPerBlock) return hipErrorInvalidValue;
+  const int nwaves = (int)nw64;
+  const int nblk = (nwaves + kWavesPerBlock - 1) / kWavesPerBlock;
   const bool zeps = a.eps == 0.0;
   auto go = [&](auto kern) {
-    hipLaunchKernelGGL(kern, dim3(nblk), dim3(64), 0, s, a.tx, a.m, a.tperm,
-                       a.bptr, a.bgeo, nblk, a.wpb, a.pptr, a.pids, a.dptr,
-                       a.dids, a.range, a.grid, (const float*)a.fhat,
+    hipLaunchKernelGGL(kern, dim3(nblk), dim3(64 * kWavesPerBlock), 0, s, a.tx, a.m,
+                       a.tperm, a.bptr, a.bgeo, nblk, nwaves, a.wpb, a.pptr, a.pids,
+                       a.dptr, a.dids, a.range, a.grid, (const float*)a.fhat,
                        (const double*)a.fhat, a.ys, a.w32, a.w64, a.n, a.eps,
                        a.poly_p, a.poly_c, a.scale_u, a.scale_w, a.out);
   };

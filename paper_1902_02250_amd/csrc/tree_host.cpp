@@ -16,6 +16,7 @@
 #include <cmath>
 #include <cstring>
 #include <numeric>
+#include <utility>
 
 #include "internal.h"
 
@@ -144,36 +145,55 @@ void build_host_tree(const double* x, const double* y, const double* z,
   t.perm.swap(B.perm);
 }
 
+namespace {
+
+// Group nodes: the maximal nodes holding at most group_max targets, plus
+// oversized (degenerate) leaves, in tree order.
+void groups_of(const HostTree& t, int32_t q, int64_t group_max,
+               std::vector<std::pair<int32_t, int32_t>>& out) {
+  const int64_t cnt = t.end[q] - t.begin[q];
+  if (cnt <= group_max || t.count[q] == 0) {
+    out.emplace_back(t.begin[q], t.end[q]);
+    return;
+  }
+  for (int32_t c = 0; c < t.count[q]; ++c) groups_of(t, t.first[q] + c, group_max, out);
+}
+
+}  // namespace
+
 void build_host_batches(const double* x, const double* y, const double* z,
                         int64_t m, int32_t batch_size, int32_t order_leaf,
-                        HostBatches& out) {
+                        int64_t group_max, HostBatches& out) {
   out = HostBatches();
+  out.bptr.push_back(0);
+  if (m == 0) return;
   HostTree order;
   build_host_tree(x, y, z, m, order_leaf, order);
   out.perm.swap(order.perm);
-  const int64_t nb = (m + batch_size - 1) / batch_size;
+  std::vector<std::pair<int32_t, int32_t>> groups;
+  groups_of(order, 0, group_max, groups);
+  out.bptr.clear();
   const double* src[3] = {x, y, z};
-  out.bptr.resize(nb + 1);
-  out.geo.resize(4 * nb);
-  for (int64_t b = 0; b < nb; ++b) {
-    const int64_t s = b * batch_size;
-    const int64_t e = std::min<int64_t>(m, s + batch_size);
-    out.bptr[b] = (int32_t)s;
-    double sq[3];
-    for (int a = 0; a < 3; ++a) {
-      double lo = src[a][out.perm[s]], hi = lo;
-      for (int64_t i = s + 1; i < e; ++i) {
-        const double v = src[a][out.perm[i]];
-        if (v < lo) lo = v;
-        if (v > hi) hi = v;
+  for (const auto& g : groups) {
+    for (int64_t s = g.first; s < g.second; s += batch_size) {
+      const int64_t e = std::min<int64_t>(g.second, s + batch_size);
+      out.bptr.push_back((int32_t)s);
+      double sq[3];
+      for (int a = 0; a < 3; ++a) {
+        double lo = src[a][out.perm[s]], hi = lo;
+        for (int64_t i = s + 1; i < e; ++i) {
+          const double v = src[a][out.perm[i]];
+          if (v < lo) lo = v;
+          if (v > hi) hi = v;
+        }
+        out.geo.push_back(0.5 * (lo + hi));
+        const double h = 0.5 * (hi - lo);
+        sq[a] = h * h;
       }
-      out.geo[4 * b + a] = 0.5 * (lo + hi);
-      const double h = 0.5 * (hi - lo);
-      sq[a] = h * h;
+      out.geo.push_back(std::sqrt((sq[0] + sq[1]) + sq[2]));
     }
-    out.geo[4 * b + 3] = std::sqrt((sq[0] + sq[1]) + sq[2]);
   }
-  out.bptr[nb] = (int32_t)m;
+  out.bptr.push_back((int32_t)m);
 }
 
 }  // namespace bltc

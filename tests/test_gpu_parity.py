@@ -56,9 +56,9 @@ def test_tree_and_batches_bit_exact(torch, orc, dist, n, leaf):
     assert T.depth == R.depth and T.nnodes == R.nnodes
     for k in TREE_KEYS:
         assert np.array_equal(a[k], getattr(R, k)), k
-    for bs, ol in [(64, 64), (100, 40), (1, 64)]:
-        g = bltc.Targets(_d(torch, p), bs, ol).export()
-        ob = orc.batches(p, bs, ol)
+    for bs, ol, gm in [(64, 64, 256), (100, 40, 150), (1, 64, 256), (64, 16, 10 ** 9)]:
+        g = bltc.Targets(_d(torch, p), bs, ol, gm).export()
+        ob = orc.batches(p, bs, ol, gm)
         for x, y in zip([g["tperm"], g["bptr"], g["bcenter"], g["bradius"]], ob):
             assert np.array_equal(x, y)
 

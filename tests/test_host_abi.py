@@ -47,11 +47,12 @@ def test_host_tree_degenerate(orc):
             assert np.array_equal(a[k], getattr(T, k)), (k, p.shape)
 
 
-@pytest.mark.parametrize("bs,leaf", [(64, 64), (1, 64), (100, 30), (1024, 200), (256, 256)])
-def test_host_batches_bit_exact(orc, bs, leaf):
+@pytest.mark.parametrize("bs,leaf,group", [(64, 64, 256), (1, 64, 256), (100, 30, 90),
+                                            (1024, 200, 10 ** 9), (256, 256, 300), (64, 16, 1)])
+def test_host_batches_bit_exact(orc, bs, leaf, group):
     p = inputs.points("mixture", 7777, 3)
-    b = bltc.host_batches(p, bs, leaf)
-    ob = orc.batches(p, bs, leaf)
+    b = bltc.host_batches(p, bs, leaf, group)
+    ob = orc.batches(p, bs, leaf, group)
     for x, y in zip([b["tperm"], b["bptr"], b["bcenter"], b["bradius"]], ob):
         assert np.array_equal(x, y)
 
@@ -91,7 +92,8 @@ def test_argument_validation_before_device_work():
     assert _status(L.bltc_build_tree(None, None, None, 1 << 31, 10, None, ctypes.byref(h))) == "EINVAL"
     assert _status(L.bltc_build_tree(None, None, None, 5, 10, None, ctypes.byref(h))) == "EINVAL"
     assert h.value is None
-    assert _status(L.bltc_build_targets(None, None, None, 0, 0, 64, None, ctypes.byref(h))) == "EINVAL"
+    assert _status(L.bltc_build_targets(None, None, None, 0, 0, 64, 256, None, ctypes.byref(h))) == "EINVAL"
+    assert _status(L.bltc_build_targets(None, None, None, 0, 64, 64, 0, None, ctypes.byref(h))) == "EINVAL"
     assert _status(L.bltc_evaluate_tree(None, None, 0, 0.01, 4, 0.7, ok, None, None)) == "EINVAL"
     assert _status(L.bltc_compute_modified_weights(None, None, 4, None)) == "EINVAL"
     assert _status(L.bltc_direct(None, None, None, 0, None, 0, None, None, None, 0, None, 5, 0.0,
@@ -99,4 +101,6 @@ def test_argument_validation_before_device_work():
     assert _status(L.bltc_direct(None, None, None, 0, None, 3, None, None, None, 0, None, 0, 0.0,
                                  ok, None, None)) == "EINVAL"
     assert _status(L.bltc_host_tree(None, None, None, 3, 4, *([None] * 11))) == "EINVAL"
-    assert _status(L.bltc_host_batches(None, None, None, 0, 0, 4, *([None] * 5))) == "EINVAL"
+    assert _status(L.bltc_host_batches(None, None, None, 0, 0, 4, 256, *([None] * 5))) == "EINVAL"
+    grp0 = bltc.options(group_max=0)
+    assert _status(ev(0, 0.01, 4, 0.7, opt=ctypes.byref(grp0))) == "EINVAL"

@@ -106,19 +106,48 @@ def test_uniform_tree_shape(orc):
     assert np.sum(T.child_count == 0) == 64
 
 
-def test_batches(orc):
-    pts = inputs.points("uniform", 1000, 5)
-    tperm, bptr, bc, br = orc.batches(pts, 64, 64)
-    T = orc.Tree(pts, 64)
+def _groups(T, G):
+    """Maximal nodes with at most G targets (or leaves), in tree order."""
+    out = []
+
+    def rec(q):
+        if T.pend[q] - T.pbegin[q] <= G or T.child_count[q] == 0:
+            out.append((T.pbegin[q], T.pend[q]))
+            return
+        for c in range(T.child_count[q]):
+            rec(T.child_first[q] + c)
+    rec(0)
+    return out
+
+
+@pytest.mark.parametrize("dist,G", [("uniform", 256), ("mixture", 100), ("uniform", 10 ** 9)])
+def test_batches(orc, dist, G):
+    pts = inputs.points(dist, 3000, 5)
+    tperm, bptr, bc, br = orc.batches(pts, 64, 16, G)
+    T = orc.Tree(pts, 16)
     assert np.array_equal(tperm, T.perm)
-    assert bptr[0] == 0 and bptr[-1] == 1000 and np.all(np.diff(bptr)[:-1] == 64)
+    # every group is cut into chunks of 64 from its start; no batch spans two
+    expect = []
+    for b, e in _groups(T, G):
+        expect.extend(range(b, e, 64))
+    assert np.array_equal(bptr, np.array(expect + [3000]))
     for b in range(bc.shape[0]):
         p = pts[:, tperm[bptr[b]:bptr[b + 1]]]
         lo, hi = p.min(axis=1), p.max(axis=1)
         assert np.array_equal(bc[b], 0.5 * (lo + hi))
         h = 0.5 * (hi - lo)
         assert br[b] == np.sqrt(h[0] * h[0] + h[1] * h[1] + h[2] * h[2])
+    if G >= 3000:   # one group: plain chunks of the tree order
+        assert np.all(np.diff(bptr)[:-1] == 64)
     # one target per batch: zero radius, center on the target
     tperm1, bptr1, bc1, br1 = orc.batches(pts, 1, 64)
     assert np.all(br1 == 0.0)
     assert np.array_equal(bc1, pts[:, tperm1].T)
+
+
+def test_batches_bound_the_radius(orc):
+    """Groups bound the batch radius: no batch is wider than its group."""
+    pts = inputs.points("uniform", 20000, 6)
+    _, bptr, _, br = orc.batches(pts, 64, 32, 256)
+    _, bptr2, _, br2 = orc.batches(pts, 64, 32, 10 ** 9)
+    assert br.max() < 0.5 * br2.max()

@@ -123,7 +123,7 @@ def test_power_of_two_scaling(orc):
         s = 2.0 ** m
         T1, T2 = orc.Tree(pts, 200), orc.Tree(s * pts, 200)
         assert np.array_equal(T1.perm, T2.perm) and np.array_equal(T1.child_first, T2.child_first)
-        L1 = orc.lists(pts, 200, pts, 0.7, 64, 64)
+        L1 = orc.lists(pts, 200, pts, 0.7, 64, 64, 256)
         L2 = orc.lists(s * pts, 200, s * pts, 0.7, 64, 64)
         for k in L1:
             assert np.array_equal(L1[k], L2[k])
@@ -150,7 +150,7 @@ def test_translation(orc):
     the velocities agree to rounding."""
     pts, w, _ = inputs.workload("c1", n=3000)
     shift = np.array([[0.25], [-0.5], [0.125]])
-    L1 = orc.lists(pts, 200, pts, 0.7, 64, 64)
+    L1 = orc.lists(pts, 200, pts, 0.7, 64, 64, 256)
     L2 = orc.lists(pts + shift, 200, pts + shift, 0.7, 64, 64)
     same = all(np.array_equal(L1[k], L2[k]) for k in L1)
     a, _, _ = orc.treecode("stokeslet", pts, pts, w, 0.01, 5, 0.7, 200, mac_mode=1)
