@@ -84,6 +84,7 @@ typedef struct {
 
 typedef struct bltc_tree_s* bltc_tree;       /* sources: tree, weights */
 typedef struct bltc_targets_s* bltc_targets; /* targets: order, batches */
+typedef struct bltc_selector_s* bltc_selector; /* per-batch (n, theta) model */
 
 void bltc_options_default(bltc_options* opt);
 const char* bltc_last_error(void);
@@ -204,6 +205,79 @@ int bltc_direct(const double* tx, const double* ty, const double* tz,
                 const double* sy, const double* sz, int64_t n, const double* w,
                 int32_t kernel, double eps, const bltc_options* opt,
                 double* out, void* stream);
+
+/* ---- per-batch (n, theta) selector network --------------------------------
+ * Not part of the paper: the paper picks (theta, n, N0) by hand and notes
+ * they are not claimed optimal (Section 6); this network predicts, from 12
+ * features of a target batch, the log10 relative error of each of k
+ * candidate (n, theta) settings.  Layout, FP32 on the device:
+ *   h1 = tanh(W1 x + b1) (64), h2 = tanh(W2 h1 + b2) (64), y = W3 h2 + b3 (k)
+ * params = W1 [64][12], b1 [64], W2 [64][64], b2 [64], W3 [k][64], b3 [k];
+ * X [rows][12]; Y [rows][k]; cache [rows][128] (h1 then h2, for backward).
+ * 1 <= k <= 128.  work is a caller-owned device scratch array of at least
+ * bltc_mlp_work_size floats, so training loops allocate nothing. */
+int bltc_mlp_params(int32_t k, int64_t* n_params);
+int bltc_mlp_work_size(int64_t rows, int32_t k, int64_t* n_floats);
+int bltc_mlp_forward(const float* params, const float* X, int64_t rows,
+                     int32_t k, float* Y, float* cache, void* stream);
+/* dY = 2 (Y - T) / (rows k) and *loss (device) = mean (Y - T)^2. */
+int bltc_mlp_loss(const float* Y, const float* T, int64_t rows, int32_t k,
+                  float* dY, float* loss, float* work, void* stream);
+/* grad = gradient of sum(dY * Y) w.r.t. params (deterministic reduction). */
+int bltc_mlp_backward(const float* params, const float* X, const float* cache,
+                      const float* dY, int64_t rows, int32_t k, float* grad,
+                      float* work, void* stream);
+/* One Adam step with bias correction (step counts from 1). */
+int bltc_adam_step(float* params, float* m, float* v, const float* grad,
+                   int64_t n, float lr, float beta1, float beta2, float eps,
+                   int64_t step, void* stream);
+
+/* ---- learned (n, theta) per batch ----------------------------------------
+ * Features of every batch (device FP32 [nb][12], unnormalised), from its
+ * geometry and one walk at theta_ref:
+ *   0 log2 targets, 1 log10 r_B/R0, 2 log10 eps/R0, 3 log10 eps/r_B,
+ *   4 log10(1 + accepted clusters), 5 log10(1 + near-field sources),
+ *   6 log10(1 + near-field leaves), 7 mean log10 r_C/R0 of accepted
+ *   clusters, 8 mean (r_B + r_C)/(theta_ref R) of accepted clusters,
+ *   9 log10 near-field source density over the mean density, 10 kernel
+ *   (0 Stokeslet, 1 rotlet), 11 log10 n;  R0 = root radius. */
+int bltc_batch_features(bltc_tree t, bltc_targets g, int32_t kernel, double eps,
+                        double theta_ref, float* feat, void* stream);
+/* Per-batch counts of the walk at theta (device int32 [nb] each): accepted
+ * clusters and near-field source particles. */
+int bltc_batch_counts(bltc_tree t, bltc_targets g, double theta, int32_t* n_proxy,
+                      int32_t* n_near, void* stream);
+
+/* A selector model file: little-endian
+ *   char[8] "BLTCSEL1"; int32 version = 1, n_in = 12, n_hidden = 64, k;
+ *   int32 cand_n[k]; double cand_theta[k];
+ *   double theta_ref, cost_far, cost_near, margin;
+ *   float mean[12], std[12]  (feature normalisation);
+ *   float params[bltc_mlp_params(k)];
+ *   uint64 FNV-1a hash of all preceding bytes.
+ * Any mismatch returns BLTC_EMODEL. */
+int bltc_selector_load(const char* path, bltc_selector* out);
+int bltc_selector_destroy(bltc_selector sel);
+int bltc_selector_info(bltc_selector sel, int32_t* k, int32_t* cand_n,
+                       double* cand_theta);
+
+/* Evaluation with a learned (n, theta) per batch.  For every batch: the
+ * network predicts the log10 relative error of each candidate; the batch
+ * takes the candidate of least modelled cost (targets x (accepted clusters
+ * x (n+1)^3 x cost_far + near sources x cost_near)) whose prediction plus
+ * margin is at most log10(tol), else the fallback (fb_degree, fb_theta).
+ * Then the guard: one target per batch is evaluated with the fallback
+ * treecode (the judge); a batch whose result differs from it by more than
+ * tol (relative L2 over the components) is evaluated again with the
+ * fallback.  The modified weights of every degree used are computed from
+ * the stored weights.  choice (host int32 [nb], may be NULL): candidate
+ * index, -1 model fallback, -2 guard fallback.  stats (host int64 [4], may
+ * be NULL): batches, model fallbacks, guard fallbacks, distinct degrees.
+ * Synchronises on stream. */
+int bltc_evaluate_adaptive(bltc_tree t, bltc_targets g, int32_t kernel, double eps,
+                           bltc_selector sel, double tol, int32_t fb_degree,
+                           double fb_theta, const bltc_options* opt, double* out,
+                           int32_t* choice, int64_t* stats, void* stream);
 
 /* ---- measurement ---------------------------------------------------------
  * Stage timing with HIP events recorded on the evaluation stream around each

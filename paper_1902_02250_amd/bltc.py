@@ -55,6 +55,10 @@ def load():
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
                            "or python paper_1902_02250_amd/build.py")
+    # torch ships its own HIP runtime; load it first so that libbltc binds to
+    # the same runtime (one process must not hold two copies, or device
+    # pointers of one are unknown to the other)
+    import torch  # noqa: F401
     L = ctypes.CDLL(LIB_PATH)
     P, I64, I32, D = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double
     sig = {
@@ -77,6 +81,19 @@ def load():
                                          I32, D, I64, P, P, P]),
         "bltc_lists_export": (ctypes.c_int, [P, P, D] + [P] * 7),
         "bltc_counts": (ctypes.c_int, [P, P, I32, D, P, P]),
+        "bltc_mlp_params": (ctypes.c_int, [I32, P]),
+        "bltc_mlp_work_size": (ctypes.c_int, [I64, I32, P]),
+        "bltc_mlp_forward": (ctypes.c_int, [P, P, I64, I32, P, P, P]),
+        "bltc_mlp_loss": (ctypes.c_int, [P, P, I64, I32, P, P, P, P]),
+        "bltc_mlp_backward": (ctypes.c_int, [P, P, P, P, I64, I32, P, P, P]),
+        "bltc_adam_step": (ctypes.c_int, [P, P, P, P, I64, ctypes.c_float, ctypes.c_float,
+                                          ctypes.c_float, ctypes.c_float, I64, P]),
+        "bltc_selector_load": (ctypes.c_int, [ctypes.c_char_p, P]),
+        "bltc_selector_destroy": (ctypes.c_int, [P]),
+        "bltc_selector_info": (ctypes.c_int, [P, P, P, P]),
+        "bltc_batch_features": (ctypes.c_int, [P, P, I32, D, D, P, P]),
+        "bltc_batch_counts": (ctypes.c_int, [P, P, D, P, P, P]),
+        "bltc_evaluate_adaptive": (ctypes.c_int, [P, P, I32, D, P, D, I32, D, P, P, P, P, P]),
         "bltc_profile_enable": (ctypes.c_int, [I32]),
         "bltc_profile_read": (ctypes.c_int, [P, P, I32]),
         "bltc_direct": (ctypes.c_int, [P, P, P, I64, P, I64, P, P, P, I64, P, I32,
@@ -358,3 +375,128 @@ def profile_read(reset=True):
     n = np.zeros(len(STAGES), np.int64)
     _check(load().bltc_profile_read(_hp(ms), _hp(n), 1 if reset else 0))
     return {s: (float(ms[i]), int(n[i])) for i, s in enumerate(STAGES)}
+
+
+# ---- selector network ------------------------------------------------------------
+def _f32(t, name):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.float32 or not t.is_cuda:
+        raise TypeError(f"{name} must be a float32 CUDA tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def mlp_params(k):
+    n = ctypes.c_int64()
+    _check(load().bltc_mlp_params(int(k), ctypes.byref(n)))
+    return n.value
+
+
+def mlp_work(rows, k):
+    """A device workspace for mlp_loss / mlp_backward."""
+    n = ctypes.c_int64()
+    _check(load().bltc_mlp_work_size(int(rows), int(k), ctypes.byref(n)))
+    return _torch().empty(n.value, dtype=_torch().float32, device="cuda")
+
+
+def mlp_forward(params, X, k, cache=True):
+    torch = _torch()
+    rows = X.shape[0]
+    Y = torch.empty((rows, k), dtype=torch.float32, device="cuda")
+    C = torch.empty((rows, 128), dtype=torch.float32, device="cuda") if cache else None
+    _check(load().bltc_mlp_forward(_f32(params, "params"), _f32(X, "X"), rows, int(k),
+                                   _f32(Y, "Y"), _f32(C, "cache") if cache else None,
+                                   _stream()))
+    return Y, C
+
+
+def mlp_loss(Y, T, work):
+    torch = _torch()
+    rows, k = Y.shape
+    dY = torch.empty_like(Y)
+    loss = torch.empty(1, dtype=torch.float32, device="cuda")
+    _check(load().bltc_mlp_loss(_f32(Y, "Y"), _f32(T, "T"), rows, k, _f32(dY, "dY"),
+                                _f32(loss, "loss"), _f32(work, "work"), _stream()))
+    return dY, loss
+
+
+def mlp_backward(params, X, cache, dY, work):
+    rows, k = dY.shape
+    grad = _torch().empty_like(params)
+    _check(load().bltc_mlp_backward(_f32(params, "params"), _f32(X, "X"), _f32(cache, "cache"),
+                                    _f32(dY, "dY"), rows, k, _f32(grad, "grad"),
+                                    _f32(work, "work"), _stream()))
+    return grad
+
+
+def adam_step(params, m, v, grad, step, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    _check(load().bltc_adam_step(_f32(params, "params"), _f32(m, "m"), _f32(v, "v"),
+                                 _f32(grad, "grad"), params.numel(), float(lr), float(beta1),
+                                 float(beta2), float(eps), int(step), _stream()))
+
+
+# ---- learned (n, theta) per batch ------------------------------------------------
+def batch_features(tree, targets, kernel, eps, theta_ref=0.7):
+    """Raw per-batch features, float32 (nb, 12) on the device."""
+    torch = _torch()
+    f = torch.empty((targets.nb, 12), dtype=torch.float32, device="cuda")
+    _check(load().bltc_batch_features(tree._h, targets._h, KERNELS[kernel], float(eps),
+                                      float(theta_ref),
+                                      ctypes.c_void_p(f.data_ptr()) if targets.nb else None,
+                                      _stream()))
+    return f
+
+
+def batch_counts(tree, targets, theta):
+    """(accepted clusters, near-field sources) per batch, int32 on the device."""
+    torch = _torch()
+    pc = torch.empty(targets.nb, dtype=torch.int32, device="cuda")
+    sc = torch.empty(targets.nb, dtype=torch.int32, device="cuda")
+    nb = targets.nb
+    _check(load().bltc_batch_counts(tree._h, targets._h, float(theta),
+                                    ctypes.c_void_p(pc.data_ptr()) if nb else None,
+                                    ctypes.c_void_p(sc.data_ptr()) if nb else None, _stream()))
+    return pc, sc
+
+
+class Selector:
+    """A per-batch (n, theta) model loaded from a selector model file."""
+
+    def __init__(self, path):
+        h = ctypes.c_void_p()
+        _check(load().bltc_selector_load(os.fsencode(path), ctypes.byref(h)))
+        self._h = h
+        k = ctypes.c_int32()
+        _check(load().bltc_selector_info(self._h, ctypes.byref(k), None, None))
+        self.k = k.value
+        self.cand_n = np.zeros(self.k, np.int32)
+        self.cand_theta = np.zeros(self.k)
+        _check(load().bltc_selector_info(self._h, None, _hp(self.cand_n), _hp(self.cand_theta)))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().bltc_selector_destroy(self._h)
+            self._h = None
+
+    __del__ = close
+
+
+def evaluate_adaptive(tree, targets, kernel, eps, selector, tol, fb_degree, fb_theta,
+                      precision="fp32_fp64acc", out=None):
+    """Returns (out, choice per batch, stats [batches, model fallbacks, guard
+    fallbacks, distinct degrees])."""
+    torch = _torch()
+    od = ODIM[kernel]
+    if out is None:
+        out = torch.empty((od, targets.m), dtype=torch.float64, device="cuda")
+    _dev(out, "out", od)
+    o = options(precision, targets.batch_size, 32)
+    choice = np.zeros(max(targets.nb, 1), np.int32)
+    stats = np.zeros(4, np.int64)
+    _check(load().bltc_evaluate_adaptive(tree._h, targets._h, KERNELS[kernel], float(eps),
+                                         selector._h, float(tol), int(fb_degree),
+                                         float(fb_theta), ctypes.byref(o),
+                                         ctypes.c_void_p(out.data_ptr()) if targets.m else None,
+                                         _hp(choice), _hp(stats), _stream()))
+    return out, choice[:targets.nb], stats

@@ -3,8 +3,12 @@
 // stream.  No exception crosses the boundary.
 #include <hip/hip_runtime_api.h>
 
+#include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
+#include <map>
+#include <utility>
 #include <new>
 #include <string>
 #include <vector>
@@ -302,8 +306,13 @@ void set_weights(bltc_tree t, const double* w, hipStream_t s) {
 void destroy_targets(bltc_targets g) {
   if (!g) return;
   dfree(g->d_tperm); dfree(g->d_x); dfree(g->d_bptr); dfree(g->d_bgeo);
-  dfree(g->d_cnt); dfree(g->d_ptr); dfree(g->d_flags); dfree(g->d_pids);
-  dfree(g->d_dids);
+  dfree(g->d_flags);
+  for (auto& L : g->ls) {
+    dfree(L.cnt); dfree(L.ptr); dfree(L.pids); dfree(L.dids);
+  }
+  dfree(g->d_feat); dfree(g->d_Y); dfree(g->d_pc); dfree(g->d_sc);
+  dfree(g->d_choice); dfree(g->d_bmap); dfree(g->d_theta_b); dfree(g->d_spos);
+  dfree(g->d_sbatch); dfree(g->d_gflag); dfree(g->d_ufb);
   delete g;
 }
 
@@ -334,8 +343,10 @@ void build_targets(const double* x, const double* y, const double* z,
   g->d_x = dalloc<double>(3 * m);
   g->d_bptr = dalloc<int32_t>(nb + 1);
   g->d_bgeo = dalloc<double4>(nb);
-  g->d_cnt = dalloc<int32_t>(2 * nb);
-  g->d_ptr = dalloc<int32_t>(2 * (nb + 1));
+  for (auto& L : g->ls) {
+    L.cnt = dalloc<int32_t>(3 * nb);
+    L.ptr = dalloc<int32_t>(2 * (nb + 1));
+  }
   g->d_flags = dalloc<int32_t>(4);
   h2d(g->d_tperm, B.perm.data(), m, s);
   h2d(g->d_x, xs.data(), 3 * m, s);
@@ -346,9 +357,8 @@ void build_targets(const double* x, const double* y, const double* z,
   sync(s);
 }
 
-// Device interaction lists for (t, g, theta); returns the list sizes.
-void build_lists(bltc_tree t, bltc_targets g, double theta, hipStream_t s,
-                 int64_t* np, int64_t* nd) {
+bltc::ListArgs list_args(bltc_tree t, bltc_targets g, double theta,
+                         const double* theta_b, bltc::ListSet& L) {
   const int64_t nb = g->nb;
   bltc::ListArgs a;
   a.bgeo = g->d_bgeo;
@@ -358,51 +368,62 @@ void build_lists(bltc_tree t, bltc_targets g, double theta, hipStream_t s,
   a.nodes.kids = t->d_kids;
   a.nodes.nn = t->host.nnodes();
   a.theta = theta;
-  a.pcnt = g->d_cnt;
-  a.dcnt = g->d_cnt + nb;
-  a.pptr = g->d_ptr;
-  a.dptr = g->d_ptr + nb + 1;
+  a.theta_b = theta_b;
+  a.pcnt = L.cnt;
+  a.dcnt = L.cnt + nb;
+  a.scnt = L.cnt + 2 * nb;
+  a.pptr = L.ptr;
+  a.dptr = L.ptr + nb + 1;
   a.pids = nullptr;
   a.dids = nullptr;
   a.err = g->d_flags;
+  return a;
+}
+
+// Device interaction lists of every batch (MAC theta, or theta_b[b] when
+// theta_b is given) into L; returns the list sizes.
+void build_lists(bltc_tree t, bltc_targets g, double theta, const double* theta_b,
+                 bltc::ListSet& L, hipStream_t s, int64_t* np, int64_t* nd) {
+  const int64_t nb = g->nb;
+  bltc::ListArgs a = list_args(t, g, theta, theta_b, L);
   StageTimer lt(BLTC_STAGE_LISTS, s);
   hipchk(bltc::launch_lists(a, false, s), "list count");
-  hipchk(bltc::launch_exclusive_scan(a.pcnt, nb, g->d_ptr, g->d_flags + 1, s), "scan");
-  hipchk(bltc::launch_exclusive_scan(a.dcnt, nb, g->d_ptr + nb + 1, g->d_flags + 2, s), "scan");
+  hipchk(bltc::launch_exclusive_scan(a.pcnt, nb, L.ptr, g->d_flags + 1, s), "scan");
+  hipchk(bltc::launch_exclusive_scan(a.dcnt, nb, L.ptr + nb + 1, g->d_flags + 2, s), "scan");
   int32_t tot[2], flags[4];
-  d2h(&tot[0], g->d_ptr + nb, 1, s);
-  d2h(&tot[1], g->d_ptr + 2 * nb + 1, 1, s);
+  d2h(&tot[0], L.ptr + nb, 1, s);
+  d2h(&tot[1], L.ptr + 2 * nb + 1, 1, s);
   d2h(flags, g->d_flags, 4, s);
   sync(s);
   if (flags[0] || flags[1] || flags[2])
     throw HipError{BLTC_EDEVICE, "interaction lists overflowed"};
-  if (tot[0] > g->pcap) {
-    dfree(g->d_pids);
-    g->d_pids = dalloc<int32_t>(tot[0]);
-    g->pcap = tot[0];
+  if (tot[0] > L.pcap) {
+    dfree(L.pids);
+    L.pids = dalloc<int32_t>(tot[0]);
+    L.pcap = tot[0];
   }
-  if (tot[1] > g->dcap) {
-    dfree(g->d_dids);
-    g->d_dids = dalloc<int32_t>(tot[1]);
-    g->dcap = tot[1];
+  if (tot[1] > L.dcap) {
+    dfree(L.dids);
+    L.dids = dalloc<int32_t>(tot[1]);
+    L.dcap = tot[1];
   }
-  a.pids = g->d_pids;
-  a.dids = g->d_dids;
+  a.pids = L.pids;
+  a.dids = L.dids;
   hipchk(bltc::launch_lists(a, true, s), "list fill");
   lt.stop();
   *np = tot[0];
   *nd = tot[1];
 }
 
-void evaluate_tree(bltc_tree t, bltc_targets g, int kernel, double eps,
-                   int degree, double theta, const bltc_options& o,
-                   double* out, hipStream_t s) {
-  if (g->m == 0) return;
-  ensure_degree(t, degree, s);
-  int64_t np = 0, nd = 0;
-  build_lists(t, g, theta, s, &np, &nd);
+// The particle-cluster evaluation of the batches in bmap (all if NULL) with
+// lists L and the modified weights of `degree`.
+void run_p2p(bltc_tree t, bltc_targets g, const bltc::ListSet& L, int kernel,
+             double eps, int degree, const bltc_options& o, const int32_t* bmap,
+             int64_t nmap, double* out, hipStream_t s) {
   const bltc_degree_data& d = t->deg.at(degree);
   bltc::P2PArgs a;
+  a.bmap = bmap;
+  a.nmap = nmap;
   a.tx = g->d_x;
   a.m = g->m;
   a.tperm = g->d_tperm;
@@ -410,10 +431,10 @@ void evaluate_tree(bltc_tree t, bltc_targets g, int kernel, double eps,
   a.bgeo = g->d_bgeo;
   a.nb = g->nb;
   a.wpb = (g->batch_size + bltc::kWave - 1) / bltc::kWave;
-  a.pptr = g->d_ptr;
-  a.pids = g->d_pids;
-  a.dptr = g->d_ptr + g->nb + 1;
-  a.dids = g->d_dids;
+  a.pptr = L.ptr;
+  a.pids = L.pids;
+  a.dptr = L.ptr + g->nb + 1;
+  a.dids = L.dids;
   a.range = t->d_range;
   a.grid = d.grid;
   a.fhat = o.precision == BLTC_FP64 ? (const void*)d.p2p64 : (const void*)d.p2p32;
@@ -429,6 +450,273 @@ void evaluate_tree(bltc_tree t, bltc_targets g, int kernel, double eps,
   StageTimer ev(BLTC_STAGE_EVAL, s);
   hipchk(bltc::launch_p2p(kernel, o.precision, degree, a, s), "p2p");
   ev.stop();
+}
+
+void evaluate_tree(bltc_tree t, bltc_targets g, int kernel, double eps,
+                   int degree, double theta, const bltc_options& o,
+                   double* out, hipStream_t s) {
+  if (g->m == 0) return;
+  ensure_degree(t, degree, s);
+  int64_t np = 0, nd = 0;
+  build_lists(t, g, theta, nullptr, g->ls[0], s, &np, &nd);
+  run_p2p(t, g, g->ls[0], kernel, eps, degree, o, nullptr, 0, out, s);
+}
+
+// ---- learned (n, theta) per batch -------------------------------------------
+void compute_features(bltc_tree t, bltc_targets g, int kernel, double eps,
+                      double theta_ref, const float* mean, const float* stdv,
+                      float* feat, hipStream_t s) {
+  bltc::FeatArgs a;
+  a.bgeo = g->d_bgeo;
+  a.bptr = g->d_bptr;
+  a.nb = g->nb;
+  a.nodes.geo = t->d_geo;
+  a.nodes.range = t->d_range;
+  a.nodes.kids = t->d_kids;
+  a.nodes.nn = t->host.nnodes();
+  a.box = t->d_box;
+  a.theta_ref = theta_ref;
+  a.eps = eps;
+  a.kernel = kernel;
+  a.n_src = t->n;
+  a.mean = mean;
+  a.stdv = stdv;
+  a.feat = feat;
+  hipchk(bltc::launch_features(a, s), "features");
+}
+
+// Per-batch proxy-cluster and near-source counts of the walk at theta.
+void batch_counts(bltc_tree t, bltc_targets g, double theta, int32_t* pc,
+                  int32_t* sc, hipStream_t s) {
+  bltc::ListSet& L = g->ls[1];
+  bltc::ListArgs a = list_args(t, g, theta, nullptr, L);
+  a.pcnt = pc;
+  a.scnt = sc;
+  hipchk(bltc::launch_lists(a, false, s), "list count");
+}
+
+void ensure_selection_scratch(bltc_targets g, int64_t k, int64_t nth) {
+  const int64_t nb = g->nb;
+  if (!g->d_feat) {
+    g->d_feat = dalloc<float>(nb * bltc::kMlpIn);
+    g->d_choice = dalloc<int32_t>(nb);
+    g->d_bmap = dalloc<int32_t>(nb);
+    g->d_theta_b = dalloc<double>(nb);
+    g->d_gflag = dalloc<int32_t>(nb);
+    g->d_ufb = dalloc<double>(6 * nb);
+    // one guard sample per batch at a hashed position inside the batch
+    std::vector<int32_t> sp(nb), sb(nb);
+    for (int64_t b = 0; b < nb; ++b) {
+      const int32_t b0 = g->host.bptr[b], cnt = g->host.bptr[b + 1] - b0;
+      const uint32_t h = (uint32_t)(b * 2654435761ull >> 7);
+      sp[b] = b0 + (int32_t)(h % (uint32_t)cnt);
+      sb[b] = (int32_t)b;
+    }
+    g->d_spos = dalloc<int32_t>(nb);
+    g->d_sbatch = dalloc<int32_t>(nb);
+    h2d(g->d_spos, sp.data(), nb, nullptr);
+    h2d(g->d_sbatch, sb.data(), nb, nullptr);
+    sync(nullptr);
+  }
+  if (nb * k > g->ycap) {
+    dfree(g->d_Y);
+    g->d_Y = dalloc<float>(nb * k);
+    g->ycap = nb * k;
+  }
+  if (nb * nth > g->pccap) {
+    dfree(g->d_pc);
+    dfree(g->d_sc);
+    g->d_pc = dalloc<int32_t>(nb * nth);
+    g->d_sc = dalloc<int32_t>(nb * nth);
+    g->pccap = nb * nth;
+  }
+}
+
+void evaluate_adaptive(bltc_tree t, bltc_targets g, int kernel, double eps,
+                       bltc_selector sel, double tol, int fb_degree, double fb_theta,
+                       const bltc_options& o, double* out, int32_t* choice_out,
+                       int64_t* stats, hipStream_t s) {
+  const int64_t nb = g->nb;
+  int64_t st[4] = {nb, 0, 0, 0};
+  if (g->m == 0) {
+    if (stats) std::memcpy(stats, st, sizeof st);
+    return;
+  }
+  const int k = sel->k;
+  // distinct thetas of the candidates
+  std::vector<double> thetas;
+  bltc::Candidates cand;
+  for (int j = 0; j < k; ++j) {
+    int ti = -1;
+    for (size_t u = 0; u < thetas.size(); ++u)
+      if (thetas[u] == sel->cand_theta[j]) ti = (int)u;
+    if (ti < 0) {
+      ti = (int)thetas.size();
+      thetas.push_back(sel->cand_theta[j]);
+    }
+    cand.n[j] = sel->cand_n[j];
+    cand.t[j] = ti;
+  }
+  const int64_t nth = (int64_t)thetas.size();
+  ensure_selection_scratch(g, k, nth);
+  // features -> predicted log10 errors -> per-theta costs -> choice
+  compute_features(t, g, kernel, eps, sel->theta_ref, sel->d_mean, sel->d_std, g->d_feat, s);
+  hipchk(bltc::launch_mlp_forward(sel->d_params, g->d_feat, nb, k, g->d_Y, nullptr, s),
+         "mlp forward");
+  for (int64_t ti = 0; ti < nth; ++ti)
+    batch_counts(t, g, thetas[ti], g->d_pc + ti * nb, g->d_sc + ti * nb, s);
+  hipchk(bltc::launch_select(g->d_Y, k, nb, g->d_bptr, g->d_pc, g->d_sc, cand,
+                             (float)std::log10(tol), (float)sel->margin,
+                             (float)sel->cost_far, (float)sel->cost_near, g->d_choice, s),
+         "select");
+  std::vector<int32_t> choice(nb);
+  d2h(choice.data(), g->d_choice, nb, s);
+  sync(s);
+  // per-batch theta and degree; batches grouped by degree
+  std::vector<double> th(nb);
+  std::map<int, std::vector<int32_t>> by_degree;
+  for (int64_t b = 0; b < nb; ++b) {
+    int deg = fb_degree;
+    double tb = fb_theta;
+    if (choice[b] >= 0) {
+      deg = sel->cand_n[choice[b]];
+      tb = sel->cand_theta[choice[b]];
+    } else {
+      st[1]++;
+    }
+    th[b] = tb;
+    by_degree[deg].push_back((int32_t)b);
+  }
+  st[3] = (int64_t)by_degree.size();
+  h2d(g->d_theta_b, th.data(), nb, s);
+  for (auto& kv : by_degree) ensure_degree(t, kv.first, s);
+  ensure_degree(t, fb_degree, s);
+  int64_t np = 0, nd = 0;
+  build_lists(t, g, 0.0, g->d_theta_b, g->ls[0], s, &np, &nd);
+  std::vector<int32_t> order;
+  std::vector<std::pair<int, std::pair<int64_t, int64_t>>> spans;
+  for (auto& kv : by_degree) {
+    spans.push_back({kv.first, {(int64_t)order.size(), (int64_t)kv.second.size()}});
+    order.insert(order.end(), kv.second.begin(), kv.second.end());
+  }
+  h2d(g->d_bmap, order.data(), nb, s);
+  for (auto& sp : spans)
+    run_p2p(t, g, g->ls[0], kernel, eps, sp.first, o, g->d_bmap + sp.second.first,
+            sp.second.second, out, s);
+  // guard: one sample per batch against the fallback treecode
+  build_lists(t, g, fb_theta, nullptr, g->ls[1], s, &np, &nd);
+  const bltc_degree_data& fd = t->deg.at(fb_degree);
+  bltc::GuardArgs ga;
+  ga.spos = g->d_spos;
+  ga.sbatch = g->d_sbatch;
+  ga.ns = (int)nb;
+  ga.tx = g->d_x;
+  ga.m = g->m;
+  ga.pptr = g->ls[1].ptr;
+  ga.pids = g->ls[1].pids;
+  ga.dptr = g->ls[1].ptr + nb + 1;
+  ga.dids = g->ls[1].dids;
+  ga.range = t->d_range;
+  ga.grid = fd.grid;
+  ga.fh32 = fd.p2p32;
+  ga.ys = t->d_y;
+  ga.w32 = t->d_w32;
+  ga.n = t->n;
+  ga.eps = eps;
+  kernel_scales(kernel, &ga.scale_u, &ga.scale_w);
+  ga.ufb = g->d_ufb;
+  std::vector<int32_t> zeros(nb, 0);
+  h2d(g->d_gflag, zeros.data(), nb, s);
+  hipchk(bltc::launch_guard(kernel, fb_degree, ga, s), "guard");
+  hipchk(bltc::launch_guard_check((int)nb, g->d_spos, g->d_sbatch, g->d_tperm, out, g->m,
+                                  odim_of(kernel), g->d_ufb, tol, g->d_gflag, s),
+         "guard check");
+  std::vector<int32_t> flag(nb);
+  d2h(flag.data(), g->d_gflag, nb, s);
+  sync(s);
+  std::vector<int32_t> redo;
+  for (int64_t b = 0; b < nb; ++b)
+    if (flag[b] && choice[b] >= 0) {
+      redo.push_back((int32_t)b);
+      choice[b] = -2;
+    }
+  st[2] = (int64_t)redo.size();
+  if (!redo.empty()) {
+    h2d(g->d_bmap, redo.data(), redo.size(), s);
+    run_p2p(t, g, g->ls[1], kernel, eps, fb_degree, o, g->d_bmap, (int64_t)redo.size(),
+            out, s);
+  }
+  sync(s);
+  if (choice_out) std::memcpy(choice_out, choice.data(), sizeof(int32_t) * nb);
+  if (stats) std::memcpy(stats, st, sizeof st);
+}
+
+// Selector model file (little endian):
+//   char magic[8] "BLTCSEL1"; int32 version (1); int32 n_in (12);
+//   int32 n_hidden (64); int32 k;
+//   int32 cand_n[k]; double cand_theta[k];
+//   double theta_ref, cost_far, cost_near, margin;
+//   float mean[12], stdv[12]; float params[bltc_mlp_params(k)];
+//   uint64 FNV-1a hash of all preceding bytes.
+uint64_t fnv1a(const unsigned char* p, size_t n) {
+  uint64_t h = 1469598103934665603ull;
+  for (size_t i = 0; i < n; ++i) {
+    h ^= p[i];
+    h *= 1099511628211ull;
+  }
+  return h;
+}
+
+int load_selector(const char* path, bltc_selector sel) {
+  FILE* f = std::fopen(path, "rb");
+  if (!f) return fail(BLTC_EMODEL, std::string("cannot open selector model ") + path);
+  std::vector<unsigned char> buf;
+  unsigned char tmp[4096];
+  size_t r;
+  while ((r = std::fread(tmp, 1, sizeof tmp, f)) > 0) buf.insert(buf.end(), tmp, tmp + r);
+  std::fclose(f);
+  size_t off = 0;
+  auto take = [&](void* dst, size_t n) {
+    if (off + n > buf.size()) return false;
+    std::memcpy(dst, buf.data() + off, n);
+    off += n;
+    return true;
+  };
+  char magic[8];
+  int32_t hdr[4];
+  if (!take(magic, 8) || std::memcmp(magic, "BLTCSEL1", 8) != 0 || !take(hdr, sizeof hdr))
+    return fail(BLTC_EMODEL, "selector model: bad magic or header");
+  if (hdr[0] != 1 || hdr[1] != bltc::kMlpIn || hdr[2] != bltc::kMlpHidden || hdr[3] < 1 ||
+      hdr[3] > bltc::kMlpMaxOut)
+    return fail(BLTC_EMODEL, "selector model: unsupported version or dimensions");
+  const int32_t k = hdr[3];
+  sel->k = k;
+  sel->cand_n.resize(k);
+  sel->cand_theta.resize(k);
+  double tail[4];
+  sel->mean.resize(bltc::kMlpIn);
+  sel->stdv.resize(bltc::kMlpIn);
+  sel->params.resize(bltc::mlp_params(k));
+  if (!take(sel->cand_n.data(), 4 * (size_t)k) || !take(sel->cand_theta.data(), 8 * (size_t)k) ||
+      !take(tail, sizeof tail) || !take(sel->mean.data(), 4 * bltc::kMlpIn) ||
+      !take(sel->stdv.data(), 4 * bltc::kMlpIn) ||
+      !take(sel->params.data(), 4 * sel->params.size()))
+    return fail(BLTC_EMODEL, "selector model: truncated");
+  const uint64_t want = fnv1a(buf.data(), off);
+  uint64_t got = 0;
+  if (!take(&got, 8) || got != want || off != buf.size())
+    return fail(BLTC_EMODEL, "selector model: checksum mismatch or trailing bytes");
+  sel->theta_ref = tail[0];
+  sel->cost_far = tail[1];
+  sel->cost_near = tail[2];
+  sel->margin = tail[3];
+  for (int j = 0; j < k; ++j)
+    if (sel->cand_n[j] < 1 || sel->cand_n[j] > bltc::kMaxDegree ||
+        !(sel->cand_theta[j] >= 0.0 && sel->cand_theta[j] <= 1.0))
+      return fail(BLTC_EMODEL, "selector model: candidate out of range");
+  for (int i = 0; i < bltc::kMlpIn; ++i)
+    if (!(sel->stdv[i] > 0.f)) return fail(BLTC_EMODEL, "selector model: non-positive std");
+  return BLTC_OK;
 }
 
 template <typename F>
@@ -702,7 +990,7 @@ int bltc_lists_export(bltc_tree t, bltc_targets g, double theta, int64_t* nb,
   if (!(theta >= 0.0 && theta <= 1.0)) return fail(BLTC_EINVAL, "theta must be in [0, 1]");
   return guarded([&] {
     int64_t np = 0, nd = 0;
-    if (g->nb > 0) build_lists(t, g, theta, nullptr, &np, &nd);
+    if (g->nb > 0) build_lists(t, g, theta, nullptr, g->ls[0], nullptr, &np, &nd);
     if (nb) *nb = g->nb;
     if (n_prox) *n_prox = np;
     if (n_dir) *n_dir = nd;
@@ -712,10 +1000,11 @@ int bltc_lists_export(bltc_tree t, bltc_targets g, double theta, int64_t* nb,
       return (int)BLTC_OK;
     }
     std::vector<int32_t> pp(g->nb + 1), dp(g->nb + 1);
-    d2h(pp.data(), g->d_ptr, g->nb + 1, nullptr);
-    d2h(dp.data(), g->d_ptr + g->nb + 1, g->nb + 1, nullptr);
-    if (prox_ids) d2h(prox_ids, g->d_pids, np, nullptr);
-    if (dir_ids) d2h(dir_ids, g->d_dids, nd, nullptr);
+    const bltc::ListSet& L = g->ls[0];
+    d2h(pp.data(), L.ptr, g->nb + 1, nullptr);
+    d2h(dp.data(), L.ptr + g->nb + 1, g->nb + 1, nullptr);
+    if (prox_ids) d2h(prox_ids, L.pids, np, nullptr);
+    if (dir_ids) d2h(dir_ids, L.dids, nd, nullptr);
     sync(nullptr);
     for (int64_t b = 0; b <= g->nb; ++b) {
       if (prox_ptr) prox_ptr[b] = pp[b];
@@ -733,13 +1022,14 @@ int bltc_counts(bltc_tree t, bltc_targets g, int32_t degree, double theta,
   if (!(theta >= 0.0 && theta <= 1.0)) return fail(BLTC_EINVAL, "theta must be in [0, 1]");
   return guarded([&] {
     int64_t np = 0, nd = 0;
-    if (g->nb > 0) build_lists(t, g, theta, nullptr, &np, &nd);
+    if (g->nb > 0) build_lists(t, g, theta, nullptr, g->ls[0], nullptr, &np, &nd);
     std::vector<int32_t> pp(g->nb + 1), dp(g->nb + 1), pi(np), di(nd);
     if (g->nb > 0) {
-      d2h(pp.data(), g->d_ptr, g->nb + 1, nullptr);
-      d2h(dp.data(), g->d_ptr + g->nb + 1, g->nb + 1, nullptr);
-      d2h(pi.data(), g->d_pids, np, nullptr);
-      d2h(di.data(), g->d_dids, nd, nullptr);
+      const bltc::ListSet& L = g->ls[0];
+      d2h(pp.data(), L.ptr, g->nb + 1, nullptr);
+      d2h(dp.data(), L.ptr + g->nb + 1, g->nb + 1, nullptr);
+      d2h(pi.data(), L.pids, np, nullptr);
+      d2h(di.data(), L.dids, nd, nullptr);
       sync(nullptr);
     }
     const int64_t nk = (int64_t)(degree + 1) * (degree + 1) * (degree + 1);
@@ -792,6 +1082,179 @@ int bltc_direct(const double* tx, const double* ty, const double* tz,
                                sz, n, w, eps, o.poly_p, o.poly_c, su, sw, out,
                                (hipStream_t)stream),
            "direct");
+    return (int)BLTC_OK;
+  });
+}
+
+int bltc_selector_load(const char* path, bltc_selector* out) {
+  if (!out) return fail(BLTC_EINVAL, "out handle pointer is NULL");
+  *out = nullptr;
+  if (!path) return fail(BLTC_EINVAL, "NULL path");
+  bltc_selector sel = new bltc_selector_s;
+  if (int rc = load_selector(path, sel)) {
+    delete sel;
+    return rc;
+  }
+  int rc = guarded([&] {
+    sel->d_params = dalloc<float>(sel->params.size());
+    sel->d_mean = dalloc<float>(bltc::kMlpIn);
+    sel->d_std = dalloc<float>(bltc::kMlpIn);
+    h2d(sel->d_params, sel->params.data(), sel->params.size(), nullptr);
+    h2d(sel->d_mean, sel->mean.data(), bltc::kMlpIn, nullptr);
+    h2d(sel->d_std, sel->stdv.data(), bltc::kMlpIn, nullptr);
+    sync(nullptr);
+    return (int)BLTC_OK;
+  });
+  if (rc) {
+    dfree(sel->d_params); dfree(sel->d_mean); dfree(sel->d_std);
+    delete sel;
+    return rc;
+  }
+  *out = sel;
+  return BLTC_OK;
+}
+
+int bltc_selector_destroy(bltc_selector sel) {
+  if (!sel) return BLTC_OK;
+  dfree(sel->d_params); dfree(sel->d_mean); dfree(sel->d_std);
+  delete sel;
+  return BLTC_OK;
+}
+
+int bltc_selector_info(bltc_selector sel, int32_t* k, int32_t* cand_n,
+                       double* cand_theta) {
+  if (!sel) return fail(BLTC_EINVAL, "NULL selector");
+  if (k) *k = sel->k;
+  for (int j = 0; j < sel->k; ++j) {
+    if (cand_n) cand_n[j] = sel->cand_n[j];
+    if (cand_theta) cand_theta[j] = sel->cand_theta[j];
+  }
+  return BLTC_OK;
+}
+
+int bltc_batch_features(bltc_tree t, bltc_targets g, int32_t kernel, double eps,
+                        double theta_ref, float* feat, void* stream) {
+  if (!t || !g) return fail(BLTC_EINVAL, "NULL tree or targets");
+  if (kernel != BLTC_STOKESLET && kernel != BLTC_ROTLET)
+    return fail(BLTC_EINVAL, "features are defined for the Stokeslet and rotlet kernels");
+  if (!(eps >= 0.0) || !std::isfinite(eps)) return fail(BLTC_EINVAL, "eps must be finite and >= 0");
+  if (!(theta_ref > 0.0 && theta_ref <= 1.0)) return fail(BLTC_EINVAL, "theta_ref must be in (0, 1]");
+  if (g->nb > 0 && !device_ptr(feat)) return fail(BLTC_EINVAL, "feat must be a device pointer");
+  if (g->nb == 0) return BLTC_OK;
+  return guarded([&] {
+    compute_features(t, g, kernel, eps, theta_ref, nullptr, nullptr, feat, (hipStream_t)stream);
+    return (int)BLTC_OK;
+  });
+}
+
+int bltc_batch_counts(bltc_tree t, bltc_targets g, double theta, int32_t* n_proxy,
+                      int32_t* n_near, void* stream) {
+  if (!t || !g) return fail(BLTC_EINVAL, "NULL tree or targets");
+  if (!(theta >= 0.0 && theta <= 1.0)) return fail(BLTC_EINVAL, "theta must be in [0, 1]");
+  if (g->nb > 0 && (!device_ptr(n_proxy) || !device_ptr(n_near)))
+    return fail(BLTC_EINVAL, "n_proxy and n_near must be device pointers");
+  if (g->nb == 0) return BLTC_OK;
+  return guarded([&] {
+    batch_counts(t, g, theta, n_proxy, n_near, (hipStream_t)stream);
+    return (int)BLTC_OK;
+  });
+}
+
+int bltc_evaluate_adaptive(bltc_tree t, bltc_targets g, int32_t kernel, double eps,
+                           bltc_selector sel, double tol, int32_t fb_degree,
+                           double fb_theta, const bltc_options* opt, double* out,
+                           int32_t* choice, int64_t* stats, void* stream) {
+  if (!t || !g || !sel) return fail(BLTC_EINVAL, "NULL tree, targets or selector");
+  if (kernel != BLTC_STOKESLET && kernel != BLTC_ROTLET)
+    return fail(BLTC_EINVAL, "the selector serves the Stokeslet and rotlet kernels");
+  if (int rc = check_eval(kernel, eps, fb_degree, fb_theta)) return rc;
+  if (!(tol > 0.0 && tol < 1.0)) return fail(BLTC_EINVAL, "tol must be in (0, 1)");
+  bltc_options o;
+  bltc_options_default(&o);
+  if (opt) o = *opt;
+  if (int rc = check_options(&o, kernel)) return rc;
+  if (g->m > 0 && !device_ptr(out)) return fail(BLTC_EINVAL, "out must be a device pointer");
+  if (!t->has_w) return fail(BLTC_ESTATE, "no weights: call bltc_compute_modified_weights first");
+  return guarded([&] {
+    evaluate_adaptive(t, g, kernel, eps, sel, tol, fb_degree, fb_theta, o, out, choice,
+                      stats, (hipStream_t)stream);
+    return (int)BLTC_OK;
+  });
+}
+
+int bltc_mlp_params(int32_t k, int64_t* n_params) {
+  if (k < 1 || k > bltc::kMlpMaxOut) return fail(BLTC_EINVAL, "k must be in [1, 128]");
+  if (!n_params) return fail(BLTC_EINVAL, "NULL output");
+  *n_params = bltc::mlp_params(k);
+  return BLTC_OK;
+}
+
+int bltc_mlp_work_size(int64_t rows, int32_t k, int64_t* n_floats) {
+  if (k < 1 || k > bltc::kMlpMaxOut) return fail(BLTC_EINVAL, "k must be in [1, 128]");
+  if (rows < 0 || !n_floats) return fail(BLTC_EINVAL, "bad rows or NULL output");
+  *n_floats = std::max<int64_t>(bltc::mlp_work_floats(rows, k), (rows * k + 255) / 256 + 1);
+  return BLTC_OK;
+}
+
+int bltc_mlp_forward(const float* params, const float* X, int64_t rows,
+                     int32_t k, float* Y, float* cache, void* stream) {
+  if (k < 1 || k > bltc::kMlpMaxOut) return fail(BLTC_EINVAL, "k must be in [1, 128]");
+  if (rows < 0) return fail(BLTC_EINVAL, "rows must be >= 0");
+  if (rows == 0) return BLTC_OK;
+  if (!device_ptr(params) || !device_ptr(X) || !device_ptr(Y) || (cache && !device_ptr(cache)))
+    return fail(BLTC_EINVAL, "params, X, Y and cache must be device pointers");
+  return guarded([&] {
+    hipchk(bltc::launch_mlp_forward(params, X, rows, k, Y, cache, (hipStream_t)stream),
+           "mlp forward");
+    return (int)BLTC_OK;
+  });
+}
+
+int bltc_mlp_loss(const float* Y, const float* T, int64_t rows, int32_t k,
+                  float* dY, float* loss, float* work, void* stream) {
+  if (k < 1 || k > bltc::kMlpMaxOut) return fail(BLTC_EINVAL, "k must be in [1, 128]");
+  if (rows < 0) return fail(BLTC_EINVAL, "rows must be >= 0");
+  if (rows == 0) return BLTC_OK;
+  if (!device_ptr(Y) || !device_ptr(T) || !device_ptr(dY) || !device_ptr(loss) || !device_ptr(work))
+    return fail(BLTC_EINVAL, "Y, T, dY, loss and work must be device pointers");
+  return guarded([&] {
+    hipchk(bltc::launch_mlp_loss(Y, T, rows * k, dY, loss, work, (hipStream_t)stream),
+           "mlp loss");
+    return (int)BLTC_OK;
+  });
+}
+
+int bltc_mlp_backward(const float* params, const float* X, const float* cache,
+                      const float* dY, int64_t rows, int32_t k, float* grad,
+                      float* work, void* stream) {
+  if (k < 1 || k > bltc::kMlpMaxOut) return fail(BLTC_EINVAL, "k must be in [1, 128]");
+  if (rows < 0) return fail(BLTC_EINVAL, "rows must be >= 0");
+  if (!device_ptr(params) || !device_ptr(grad) || !device_ptr(work) ||
+      (rows > 0 && (!device_ptr(X) || !device_ptr(cache) || !device_ptr(dY))))
+    return fail(BLTC_EINVAL, "params, X, cache, dY, grad and work must be device pointers");
+  return guarded([&] {
+    hipchk(bltc::launch_mlp_backward(params, X, cache, dY, rows, k, grad, work,
+                                     (hipStream_t)stream),
+           "mlp backward");
+    return (int)BLTC_OK;
+  });
+}
+
+int bltc_adam_step(float* params, float* m, float* v, const float* grad,
+                   int64_t n, float lr, float beta1, float beta2, float eps,
+                   int64_t step, void* stream) {
+  if (n < 0 || step < 1) return fail(BLTC_EINVAL, "n must be >= 0 and step >= 1");
+  if (!(beta1 >= 0.f && beta1 < 1.f && beta2 >= 0.f && beta2 < 1.f))
+    return fail(BLTC_EINVAL, "beta1 and beta2 must be in [0, 1)");
+  if (n == 0) return BLTC_OK;
+  if (!device_ptr(params) || !device_ptr(m) || !device_ptr(v) || !device_ptr(grad))
+    return fail(BLTC_EINVAL, "params, m, v and grad must be device pointers");
+  return guarded([&] {
+    const double bc1 = 1.0 - std::pow((double)beta1, (double)step);
+    const double bc2 = 1.0 - std::pow((double)beta2, (double)step);
+    hipchk(bltc::launch_adam(params, m, v, grad, n, lr, beta1, beta2, eps, (float)bc1,
+                             (float)bc2, (hipStream_t)stream),
+           "adam");
     return (int)BLTC_OK;
   });
 }

@@ -15,6 +15,9 @@ constexpr int kMaxDegree = 12;
 constexpr int kWave = 64;
 constexpr int kStackMax = 512;       // depth-first stack of the list walk
 constexpr int kUpwardChunk = 2048;   // particles per upward-pass work group
+constexpr int kMlpIn = 12;           // selector network: features
+constexpr int kMlpHidden = 64;       // selector network: hidden width
+constexpr int kMlpMaxOut = 128;      // selector network: most candidates
 
 // ---- host tree (Section 6) ------------------------------------------------
 struct HostTree {
@@ -59,8 +62,10 @@ struct ListArgs {
   int64_t nb;
   Nodes nodes;
   double theta;
+  const double* theta_b = nullptr;  // [nb] per-batch theta, or NULL
   int32_t* pcnt;               // [nb] proxy count (count pass)
   int32_t* dcnt;               // [nb] direct count
+  int32_t* scnt = nullptr;     // [nb] near-field source count, or NULL
   const int32_t* pptr;         // [nb+1] (fill pass)
   const int32_t* dptr;
   int32_t* pids;
@@ -69,6 +74,8 @@ struct ListArgs {
 };
 
 struct P2PArgs {
+  const int32_t* bmap = nullptr;  // batches to evaluate (NULL: all nb)
+  int64_t nmap = 0;
   const double* tx;            // tree-ordered targets [3][m]
   int64_t m;
   const int32_t* tperm;        // target position -> caller index
@@ -94,7 +101,57 @@ struct P2PArgs {
   double* out;                 // [odim][m] caller order
 };
 
+struct GuardArgs {
+  const int32_t* spos;         // [ns] sampled target positions (tree order)
+  const int32_t* sbatch;       // [ns] their batches
+  int ns;
+  const double* tx;
+  int64_t m;
+  const int32_t* pptr;
+  const int32_t* pids;
+  const int32_t* dptr;
+  const int32_t* dids;
+  const int2* range;
+  const double* grid;
+  const float* fh32;
+  const double* ys;
+  const float* w32;
+  int64_t n;
+  double eps, scale_u, scale_w;
+  double* ufb;                 // [ns][odim]
+};
+
+struct FeatArgs {
+  const double4* bgeo;
+  const int32_t* bptr;
+  int64_t nb;
+  Nodes nodes;
+  const double* box;           // [nn][6]
+  double theta_ref;
+  double eps;
+  int kernel;
+  int64_t n_src;
+  const float* mean;           // [12] or NULL: raw features
+  const float* stdv;
+  float* feat;                 // [nb][12]
+};
+
+struct Candidates {
+  int32_t n[kMlpMaxOut];
+  int32_t t[kMlpMaxOut];       // index of the candidate's theta
+};
+
 // ---- launchers (defined in the .hip files) --------------------------------
+hipError_t launch_guard(int kernel, int degree, const GuardArgs& a, hipStream_t s);
+hipError_t launch_features(const FeatArgs& a, hipStream_t s);
+hipError_t launch_select(const float* Y, int k, int64_t nb, const int32_t* bptr,
+                         const int32_t* pcnt, const int32_t* scnt,
+                         const Candidates& c, float logtol, float margin,
+                         float cfar, float cnear, int32_t* choice, hipStream_t s);
+hipError_t launch_guard_check(int ns, const int32_t* spos, const int32_t* sbatch,
+                              const int32_t* tperm, const double* out, int64_t m,
+                              int od, const double* ufb, double tol,
+                              int32_t* flag, hipStream_t s);
 hipError_t launch_gather_points(const double* x, const double* y,
                                 const double* z, const int32_t* perm,
                                 int64_t n, double* out3, hipStream_t s);
@@ -123,6 +180,21 @@ hipError_t launch_direct(int kernel, int precision, const double* tx,
                          const double* w, double eps, int32_t poly_p,
                          double poly_c, double scale_u, double scale_w,
                          double* out, hipStream_t s);
+
+// selector network (k_mlp.hip)
+int64_t mlp_params(int k);
+int64_t mlp_work_floats(int64_t rows, int k);
+hipError_t launch_mlp_forward(const float* p, const float* X, int64_t rows,
+                              int k, float* Y, float* cache, hipStream_t s);
+hipError_t launch_mlp_loss(const float* Y, const float* T, int64_t total,
+                           float* dY, float* loss, float* work, hipStream_t s);
+hipError_t launch_mlp_backward(const float* p, const float* X,
+                               const float* cache, const float* dY,
+                               int64_t rows, int k, float* grad, float* work,
+                               hipStream_t s);
+hipError_t launch_adam(float* p, float* m, float* v, const float* g, int64_t n,
+                       float lr, float b1, float b2, float eps, float bc1,
+                       float bc2, hipStream_t s);
 
 }  // namespace bltc
 
@@ -157,6 +229,17 @@ struct bltc_tree_s {
   size_t partial_cap = 0;      // doubles
 };
 
+namespace bltc {
+// Interaction lists of one walk over all batches (grown on demand).
+struct ListSet {
+  int32_t* cnt = nullptr;      // [3][nb]: proxies, leaves, near sources
+  int32_t* ptr = nullptr;      // [2][nb+1]: proxy and leaf CSR pointers
+  int32_t* pids = nullptr;
+  int32_t* dids = nullptr;
+  int64_t pcap = 0, dcap = 0;
+};
+}  // namespace bltc
+
 struct bltc_targets_s {
   int device = 0;
   int64_t m = 0, nb = 0;
@@ -167,11 +250,31 @@ struct bltc_targets_s {
   double* d_x = nullptr;       // tree-ordered [3][m]
   int32_t* d_bptr = nullptr;
   double4* d_bgeo = nullptr;
-  // interaction-list scratch, grown on demand
-  int32_t* d_cnt = nullptr;    // [2][nb]
-  int32_t* d_ptr = nullptr;    // [2][nb+1]
-  int32_t* d_flags = nullptr;  // [4]: stack overflow, scan overflow
-  int32_t* d_pids = nullptr;
-  int32_t* d_dids = nullptr;
-  int64_t pcap = 0, dcap = 0;
+  int32_t* d_flags = nullptr;  // [4]: stack overflow, scan overflow x2
+  bltc::ListSet ls[2];         // [0] evaluation lists, [1] guard lists
+  // per-batch selection scratch (allocated on first adaptive call)
+  float* d_feat = nullptr;     // [nb][12]
+  float* d_Y = nullptr;        // [nb][k]
+  int64_t ycap = 0;
+  int32_t* d_pc = nullptr;     // [ntheta][nb]
+  int32_t* d_sc = nullptr;
+  int64_t pccap = 0;
+  int32_t* d_choice = nullptr; // [nb]
+  int32_t* d_bmap = nullptr;   // [nb]
+  double* d_theta_b = nullptr; // [nb]
+  int32_t* d_spos = nullptr;   // guard samples, one per batch
+  int32_t* d_sbatch = nullptr;
+  int32_t* d_gflag = nullptr;  // [nb]
+  double* d_ufb = nullptr;     // [nb][6]
+};
+
+struct bltc_selector_s {
+  int32_t k = 0;
+  std::vector<int32_t> cand_n;
+  std::vector<double> cand_theta;
+  double theta_ref = 0.7, cost_far = 1.0, cost_near = 1.0, margin = 0.0;
+  std::vector<float> mean, stdv, params;
+  float* d_params = nullptr;
+  float* d_mean = nullptr;
+  float* d_std = nullptr;
 };

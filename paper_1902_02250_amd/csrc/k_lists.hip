@@ -23,10 +23,12 @@ __global__ __launch_bounds__(128) void k_lists(ListArgs a) {
   const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= a.nb) return;
   const double4 g = a.bgeo[b];
-  const double th2 = a.theta * a.theta;
+  const double th = a.theta_b ? a.theta_b[b] : a.theta;
+  const double th2 = th * th;
   int32_t stack[kStackMax];
   int sp = 0;
   int32_t np = 0, nd = 0;
+  int64_t ns = 0;   // near-field sources
   int32_t* pout = nullptr;
   int32_t* dout = nullptr;
   if (FILL) {
@@ -51,6 +53,8 @@ __global__ __launch_bounds__(128) void k_lists(ListArgs a) {
     if (kd.y == 0) {
       if (FILL) dout[nd] = q;
       ++nd;
+      const int2 rg = a.nodes.range[q];
+      ns += rg.y - rg.x;
       continue;
     }
     if (sp + kd.y > kStackMax) {   // cannot happen for depth <= 70; guarded
@@ -62,6 +66,7 @@ __global__ __launch_bounds__(128) void k_lists(ListArgs a) {
   if (!FILL) {
     a.pcnt[b] = np;
     a.dcnt[b] = nd;
+    if (a.scnt) a.scnt[b] = (int32_t)(ns < 0x7fffffff ? ns : 0x7fffffff);
   }
 }
 

@@ -1,0 +1,372 @@
+"""The learned per-batch (n, theta) selector: candidates, model file,
+training data from the treecode's own runs, and training on the device.
+
+Not part of the paper, which fixes (theta, n, N0) by hand (Section 6) and
+reads the most efficient settings off the lower envelope of cost against
+error (Section 8.1).  Here a small network predicts, for every target batch,
+the log10 relative error of each candidate (n, theta); the evaluation then
+gives each batch the cheapest candidate predicted to meet the tolerance, with
+the fixed-(n, theta) treecode as fallback and judge (bltc_evaluate_adaptive).
+
+Every step runs in libbltc's kernels: the training data come from
+bltc_evaluate_tree (FP32 evaluation, FP64 accumulation) and bltc_direct (FP64
+reference sums at sampled targets), and the network is trained with
+bltc_mlp_forward / bltc_mlp_loss / bltc_mlp_backward / bltc_adam_step.  This
+module only orders the calls and handles host-side bookkeeping.
+"""
+import json
+import os
+import struct
+import sys
+import time
+
+import numpy as np
+
+from . import bltc, inputs
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+MODEL_PATH = os.path.join(HERE, "data", "selector_v1.bin")
+
+CAND_N = tuple(range(2, 13))
+CAND_THETA = (0.4, 0.5, 0.6, 0.7, 0.8, 0.9)
+CANDIDATES = [(n, t) for n in CAND_N for t in CAND_THETA]
+K = len(CANDIDATES)
+THETA_REF = 0.7
+# Relative cost of one far-field and one near-field kernel evaluation,
+# measured with the evaluation kernel on MI355X (3.3e12 and 2.0e12 per s).
+COST_FAR, COST_NEAR = 0.6, 1.0
+LOG_FLOOR = -12.0          # labels are log10(max(error, 1e-12))
+SAMPLES_PER_BATCH = 4
+TRAIN_SEEDS = range(0, 200)
+
+
+# ---- model file -------------------------------------------------------------------
+def _fnv1a(data):
+    h = 1469598103934665603
+    for b in data:
+        h = ((h ^ b) * 1099511628211) & 0xFFFFFFFFFFFFFFFF
+    return h
+
+
+def write_model(path, params, mean, std, margin, cand=CANDIDATES, theta_ref=THETA_REF,
+                cost_far=COST_FAR, cost_near=COST_NEAR):
+    k = len(cand)
+    params = np.ascontiguousarray(params, dtype=np.float32)
+    assert params.size == bltc_param_count(k)
+    body = b"BLTCSEL1" + struct.pack("<4i", 1, 12, 64, k)
+    body += np.array([c[0] for c in cand], dtype="<i4").tobytes()
+    body += np.array([c[1] for c in cand], dtype="<f8").tobytes()
+    body += struct.pack("<4d", theta_ref, cost_far, cost_near, margin)
+    body += np.asarray(mean, dtype="<f4").tobytes() + np.asarray(std, dtype="<f4").tobytes()
+    body += params.astype("<f4").tobytes()
+    body += struct.pack("<Q", _fnv1a(body))
+    os.makedirs(os.path.dirname(os.path.abspath(path)), exist_ok=True)
+    with open(path, "wb") as fh:
+        fh.write(body)
+
+
+def bltc_param_count(k):
+    return 64 * 12 + 64 + 64 * 64 + 64 + k * 64 + k
+
+
+# ---- training data ------------------------------------------------------------------
+def run_config(seed):
+    """The synthetic workload of training (or evaluation) run `seed`."""
+    r = inputs.uniform01(seed, 7, 0, 6)
+    return dict(dist=("uniform", "mixture", "union")[int(r[0] * 3)],
+                n=int(round(10 ** (4.3 + 1.4 * r[1]))),
+                kernel="stokeslet" if r[2] < 0.5 else "rotlet",
+                eps=float(10 ** (-3.0 + 1.5 * r[3])),
+                leaf=(500, 1000, 2000)[int(r[4] * 3)], seed=int(seed))
+
+
+def sample_positions(bptr, s=SAMPLES_PER_BATCH):
+    """s evenly spaced target positions inside every batch (fewer if the
+    batch is smaller); returns positions and their batch ids."""
+    pos, bat = [], []
+    for b in range(bptr.size - 1):
+        b0, cnt = int(bptr[b]), int(bptr[b + 1] - bptr[b])
+        for i in range(min(s, cnt)):
+            pos.append(b0 + (i * cnt) // min(s, cnt))
+            bat.append(b)
+    return np.array(pos, np.int64), np.array(bat, np.int64)
+
+
+def label_run(cfg, log=print):
+    """Features, per-candidate log10 errors and per-theta costs of one run."""
+    import torch
+    dev = torch.device("cuda:0")
+    src = inputs.points(cfg["dist"], cfg["n"], cfg["seed"])
+    w = inputs.weights(cfg["n"], cfg["seed"])
+    d_src = torch.from_numpy(src).to(dev)
+    d_w = torch.from_numpy(w).to(dev)
+    tree = bltc.Tree(d_src, cfg["leaf"])
+    tg = bltc.Targets(d_src, 64, 32, 512)
+    kernel, eps = cfg["kernel"], cfg["eps"]
+    X = bltc.batch_features(tree, tg, kernel, eps, THETA_REF).cpu().numpy()
+    ex = tg.export()
+    pos, bat = sample_positions(ex["bptr"])
+    idx = ex["tperm"][pos]
+    d_idx = torch.from_numpy(idx).to(dev)
+    ref = bltc.direct(d_src, d_src, d_w, kernel, eps, idx=d_idx, precision="fp64")
+    den = np.bincount(bat, weights=(ref * ref).sum(0).cpu().numpy(), minlength=tg.nb)
+    T = np.zeros((tg.nb, K), np.float32)
+    pc = np.zeros((len(CAND_THETA), tg.nb), np.int64)
+    sc = np.zeros((len(CAND_THETA), tg.nb), np.int64)
+    for ti, th in enumerate(CAND_THETA):
+        a, b = bltc.batch_counts(tree, tg, th)
+        pc[ti], sc[ti] = a.cpu().numpy(), b.cpu().numpy()
+    out = torch.empty((bltc.ODIM[kernel], cfg["n"]), dtype=torch.float64, device=dev)
+    for n in CAND_N:
+        tree.compute_weights(d_w, n)
+        for ti, th in enumerate(CAND_THETA):
+            bltc.evaluate_tree(tree, tg, kernel, eps, n, th, precision="fp32_fp64acc", out=out)
+            diff = out[:, d_idx] - ref
+            num = np.bincount(bat, weights=(diff * diff).sum(0).cpu().numpy(), minlength=tg.nb)
+            err = np.sqrt(num / np.maximum(den, 1e-300))
+            T[:, CANDIDATES.index((n, th))] = np.log10(np.maximum(err, 10.0 ** LOG_FLOOR))
+    cnt = np.diff(ex["bptr"])
+    return dict(X=X, T=T, pc=pc, sc=sc, cnt=cnt, cfg=cfg)
+
+
+def generate(seeds, path, log=print):
+    runs = []
+    t0 = time.time()
+    for i, seed in enumerate(seeds):
+        cfg = run_config(seed)
+        runs.append(label_run(cfg, log))
+        log(f"[selector] run {i + 1}/{len(seeds)} seed {seed}: {cfg['dist']} n={cfg['n']} "
+            f"{cfg['kernel']} eps={cfg['eps']:.4f} N0={cfg['leaf']} batches={runs[-1]['T'].shape[0]}"
+            f" ({time.time() - t0:.0f} s)")
+    save_runs(runs, path)
+    return runs
+
+
+def save_runs(runs, path, per_run=300):
+    """Saves at most per_run batches of every run (seeded choice)."""
+    out = {}
+    for i, r in enumerate(runs):
+        nb = r["T"].shape[0]
+        keep = np.sort(np.random.default_rng(i).permutation(nb)[:per_run])
+        out[f"X_{i}"] = r["X"][keep]
+        out[f"T_{i}"] = r["T"][keep].astype(np.float16)
+        out[f"pc_{i}"] = r["pc"][:, keep].astype(np.int32)
+        out[f"sc_{i}"] = r["sc"][:, keep].astype(np.int32)
+        out[f"cnt_{i}"] = r["cnt"][keep].astype(np.int32)
+    np.savez_compressed(path, cfgs=np.array([json.dumps(r["cfg"]) for r in runs]), **out)
+
+
+def load_runs(path):
+    z = np.load(path, allow_pickle=False)
+    cfgs = [json.loads(str(c)) for c in z["cfgs"]]
+    return [dict(X=z[f"X_{i}"], T=z[f"T_{i}"].astype(np.float32), pc=z[f"pc_{i}"],
+                 sc=z[f"sc_{i}"], cnt=z[f"cnt_{i}"], cfg=c) for i, c in enumerate(cfgs)]
+
+
+# ---- training on the device ------------------------------------------------------------
+def glorot(k, seed):
+    rng = np.random.default_rng(seed)
+    parts = []
+    for fan_out, fan_in in ((64, 12), (64, 64), (k, 64)):
+        a = np.sqrt(6.0 / (fan_in + fan_out))
+        parts.append(rng.uniform(-a, a, fan_out * fan_in))
+        parts.append(np.zeros(fan_out))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def train(X, T, epochs=60, batch=4096, lr=2e-3, seed=0, log=print):
+    """Returns (params, mean, std, loss per epoch)."""
+    import torch
+    dev = torch.device("cuda:0")
+    mean = X.mean(axis=0).astype(np.float32)
+    std = np.maximum(X.std(axis=0), 1e-3).astype(np.float32)
+    Xn = torch.from_numpy(((X - mean) / std).astype(np.float32)).to(dev)
+    Tt = torch.from_numpy(T.astype(np.float32)).to(dev)
+    k = T.shape[1]
+    rows = X.shape[0]
+    batch = max(1, min(batch, rows))
+    P = torch.from_numpy(glorot(k, seed)).to(dev)
+    M = torch.zeros_like(P)
+    V = torch.zeros_like(P)
+    work = bltc.mlp_work(batch, k)
+    rng = np.random.default_rng(seed + 1)
+    step = 0
+    hist = []
+    for ep in range(epochs):
+        perm = torch.from_numpy(rng.permutation(rows)).to(dev)
+        tot = 0.0
+        nbat = 0
+        for s0 in range(0, rows - batch + 1, batch):
+            sel = perm[s0:s0 + batch]
+            xb = Xn[sel].contiguous()
+            tb = Tt[sel].contiguous()
+            Y, C = bltc.mlp_forward(P, xb, k)
+            dY, loss = bltc.mlp_loss(Y, tb, work)
+            G = bltc.mlp_backward(P, xb, C, dY, work)
+            step += 1
+            rate = lr * (0.5 * (1 + np.cos(np.pi * ep / epochs)))   # cosine schedule
+            bltc.adam_step(P, M, V, G, step, rate)
+            tot += loss.item()
+            nbat += 1
+        hist.append(tot / max(nbat, 1))
+        log(f"[selector] epoch {ep + 1}/{epochs}: train loss {hist[-1]:.4f}")
+    return P.cpu().numpy(), mean, std, hist
+
+
+def predict(params, mean, std, X):
+    import torch
+    dev = torch.device("cuda:0")
+    P = torch.from_numpy(np.ascontiguousarray(params, np.float32)).to(dev)
+    Xn = torch.from_numpy(((X - mean) / std).astype(np.float32)).to(dev)
+    Y, _ = bltc.mlp_forward(P, Xn, K, cache=False)
+    return Y.cpu().numpy()
+
+
+# ---- offline check of a policy ---------------------------------------------------------------
+def batch_costs(run):
+    """Modelled cost of every (batch, candidate), [nb][K]."""
+    cost = np.zeros((run["cnt"].size, K))
+    for j, (n, th) in enumerate(CANDIDATES):
+        ti = CAND_THETA.index(th)
+        cost[:, j] = run["cnt"] * (run["pc"][ti] * (n + 1) ** 3 * COST_FAR + run["sc"][ti] * COST_NEAR)
+    return cost
+
+
+def policy_summary(run, Y, tol, margin):
+    """Realised global relative error and modelled cost of the learned choice
+    versus the best fixed candidate meeting tol (both from the labels)."""
+    T, cost = run["T"], batch_costs(run)
+    nb = T.shape[0]
+    ok = Y + margin <= np.log10(tol)
+    choice = np.where(ok.any(1), np.where(ok, cost, np.inf).argmin(1), -1)
+    err2 = 10.0 ** (2 * T)             # per-batch relative error squared
+    fb = CANDIDATES.index((10, 0.6))
+    ch = np.where(choice >= 0, choice, fb)
+    learned_e = np.sqrt(err2[np.arange(nb), ch].mean())
+    learned_c = cost[np.arange(nb), ch].sum()
+    fixed_e = np.sqrt(err2.mean(0))
+    fixed_c = cost.sum(0)
+    good = np.where(fixed_e <= tol)[0]
+    best = good[fixed_c[good].argmin()] if good.size else fb
+    return dict(learned_err=float(learned_e), learned_cost=float(learned_c),
+                best_fixed=CANDIDATES[best], fixed_err=float(fixed_e[best]),
+                fixed_cost=float(fixed_c[best]), fallbacks=int((choice < 0).sum()))
+
+
+def calibrate_margin(val_runs, Ys, tols=(1e-4, 1e-5, 1e-6, 1e-7), grid=None):
+    """Smallest margin (most aggressive) for which the realised global error of
+    the learned choice stays within tol on every held-out run and tolerance."""
+    grid = np.arange(-1.0, 3.01, 0.05) if grid is None else grid
+    for m in grid:
+        if all(policy_summary(r, Y, tol, m)["learned_err"] <= tol
+               for r, Y in zip(val_runs, Ys) for tol in tols):
+            return float(m)
+    return float(grid[-1])
+
+
+def compare(workload, model=MODEL_PATH, tol=None, fb=(10, 0.6), reps=2, n=None, log=print):
+    """Learned (n, theta) against every fixed candidate on one workload:
+    step time (modified weights + evaluation, HIP events) and relative L2
+    error against the FP64 direct sum on 10,000 sampled targets.  tol=None
+    takes the error of the workload's own fixed (n, theta)."""
+    import torch
+    dev = torch.device("cuda:0")
+    cfg = dict(inputs.CONFIGS[workload])
+    if n:
+        cfg["n"] = n
+    src = inputs.points(cfg["dist"], cfg["n"], cfg["seed"])
+    w = inputs.weights(cfg["n"], cfg["seed"])
+    d_src, d_w = torch.from_numpy(src).to(dev), torch.from_numpy(w).to(dev)
+    tree = bltc.Tree(d_src, cfg["leaf"])
+    tg = bltc.Targets(d_src, 64, 32, 512)
+    kernel, eps = cfg["kernel"], cfg["eps"]
+    idx = inputs.sample_indices(cfg["n"], min(10000, cfg["n"]), cfg["seed"] + 11)
+    d_idx = torch.from_numpy(idx).to(dev)
+    ref = bltc.direct(d_src, d_src, d_w, kernel, eps, idx=d_idx, precision="fp64")
+    out = torch.empty((bltc.ODIM[kernel], cfg["n"]), dtype=torch.float64, device=dev)
+
+    def timed(step):
+        step()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            res = step()
+        e1.record()
+        torch.cuda.synchronize()
+        err = (torch.linalg.norm(out[:, d_idx] - ref) / torch.linalg.norm(ref)).item()
+        return e0.elapsed_time(e1) / reps, err, res
+
+    fixed = {}
+    for (nn, th) in CANDIDATES:
+        def step(nn=nn, th=th):
+            tree.compute_weights(d_w, nn)
+            bltc.evaluate_tree(tree, tg, kernel, eps, nn, th, precision="fp32_fp64acc", out=out)
+        ms, err, _ = timed(step)
+        fixed[(nn, th)] = (ms, err)
+    if tol is None:
+        tol = fixed[(cfg["degree"], cfg["theta"])][1]
+    ok = [c for c in CANDIDATES if fixed[c][1] <= tol]
+    best = min(ok, key=lambda c: fixed[c][0]) if ok else None
+    sel = bltc.Selector(model)
+
+    def lstep():
+        tree.compute_weights(d_w, fb[0])
+        return bltc.evaluate_adaptive(tree, tg, kernel, eps, sel, tol, fb[0], fb[1],
+                                      precision="fp32_fp64acc", out=out)
+    ms_l, err_l, (_, choice, stats) = timed(lstep)
+    used = np.bincount(choice[choice >= 0], minlength=K)
+    res = dict(workload=workload, n=cfg["n"], kernel=kernel, tol=tol,
+               learned=dict(ms=ms_l, err=err_l, batches=int(stats[0]),
+                            model_fallbacks=int(stats[1]), guard_fallbacks=int(stats[2]),
+                            degrees=int(stats[3]),
+                            top_choices=[(CANDIDATES[j], int(used[j]))
+                                         for j in np.argsort(-used)[:5] if used[j]]),
+               best_fixed=None if best is None else dict(n=best[0], theta=best[1],
+                                                         ms=fixed[best][0], err=fixed[best][1]),
+               fallback_fixed=dict(n=fb[0], theta=fb[1], ms=fixed[fb][0], err=fixed[fb][1]),
+               fixed_sweep={f"{c[0]},{c[1]}": [round(fixed[c][0], 3), fixed[c][1]]
+                            for c in CANDIDATES})
+    if best is not None:
+        res["speedup_vs_best_fixed"] = fixed[best][0] / ms_l
+    log(f"[selector] {workload}: learned {ms_l:.2f} ms E={err_l:.3e}; best fixed "
+        f"{best} {fixed[best][0] if best else float('nan'):.2f} ms; tol {tol:.3e}")
+    return res
+
+
+def main(argv=None):
+    import argparse
+    ap = argparse.ArgumentParser(description="generate training runs and train the selector")
+    ap.add_argument("--data", default="gpurun_out/selector_runs.npz")
+    ap.add_argument("--model", default="gpurun_out/selector_v1.bin")
+    ap.add_argument("--runs", type=int, default=200)
+    ap.add_argument("--epochs", type=int, default=60)
+    ap.add_argument("--skip-generate", action="store_true")
+    args = ap.parse_args(argv)
+    log = lambda *a: print(*a, flush=True)
+    bltc.load()
+    if args.skip_generate:
+        runs = load_runs(args.data)
+    else:
+        runs = generate(list(TRAIN_SEEDS)[:args.runs], args.data, log)
+    nval = max(1, len(runs) // 10)
+    train_runs, val_runs = runs[:-nval], runs[-nval:]
+    X = np.concatenate([r["X"] for r in train_runs])
+    T = np.concatenate([r["T"] for r in train_runs])
+    params, mean, std, hist = train(X, T, epochs=args.epochs, log=log)
+    Ys = [predict(params, mean, std, r["X"]) for r in val_runs]
+    resid = np.concatenate([r["T"] - Y for r, Y in zip(val_runs, Ys)])
+    margin = calibrate_margin(val_runs, Ys)
+    log(f"[selector] validation: rms residual {np.sqrt((resid ** 2).mean()):.3f} dex; "
+        f"calibrated margin {margin:.2f} dex")
+    write_model(args.model, params, mean, std, margin)
+    for r, Y in zip(val_runs, Ys):
+        s = policy_summary(r, Y, 1e-6, margin)
+        log(f"[selector] held-out {r['cfg']['dist']} n={r['cfg']['n']} {r['cfg']['kernel']}: "
+            f"learned E={s['learned_err']:.2e} cost={s['learned_cost']:.3e}; best fixed "
+            f"{s['best_fixed']} E={s['fixed_err']:.2e} cost={s['fixed_cost']:.3e}")
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

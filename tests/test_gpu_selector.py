@@ -1,0 +1,140 @@
+"""GPU checks of the learned (n, theta) path through the C ABI: batch
+features and counts against the oracle's tree and lists, and the adaptive
+evaluation composed exactly of per-candidate fixed evaluations (including
+the guard's fallback)."""
+import numpy as np
+import pytest
+
+from paper_1902_02250_amd import bltc, inputs, selector
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available()
+    bltc.load()
+    return t
+
+
+def _d(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+@pytest.fixture(scope="module")
+def case(torch):
+    src = inputs.points("mixture", 30000, 71)
+    w = inputs.weights(30000, 71)
+    T = bltc.Tree(_d(torch, src), 300)
+    T.compute_weights(_d(torch, w), 4)
+    G = bltc.Targets(_d(torch, src), 64, 32, 512)
+    return dict(src=src, w=w, T=T, G=G, d_w=_d(torch, w))
+
+
+def test_counts_match_oracle_lists(torch, orc, case):
+    for theta in (0.4, 0.7, 0.9):
+        pc, sc = bltc.batch_counts(case["T"], case["G"], theta)
+        L = orc.lists(case["src"], 300, case["src"], theta, 64, 32, 512)
+        R = orc.Tree(case["src"], 300)
+        np_ = np.diff(L["prox_ptr"])
+        sizes = R.pend - R.pbegin
+        ns = np.array([sizes[L["dir_ids"][L["dir_ptr"][b]:L["dir_ptr"][b + 1]]].sum()
+                       for b in range(np_.size)])
+        assert np.array_equal(pc.cpu().numpy(), np_)
+        assert np.array_equal(sc.cpu().numpy(), ns)
+
+
+def test_features_match_oracle(torch, orc, case):
+    eps, th = 0.01, 0.7
+    f = bltc.batch_features(case["T"], case["G"], "rotlet", eps, th).cpu().numpy()
+    src = case["src"]
+    R = orc.Tree(src, 300)
+    L = orc.lists(src, 300, src, th, 64, 32, 512)
+    tperm, bptr, bc, br = orc.batches(src, 64, 32, 512)
+    R0 = R.radius[0]
+    tiny = 1e-12 * R0
+    lo, hi = R.box[0, :3], R.box[0, 3:]
+    dens = src.shape[1] / np.prod(hi - lo + tiny)
+    for b in range(bptr.size - 1):
+        prox = L["prox_ids"][L["prox_ptr"][b]:L["prox_ptr"][b + 1]]
+        dirs = L["dir_ids"][L["dir_ptr"][b]:L["dir_ptr"][b + 1]]
+        P, Lc = prox.size, dirs.size
+        D = (R.pend[dirs] - R.pbegin[dirs]).sum()
+        Rd = np.linalg.norm(bc[b] - R.center[prox], axis=1)
+        vol = np.prod(R.box[dirs, 3:] - R.box[dirs, :3] + tiny, axis=1).sum()
+        ref = [np.log2(max(bptr[b + 1] - bptr[b], 1)), np.log10((br[b] + tiny) / R0),
+               np.log10((eps + tiny) / R0), np.log10((eps + tiny) / (br[b] + tiny)),
+               np.log10(1 + P), np.log10(1 + D), np.log10(1 + Lc),
+               np.mean(np.log10((R.radius[prox] + tiny) / R0)) if P else 0.0,
+               np.mean((br[b] + R.radius[prox]) / (th * Rd)) if P else 0.0,
+               np.log10((D + 1) / (vol + tiny ** 3) / dens), 1.0, np.log10(src.shape[1])]
+        assert np.allclose(f[b], ref, rtol=2e-5, atol=2e-5), (b, f[b], ref)
+
+
+def _const_model(tmp_path, j, value, other=5.0):
+    k = selector.K
+    p = np.zeros(selector.bltc_param_count(k), np.float32)
+    b3 = np.full(k, other, np.float32)
+    b3[j] = value
+    p[-k:] = b3
+    path = str(tmp_path / f"const_{j}.bin")
+    selector.write_model(path, p, np.zeros(12), np.ones(12), 0.0)
+    return path
+
+
+def _targets_of(G, b):
+    ex = G.export()
+    return ex["tperm"][ex["bptr"][b]:ex["bptr"][b + 1]]
+
+
+def _fixed(torch, case, n, th, kernel="stokeslet", eps=0.01):
+    case["T"].compute_weights(case["d_w"], n)
+    return bltc.evaluate_tree(case["T"], case["G"], kernel, eps, n, th,
+                              precision="fp32_fp64acc").cpu().numpy()
+
+
+def test_adaptive_constant_choice(torch, tmp_path, case):
+    j = selector.CANDIDATES.index((6, 0.7))
+    sel = bltc.Selector(_const_model(tmp_path, j, -5.0))
+    out, choice, stats = bltc.evaluate_adaptive(case["T"], case["G"], "stokeslet", 0.01, sel,
+                                                1e-3, 10, 0.6)
+    assert np.all(choice == j) and stats[1] == 0 and stats[2] == 0
+    assert np.array_equal(out.cpu().numpy(), _fixed(torch, case, 6, 0.7))
+
+
+def test_adaptive_guard_fallback(torch, tmp_path, case):
+    """With a tolerance below FP32 rounding every batch fails the guard and is
+    evaluated again with the fallback treecode."""
+    j = selector.CANDIDATES.index((3, 0.9))
+    sel = bltc.Selector(_const_model(tmp_path, j, -13.0))
+    out, choice, stats = bltc.evaluate_adaptive(case["T"], case["G"], "stokeslet", 0.01, sel,
+                                                1e-12, 10, 0.6)
+    assert np.all(choice == -2) and stats[2] == case["G"].nb
+    assert np.array_equal(out.cpu().numpy(), _fixed(torch, case, 10, 0.6))
+    # nothing qualifies: every batch takes the fallback without the model
+    sel2 = bltc.Selector(_const_model(tmp_path, j, 5.0))
+    out2, choice2, stats2 = bltc.evaluate_adaptive(case["T"], case["G"], "stokeslet", 0.01,
+                                                   sel2, 1e-6, 10, 0.6)
+    assert np.all(choice2 == -1) and stats2[1] == case["G"].nb
+    assert np.array_equal(out2.cpu().numpy(), _fixed(torch, case, 10, 0.6))
+
+
+def test_adaptive_is_per_batch_composition(torch, tmp_path, case):
+    k = selector.K
+    p = selector.glorot(k, seed=4)
+    p[-k:] = np.random.default_rng(5).uniform(-7.0, -4.0, k)
+    path = str(tmp_path / "rand.bin")
+    selector.write_model(path, p, np.zeros(12), np.full(12, 3.0), 0.0)
+    sel = bltc.Selector(path)
+    out, choice, stats = bltc.evaluate_adaptive(case["T"], case["G"], "rotlet", 0.01, sel,
+                                                1e-5, 8, 0.6)
+    out = out.cpu().numpy()
+    used = sorted(set(choice.tolist()))
+    assert len([u for u in used if u >= 0]) >= 2, used
+    for u in used:
+        n, th = selector.CANDIDATES[u] if u >= 0 else (8, 0.6)
+        ref = _fixed(torch, case, n, th, kernel="rotlet")
+        for b in np.where(choice == u)[0]:
+            t = _targets_of(case["G"], b)
+            assert np.array_equal(out[:, t], ref[:, t]), (u, b)

@@ -124,7 +124,7 @@ def test_power_of_two_scaling(orc):
         T1, T2 = orc.Tree(pts, 200), orc.Tree(s * pts, 200)
         assert np.array_equal(T1.perm, T2.perm) and np.array_equal(T1.child_first, T2.child_first)
         L1 = orc.lists(pts, 200, pts, 0.7, 64, 64, 256)
-        L2 = orc.lists(s * pts, 200, s * pts, 0.7, 64, 64)
+        L2 = orc.lists(s * pts, 200, s * pts, 0.7, 64, 64, 256)
         for k in L1:
             assert np.array_equal(L1[k], L2[k])
         a, _, _ = orc.treecode("stokeslet", pts, pts, w, 0.01, 5, 0.7, 200)
@@ -151,7 +151,7 @@ def test_translation(orc):
     pts, w, _ = inputs.workload("c1", n=3000)
     shift = np.array([[0.25], [-0.5], [0.125]])
     L1 = orc.lists(pts, 200, pts, 0.7, 64, 64, 256)
-    L2 = orc.lists(pts + shift, 200, pts + shift, 0.7, 64, 64)
+    L2 = orc.lists(pts + shift, 200, pts + shift, 0.7, 64, 64, 256)
     same = all(np.array_equal(L1[k], L2[k]) for k in L1)
     a, _, _ = orc.treecode("stokeslet", pts, pts, w, 0.01, 5, 0.7, 200, mac_mode=1)
     b, _, _ = orc.treecode("stokeslet", pts + shift, pts + shift, w, 0.01, 5, 0.7, 200, mac_mode=1)
