@@ -44,56 +44,112 @@ namespace bltc {
 namespace {
 
 // ---- far field ---------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ T fmat(T a, T b, T c) {
+  if constexpr (sizeof(T) == 4) return __builtin_fmaf(a, b, c);
+  else return __builtin_fma(a, b, c);
+}
+
+// Sums K(x, s_k) fhat_k over one cluster's (n+1)^3 proxies into p.  The grid
+// is a tensor product: a row (k1, k2) shares dx and dy, and a k3 column
+// shares dz.  A term c_k d_k (c a scalar per proxy) is therefore summed as
+//   dx * (row sum of c),  dy * (row sum of c),  sum_k3 dz_k3 * (column sum of c),
+// so the d-weighted parts of the kernels cost one multiply-add per proxy and
+// marginal instead of a product and a multiply-add per component.
 template <int KERN, int N1, bool ZEPS, typename T, typename F>
 __device__ __forceinline__ void proxies(double x, double y, double z,
                                         const double* __restrict__ g,
                                         const F* __restrict__ fh, T e2,
                                         T* p) {
-  constexpr int OD = Dims<KERN>::OD;
   T dz[N1], dz2[N1];
 #pragma unroll
   for (int k = 0; k < N1; ++k) {
     dz[k] = (T)(z - g[2 * N1 + k]);
     dz2[k] = dz[k] * dz[k];
   }
-  for (int k1 = 0; k1 < N1; ++k1) {
-    const T dx = (T)(x - g[k1]);
-    const T dx2e = dx * dx + e2;
-    for (int k2 = 0; k2 < N1; ++k2) {
-      const T dy = (T)(y - g[N1 + k2]);
-      const T dxy2 = dy * dy + dx2e;
-      const F* __restrict__ R = fh + (k1 * N1 + k2) * 3 * N1;
-      if constexpr (KERN == KSTOKES) {
+  if constexpr (KERN == KSTOKES) {
+    // u = sum f H1 + sum (f.d) H2 d,  H2 = inv^3
+    T cz[N1];   // column sums of (f.d) inv^3
+#pragma unroll
+    for (int k = 0; k < N1; ++k) cz[k] = 0;
+    for (int k1 = 0; k1 < N1; ++k1) {
+      const T dx = (T)(x - g[k1]);
+      const T dx2e = dx * dx + e2;
+      for (int k2 = 0; k2 < N1; ++k2) {
+        const T dy = (T)(y - g[N1 + k2]);
+        const T dxy2 = dy * dy + dx2e;
+        const F* __restrict__ R = fh + (k1 * N1 + k2) * 3 * N1;
         T S = 0, ax = 0, ay = 0, az = 0;
 #pragma unroll
         for (int k3 = 0; k3 < N1; ++k3) {
           const T fx = (T)R[k3], fy = (T)R[N1 + k3], fz = (T)R[2 * N1 + k3];
-          const T r2 = dxy2 + dz2[k3];
-          const T inv = inv_rho<ZEPS>(r2);
+          const T inv = inv_rho<ZEPS>(dxy2 + dz2[k3]);
           const T inv3 = (inv * inv) * inv;
           const T fd = fz * dz[k3] + (fy * dy + fx * dx);
           const T h1 = e2 * inv3 + inv;
-          const T s = fd * inv3;
           ax = fx * h1 + ax;
           ay = fy * h1 + ay;
           az = fz * h1 + az;
-          az = dz[k3] * s + az;
-          S += s;
+          S = fmat(fd, inv3, S);
+          cz[k3] = fmat(fd, inv3, cz[k3]);
         }
         p[0] += dx * S + ax;
         p[1] += dy * S + ay;
         p[2] += az;
-      } else {
-        T a[OD];
-#pragma unroll
-        for (int c = 0; c < OD; ++c) a[c] = 0;
-#pragma unroll
-        for (int k3 = 0; k3 < N1; ++k3)
-          pair<KERN, ZEPS, T>(dx, dy, dz[k3], dxy2 + dz2[k3], e2, (T)R[k3],
-                              (T)R[N1 + k3], (T)R[2 * N1 + k3], a);
-#pragma unroll
-        for (int c = 0; c < OD; ++c) p[c] += a[c];
       }
+    }
+#pragma unroll
+    for (int k = 0; k < N1; ++k) p[2] = dz[k] * cz[k] + p[2];
+  } else {
+    // u = sum Q (n x d),  w = sum D1 n + sum D2 (n.d) d
+    T cqx[N1], cqy[N1], cg[N1];   // column sums of Q nx, Q ny, D2 (n.d)
+#pragma unroll
+    for (int k = 0; k < N1; ++k) cqx[k] = cqy[k] = cg[k] = 0;
+    const T q2 = T(3) * e2, d2c = T(15) * e2, d1a = T(15) * e2 * e2, d1b = T(-3) * e2;
+    for (int k1 = 0; k1 < N1; ++k1) {
+      const T dx = (T)(x - g[k1]);
+      const T dx2e = dx * dx + e2;
+      for (int k2 = 0; k2 < N1; ++k2) {
+        const T dy = (T)(y - g[N1 + k2]);
+        const T dxy2 = dy * dy + dx2e;
+        const F* __restrict__ R = fh + (k1 * N1 + k2) * 3 * N1;
+        T qx = 0, qy = 0, qz = 0, G = 0, wx = 0, wy = 0, wz = 0;
+#pragma unroll
+        for (int k3 = 0; k3 < N1; ++k3) {
+          const T nx = (T)R[k3], ny = (T)R[N1 + k3], nz = (T)R[2 * N1 + k3];
+          const T inv = inv_rho<ZEPS>(dxy2 + dz2[k3]);
+          const T inv2 = inv * inv;
+          const T inv3 = inv2 * inv;
+          const T inv5 = inv3 * inv2;
+          const T q = (q2 * inv2 + T(2)) * inv3;                      // Q
+          const T d1 = (inv2 * (d1a * inv2 + d1b) + T(-2)) * inv3;    // D1
+          const T d2 = (d2c * inv2 + T(6)) * inv5;                    // D2
+          const T nd = nz * dz[k3] + (ny * dy + nx * dx);
+          qx = fmat(q, nx, qx);
+          qy = fmat(q, ny, qy);
+          qz = fmat(q, nz, qz);
+          cqx[k3] = fmat(q, nx, cqx[k3]);
+          cqy[k3] = fmat(q, ny, cqy[k3]);
+          wx = d1 * nx + wx;
+          wy = d1 * ny + wy;
+          wz = d1 * nz + wz;
+          G = fmat(d2, nd, G);
+          cg[k3] = fmat(d2, nd, cg[k3]);
+        }
+        // n x d = (ny dz - nz dy, nz dx - nx dz, nx dy - ny dx)
+        p[0] = -dy * qz + p[0];
+        p[1] = dx * qz + p[1];
+        p[2] += dy * qx - dx * qy;
+        p[3] += dx * G + wx;
+        p[4] += dy * G + wy;
+        p[5] += wz;
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < N1; ++k) {
+      p[0] = dz[k] * cqy[k] + p[0];
+      p[1] = -dz[k] * cqx[k] + p[1];
+      p[5] = dz[k] * cg[k] + p[5];
     }
   }
 }
