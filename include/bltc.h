@@ -80,6 +80,19 @@ typedef struct {
   int32_t poly_p;      /* BLTC_POLY exponent, default 2 */
   double poly_c;       /* BLTC_POLY constant, default 1 */
   int64_t group_max;   /* batches never span two target groups, default 512 */
+  int32_t deg_min;     /* 0 (default): every accepted cluster is interpolated
+                          at the evaluation's degree n, as in the paper.
+                          1 <= deg_min < n: separation rule (not in the
+                          paper): an accepted cluster at ratio
+                          rho = (r_B + r_C)/R takes the smallest degree d in
+                          [deg_min, n] with kappa(rho)^(d+1) <=
+                          kappa(theta)^(n+1), kappa(r) = r/(1 + sqrt(1 - r^2))
+                          (Chebyshev interpolation converges like kappa^d for
+                          a singularity at ratio r); tested as
+                          rho^2 <= (2k/(1+k^2))^2, k = kappa(theta)^((n+1)/(d+1)).
+                          The modified weights of the lower degrees are
+                          computed by the evaluation for the clusters that
+                          need them. */
 } bltc_options;
 
 typedef struct bltc_tree_s* bltc_tree;       /* sources: tree, weights */
@@ -184,16 +197,20 @@ int bltc_evaluate(const double* tx, const double* ty, const double* tz,
 
 /* Interaction lists of the batch walk, host copies (synchronises): sizes
  * first (lists pointers NULL), then contents.  prox_ptr/dir_ptr[nb+1] index
- * prox_ids/dir_ids (cluster ids in depth-first order, children in order). */
-int bltc_lists_export(bltc_tree t, bltc_targets g, double theta,
-                      int64_t* nb, int64_t* n_prox, int64_t* n_dir,
-                      int64_t* prox_ptr, int32_t* prox_ids, int64_t* dir_ptr,
-                      int32_t* dir_ids);
+ * prox_ids/dir_ids (cluster ids in depth-first order, children in order);
+ * prox_deg (may be NULL) receives each accepted cluster's degree under the
+ * separation rule of bltc_options.deg_min for evaluation degree `degree`
+ * (all equal to degree when deg_min = 0). */
+int bltc_lists_export(bltc_tree t, bltc_targets g, double theta, int32_t degree,
+                      int32_t deg_min, int64_t* nb, int64_t* n_prox, int64_t* n_dir,
+                      int64_t* prox_ptr, int32_t* prox_ids, int32_t* prox_deg,
+                      int64_t* dir_ptr, int32_t* dir_ids);
 /* Kernel evaluations an evaluation performs (synchronises): proxy
- * evaluations sum over targets of (degree+1)^3 per accepted cluster, direct
- * ones the leaf sizes of the direct list. */
+ * evaluations sum over targets of (d+1)^3 per accepted cluster of degree d
+ * (degree, or the separation rule's when deg_min >= 1), direct ones the leaf
+ * sizes of the direct list. */
 int bltc_counts(bltc_tree t, bltc_targets g, int32_t degree, double theta,
-                int64_t* n_proxy_evals, int64_t* n_direct_evals);
+                int32_t deg_min, int64_t* n_proxy_evals, int64_t* n_direct_evals);
 
 /* Direct sum (eq. N-body) on the device for the k targets idx[0:k] (device
  * int64 indices into the m target arrays, each checked to lie in [0, m),
@@ -249,9 +266,9 @@ int bltc_batch_counts(bltc_tree t, bltc_targets g, double theta, int32_t* n_prox
                       int32_t* n_near, void* stream);
 
 /* A selector model file: little-endian
- *   char[8] "BLTCSEL1"; int32 version = 1, n_in = 12, n_hidden = 64, k;
+ *   char[8] "BLTCSEL1"; int32 version = 2, n_in = 12, n_hidden = 64, k;
  *   int32 cand_n[k]; double cand_theta[k];
- *   double theta_ref, cost_far, cost_near, margin;
+ *   double theta_ref, cost_far, cost_row, cost_cluster, cost_near, margin;
  *   float mean[12], std[12]  (feature normalisation);
  *   float params[bltc_mlp_params(k)];
  *   uint64 FNV-1a hash of all preceding bytes.
@@ -261,23 +278,36 @@ int bltc_selector_destroy(bltc_selector sel);
 int bltc_selector_info(bltc_selector sel, int32_t* k, int32_t* cand_n,
                        double* cand_theta);
 
-/* Evaluation with a learned (n, theta) per batch.  For every batch: the
- * network predicts the log10 relative error of each candidate; the batch
- * takes the candidate of least modelled cost (targets x (accepted clusters
- * x (n+1)^3 x cost_far + near sources x cost_near)) whose prediction plus
- * margin is at most log10(tol), else the fallback (fb_degree, fb_theta).
- * Then the guard: one target per batch is evaluated with the fallback
- * treecode (the judge); a batch whose result differs from it by more than
- * tol (relative L2 over the components) is evaluated again with the
- * fallback.  The modified weights of every degree used are computed from
- * the stored weights.  choice (host int32 [nb], may be NULL): candidate
- * index, -1 model fallback, -2 guard fallback.  stats (host int64 [4], may
- * be NULL): batches, model fallbacks, guard fallbacks, distinct degrees.
- * Synchronises on stream. */
+/* Evaluation with a learned (n, theta) per batch, aiming at a relative L2
+ * error tol over all targets (the paper's eq. error).  Not in the paper,
+ * which fixes (theta, n) for a run (Section 6).
+ *  1. The network predicts e_b(j), the relative error of batch b under each
+ *     candidate j; the walk counts at each candidate theta give its modelled
+ *     wave cost  P (cost_far (n+1)^3 + cost_row (n+1)^2 + cost_cluster)
+ *     + S cost_near  (P accepted clusters, S near-field sources).
+ *  2. The judge: one target per batch is evaluated with the fallback
+ *     treecode (fb_degree, fb_theta); w_b = targets_b |u_fb|^2 estimates the
+ *     batch's share of the reference norm.
+ *  3. The batches share the error budget: the choice minimises the total
+ *     cost subject to  sum_b w_b e_b^2 <= tau^2 sum_b w_b,
+ *     tau = tol 10^-margin, through the Lagrange multiplier of
+ *     cost + lam w_b e_b^2 (searched on a log grid in two passes).
+ *  4. Modified weights of every chosen degree are computed (for the
+ *     clusters its batches accept only); lists at each batch's theta;
+ *     evaluation grouped by degree.
+ *  5. The judge's estimate E^2 = sum_b targets_b |u - u_fb|^2 / sum_b w_b at
+ *     the samples; if E > tol, every batch whose term exceeds tol^2 sum w / nb
+ *     is evaluated again with the fallback.
+ * choice (host int32 [nb], may be NULL): candidate index, or -2 for a batch
+ * the judge sent to the fallback.  stats (host int64 [4], may be NULL):
+ * batches, distinct degrees, batches re-evaluated, 0.  judge (host double
+ * [2], may be NULL): the judge's error estimate before and after its
+ * re-evaluation.  Synchronises on stream. */
 int bltc_evaluate_adaptive(bltc_tree t, bltc_targets g, int32_t kernel, double eps,
                            bltc_selector sel, double tol, int32_t fb_degree,
                            double fb_theta, const bltc_options* opt, double* out,
-                           int32_t* choice, int64_t* stats, void* stream);
+                           int32_t* choice, int64_t* stats, double* judge,
+                           void* stream);
 
 /* ---- measurement ---------------------------------------------------------
  * Stage timing with HIP events recorded on the evaluation stream around each

@@ -70,8 +70,12 @@ def _load():
     L.orc_treecode.argtypes = [P, P, P, P, I64, P, P, P, I64, P, P, I64, P,
                                P, P]
     L.orc_lists_new.argtypes = [P, P, P, I64, I64, P, P, P, I64, D, I64, I64,
-                                I64]
+                                I64, ctypes.c_int, ctypes.c_int]
     L.orc_lists_new.restype = P
+    L.orc_lists_export_degrees.argtypes = [P, P]
+    L.orc_rule_table.argtypes = [P, P]
+    L.orc_rule_degree.argtypes = [P, P, D, D]
+    L.orc_rule_degree.restype = ctypes.c_int
     L.orc_lists_sizes.argtypes = [P, P, P, P]
     L.orc_lists_export.argtypes = [P] * 7
     L.orc_lists_free.argtypes = [P]
@@ -95,7 +99,7 @@ class _Params(ctypes.Structure):
                 ("degree", ctypes.c_int), ("theta", ctypes.c_double),
                 ("leaf_max", ctypes.c_int64), ("mac_mode", ctypes.c_int),
                 ("batch_size", ctypes.c_int64), ("order_leaf", ctypes.c_int64),
-                ("group_max", ctypes.c_int64)]
+                ("group_max", ctypes.c_int64), ("deg_min", ctypes.c_int)]
 
 
 # ---- kernels ----------------------------------------------------------------
@@ -244,14 +248,15 @@ def lagrange_product(n, s, t):
 # ---- treecode ---------------------------------------------------------------
 def treecode(kernel, tgt, src, w, eps, degree, theta, leaf_max, mac_mode=0,
              batch_size=64, order_leaf=64, group_max=512, sample=None, poly_p=0,
-             poly_c=0.0):
+             poly_c=0.0, deg_min=0):
     """Algorithm 2.  Returns (out (odim, m or len(sample)), n_proxy_evals,
-    n_direct_evals)."""
+    n_direct_evals).  deg_min >= 1 selects the separation rule for the
+    degree of each accepted cluster (orc_rule_degree)."""
     tgt, src, w = _c(tgt), _c(src), _c(w)
     m, n = tgt.shape[1], src.shape[1]
     prm = _Params(KERNELS[kernel], float(eps), int(poly_p), float(poly_c),
                   int(degree), float(theta), int(leaf_max), int(mac_mode),
-                  int(batch_size), int(order_leaf), int(group_max))
+                  int(batch_size), int(order_leaf), int(group_max), int(deg_min))
     if sample is not None:
         sample = _c(sample, np.int64)
         k = sample.size
@@ -268,14 +273,16 @@ def treecode(kernel, tgt, src, w, eps, degree, theta, leaf_max, mac_mode=0,
     return out, npx.value, ndr.value
 
 
-def lists(src, leaf_max, tgt, theta, batch_size, order_leaf, group_max=512):
-    """Batch-walk interaction lists as a dict of CSR arrays."""
+def lists(src, leaf_max, tgt, theta, batch_size, order_leaf, group_max=512, degree=1,
+          deg_min=0):
+    """Batch-walk interaction lists as a dict of CSR arrays, with the degree
+    of every proxy entry (`degree` unless deg_min >= 1)."""
     src, tgt = _c(src), _c(tgt)
     L = _load()
     h = L.orc_lists_new(_p(src[0]), _p(src[1]), _p(src[2]), src.shape[1],
                         int(leaf_max), _p(tgt[0]), _p(tgt[1]), _p(tgt[2]),
                         tgt.shape[1], float(theta), int(batch_size),
-                        int(order_leaf), int(group_max))
+                        int(order_leaf), int(group_max), int(degree), int(deg_min))
     nb, npx, ndr = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
     L.orc_lists_sizes(h, ctypes.byref(nb), ctypes.byref(npx), ctypes.byref(ndr))
     out = dict(tperm=np.zeros(tgt.shape[1], np.int64),
@@ -287,6 +294,8 @@ def lists(src, leaf_max, tgt, theta, batch_size, order_leaf, group_max=512):
     L.orc_lists_export(h, _p(out["tperm"]), _p(out["bptr"]),
                        _p(out["prox_ptr"]), _p(out["prox_ids"]),
                        _p(out["dir_ptr"]), _p(out["dir_ids"]))
+    out["prox_deg"] = np.zeros(npx.value, np.int32)
+    L.orc_lists_export_degrees(h, _p(out["prox_deg"]))
     L.orc_lists_free(h)
     return out
 

@@ -108,6 +108,7 @@ int orc_modified_weights(const orc_tree* t, const double* x, const double* y,
                          int form, double* fhat);
 
 /* ---- treecode.c --------------------------------------------------------- */
+#define ORC_MAX_DEGREE 16
 typedef struct {
   int kernel;          /* ORC_STOKESLET, ORC_ROTLET, ORC_POLY */
   double eps;          /* MRS regularisation */
@@ -121,7 +122,15 @@ typedef struct {
   int64_t batch_size;  /* targets per batch (mode 1) */
   int64_t order_leaf;  /* leaf size of the target ordering tree (mode 1) */
   int64_t group_max;   /* batches never span two groups of this size (mode 1) */
+  int deg_min;         /* 0: every accepted cluster uses `degree` (paper);
+                          >= 1: separation rule, degrees in [deg_min, degree] */
 } orc_params;
+
+/* Separation rule (deg_min >= 1), see treecode.c: thresholds T[d] for
+ * d in [deg_min, degree - 1] (others -1), and the degree of an accepted
+ * cluster: the smallest such d with (rr*rr)/R2 <= T[d], else `degree`. */
+void orc_rule_table(const orc_params* p, double* T);
+int orc_rule_degree(const orc_params* p, const double* T, double rr, double R2);
 
 /* Treecode velocities out[odim][m] in input order.  Counts of kernel
  * evaluations (proxy and direct) are returned through the two pointers
@@ -140,7 +149,10 @@ orc_lists* orc_lists_new(const double* sx, const double* sy, const double* sz,
                          int64_t n, int64_t leaf_max,
                          const double* tx, const double* ty, const double* tz,
                          int64_t m, double theta, int64_t batch_size,
-                         int64_t order_leaf, int64_t group_max);
+                         int64_t order_leaf, int64_t group_max, int degree,
+                         int deg_min);
+/* Degree of every proxy-list entry (orc_rule_degree; `degree` if deg_min = 0). */
+void orc_lists_export_degrees(const orc_lists* L, int32_t* prox_deg);
 void orc_lists_sizes(const orc_lists* L, int64_t* nb, int64_t* nprox,
                      int64_t* ndir);
 void orc_lists_export(const orc_lists* L, int64_t* tperm, int64_t* bptr,

@@ -19,6 +19,19 @@
  * also satisfies the per-target MAC for theta <= 1; with one target per
  * batch (r_B = 0) the two modes agree bit for bit.
  *
+ * Separation rule (deg_min >= 1; not in the paper, which uses one degree):
+ * Chebyshev interpolation of a function analytic inside the Bernstein
+ * ellipse of parameter 1/kappa converges like kappa^n; for the kernel seen
+ * from a cluster at ratio rho = r/R the singularity at the target gives
+ * kappa(rho) = rho / (1 + sqrt(1 - rho^2)).  An accepted cluster at ratio
+ * rho = (r_B + r_C)/R is interpolated with the smallest degree
+ * d in [deg_min, degree] with kappa(rho)^(d+1) <= kappa(theta)^(degree+1):
+ * no cluster exceeds the error scale of the worst accepted cluster of the
+ * fixed-degree walk (rho = theta, degree), and well-separated clusters use
+ * fewer grid points.  Equivalently rho^2 <= T[d] with the thresholds
+ *   T[d] = (2k / (1 + k^2))^2,  k = kappa(theta)^((degree+1)/(d+1)),
+ * so the per-cluster decision needs only the MAC's rr and R2.
+ *
  * Summation order: clusters in depth-first order with children in their
  * stored order, grid points with k3 fastest, leaf particles in tree order.
  */
@@ -38,13 +51,33 @@ typedef struct {
   int64_t* pend;
   double* ys;      /* tree-ordered sources [3][n] */
   double* ws;      /* tree-ordered weights [wdim][n] */
-  double* grid;    /* [nn][3][n1] */
-  double* fhat;    /* [nn][wdim][nk] */
-  int wdim, odim, n1;
-  int64_t nk;
+  double T[ORC_MAX_DEGREE + 1];       /* separation-rule thresholds */
+  double* grid[ORC_MAX_DEGREE + 1];   /* per degree d: [nn][3][d+1] */
+  double* fhat[ORC_MAX_DEGREE + 1];   /* per degree d: [nn][wdim][(d+1)^3] */
+  int wdim, odim;
   const orc_params* p;
 } walk_ctx;
 
+void orc_rule_table(const orc_params* p, double* T) {
+  for (int d = 0; d <= ORC_MAX_DEGREE; ++d) T[d] = -1.0;
+  if (p->deg_min < 1 || p->deg_min >= p->degree) return;
+  const double kt = p->theta / (1.0 + sqrt(1.0 - p->theta * p->theta));
+  for (int d = p->deg_min; d < p->degree; ++d) {
+    const double k = pow(kt, (double)(p->degree + 1) / (double)(d + 1));
+    const double r = (2.0 * k) / (1.0 + k * k);
+    T[d] = r * r;
+  }
+}
+
+int orc_rule_degree(const orc_params* p, const double* T, double rr, double R2) {
+  if (p->deg_min < 1 || p->deg_min >= p->degree) return p->degree;
+  const double q = (rr * rr) / R2;
+  for (int d = p->deg_min; d < p->degree; ++d)
+    if (q <= T[d]) return d;
+  return p->degree;
+}
+
+/* 0 if the MAC fails, else 1 + the degree the cluster is interpolated with. */
 static int mac_holds(const walk_ctx* c, const double xc[3], double rB,
                      int64_t q) {
   double dx = xc[0] - c->center[3 * q + 0];
@@ -53,25 +86,29 @@ static int mac_holds(const walk_ctx* c, const double xc[3], double rB,
   double R2 = dx * dx + dy * dy + dz * dz;
   if (!(R2 > 0.0)) return 0;
   double rr = rB + c->radius[q];
-  return rr * rr <= (c->p->theta * c->p->theta) * R2;
+  if (!(rr * rr <= (c->p->theta * c->p->theta) * R2)) return 0;
+  return 1 + orc_rule_degree(c->p, c->T, rr, R2);
 }
 
 static void compute_velocity(const walk_ctx* c, const double x[3],
                              const double xc[3], double rB, int64_t q,
                              double* acc, int64_t* np, int64_t* nd) {
   const orc_params* p = c->p;
-  if (mac_holds(c, xc, rB, q)) {
-    const double* g = c->grid + q * 3 * c->n1;
-    const double* fq = c->fhat + q * c->wdim * c->nk;
-    for (int k1 = 0; k1 < c->n1; ++k1)
-      for (int k2 = 0; k2 < c->n1; ++k2)
-        for (int k3 = 0; k3 < c->n1; ++k3) {
-          int64_t kk = ((int64_t)k1 * c->n1 + k2) * c->n1 + k3;
-          double s[3] = {g[k1], g[c->n1 + k2], g[2 * c->n1 + k3]};
-          double f[3] = {fq[kk], fq[c->nk + kk], fq[2 * c->nk + kk]};
+  const int acc_deg = mac_holds(c, xc, rB, q);
+  if (acc_deg) {
+    const int n1 = acc_deg;   /* degree + 1 */
+    const int64_t nk = (int64_t)n1 * n1 * n1;
+    const double* g = c->grid[n1 - 1] + q * 3 * n1;
+    const double* fq = c->fhat[n1 - 1] + q * c->wdim * nk;
+    for (int k1 = 0; k1 < n1; ++k1)
+      for (int k2 = 0; k2 < n1; ++k2)
+        for (int k3 = 0; k3 < n1; ++k3) {
+          int64_t kk = ((int64_t)k1 * n1 + k2) * n1 + k3;
+          double s[3] = {g[k1], g[n1 + k2], g[2 * n1 + k3]};
+          double f[3] = {fq[kk], fq[nk + kk], fq[2 * nk + kk]};
           orc_pair(p->kernel, p->eps, p->poly_p, p->poly_c, x, s, f, acc);
         }
-    *np += c->nk;
+    *np += nk;
   } else if (c->child_count[q] == 0) {
     for (int64_t j = c->pbegin[q]; j < c->pend[q]; ++j) {
       double y[3] = {c->ys[j], c->ys[c->n + j], c->ys[2 * c->n + j]};
@@ -88,7 +125,8 @@ static void compute_velocity(const walk_ctx* c, const double x[3],
 static void ctx_free(walk_ctx* c) {
   free(c->perm); free(c->center); free(c->radius); free(c->child_first);
   free(c->child_count); free(c->pbegin); free(c->pend); free(c->ys);
-  free(c->ws); free(c->grid); free(c->fhat);
+  free(c->ws);
+  for (int d = 0; d <= ORC_MAX_DEGREE; ++d) { free(c->grid[d]); free(c->fhat[d]); }
 }
 
 /* Tree export plus tree-ordered copies of the sources; with degree >= 1 also
@@ -98,6 +136,7 @@ static int ctx_init(walk_ctx* c, const orc_params* p, const double* sx,
                     const double* w) {
   memset(c, 0, sizeof *c);
   c->p = p;
+  orc_rule_table(p, c->T);
   if (orc_kernel_dims(p->kernel, &c->wdim, &c->odim)) return -1;
   orc_tree* t = orc_tree_new(sx, sy, sz, n, p->leaf_max);
   int64_t nn = orc_tree_nnodes(t);
@@ -122,13 +161,15 @@ static int ctx_init(walk_ctx* c, const orc_params* p, const double* sx,
     c->ys[2 * n + i] = sz[j];
     for (int k = 0; k < c->wdim; ++k) c->ws[k * n + i] = w[k * n + j];
   }
-  c->n1 = p->degree + 1;
-  c->nk = (int64_t)c->n1 * c->n1 * c->n1;
-  c->grid = malloc(sizeof(double) * 3 * c->n1 * nn1);
-  c->fhat = malloc(sizeof(double) * c->wdim * c->nk * nn1);
-  orc_cluster_grids(t, p->degree, c->grid);
-  int rc = orc_modified_weights(t, sx, sy, sz, w, c->wdim, p->degree, 0,
-                                c->fhat);
+  int rc = 0;
+  const int dlo = p->deg_min >= 1 && p->deg_min < p->degree ? p->deg_min : p->degree;
+  for (int d = dlo; d <= p->degree && rc == 0; ++d) {
+    const int64_t n1 = d + 1;
+    c->grid[d] = malloc(sizeof(double) * 3 * n1 * nn1);
+    c->fhat[d] = malloc(sizeof(double) * c->wdim * n1 * n1 * n1 * nn1);
+    orc_cluster_grids(t, d, c->grid[d]);
+    rc = orc_modified_weights(t, sx, sy, sz, w, c->wdim, d, 0, c->fhat[d]);
+  }
   orc_tree_free(t);
   return rc;
 }
@@ -138,7 +179,8 @@ int orc_treecode(const orc_params* p,
                  const double* sx, const double* sy, const double* sz, int64_t n,
                  const double* w, const int64_t* sample, int64_t ksample,
                  double* out, int64_t* n_proxy_evals, int64_t* n_direct_evals) {
-  if (p->degree < 1 || p->leaf_max < 1) return -1;
+  if (p->degree < 1 || p->degree > ORC_MAX_DEGREE || p->leaf_max < 1 || p->deg_min < 0)
+    return -1;
   walk_ctx c;
   if (ctx_init(&c, p, sx, sy, sz, n, w)) { ctx_free(&c); return -1; }
   int64_t nout = ksample > 0 ? ksample : m;
@@ -197,6 +239,7 @@ struct orc_lists {
   int64_t* prox_ptr;
   int64_t* dir_ptr;
   int32_t* prox;
+  int32_t* pdeg;
   int32_t* dir;
   int64_t nprox, ndir;
 };
@@ -211,14 +254,16 @@ static void ipush(ivec* a, int32_t x) {
 }
 
 static void list_walk(const walk_ctx* c, const double xc[3], double rB,
-                      int64_t q, ivec* prox, ivec* dir) {
-  if (mac_holds(c, xc, rB, q)) {
+                      int64_t q, ivec* prox, ivec* pdeg, ivec* dir) {
+  const int acc_deg = mac_holds(c, xc, rB, q);
+  if (acc_deg) {
     ipush(prox, (int32_t)q);
+    ipush(pdeg, acc_deg - 1);
   } else if (c->child_count[q] == 0) {
     ipush(dir, (int32_t)q);
   } else {
     for (int32_t ch = 0; ch < c->child_count[q]; ++ch)
-      list_walk(c, xc, rB, c->child_first[q] + ch, prox, dir);
+      list_walk(c, xc, rB, c->child_first[q] + ch, prox, pdeg, dir);
   }
 }
 
@@ -226,11 +271,13 @@ orc_lists* orc_lists_new(const double* sx, const double* sy, const double* sz,
                          int64_t n, int64_t leaf_max,
                          const double* tx, const double* ty, const double* tz,
                          int64_t m, double theta, int64_t batch_size,
-                         int64_t order_leaf, int64_t group_max) {
+                         int64_t order_leaf, int64_t group_max, int degree,
+                         int deg_min) {
   orc_params p;
   memset(&p, 0, sizeof p);
   p.kernel = ORC_STOKESLET;
-  p.degree = 1;
+  p.degree = degree >= 1 ? degree : 1;
+  p.deg_min = deg_min;
   p.theta = theta;
   p.leaf_max = leaf_max;
   p.mac_mode = 1;
@@ -238,6 +285,7 @@ orc_lists* orc_lists_new(const double* sx, const double* sy, const double* sz,
   walk_ctx c;
   memset(&c, 0, sizeof c);
   c.p = &p;
+  orc_rule_table(&p, c.T);
   orc_tree* t = orc_tree_new(sx, sy, sz, n, leaf_max);
   int64_t nn = orc_tree_nnodes(t), nn1 = nn > 0 ? nn : 1;
   c.nn = nn;
@@ -261,15 +309,16 @@ orc_lists* orc_lists_new(const double* sx, const double* sy, const double* sz,
                       L->tperm, L->bptr, bc, br);
   L->prox_ptr = malloc(sizeof(int64_t) * (L->nb + 1));
   L->dir_ptr = malloc(sizeof(int64_t) * (L->nb + 1));
-  ivec prox = {0}, dir = {0};
+  ivec prox = {0}, pdeg = {0}, dir = {0};
   for (int64_t b = 0; b < L->nb; ++b) {
     L->prox_ptr[b] = prox.n;
     L->dir_ptr[b] = dir.n;
-    if (nn > 0) list_walk(&c, bc + 3 * b, br[b], 0, &prox, &dir);
+    if (nn > 0) list_walk(&c, bc + 3 * b, br[b], 0, &prox, &pdeg, &dir);
   }
   L->prox_ptr[L->nb] = prox.n;
   L->dir_ptr[L->nb] = dir.n;
   L->prox = prox.v;
+  L->pdeg = pdeg.v;
   L->dir = dir.v;
   L->nprox = prox.n;
   L->ndir = dir.n;
@@ -296,9 +345,13 @@ void orc_lists_export(const orc_lists* L, int64_t* tperm, int64_t* bptr,
   if (dir_ids && L->ndir) memcpy(dir_ids, L->dir, sizeof(int32_t) * L->ndir);
 }
 
+void orc_lists_export_degrees(const orc_lists* L, int32_t* prox_deg) {
+  if (prox_deg && L->nprox) memcpy(prox_deg, L->pdeg, sizeof(int32_t) * L->nprox);
+}
+
 void orc_lists_free(orc_lists* L) {
   if (!L) return;
   free(L->tperm); free(L->bptr); free(L->prox_ptr); free(L->dir_ptr);
-  free(L->prox); free(L->dir);
+  free(L->prox); free(L->pdeg); free(L->dir);
   free(L);
 }

@@ -38,7 +38,7 @@ class Options(ctypes.Structure):
     _fields_ = [("size", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("batch_size", ctypes.c_int32), ("order_leaf", ctypes.c_int32),
                 ("poly_p", ctypes.c_int32), ("poly_c", ctypes.c_double),
-                ("group_max", ctypes.c_int64)]
+                ("group_max", ctypes.c_int64), ("deg_min", ctypes.c_int32)]
 
 
 def declared_functions():
@@ -79,8 +79,8 @@ def load():
         "bltc_evaluate_tree": (ctypes.c_int, [P, P, I32, D, I32, D, P, P, P]),
         "bltc_evaluate": (ctypes.c_int, [P, P, P, I64, P, P, P, I64, P, I32, D,
                                          I32, D, I64, P, P, P]),
-        "bltc_lists_export": (ctypes.c_int, [P, P, D] + [P] * 7),
-        "bltc_counts": (ctypes.c_int, [P, P, I32, D, P, P]),
+        "bltc_lists_export": (ctypes.c_int, [P, P, D, I32, I32] + [P] * 8),
+        "bltc_counts": (ctypes.c_int, [P, P, I32, D, I32, P, P]),
         "bltc_mlp_params": (ctypes.c_int, [I32, P]),
         "bltc_mlp_work_size": (ctypes.c_int, [I64, I32, P]),
         "bltc_mlp_forward": (ctypes.c_int, [P, P, I64, I32, P, P, P]),
@@ -93,7 +93,7 @@ def load():
         "bltc_selector_info": (ctypes.c_int, [P, P, P, P]),
         "bltc_batch_features": (ctypes.c_int, [P, P, I32, D, D, P, P]),
         "bltc_batch_counts": (ctypes.c_int, [P, P, D, P, P, P]),
-        "bltc_evaluate_adaptive": (ctypes.c_int, [P, P, I32, D, P, D, I32, D, P, P, P, P, P]),
+        "bltc_evaluate_adaptive": (ctypes.c_int, [P, P, I32, D, P, D, I32, D, P, P, P, P, P, P]),
         "bltc_profile_enable": (ctypes.c_int, [I32]),
         "bltc_profile_read": (ctypes.c_int, [P, P, I32]),
         "bltc_direct": (ctypes.c_int, [P, P, P, I64, P, I64, P, P, P, I64, P, I32,
@@ -113,9 +113,10 @@ def _check(rc):
 
 
 def options(precision="fp64", batch_size=64, order_leaf=32, poly_p=2,
-            poly_c=1.0, group_max=512):
+            poly_c=1.0, group_max=512, deg_min=0):
     o = Options()
     load().bltc_options_default(ctypes.byref(o))
+    o.deg_min = int(deg_min)
     o.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     o.batch_size = int(batch_size)
     o.order_leaf = int(order_leaf)
@@ -248,13 +249,14 @@ class Targets:
 
 
 def evaluate_tree(tree, targets, kernel, eps, degree, theta, precision="fp64",
-                  out=None, poly_p=2, poly_c=1.0):
+                  out=None, poly_p=2, poly_c=1.0, deg_min=0):
+    """deg_min >= 1 turns on the separation rule (bltc_options.deg_min)."""
     torch = _torch()
     od = ODIM[kernel]
     if out is None:
         out = torch.empty((od, targets.m), dtype=torch.float64, device="cuda")
     _dev(out, "out", od)
-    o = options(precision, targets.batch_size, 32, poly_p, poly_c)
+    o = options(precision, targets.batch_size, 32, poly_p, poly_c, deg_min=deg_min)
     ptr = ctypes.c_void_p(out.data_ptr()) if targets.m else None
     _check(load().bltc_evaluate_tree(tree._h, targets._h, KERNELS[kernel], float(eps),
                                      int(degree), float(theta), ctypes.byref(o), ptr,
@@ -264,7 +266,7 @@ def evaluate_tree(tree, targets, kernel, eps, degree, theta, precision="fp64",
 
 def evaluate(tgt, src, w, kernel, eps, degree, theta, leaf_max, precision="fp64",
              batch_size=64, order_leaf=32, group_max=512, poly_p=2, poly_c=1.0,
-             out=None):
+             out=None, deg_min=0):
     """One call: tree, batches, modified weights and evaluation."""
     torch = _torch()
     tx, ty, tz, m = _rows(tgt, "tgt")
@@ -274,7 +276,7 @@ def evaluate(tgt, src, w, kernel, eps, degree, theta, leaf_max, precision="fp64"
     if out is None:
         out = torch.empty((od, m), dtype=torch.float64, device="cuda")
     _dev(out, "out", od)
-    o = options(precision, batch_size, order_leaf, poly_p, poly_c, group_max)
+    o = options(precision, batch_size, order_leaf, poly_p, poly_c, group_max, deg_min)
     _check(load().bltc_evaluate(tx, ty, tz, m, sx, sy, sz, n,
                                 ctypes.c_void_p(w.data_ptr()) if n else None,
                                 KERNELS[kernel], float(eps), int(degree), float(theta),
@@ -283,22 +285,26 @@ def evaluate(tgt, src, w, kernel, eps, degree, theta, leaf_max, precision="fp64"
     return out
 
 
-def lists(tree, targets, theta):
+def lists(tree, targets, theta, degree=1, deg_min=0):
+    """Interaction lists (host arrays); prox_deg holds each accepted cluster's
+    degree (degree unless the separation rule is on)."""
     L = load()
     nb, npx, ndr = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
-    _check(L.bltc_lists_export(tree._h, targets._h, float(theta), ctypes.byref(nb),
-                               ctypes.byref(npx), ctypes.byref(ndr), None, None, None, None))
+    _check(L.bltc_lists_export(tree._h, targets._h, float(theta), int(degree), int(deg_min),
+                               ctypes.byref(nb), ctypes.byref(npx), ctypes.byref(ndr),
+                               None, None, None, None, None))
     out = dict(prox_ptr=np.zeros(nb.value + 1, np.int64), prox_ids=np.zeros(npx.value, np.int32),
+               prox_deg=np.zeros(npx.value, np.int32),
                dir_ptr=np.zeros(nb.value + 1, np.int64), dir_ids=np.zeros(ndr.value, np.int32))
-    _check(L.bltc_lists_export(tree._h, targets._h, float(theta), None, None, None,
-                               _hp(out["prox_ptr"]), _hp(out["prox_ids"]),
-                               _hp(out["dir_ptr"]), _hp(out["dir_ids"])))
+    _check(L.bltc_lists_export(tree._h, targets._h, float(theta), int(degree), int(deg_min),
+                               None, None, None, _hp(out["prox_ptr"]), _hp(out["prox_ids"]),
+                               _hp(out["prox_deg"]), _hp(out["dir_ptr"]), _hp(out["dir_ids"])))
     return out
 
 
-def counts(tree, targets, degree, theta):
+def counts(tree, targets, degree, theta, deg_min=0):
     a, b = ctypes.c_int64(), ctypes.c_int64()
-    _check(load().bltc_counts(tree._h, targets._h, int(degree), float(theta),
+    _check(load().bltc_counts(tree._h, targets._h, int(degree), float(theta), int(deg_min),
                               ctypes.byref(a), ctypes.byref(b)))
     return a.value, b.value
 
@@ -484,8 +490,9 @@ class Selector:
 
 def evaluate_adaptive(tree, targets, kernel, eps, selector, tol, fb_degree, fb_theta,
                       precision="fp32_fp64acc", out=None):
-    """Returns (out, choice per batch, stats [batches, model fallbacks, guard
-    fallbacks, distinct degrees])."""
+    """Returns (out, choice per batch (candidate index, or -2 when the judge
+    sent the batch to the fallback), stats [batches, distinct degrees, batches
+    re-evaluated, 0], judge [error estimate before, after re-evaluation])."""
     torch = _torch()
     od = ODIM[kernel]
     if out is None:
@@ -494,9 +501,10 @@ def evaluate_adaptive(tree, targets, kernel, eps, selector, tol, fb_degree, fb_t
     o = options(precision, targets.batch_size, 32)
     choice = np.zeros(max(targets.nb, 1), np.int32)
     stats = np.zeros(4, np.int64)
+    judge = np.zeros(2, np.float64)
     _check(load().bltc_evaluate_adaptive(tree._h, targets._h, KERNELS[kernel], float(eps),
                                          selector._h, float(tol), int(fb_degree),
                                          float(fb_theta), ctypes.byref(o),
                                          ctypes.c_void_p(out.data_ptr()) if targets.m else None,
-                                         _hp(choice), _hp(stats), _stream()))
-    return out, choice[:targets.nb], stats
+                                         _hp(choice), _hp(stats), _hp(judge), _stream()))
+    return out, choice[:targets.nb], stats, judge

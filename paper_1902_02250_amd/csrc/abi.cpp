@@ -7,7 +7,9 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <array>
 #include <map>
+#include <mutex>
 #include <utility>
 #include <new>
 #include <string>
@@ -66,6 +68,37 @@ void d2h(T* dst, const T* src, size_t count, hipStream_t s) {
 
 void sync(hipStream_t s) { hipchk(hipStreamSynchronize(s), "hipStreamSynchronize"); }
 
+// Library-owned streams (default priority) for independent launches, per
+// device, created on first use and kept for the life of the process.
+constexpr int kSideStreams = 4;
+std::mutex g_side_mu;
+std::map<int, std::array<hipStream_t, kSideStreams>> g_side;
+
+hipStream_t side_stream(int i) {
+  int dev = 0;
+  hipchk(hipGetDevice(&dev), "hipGetDevice");
+  std::lock_guard<std::mutex> lock(g_side_mu);
+  auto it = g_side.find(dev);
+  if (it == g_side.end()) it = g_side.emplace(dev, std::array<hipStream_t, kSideStreams>{}).first;
+  hipStream_t& st = it->second[i % kSideStreams];
+  if (!st) hipchk(hipStreamCreateWithFlags(&st, hipStreamNonBlocking), "hipStreamCreate");
+  return st;
+}
+
+// Events without timing, destroyed with the holder.
+struct Events {
+  std::vector<hipEvent_t> ev;
+  hipEvent_t make() {
+    hipEvent_t e;
+    hipchk(hipEventCreateWithFlags(&e, hipEventDisableTiming), "hipEventCreate");
+    ev.push_back(e);
+    return e;
+  }
+  ~Events() {
+    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+  }
+};
+
 // True if p points into device (or managed) memory that kernels may read.
 bool device_ptr(const void* p) {
   if (!p) return false;
@@ -115,6 +148,8 @@ int check_options(const bltc_options* o, int kernel) {
   if (o->order_leaf < 1) return fail(BLTC_EINVAL, "order_leaf must be >= 1");
   if (o->group_max < 1) return fail(BLTC_EINVAL, "group_max must be >= 1");
   if (o->poly_p < 0 || o->poly_p > 64) return fail(BLTC_EINVAL, "poly_p must be in [0, 64]");
+  if (o->deg_min < 0 || o->deg_min > bltc::kMaxDegree)
+    return fail(BLTC_EINVAL, "deg_min must be in [0, 12]");
   return BLTC_OK;
 }
 
@@ -189,6 +224,7 @@ void destroy_tree(bltc_tree t) {
   dfree(t->d_perm); dfree(t->d_y); dfree(t->d_box); dfree(t->d_geo);
   dfree(t->d_range); dfree(t->d_kids); dfree(t->d_w64); dfree(t->d_w32);
   dfree(t->d_chunks); dfree(t->d_chunk_ptr); dfree(t->d_partial);
+  dfree(t->d_need);
   delete t;
 }
 
@@ -251,8 +287,16 @@ void build_tree(const double* x, const double* y, const double* z, int64_t n,
 
 // Grid and modified weights of one degree from the stored tree-ordered
 // weights.
-void ensure_degree(bltc_tree t, int degree, hipStream_t s) {
-  if (t->deg.count(degree)) return;
+// Modified weights at `degree`, cached per degree until the weights change.
+// With a need mask (device bytes per cluster) only the flagged clusters get
+// weights; such a partial set is never reused.
+void ensure_degree(bltc_tree t, int degree, hipStream_t s, const uint8_t* need = nullptr) {
+  auto it = t->deg.find(degree);
+  if (it != t->deg.end()) {
+    if (!it->second.partial) return;
+    destroy_degree(it->second);
+    t->deg.erase(it);
+  }
   const int64_t nn = t->host.nnodes();
   const int n1 = degree + 1;
   const int64_t nk = (int64_t)n1 * n1 * n1;
@@ -262,22 +306,23 @@ void ensure_degree(bltc_tree t, int degree, hipStream_t s) {
     d.fhat64 = dalloc<double>(nn * 3 * nk);
     d.p2p64 = dalloc<double>(nn * 3 * nk);
     d.p2p32 = dalloc<float>(nn * 3 * nk);
+    d.partial = need != nullptr;
     double tk[bltc::kMaxDegree + 1];
     bltc::cheb_points(degree, tk);
     StageTimer prep(BLTC_STAGE_PREP, s);
     hipchk(bltc::launch_grids(t->d_box, nn, degree, tk, d.grid, s), "grids");
     prep.stop();
-    const size_t need = (size_t)t->nchunks * 3 * nk;
-    if (need > t->partial_cap) {
+    const size_t want = (size_t)t->nchunks * 3 * nk;
+    if (want > t->partial_cap) {
       dfree(t->d_partial);
-      t->d_partial = dalloc<double>(need);
-      t->partial_cap = need;
+      t->d_partial = dalloc<double>(want);
+      t->partial_cap = want;
     }
     StageTimer up(BLTC_STAGE_UPWARD, s);
     hipchk(bltc::launch_upward(t->d_y, t->d_w64, t->n, t->d_chunks,
-                               t->nchunks, d.grid, degree, t->d_partial, s),
+                               t->nchunks, d.grid, degree, need, t->d_partial, s),
            "upward");
-    hipchk(bltc::launch_upward_reduce(t->d_chunk_ptr, nn, t->d_partial, degree,
+    hipchk(bltc::launch_upward_reduce(t->d_chunk_ptr, nn, t->d_partial, degree, need,
                                       d.fhat64, d.p2p64, d.p2p32, s),
            "upward reduce");
     up.stop();
@@ -313,6 +358,7 @@ void destroy_targets(bltc_targets g) {
   dfree(g->d_feat); dfree(g->d_Y); dfree(g->d_pc); dfree(g->d_sc);
   dfree(g->d_choice); dfree(g->d_bmap); dfree(g->d_theta_b); dfree(g->d_spos);
   dfree(g->d_sbatch); dfree(g->d_gflag); dfree(g->d_ufb);
+  dfree(g->d_wt); dfree(g->d_contrib); dfree(g->d_part); dfree(g->d_sums); dfree(g->d_lam);
   delete g;
 }
 
@@ -357,6 +403,24 @@ void build_targets(const double* x, const double* y, const double* z,
   sync(s);
 }
 
+// Separation-rule thresholds for evaluation degree n and MAC theta: for d in
+// [deg_min, n), T[d] = (2k / (1 + k^2))^2 with k = kappa(theta)^((n+1)/(d+1)),
+// kappa(r) = r / (1 + sqrt(1 - r^2)); a cluster at ratio rho takes the first
+// d with rho^2 <= T[d].  deg_min outside [1, n) turns the rule off.
+bltc::Rule make_rule(double theta, int degree, int deg_min) {
+  bltc::Rule r;
+  if (deg_min < 1 || deg_min >= degree) return r;
+  r.deg_min = deg_min;
+  r.degree = degree;
+  const double kt = theta / (1.0 + std::sqrt(1.0 - theta * theta));
+  for (int d = deg_min; d < degree; ++d) {
+    const double k = std::pow(kt, (double)(degree + 1) / (double)(d + 1));
+    const double rho = (2.0 * k) / (1.0 + k * k);
+    r.T[d] = rho * rho;
+  }
+  return r;
+}
+
 bltc::ListArgs list_args(bltc_tree t, bltc_targets g, double theta,
                          const double* theta_b, bltc::ListSet& L) {
   const int64_t nb = g->nb;
@@ -383,9 +447,15 @@ bltc::ListArgs list_args(bltc_tree t, bltc_targets g, double theta,
 // Device interaction lists of every batch (MAC theta, or theta_b[b] when
 // theta_b is given) into L; returns the list sizes.
 void build_lists(bltc_tree t, bltc_targets g, double theta, const double* theta_b,
-                 bltc::ListSet& L, hipStream_t s, int64_t* np, int64_t* nd) {
+                 bltc::ListSet& L, hipStream_t s, int64_t* np, int64_t* nd,
+                 const bltc::Rule* rule = nullptr) {
   const int64_t nb = g->nb;
   bltc::ListArgs a = list_args(t, g, theta, theta_b, L);
+  if (rule) {
+    if (rule->deg_min > 0 && t->host.nnodes() > bltc::kIdMask)
+      throw HipError{BLTC_EINVAL, "the separation rule supports at most 2^27 - 1 clusters"};
+    a.rule = *rule;
+  }
   StageTimer lt(BLTC_STAGE_LISTS, s);
   hipchk(bltc::launch_lists(a, false, s), "list count");
   hipchk(bltc::launch_exclusive_scan(a.pcnt, nb, L.ptr, g->d_flags + 1, s), "scan");
@@ -438,6 +508,13 @@ void run_p2p(bltc_tree t, bltc_targets g, const bltc::ListSet& L, int kernel,
   a.range = t->d_range;
   a.grid = d.grid;
   a.fhat = o.precision == BLTC_FP64 ? (const void*)d.p2p64 : (const void*)d.p2p32;
+  if (o.deg_min >= 1 && o.deg_min < degree) {
+    for (int dd = o.deg_min; dd <= degree; ++dd) {
+      const bltc_degree_data& e = t->deg.at(dd);
+      a.grid_d[dd] = e.grid;
+      a.fhat_d[dd] = o.precision == BLTC_FP64 ? (const void*)e.p2p64 : (const void*)e.p2p32;
+    }
+  }
   a.ys = t->d_y;
   a.w64 = t->d_w64;
   a.w32 = t->d_w32;
@@ -458,7 +535,20 @@ void evaluate_tree(bltc_tree t, bltc_targets g, int kernel, double eps,
   if (g->m == 0) return;
   ensure_degree(t, degree, s);
   int64_t np = 0, nd = 0;
-  build_lists(t, g, theta, nullptr, g->ls[0], s, &np, &nd);
+  const bltc::Rule rule = make_rule(theta, degree, o.deg_min);
+  build_lists(t, g, theta, nullptr, g->ls[0], s, &np, &nd, &rule);
+  if (rule.deg_min > 0) {
+    // the lower degrees, for the clusters the rule gives them
+    const int64_t nn = t->host.nnodes();
+    if (!t->d_need) t->d_need = dalloc<uint8_t>(nn);
+    for (int d = rule.deg_min; d < degree; ++d) {
+      const auto it = t->deg.find(d);
+      if (it != t->deg.end() && !it->second.partial) continue;
+      hipchk(bltc::launch_need_degree(g->nb, g->ls[0].ptr, g->ls[0].pids, d, t->d_need, nn, s),
+             "need mask");
+      ensure_degree(t, d, s, t->d_need);
+    }
+  }
   run_p2p(t, g, g->ls[0], kernel, eps, degree, o, nullptr, 0, out, s);
 }
 
@@ -495,6 +585,8 @@ void batch_counts(bltc_tree t, bltc_targets g, double theta, int32_t* pc,
   hipchk(bltc::launch_lists(a, false, s), "list count");
 }
 
+constexpr int kLamGrid = 64;   // multipliers per allocation pass
+
 void ensure_selection_scratch(bltc_targets g, int64_t k, int64_t nth) {
   const int64_t nb = g->nb;
   if (!g->d_feat) {
@@ -504,7 +596,12 @@ void ensure_selection_scratch(bltc_targets g, int64_t k, int64_t nth) {
     g->d_theta_b = dalloc<double>(nb);
     g->d_gflag = dalloc<int32_t>(nb);
     g->d_ufb = dalloc<double>(6 * nb);
-    // one guard sample per batch at a hashed position inside the batch
+    g->d_wt = dalloc<double>(nb);
+    g->d_contrib = dalloc<double>(nb);
+    g->d_part = dalloc<double>(bltc::alloc_blocks(nb) * kLamGrid * 2);
+    g->d_sums = dalloc<double>(kLamGrid * 2);
+    g->d_lam = dalloc<double>(kLamGrid);
+    // one judge sample per batch at a hashed position inside the batch
     std::vector<int32_t> sp(nb), sb(nb);
     for (int64_t b = 0; b < nb; ++b) {
       const int32_t b0 = g->host.bptr[b], cnt = g->host.bptr[b + 1] - b0;
@@ -532,19 +629,33 @@ void ensure_selection_scratch(bltc_targets g, int64_t k, int64_t nth) {
   }
 }
 
+// Judge sums (sum of cnt |u_fb|^2, sum of cnt |u - u_fb|^2) over the one
+// sample per batch; `out` NULL gives the weights only.
+void judge_sums(bltc_targets g, int kernel, const double* out, double sums[2],
+                hipStream_t s) {
+  hipchk(bltc::launch_judge((int)g->nb, g->d_bptr, g->d_spos, g->d_tperm, out, g->m,
+                            odim_of(kernel), g->d_ufb, g->d_wt, g->d_contrib, g->d_part,
+                            g->d_sums, s),
+         "judge");
+  d2h(sums, g->d_sums, 2, s);
+  sync(s);
+}
+
+// Evaluation with (n, theta) chosen per batch (see bltc_evaluate_adaptive).
 void evaluate_adaptive(bltc_tree t, bltc_targets g, int kernel, double eps,
                        bltc_selector sel, double tol, int fb_degree, double fb_theta,
                        const bltc_options& o, double* out, int32_t* choice_out,
-                       int64_t* stats, hipStream_t s) {
+                       int64_t* stats, double* judge, hipStream_t s) {
   const int64_t nb = g->nb;
   int64_t st[4] = {nb, 0, 0, 0};
+  double jd[2] = {0.0, 0.0};
   if (g->m == 0) {
     if (stats) std::memcpy(stats, st, sizeof st);
+    if (judge) std::memcpy(judge, jd, sizeof jd);
     return;
   }
   const int k = sel->k;
-  // distinct thetas of the candidates
-  std::vector<double> thetas;
+  std::vector<double> thetas;   // distinct thetas of the candidates
   bltc::Candidates cand;
   for (int j = 0; j < k; ++j) {
     int ti = -1;
@@ -557,53 +668,22 @@ void evaluate_adaptive(bltc_tree t, bltc_targets g, int kernel, double eps,
     cand.n[j] = sel->cand_n[j];
     cand.t[j] = ti;
   }
+  const bltc::Costs costs{(float)sel->cost_far, (float)sel->cost_row, (float)sel->cost_clu,
+                          (float)sel->cost_near};
   const int64_t nth = (int64_t)thetas.size();
   ensure_selection_scratch(g, k, nth);
-  // features -> predicted log10 errors -> per-theta costs -> choice
+  const int od = odim_of(kernel);
+
+  // 1. predicted log10 errors of every candidate, and per-theta work counts
   compute_features(t, g, kernel, eps, sel->theta_ref, sel->d_mean, sel->d_std, g->d_feat, s);
   hipchk(bltc::launch_mlp_forward(sel->d_params, g->d_feat, nb, k, g->d_Y, nullptr, s),
          "mlp forward");
   for (int64_t ti = 0; ti < nth; ++ti)
     batch_counts(t, g, thetas[ti], g->d_pc + ti * nb, g->d_sc + ti * nb, s);
-  hipchk(bltc::launch_select(g->d_Y, k, nb, g->d_bptr, g->d_pc, g->d_sc, cand,
-                             (float)std::log10(tol), (float)sel->margin,
-                             (float)sel->cost_far, (float)sel->cost_near, g->d_choice, s),
-         "select");
-  std::vector<int32_t> choice(nb);
-  d2h(choice.data(), g->d_choice, nb, s);
-  sync(s);
-  // per-batch theta and degree; batches grouped by degree
-  std::vector<double> th(nb);
-  std::map<int, std::vector<int32_t>> by_degree;
-  for (int64_t b = 0; b < nb; ++b) {
-    int deg = fb_degree;
-    double tb = fb_theta;
-    if (choice[b] >= 0) {
-      deg = sel->cand_n[choice[b]];
-      tb = sel->cand_theta[choice[b]];
-    } else {
-      st[1]++;
-    }
-    th[b] = tb;
-    by_degree[deg].push_back((int32_t)b);
-  }
-  st[3] = (int64_t)by_degree.size();
-  h2d(g->d_theta_b, th.data(), nb, s);
-  for (auto& kv : by_degree) ensure_degree(t, kv.first, s);
+
+  // 2. the judge: the fallback treecode at one sample per batch
   ensure_degree(t, fb_degree, s);
   int64_t np = 0, nd = 0;
-  build_lists(t, g, 0.0, g->d_theta_b, g->ls[0], s, &np, &nd);
-  std::vector<int32_t> order;
-  std::vector<std::pair<int, std::pair<int64_t, int64_t>>> spans;
-  for (auto& kv : by_degree) {
-    spans.push_back({kv.first, {(int64_t)order.size(), (int64_t)kv.second.size()}});
-    order.insert(order.end(), kv.second.begin(), kv.second.end());
-  }
-  h2d(g->d_bmap, order.data(), nb, s);
-  for (auto& sp : spans)
-    run_p2p(t, g, g->ls[0], kernel, eps, sp.first, o, g->d_bmap + sp.second.first,
-            sp.second.second, out, s);
-  // guard: one sample per batch against the fallback treecode
   build_lists(t, g, fb_theta, nullptr, g->ls[1], s, &np, &nd);
   const bltc_degree_data& fd = t->deg.at(fb_degree);
   bltc::GuardArgs ga;
@@ -625,37 +705,152 @@ void evaluate_adaptive(bltc_tree t, bltc_targets g, int kernel, double eps,
   ga.eps = eps;
   kernel_scales(kernel, &ga.scale_u, &ga.scale_w);
   ga.ufb = g->d_ufb;
-  std::vector<int32_t> zeros(nb, 0);
-  h2d(g->d_gflag, zeros.data(), nb, s);
-  hipchk(bltc::launch_guard(kernel, fb_degree, ga, s), "guard");
-  hipchk(bltc::launch_guard_check((int)nb, g->d_spos, g->d_sbatch, g->d_tperm, out, g->m,
-                                  odim_of(kernel), g->d_ufb, tol, g->d_gflag, s),
-         "guard check");
-  std::vector<int32_t> flag(nb);
-  d2h(flag.data(), g->d_gflag, nb, s);
-  sync(s);
-  std::vector<int32_t> redo;
-  for (int64_t b = 0; b < nb; ++b)
-    if (flag[b] && choice[b] >= 0) {
-      redo.push_back((int32_t)b);
-      choice[b] = -2;
+  hipchk(bltc::launch_guard(kernel, fb_degree, ga, s), "judge samples");
+  double ws[2];
+  judge_sums(g, kernel, nullptr, ws, s);
+  const double wsum = ws[0];
+
+  // 3. error budget: minimise the modelled cost subject to
+  //    sum_b wn_b e_b^2 <= tau^2,  wn_b = w_b / sum w,  tau = tol 10^-margin,
+  //    by the multiplier lam of cost + lam wn e^2 / tau^2 (two grid passes)
+  const double tau = tol * std::pow(10.0, -sel->margin);
+  const double inv_w = wsum > 0.0 ? 1.0 / (wsum * tau * tau) : 0.0;
+  double lam_star = 0.0;
+  if (inv_w > 0.0) {
+    double lo = 0.0, hi = 24.0;   // log10 of the multiplier range
+    lam_star = std::pow(10.0, hi);
+    std::vector<double> lam(kLamGrid), sums(2 * kLamGrid);
+    for (int pass = 0; pass < 2; ++pass) {
+      for (int i = 0; i < kLamGrid; ++i)
+        lam[i] = std::pow(10.0, lo + (hi - lo) * i / (kLamGrid - 1));
+      h2d(g->d_lam, lam.data(), kLamGrid, s);
+      hipchk(bltc::launch_alloc(g->d_Y, k, nb, g->d_pc, g->d_sc, cand, costs, g->d_wt, inv_w,
+                                g->d_lam, kLamGrid, g->d_part, g->d_sums, s),
+             "allocation");
+      d2h(sums.data(), g->d_sums, 2 * kLamGrid, s);
+      sync(s);
+      // err sums are in units of tau^2 (wn carries 1/tau^2)
+      int first = -1;
+      for (int i = 0; i < kLamGrid; ++i)
+        if (sums[2 * i + 1] <= 1.0) {
+          first = i;
+          break;
+        }
+      if (first < 0) {         // not even the most accurate choices meet it
+        lam_star = lam[kLamGrid - 1];
+        break;
+      }
+      lam_star = lam[first];
+      if (first == 0) break;   // the cheapest choices already meet it
+      const double step = (hi - lo) / (kLamGrid - 1);
+      hi = lo + step * first;
+      lo = hi - step;
     }
-  st[2] = (int64_t)redo.size();
-  if (!redo.empty()) {
-    h2d(g->d_bmap, redo.data(), redo.size(), s);
-    run_p2p(t, g, g->ls[1], kernel, eps, fb_degree, o, g->d_bmap, (int64_t)redo.size(),
-            out, s);
+  }
+  hipchk(bltc::launch_choose(g->d_Y, k, nb, g->d_pc, g->d_sc, cand, costs, g->d_wt, inv_w,
+                             lam_star, g->d_choice, s),
+         "choose");
+  std::vector<int32_t> choice(nb);
+  d2h(choice.data(), g->d_choice, nb, s);
+  sync(s);
+
+  // 4. lists at each batch's theta; modified weights of every chosen degree
+  //    for the clusters its batches use; evaluation grouped by degree
+  std::vector<double> th(nb);
+  std::map<int, std::vector<int32_t>> by_degree;
+  for (int64_t b = 0; b < nb; ++b) {
+    th[b] = sel->cand_theta[choice[b]];
+    by_degree[sel->cand_n[choice[b]]].push_back((int32_t)b);
+  }
+  st[1] = (int64_t)by_degree.size();
+  h2d(g->d_theta_b, th.data(), nb, s);
+  build_lists(t, g, 0.0, g->d_theta_b, g->ls[0], s, &np, &nd);
+  std::vector<int32_t> order;
+  std::vector<std::pair<int, std::pair<int64_t, int64_t>>> spans;
+  for (auto& kv : by_degree) {
+    spans.push_back({kv.first, {(int64_t)order.size(), (int64_t)kv.second.size()}});
+    order.insert(order.end(), kv.second.begin(), kv.second.end());
+  }
+  h2d(g->d_bmap, order.data(), nb, s);
+  const int64_t nn = t->host.nnodes();
+  if (!t->d_need) t->d_need = dalloc<uint8_t>(nn);
+  for (auto& sp : spans) {   // upward passes in turn: they share scratch
+    const auto it = t->deg.find(sp.first);
+    if (it == t->deg.end() || it->second.partial) {
+      hipchk(bltc::launch_need(g->d_bmap + sp.second.first, sp.second.second, g->ls[0].ptr,
+                               g->ls[0].pids, t->d_need, nn, s),
+             "need mask");
+      ensure_degree(t, sp.first, s, t->d_need);
+    }
+  }
+  // the degree groups write disjoint targets: with more than one, they run
+  // concurrently on side streams, largest first
+  Events evs;
+  if (spans.size() == 1) {
+    run_p2p(t, g, g->ls[0], kernel, eps, spans[0].first, o, g->d_bmap, nb, out, s);
+  } else {
+    std::sort(spans.begin(), spans.end(), [](const auto& a, const auto& b) {
+      const double wa = (double)a.second.second * std::pow(a.first + 1.0, 3);
+      const double wb = (double)b.second.second * std::pow(b.first + 1.0, 3);
+      return wa > wb;
+    });
+    hipEvent_t ready = evs.make();
+    hipchk(hipEventRecord(ready, s), "hipEventRecord");
+    std::vector<hipEvent_t> done;
+    for (size_t i = 0; i < spans.size(); ++i) {
+      hipStream_t ss = side_stream((int)i);
+      hipchk(hipStreamWaitEvent(ss, ready, 0), "hipStreamWaitEvent");
+      run_p2p(t, g, g->ls[0], kernel, eps, spans[i].first, o,
+              g->d_bmap + spans[i].second.first, spans[i].second.second, out, ss);
+      if (i + kSideStreams >= spans.size()) {   // last launch on this side stream
+        hipEvent_t e = evs.make();
+        hipchk(hipEventRecord(e, ss), "hipEventRecord");
+        done.push_back(e);
+      }
+    }
+    for (hipEvent_t e : done) hipchk(hipStreamWaitEvent(s, e, 0), "hipStreamWaitEvent");
+  }
+
+  // 5. the judge's estimate of the global error; when it exceeds tol, every
+  //    batch above an equal share of the budget is evaluated again with the
+  //    fallback, which brings the estimate within tol
+  double js[2];
+  judge_sums(g, kernel, out, js, s);
+  jd[0] = jd[1] = wsum > 0.0 ? std::sqrt(js[1] / wsum) : 0.0;
+  if (js[1] > tol * tol * wsum) {
+    hipchk(bltc::launch_flag((int)nb, g->d_contrib, tol * tol * wsum / (double)nb, g->d_gflag,
+                             s),
+           "judge flags");
+    std::vector<int32_t> flag(nb);
+    d2h(flag.data(), g->d_gflag, nb, s);
+    sync(s);
+    std::vector<int32_t> redo;
+    for (int64_t b = 0; b < nb; ++b)
+      if (flag[b]) {
+        redo.push_back((int32_t)b);
+        choice[b] = -2;
+      }
+    st[2] = (int64_t)redo.size();
+    if (!redo.empty()) {
+      h2d(g->d_bmap, redo.data(), redo.size(), s);
+      run_p2p(t, g, g->ls[1], kernel, eps, fb_degree, o, g->d_bmap, (int64_t)redo.size(),
+              out, s);
+      judge_sums(g, kernel, out, js, s);
+      jd[1] = std::sqrt(js[1] / wsum);
+    }
   }
   sync(s);
+  (void)od;
   if (choice_out) std::memcpy(choice_out, choice.data(), sizeof(int32_t) * nb);
   if (stats) std::memcpy(stats, st, sizeof st);
+  if (judge) std::memcpy(judge, jd, sizeof jd);
 }
 
 // Selector model file (little endian):
-//   char magic[8] "BLTCSEL1"; int32 version (1); int32 n_in (12);
+//   char magic[8] "BLTCSEL1"; int32 version (2); int32 n_in (12);
 //   int32 n_hidden (64); int32 k;
 //   int32 cand_n[k]; double cand_theta[k];
-//   double theta_ref, cost_far, cost_near, margin;
+//   double theta_ref, cost_far, cost_row, cost_cluster, cost_near, margin;
 //   float mean[12], stdv[12]; float params[bltc_mlp_params(k)];
 //   uint64 FNV-1a hash of all preceding bytes.
 uint64_t fnv1a(const unsigned char* p, size_t n) {
@@ -686,14 +881,14 @@ int load_selector(const char* path, bltc_selector sel) {
   int32_t hdr[4];
   if (!take(magic, 8) || std::memcmp(magic, "BLTCSEL1", 8) != 0 || !take(hdr, sizeof hdr))
     return fail(BLTC_EMODEL, "selector model: bad magic or header");
-  if (hdr[0] != 1 || hdr[1] != bltc::kMlpIn || hdr[2] != bltc::kMlpHidden || hdr[3] < 1 ||
+  if (hdr[0] != 2 || hdr[1] != bltc::kMlpIn || hdr[2] != bltc::kMlpHidden || hdr[3] < 1 ||
       hdr[3] > bltc::kMlpMaxOut)
     return fail(BLTC_EMODEL, "selector model: unsupported version or dimensions");
   const int32_t k = hdr[3];
   sel->k = k;
   sel->cand_n.resize(k);
   sel->cand_theta.resize(k);
-  double tail[4];
+  double tail[6];
   sel->mean.resize(bltc::kMlpIn);
   sel->stdv.resize(bltc::kMlpIn);
   sel->params.resize(bltc::mlp_params(k));
@@ -708,8 +903,15 @@ int load_selector(const char* path, bltc_selector sel) {
     return fail(BLTC_EMODEL, "selector model: checksum mismatch or trailing bytes");
   sel->theta_ref = tail[0];
   sel->cost_far = tail[1];
-  sel->cost_near = tail[2];
-  sel->margin = tail[3];
+  sel->cost_row = tail[2];
+  sel->cost_clu = tail[3];
+  sel->cost_near = tail[4];
+  sel->margin = tail[5];
+  for (int i = 1; i < 5; ++i)
+    if (!(tail[i] >= 0.0 && tail[i] < 1e6))
+      return fail(BLTC_EMODEL, "selector model: cost weight out of range");
+  if (!(tail[5] > -6.0 && tail[5] < 6.0))
+    return fail(BLTC_EMODEL, "selector model: margin out of range");
   for (int j = 0; j < k; ++j)
     if (sel->cand_n[j] < 1 || sel->cand_n[j] > bltc::kMaxDegree ||
         !(sel->cand_theta[j] >= 0.0 && sel->cand_theta[j] <= 1.0))
@@ -983,14 +1185,20 @@ int bltc_evaluate(const double* tx, const double* ty, const double* tz,
   });
 }
 
-int bltc_lists_export(bltc_tree t, bltc_targets g, double theta, int64_t* nb,
-                      int64_t* n_prox, int64_t* n_dir, int64_t* prox_ptr,
-                      int32_t* prox_ids, int64_t* dir_ptr, int32_t* dir_ids) {
+int bltc_lists_export(bltc_tree t, bltc_targets g, double theta, int32_t degree,
+                      int32_t deg_min, int64_t* nb, int64_t* n_prox, int64_t* n_dir,
+                      int64_t* prox_ptr, int32_t* prox_ids, int32_t* prox_deg,
+                      int64_t* dir_ptr, int32_t* dir_ids) {
   if (!t || !g) return fail(BLTC_EINVAL, "NULL tree or targets");
   if (!(theta >= 0.0 && theta <= 1.0)) return fail(BLTC_EINVAL, "theta must be in [0, 1]");
+  if (degree < 1 || degree > bltc::kMaxDegree)
+    return fail(BLTC_EINVAL, "degree must be in [1, 12]");
+  if (deg_min < 0 || deg_min > bltc::kMaxDegree)
+    return fail(BLTC_EINVAL, "deg_min must be in [0, 12]");
   return guarded([&] {
     int64_t np = 0, nd = 0;
-    if (g->nb > 0) build_lists(t, g, theta, nullptr, g->ls[0], nullptr, &np, &nd);
+    const bltc::Rule rule = make_rule(theta, degree, deg_min);
+    if (g->nb > 0) build_lists(t, g, theta, nullptr, g->ls[0], nullptr, &np, &nd, &rule);
     if (nb) *nb = g->nb;
     if (n_prox) *n_prox = np;
     if (n_dir) *n_dir = nd;
@@ -999,13 +1207,20 @@ int bltc_lists_export(bltc_tree t, bltc_targets g, double theta, int64_t* nb,
       if (dir_ptr) dir_ptr[0] = 0;
       return (int)BLTC_OK;
     }
-    std::vector<int32_t> pp(g->nb + 1), dp(g->nb + 1);
+    std::vector<int32_t> pp(g->nb + 1), dp(g->nb + 1), pe(np);
     const bltc::ListSet& L = g->ls[0];
     d2h(pp.data(), L.ptr, g->nb + 1, nullptr);
     d2h(dp.data(), L.ptr + g->nb + 1, g->nb + 1, nullptr);
-    if (prox_ids) d2h(prox_ids, L.pids, np, nullptr);
+    d2h(pe.data(), L.pids, np, nullptr);
     if (dir_ids) d2h(dir_ids, L.dids, nd, nullptr);
     sync(nullptr);
+    for (int64_t i = 0; i < np; ++i) {
+      if (prox_ids) prox_ids[i] = pe[i] & bltc::kIdMask;
+      if (prox_deg) {
+        const int dd = pe[i] >> bltc::kDegShift;
+        prox_deg[i] = dd ? dd : degree;
+      }
+    }
     for (int64_t b = 0; b <= g->nb; ++b) {
       if (prox_ptr) prox_ptr[b] = pp[b];
       if (dir_ptr) dir_ptr[b] = dp[b];
@@ -1014,15 +1229,18 @@ int bltc_lists_export(bltc_tree t, bltc_targets g, double theta, int64_t* nb,
   });
 }
 
-int bltc_counts(bltc_tree t, bltc_targets g, int32_t degree, double theta,
+int bltc_counts(bltc_tree t, bltc_targets g, int32_t degree, double theta, int32_t deg_min,
                 int64_t* n_proxy_evals, int64_t* n_direct_evals) {
   if (!t || !g) return fail(BLTC_EINVAL, "NULL tree or targets");
   if (degree < 1 || degree > bltc::kMaxDegree)
     return fail(BLTC_EINVAL, "degree must be in [1, 12]");
   if (!(theta >= 0.0 && theta <= 1.0)) return fail(BLTC_EINVAL, "theta must be in [0, 1]");
+  if (deg_min < 0 || deg_min > bltc::kMaxDegree)
+    return fail(BLTC_EINVAL, "deg_min must be in [0, 12]");
   return guarded([&] {
     int64_t np = 0, nd = 0;
-    if (g->nb > 0) build_lists(t, g, theta, nullptr, g->ls[0], nullptr, &np, &nd);
+    const bltc::Rule rule = make_rule(theta, degree, deg_min);
+    if (g->nb > 0) build_lists(t, g, theta, nullptr, g->ls[0], nullptr, &np, &nd, &rule);
     std::vector<int32_t> pp(g->nb + 1), dp(g->nb + 1), pi(np), di(nd);
     if (g->nb > 0) {
       const bltc::ListSet& L = g->ls[0];
@@ -1032,12 +1250,17 @@ int bltc_counts(bltc_tree t, bltc_targets g, int32_t degree, double theta,
       d2h(di.data(), L.dids, nd, nullptr);
       sync(nullptr);
     }
-    const int64_t nk = (int64_t)(degree + 1) * (degree + 1) * (degree + 1);
     int64_t cp = 0, cd = 0;
     const bltc::HostTree& H = t->host;
     for (int64_t b = 0; b < g->nb; ++b) {
       const int64_t cnt = g->host.bptr[b + 1] - g->host.bptr[b];
-      cp += cnt * (pp[b + 1] - pp[b]) * nk;
+      int64_t prox = 0;
+      for (int32_t k = pp[b]; k < pp[b + 1]; ++k) {
+        const int dd = pi[k] >> bltc::kDegShift;
+        const int64_t n1 = (dd ? dd : degree) + 1;
+        prox += n1 * n1 * n1;
+      }
+      cp += cnt * prox;
       int64_t leaf = 0;
       for (int32_t k = dp[b]; k < dp[b + 1]; ++k) leaf += H.end[di[k]] - H.begin[di[k]];
       cd += cnt * leaf;
@@ -1163,7 +1386,7 @@ int bltc_batch_counts(bltc_tree t, bltc_targets g, double theta, int32_t* n_prox
 int bltc_evaluate_adaptive(bltc_tree t, bltc_targets g, int32_t kernel, double eps,
                            bltc_selector sel, double tol, int32_t fb_degree,
                            double fb_theta, const bltc_options* opt, double* out,
-                           int32_t* choice, int64_t* stats, void* stream) {
+                           int32_t* choice, int64_t* stats, double* judge, void* stream) {
   if (!t || !g || !sel) return fail(BLTC_EINVAL, "NULL tree, targets or selector");
   if (kernel != BLTC_STOKESLET && kernel != BLTC_ROTLET)
     return fail(BLTC_EINVAL, "the selector serves the Stokeslet and rotlet kernels");
@@ -1173,11 +1396,13 @@ int bltc_evaluate_adaptive(bltc_tree t, bltc_targets g, int32_t kernel, double e
   bltc_options_default(&o);
   if (opt) o = *opt;
   if (int rc = check_options(&o, kernel)) return rc;
+  if (o.deg_min != 0)
+    return fail(BLTC_EINVAL, "the learned evaluation uses fixed degrees (deg_min = 0)");
   if (g->m > 0 && !device_ptr(out)) return fail(BLTC_EINVAL, "out must be a device pointer");
   if (!t->has_w) return fail(BLTC_ESTATE, "no weights: call bltc_compute_modified_weights first");
   return guarded([&] {
     evaluate_adaptive(t, g, kernel, eps, sel, tol, fb_degree, fb_theta, o, out, choice,
-                      stats, (hipStream_t)stream);
+                      stats, judge, (hipStream_t)stream);
     return (int)BLTC_OK;
   });
 }

@@ -18,6 +18,11 @@ constexpr int kUpwardChunk = 2048;   // particles per upward-pass work group
 constexpr int kMlpIn = 12;           // selector network: features
 constexpr int kMlpHidden = 64;       // selector network: hidden width
 constexpr int kMlpMaxOut = 128;      // selector network: most candidates
+// A proxy-list entry holds the cluster id in its low kDegShift bits and,
+// under the separation rule, the cluster's degree above them (0: the
+// evaluation's degree).
+constexpr int kDegShift = 27;
+constexpr int32_t kIdMask = (1 << kDegShift) - 1;
 
 // ---- host tree (Section 6) ------------------------------------------------
 struct HostTree {
@@ -57,11 +62,20 @@ struct Nodes {                 // device node arrays
   int64_t nn;
 };
 
+// Separation rule for the degree of an accepted cluster: the smallest d in
+// [deg_min, degree) with (r_B + r_C)^2 / R^2 <= T[d], else degree; off when
+// deg_min = 0.
+struct Rule {
+  int32_t deg_min = 0, degree = 0;
+  double T[kMaxDegree + 1] = {};
+};
+
 struct ListArgs {
   const double4* bgeo;         // batch center, radius
   int64_t nb;
   Nodes nodes;
   double theta;
+  Rule rule;
   const double* theta_b = nullptr;  // [nb] per-batch theta, or NULL
   int32_t* pcnt;               // [nb] proxy count (count pass)
   int32_t* dcnt;               // [nb] direct count
@@ -90,6 +104,8 @@ struct P2PArgs {
   const int2* range;
   const double* grid;          // [nn][3][n1]
   const void* fhat;            // [nn][n1][n1][3][n1], FP64 or FP32
+  const double* grid_d[kMaxDegree + 1] = {};  // per degree (separation rule)
+  const void* fhat_d[kMaxDegree + 1] = {};
   const double* ys;            // tree-ordered sources [3][n]
   const double* w64;           // tree-ordered weights [3][n]
   const float* w32;
@@ -141,17 +157,34 @@ struct Candidates {
   int32_t t[kMlpMaxOut];       // index of the candidate's theta
 };
 
+// Modelled cost weights of one wave: per proxy evaluation, per grid row,
+// per accepted cluster and per near-field source.
+struct Costs {
+  float far, row, clu, nearf;
+};
+
 // ---- launchers (defined in the .hip files) --------------------------------
 hipError_t launch_guard(int kernel, int degree, const GuardArgs& a, hipStream_t s);
 hipError_t launch_features(const FeatArgs& a, hipStream_t s);
-hipError_t launch_select(const float* Y, int k, int64_t nb, const int32_t* bptr,
-                         const int32_t* pcnt, const int32_t* scnt,
-                         const Candidates& c, float logtol, float margin,
-                         float cfar, float cnear, int32_t* choice, hipStream_t s);
-hipError_t launch_guard_check(int ns, const int32_t* spos, const int32_t* sbatch,
-                              const int32_t* tperm, const double* out, int64_t m,
-                              int od, const double* ufb, double tol,
-                              int32_t* flag, hipStream_t s);
+int64_t alloc_blocks(int64_t nb);
+hipError_t launch_alloc(const float* Y, int k, int64_t nb, const int32_t* pcnt,
+                        const int32_t* scnt, const Candidates& c, const Costs& w,
+                        const double* wt, double inv_wsum, const double* lam, int G,
+                        double* partial, double* sums, hipStream_t s);
+hipError_t launch_choose(const float* Y, int k, int64_t nb, const int32_t* pcnt,
+                         const int32_t* scnt, const Candidates& c, const Costs& w,
+                         const double* wt, double inv_wsum, double lam, int32_t* choice,
+                         hipStream_t s);
+hipError_t launch_judge(int ns, const int32_t* bptr, const int32_t* spos,
+                        const int32_t* tperm, const double* out, int64_t m, int od,
+                        const double* ufb, double* wt, double* contrib, double* partial,
+                        double* sums, hipStream_t s);
+hipError_t launch_flag(int ns, const double* contrib, double thr, int32_t* flag,
+                       hipStream_t s);
+hipError_t launch_need(const int32_t* bsel, int64_t nsel, const int32_t* pptr,
+                       const int32_t* pids, uint8_t* need, int64_t nn, hipStream_t s);
+hipError_t launch_need_degree(int64_t nb, const int32_t* pptr, const int32_t* pids, int d,
+                              uint8_t* need, int64_t nn, hipStream_t s);
 hipError_t launch_gather_points(const double* x, const double* y,
                                 const double* z, const int32_t* perm,
                                 int64_t n, double* out3, hipStream_t s);
@@ -162,12 +195,12 @@ hipError_t launch_grids(const double* box, int64_t nn, int degree,
                         const double* unit_nodes, double* grid, hipStream_t s);
 hipError_t launch_upward(const double* ys, const double* w64, int64_t n,
                          const int4* chunks, int64_t nchunks,
-                         const double* grid, int degree, double* partial,
-                         hipStream_t s);
+                         const double* grid, int degree, const uint8_t* need,
+                         double* partial, hipStream_t s);
 hipError_t launch_upward_reduce(const int32_t* chunk_ptr, int64_t nn,
                                 const double* partial, int degree,
-                                double* fhat64, double* p2p64, float* p2p32,
-                                hipStream_t s);
+                                const uint8_t* need, double* fhat64, double* p2p64,
+                                float* p2p32, hipStream_t s);
 hipError_t launch_lists(const ListArgs& a, bool fill, hipStream_t s);
 hipError_t launch_exclusive_scan(const int32_t* in, int64_t n, int32_t* out,
                                  int32_t* overflow, hipStream_t s);
@@ -204,6 +237,7 @@ struct bltc_degree_data {
   double* fhat64 = nullptr;    // [nn][3][nk] (k3 fastest)
   double* p2p64 = nullptr;     // [nn][n1][n1][3][n1]
   float* p2p32 = nullptr;
+  bool partial = false;        // weights only for the clusters of a need mask
 };
 
 struct bltc_tree_s {
@@ -227,6 +261,7 @@ struct bltc_tree_s {
   int32_t* d_chunk_ptr = nullptr;  // [nn+1]
   double* d_partial = nullptr;
   size_t partial_cap = 0;      // doubles
+  uint8_t* d_need = nullptr;   // [nn] clusters a degree must provide
 };
 
 namespace bltc {
@@ -266,13 +301,19 @@ struct bltc_targets_s {
   int32_t* d_sbatch = nullptr;
   int32_t* d_gflag = nullptr;  // [nb]
   double* d_ufb = nullptr;     // [nb][6]
+  double* d_wt = nullptr;      // [nb] judge weights
+  double* d_contrib = nullptr; // [nb] judge error contributions
+  double* d_part = nullptr;    // [blocks][G][2] partial sums
+  double* d_sums = nullptr;    // [G][2]
+  double* d_lam = nullptr;     // [G]
 };
 
 struct bltc_selector_s {
   int32_t k = 0;
   std::vector<int32_t> cand_n;
   std::vector<double> cand_theta;
-  double theta_ref = 0.7, cost_far = 1.0, cost_near = 1.0, margin = 0.0;
+  double theta_ref = 0.7, margin = 0.0;
+  double cost_far = 1.0, cost_row = 0.0, cost_clu = 0.0, cost_near = 1.0;
   std::vector<float> mean, stdv, params;
   float* d_params = nullptr;
   float* d_mean = nullptr;

@@ -9,7 +9,10 @@
 // R2 = dx dx + dy dy + dz dz from the batch center to the cluster center,
 // in FP64 without fused multiply-adds (this file is built with
 // -ffp-contract=off), so the integer lists are reproducible bit for bit.
-// The count pass sizes the lists; the fill pass writes them.
+// The count pass sizes the lists; the fill pass writes them.  Under the
+// separation rule the fill pass also stores each accepted cluster's degree:
+// the smallest d in [deg_min, degree) with rr^2 / R2 <= T[d], else degree
+// (one division and comparisons, reproducible bit for bit).
 #include <hip/hip_runtime.h>
 
 #include "internal.h"
@@ -45,7 +48,16 @@ __global__ __launch_bounds__(128) void k_lists(ListArgs a) {
     const double R2 = dx * dx + dy * dy + dz * dz;
     const double rr = g.w + c.w;
     if (R2 > 0.0 && rr * rr <= th2 * R2) {
-      if (FILL) pout[np] = q;
+      if (FILL) {
+        int32_t e = q;
+        if (a.rule.deg_min > 0) {
+          const double qq = (rr * rr) / R2;
+          int d = a.rule.deg_min;
+          while (d < a.rule.degree && !(qq <= a.rule.T[d])) ++d;
+          e |= d << kDegShift;
+        }
+        pout[np] = e;
+      }
       ++np;
       continue;
     }

@@ -178,6 +178,36 @@ __device__ __forceinline__ void proxies_poly(double x, double y, double z,
     }
 }
 
+// The far field of a cluster whose degree (separation rule) is n1 - 1 for
+// some n1 in [2, M]: one unrolled instance per degree, chosen by the
+// wave-uniform n1.
+template <int KERN, int M, bool ZEPS, typename T, typename F>
+__device__ __forceinline__ void proxies_low(int n1, double x, double y, double z,
+                                            const double* __restrict__ g,
+                                            const F* __restrict__ fh, T e2, T* p) {
+  if constexpr (M >= 2) {
+    if (n1 == M) {
+      proxies<KERN, M, ZEPS, T, F>(x, y, z, g, fh, e2, p);
+      return;
+    }
+    proxies_low<KERN, M - 1, ZEPS, T, F>(n1, x, y, z, g, fh, e2, p);
+  }
+}
+
+template <int M>
+__device__ __forceinline__ void proxies_poly_low(int n1, double x, double y, double z,
+                                                 const double* __restrict__ g,
+                                                 const double* __restrict__ fh, int pp,
+                                                 double pc, double* p) {
+  if constexpr (M >= 2) {
+    if (n1 == M) {
+      proxies_poly<M>(x, y, z, g, fh, pp, pc, p);
+      return;
+    }
+    proxies_poly_low<M - 1>(n1, x, y, z, g, fh, pp, pc, p);
+  }
+}
+
 // ---- accumulators --------------------------------------------------------------
 template <int PREC, int OD>
 struct Acc {
@@ -251,7 +281,14 @@ constexpr int kWavesPerBlock = 1;
 
 // Wave gw serves targets
 // [bptr[b] + 64 wv, ...) of batch b = gw / wpb, wv = gw % wpb.
-template <int KERN, int PREC, int N1, bool ZEPS>
+// Per-degree grids and modified weights for entries that carry their own
+// degree (separation rule).
+struct DegTables {
+  const double* grid[kMaxDegree + 1];
+  const void* fh[kMaxDegree + 1];
+};
+
+template <int KERN, int PREC, int N1, bool ZEPS, bool RULE>
 __global__ __launch_bounds__(64 * kWavesPerBlock) void k_p2p(
     const double* __restrict__ tx, int64_t m, const int32_t* __restrict__ tperm,
     const int32_t* __restrict__ bptr, const double4* __restrict__ bgeo,
@@ -263,7 +300,7 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void k_p2p(
     const double* __restrict__ fh64, const double* __restrict__ ys,
     const float* __restrict__ w32, const double* __restrict__ w64, int64_t n,
     double eps, int poly_p, double poly_c, double su, double sw,
-    double* __restrict__ out) {
+    double* __restrict__ out, DegTables dt) {
   constexpr int OD = Dims<KERN>::OD;
   constexpr int NK = N1 * N1 * N1;
   constexpr bool F64 = PREC == BLTC_FP64;
@@ -295,17 +332,33 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void k_p2p(
 
   // far field
   for (int li = pptr[b]; li < pptr[b + 1]; ++li) {
-    const int q = pids[li];
-    const double* __restrict__ g = grid + (int64_t)q * 3 * N1;
+    const int e = pids[li];
+    const int q = e & kIdMask;
+    const int n1 = RULE ? (e >> kDegShift) + 1 : N1;
     T p[OD];
 #pragma unroll
     for (int c = 0; c < OD; ++c) p[c] = 0;
-    if constexpr (KERN == KPOLY)
-      proxies_poly<N1>(x, y, z, g, fh64 + (int64_t)q * 3 * NK, poly_p, poly_c, p);
-    else if constexpr (F64)
-      proxies<KERN, N1, ZEPS, T, double>(x, y, z, g, fh64 + (int64_t)q * 3 * NK, e2, p);
-    else
-      proxies<KERN, N1, ZEPS, T, float>(x, y, z, g, fh32 + (int64_t)q * 3 * NK, e2, p);
+    if (n1 == N1) {
+      const double* __restrict__ g = grid + (int64_t)q * 3 * N1;
+      if constexpr (KERN == KPOLY)
+        proxies_poly<N1>(x, y, z, g, fh64 + (int64_t)q * 3 * NK, poly_p, poly_c, p);
+      else if constexpr (F64)
+        proxies<KERN, N1, ZEPS, T, double>(x, y, z, g, fh64 + (int64_t)q * 3 * NK, e2, p);
+      else
+        proxies<KERN, N1, ZEPS, T, float>(x, y, z, g, fh32 + (int64_t)q * 3 * NK, e2, p);
+    } else if (RULE && n1 >= 2 && n1 < N1) {
+      const double* __restrict__ g = dt.grid[n1 - 1] + (int64_t)q * 3 * n1;
+      const int64_t o = (int64_t)q * 3 * n1 * n1 * n1;
+      if constexpr (KERN == KPOLY)
+        proxies_poly_low<N1 - 1>(n1, x, y, z, g, (const double*)dt.fh[n1 - 1] + o, poly_p,
+                                 poly_c, p);
+      else if constexpr (F64)
+        proxies_low<KERN, N1 - 1, ZEPS, T, double>(n1, x, y, z, g,
+                                                   (const double*)dt.fh[n1 - 1] + o, e2, p);
+      else
+        proxies_low<KERN, N1 - 1, ZEPS, T, float>(n1, x, y, z, g,
+                                                  (const float*)dt.fh[n1 - 1] + o, e2, p);
+    }
     acc.fold(p);
   }
 
@@ -410,17 +463,31 @@ hipError_t run_p2p(const P2PArgs& a, hipStream_t s) {
   const int nwaves = (int)nw64;
   const int nblk = (nwaves + kWavesPerBlock - 1) / kWavesPerBlock;
   const bool zeps = a.eps == 0.0;
+  DegTables dt;
+  bool rule = false;
+  for (int d = 0; d <= kMaxDegree; ++d) {
+    dt.grid[d] = a.grid_d[d];
+    dt.fh[d] = a.fhat_d[d];
+    if (d < N1 - 1 && a.grid_d[d]) rule = true;
+  }
   auto go = [&](auto kern) {
     hipLaunchKernelGGL(kern, dim3(nblk), dim3(64 * kWavesPerBlock), 0, s, a.tx, a.m,
                        a.tperm, a.bptr, a.bgeo, nblk, nwaves, a.wpb, a.bmap, a.pptr, a.pids,
                        a.dptr, a.dids, a.range, a.grid, (const float*)a.fhat,
                        (const double*)a.fhat, a.ys, a.w32, a.w64, a.n, a.eps,
-                       a.poly_p, a.poly_c, a.scale_u, a.scale_w, a.out);
+                       a.poly_p, a.poly_c, a.scale_u, a.scale_w, a.out, dt);
   };
-  if (zeps)
-    go(k_p2p<KERN, PREC, N1, true>);
-  else
-    go(k_p2p<KERN, PREC, N1, false>);
+  if (rule) {
+    if (zeps)
+      go(k_p2p<KERN, PREC, N1, true, true>);
+    else
+      go(k_p2p<KERN, PREC, N1, false, true>);
+  } else {
+    if (zeps)
+      go(k_p2p<KERN, PREC, N1, true, false>);
+    else
+      go(k_p2p<KERN, PREC, N1, false, false>);
+  }
   return hipGetLastError();
 }
 

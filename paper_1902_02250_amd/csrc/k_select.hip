@@ -1,6 +1,6 @@
 // Per-batch (n, theta) selection on the device: batch features, the
-// cheapest candidate whose predicted error meets the tolerance, and the
-// guard's comparison against the fallback.
+// allocation of an error budget over the batches, the judge's sums against
+// the fallback, and the clusters a degree needs.
 #include <hip/hip_runtime.h>
 
 #include "bltc.h"
@@ -79,54 +79,181 @@ __global__ __launch_bounds__(128) void k_features(FeatArgs a) {
   }
 }
 
-// choice[b] = the candidate of least modelled cost whose predicted log10
-// error plus margin is at most logtol, or -1 if none qualifies.  Modelled
-// cost = targets x (proxy clusters x (n+1)^3 x cfar + near sources x cnear).
-__global__ void k_select(const float* __restrict__ Y, int k, int64_t nb,
-                         const int32_t* __restrict__ bptr,
+// Modelled wave cost of candidate j for batch b: proxy clusters x
+// (cfar (n+1)^3 + crow (n+1)^2 + cclu) + near sources x cnear.
+__device__ __forceinline__ double cand_cost(const Candidates& c, const Costs& w, int j,
+                                           int64_t nb, int64_t b,
+                                           const int32_t* __restrict__ pcnt,
+                                           const int32_t* __restrict__ scnt) {
+  const int ti = c.t[j];
+  const double n1 = (double)(c.n[j] + 1);
+  const double P = (double)pcnt[(int64_t)ti * nb + b];
+  const double S = (double)scnt[(int64_t)ti * nb + b];
+  return P * (((double)w.far * n1 + (double)w.row) * n1 * n1 + (double)w.clu) +
+         S * (double)w.nearf;
+}
+
+// The candidate minimising cost + lam wn e^2 with e = 10^Y the predicted
+// relative error; ties go to the lower index.
+__device__ __forceinline__ int best_candidate(const float* __restrict__ Yb, int k,
+                                             const Candidates& c, const Costs& w,
+                                             int64_t nb, int64_t b,
+                                             const int32_t* __restrict__ pcnt,
+                                             const int32_t* __restrict__ scnt,
+                                             double lw, double* cost, double* err2) {
+  int best = 0;
+  double bv = 0.0, bc = 0.0, be = 0.0;
+  for (int j = 0; j < k; ++j) {
+    const double e2 = exp10(2.0 * (double)Yb[j]);
+    const double cj = cand_cost(c, w, j, nb, b, pcnt, scnt);
+    const double v = cj + lw * e2;
+    if (j == 0 || v < bv) {
+      best = j;
+      bv = v;
+      bc = cj;
+      be = e2;
+    }
+  }
+  *cost = bc;
+  *err2 = be;
+  return best;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Sums (a, b) over the work group's threads in a fixed order.
+template <int NT>
+__device__ __forceinline__ void block_sum2(double a, double b, double* out2) {
+  __shared__ double red[2][NT / 64];
+  a = wave_sum(a);
+  b = wave_sum(b);
+  const int wv = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    red[0][wv] = a;
+    red[1][wv] = b;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double sa = 0.0, sb = 0.0;
+    for (int i = 0; i < NT / 64; ++i) {
+      sa += red[0][i];
+      sb += red[1][i];
+    }
+    out2[0] = sa;
+    out2[1] = sb;
+  }
+  __syncthreads();
+}
+
+constexpr int kSelThreads = 256;
+
+// For every multiplier lam[g], g < G: each batch takes its best candidate
+// for lam[g] wn_b (wn_b = wt[b] / sum wt); partial[blk][g] = (sum of cost,
+// sum of wn e^2) over the work group's batches.
+__global__ __launch_bounds__(kSelThreads) void k_alloc(
+    const float* __restrict__ Y, int k, int64_t nb, const int32_t* __restrict__ pcnt,
+    const int32_t* __restrict__ scnt, Candidates c, Costs w,
+    const double* __restrict__ wt, double inv_wsum, const double* __restrict__ lam,
+    int G, double* __restrict__ partial) {
+  const int64_t b = (int64_t)blockIdx.x * kSelThreads + threadIdx.x;
+  const bool act = b < nb;
+  const double wn = act ? wt[b] * inv_wsum : 0.0;
+  for (int g = 0; g < G; ++g) {
+    double cost = 0.0, e2 = 0.0;
+    if (act) best_candidate(Y + b * k, k, c, w, nb, b, pcnt, scnt, lam[g] * wn, &cost, &e2);
+    block_sum2<kSelThreads>(cost, wn * e2, partial + ((int64_t)blockIdx.x * G + g) * 2);
+  }
+}
+
+__global__ void k_choose(const float* __restrict__ Y, int k, int64_t nb,
                          const int32_t* __restrict__ pcnt,
-                         const int32_t* __restrict__ scnt, Candidates c,
-                         float logtol, float margin, float cfar, float cnear,
+                         const int32_t* __restrict__ scnt, Candidates c, Costs w,
+                         const double* __restrict__ wt, double inv_wsum, double lam,
                          int32_t* __restrict__ choice) {
   const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= nb) return;
-  const double cnt = (double)(bptr[b + 1] - bptr[b]);
-  int best = -1;
-  double bestcost = 0.0;
-  for (int j = 0; j < k; ++j) {
-    if (!(Y[b * k + j] + margin <= logtol)) continue;
-    const int ti = c.t[j];
-    const double n1 = (double)(c.n[j] + 1);
-    const double cost = cnt * ((double)pcnt[(int64_t)ti * nb + b] * n1 * n1 * n1 * cfar +
-                               (double)scnt[(int64_t)ti * nb + b] * cnear);
-    if (best < 0 || cost < bestcost) {
-      best = j;
-      bestcost = cost;
-    }
-  }
-  choice[b] = best;
+  double cost, e2;
+  choice[b] = best_candidate(Y + b * k, k, c, w, nb, b, pcnt, scnt, lam * wt[b] * inv_wsum,
+                             &cost, &e2);
 }
 
-// flag[batch] = 1 when the learned result at a sampled target differs from
-// the fallback result by more than tol relative (in the L2 norm over the
-// components).
-__global__ void k_guard_check(int ns, const int32_t* __restrict__ spos,
-                              const int32_t* __restrict__ sbatch,
-                              const int32_t* __restrict__ tperm,
-                              const double* __restrict__ out, int64_t m, int od,
-                              const double* __restrict__ ufb, double tol,
-                              int32_t* __restrict__ flag) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= ns) return;
-  const int64_t o = tperm[spos[i]];
-  double num = 0.0, den = 0.0;
-  for (int c = 0; c < od; ++c) {
-    const double r = ufb[(int64_t)i * od + c];
-    const double d = out[c * m + o] - r;
-    num += d * d;
-    den += r * r;
+// Judge sums over the sampled targets (one per batch, sample i of batch i):
+//   wt[i]      = cnt_i |u_fb|^2
+//   contrib[i] = cnt_i |u - u_fb|^2   (when out is given, else 0)
+// with u_fb the fallback treecode at the sample; partial[blk] = the work
+// group's sums of (wt, contrib).
+__global__ __launch_bounds__(kSelThreads) void k_judge(
+    int ns, const int32_t* __restrict__ bptr, const int32_t* __restrict__ spos,
+    const int32_t* __restrict__ tperm, const double* __restrict__ out, int64_t m, int od,
+    const double* __restrict__ ufb, double* __restrict__ wt,
+    double* __restrict__ contrib, double* __restrict__ partial) {
+  const int i = blockIdx.x * kSelThreads + threadIdx.x;
+  double wv = 0.0, cv = 0.0;
+  if (i < ns) {
+    const double cnt = (double)(bptr[i + 1] - bptr[i]);
+    const int64_t o = out ? tperm[spos[i]] : 0;
+    double num = 0.0, den = 0.0;
+    for (int c = 0; c < od; ++c) {
+      const double r = ufb[(int64_t)i * od + c];
+      den += r * r;
+      if (out) {
+        const double d = out[c * m + o] - r;
+        num += d * d;
+      }
+    }
+    wv = cnt * den;
+    cv = cnt * num;
+    wt[i] = wv;
+    contrib[i] = cv;
   }
-  if (num > tol * tol * den) atomicOr(&flag[sbatch[i]], 1);
+  block_sum2<kSelThreads>(wv, cv, partial + (int64_t)blockIdx.x * 2);
+}
+
+// out[c] = sum over blk of partial[blk][c], in work-group order.
+__global__ void k_sum_columns(const double* __restrict__ partial, int nblk, int ncol,
+                              double* __restrict__ out) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncol) return;
+  double s = 0.0;
+  for (int b = 0; b < nblk; ++b) s += partial[(int64_t)b * ncol + c];
+  out[c] = s;
+}
+
+__global__ void k_flag(int ns, const double* __restrict__ contrib, double thr,
+                       int32_t* __restrict__ flag) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < ns) flag[i] = contrib[i] > thr ? 1 : 0;
+}
+
+// need[q] = 1 for every proxy cluster q on the lists of the batches bsel[0..nsel).
+__global__ void k_need(const int32_t* __restrict__ bsel, int64_t nsel,
+                       const int32_t* __restrict__ pptr, const int32_t* __restrict__ pids,
+                       uint8_t* __restrict__ need) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nsel) return;
+  const int b = bsel[i];
+  for (int l = pptr[b]; l < pptr[b + 1]; ++l) need[pids[l] & kIdMask] = 1;
+}
+
+// need[q] = 1 for every proxy entry of degree d (separation rule).
+__global__ void k_need_degree(int64_t nb, const int32_t* __restrict__ pptr,
+                              const int32_t* __restrict__ pids, int d,
+                              uint8_t* __restrict__ need) {
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nb) return;
+  for (int l = pptr[b]; l < pptr[b + 1]; ++l) {
+    const int e = pids[l];
+    if ((e >> kDegShift) == d) need[e & kIdMask] = 1;
+  }
+}
+
+__global__ void k_fill_u8(uint8_t* __restrict__ p, int64_t n, uint8_t v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
 }
 
 }  // namespace
@@ -137,23 +264,69 @@ hipError_t launch_features(const FeatArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_select(const float* Y, int k, int64_t nb, const int32_t* bptr,
-                         const int32_t* pcnt, const int32_t* scnt,
-                         const Candidates& c, float logtol, float margin,
-                         float cfar, float cnear, int32_t* choice, hipStream_t s) {
+int64_t alloc_blocks(int64_t nb) { return (nb + kSelThreads - 1) / kSelThreads; }
+
+hipError_t launch_alloc(const float* Y, int k, int64_t nb, const int32_t* pcnt,
+                        const int32_t* scnt, const Candidates& c, const Costs& w,
+                        const double* wt, double inv_wsum, const double* lam, int G,
+                        double* partial, double* sums, hipStream_t s) {
   if (nb == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_select, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, s, Y, k,
-                     nb, bptr, pcnt, scnt, c, logtol, margin, cfar, cnear, choice);
+  const int nblk = (int)alloc_blocks(nb);
+  hipLaunchKernelGGL(k_alloc, dim3(nblk), dim3(kSelThreads), 0, s, Y, k, nb, pcnt, scnt, c,
+                     w, wt, inv_wsum, lam, G, partial);
+  hipLaunchKernelGGL(k_sum_columns, dim3((2 * G + 63) / 64), dim3(64), 0, s, partial, nblk,
+                     2 * G, sums);
   return hipGetLastError();
 }
 
-hipError_t launch_guard_check(int ns, const int32_t* spos, const int32_t* sbatch,
-                              const int32_t* tperm, const double* out, int64_t m,
-                              int od, const double* ufb, double tol,
-                              int32_t* flag, hipStream_t s) {
+hipError_t launch_choose(const float* Y, int k, int64_t nb, const int32_t* pcnt,
+                         const int32_t* scnt, const Candidates& c, const Costs& w,
+                         const double* wt, double inv_wsum, double lam, int32_t* choice,
+                         hipStream_t s) {
+  if (nb == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_choose, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, s, Y, k, nb,
+                     pcnt, scnt, c, w, wt, inv_wsum, lam, choice);
+  return hipGetLastError();
+}
+
+hipError_t launch_judge(int ns, const int32_t* bptr, const int32_t* spos,
+                        const int32_t* tperm, const double* out, int64_t m, int od,
+                        const double* ufb, double* wt, double* contrib, double* partial,
+                        double* sums, hipStream_t s) {
   if (ns == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_guard_check, dim3((ns + 255) / 256), dim3(256), 0, s, ns, spos,
-                     sbatch, tperm, out, m, od, ufb, tol, flag);
+  const int nblk = (int)alloc_blocks(ns);
+  hipLaunchKernelGGL(k_judge, dim3(nblk), dim3(kSelThreads), 0, s, ns, bptr, spos, tperm, out,
+                     m, od, ufb, wt, contrib, partial);
+  hipLaunchKernelGGL(k_sum_columns, dim3(1), dim3(64), 0, s, partial, nblk, 2, sums);
+  return hipGetLastError();
+}
+
+hipError_t launch_flag(int ns, const double* contrib, double thr, int32_t* flag,
+                       hipStream_t s) {
+  if (ns == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_flag, dim3((ns + 255) / 256), dim3(256), 0, s, ns, contrib, thr, flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_need(const int32_t* bsel, int64_t nsel, const int32_t* pptr,
+                       const int32_t* pids, uint8_t* need, int64_t nn, hipStream_t s) {
+  if (nn > 0)
+    hipLaunchKernelGGL(k_fill_u8, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, s, need,
+                       nn, (uint8_t)0);
+  if (nsel > 0)
+    hipLaunchKernelGGL(k_need, dim3((unsigned)((nsel + 127) / 128)), dim3(128), 0, s, bsel,
+                       nsel, pptr, pids, need);
+  return hipGetLastError();
+}
+
+hipError_t launch_need_degree(int64_t nb, const int32_t* pptr, const int32_t* pids, int d,
+                              uint8_t* need, int64_t nn, hipStream_t s) {
+  if (nn > 0)
+    hipLaunchKernelGGL(k_fill_u8, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, s, need,
+                       nn, (uint8_t)0);
+  if (nb > 0)
+    hipLaunchKernelGGL(k_need_degree, dim3((unsigned)((nb + 127) / 128)), dim3(128), 0, s, nb,
+                       pptr, pids, d, need);
   return hipGetLastError();
 }
 

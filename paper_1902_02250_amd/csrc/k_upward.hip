@@ -13,7 +13,8 @@
 // values k3 of its (k1, k2, c) items, a tensor-product contraction of
 // (n1^2 x 3) by n1 over the chunk's particles.  Chunk partial sums land in
 // a scratch array and a second kernel adds them per cluster in chunk order,
-// so the result is deterministic.  FP64 throughout.
+// so the result is deterministic.  FP64 throughout.  An optional need mask
+// (one byte per cluster) restricts both kernels to the flagged clusters.
 #include <float.h>
 #include <hip/hip_runtime.h>
 
@@ -30,7 +31,7 @@ template <int N1>
 __global__ __launch_bounds__(kThreads) void k_upward(
     const double* __restrict__ ys, const double* __restrict__ w64, int64_t n,
     const int4* __restrict__ chunks, const double* __restrict__ grid,
-    double* __restrict__ partial) {
+    const uint8_t* __restrict__ need, double* __restrict__ partial) {
   constexpr int NK = N1 * N1 * N1;
   constexpr int NITEM = N1 * N1 * 3;                       // (k1, k2, c)
   constexpr int IPT = (NITEM + kThreads - 1) / kThreads;   // items per thread
@@ -40,6 +41,7 @@ __global__ __launch_bounds__(kThreads) void k_upward(
 
   const int4 ch = chunks[blockIdx.x];
   const int q = ch.x, b = ch.y, e = ch.z;
+  if (need && !need[q]) return;   // uniform over the work group
   const int t = threadIdx.x;
   if (t < 3 * N1) sS[t / N1][t % N1] = grid[(int64_t)q * 3 * N1 + t];
 
@@ -127,13 +129,15 @@ __global__ __launch_bounds__(kThreads) void k_upward(
 // evaluation layout p2p[q][k1][k2][c][k3] in FP64 and FP32.
 __global__ void k_upward_reduce(const int32_t* __restrict__ chunk_ptr,
                                 int64_t nn, const double* __restrict__ partial,
-                                int n1, double* __restrict__ fhat64,
+                                int n1, const uint8_t* __restrict__ need,
+                                double* __restrict__ fhat64,
                                 double* __restrict__ p2p64,
                                 float* __restrict__ p2p32) {
   const int nk = n1 * n1 * n1;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nn * 3 * nk) return;
   const int64_t q = i / (3 * nk);
+  if (need && !need[q]) return;
   const int r = (int)(i % (3 * nk));
   double s = 0.0;
   for (int32_t c = chunk_ptr[q]; c < chunk_ptr[q + 1]; ++c)
@@ -149,9 +153,9 @@ __global__ void k_upward_reduce(const int32_t* __restrict__ chunk_ptr,
 template <int N1>
 hipError_t run_upward(const double* ys, const double* w64, int64_t n,
                       const int4* chunks, int64_t nchunks, const double* grid,
-                      double* partial, hipStream_t s) {
+                      const uint8_t* need, double* partial, hipStream_t s) {
   hipLaunchKernelGGL(k_upward<N1>, dim3((unsigned)nchunks), dim3(kThreads), 0,
-                     s, ys, w64, n, chunks, grid, partial);
+                     s, ys, w64, n, chunks, grid, need, partial);
   return hipGetLastError();
 }
 
@@ -159,13 +163,13 @@ hipError_t run_upward(const double* ys, const double* w64, int64_t n,
 
 hipError_t launch_upward(const double* ys, const double* w64, int64_t n,
                          const int4* chunks, int64_t nchunks,
-                         const double* grid, int degree, double* partial,
-                         hipStream_t s) {
+                         const double* grid, int degree, const uint8_t* need,
+                         double* partial, hipStream_t s) {
   if (nchunks == 0) return hipSuccess;
   switch (degree + 1) {
 #define BLTC_UP(N) \
   case N:          \
-    return run_upward<N>(ys, w64, n, chunks, nchunks, grid, partial, s);
+    return run_upward<N>(ys, w64, n, chunks, nchunks, grid, need, partial, s);
     BLTC_UP(2) BLTC_UP(3) BLTC_UP(4) BLTC_UP(5) BLTC_UP(6) BLTC_UP(7)
     BLTC_UP(8) BLTC_UP(9) BLTC_UP(10) BLTC_UP(11) BLTC_UP(12) BLTC_UP(13)
 #undef BLTC_UP
@@ -176,13 +180,13 @@ hipError_t launch_upward(const double* ys, const double* w64, int64_t n,
 
 hipError_t launch_upward_reduce(const int32_t* chunk_ptr, int64_t nn,
                                 const double* partial, int degree,
-                                double* fhat64, double* p2p64, float* p2p32,
-                                hipStream_t s) {
+                                const uint8_t* need, double* fhat64, double* p2p64,
+                                float* p2p32, hipStream_t s) {
   if (nn == 0) return hipSuccess;
   const int n1 = degree + 1;
   const int64_t tot = nn * 3 * n1 * n1 * n1;
   hipLaunchKernelGGL(k_upward_reduce, dim3((unsigned)((tot + 255) / 256)),
-                     dim3(256), 0, s, chunk_ptr, nn, partial, n1, fhat64,
+                     dim3(256), 0, s, chunk_ptr, nn, partial, n1, need, fhat64,
                      p2p64, p2p32);
   return hipGetLastError();
 }

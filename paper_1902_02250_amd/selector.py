@@ -5,8 +5,10 @@ Not part of the paper, which fixes (theta, n, N0) by hand (Section 6) and
 reads the most efficient settings off the lower envelope of cost against
 error (Section 8.1).  Here a small network predicts, for every target batch,
 the log10 relative error of each candidate (n, theta); the evaluation then
-gives each batch the cheapest candidate predicted to meet the tolerance, with
-the fixed-(n, theta) treecode as fallback and judge (bltc_evaluate_adaptive).
+shares the error budget of the requested global relative error between the
+batches at least modelled cost, with the fixed-(n, theta) treecode as the
+judge of the result and the fallback of the batches it rejects
+(bltc_evaluate_adaptive).
 
 Every step runs in libbltc's kernels: the training data come from
 bltc_evaluate_tree (FP32 evaluation, FP64 accumulation) and bltc_direct (FP64
@@ -32,11 +34,14 @@ CAND_THETA = (0.4, 0.5, 0.6, 0.7, 0.8, 0.9)
 CANDIDATES = [(n, t) for n in CAND_N for t in CAND_THETA]
 K = len(CANDIDATES)
 THETA_REF = 0.7
-# Relative cost of one far-field and one near-field kernel evaluation,
-# measured with the evaluation kernel on MI355X (3.3e12 and 2.0e12 per s).
-COST_FAR, COST_NEAR = 0.6, 1.0
+# Modelled wave cost, in units of one near-field kernel evaluation, of one
+# proxy evaluation, one grid row and one accepted cluster, from the VALU
+# instruction counts of the evaluation kernel (Stokeslet: 13.9 per proxy,
+# about 8 per row and 50 per cluster, 20.3 per near-field pair).
+COST_FAR, COST_ROW, COST_CLU, COST_NEAR = 0.69, 0.5, 2.5, 1.0
+LAM_GRID, LAM_LO, LAM_HI = 64, 0.0, 24.0   # multiplier search, log10 range
 LOG_FLOOR = -12.0          # labels are log10(max(error, 1e-12))
-SAMPLES_PER_BATCH = 4
+SAMPLES_PER_BATCH = 8
 TRAIN_SEEDS = range(0, 200)
 
 
@@ -49,14 +54,14 @@ def _fnv1a(data):
 
 
 def write_model(path, params, mean, std, margin, cand=CANDIDATES, theta_ref=THETA_REF,
-                cost_far=COST_FAR, cost_near=COST_NEAR):
+                costs=(COST_FAR, COST_ROW, COST_CLU, COST_NEAR)):
     k = len(cand)
     params = np.ascontiguousarray(params, dtype=np.float32)
     assert params.size == bltc_param_count(k)
-    body = b"BLTCSEL1" + struct.pack("<4i", 1, 12, 64, k)
+    body = b"BLTCSEL1" + struct.pack("<4i", 2, 12, 64, k)
     body += np.array([c[0] for c in cand], dtype="<i4").tobytes()
     body += np.array([c[1] for c in cand], dtype="<f8").tobytes()
-    body += struct.pack("<4d", theta_ref, cost_far, cost_near, margin)
+    body += struct.pack("<6d", theta_ref, *costs, margin)
     body += np.asarray(mean, dtype="<f4").tobytes() + np.asarray(std, dtype="<f4").tobytes()
     body += params.astype("<f4").tobytes()
     body += struct.pack("<Q", _fnv1a(body))
@@ -126,13 +131,20 @@ def label_run(cfg, log=print):
             err = np.sqrt(num / np.maximum(den, 1e-300))
             T[:, CANDIDATES.index((n, th))] = np.log10(np.maximum(err, 10.0 ** LOG_FLOOR))
     cnt = np.diff(ex["bptr"])
-    return dict(X=X, T=T, pc=pc, sc=sc, cnt=cnt, cfg=cfg)
+    ns = np.bincount(bat, minlength=tg.nb)
+    wt = den * cnt / np.maximum(ns, 1)      # batch share of the reference norm
+    return dict(X=X, T=T, pc=pc, sc=sc, cnt=cnt, wt=wt, cfg=cfg)
 
 
-def generate(seeds, path, log=print):
+def generate(seeds, path, log=print, budget_s=None):
+    """Labels the runs of `seeds` in order; stops early once budget_s seconds
+    have passed."""
     runs = []
     t0 = time.time()
     for i, seed in enumerate(seeds):
+        if budget_s is not None and time.time() - t0 > budget_s:
+            log(f"[selector] time budget reached after {i} runs")
+            break
         cfg = run_config(seed)
         runs.append(label_run(cfg, log))
         log(f"[selector] run {i + 1}/{len(seeds)} seed {seed}: {cfg['dist']} n={cfg['n']} "
@@ -153,6 +165,7 @@ def save_runs(runs, path, per_run=300):
         out[f"pc_{i}"] = r["pc"][:, keep].astype(np.int32)
         out[f"sc_{i}"] = r["sc"][:, keep].astype(np.int32)
         out[f"cnt_{i}"] = r["cnt"][keep].astype(np.int32)
+        out[f"wt_{i}"] = r["wt"][keep]
     np.savez_compressed(path, cfgs=np.array([json.dumps(r["cfg"]) for r in runs]), **out)
 
 
@@ -160,7 +173,8 @@ def load_runs(path):
     z = np.load(path, allow_pickle=False)
     cfgs = [json.loads(str(c)) for c in z["cfgs"]]
     return [dict(X=z[f"X_{i}"], T=z[f"T_{i}"].astype(np.float32), pc=z[f"pc_{i}"],
-                 sc=z[f"sc_{i}"], cnt=z[f"cnt_{i}"], cfg=c) for i, c in enumerate(cfgs)]
+                 sc=z[f"sc_{i}"], cnt=z[f"cnt_{i}"], wt=z[f"wt_{i}"], cfg=c)
+            for i, c in enumerate(cfgs)]
 
 
 # ---- training on the device ------------------------------------------------------------
@@ -223,43 +237,82 @@ def predict(params, mean, std, X):
 
 
 # ---- offline check of a policy ---------------------------------------------------------------
-def batch_costs(run):
-    """Modelled cost of every (batch, candidate), [nb][K]."""
+def batch_costs(run, costs=(COST_FAR, COST_ROW, COST_CLU, COST_NEAR)):
+    """Modelled wave cost of every (batch, candidate), [nb][K]."""
+    cf, cr, cc, cn = costs
     cost = np.zeros((run["cnt"].size, K))
     for j, (n, th) in enumerate(CANDIDATES):
         ti = CAND_THETA.index(th)
-        cost[:, j] = run["cnt"] * (run["pc"][ti] * (n + 1) ** 3 * COST_FAR + run["sc"][ti] * COST_NEAR)
+        n1 = n + 1.0
+        cost[:, j] = run["pc"][ti] * ((cf * n1 + cr) * n1 * n1 + cc) + run["sc"][ti] * cn
     return cost
 
 
+def allocate(Y, cost, wt, tau):
+    """The budget allocation of bltc_evaluate_adaptive: per batch the
+    candidate minimising cost + lam wn e^2, wn = wt / (sum wt tau^2), with lam
+    the smallest point of a log grid (refined once) meeting sum wn e^2 <= 1."""
+    e2 = 10.0 ** (2.0 * Y.astype(np.float64))
+    wn = wt / (wt.sum() * tau * tau)
+    rows = np.arange(Y.shape[0])
+
+    def pick(lam):
+        return (cost + lam * wn[:, None] * e2).argmin(1)
+
+    lo, hi = LAM_LO, LAM_HI
+    lam_star = 10.0 ** hi
+    for _ in range(2):
+        grid = 10.0 ** (lo + (hi - lo) * np.arange(LAM_GRID) / (LAM_GRID - 1))
+        ok = [(wn * e2[rows, pick(l)]).sum() <= 1.0 for l in grid]
+        if not any(ok):
+            lam_star = grid[-1]
+            break
+        first = ok.index(True)
+        lam_star = grid[first]
+        if first == 0:
+            break
+        step = (hi - lo) / (LAM_GRID - 1)
+        hi = lo + step * first
+        lo = hi - step
+    return pick(lam_star)
+
+
 def policy_summary(run, Y, tol, margin):
-    """Realised global relative error and modelled cost of the learned choice
-    versus the best fixed candidate meeting tol (both from the labels)."""
-    T, cost = run["T"], batch_costs(run)
+    """Realised global relative error and modelled cost of the allocation
+    versus the cheapest fixed candidate meeting tol (both from the labels)."""
+    T, cost, wt = run["T"], batch_costs(run), run["wt"]
     nb = T.shape[0]
-    ok = Y + margin <= np.log10(tol)
-    choice = np.where(ok.any(1), np.where(ok, cost, np.inf).argmin(1), -1)
-    err2 = 10.0 ** (2 * T)             # per-batch relative error squared
-    fb = CANDIDATES.index((10, 0.6))
-    ch = np.where(choice >= 0, choice, fb)
-    learned_e = np.sqrt(err2[np.arange(nb), ch].mean())
+    ch = allocate(Y, cost, wt, tol * 10.0 ** (-margin))
+    err2 = 10.0 ** (2 * T.astype(np.float64))           # per-batch relative error squared
+    W = wt.sum()
+    learned_e = np.sqrt((wt * err2[np.arange(nb), ch]).sum() / W)
     learned_c = cost[np.arange(nb), ch].sum()
-    fixed_e = np.sqrt(err2.mean(0))
+    fixed_e = np.sqrt((wt[:, None] * err2).sum(0) / W)
     fixed_c = cost.sum(0)
     good = np.where(fixed_e <= tol)[0]
-    best = good[fixed_c[good].argmin()] if good.size else fb
+    best = good[fixed_c[good].argmin()] if good.size else CANDIDATES.index((10, 0.6))
     return dict(learned_err=float(learned_e), learned_cost=float(learned_c),
                 best_fixed=CANDIDATES[best], fixed_err=float(fixed_e[best]),
-                fixed_cost=float(fixed_c[best]), fallbacks=int((choice < 0).sum()))
+                fixed_cost=float(fixed_c[best]), attainable=bool(good.size),
+                degrees=int(np.unique(np.array([CANDIDATES[j][0] for j in ch])).size))
 
 
-def calibrate_margin(val_runs, Ys, tols=(1e-4, 1e-5, 1e-6, 1e-7), grid=None):
+def calibrate_margin(val_runs, Ys, tols=(1e-4, 1e-5, 1e-6), grid=None):
     """Smallest margin (most aggressive) for which the realised global error of
-    the learned choice stays within tol on every held-out run and tolerance."""
-    grid = np.arange(-1.0, 3.01, 0.05) if grid is None else grid
+    the allocation stays within tol on every held-out run and tolerance that
+    some fixed candidate attains."""
+    grid = np.arange(-0.5, 2.01, 0.05) if grid is None else grid
     for m in grid:
-        if all(policy_summary(r, Y, tol, m)["learned_err"] <= tol
-               for r, Y in zip(val_runs, Ys) for tol in tols):
+        ok = True
+        for r, Y in zip(val_runs, Ys):
+            for tol in tols:
+                s = policy_summary(r, Y, tol, m)
+                if s["attainable"] and s["learned_err"] > tol:
+                    ok = False
+                    break
+            if not ok:
+                break
+        if ok:
             return float(m)
     return float(grid[-1])
 
@@ -304,51 +357,72 @@ def compare(workload, model=MODEL_PATH, tol=None, fb=(10, 0.6), reps=2, n=None, 
             bltc.evaluate_tree(tree, tg, kernel, eps, nn, th, precision="fp32_fp64acc", out=out)
         ms, err, _ = timed(step)
         fixed[(nn, th)] = (ms, err)
+        if th == CAND_THETA[-1]:
+            log(f"[selector] {workload} fixed n={nn}: " + ", ".join(
+                f"theta {t}: {fixed[(nn, t)][0]:.1f} ms E={fixed[(nn, t)][1]:.2e}"
+                for t in CAND_THETA))
     if tol is None:
-        tol = fixed[(cfg["degree"], cfg["theta"])][1]
+        tol = cfg.get("tol") or fixed[(cfg["degree"], cfg["theta"])][1]
     ok = [c for c in CANDIDATES if fixed[c][1] <= tol]
     best = min(ok, key=lambda c: fixed[c][0]) if ok else None
-    sel = bltc.Selector(model)
-
-    def lstep():
-        tree.compute_weights(d_w, fb[0])
-        return bltc.evaluate_adaptive(tree, tg, kernel, eps, sel, tol, fb[0], fb[1],
-                                      precision="fp32_fp64acc", out=out)
-    ms_l, err_l, (_, choice, stats) = timed(lstep)
-    used = np.bincount(choice[choice >= 0], minlength=K)
+    models = [model] if isinstance(model, str) else list(model)
     res = dict(workload=workload, n=cfg["n"], kernel=kernel, tol=tol,
-               learned=dict(ms=ms_l, err=err_l, batches=int(stats[0]),
-                            model_fallbacks=int(stats[1]), guard_fallbacks=int(stats[2]),
-                            degrees=int(stats[3]),
-                            top_choices=[(CANDIDATES[j], int(used[j]))
-                                         for j in np.argsort(-used)[:5] if used[j]]),
                best_fixed=None if best is None else dict(n=best[0], theta=best[1],
                                                          ms=fixed[best][0], err=fixed[best][1]),
                fallback_fixed=dict(n=fb[0], theta=fb[1], ms=fixed[fb][0], err=fixed[fb][1]),
                fixed_sweep={f"{c[0]},{c[1]}": [round(fixed[c][0], 3), fixed[c][1]]
-                            for c in CANDIDATES})
-    if best is not None:
-        res["speedup_vs_best_fixed"] = fixed[best][0] / ms_l
-    log(f"[selector] {workload}: learned {ms_l:.2f} ms E={err_l:.3e}; best fixed "
-        f"{best} {fixed[best][0] if best else float('nan'):.2f} ms; tol {tol:.3e}")
+                            for c in CANDIDATES},
+               learned=[])
+    for mpath in models:
+        sel = bltc.Selector(mpath)
+
+        def lstep():
+            tree.compute_weights(d_w, fb[0])
+            return bltc.evaluate_adaptive(tree, tg, kernel, eps, sel, tol, fb[0], fb[1],
+                                          precision="fp32_fp64acc", out=out)
+        ms_l, err_l, (_, choice, stats, judge) = timed(lstep)
+        used = np.bincount(choice[choice >= 0], minlength=K)
+        r = dict(model=os.path.basename(mpath), ms=ms_l, err=err_l, batches=int(stats[0]),
+                 degrees=int(stats[1]), judge_redo=int(stats[2]),
+                 judge_estimate=[float(judge[0]), float(judge[1])],
+                 top_choices=[(CANDIDATES[j], int(used[j]))
+                              for j in np.argsort(-used)[:6] if used[j]])
+        if best is not None:
+            r["speedup_vs_best_fixed"] = fixed[best][0] / ms_l
+        res["learned"].append(r)
+        log(f"[selector] {workload} {r['model']}: learned {ms_l:.2f} ms E={err_l:.3e} "
+            f"(judge {judge[0]:.2e} -> {judge[1]:.2e}, {int(stats[2])} redone, "
+            f"{int(stats[1])} degrees); best fixed {best} "
+            f"{fixed[best][0] if best else float('nan'):.2f} ms; tol {tol:.3e}")
     return res
 
 
 def main(argv=None):
     import argparse
-    ap = argparse.ArgumentParser(description="generate training runs and train the selector")
+    ap = argparse.ArgumentParser(description="train the selector, or compare it with fixed "
+                                             "(n, theta) on a workload")
     ap.add_argument("--data", default="gpurun_out/selector_runs.npz")
     ap.add_argument("--model", default="gpurun_out/selector_v1.bin")
     ap.add_argument("--runs", type=int, default=200)
     ap.add_argument("--epochs", type=int, default=60)
     ap.add_argument("--skip-generate", action="store_true")
+    ap.add_argument("--budget", type=float, default=None, help="seconds for labelling")
+    ap.add_argument("--compare", default=None, help="workload name: time learned vs fixed")
+    ap.add_argument("--tol", type=float, default=None)
+    ap.add_argument("--out", default=None, help="JSON file for the comparison")
     args = ap.parse_args(argv)
     log = lambda *a: print(*a, flush=True)
     bltc.load()
+    if args.compare:
+        res = compare(args.compare, model=args.model.split(","), tol=args.tol, log=log)
+        if args.out:
+            with open(args.out, "w") as fh:
+                json.dump(res, fh, indent=1)
+        return 0
     if args.skip_generate:
         runs = load_runs(args.data)
     else:
-        runs = generate(list(TRAIN_SEEDS)[:args.runs], args.data, log)
+        runs = generate(list(TRAIN_SEEDS)[:args.runs], args.data, log, args.budget)
     nval = max(1, len(runs) // 10)
     train_runs, val_runs = runs[:-nval], runs[-nval:]
     X = np.concatenate([r["X"] for r in train_runs])
@@ -360,11 +434,18 @@ def main(argv=None):
     log(f"[selector] validation: rms residual {np.sqrt((resid ** 2).mean()):.3f} dex; "
         f"calibrated margin {margin:.2f} dex")
     write_model(args.model, params, mean, std, margin)
-    for r, Y in zip(val_runs, Ys):
-        s = policy_summary(r, Y, 1e-6, margin)
-        log(f"[selector] held-out {r['cfg']['dist']} n={r['cfg']['n']} {r['cfg']['kernel']}: "
-            f"learned E={s['learned_err']:.2e} cost={s['learned_cost']:.3e}; best fixed "
-            f"{s['best_fixed']} E={s['fixed_err']:.2e} cost={s['fixed_cost']:.3e}")
+    for tol in (1e-4, 1e-6):
+        gains = []
+        for r, Y in zip(val_runs, Ys):
+            s = policy_summary(r, Y, tol, margin)
+            if s["attainable"]:
+                gains.append(s["fixed_cost"] / s["learned_cost"])
+            log(f"[selector] held-out tol {tol:.0e} {r['cfg']['dist']} n={r['cfg']['n']} "
+                f"{r['cfg']['kernel']}: learned E={s['learned_err']:.2e} "
+                f"cost={s['learned_cost']:.3e} ({s['degrees']} degrees); best fixed "
+                f"{s['best_fixed']} E={s['fixed_err']:.2e} cost={s['fixed_cost']:.3e}")
+        log(f"[selector] tol {tol:.0e}: modelled cost gain over the best fixed candidate, "
+            f"median {np.median(gains):.2f}, min {np.min(gains):.2f}, max {np.max(gains):.2f}")
     return 0
 
 

@@ -110,6 +110,23 @@ def test_lists_bit_exact(torch, orc, theta, bs):
         assert np.array_equal(L[k], R[k]), k
 
 
+@pytest.mark.parametrize("theta,degree,deg_min", [(0.7, 8, 1), (0.5, 6, 3), (0.9, 12, 2),
+                                                  (0.7, 5, 5)])
+def test_lists_rule_bit_exact(torch, orc, theta, degree, deg_min):
+    """Separation-rule degrees of every accepted cluster, bit for bit."""
+    src = inputs.points("mixture", 12000, 43)
+    tgt = inputs.points("uniform", 3001, 44) * 1.2
+    w = inputs.weights(12000, 43)
+    T = _gpu_tree(torch, src, w, 120, 3)
+    G = bltc.Targets(_d(torch, tgt), 64, 32)
+    L = bltc.lists(T, G, theta, degree, deg_min)
+    R = orc.lists(src, 120, tgt, theta, 64, 32, degree=degree, deg_min=deg_min)
+    for k in ["prox_ptr", "prox_ids", "prox_deg", "dir_ptr", "dir_ids"]:
+        assert np.array_equal(L[k], R[k]), k
+    if deg_min < degree:
+        assert np.any(L["prox_deg"] < degree)
+
+
 @pytest.mark.parametrize("kernel", ["stokeslet", "rotlet"])
 def test_direct_fp64(torch, orc, kernel):
     src = inputs.points("uniform", 5003, 3)
@@ -145,7 +162,7 @@ def _tree_case(torch, orc, kernel, src, tgt, w, eps, degree, theta, leaf, bs, ol
                              **kw).cpu().numpy()
     ref, npx, ndr = orc.treecode(kernel, tgt, src, w, eps, degree, theta, leaf, mac_mode=1,
                                  batch_size=bs, order_leaf=ol, **kw)
-    cp, cd = bltc.counts(T, G, degree, theta)
+    cp, cd = bltc.counts(T, G, degree, theta, kw.get("deg_min", 0))
     assert (cp, cd) == (npx, ndr)
     return got, ref
 
@@ -248,3 +265,46 @@ def test_errors_on_device(torch):
     assert e.value.status == 4   # degree 5 not computed
     with pytest.raises(TypeError):
         bltc.Tree(torch.zeros((3, 10), dtype=torch.float32, device="cuda"), 5)
+
+
+@pytest.mark.parametrize("kernel", ["stokeslet", "rotlet"])
+@pytest.mark.parametrize("theta,degree,deg_min", [(0.7, 8, 1), (0.6, 6, 2)])
+def test_treecode_rule_fp64(torch, orc, kernel, theta, degree, deg_min):
+    """Separation rule: every accepted cluster at its own degree, FP64."""
+    src = inputs.points("mixture", 9000, 51)
+    w = inputs.weights(9000, 51)
+    got, ref = _tree_case(torch, orc, kernel, src, src, w, 0.01, degree, theta, 300, 64, 32,
+                          deg_min=deg_min)
+    assert orc.rel_l2(ref, got) <= FP64_TOL
+
+
+@pytest.mark.parametrize("precision", ["fp32_fp64acc", "fp32_kahan"])
+@pytest.mark.parametrize("kernel", ["stokeslet", "rotlet"])
+def test_treecode_rule_mixed(torch, orc, kernel, precision):
+    src = inputs.points("uniform", 9000, 52)
+    w = inputs.weights(9000, 52)
+    got, ref = _tree_case(torch, orc, kernel, src, src, w, 0.005, 9, 0.7, 300, 64, 32,
+                          precision=precision, deg_min=1)
+    assert orc.rel_l2(ref, got) <= MIXED_TOL
+
+
+def test_treecode_rule_poly_exact(torch, orc):
+    """(c + x.y)^3 with deg_min = 3: every cluster's own degree reproduces it."""
+    pts = inputs.points("uniform", 4000, 53)
+    w = inputs.weights(4000, 53)
+    got, ref = _tree_case(torch, orc, "poly", pts, pts, w, 0.0, 9, 0.8, 100, 64, 32,
+                          poly_p=3, poly_c=1.5, deg_min=3)
+    d = orc.direct("poly", pts, pts, w, poly_p=3, poly_c=1.5)
+    assert orc.rel_l2(ref, got) <= FP64_TOL
+    assert orc.rel_l2(d, got) <= FP64_TOL
+
+
+def test_rule_off_when_deg_min_reaches_degree(torch, orc):
+    src = inputs.points("uniform", 6000, 54)
+    w = inputs.weights(6000, 54)
+    T = _gpu_tree(torch, src, w, 200, 6)
+    G = bltc.Targets(_d(torch, src), 64, 32)
+    a = bltc.evaluate_tree(T, G, "stokeslet", 0.01, 6, 0.7, precision="fp32_fp64acc")
+    b = bltc.evaluate_tree(T, G, "stokeslet", 0.01, 6, 0.7, precision="fp32_fp64acc",
+                           deg_min=6)
+    assert torch.equal(a, b)

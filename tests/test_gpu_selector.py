@@ -1,7 +1,7 @@
 """GPU checks of the learned (n, theta) path through the C ABI: batch
 features and counts against the oracle's tree and lists, and the adaptive
 evaluation composed exactly of per-candidate fixed evaluations (including
-the guard's fallback)."""
+the batches the judge sends to the fallback)."""
 import numpy as np
 import pytest
 
@@ -97,26 +97,29 @@ def _fixed(torch, case, n, th, kernel="stokeslet", eps=0.01):
 def test_adaptive_constant_choice(torch, tmp_path, case):
     j = selector.CANDIDATES.index((6, 0.7))
     sel = bltc.Selector(_const_model(tmp_path, j, -5.0))
-    out, choice, stats = bltc.evaluate_adaptive(case["T"], case["G"], "stokeslet", 0.01, sel,
-                                                1e-3, 10, 0.6)
-    assert np.all(choice == j) and stats[1] == 0 and stats[2] == 0
+    out, choice, stats, judge = bltc.evaluate_adaptive(case["T"], case["G"], "stokeslet", 0.01,
+                                                       sel, 1e-3, 10, 0.6)
+    assert np.all(choice == j) and stats[1] == 1 and stats[2] == 0
+    assert 0 < judge[0] == judge[1] < 1e-3
     assert np.array_equal(out.cpu().numpy(), _fixed(torch, case, 6, 0.7))
 
 
-def test_adaptive_guard_fallback(torch, tmp_path, case):
-    """With a tolerance below FP32 rounding every batch fails the guard and is
+def test_adaptive_judge_fallback(torch, tmp_path, case):
+    """With a tolerance below FP32 rounding every batch fails the judge and is
     evaluated again with the fallback treecode."""
     j = selector.CANDIDATES.index((3, 0.9))
     sel = bltc.Selector(_const_model(tmp_path, j, -13.0))
-    out, choice, stats = bltc.evaluate_adaptive(case["T"], case["G"], "stokeslet", 0.01, sel,
-                                                1e-12, 10, 0.6)
+    out, choice, stats, judge = bltc.evaluate_adaptive(case["T"], case["G"], "stokeslet", 0.01,
+                                                       sel, 1e-12, 10, 0.6)
     assert np.all(choice == -2) and stats[2] == case["G"].nb
+    assert judge[1] < judge[0]
     assert np.array_equal(out.cpu().numpy(), _fixed(torch, case, 10, 0.6))
-    # nothing qualifies: every batch takes the fallback without the model
+    # every candidate predicted far above the budget: the cheapest is taken,
+    # and the judge sends every batch to the fallback
     sel2 = bltc.Selector(_const_model(tmp_path, j, 5.0))
-    out2, choice2, stats2 = bltc.evaluate_adaptive(case["T"], case["G"], "stokeslet", 0.01,
-                                                   sel2, 1e-6, 10, 0.6)
-    assert np.all(choice2 == -1) and stats2[1] == case["G"].nb
+    out2, choice2, stats2, _ = bltc.evaluate_adaptive(case["T"], case["G"], "stokeslet", 0.01,
+                                                      sel2, 1e-6, 10, 0.6)
+    assert np.all(choice2 == -2) and stats2[2] == case["G"].nb
     assert np.array_equal(out2.cpu().numpy(), _fixed(torch, case, 10, 0.6))
 
 
@@ -127,11 +130,12 @@ def test_adaptive_is_per_batch_composition(torch, tmp_path, case):
     path = str(tmp_path / "rand.bin")
     selector.write_model(path, p, np.zeros(12), np.full(12, 3.0), 0.0)
     sel = bltc.Selector(path)
-    out, choice, stats = bltc.evaluate_adaptive(case["T"], case["G"], "rotlet", 0.01, sel,
-                                                1e-5, 8, 0.6)
+    out, choice, stats, judge = bltc.evaluate_adaptive(case["T"], case["G"], "rotlet", 0.01,
+                                                       sel, 1e-5, 8, 0.6)
     out = out.cpu().numpy()
     used = sorted(set(choice.tolist()))
     assert len([u for u in used if u >= 0]) >= 2, used
+    assert stats[1] >= len({selector.CANDIDATES[u][0] for u in used if u >= 0})
     for u in used:
         n, th = selector.CANDIDATES[u] if u >= 0 else (8, 0.6)
         ref = _fixed(torch, case, n, th, kernel="rotlet")
