@@ -265,8 +265,20 @@ int bltc_batch_features(bltc_tree t, bltc_targets g, int32_t kernel, double eps,
 int bltc_batch_counts(bltc_tree t, bltc_targets g, double theta, int32_t* n_proxy,
                       int32_t* n_near, void* stream);
 
+/* Modelled wave cost of every batch under each of k candidates
+ * (cand_n[j], cand_theta[j]) (host arrays), into cost (device float
+ * [k][nb]): one walk per distinct theta; an accepted cluster of degree d
+ * (the candidate's, or the separation rule's when deg_min >= 1) costs
+ * (weights[0] (d+1) + weights[1]) (d+1)^2 + weights[2], a near-field source
+ * weights[3].  weights: host float[4] (per proxy evaluation, per grid row,
+ * per cluster, per near source). */
+int bltc_batch_costs(bltc_tree t, bltc_targets g, int32_t k, const int32_t* cand_n,
+                     const double* cand_theta, int32_t deg_min, const float* weights,
+                     float* cost, void* stream);
+
 /* A selector model file: little-endian
- *   char[8] "BLTCSEL1"; int32 version = 2, n_in = 12, n_hidden = 64, k;
+ *   char[8] "BLTCSEL1"; int32 version = 3, n_in = 12, n_hidden = 64, k,
+ *   deg_min (the separation rule the candidates are evaluated with, 0 = off);
  *   int32 cand_n[k]; double cand_theta[k];
  *   double theta_ref, cost_far, cost_row, cost_cluster, cost_near, margin;
  *   float mean[12], std[12]  (feature normalisation);
@@ -282,9 +294,8 @@ int bltc_selector_info(bltc_selector sel, int32_t* k, int32_t* cand_n,
  * error tol over all targets (the paper's eq. error).  Not in the paper,
  * which fixes (theta, n) for a run (Section 6).
  *  1. The network predicts e_b(j), the relative error of batch b under each
- *     candidate j; the walk counts at each candidate theta give its modelled
- *     wave cost  P (cost_far (n+1)^3 + cost_row (n+1)^2 + cost_cluster)
- *     + S cost_near  (P accepted clusters, S near-field sources).
+ *     candidate j; bltc_batch_costs gives its modelled wave cost with the
+ *     model's cost weights, under the model's separation rule (deg_min).
  *  2. The judge: one target per batch is evaluated with the fallback
  *     treecode (fb_degree, fb_theta); w_b = targets_b |u_fb|^2 estimates the
  *     batch's share of the reference norm.
@@ -292,9 +303,10 @@ int bltc_selector_info(bltc_selector sel, int32_t* k, int32_t* cand_n,
  *     cost subject to  sum_b w_b e_b^2 <= tau^2 sum_b w_b,
  *     tau = tol 10^-margin, through the Lagrange multiplier of
  *     cost + lam w_b e_b^2 (searched on a log grid in two passes).
- *  4. Modified weights of every chosen degree are computed (for the
- *     clusters its batches accept only); lists at each batch's theta;
- *     evaluation grouped by degree.
+ *  4. Lists at each batch's theta (and the separation rule's degrees);
+ *     modified weights of every degree in use, for the clusters that use it
+ *     only; evaluation grouped by the batches' degrees, the groups running
+ *     concurrently.
  *  5. The judge's estimate E^2 = sum_b targets_b |u - u_fb|^2 / sum_b w_b at
  *     the samples; if E > tol, every batch whose term exceeds tol^2 sum w / nb
  *     is evaluated again with the fallback.

@@ -81,6 +81,7 @@ def load():
                                          I32, D, I64, P, P, P]),
         "bltc_lists_export": (ctypes.c_int, [P, P, D, I32, I32] + [P] * 8),
         "bltc_counts": (ctypes.c_int, [P, P, I32, D, I32, P, P]),
+        "bltc_batch_costs": (ctypes.c_int, [P, P, I32, P, P, I32, P, P, P]),
         "bltc_mlp_params": (ctypes.c_int, [I32, P]),
         "bltc_mlp_work_size": (ctypes.c_int, [I64, I32, P]),
         "bltc_mlp_forward": (ctypes.c_int, [P, P, I64, I32, P, P, P]),
@@ -452,6 +453,20 @@ def batch_features(tree, targets, kernel, eps, theta_ref=0.7):
                                       ctypes.c_void_p(f.data_ptr()) if targets.nb else None,
                                       _stream()))
     return f
+
+
+def batch_costs(tree, targets, cands, deg_min, weights):
+    """Modelled wave cost [k][nb] (device float32) of every batch under each
+    candidate (n, theta) of `cands`."""
+    torch = _torch()
+    k = len(cands)
+    cn = np.array([c[0] for c in cands], np.int32)
+    ct = np.array([c[1] for c in cands], np.float64)
+    wv = np.array(weights, np.float32)
+    out = torch.zeros((k, max(targets.nb, 1)), dtype=torch.float32, device="cuda")
+    _check(load().bltc_batch_costs(tree._h, targets._h, k, _hp(cn), _hp(ct), int(deg_min),
+                                   _hp(wv), ctypes.c_void_p(out.data_ptr()), _stream()))
+    return out[:, :targets.nb]
 
 
 def batch_counts(tree, targets, theta):

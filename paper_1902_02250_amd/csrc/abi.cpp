@@ -359,6 +359,7 @@ void destroy_targets(bltc_targets g) {
   dfree(g->d_choice); dfree(g->d_bmap); dfree(g->d_theta_b); dfree(g->d_spos);
   dfree(g->d_sbatch); dfree(g->d_gflag); dfree(g->d_ufb);
   dfree(g->d_wt); dfree(g->d_contrib); dfree(g->d_part); dfree(g->d_sums); dfree(g->d_lam);
+  dfree(g->d_cost); dfree(g->d_candT); dfree(g->d_candn);
   delete g;
 }
 
@@ -448,13 +449,18 @@ bltc::ListArgs list_args(bltc_tree t, bltc_targets g, double theta,
 // theta_b is given) into L; returns the list sizes.
 void build_lists(bltc_tree t, bltc_targets g, double theta, const double* theta_b,
                  bltc::ListSet& L, hipStream_t s, int64_t* np, int64_t* nd,
-                 const bltc::Rule* rule = nullptr) {
+                 const bltc::Rule* rule = nullptr, const bltc::ListArgs* per_batch = nullptr) {
   const int64_t nb = g->nb;
   bltc::ListArgs a = list_args(t, g, theta, theta_b, L);
-  if (rule) {
-    if (rule->deg_min > 0 && t->host.nnodes() > bltc::kIdMask)
-      throw HipError{BLTC_EINVAL, "the separation rule supports at most 2^27 - 1 clusters"};
-    a.rule = *rule;
+  const bool on = (rule && rule->deg_min > 0) || (per_batch && per_batch->rule_deg_min > 0);
+  if (on && t->host.nnodes() > bltc::kIdMask)
+    throw HipError{BLTC_EINVAL, "the separation rule supports at most 2^27 - 1 clusters"};
+  if (rule) a.rule = *rule;
+  if (per_batch) {
+    a.choice = per_batch->choice;
+    a.cand_T = per_batch->cand_T;
+    a.cand_deg = per_batch->cand_deg;
+    a.rule_deg_min = per_batch->rule_deg_min;
   }
   StageTimer lt(BLTC_STAGE_LISTS, s);
   hipchk(bltc::launch_lists(a, false, s), "list count");
@@ -587,6 +593,41 @@ void batch_counts(bltc_tree t, bltc_targets g, double theta, int32_t* pc,
 
 constexpr int kLamGrid = 64;   // multipliers per allocation pass
 
+// Modelled wave cost of every batch under each of the k candidates
+// (cand_n[j], cand_theta[j]) into cost[j][nb] (device), with the separation
+// rule when deg_min >= 1: one walk per distinct theta.
+void candidate_costs(bltc_tree t, bltc_targets g, int k, const int32_t* cand_n,
+                     const double* cand_theta, int deg_min, const bltc::Costs& w,
+                     float* cost, hipStream_t s) {
+  std::vector<bool> done(k, false);
+  for (int j0 = 0; j0 < k; ++j0) {
+    if (done[j0]) continue;
+    bltc::CostArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.bgeo = g->d_bgeo;
+    a.nb = g->nb;
+    a.nodes.geo = t->d_geo;
+    a.nodes.range = t->d_range;
+    a.nodes.kids = t->d_kids;
+    a.nodes.nn = t->host.nnodes();
+    a.theta = cand_theta[j0];
+    a.deg_min = deg_min;
+    a.w = w;
+    a.cost = cost;
+    a.err = g->d_flags;
+    for (int j = j0; j < k && a.nc < bltc::kMaxPerTheta; ++j) {
+      if (done[j] || cand_theta[j] != cand_theta[j0]) continue;
+      done[j] = true;
+      a.deg[a.nc] = cand_n[j];
+      a.row[a.nc] = j;
+      const bltc::Rule r = make_rule(cand_theta[j], cand_n[j], deg_min);
+      for (int d = 0; d <= bltc::kMaxDegree; ++d) a.T[a.nc][d] = r.T[d];
+      ++a.nc;
+    }
+    hipchk(bltc::launch_cand_costs(a, s), "candidate costs");
+  }
+}
+
 void ensure_selection_scratch(bltc_targets g, int64_t k, int64_t nth) {
   const int64_t nb = g->nb;
   if (!g->d_feat) {
@@ -620,13 +661,16 @@ void ensure_selection_scratch(bltc_targets g, int64_t k, int64_t nth) {
     g->d_Y = dalloc<float>(nb * k);
     g->ycap = nb * k;
   }
-  if (nb * nth > g->pccap) {
-    dfree(g->d_pc);
-    dfree(g->d_sc);
-    g->d_pc = dalloc<int32_t>(nb * nth);
-    g->d_sc = dalloc<int32_t>(nb * nth);
-    g->pccap = nb * nth;
+  if (nb * k > g->costcap) {
+    dfree(g->d_cost);
+    g->d_cost = dalloc<float>(nb * k);
+    g->costcap = nb * k;
   }
+  if (!g->d_candT) {
+    g->d_candT = dalloc<double>((size_t)bltc::kMlpMaxOut * (bltc::kMaxDegree + 1));
+    g->d_candn = dalloc<int32_t>(bltc::kMlpMaxOut);
+  }
+  (void)nth;
 }
 
 // Judge sums (sum of cnt |u_fb|^2, sum of cnt |u - u_fb|^2) over the one
@@ -655,31 +699,26 @@ void evaluate_adaptive(bltc_tree t, bltc_targets g, int kernel, double eps,
     return;
   }
   const int k = sel->k;
-  std::vector<double> thetas;   // distinct thetas of the candidates
-  bltc::Candidates cand;
-  for (int j = 0; j < k; ++j) {
-    int ti = -1;
-    for (size_t u = 0; u < thetas.size(); ++u)
-      if (thetas[u] == sel->cand_theta[j]) ti = (int)u;
-    if (ti < 0) {
-      ti = (int)thetas.size();
-      thetas.push_back(sel->cand_theta[j]);
-    }
-    cand.n[j] = sel->cand_n[j];
-    cand.t[j] = ti;
-  }
+  const int rule_min = sel->deg_min;
   const bltc::Costs costs{(float)sel->cost_far, (float)sel->cost_row, (float)sel->cost_clu,
                           (float)sel->cost_near};
-  const int64_t nth = (int64_t)thetas.size();
-  ensure_selection_scratch(g, k, nth);
-  const int od = odim_of(kernel);
+  ensure_selection_scratch(g, k, 0);
 
-  // 1. predicted log10 errors of every candidate, and per-theta work counts
+  // 1. predicted log10 errors of every candidate, and their modelled costs
   compute_features(t, g, kernel, eps, sel->theta_ref, sel->d_mean, sel->d_std, g->d_feat, s);
   hipchk(bltc::launch_mlp_forward(sel->d_params, g->d_feat, nb, k, g->d_Y, nullptr, s),
          "mlp forward");
-  for (int64_t ti = 0; ti < nth; ++ti)
-    batch_counts(t, g, thetas[ti], g->d_pc + ti * nb, g->d_sc + ti * nb, s);
+  candidate_costs(t, g, k, sel->cand_n.data(), sel->cand_theta.data(), rule_min, costs,
+                  g->d_cost, s);
+  if (rule_min > 0) {   // the separation rule's thresholds of every candidate
+    std::vector<double> T((size_t)k * (bltc::kMaxDegree + 1));
+    for (int j = 0; j < k; ++j) {
+      const bltc::Rule r = make_rule(sel->cand_theta[j], sel->cand_n[j], rule_min);
+      for (int d = 0; d <= bltc::kMaxDegree; ++d) T[(size_t)j * (bltc::kMaxDegree + 1) + d] = r.T[d];
+    }
+    h2d(g->d_candT, T.data(), T.size(), s);
+    h2d(g->d_candn, sel->cand_n.data(), k, s);
+  }
 
   // 2. the judge: the fallback treecode at one sample per batch
   ensure_degree(t, fb_degree, s);
@@ -724,7 +763,7 @@ void evaluate_adaptive(bltc_tree t, bltc_targets g, int kernel, double eps,
       for (int i = 0; i < kLamGrid; ++i)
         lam[i] = std::pow(10.0, lo + (hi - lo) * i / (kLamGrid - 1));
       h2d(g->d_lam, lam.data(), kLamGrid, s);
-      hipchk(bltc::launch_alloc(g->d_Y, k, nb, g->d_pc, g->d_sc, cand, costs, g->d_wt, inv_w,
+      hipchk(bltc::launch_alloc(g->d_Y, k, nb, g->d_cost, g->d_wt, inv_w,
                                 g->d_lam, kLamGrid, g->d_part, g->d_sums, s),
              "allocation");
       d2h(sums.data(), g->d_sums, 2 * kLamGrid, s);
@@ -747,7 +786,7 @@ void evaluate_adaptive(bltc_tree t, bltc_targets g, int kernel, double eps,
       lo = hi - step;
     }
   }
-  hipchk(bltc::launch_choose(g->d_Y, k, nb, g->d_pc, g->d_sc, cand, costs, g->d_wt, inv_w,
+  hipchk(bltc::launch_choose(g->d_Y, k, nb, g->d_cost, g->d_wt, inv_w,
                              lam_star, g->d_choice, s),
          "choose");
   std::vector<int32_t> choice(nb);
@@ -764,7 +803,14 @@ void evaluate_adaptive(bltc_tree t, bltc_targets g, int kernel, double eps,
   }
   st[1] = (int64_t)by_degree.size();
   h2d(g->d_theta_b, th.data(), nb, s);
-  build_lists(t, g, 0.0, g->d_theta_b, g->ls[0], s, &np, &nd);
+  {
+    bltc::ListArgs extra;
+    extra.choice = g->d_choice;
+    extra.cand_T = g->d_candT;
+    extra.cand_deg = g->d_candn;
+    extra.rule_deg_min = rule_min;
+    build_lists(t, g, 0.0, g->d_theta_b, g->ls[0], s, &np, &nd, nullptr, &extra);
+  }
   std::vector<int32_t> order;
   std::vector<std::pair<int, std::pair<int64_t, int64_t>>> spans;
   for (auto& kv : by_degree) {
@@ -774,20 +820,34 @@ void evaluate_adaptive(bltc_tree t, bltc_targets g, int kernel, double eps,
   h2d(g->d_bmap, order.data(), nb, s);
   const int64_t nn = t->host.nnodes();
   if (!t->d_need) t->d_need = dalloc<uint8_t>(nn);
-  for (auto& sp : spans) {   // upward passes in turn: they share scratch
-    const auto it = t->deg.find(sp.first);
-    if (it == t->deg.end() || it->second.partial) {
-      hipchk(bltc::launch_need(g->d_bmap + sp.second.first, sp.second.second, g->ls[0].ptr,
-                               g->ls[0].pids, t->d_need, nn, s),
+  if (rule_min > 0) {
+    // every entry carries its degree: one need mask per degree over all batches
+    const int top = std::max(by_degree.rbegin()->first, rule_min);
+    for (int d = rule_min; d <= top; ++d) {
+      const auto it = t->deg.find(d);
+      if (it != t->deg.end() && !it->second.partial) continue;
+      hipchk(bltc::launch_need_degree(nb, g->ls[0].ptr, g->ls[0].pids, d, t->d_need, nn, s),
              "need mask");
-      ensure_degree(t, sp.first, s, t->d_need);
+      ensure_degree(t, d, s, t->d_need);
+    }
+  } else {
+    for (auto& sp : spans) {   // upward passes in turn: they share scratch
+      const auto it = t->deg.find(sp.first);
+      if (it == t->deg.end() || it->second.partial) {
+        hipchk(bltc::launch_need(g->d_bmap + sp.second.first, sp.second.second, g->ls[0].ptr,
+                                 g->ls[0].pids, t->d_need, nn, s),
+               "need mask");
+        ensure_degree(t, sp.first, s, t->d_need);
+      }
     }
   }
+  bltc_options og = o;
+  og.deg_min = rule_min;
   // the degree groups write disjoint targets: with more than one, they run
   // concurrently on side streams, largest first
   Events evs;
   if (spans.size() == 1) {
-    run_p2p(t, g, g->ls[0], kernel, eps, spans[0].first, o, g->d_bmap, nb, out, s);
+    run_p2p(t, g, g->ls[0], kernel, eps, spans[0].first, og, g->d_bmap, nb, out, s);
   } else {
     std::sort(spans.begin(), spans.end(), [](const auto& a, const auto& b) {
       const double wa = (double)a.second.second * std::pow(a.first + 1.0, 3);
@@ -800,7 +860,7 @@ void evaluate_adaptive(bltc_tree t, bltc_targets g, int kernel, double eps,
     for (size_t i = 0; i < spans.size(); ++i) {
       hipStream_t ss = side_stream((int)i);
       hipchk(hipStreamWaitEvent(ss, ready, 0), "hipStreamWaitEvent");
-      run_p2p(t, g, g->ls[0], kernel, eps, spans[i].first, o,
+      run_p2p(t, g, g->ls[0], kernel, eps, spans[i].first, og,
               g->d_bmap + spans[i].second.first, spans[i].second.second, out, ss);
       if (i + kSideStreams >= spans.size()) {   // last launch on this side stream
         hipEvent_t e = evs.make();
@@ -840,15 +900,14 @@ void evaluate_adaptive(bltc_tree t, bltc_targets g, int kernel, double eps,
     }
   }
   sync(s);
-  (void)od;
   if (choice_out) std::memcpy(choice_out, choice.data(), sizeof(int32_t) * nb);
   if (stats) std::memcpy(stats, st, sizeof st);
   if (judge) std::memcpy(judge, jd, sizeof jd);
 }
 
 // Selector model file (little endian):
-//   char magic[8] "BLTCSEL1"; int32 version (2); int32 n_in (12);
-//   int32 n_hidden (64); int32 k;
+//   char magic[8] "BLTCSEL1"; int32 version (3); int32 n_in (12);
+//   int32 n_hidden (64); int32 k; int32 deg_min (separation rule, 0 = off);
 //   int32 cand_n[k]; double cand_theta[k];
 //   double theta_ref, cost_far, cost_row, cost_cluster, cost_near, margin;
 //   float mean[12], stdv[12]; float params[bltc_mlp_params(k)];
@@ -878,14 +937,17 @@ int load_selector(const char* path, bltc_selector sel) {
     return true;
   };
   char magic[8];
-  int32_t hdr[4];
+  int32_t hdr[5];
   if (!take(magic, 8) || std::memcmp(magic, "BLTCSEL1", 8) != 0 || !take(hdr, sizeof hdr))
     return fail(BLTC_EMODEL, "selector model: bad magic or header");
-  if (hdr[0] != 2 || hdr[1] != bltc::kMlpIn || hdr[2] != bltc::kMlpHidden || hdr[3] < 1 ||
+  if (hdr[4] < 0 || hdr[4] > bltc::kMaxDegree)
+    return fail(BLTC_EMODEL, "selector model: deg_min out of range");
+  if (hdr[0] != 3 || hdr[1] != bltc::kMlpIn || hdr[2] != bltc::kMlpHidden || hdr[3] < 1 ||
       hdr[3] > bltc::kMlpMaxOut)
     return fail(BLTC_EMODEL, "selector model: unsupported version or dimensions");
   const int32_t k = hdr[3];
   sel->k = k;
+  sel->deg_min = hdr[4];
   sel->cand_n.resize(k);
   sel->cand_theta.resize(k);
   double tail[6];
@@ -1370,6 +1432,29 @@ int bltc_batch_features(bltc_tree t, bltc_targets g, int32_t kernel, double eps,
   });
 }
 
+int bltc_batch_costs(bltc_tree t, bltc_targets g, int32_t k, const int32_t* cand_n,
+                     const double* cand_theta, int32_t deg_min, const float* weights,
+                     float* cost, void* stream) {
+  if (!t || !g || !cand_n || !cand_theta || !weights)
+    return fail(BLTC_EINVAL, "NULL tree, targets, candidates or weights");
+  if (k < 1 || k > bltc::kMlpMaxOut) return fail(BLTC_EINVAL, "k must be in [1, 128]");
+  if (deg_min < 0 || deg_min > bltc::kMaxDegree)
+    return fail(BLTC_EINVAL, "deg_min must be in [0, 12]");
+  for (int j = 0; j < k; ++j)
+    if (cand_n[j] < 1 || cand_n[j] > bltc::kMaxDegree ||
+        !(cand_theta[j] >= 0.0 && cand_theta[j] <= 1.0))
+      return fail(BLTC_EINVAL, "candidate out of range");
+  for (int i = 0; i < 4; ++i)
+    if (!(weights[i] >= 0.f)) return fail(BLTC_EINVAL, "cost weights must be >= 0");
+  if (g->nb > 0 && !device_ptr(cost)) return fail(BLTC_EINVAL, "cost must be a device pointer");
+  if (g->nb == 0) return BLTC_OK;
+  return guarded([&] {
+    const bltc::Costs w{weights[0], weights[1], weights[2], weights[3]};
+    candidate_costs(t, g, k, cand_n, cand_theta, deg_min, w, cost, (hipStream_t)stream);
+    return (int)BLTC_OK;
+  });
+}
+
 int bltc_batch_counts(bltc_tree t, bltc_targets g, double theta, int32_t* n_proxy,
                       int32_t* n_near, void* stream) {
   if (!t || !g) return fail(BLTC_EINVAL, "NULL tree or targets");
@@ -1396,8 +1481,6 @@ int bltc_evaluate_adaptive(bltc_tree t, bltc_targets g, int32_t kernel, double e
   bltc_options_default(&o);
   if (opt) o = *opt;
   if (int rc = check_options(&o, kernel)) return rc;
-  if (o.deg_min != 0)
-    return fail(BLTC_EINVAL, "the learned evaluation uses fixed degrees (deg_min = 0)");
   if (g->m > 0 && !device_ptr(out)) return fail(BLTC_EINVAL, "out must be a device pointer");
   if (!t->has_w) return fail(BLTC_ESTATE, "no weights: call bltc_compute_modified_weights first");
   return guarded([&] {

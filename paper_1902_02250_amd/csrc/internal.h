@@ -76,6 +76,13 @@ struct ListArgs {
   Nodes nodes;
   double theta;
   Rule rule;
+  // separation rule per batch (learned evaluation): batch b uses candidate
+  // choice[b], whose thresholds are cand_T[choice[b]][.] and degree
+  // cand_deg[choice[b]]; rule_deg_min 0 turns it off
+  const int32_t* choice = nullptr;
+  const double* cand_T = nullptr;
+  const int32_t* cand_deg = nullptr;
+  int32_t rule_deg_min = 0;
   const double* theta_b = nullptr;  // [nb] per-batch theta, or NULL
   int32_t* pcnt;               // [nb] proxy count (count pass)
   int32_t* dcnt;               // [nb] direct count
@@ -163,16 +170,34 @@ struct Costs {
   float far, row, clu, nearf;
 };
 
+// Modelled wave cost of every batch under the candidates that share one
+// theta: one walk per batch; an accepted cluster costs
+// (far n1 + row) n1^2 + clu with n1 - 1 its degree (the candidate's, or the
+// separation rule's), a near-field source costs nearf.
+constexpr int kMaxPerTheta = 16;
+struct CostArgs {
+  const double4* bgeo;
+  int64_t nb;
+  Nodes nodes;
+  double theta;
+  int32_t nc;                          // candidates with this theta
+  int32_t deg[kMaxPerTheta];           // their degrees
+  int32_t deg_min;                     // separation rule (0: off)
+  double T[kMaxPerTheta][kMaxDegree + 1];
+  Costs w;
+  int32_t row[kMaxPerTheta];           // output row of each candidate
+  float* cost;                         // [rows][nb]
+  int32_t* err;
+};
+
 // ---- launchers (defined in the .hip files) --------------------------------
 hipError_t launch_guard(int kernel, int degree, const GuardArgs& a, hipStream_t s);
 hipError_t launch_features(const FeatArgs& a, hipStream_t s);
 int64_t alloc_blocks(int64_t nb);
-hipError_t launch_alloc(const float* Y, int k, int64_t nb, const int32_t* pcnt,
-                        const int32_t* scnt, const Candidates& c, const Costs& w,
+hipError_t launch_alloc(const float* Y, int k, int64_t nb, const float* cost,
                         const double* wt, double inv_wsum, const double* lam, int G,
                         double* partial, double* sums, hipStream_t s);
-hipError_t launch_choose(const float* Y, int k, int64_t nb, const int32_t* pcnt,
-                         const int32_t* scnt, const Candidates& c, const Costs& w,
+hipError_t launch_choose(const float* Y, int k, int64_t nb, const float* cost,
                          const double* wt, double inv_wsum, double lam, int32_t* choice,
                          hipStream_t s);
 hipError_t launch_judge(int ns, const int32_t* bptr, const int32_t* spos,
@@ -183,6 +208,7 @@ hipError_t launch_flag(int ns, const double* contrib, double thr, int32_t* flag,
                        hipStream_t s);
 hipError_t launch_need(const int32_t* bsel, int64_t nsel, const int32_t* pptr,
                        const int32_t* pids, uint8_t* need, int64_t nn, hipStream_t s);
+hipError_t launch_cand_costs(const CostArgs& a, hipStream_t s);
 hipError_t launch_need_degree(int64_t nb, const int32_t* pptr, const int32_t* pids, int d,
                               uint8_t* need, int64_t nn, hipStream_t s);
 hipError_t launch_gather_points(const double* x, const double* y,
@@ -306,6 +332,10 @@ struct bltc_targets_s {
   double* d_part = nullptr;    // [blocks][G][2] partial sums
   double* d_sums = nullptr;    // [G][2]
   double* d_lam = nullptr;     // [G]
+  float* d_cost = nullptr;     // [k][nb] modelled costs
+  int64_t costcap = 0;
+  double* d_candT = nullptr;   // [k][kMaxDegree+1] rule thresholds
+  int32_t* d_candn = nullptr;  // [k] candidate degrees
 };
 
 struct bltc_selector_s {
@@ -313,6 +343,7 @@ struct bltc_selector_s {
   std::vector<int32_t> cand_n;
   std::vector<double> cand_theta;
   double theta_ref = 0.7, margin = 0.0;
+  int32_t deg_min = 0;         // separation rule the candidates use
   double cost_far = 1.0, cost_row = 0.0, cost_clu = 0.0, cost_near = 1.0;
   std::vector<float> mean, stdv, params;
   float* d_params = nullptr;

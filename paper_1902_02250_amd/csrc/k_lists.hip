@@ -27,6 +27,17 @@ __global__ __launch_bounds__(128) void k_lists(ListArgs a) {
   if (b >= a.nb) return;
   const double4 g = a.bgeo[b];
   const double th = a.theta_b ? a.theta_b[b] : a.theta;
+  // under the separation rule every entry carries its degree
+  bool enc = a.rule.deg_min > 0;
+  int rmin = a.rule.deg_min, rdeg = a.rule.degree;
+  const double* rT = a.rule.T;
+  if (a.choice && a.rule_deg_min > 0) {
+    const int j = a.choice[b];
+    enc = true;
+    rmin = a.rule_deg_min;
+    rdeg = a.cand_deg[j];
+    rT = a.cand_T + (int64_t)j * (kMaxDegree + 1);
+  }
   const double th2 = th * th;
   int32_t stack[kStackMax];
   int sp = 0;
@@ -50,10 +61,10 @@ __global__ __launch_bounds__(128) void k_lists(ListArgs a) {
     if (R2 > 0.0 && rr * rr <= th2 * R2) {
       if (FILL) {
         int32_t e = q;
-        if (a.rule.deg_min > 0) {
+        if (enc) {
           const double qq = (rr * rr) / R2;
-          int d = a.rule.deg_min;
-          while (d < a.rule.degree && !(qq <= a.rule.T[d])) ++d;
+          int d = rmin < rdeg ? rmin : rdeg;
+          while (d < rdeg && !(qq <= rT[d])) ++d;
           e |= d << kDegShift;
         }
         pout[np] = e;

@@ -334,7 +334,8 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void k_p2p(
   for (int li = pptr[b]; li < pptr[b + 1]; ++li) {
     const int e = pids[li];
     const int q = e & kIdMask;
-    const int n1 = RULE ? (e >> kDegShift) + 1 : N1;
+    const int dd = e >> kDegShift;
+    const int n1 = (RULE && dd) ? dd + 1 : N1;
     T p[OD];
 #pragma unroll
     for (int c = 0; c < OD; ++c) p[c] = 0;

@@ -79,33 +79,68 @@ __global__ __launch_bounds__(128) void k_features(FeatArgs a) {
   }
 }
 
-// Modelled wave cost of candidate j for batch b: proxy clusters x
-// (cfar (n+1)^3 + crow (n+1)^2 + cclu) + near sources x cnear.
-__device__ __forceinline__ double cand_cost(const Candidates& c, const Costs& w, int j,
-                                           int64_t nb, int64_t b,
-                                           const int32_t* __restrict__ pcnt,
-                                           const int32_t* __restrict__ scnt) {
-  const int ti = c.t[j];
-  const double n1 = (double)(c.n[j] + 1);
-  const double P = (double)pcnt[(int64_t)ti * nb + b];
-  const double S = (double)scnt[(int64_t)ti * nb + b];
-  return P * (((double)w.far * n1 + (double)w.row) * n1 * n1 + (double)w.clu) +
-         S * (double)w.nearf;
+// Modelled wave costs of the candidates sharing one theta (CostArgs): one
+// walk per batch; an accepted cluster at ratio^2 qq costs
+// (far n1 + row) n1^2 + clu with n1 - 1 the candidate's degree, or under the
+// separation rule the first d >= deg_min with qq <= T[d].
+__global__ __launch_bounds__(128) void k_cand_costs(CostArgs a) {
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= a.nb) return;
+  const double4 g = a.bgeo[b];
+  const double th2 = a.theta * a.theta;
+  float far[kMaxPerTheta];
+  for (int i = 0; i < kMaxPerTheta; ++i) far[i] = 0.f;
+  double S = 0.0;
+  int32_t stack[kStackMax];
+  int sp = 0;
+  if (a.nodes.nn > 0) stack[sp++] = 0;
+  while (sp > 0) {
+    const int32_t q = stack[--sp];
+    const double4 c = a.nodes.geo[q];
+    const double dx = g.x - c.x;
+    const double dy = g.y - c.y;
+    const double dz = g.z - c.z;
+    const double R2 = dx * dx + dy * dy + dz * dz;
+    const double rr = g.w + c.w;
+    if (R2 > 0.0 && rr * rr <= th2 * R2) {
+      const double qq = (rr * rr) / R2;
+      for (int i = 0; i < a.nc; ++i) {
+        int d = a.deg[i];
+        if (a.deg_min > 0 && a.deg_min < a.deg[i]) {
+          d = a.deg_min;
+          while (d < a.deg[i] && !(qq <= a.T[i][d])) ++d;
+        }
+        const float n1 = (float)(d + 1);
+        far[i] += (a.w.far * n1 + a.w.row) * n1 * n1 + a.w.clu;
+      }
+      continue;
+    }
+    const int2 kd = a.nodes.kids[q];
+    if (kd.y == 0) {
+      const int2 rg = a.nodes.range[q];
+      S += rg.y - rg.x;
+      continue;
+    }
+    if (sp + kd.y > kStackMax) {
+      *a.err = 1;
+      break;
+    }
+    for (int k = kd.y - 1; k >= 0; --k) stack[sp++] = kd.x + k;
+  }
+  for (int i = 0; i < a.nc; ++i) a.cost[(int64_t)a.row[i] * a.nb + b] = far[i] + (float)S * a.w.nearf;
 }
 
 // The candidate minimising cost + lam wn e^2 with e = 10^Y the predicted
 // relative error; ties go to the lower index.
 __device__ __forceinline__ int best_candidate(const float* __restrict__ Yb, int k,
-                                             const Candidates& c, const Costs& w,
                                              int64_t nb, int64_t b,
-                                             const int32_t* __restrict__ pcnt,
-                                             const int32_t* __restrict__ scnt,
+                                             const float* __restrict__ cost_jb,
                                              double lw, double* cost, double* err2) {
   int best = 0;
   double bv = 0.0, bc = 0.0, be = 0.0;
   for (int j = 0; j < k; ++j) {
     const double e2 = exp10(2.0 * (double)Yb[j]);
-    const double cj = cand_cost(c, w, j, nb, b, pcnt, scnt);
+    const double cj = (double)cost_jb[(int64_t)j * nb + b];
     const double v = cj + lw * e2;
     if (j == 0 || v < bv) {
       best = j;
@@ -155,8 +190,7 @@ constexpr int kSelThreads = 256;
 // for lam[g] wn_b (wn_b = wt[b] / sum wt); partial[blk][g] = (sum of cost,
 // sum of wn e^2) over the work group's batches.
 __global__ __launch_bounds__(kSelThreads) void k_alloc(
-    const float* __restrict__ Y, int k, int64_t nb, const int32_t* __restrict__ pcnt,
-    const int32_t* __restrict__ scnt, Candidates c, Costs w,
+    const float* __restrict__ Y, int k, int64_t nb, const float* __restrict__ costs,
     const double* __restrict__ wt, double inv_wsum, const double* __restrict__ lam,
     int G, double* __restrict__ partial) {
   const int64_t b = (int64_t)blockIdx.x * kSelThreads + threadIdx.x;
@@ -164,21 +198,18 @@ __global__ __launch_bounds__(kSelThreads) void k_alloc(
   const double wn = act ? wt[b] * inv_wsum : 0.0;
   for (int g = 0; g < G; ++g) {
     double cost = 0.0, e2 = 0.0;
-    if (act) best_candidate(Y + b * k, k, c, w, nb, b, pcnt, scnt, lam[g] * wn, &cost, &e2);
+    if (act) best_candidate(Y + b * k, k, nb, b, costs, lam[g] * wn, &cost, &e2);
     block_sum2<kSelThreads>(cost, wn * e2, partial + ((int64_t)blockIdx.x * G + g) * 2);
   }
 }
 
 __global__ void k_choose(const float* __restrict__ Y, int k, int64_t nb,
-                         const int32_t* __restrict__ pcnt,
-                         const int32_t* __restrict__ scnt, Candidates c, Costs w,
-                         const double* __restrict__ wt, double inv_wsum, double lam,
-                         int32_t* __restrict__ choice) {
+                         const float* __restrict__ costs, const double* __restrict__ wt,
+                         double inv_wsum, double lam, int32_t* __restrict__ choice) {
   const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= nb) return;
   double cost, e2;
-  choice[b] = best_candidate(Y + b * k, k, c, w, nb, b, pcnt, scnt, lam * wt[b] * inv_wsum,
-                             &cost, &e2);
+  choice[b] = best_candidate(Y + b * k, k, nb, b, costs, lam * wt[b] * inv_wsum, &cost, &e2);
 }
 
 // Judge sums over the sampled targets (one per batch, sample i of batch i):
@@ -266,26 +297,24 @@ hipError_t launch_features(const FeatArgs& a, hipStream_t s) {
 
 int64_t alloc_blocks(int64_t nb) { return (nb + kSelThreads - 1) / kSelThreads; }
 
-hipError_t launch_alloc(const float* Y, int k, int64_t nb, const int32_t* pcnt,
-                        const int32_t* scnt, const Candidates& c, const Costs& w,
+hipError_t launch_alloc(const float* Y, int k, int64_t nb, const float* cost,
                         const double* wt, double inv_wsum, const double* lam, int G,
                         double* partial, double* sums, hipStream_t s) {
   if (nb == 0) return hipSuccess;
   const int nblk = (int)alloc_blocks(nb);
-  hipLaunchKernelGGL(k_alloc, dim3(nblk), dim3(kSelThreads), 0, s, Y, k, nb, pcnt, scnt, c,
-                     w, wt, inv_wsum, lam, G, partial);
+  hipLaunchKernelGGL(k_alloc, dim3(nblk), dim3(kSelThreads), 0, s, Y, k, nb, cost, wt,
+                     inv_wsum, lam, G, partial);
   hipLaunchKernelGGL(k_sum_columns, dim3((2 * G + 63) / 64), dim3(64), 0, s, partial, nblk,
                      2 * G, sums);
   return hipGetLastError();
 }
 
-hipError_t launch_choose(const float* Y, int k, int64_t nb, const int32_t* pcnt,
-                         const int32_t* scnt, const Candidates& c, const Costs& w,
+hipError_t launch_choose(const float* Y, int k, int64_t nb, const float* cost,
                          const double* wt, double inv_wsum, double lam, int32_t* choice,
                          hipStream_t s) {
   if (nb == 0) return hipSuccess;
   hipLaunchKernelGGL(k_choose, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, s, Y, k, nb,
-                     pcnt, scnt, c, w, wt, inv_wsum, lam, choice);
+                     cost, wt, inv_wsum, lam, choice);
   return hipGetLastError();
 }
 
@@ -316,6 +345,12 @@ hipError_t launch_need(const int32_t* bsel, int64_t nsel, const int32_t* pptr,
   if (nsel > 0)
     hipLaunchKernelGGL(k_need, dim3((unsigned)((nsel + 127) / 128)), dim3(128), 0, s, bsel,
                        nsel, pptr, pids, need);
+  return hipGetLastError();
+}
+
+hipError_t launch_cand_costs(const CostArgs& a, hipStream_t s) {
+  if (a.nb == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_cand_costs, dim3((unsigned)((a.nb + 127) / 128)), dim3(128), 0, s, a);
   return hipGetLastError();
 }
 

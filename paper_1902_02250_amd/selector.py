@@ -40,6 +40,7 @@ THETA_REF = 0.7
 # about 8 per row and 50 per cluster, 20.3 per near-field pair).
 COST_FAR, COST_ROW, COST_CLU, COST_NEAR = 0.69, 0.5, 2.5, 1.0
 LAM_GRID, LAM_LO, LAM_HI = 64, 0.0, 24.0   # multiplier search, log10 range
+DEG_MIN = 1                # the candidates are evaluated with the separation rule
 LOG_FLOOR = -12.0          # labels are log10(max(error, 1e-12))
 SAMPLES_PER_BATCH = 8
 TRAIN_SEEDS = range(0, 200)
@@ -54,11 +55,11 @@ def _fnv1a(data):
 
 
 def write_model(path, params, mean, std, margin, cand=CANDIDATES, theta_ref=THETA_REF,
-                costs=(COST_FAR, COST_ROW, COST_CLU, COST_NEAR)):
+                costs=(COST_FAR, COST_ROW, COST_CLU, COST_NEAR), deg_min=DEG_MIN):
     k = len(cand)
     params = np.ascontiguousarray(params, dtype=np.float32)
     assert params.size == bltc_param_count(k)
-    body = b"BLTCSEL1" + struct.pack("<4i", 2, 12, 64, k)
+    body = b"BLTCSEL1" + struct.pack("<5i", 3, 12, 64, k, deg_min)
     body += np.array([c[0] for c in cand], dtype="<i4").tobytes()
     body += np.array([c[1] for c in cand], dtype="<f8").tobytes()
     body += struct.pack("<6d", theta_ref, *costs, margin)
@@ -79,7 +80,7 @@ def run_config(seed):
     """The synthetic workload of training (or evaluation) run `seed`."""
     r = inputs.uniform01(seed, 7, 0, 6)
     return dict(dist=("uniform", "mixture", "union")[int(r[0] * 3)],
-                n=int(round(10 ** (4.3 + 1.4 * r[1]))),
+                n=int(round(10 ** (4.3 + 2.3 * r[1]))),
                 kernel="stokeslet" if r[2] < 0.5 else "rotlet",
                 eps=float(10 ** (-3.0 + 1.5 * r[3])),
                 leaf=(500, 1000, 2000)[int(r[4] * 3)], seed=int(seed))
@@ -116,16 +117,14 @@ def label_run(cfg, log=print):
     ref = bltc.direct(d_src, d_src, d_w, kernel, eps, idx=d_idx, precision="fp64")
     den = np.bincount(bat, weights=(ref * ref).sum(0).cpu().numpy(), minlength=tg.nb)
     T = np.zeros((tg.nb, K), np.float32)
-    pc = np.zeros((len(CAND_THETA), tg.nb), np.int64)
-    sc = np.zeros((len(CAND_THETA), tg.nb), np.int64)
-    for ti, th in enumerate(CAND_THETA):
-        a, b = bltc.batch_counts(tree, tg, th)
-        pc[ti], sc[ti] = a.cpu().numpy(), b.cpu().numpy()
+    cost = bltc.batch_costs(tree, tg, CANDIDATES, DEG_MIN,
+                            (COST_FAR, COST_ROW, COST_CLU, COST_NEAR)).cpu().numpy()
     out = torch.empty((bltc.ODIM[kernel], cfg["n"]), dtype=torch.float64, device=dev)
     for n in CAND_N:
         tree.compute_weights(d_w, n)
         for ti, th in enumerate(CAND_THETA):
-            bltc.evaluate_tree(tree, tg, kernel, eps, n, th, precision="fp32_fp64acc", out=out)
+            bltc.evaluate_tree(tree, tg, kernel, eps, n, th, precision="fp32_fp64acc", out=out,
+                               deg_min=DEG_MIN)
             diff = out[:, d_idx] - ref
             num = np.bincount(bat, weights=(diff * diff).sum(0).cpu().numpy(), minlength=tg.nb)
             err = np.sqrt(num / np.maximum(den, 1e-300))
@@ -133,7 +132,7 @@ def label_run(cfg, log=print):
     cnt = np.diff(ex["bptr"])
     ns = np.bincount(bat, minlength=tg.nb)
     wt = den * cnt / np.maximum(ns, 1)      # batch share of the reference norm
-    return dict(X=X, T=T, pc=pc, sc=sc, cnt=cnt, wt=wt, cfg=cfg)
+    return dict(X=X, T=T, cost=cost, cnt=cnt, wt=wt, cfg=cfg)
 
 
 def generate(seeds, path, log=print, budget_s=None):
@@ -162,8 +161,7 @@ def save_runs(runs, path, per_run=300):
         keep = np.sort(np.random.default_rng(i).permutation(nb)[:per_run])
         out[f"X_{i}"] = r["X"][keep]
         out[f"T_{i}"] = r["T"][keep].astype(np.float16)
-        out[f"pc_{i}"] = r["pc"][:, keep].astype(np.int32)
-        out[f"sc_{i}"] = r["sc"][:, keep].astype(np.int32)
+        out[f"cost_{i}"] = r["cost"][:, keep].astype(np.float32)
         out[f"cnt_{i}"] = r["cnt"][keep].astype(np.int32)
         out[f"wt_{i}"] = r["wt"][keep]
     np.savez_compressed(path, cfgs=np.array([json.dumps(r["cfg"]) for r in runs]), **out)
@@ -172,8 +170,8 @@ def save_runs(runs, path, per_run=300):
 def load_runs(path):
     z = np.load(path, allow_pickle=False)
     cfgs = [json.loads(str(c)) for c in z["cfgs"]]
-    return [dict(X=z[f"X_{i}"], T=z[f"T_{i}"].astype(np.float32), pc=z[f"pc_{i}"],
-                 sc=z[f"sc_{i}"], cnt=z[f"cnt_{i}"], wt=z[f"wt_{i}"], cfg=c)
+    return [dict(X=z[f"X_{i}"], T=z[f"T_{i}"].astype(np.float32), cost=z[f"cost_{i}"],
+                 cnt=z[f"cnt_{i}"], wt=z[f"wt_{i}"], cfg=c)
             for i, c in enumerate(cfgs)]
 
 
@@ -237,15 +235,10 @@ def predict(params, mean, std, X):
 
 
 # ---- offline check of a policy ---------------------------------------------------------------
-def batch_costs(run, costs=(COST_FAR, COST_ROW, COST_CLU, COST_NEAR)):
-    """Modelled wave cost of every (batch, candidate), [nb][K]."""
-    cf, cr, cc, cn = costs
-    cost = np.zeros((run["cnt"].size, K))
-    for j, (n, th) in enumerate(CANDIDATES):
-        ti = CAND_THETA.index(th)
-        n1 = n + 1.0
-        cost[:, j] = run["pc"][ti] * ((cf * n1 + cr) * n1 * n1 + cc) + run["sc"][ti] * cn
-    return cost
+def batch_costs(run):
+    """Modelled wave cost of every (batch, candidate), [nb][K], as
+    bltc_batch_costs gave it when the run was labelled."""
+    return run["cost"].T.astype(np.float64)
 
 
 def allocate(Y, cost, wt, tau):
@@ -350,28 +343,37 @@ def compare(workload, model=MODEL_PATH, tol=None, fb=(10, 0.6), reps=2, n=None, 
         err = (torch.linalg.norm(out[:, d_idx] - ref) / torch.linalg.norm(ref)).item()
         return e0.elapsed_time(e1) / reps, err, res
 
-    fixed = {}
-    for (nn, th) in CANDIDATES:
-        def step(nn=nn, th=th):
-            tree.compute_weights(d_w, nn)
-            bltc.evaluate_tree(tree, tg, kernel, eps, nn, th, precision="fp32_fp64acc", out=out)
-        ms, err, _ = timed(step)
-        fixed[(nn, th)] = (ms, err)
-        if th == CAND_THETA[-1]:
-            log(f"[selector] {workload} fixed n={nn}: " + ", ".join(
-                f"theta {t}: {fixed[(nn, t)][0]:.1f} ms E={fixed[(nn, t)][1]:.2e}"
-                for t in CAND_THETA))
+    fixed, ruled = {}, {}
+    for rule, table in ((0, fixed), (DEG_MIN, ruled)):
+        for (nn, th) in CANDIDATES:
+            def step(nn=nn, th=th):
+                tree.compute_weights(d_w, nn)
+                bltc.evaluate_tree(tree, tg, kernel, eps, nn, th, precision="fp32_fp64acc",
+                                   out=out, deg_min=rule)
+            ms, err, _ = timed(step)
+            table[(nn, th)] = (ms, err)
+            if th == CAND_THETA[-1]:
+                log(f"[selector] {workload} rule {rule} n={nn}: " + ", ".join(
+                    f"theta {t}: {table[(nn, t)][0]:.1f} ms E={table[(nn, t)][1]:.2e}"
+                    for t in CAND_THETA))
     if tol is None:
         tol = cfg.get("tol") or fixed[(cfg["degree"], cfg["theta"])][1]
     ok = [c for c in CANDIDATES if fixed[c][1] <= tol]
     best = min(ok, key=lambda c: fixed[c][0]) if ok else None
+    okr = [c for c in CANDIDATES if ruled[c][1] <= tol]
+    best_r = min(okr, key=lambda c: ruled[c][0]) if okr else None
     models = [model] if isinstance(model, str) else list(model)
     res = dict(workload=workload, n=cfg["n"], kernel=kernel, tol=tol,
                best_fixed=None if best is None else dict(n=best[0], theta=best[1],
                                                          ms=fixed[best][0], err=fixed[best][1]),
+               best_fixed_rule=None if best_r is None else dict(
+                   n=best_r[0], theta=best_r[1], deg_min=DEG_MIN, ms=ruled[best_r][0],
+                   err=ruled[best_r][1]),
                fallback_fixed=dict(n=fb[0], theta=fb[1], ms=fixed[fb][0], err=fixed[fb][1]),
                fixed_sweep={f"{c[0]},{c[1]}": [round(fixed[c][0], 3), fixed[c][1]]
                             for c in CANDIDATES},
+               rule_sweep={f"{c[0]},{c[1]}": [round(ruled[c][0], 3), ruled[c][1]]
+                           for c in CANDIDATES},
                learned=[])
     for mpath in models:
         sel = bltc.Selector(mpath)
@@ -389,11 +391,14 @@ def compare(workload, model=MODEL_PATH, tol=None, fb=(10, 0.6), reps=2, n=None, 
                               for j in np.argsort(-used)[:6] if used[j]])
         if best is not None:
             r["speedup_vs_best_fixed"] = fixed[best][0] / ms_l
+        if best_r is not None:
+            r["speedup_vs_best_fixed_rule"] = ruled[best_r][0] / ms_l
         res["learned"].append(r)
         log(f"[selector] {workload} {r['model']}: learned {ms_l:.2f} ms E={err_l:.3e} "
             f"(judge {judge[0]:.2e} -> {judge[1]:.2e}, {int(stats[2])} redone, "
             f"{int(stats[1])} degrees); best fixed {best} "
-            f"{fixed[best][0] if best else float('nan'):.2f} ms; tol {tol:.3e}")
+            f"{fixed[best][0] if best else float('nan'):.2f} ms; best fixed with the rule "
+            f"{best_r} {ruled[best_r][0] if best_r else float('nan'):.2f} ms; tol {tol:.3e}")
     return res
 
 

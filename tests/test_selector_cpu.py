@@ -21,9 +21,9 @@ def test_model_layout(tmp_path):
     path, params = _write(tmp_path)
     raw = open(path, "rb").read()
     assert raw[:8] == b"BLTCSEL1"
-    assert struct.unpack("<4i", raw[8:24]) == (2, 12, 64, selector.K)
+    assert struct.unpack("<5i", raw[8:28]) == (3, 12, 64, selector.K, selector.DEG_MIN)
     k = selector.K
-    off = 24 + 4 * k + 8 * k
+    off = 28 + 4 * k + 8 * k
     assert struct.unpack("<6d", raw[off:off + 48]) == (
         selector.THETA_REF, selector.COST_FAR, selector.COST_ROW, selector.COST_CLU,
         selector.COST_NEAR, 0.25)
@@ -45,7 +45,7 @@ def test_loader_rejects_damage(tmp_path):
     bad = tmp_path / "bad.bin"
     for mutate in (lambda b: b.__setitem__(100, b[100] ^ 1),      # checksum
                    lambda b: b.__setitem__(0, ord("X")),         # magic
-                   lambda b: b.__setitem__(8, 3)):               # version
+                   lambda b: b.__setitem__(8, 4)):               # version
         b = bytearray(raw)
         mutate(b)
         bad.write_bytes(bytes(b))
@@ -59,6 +59,8 @@ def test_loader_rejects_damage(tmp_path):
     assert _status(path2) == "EMODEL"
     path3, _ = _write(tmp_path, costs=(-1.0, 0.5, 2.5, 1.0))     # negative cost weight
     assert _status(path3) == "EMODEL"
+    path4, _ = _write(tmp_path, deg_min=13)                      # rule out of range
+    assert _status(path4) == "EMODEL"
 
 
 def _toy(seed, nb=300):
