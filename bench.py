@@ -99,6 +99,7 @@ def main():
     ap.add_argument("--precision", default="fp32_fp64acc",
                     choices=["fp64", "fp32_fp64acc", "fp32_kahan"])
     ap.add_argument("--degree", type=int, default=None)
+    ap.add_argument("--kernel", default=None, choices=["stokeslet", "rotlet"])
     ap.add_argument("--theta", type=float, default=None)
     ap.add_argument("--batch-size", type=int, default=64)
     ap.add_argument("--order-leaf", type=int, default=32)
@@ -106,6 +107,9 @@ def main():
     ap.add_argument("--err-sample", type=int, default=10000)
     ap.add_argument("--cpu-sample", type=int, default=65536)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tol-settings", default="9,0.7,0;10,0.7,1",
+                    help="n,theta,deg_min;... settings also timed, with their error, "
+                         "beside the headline configuration ('' for none)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first run one device-to-device copy of MIB MiB, the reference "
                          "for scaling HBM byte counters")
@@ -140,12 +144,14 @@ def main():
         cfg["degree"] = args.degree
     if args.theta is not None:
         cfg["theta"] = args.theta
+    if args.kernel:
+        cfg["kernel"] = args.kernel
     kernel, eps, degree, theta = cfg["kernel"], cfg["eps"], cfg["degree"], cfg["theta"]
     n = cfg["n"]
     log(f"[bench] generating {args.workload}: n={n} {cfg['dist']} {kernel} eps={eps} "
         f"degree={degree} theta={theta} leaf={cfg['leaf']} precision={args.precision}")
     src = inputs.points(cfg["dist"], n, cfg["seed"])
-    w = inputs.weights(n, cfg["seed"])
+    w = inputs.weights_for(cfg["dist"], n, cfg["seed"])
     dev = torch.device("cuda:0")
     d_src = torch.from_numpy(src).to(dev)
     d_w = torch.from_numpy(w).to(dev)
@@ -234,6 +240,33 @@ def main():
         "roofline": roof,
         "cpu_baseline": None,
     }
+    # further settings of the same workload: fixed degree and separation rule
+    extra = []
+    for item in [t for t in args.tol_settings.split(";") if t.strip()]:
+        dn, th, dm = item.split(",")
+        dn, th, dm = int(dn), float(th), int(dm)
+
+        def xstep(dn=dn, th=th, dm=dm):
+            tree.compute_weights(d_w, dn)
+            bltc.evaluate_tree(tree, tg, kernel, eps, dn, th, precision=args.precision,
+                               out=out, deg_min=dm)
+        xstep()
+        torch.cuda.synchronize()
+        xs = max(2, args.steps // 2)
+        e0.record()
+        for i in range(xs):
+            xstep()
+        e1.record()
+        torch.cuda.synchronize()
+        xms = e0.elapsed_time(e1) / xs
+        xerr = (torch.linalg.norm(out[:, d_idx] - ref) / torch.linalg.norm(ref)).item()
+        xp, xd = bltc.counts(tree, tg, dn, th, dm)
+        extra.append({"degree": dn, "theta": th, "deg_min": dm, "steps": xs,
+                      "ms_per_step": round(xms, 4), "rel_l2_err": xerr,
+                      "interactions_per_step": xp + xd,
+                      "interactions_per_s": (xp + xd) / (xms * 1e-3)})
+        log(f"[bench] n={dn} theta={th} deg_min={dm}: {xms:.3f} ms/step, E={xerr:.3e}")
+    res["settings"] = extra
     if not args.no_cpu_baseline:
         log(f"[bench] CPU oracle baseline on {args.cpu_sample} targets ...")
         res["cpu_baseline"] = cpu_baseline(cfg, src, w, args.cpu_sample, args.precision)

@@ -14,8 +14,14 @@ Workloads (particle positions are (3, n) float64, weights (3, n) float64):
               draws); a point falling outside the cube is drawn again
   union     - half uniform, half mixture, concatenated and then shuffled by
               a seeded permutation
+  pairs     - the microorganism pairs of the paper's first example (Section
+              8.1): bodies uniform in a cube of side 10, each with a
+              flagellum particle at distance 0.02 along a direction uniform on
+              the sphere; the two exert unit forces in opposite directions
+              along that direction (body +u, flagellum -u)
 Weights (forces or torques) are i.i.d. uniform in [-1, 1] per component and
-come from their own stream of the same seed.
+come from their own stream of the same seed, except for `pairs`, whose forces
+follow from the orientations.
 """
 import numpy as np
 
@@ -24,7 +30,7 @@ _M1 = np.uint64(0xBF58476D1CE4E5B9)
 _M2 = np.uint64(0x94D049BB133111EB)
 
 # stream identifiers, so positions, weights, etc. never share counters
-S_POS, S_WEIGHT, S_MIX_PARAM, S_MIX_POINT, S_SHUFFLE, S_SAMPLE = range(6)
+S_POS, S_WEIGHT, S_MIX_PARAM, S_MIX_POINT, S_SHUFFLE, S_SAMPLE, S_PAIR = range(7)
 
 
 def _mix(z):
@@ -51,6 +57,13 @@ def uniform_points(n, seed, lo=-1.0, hi=1.0):
 def weights(n, seed, wdim=3):
     u = uniform01(seed, S_WEIGHT, 0, wdim * n).reshape(n, wdim).T
     return np.ascontiguousarray(-1.0 + 2.0 * u)
+
+
+def weights_for(dist, n, seed):
+    """The weights of a workload: the pair forces for `pairs`, else weights()."""
+    if dist == "pairs":
+        return _pairs(n, seed)[1]
+    return weights(n, seed)
 
 
 def mixture_params(seed, ncomp=32):
@@ -117,7 +130,28 @@ def union_points(n, seed):
     return np.ascontiguousarray(p[:, shuffle_perm(n, seed)])
 
 
+def _pairs(n, seed, side=10.0, length=0.02):
+    """Positions and forces of n particles as body-flagellum pairs (a last
+    unpaired body when n is odd)."""
+    m = (n + 1) // 2
+    body = side * uniform01(seed, S_POS, 0, 3 * m).reshape(m, 3)
+    u = uniform01(seed, S_PAIR, 0, 2 * m).reshape(m, 2)
+    z = 2.0 * u[:, 0] - 1.0
+    phi = 2.0 * np.pi * u[:, 1]
+    rxy = np.sqrt(np.maximum(0.0, 1.0 - z * z))
+    d = np.stack([rxy * np.cos(phi), rxy * np.sin(phi), z], axis=1)
+    pos = np.empty((2 * m, 3))
+    pos[0::2] = body
+    pos[1::2] = body + length * d
+    frc = np.empty((2 * m, 3))
+    frc[0::2] = d
+    frc[1::2] = -d
+    return np.ascontiguousarray(pos[:n].T), np.ascontiguousarray(frc[:n].T)
+
+
 def points(dist, n, seed):
+    if dist == "pairs":
+        return _pairs(n, seed)[0]
     if dist == "uniform":
         return uniform_points(n, seed)
     if dist == "mixture":
@@ -152,6 +186,9 @@ CONFIGS = {
     "c5": dict(n=4000000, dist="union", kernel="stokeslet", eps=0.002,
                degree=10, theta=0.6, leaf=2000, seed=SEED_BASE + 5,
                error_sample=10000, tol=1e-6),
+    # the paper's first example at its 640K size (Section 8.1, Tables 1 and 4)
+    "e1": dict(n=640000, dist="pairs", kernel="stokeslet", eps=0.02, degree=7,
+               theta=0.7, leaf=2000, seed=SEED_BASE + 11, error_sample=10000),
 }
 
 
@@ -162,5 +199,5 @@ def workload(name, n=None):
     if n is not None:
         cfg["n"] = n
     pts = points(cfg["dist"], cfg["n"], cfg["seed"])
-    w = weights(cfg["n"], cfg["seed"])
+    w = weights_for(cfg["dist"], cfg["n"], cfg["seed"])
     return pts, w, cfg

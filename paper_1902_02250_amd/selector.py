@@ -186,7 +186,7 @@ def glorot(k, seed):
     return np.concatenate(parts).astype(np.float32)
 
 
-def train(X, T, epochs=60, batch=4096, lr=2e-3, seed=0, log=print):
+def train(X, T, epochs=200, batch=512, lr=2e-3, seed=0, log=print):
     """Returns (params, mean, std, loss per epoch)."""
     import torch
     dev = torch.device("cuda:0")
@@ -321,7 +321,7 @@ def compare(workload, model=MODEL_PATH, tol=None, fb=(10, 0.6), reps=2, n=None, 
     if n:
         cfg["n"] = n
     src = inputs.points(cfg["dist"], cfg["n"], cfg["seed"])
-    w = inputs.weights(cfg["n"], cfg["seed"])
+    w = inputs.weights_for(cfg["dist"], cfg["n"], cfg["seed"])
     d_src, d_w = torch.from_numpy(src).to(dev), torch.from_numpy(w).to(dev)
     tree = bltc.Tree(d_src, cfg["leaf"])
     tg = bltc.Targets(d_src, 64, 32, 512)
@@ -409,7 +409,9 @@ def main(argv=None):
     ap.add_argument("--data", default="gpurun_out/selector_runs.npz")
     ap.add_argument("--model", default="gpurun_out/selector_v1.bin")
     ap.add_argument("--runs", type=int, default=200)
-    ap.add_argument("--epochs", type=int, default=60)
+    ap.add_argument("--seeds", default=None, help="first:last training seeds to label")
+    ap.add_argument("--label-only", action="store_true", help="label and save, no training")
+    ap.add_argument("--epochs", type=int, default=200)
     ap.add_argument("--skip-generate", action="store_true")
     ap.add_argument("--budget", type=float, default=None, help="seconds for labelling")
     ap.add_argument("--compare", default=None, help="workload name: time learned vs fixed")
@@ -425,9 +427,15 @@ def main(argv=None):
                 json.dump(res, fh, indent=1)
         return 0
     if args.skip_generate:
-        runs = load_runs(args.data)
+        runs = [r for path in args.data.split(",") for r in load_runs(path)]
     else:
-        runs = generate(list(TRAIN_SEEDS)[:args.runs], args.data, log, args.budget)
+        seeds = list(TRAIN_SEEDS)[:args.runs]
+        if args.seeds:
+            a, b = (int(v) for v in args.seeds.split(":"))
+            seeds = list(range(a, b))
+        runs = generate(seeds, args.data, log, args.budget)
+        if args.label_only:
+            return 0
     nval = max(1, len(runs) // 10)
     train_runs, val_runs = runs[:-nval], runs[-nval:]
     X = np.concatenate([r["X"] for r in train_runs])
