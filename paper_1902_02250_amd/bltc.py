@@ -178,6 +178,7 @@ class Tree:
         h = ctypes.c_void_p()
         _check(L.bltc_build_tree(x, y, z, n, int(leaf_max), _stream(), ctypes.byref(h)))
         self._h = h
+        self._lib = load()
         nn, dep = ctypes.c_int64(), ctypes.c_int32()
         _check(L.bltc_tree_info(self._h, ctypes.byref(nn), ctypes.byref(dep)))
         self.nnodes, self.depth = nn.value, dep.value
@@ -210,8 +211,11 @@ class Tree:
         return f, g
 
     def close(self):
-        if getattr(self, "_h", None):
-            load().bltc_tree_destroy(self._h)
+        # the library object is kept on the handle: at interpreter exit the
+        # module's globals may already be gone
+        lib = getattr(self, "_lib", None)
+        if getattr(self, "_h", None) and lib is not None:
+            lib.bltc_tree_destroy(self._h)
             self._h = None
 
     __del__ = close
@@ -229,6 +233,7 @@ class Targets:
         _check(L.bltc_build_targets(x, y, z, m, int(batch_size), int(order_leaf),
                                     int(group_max), _stream(), ctypes.byref(h)))
         self._h = h
+        self._lib = load()
         nb = ctypes.c_int64()
         _check(L.bltc_targets_export(self._h, ctypes.byref(nb), None, None, None, None))
         self.nb = nb.value
@@ -242,8 +247,11 @@ class Targets:
         return out
 
     def close(self):
-        if getattr(self, "_h", None):
-            load().bltc_targets_destroy(self._h)
+        # the library object is kept on the handle: at interpreter exit the
+        # module's globals may already be gone
+        lib = getattr(self, "_lib", None)
+        if getattr(self, "_h", None) and lib is not None:
+            lib.bltc_targets_destroy(self._h)
             self._h = None
 
     __del__ = close
@@ -488,6 +496,7 @@ class Selector:
         h = ctypes.c_void_p()
         _check(load().bltc_selector_load(os.fsencode(path), ctypes.byref(h)))
         self._h = h
+        self._lib = load()
         k = ctypes.c_int32()
         _check(load().bltc_selector_info(self._h, ctypes.byref(k), None, None))
         self.k = k.value
@@ -496,8 +505,11 @@ class Selector:
         _check(load().bltc_selector_info(self._h, None, _hp(self.cand_n), _hp(self.cand_theta)))
 
     def close(self):
-        if getattr(self, "_h", None):
-            load().bltc_selector_destroy(self._h)
+        # the library object is kept on the handle: at interpreter exit the
+        # module's globals may already be gone
+        lib = getattr(self, "_lib", None)
+        if getattr(self, "_h", None) and lib is not None:
+            lib.bltc_selector_destroy(self._h)
             self._h = None
 
     __del__ = close

@@ -359,7 +359,7 @@ void destroy_targets(bltc_targets g) {
   dfree(g->d_choice); dfree(g->d_bmap); dfree(g->d_theta_b); dfree(g->d_spos);
   dfree(g->d_sbatch); dfree(g->d_gflag); dfree(g->d_ufb);
   dfree(g->d_wt); dfree(g->d_contrib); dfree(g->d_part); dfree(g->d_sums); dfree(g->d_lam);
-  dfree(g->d_cost); dfree(g->d_candT); dfree(g->d_candn);
+  dfree(g->d_cost); dfree(g->d_e2); dfree(g->d_candT); dfree(g->d_candn);
   delete g;
 }
 
@@ -599,6 +599,18 @@ constexpr int kLamGrid = 64;   // multipliers per allocation pass
 void candidate_costs(bltc_tree t, bltc_targets g, int k, const int32_t* cand_n,
                      const double* cand_theta, int deg_min, const bltc::Costs& w,
                      float* cost, hipStream_t s) {
+  // the rule's thresholds of every candidate, [k][kMaxDegree + 1], on the device
+  if (!g->d_candT) {
+    g->d_candT = dalloc<double>((size_t)bltc::kMlpMaxOut * (bltc::kMaxDegree + 1));
+    g->d_candn = dalloc<int32_t>(bltc::kMlpMaxOut);
+  }
+  std::vector<double> T((size_t)k * (bltc::kMaxDegree + 1));
+  for (int j = 0; j < k; ++j) {
+    const bltc::Rule r = make_rule(cand_theta[j], cand_n[j], deg_min);
+    for (int d = 0; d <= bltc::kMaxDegree; ++d) T[(size_t)j * (bltc::kMaxDegree + 1) + d] = r.T[d];
+  }
+  h2d(g->d_candT, T.data(), T.size(), s);
+  h2d(g->d_candn, cand_n, k, s);
   std::vector<bool> done(k, false);
   for (int j0 = 0; j0 < k; ++j0) {
     if (done[j0]) continue;
@@ -612,6 +624,7 @@ void candidate_costs(bltc_tree t, bltc_targets g, int k, const int32_t* cand_n,
     a.nodes.nn = t->host.nnodes();
     a.theta = cand_theta[j0];
     a.deg_min = deg_min;
+    a.T = g->d_candT;
     a.w = w;
     a.cost = cost;
     a.err = g->d_flags;
@@ -620,8 +633,6 @@ void candidate_costs(bltc_tree t, bltc_targets g, int k, const int32_t* cand_n,
       done[j] = true;
       a.deg[a.nc] = cand_n[j];
       a.row[a.nc] = j;
-      const bltc::Rule r = make_rule(cand_theta[j], cand_n[j], deg_min);
-      for (int d = 0; d <= bltc::kMaxDegree; ++d) a.T[a.nc][d] = r.T[d];
       ++a.nc;
     }
     hipchk(bltc::launch_cand_costs(a, s), "candidate costs");
@@ -663,7 +674,9 @@ void ensure_selection_scratch(bltc_targets g, int64_t k, int64_t nth) {
   }
   if (nb * k > g->costcap) {
     dfree(g->d_cost);
+    dfree(g->d_e2);
     g->d_cost = dalloc<float>(nb * k);
+    g->d_e2 = dalloc<double>(nb * k);
     g->costcap = nb * k;
   }
   if (!g->d_candT) {
@@ -710,15 +723,7 @@ void evaluate_adaptive(bltc_tree t, bltc_targets g, int kernel, double eps,
          "mlp forward");
   candidate_costs(t, g, k, sel->cand_n.data(), sel->cand_theta.data(), rule_min, costs,
                   g->d_cost, s);
-  if (rule_min > 0) {   // the separation rule's thresholds of every candidate
-    std::vector<double> T((size_t)k * (bltc::kMaxDegree + 1));
-    for (int j = 0; j < k; ++j) {
-      const bltc::Rule r = make_rule(sel->cand_theta[j], sel->cand_n[j], rule_min);
-      for (int d = 0; d <= bltc::kMaxDegree; ++d) T[(size_t)j * (bltc::kMaxDegree + 1) + d] = r.T[d];
-    }
-    h2d(g->d_candT, T.data(), T.size(), s);
-    h2d(g->d_candn, sel->cand_n.data(), k, s);
-  }
+  hipchk(bltc::launch_pred_err2(g->d_Y, k, nb, g->d_e2, s), "predicted errors");
 
   // 2. the judge: the fallback treecode at one sample per batch
   ensure_degree(t, fb_degree, s);
@@ -763,7 +768,7 @@ void evaluate_adaptive(bltc_tree t, bltc_targets g, int kernel, double eps,
       for (int i = 0; i < kLamGrid; ++i)
         lam[i] = std::pow(10.0, lo + (hi - lo) * i / (kLamGrid - 1));
       h2d(g->d_lam, lam.data(), kLamGrid, s);
-      hipchk(bltc::launch_alloc(g->d_Y, k, nb, g->d_cost, g->d_wt, inv_w,
+      hipchk(bltc::launch_alloc(g->d_e2, k, nb, g->d_cost, g->d_wt, inv_w,
                                 g->d_lam, kLamGrid, g->d_part, g->d_sums, s),
              "allocation");
       d2h(sums.data(), g->d_sums, 2 * kLamGrid, s);
@@ -786,7 +791,7 @@ void evaluate_adaptive(bltc_tree t, bltc_targets g, int kernel, double eps,
       lo = hi - step;
     }
   }
-  hipchk(bltc::launch_choose(g->d_Y, k, nb, g->d_cost, g->d_wt, inv_w,
+  hipchk(bltc::launch_choose(g->d_e2, k, nb, g->d_cost, g->d_wt, inv_w,
                              lam_star, g->d_choice, s),
          "choose");
   std::vector<int32_t> choice(nb);

@@ -183,9 +183,9 @@ struct CostArgs {
   int32_t nc;                          // candidates with this theta
   int32_t deg[kMaxPerTheta];           // their degrees
   int32_t deg_min;                     // separation rule (0: off)
-  double T[kMaxPerTheta][kMaxDegree + 1];
+  const double* T;                     // [rows][kMaxDegree + 1] rule thresholds (device)
   Costs w;
-  int32_t row[kMaxPerTheta];           // output row of each candidate
+  int32_t row[kMaxPerTheta];           // output row (and T row) of each candidate
   float* cost;                         // [rows][nb]
   int32_t* err;
 };
@@ -194,10 +194,11 @@ struct CostArgs {
 hipError_t launch_guard(int kernel, int degree, const GuardArgs& a, hipStream_t s);
 hipError_t launch_features(const FeatArgs& a, hipStream_t s);
 int64_t alloc_blocks(int64_t nb);
-hipError_t launch_alloc(const float* Y, int k, int64_t nb, const float* cost,
+hipError_t launch_pred_err2(const float* Y, int k, int64_t nb, double* e2, hipStream_t s);
+hipError_t launch_alloc(const double* e2, int k, int64_t nb, const float* cost,
                         const double* wt, double inv_wsum, const double* lam, int G,
                         double* partial, double* sums, hipStream_t s);
-hipError_t launch_choose(const float* Y, int k, int64_t nb, const float* cost,
+hipError_t launch_choose(const double* e2, int k, int64_t nb, const float* cost,
                          const double* wt, double inv_wsum, double lam, int32_t* choice,
                          hipStream_t s);
 hipError_t launch_judge(int ns, const int32_t* bptr, const int32_t* spos,
@@ -333,6 +334,7 @@ struct bltc_targets_s {
   double* d_sums = nullptr;    // [G][2]
   double* d_lam = nullptr;     // [G]
   float* d_cost = nullptr;     // [k][nb] modelled costs
+  double* d_e2 = nullptr;      // [k][nb] predicted squared errors
   int64_t costcap = 0;
   double* d_candT = nullptr;   // [k][kMaxDegree+1] rule thresholds
   int32_t* d_candn = nullptr;  // [k] candidate degrees

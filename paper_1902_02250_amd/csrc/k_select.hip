@@ -82,13 +82,15 @@ __global__ __launch_bounds__(128) void k_features(FeatArgs a) {
 // Modelled wave costs of the candidates sharing one theta (CostArgs): one
 // walk per batch; an accepted cluster at ratio^2 qq costs
 // (far n1 + row) n1^2 + clu with n1 - 1 the candidate's degree, or under the
-// separation rule the first d >= deg_min with qq <= T[d].
+// separation rule the first d >= deg_min with qq <= T[d].  The candidate
+// loop is unrolled to kMaxPerTheta so the sums stay in registers.
 __global__ __launch_bounds__(128) void k_cand_costs(CostArgs a) {
   const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= a.nb) return;
   const double4 g = a.bgeo[b];
   const double th2 = a.theta * a.theta;
   float far[kMaxPerTheta];
+#pragma unroll
   for (int i = 0; i < kMaxPerTheta; ++i) far[i] = 0.f;
   double S = 0.0;
   int32_t stack[kStackMax];
@@ -104,14 +106,19 @@ __global__ __launch_bounds__(128) void k_cand_costs(CostArgs a) {
     const double rr = g.w + c.w;
     if (R2 > 0.0 && rr * rr <= th2 * R2) {
       const double qq = (rr * rr) / R2;
-      for (int i = 0; i < a.nc; ++i) {
-        int d = a.deg[i];
-        if (a.deg_min > 0 && a.deg_min < a.deg[i]) {
-          d = a.deg_min;
-          while (d < a.deg[i] && !(qq <= a.T[i][d])) ++d;
+#pragma unroll
+      for (int i = 0; i < kMaxPerTheta; ++i) {
+        if (i < a.nc) {
+          const int n = a.deg[i];
+          int d = n;
+          if (a.deg_min > 0 && a.deg_min < n) {
+            const double* __restrict__ T = a.T + (int64_t)a.row[i] * (kMaxDegree + 1);
+            d = a.deg_min;
+            while (d < n && !(qq <= T[d])) ++d;
+          }
+          const float n1 = (float)(d + 1);
+          far[i] += (a.w.far * n1 + a.w.row) * n1 * n1 + a.w.clu;
         }
-        const float n1 = (float)(d + 1);
-        far[i] += (a.w.far * n1 + a.w.row) * n1 * n1 + a.w.clu;
       }
       continue;
     }
@@ -127,19 +134,30 @@ __global__ __launch_bounds__(128) void k_cand_costs(CostArgs a) {
     }
     for (int k = kd.y - 1; k >= 0; --k) stack[sp++] = kd.x + k;
   }
-  for (int i = 0; i < a.nc; ++i) a.cost[(int64_t)a.row[i] * a.nb + b] = far[i] + (float)S * a.w.nearf;
+#pragma unroll
+  for (int i = 0; i < kMaxPerTheta; ++i)
+    if (i < a.nc) a.cost[(int64_t)a.row[i] * a.nb + b] = far[i] + (float)S * a.w.nearf;
+}
+
+// e2[j][b] = 10^(2 Y[b][j]): the predicted squared relative errors.
+__global__ void k_pred_err2(const float* __restrict__ Y, int k, int64_t nb,
+                            double* __restrict__ e2) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nb * k) return;
+  const int64_t b = i % nb, j = i / nb;
+  e2[i] = exp10(2.0 * (double)Y[b * k + j]);
 }
 
 // The candidate minimising cost + lam wn e^2 with e = 10^Y the predicted
 // relative error; ties go to the lower index.
-__device__ __forceinline__ int best_candidate(const float* __restrict__ Yb, int k,
+__device__ __forceinline__ int best_candidate(const double* __restrict__ e2_jb, int k,
                                              int64_t nb, int64_t b,
                                              const float* __restrict__ cost_jb,
                                              double lw, double* cost, double* err2) {
   int best = 0;
   double bv = 0.0, bc = 0.0, be = 0.0;
   for (int j = 0; j < k; ++j) {
-    const double e2 = exp10(2.0 * (double)Yb[j]);
+    const double e2 = e2_jb[(int64_t)j * nb + b];
     const double cj = (double)cost_jb[(int64_t)j * nb + b];
     const double v = cj + lw * e2;
     if (j == 0 || v < bv) {
@@ -190,7 +208,7 @@ constexpr int kSelThreads = 256;
 // for lam[g] wn_b (wn_b = wt[b] / sum wt); partial[blk][g] = (sum of cost,
 // sum of wn e^2) over the work group's batches.
 __global__ __launch_bounds__(kSelThreads) void k_alloc(
-    const float* __restrict__ Y, int k, int64_t nb, const float* __restrict__ costs,
+    const double* __restrict__ E2, int k, int64_t nb, const float* __restrict__ costs,
     const double* __restrict__ wt, double inv_wsum, const double* __restrict__ lam,
     int G, double* __restrict__ partial) {
   const int64_t b = (int64_t)blockIdx.x * kSelThreads + threadIdx.x;
@@ -198,18 +216,18 @@ __global__ __launch_bounds__(kSelThreads) void k_alloc(
   const double wn = act ? wt[b] * inv_wsum : 0.0;
   for (int g = 0; g < G; ++g) {
     double cost = 0.0, e2 = 0.0;
-    if (act) best_candidate(Y + b * k, k, nb, b, costs, lam[g] * wn, &cost, &e2);
+    if (act) best_candidate(E2, k, nb, b, costs, lam[g] * wn, &cost, &e2);
     block_sum2<kSelThreads>(cost, wn * e2, partial + ((int64_t)blockIdx.x * G + g) * 2);
   }
 }
 
-__global__ void k_choose(const float* __restrict__ Y, int k, int64_t nb,
+__global__ void k_choose(const double* __restrict__ E2, int k, int64_t nb,
                          const float* __restrict__ costs, const double* __restrict__ wt,
                          double inv_wsum, double lam, int32_t* __restrict__ choice) {
   const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= nb) return;
   double cost, e2;
-  choice[b] = best_candidate(Y + b * k, k, nb, b, costs, lam * wt[b] * inv_wsum, &cost, &e2);
+  choice[b] = best_candidate(E2, k, nb, b, costs, lam * wt[b] * inv_wsum, &cost, &e2);
 }
 
 // Judge sums over the sampled targets (one per batch, sample i of batch i):
@@ -297,23 +315,31 @@ hipError_t launch_features(const FeatArgs& a, hipStream_t s) {
 
 int64_t alloc_blocks(int64_t nb) { return (nb + kSelThreads - 1) / kSelThreads; }
 
-hipError_t launch_alloc(const float* Y, int k, int64_t nb, const float* cost,
+hipError_t launch_pred_err2(const float* Y, int k, int64_t nb, double* e2, hipStream_t s) {
+  const int64_t tot = nb * k;
+  if (tot == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_pred_err2, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, Y, k,
+                     nb, e2);
+  return hipGetLastError();
+}
+
+hipError_t launch_alloc(const double* e2, int k, int64_t nb, const float* cost,
                         const double* wt, double inv_wsum, const double* lam, int G,
                         double* partial, double* sums, hipStream_t s) {
   if (nb == 0) return hipSuccess;
   const int nblk = (int)alloc_blocks(nb);
-  hipLaunchKernelGGL(k_alloc, dim3(nblk), dim3(kSelThreads), 0, s, Y, k, nb, cost, wt,
+  hipLaunchKernelGGL(k_alloc, dim3(nblk), dim3(kSelThreads), 0, s, e2, k, nb, cost, wt,
                      inv_wsum, lam, G, partial);
   hipLaunchKernelGGL(k_sum_columns, dim3((2 * G + 63) / 64), dim3(64), 0, s, partial, nblk,
                      2 * G, sums);
   return hipGetLastError();
 }
 
-hipError_t launch_choose(const float* Y, int k, int64_t nb, const float* cost,
+hipError_t launch_choose(const double* e2, int k, int64_t nb, const float* cost,
                          const double* wt, double inv_wsum, double lam, int32_t* choice,
                          hipStream_t s) {
   if (nb == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_choose, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, s, Y, k, nb,
+  hipLaunchKernelGGL(k_choose, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, s, e2, k, nb,
                      cost, wt, inv_wsum, lam, choice);
   return hipGetLastError();
 }

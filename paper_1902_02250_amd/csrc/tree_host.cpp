@@ -12,10 +12,16 @@
 //     h = 0.5 (hi - lo); nodes are numbered breadth first.
 // Built with -ffp-contract=off so the FP64 expressions round exactly as
 // written.  The coordinates travel with the permutation, so each box is a
-// scan over contiguous memory.
+// scan over contiguous memory.  The nodes of one level own disjoint particle
+// ranges, so a level is processed by several host threads and its children
+// are numbered afterwards in node order: the result does not depend on the
+// thread count.
+#include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <numeric>
+#include <thread>
 #include <utility>
 
 #include "internal.h"
@@ -31,6 +37,26 @@ struct Builder {
   std::vector<int32_t> tperm;
   std::vector<uint8_t> code;
 };
+
+// Runs fn(i) for i in [0, n) on up to hardware_concurrency threads (at most
+// 16), handing out indices in order.
+template <typename F>
+void parallel_for(int64_t n, F&& fn) {
+  const int64_t hw = std::max<int64_t>(1, std::min<int64_t>(16, std::thread::hardware_concurrency()));
+  const int64_t nt = std::min<int64_t>(hw, n);
+  if (nt <= 1) {
+    for (int64_t i = 0; i < n; ++i) fn(i);
+    return;
+  }
+  std::atomic<int64_t> next(0);
+  auto work = [&] {
+    for (int64_t i = next++; i < n; i = next++) fn(i);
+  };
+  std::vector<std::thread> th;
+  for (int64_t k = 1; k < nt; ++k) th.emplace_back(work);
+  work();
+  for (auto& x : th) x.join();
+}
 
 void node_geometry(const Builder& B, int32_t b, int32_t e, double lo[3],
                    double hi[3]) {
@@ -78,69 +104,138 @@ void build_host_tree(const double* x, const double* y, const double* z,
     t.count.push_back(0);
     if (lev > t.depth) t.depth = lev;
   };
+  // what the processing of one node leaves for the numbering pass
+  struct NodeOut {
+    double lo[3], hi[3], ctr[3], rad;
+    int32_t off[8], cnt[8];
+    int nch;
+  };
   add(0, (int32_t)n, 0);
-  for (size_t q = 0; q < t.begin.size(); ++q) {
-    const int32_t b = t.begin[q], e = t.end[q];
-    double lo[3], hi[3], side[3], hsq[3];
-    node_geometry(B, b, e, lo, hi);
-    for (int a = 0; a < 3; ++a) t.box.push_back(lo[a]);
-    for (int a = 0; a < 3; ++a) t.box.push_back(hi[a]);
-    for (int a = 0; a < 3; ++a) {
-      side[a] = hi[a] - lo[a];
-      t.ctr.push_back(0.5 * (lo[a] + hi[a]));
-      const double half = 0.5 * (hi[a] - lo[a]);
-      hsq[a] = half * half;
-    }
-    t.rad.push_back(std::sqrt((hsq[0] + hsq[1]) + hsq[2]));
-    double lmax = std::max(side[0], std::max(side[1], side[2]));
-    if ((int64_t)(e - b) <= leaf_max || !(lmax > 0.0)) continue;
+  size_t lev_begin = 0;
+  while (lev_begin < t.begin.size()) {
+    const size_t lev_end = t.begin.size();
+    std::vector<NodeOut> res(lev_end - lev_begin);
+    auto process = [&](int64_t k, bool intra) {
+      const size_t q = lev_begin + (size_t)k;
+      NodeOut& o = res[k];
+      o.nch = 0;
+      const int32_t b = t.begin[q], e = t.end[q];
+      // chunks of the node's range for the intra-node parallel passes
+      const int64_t nck = intra ? std::min<int64_t>(64, std::max<int64_t>(1, (e - b) >> 15)) : 1;
+      auto cb = [&](int64_t c) { return (int32_t)(b + ((int64_t)(e - b) * c) / nck); };
+      double side[3], hsq[3];
+      if (nck == 1) {
+        node_geometry(B, b, e, o.lo, o.hi);
+      } else {   // min and max are exact in any order
+        std::vector<double> clo(3 * nck), chi(3 * nck);
+        parallel_for(nck, [&](int64_t c) {
+          node_geometry(B, cb(c), cb(c + 1), &clo[3 * c], &chi[3 * c]);
+        });
+        for (int a = 0; a < 3; ++a) {
+          o.lo[a] = clo[a];
+          o.hi[a] = chi[a];
+          for (int64_t c = 1; c < nck; ++c) {
+            if (clo[3 * c + a] < o.lo[a]) o.lo[a] = clo[3 * c + a];
+            if (chi[3 * c + a] > o.hi[a]) o.hi[a] = chi[3 * c + a];
+          }
+        }
+      }
+      for (int a = 0; a < 3; ++a) {
+        side[a] = o.hi[a] - o.lo[a];
+        o.ctr[a] = 0.5 * (o.lo[a] + o.hi[a]);
+        const double half = 0.5 * (o.hi[a] - o.lo[a]);
+        hsq[a] = half * half;
+      }
+      o.rad = std::sqrt((hsq[0] + hsq[1]) + hsq[2]);
+      const double lmax = std::max(side[0], std::max(side[1], side[2]));
+      if ((int64_t)(e - b) <= leaf_max || !(lmax > 0.0)) return;
 
-    const double cut = lmax * 0.70710678118654752440;   // l_max / sqrt(2)
-    bool split[3];
-    double mid[3];
-    for (int a = 0; a < 3; ++a) {
-      split[a] = side[a] > cut;
-      mid[a] = t.ctr[3 * q + a];
-    }
-    int32_t hist[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    for (int32_t i = b; i < e; ++i) {
-      uint8_t cd = 0;
-      if (split[0] && !(B.c[0][i] < mid[0])) cd |= 1;
-      if (split[1] && !(B.c[1][i] < mid[1])) cd |= 2;
-      if (split[2] && !(B.c[2][i] < mid[2])) cd |= 4;
-      B.code[i] = cd;
-      ++hist[cd];
-    }
-    int used = 0;
-    for (int k = 0; k < 8; ++k) used += hist[k] != 0;
-    if (used < 2) continue;
+      const double cut = lmax * 0.70710678118654752440;   // l_max / sqrt(2)
+      bool split[3];
+      for (int a = 0; a < 3; ++a) split[a] = side[a] > cut;
+      // codes and per-chunk histograms; the stable partition places chunk c's
+      // particles of code k after those of the chunks before it
+      std::vector<int32_t> hist(8 * nck, 0);
+      auto codes = [&](int64_t c) {
+        int32_t* h = &hist[8 * c];
+        for (int32_t i = cb(c); i < cb(c + 1); ++i) {
+          uint8_t cd = 0;
+          if (split[0] && !(B.c[0][i] < o.ctr[0])) cd |= 1;
+          if (split[1] && !(B.c[1][i] < o.ctr[1])) cd |= 2;
+          if (split[2] && !(B.c[2][i] < o.ctr[2])) cd |= 4;
+          B.code[i] = cd;
+          ++h[cd];
+        }
+      };
+      if (nck == 1) codes(0); else parallel_for(nck, codes);
+      int32_t tot[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+      for (int64_t c = 0; c < nck; ++c)
+        for (int k8 = 0; k8 < 8; ++k8) tot[k8] += hist[8 * c + k8];
+      int used = 0;
+      for (int k8 = 0; k8 < 8; ++k8) used += tot[k8] != 0;
+      if (used < 2) return;
 
-    int32_t off[8];
-    int32_t acc = b;
-    for (int k = 0; k < 8; ++k) {
-      off[k] = acc;
-      acc += hist[k];
+      int32_t off[8];
+      int32_t acc = b;
+      for (int k8 = 0; k8 < 8; ++k8) {
+        off[k8] = acc;
+        acc += tot[k8];
+      }
+      std::vector<int32_t> pos(8 * nck);
+      for (int k8 = 0; k8 < 8; ++k8) {
+        int32_t p = off[k8];
+        for (int64_t c = 0; c < nck; ++c) {
+          pos[8 * c + k8] = p;
+          p += hist[8 * c + k8];
+        }
+      }
+      auto scatter = [&](int64_t c) {
+        int32_t* ps = &pos[8 * c];
+        for (int32_t i = cb(c); i < cb(c + 1); ++i) {
+          const int32_t d = ps[B.code[i]]++;
+          B.tperm[d] = B.perm[i];
+          for (int a = 0; a < 3; ++a) B.tc[a][d] = B.c[a][i];
+        }
+      };
+      auto copyback = [&](int64_t c) {
+        const int32_t lo = cb(c), hi = cb(c + 1);
+        std::memcpy(B.perm.data() + lo, B.tperm.data() + lo, sizeof(int32_t) * (hi - lo));
+        for (int a = 0; a < 3; ++a)
+          std::memcpy(B.c[a].data() + lo, B.tc[a].data() + lo, sizeof(double) * (hi - lo));
+      };
+      if (nck == 1) {
+        scatter(0);
+        copyback(0);
+      } else {
+        parallel_for(nck, scatter);
+        parallel_for(nck, copyback);
+      }
+      for (int k8 = 0; k8 < 8; ++k8) {
+        if (!tot[k8]) continue;
+        o.off[o.nch] = off[k8];
+        o.cnt[o.nch] = tot[k8];
+        ++o.nch;
+      }
+    };
+    const int64_t nlev = (int64_t)(lev_end - lev_begin);
+    if (nlev < 8) {
+      for (int64_t k = 0; k < nlev; ++k) process(k, true);
+    } else {
+      parallel_for(nlev, [&](int64_t k) { process(k, false); });
     }
-    int32_t pos[8];
-    std::memcpy(pos, off, sizeof pos);
-    for (int32_t i = b; i < e; ++i) {
-      const int32_t d = pos[B.code[i]]++;
-      B.tperm[d] = B.perm[i];
-      for (int a = 0; a < 3; ++a) B.tc[a][d] = B.c[a][i];
+    // geometry and children of the level, in node order (breadth first)
+    for (size_t q = lev_begin; q < lev_end; ++q) {
+      const NodeOut& o = res[q - lev_begin];
+      for (int a = 0; a < 3; ++a) t.box.push_back(o.lo[a]);
+      for (int a = 0; a < 3; ++a) t.box.push_back(o.hi[a]);
+      for (int a = 0; a < 3; ++a) t.ctr.push_back(o.ctr[a]);
+      t.rad.push_back(o.rad);
+      if (o.nch == 0) continue;
+      t.first[q] = (int32_t)t.begin.size();
+      t.count[q] = o.nch;
+      for (int c = 0; c < o.nch; ++c) add(o.off[c], o.off[c] + o.cnt[c], t.level[q] + 1);
     }
-    std::memcpy(B.perm.data() + b, B.tperm.data() + b, sizeof(int32_t) * (e - b));
-    for (int a = 0; a < 3; ++a)
-      std::memcpy(B.c[a].data() + b, B.tc[a].data() + b, sizeof(double) * (e - b));
-
-    const int32_t child0 = (int32_t)t.begin.size();
-    int32_t nch = 0;
-    for (int k = 0; k < 8; ++k) {
-      if (!hist[k]) continue;
-      add(off[k], off[k] + hist[k], t.level[q] + 1);
-      ++nch;
-    }
-    t.first[q] = child0;
-    t.count[q] = nch;
+    lev_begin = lev_end;
   }
   t.perm.swap(B.perm);
 }
@@ -174,26 +269,35 @@ void build_host_batches(const double* x, const double* y, const double* z,
   groups_of(order, 0, group_max, groups);
   out.bptr.clear();
   const double* src[3] = {x, y, z};
-  for (const auto& g : groups) {
-    for (int64_t s = g.first; s < g.second; s += batch_size) {
-      const int64_t e = std::min<int64_t>(g.second, s + batch_size);
-      out.bptr.push_back((int32_t)s);
-      double sq[3];
-      for (int a = 0; a < 3; ++a) {
-        double lo = src[a][out.perm[s]], hi = lo;
-        for (int64_t i = s + 1; i < e; ++i) {
-          const double v = src[a][out.perm[i]];
-          if (v < lo) lo = v;
-          if (v > hi) hi = v;
-        }
-        out.geo.push_back(0.5 * (lo + hi));
-        const double h = 0.5 * (hi - lo);
-        sq[a] = h * h;
-      }
-      out.geo.push_back(std::sqrt((sq[0] + sq[1]) + sq[2]));
-    }
-  }
+  for (const auto& g : groups)
+    for (int64_t s = g.first; s < g.second; s += batch_size) out.bptr.push_back((int32_t)s);
+  const int64_t nb = (int64_t)out.bptr.size();
   out.bptr.push_back((int32_t)m);
+  // every batch ends at the next batch's start or at its group's end
+  std::vector<int32_t> bend(nb);
+  {
+    int64_t b = 0;
+    for (const auto& g : groups)
+      for (int64_t s = g.first; s < g.second; s += batch_size)
+        bend[b++] = (int32_t)std::min<int64_t>(g.second, s + batch_size);
+  }
+  out.geo.resize(4 * nb);
+  parallel_for(nb, [&](int64_t b) {
+    const int64_t s = out.bptr[b], e = bend[b];
+    double sq[3];
+    for (int a = 0; a < 3; ++a) {
+      double lo = src[a][out.perm[s]], hi = lo;
+      for (int64_t i = s + 1; i < e; ++i) {
+        const double v = src[a][out.perm[i]];
+        if (v < lo) lo = v;
+        if (v > hi) hi = v;
+      }
+      out.geo[4 * b + a] = 0.5 * (lo + hi);
+      const double h = 0.5 * (hi - lo);
+      sq[a] = h * h;
+    }
+    out.geo[4 * b + 3] = std::sqrt((sq[0] + sq[1]) + sq[2]);
+  });
 }
 
 }  // namespace bltc
