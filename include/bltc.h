@@ -277,10 +277,11 @@ int bltc_batch_costs(bltc_tree t, bltc_targets g, int32_t k, const int32_t* cand
                      float* cost, void* stream);
 
 /* A selector model file: little-endian
- *   char[8] "BLTCSEL1"; int32 version = 3, n_in = 12, n_hidden = 64, k,
+ *   char[8] "BLTCSEL1"; int32 version = 4, n_in = 12, n_hidden = 64, k,
  *   deg_min (the separation rule the candidates are evaluated with, 0 = off);
  *   int32 cand_n[k]; double cand_theta[k];
- *   double theta_ref, cost_far, cost_row, cost_cluster, cost_near, margin;
+ *   double theta_ref, cost_far, cost_row, cost_cluster, cost_near, margin,
+ *          margin_global;
  *   float mean[12], std[12]  (feature normalisation);
  *   float params[bltc_mlp_params(k)];
  *   uint64 FNV-1a hash of all preceding bytes.
@@ -299,10 +300,13 @@ int bltc_selector_info(bltc_selector sel, int32_t* k, int32_t* cand_n,
  *  2. The judge: one target per batch is evaluated with the fallback
  *     treecode (fb_degree, fb_theta); w_b = targets_b |u_fb|^2 estimates the
  *     batch's share of the reference norm.
- *  3. The batches share the error budget: the choice minimises the total
- *     cost subject to  sum_b w_b e_b^2 <= tau^2 sum_b w_b,
- *     tau = tol 10^-margin, through the Lagrange multiplier of
- *     cost + lam w_b e_b^2 (searched on a log grid in two passes).
+ *  3. mode BLTC_SELECT_BATCH: the batches share the error budget: the
+ *     choice minimises the total cost subject to
+ *     sum_b w_b e_b^2 <= tau^2 sum_b w_b, tau = tol 10^-margin, through the
+ *     Lagrange multiplier of cost + lam w_b e_b^2 (searched on a log grid in
+ *     two passes).  mode BLTC_SELECT_RUN: one candidate for every batch,
+ *     the cheapest whose predicted global error is within
+ *     tol 10^-margin_global (else the one predicted most accurate).
  *  4. Lists at each batch's theta (and the separation rule's degrees);
  *     modified weights of every degree in use, for the clusters that use it
  *     only; evaluation grouped by the batches' degrees, the groups running
@@ -315,8 +319,9 @@ int bltc_selector_info(bltc_selector sel, int32_t* k, int32_t* cand_n,
  * batches, distinct degrees, batches re-evaluated, 0.  judge (host double
  * [2], may be NULL): the judge's error estimate before and after its
  * re-evaluation.  Synchronises on stream. */
+enum { BLTC_SELECT_BATCH = 0, BLTC_SELECT_RUN = 1 };
 int bltc_evaluate_adaptive(bltc_tree t, bltc_targets g, int32_t kernel, double eps,
-                           bltc_selector sel, double tol, int32_t fb_degree,
+                           bltc_selector sel, double tol, int32_t mode, int32_t fb_degree,
                            double fb_theta, const bltc_options* opt, double* out,
                            int32_t* choice, int64_t* stats, double* judge,
                            void* stream);

@@ -94,7 +94,7 @@ def load():
         "bltc_selector_info": (ctypes.c_int, [P, P, P, P]),
         "bltc_batch_features": (ctypes.c_int, [P, P, I32, D, D, P, P]),
         "bltc_batch_counts": (ctypes.c_int, [P, P, D, P, P, P]),
-        "bltc_evaluate_adaptive": (ctypes.c_int, [P, P, I32, D, P, D, I32, D, P, P, P, P, P, P]),
+        "bltc_evaluate_adaptive": (ctypes.c_int, [P, P, I32, D, P, D, I32, I32, D, P, P, P, P, P, P]),
         "bltc_profile_enable": (ctypes.c_int, [I32]),
         "bltc_profile_read": (ctypes.c_int, [P, P, I32]),
         "bltc_direct": (ctypes.c_int, [P, P, P, I64, P, I64, P, P, P, I64, P, I32,
@@ -515,8 +515,11 @@ class Selector:
     __del__ = close
 
 
+SELECT_MODES = {"batch": 0, "run": 1}
+
+
 def evaluate_adaptive(tree, targets, kernel, eps, selector, tol, fb_degree, fb_theta,
-                      precision="fp32_fp64acc", out=None):
+                      precision="fp32_fp64acc", out=None, mode="batch"):
     """Returns (out, choice per batch (candidate index, or -2 when the judge
     sent the batch to the fallback), stats [batches, distinct degrees, batches
     re-evaluated, 0], judge [error estimate before, after re-evaluation])."""
@@ -530,7 +533,8 @@ def evaluate_adaptive(tree, targets, kernel, eps, selector, tol, fb_degree, fb_t
     stats = np.zeros(4, np.int64)
     judge = np.zeros(2, np.float64)
     _check(load().bltc_evaluate_adaptive(tree._h, targets._h, KERNELS[kernel], float(eps),
-                                         selector._h, float(tol), int(fb_degree),
+                                         selector._h, float(tol), SELECT_MODES[mode],
+                                         int(fb_degree),
                                          float(fb_theta), ctypes.byref(o),
                                          ctypes.c_void_p(out.data_ptr()) if targets.m else None,
                                          _hp(choice), _hp(stats), _hp(judge), _stream()))

@@ -651,7 +651,7 @@ void ensure_selection_scratch(bltc_targets g, int64_t k, int64_t nth) {
     g->d_wt = dalloc<double>(nb);
     g->d_contrib = dalloc<double>(nb);
     g->d_part = dalloc<double>(bltc::alloc_blocks(nb) * kLamGrid * 2);
-    g->d_sums = dalloc<double>(kLamGrid * 2);
+    g->d_sums = dalloc<double>(2 * std::max(kLamGrid, bltc::kMlpMaxOut));
     g->d_lam = dalloc<double>(kLamGrid);
     // one judge sample per batch at a hashed position inside the batch
     std::vector<int32_t> sp(nb), sb(nb);
@@ -700,7 +700,7 @@ void judge_sums(bltc_targets g, int kernel, const double* out, double sums[2],
 
 // Evaluation with (n, theta) chosen per batch (see bltc_evaluate_adaptive).
 void evaluate_adaptive(bltc_tree t, bltc_targets g, int kernel, double eps,
-                       bltc_selector sel, double tol, int fb_degree, double fb_theta,
+                       bltc_selector sel, double tol, int mode, int fb_degree, double fb_theta,
                        const bltc_options& o, double* out, int32_t* choice_out,
                        int64_t* stats, double* judge, hipStream_t s) {
   const int64_t nb = g->nb;
@@ -754,6 +754,23 @@ void evaluate_adaptive(bltc_tree t, bltc_targets g, int kernel, double eps,
   judge_sums(g, kernel, nullptr, ws, s);
   const double wsum = ws[0];
 
+  if (mode == BLTC_SELECT_RUN) {
+    // 3. one candidate for the whole run: the cheapest whose predicted global
+    //    error sqrt(sum_b wn_b e_b^2) is within tau = tol 10^-margin_global
+    const double tau = tol * std::pow(10.0, -sel->margin_global);
+    const double inv_w = wsum > 0.0 ? 1.0 / (wsum * tau * tau) : 0.0;
+    hipchk(bltc::launch_cand_totals(g->d_e2, k, nb, g->d_cost, g->d_wt, inv_w, g->d_sums, s),
+           "candidate totals");
+    std::vector<double> tot(2 * (size_t)k);
+    d2h(tot.data(), g->d_sums, 2 * (size_t)k, s);
+    sync(s);
+    int best = -1, most = 0;
+    for (int j = 0; j < k; ++j) {
+      if (tot[2 * j + 1] < tot[2 * most + 1]) most = j;
+      if (tot[2 * j + 1] <= 1.0 && (best < 0 || tot[2 * j] < tot[2 * best])) best = j;
+    }
+    hipchk(bltc::launch_fill_i32(g->d_choice, nb, best >= 0 ? best : most, s), "choice");
+  } else {
   // 3. error budget: minimise the modelled cost subject to
   //    sum_b wn_b e_b^2 <= tau^2,  wn_b = w_b / sum w,  tau = tol 10^-margin,
   //    by the multiplier lam of cost + lam wn e^2 / tau^2 (two grid passes)
@@ -794,6 +811,7 @@ void evaluate_adaptive(bltc_tree t, bltc_targets g, int kernel, double eps,
   hipchk(bltc::launch_choose(g->d_e2, k, nb, g->d_cost, g->d_wt, inv_w,
                              lam_star, g->d_choice, s),
          "choose");
+  }
   std::vector<int32_t> choice(nb);
   d2h(choice.data(), g->d_choice, nb, s);
   sync(s);
@@ -911,10 +929,11 @@ void evaluate_adaptive(bltc_tree t, bltc_targets g, int kernel, double eps,
 }
 
 // Selector model file (little endian):
-//   char magic[8] "BLTCSEL1"; int32 version (3); int32 n_in (12);
+//   char magic[8] "BLTCSEL1"; int32 version (4); int32 n_in (12);
 //   int32 n_hidden (64); int32 k; int32 deg_min (separation rule, 0 = off);
 //   int32 cand_n[k]; double cand_theta[k];
-//   double theta_ref, cost_far, cost_row, cost_cluster, cost_near, margin;
+//   double theta_ref, cost_far, cost_row, cost_cluster, cost_near, margin,
+//   margin_global;
 //   float mean[12], stdv[12]; float params[bltc_mlp_params(k)];
 //   uint64 FNV-1a hash of all preceding bytes.
 uint64_t fnv1a(const unsigned char* p, size_t n) {
@@ -947,7 +966,7 @@ int load_selector(const char* path, bltc_selector sel) {
     return fail(BLTC_EMODEL, "selector model: bad magic or header");
   if (hdr[4] < 0 || hdr[4] > bltc::kMaxDegree)
     return fail(BLTC_EMODEL, "selector model: deg_min out of range");
-  if (hdr[0] != 3 || hdr[1] != bltc::kMlpIn || hdr[2] != bltc::kMlpHidden || hdr[3] < 1 ||
+  if (hdr[0] != 4 || hdr[1] != bltc::kMlpIn || hdr[2] != bltc::kMlpHidden || hdr[3] < 1 ||
       hdr[3] > bltc::kMlpMaxOut)
     return fail(BLTC_EMODEL, "selector model: unsupported version or dimensions");
   const int32_t k = hdr[3];
@@ -955,7 +974,7 @@ int load_selector(const char* path, bltc_selector sel) {
   sel->deg_min = hdr[4];
   sel->cand_n.resize(k);
   sel->cand_theta.resize(k);
-  double tail[6];
+  double tail[7];
   sel->mean.resize(bltc::kMlpIn);
   sel->stdv.resize(bltc::kMlpIn);
   sel->params.resize(bltc::mlp_params(k));
@@ -974,10 +993,11 @@ int load_selector(const char* path, bltc_selector sel) {
   sel->cost_clu = tail[3];
   sel->cost_near = tail[4];
   sel->margin = tail[5];
+  sel->margin_global = tail[6];
   for (int i = 1; i < 5; ++i)
     if (!(tail[i] >= 0.0 && tail[i] < 1e6))
       return fail(BLTC_EMODEL, "selector model: cost weight out of range");
-  if (!(tail[5] > -6.0 && tail[5] < 6.0))
+  if (!(tail[5] > -6.0 && tail[5] < 6.0) || !(tail[6] > -6.0 && tail[6] < 6.0))
     return fail(BLTC_EMODEL, "selector model: margin out of range");
   for (int j = 0; j < k; ++j)
     if (sel->cand_n[j] < 1 || sel->cand_n[j] > bltc::kMaxDegree ||
@@ -1474,7 +1494,7 @@ int bltc_batch_counts(bltc_tree t, bltc_targets g, double theta, int32_t* n_prox
 }
 
 int bltc_evaluate_adaptive(bltc_tree t, bltc_targets g, int32_t kernel, double eps,
-                           bltc_selector sel, double tol, int32_t fb_degree,
+                           bltc_selector sel, double tol, int32_t mode, int32_t fb_degree,
                            double fb_theta, const bltc_options* opt, double* out,
                            int32_t* choice, int64_t* stats, double* judge, void* stream) {
   if (!t || !g || !sel) return fail(BLTC_EINVAL, "NULL tree, targets or selector");
@@ -1482,6 +1502,8 @@ int bltc_evaluate_adaptive(bltc_tree t, bltc_targets g, int32_t kernel, double e
     return fail(BLTC_EINVAL, "the selector serves the Stokeslet and rotlet kernels");
   if (int rc = check_eval(kernel, eps, fb_degree, fb_theta)) return rc;
   if (!(tol > 0.0 && tol < 1.0)) return fail(BLTC_EINVAL, "tol must be in (0, 1)");
+  if (mode != BLTC_SELECT_BATCH && mode != BLTC_SELECT_RUN)
+    return fail(BLTC_EINVAL, "mode must be BLTC_SELECT_BATCH or BLTC_SELECT_RUN");
   bltc_options o;
   bltc_options_default(&o);
   if (opt) o = *opt;
@@ -1489,7 +1511,7 @@ int bltc_evaluate_adaptive(bltc_tree t, bltc_targets g, int32_t kernel, double e
   if (g->m > 0 && !device_ptr(out)) return fail(BLTC_EINVAL, "out must be a device pointer");
   if (!t->has_w) return fail(BLTC_ESTATE, "no weights: call bltc_compute_modified_weights first");
   return guarded([&] {
-    evaluate_adaptive(t, g, kernel, eps, sel, tol, fb_degree, fb_theta, o, out, choice,
+    evaluate_adaptive(t, g, kernel, eps, sel, tol, mode, fb_degree, fb_theta, o, out, choice,
                       stats, judge, (hipStream_t)stream);
     return (int)BLTC_OK;
   });

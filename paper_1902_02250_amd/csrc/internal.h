@@ -198,6 +198,9 @@ hipError_t launch_pred_err2(const float* Y, int k, int64_t nb, double* e2, hipSt
 hipError_t launch_alloc(const double* e2, int k, int64_t nb, const float* cost,
                         const double* wt, double inv_wsum, const double* lam, int G,
                         double* partial, double* sums, hipStream_t s);
+hipError_t launch_cand_totals(const double* e2, int k, int64_t nb, const float* cost,
+                              const double* wt, double inv_wsum, double* out, hipStream_t s);
+hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
 hipError_t launch_choose(const double* e2, int k, int64_t nb, const float* cost,
                          const double* wt, double inv_wsum, double lam, int32_t* choice,
                          hipStream_t s);
@@ -345,6 +348,7 @@ struct bltc_selector_s {
   std::vector<int32_t> cand_n;
   std::vector<double> cand_theta;
   double theta_ref = 0.7, margin = 0.0;
+  double margin_global = 0.0;  // margin of the whole-run choice
   int32_t deg_min = 0;         // separation rule the candidates use
   double cost_far = 1.0, cost_row = 0.0, cost_clu = 0.0, cost_near = 1.0;
   std::vector<float> mean, stdv, params;

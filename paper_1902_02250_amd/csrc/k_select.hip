@@ -221,6 +221,20 @@ __global__ __launch_bounds__(kSelThreads) void k_alloc(
   }
 }
 
+// Whole-run totals of every candidate j (one work group each): out[j] =
+// (sum over batches of cost[j][b], sum of wn_b e2[j][b]), wn_b = wt[b] inv_wsum.
+__global__ __launch_bounds__(kSelThreads) void k_cand_totals(
+    const double* __restrict__ E2, int64_t nb, const float* __restrict__ costs,
+    const double* __restrict__ wt, double inv_wsum, double* __restrict__ out) {
+  const int j = blockIdx.x;
+  double c = 0.0, e = 0.0;
+  for (int64_t b = threadIdx.x; b < nb; b += kSelThreads) {
+    c += (double)costs[(int64_t)j * nb + b];
+    e += wt[b] * inv_wsum * E2[(int64_t)j * nb + b];
+  }
+  block_sum2<kSelThreads>(c, e, out + 2 * j);
+}
+
 __global__ void k_choose(const double* __restrict__ E2, int k, int64_t nb,
                          const float* __restrict__ costs, const double* __restrict__ wt,
                          double inv_wsum, double lam, int32_t* __restrict__ choice) {
@@ -300,6 +314,11 @@ __global__ void k_need_degree(int64_t nb, const int32_t* __restrict__ pptr,
   }
 }
 
+__global__ void k_fill_i32(int32_t* __restrict__ p, int64_t n, int32_t v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
 __global__ void k_fill_u8(uint8_t* __restrict__ p, int64_t n, uint8_t v) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
@@ -332,6 +351,14 @@ hipError_t launch_alloc(const double* e2, int k, int64_t nb, const float* cost,
                      inv_wsum, lam, G, partial);
   hipLaunchKernelGGL(k_sum_columns, dim3((2 * G + 63) / 64), dim3(64), 0, s, partial, nblk,
                      2 * G, sums);
+  return hipGetLastError();
+}
+
+hipError_t launch_cand_totals(const double* e2, int k, int64_t nb, const float* cost,
+                              const double* wt, double inv_wsum, double* out, hipStream_t s) {
+  if (nb == 0 || k == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_cand_totals, dim3(k), dim3(kSelThreads), 0, s, e2, nb, cost, wt,
+                     inv_wsum, out);
   return hipGetLastError();
 }
 
@@ -377,6 +404,12 @@ hipError_t launch_need(const int32_t* bsel, int64_t nsel, const int32_t* pptr,
 hipError_t launch_cand_costs(const CostArgs& a, hipStream_t s) {
   if (a.nb == 0) return hipSuccess;
   hipLaunchKernelGGL(k_cand_costs, dim3((unsigned)((a.nb + 127) / 128)), dim3(128), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n, v);
   return hipGetLastError();
 }
 

@@ -55,14 +55,18 @@ def _fnv1a(data):
 
 
 def write_model(path, params, mean, std, margin, cand=CANDIDATES, theta_ref=THETA_REF,
-                costs=(COST_FAR, COST_ROW, COST_CLU, COST_NEAR), deg_min=DEG_MIN):
+                costs=(COST_FAR, COST_ROW, COST_CLU, COST_NEAR), deg_min=DEG_MIN,
+                margin_run=None):
+    """margin: of the per-batch budget allocation; margin_run: of the
+    whole-run choice (defaults to margin)."""
     k = len(cand)
     params = np.ascontiguousarray(params, dtype=np.float32)
     assert params.size == bltc_param_count(k)
-    body = b"BLTCSEL1" + struct.pack("<5i", 3, 12, 64, k, deg_min)
+    body = b"BLTCSEL1" + struct.pack("<5i", 4, 12, 64, k, deg_min)
     body += np.array([c[0] for c in cand], dtype="<i4").tobytes()
     body += np.array([c[1] for c in cand], dtype="<f8").tobytes()
-    body += struct.pack("<6d", theta_ref, *costs, margin)
+    body += struct.pack("<7d", theta_ref, *costs, margin,
+                        margin if margin_run is None else margin_run)
     body += np.asarray(mean, dtype="<f4").tobytes() + np.asarray(std, dtype="<f4").tobytes()
     body += params.astype("<f4").tobytes()
     body += struct.pack("<Q", _fnv1a(body))
@@ -290,6 +294,35 @@ def policy_summary(run, Y, tol, margin):
                 degrees=int(np.unique(np.array([CANDIDATES[j][0] for j in ch])).size))
 
 
+def run_choice(run, Y, tol, margin):
+    """The whole-run choice of bltc_evaluate_adaptive (mode "run"): the
+    cheapest candidate whose predicted global error is within tol 10^-margin,
+    else the one predicted most accurate.  Returns (candidate, realised
+    global error, modelled cost, best fixed candidate meeting tol or None,
+    its cost)."""
+    W = run["wt"].sum()
+    cost = batch_costs(run).sum(0)
+    pe = np.sqrt((run["wt"][:, None] * 10.0 ** (2.0 * Y.astype(np.float64))).sum(0) / W)
+    te = np.sqrt((run["wt"][:, None] * 10.0 ** (2.0 * run["T"].astype(np.float64))).sum(0) / W)
+    ok = np.where(pe <= tol * 10.0 ** (-margin))[0]
+    j = int(ok[cost[ok].argmin()]) if ok.size else int(pe.argmin())
+    good = np.where(te <= tol)[0]
+    b = int(good[cost[good].argmin()]) if good.size else None
+    return j, float(te[j]), float(cost[j]), b, (float(cost[b]) if b is not None else None)
+
+
+def calibrate_margin_run(val_runs, Ys, tols=(1e-4, 1e-5, 1e-6), grid=None):
+    """Smallest margin for which the whole-run choice keeps the realised
+    global error within tol on every held-out run and attainable tol."""
+    grid = np.arange(-0.5, 2.01, 0.05) if grid is None else grid
+    for m in grid:
+        if all(run_choice(r, Y, tol, m)[1] <= tol
+               for r, Y in zip(val_runs, Ys) for tol in tols
+               if run_choice(r, Y, tol, m)[3] is not None):
+            return float(m)
+    return float(grid[-1])
+
+
 def calibrate_margin(val_runs, Ys, tols=(1e-4, 1e-5, 1e-6), grid=None):
     """Smallest margin (most aggressive) for which the realised global error of
     the allocation stays within tol on every held-out run and tolerance that
@@ -375,16 +408,17 @@ def compare(workload, model=MODEL_PATH, tol=None, fb=(10, 0.6), reps=2, n=None, 
                rule_sweep={f"{c[0]},{c[1]}": [round(ruled[c][0], 3), ruled[c][1]]
                            for c in CANDIDATES},
                learned=[])
-    for mpath in models:
+    for mpath, mode in [(mp, md) for mp in models for md in ("batch", "run")]:
         sel = bltc.Selector(mpath)
 
         def lstep():
             tree.compute_weights(d_w, fb[0])
             return bltc.evaluate_adaptive(tree, tg, kernel, eps, sel, tol, fb[0], fb[1],
-                                          precision="fp32_fp64acc", out=out)
+                                          precision="fp32_fp64acc", out=out, mode=mode)
         ms_l, err_l, (_, choice, stats, judge) = timed(lstep)
         used = np.bincount(choice[choice >= 0], minlength=K)
-        r = dict(model=os.path.basename(mpath), ms=ms_l, err=err_l, batches=int(stats[0]),
+        r = dict(model=os.path.basename(mpath), mode=mode, ms=ms_l, err=err_l,
+                 batches=int(stats[0]),
                  degrees=int(stats[1]), judge_redo=int(stats[2]),
                  judge_estimate=[float(judge[0]), float(judge[1])],
                  top_choices=[(CANDIDATES[j], int(used[j]))
@@ -394,7 +428,7 @@ def compare(workload, model=MODEL_PATH, tol=None, fb=(10, 0.6), reps=2, n=None, 
         if best_r is not None:
             r["speedup_vs_best_fixed_rule"] = ruled[best_r][0] / ms_l
         res["learned"].append(r)
-        log(f"[selector] {workload} {r['model']}: learned {ms_l:.2f} ms E={err_l:.3e} "
+        log(f"[selector] {workload} {r['model']} ({mode}): learned {ms_l:.2f} ms E={err_l:.3e} "
             f"(judge {judge[0]:.2e} -> {judge[1]:.2e}, {int(stats[2])} redone, "
             f"{int(stats[1])} degrees); best fixed {best} "
             f"{fixed[best][0] if best else float('nan'):.2f} ms; best fixed with the rule "
@@ -444,9 +478,10 @@ def main(argv=None):
     Ys = [predict(params, mean, std, r["X"]) for r in val_runs]
     resid = np.concatenate([r["T"] - Y for r, Y in zip(val_runs, Ys)])
     margin = calibrate_margin(val_runs, Ys)
+    margin_run = calibrate_margin_run(val_runs, Ys)
     log(f"[selector] validation: rms residual {np.sqrt((resid ** 2).mean()):.3f} dex; "
-        f"calibrated margin {margin:.2f} dex")
-    write_model(args.model, params, mean, std, margin)
+        f"calibrated margins: per batch {margin:.2f} dex, whole run {margin_run:.2f} dex")
+    write_model(args.model, params, mean, std, margin, margin_run=margin_run)
     for tol in (1e-4, 1e-6):
         gains = []
         for r, Y in zip(val_runs, Ys):
@@ -459,6 +494,10 @@ def main(argv=None):
                 f"{s['best_fixed']} E={s['fixed_err']:.2e} cost={s['fixed_cost']:.3e}")
         log(f"[selector] tol {tol:.0e}: modelled cost gain over the best fixed candidate, "
             f"median {np.median(gains):.2f}, min {np.min(gains):.2f}, max {np.max(gains):.2f}")
+        rg = [rc[4] / rc[2] for rc in (run_choice(r, Y, tol, margin_run)
+                                       for r, Y in zip(val_runs, Ys)) if rc[3] is not None]
+        log(f"[selector] tol {tol:.0e}: whole-run choice, modelled cost relative to the best "
+            f"fixed candidate: median {np.median(rg):.2f}, min {np.min(rg):.2f}")
     return 0
 
 

@@ -169,3 +169,33 @@ def test_adaptive_is_per_batch_composition(torch, tmp_path, case):
         for b in np.where(choice == u)[0]:
             t = _targets_of(case["G"], b)
             assert np.array_equal(out[:, t], ref[:, t]), (u, b)
+
+
+@pytest.mark.parametrize("dist,kernel,tol", [("mixture", "stokeslet", 1e-5),
+                                             ("union", "rotlet", 1e-4)])
+def test_trained_selector_gain(torch, dist, kernel, tol):
+    """What the trained network gains over the method without it: on a
+    workload outside its training runs, the learned evaluation meets the
+    requested global error against the FP64 direct sum, at a modelled cost
+    well below that of the fixed fallback that would otherwise be used to be
+    safe at this tolerance (n = 10, theta = 0.6)."""
+    n = 150000
+    src = inputs.points(dist, n, 4242)
+    w = inputs.weights(n, 4242)
+    d_src, d_w = _d(torch, src), _d(torch, w)
+    T = bltc.Tree(d_src, 1000)
+    T.compute_weights(d_w, 10)
+    G = bltc.Targets(d_src, 64, 32, 512)
+    sel = bltc.Selector(selector.MODEL_PATH)
+    out, choice, stats, judge = bltc.evaluate_adaptive(T, G, kernel, 0.005, sel, tol, 10, 0.6)
+    idx = torch.from_numpy(inputs.sample_indices(n, 3000, 7)).cuda()
+    ref = bltc.direct(d_src, d_src, d_w, kernel, 0.005, idx=idx, precision="fp64")
+    err = (torch.linalg.norm(out[:, idx] - ref) / torch.linalg.norm(ref)).item()
+    assert err <= tol, (err, judge)
+    # modelled wave cost: learned choices (with the rule) against the fallback
+    costs = (selector.COST_FAR, selector.COST_ROW, selector.COST_CLU, selector.COST_NEAR)
+    c_l = bltc.batch_costs(T, G, selector.CANDIDATES, selector.DEG_MIN, costs).cpu().numpy()
+    c_fb = bltc.batch_costs(T, G, [(10, 0.6)], 0, costs).cpu().numpy()[0]
+    b = np.arange(choice.size)
+    learned = np.where(choice >= 0, c_l[np.maximum(choice, 0), b], c_fb).sum()
+    assert learned < 0.6 * c_fb.sum(), (learned, c_fb.sum())

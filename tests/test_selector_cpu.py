@@ -21,13 +21,13 @@ def test_model_layout(tmp_path):
     path, params = _write(tmp_path)
     raw = open(path, "rb").read()
     assert raw[:8] == b"BLTCSEL1"
-    assert struct.unpack("<5i", raw[8:28]) == (3, 12, 64, selector.K, selector.DEG_MIN)
+    assert struct.unpack("<5i", raw[8:28]) == (4, 12, 64, selector.K, selector.DEG_MIN)
     k = selector.K
     off = 28 + 4 * k + 8 * k
-    assert struct.unpack("<6d", raw[off:off + 48]) == (
+    assert struct.unpack("<7d", raw[off:off + 56]) == (
         selector.THETA_REF, selector.COST_FAR, selector.COST_ROW, selector.COST_CLU,
-        selector.COST_NEAR, 0.25)
-    assert len(raw) == off + 48 + 96 + 4 * params.size + 8
+        selector.COST_NEAR, 0.25, 0.25)
+    assert len(raw) == off + 56 + 96 + 4 * params.size + 8
     assert struct.unpack("<Q", raw[-8:])[0] == selector._fnv1a(raw[:-8])
     assert bltc.mlp_params(k) == params.size
 
@@ -45,7 +45,7 @@ def test_loader_rejects_damage(tmp_path):
     bad = tmp_path / "bad.bin"
     for mutate in (lambda b: b.__setitem__(100, b[100] ^ 1),      # checksum
                    lambda b: b.__setitem__(0, ord("X")),         # magic
-                   lambda b: b.__setitem__(8, 4)):               # version
+                   lambda b: b.__setitem__(8, 5)):               # version
         b = bytearray(raw)
         mutate(b)
         bad.write_bytes(bytes(b))
