@@ -30,8 +30,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 # Algorithmic flops per kernel evaluation (FMA = 2, rsqrt = 1), from the
-# formulas of eq. Velocity_1 and eq. MRS_2.
-FLOPS = {"stokeslet": 32, "rotlet": 58}
+# formulas of eq. Velocity_1 and eq. MRS_2 (both parts together for "full").
+FLOPS = {"stokeslet": 32, "rotlet": 58, "full": 92}
 # MI355X published vector peaks (TFLOP/s).
 PEAK = {"fp32": 157.3, "fp64": 78.6}
 
@@ -99,7 +99,7 @@ def main():
     ap.add_argument("--precision", default="fp32_fp64acc",
                     choices=["fp64", "fp32_fp64acc", "fp32_kahan"])
     ap.add_argument("--degree", type=int, default=None)
-    ap.add_argument("--kernel", default=None, choices=["stokeslet", "rotlet"])
+    ap.add_argument("--kernel", default=None, choices=["stokeslet", "rotlet", "full"])
     ap.add_argument("--theta", type=float, default=None)
     ap.add_argument("--batch-size", type=int, default=64)
     ap.add_argument("--order-leaf", type=int, default=32)
@@ -152,6 +152,9 @@ def main():
         f"degree={degree} theta={theta} leaf={cfg['leaf']} precision={args.precision}")
     src = inputs.points(cfg["dist"], n, cfg["seed"])
     w = inputs.weights_for(cfg["dist"], n, cfg["seed"])
+    wd = bltc.WDIM[kernel]
+    if w.shape[0] != wd:   # a kernel other than the workload's own
+        w = w[:wd] if w.shape[0] > wd else inputs.weights(n, cfg["seed"], wd)
     dev = torch.device("cuda:0")
     d_src = torch.from_numpy(src).to(dev)
     d_w = torch.from_numpy(w).to(dev)
@@ -200,9 +203,19 @@ def main():
     idx = inputs.sample_indices(n, k, cfg["seed"] + 11)
     d_idx = torch.from_numpy(idx).to(dev)
     ref = bltc.direct(d_src, d_src, d_w, kernel, eps, idx=d_idx, precision="fp64")
-    got = out[:, d_idx]
-    err = (torch.linalg.norm(got - ref) / torch.linalg.norm(ref)).item()
-    log(f"[bench] rel L2 error vs FP64 direct on {k} targets: {err:.3e}")
+    def errors(got):
+        """E over every output row; for six rows also over u (the velocity
+        of eq. error) and over w alone."""
+        e = {"rel_l2_err": (torch.linalg.norm(got - ref) / torch.linalg.norm(ref)).item()}
+        if got.shape[0] == 6:
+            for key, r in (("rel_l2_err_u", slice(0, 3)), ("rel_l2_err_w", slice(3, 6))):
+                e[key] = (torch.linalg.norm(got[r] - ref[r]) / torch.linalg.norm(ref[r])).item()
+        return e
+
+    errs = errors(out[:, d_idx])
+    err = errs["rel_l2_err"]
+    log(f"[bench] rel L2 error vs FP64 direct on {k} targets: " +
+        ", ".join(f"{a} {b:.3e}" for a, b in errs.items()))
 
     ev_ms = prof["eval"][0] / max(prof["eval"][1], 1)
     flops = inter * FLOPS.get(kernel, 32)
@@ -224,7 +237,7 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64" if args.precision == "fp64" else "f32",
         "data": "synthetic",
-        "config": {"workload": (f"{args.workload}: N={n} {cfg['dist']} in [-1,1]^3, {kernel} "
+        "config": {"workload": (f"{args.workload}: N={n} {cfg['dist']}, {kernel} "
                                 f"eps={eps}, n={degree}, theta={theta}, N0={cfg['leaf']}, "
                                 f"{args.precision}, batch {args.batch_size}"),
                    "n": n, "kernel": kernel, "eps": eps, "degree": degree, "theta": theta,
@@ -234,7 +247,7 @@ def main():
         "eval_s": round(ms * 1e-3, 6),
         "interactions_per_step": inter,
         "direct_equivalent_per_s": float(n) * n / (ms * 1e-3),
-        "rel_l2_err": err, "err_sample": k,
+        **errs, "err_sample": k,
         "stage_ms": {s: round(v[0] / max(v[1], 1), 4) for s, v in prof.items()},
         "build_ms": {"tree": round((t1 - t0) * 1e3, 1), "targets": round((t2 - t1) * 1e3, 1)},
         "roofline": roof,
@@ -259,10 +272,11 @@ def main():
         e1.record()
         torch.cuda.synchronize()
         xms = e0.elapsed_time(e1) / xs
-        xerr = (torch.linalg.norm(out[:, d_idx] - ref) / torch.linalg.norm(ref)).item()
+        xerrs = errors(out[:, d_idx])
+        xerr = xerrs["rel_l2_err"]
         xp, xd = bltc.counts(tree, tg, dn, th, dm)
         extra.append({"degree": dn, "theta": th, "deg_min": dm, "steps": xs,
-                      "ms_per_step": round(xms, 4), "rel_l2_err": xerr,
+                      "ms_per_step": round(xms, 4), **xerrs,
                       "interactions_per_step": xp + xd,
                       "interactions_per_s": (xp + xd) / (xms * 1e-3)})
         log(f"[bench] n={dn} theta={th} deg_min={dm}: {xms:.3f} ms/step, E={xerr:.3e}")

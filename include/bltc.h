@@ -1,7 +1,7 @@
 /*
  * bltc.h - C ABI of the MI355X (gfx950) barycentric Lagrange treecode
  * (Wang, Krasny and Tlupova, arXiv:1902.02250): the evaluation phase for the
- * 3D regularized Stokeslet and rotlet kernels.
+ * 3D regularized Stokeslet and rotlet kernels (each alone, or both together).
  *
  * What is computed (eq. N-body): for targets x_i and sources y_j with vector
  * weights f_j,
@@ -20,6 +20,10 @@
  *   BLTC_STOKESLET  f (3) -> u (3):  u = sum f H1 + (f.d) d H2  (eq. Velocity_1)
  *   BLTC_ROTLET     n (3) -> (u, w) (6): the torque terms of eq. MRS_2,
  *                   u = sum 1/2 (n x d) Q,  w = sum 1/4 n D1 + 1/4 (n.d) d D2
+ *   BLTC_FULL       (f, n) (6) -> (u, w) (6): both parts of eq. MRS_2,
+ *                   u = sum f H1 + (f.d) d H2 + 1/2 (n x d) Q,
+ *                   w = sum 1/2 (f x d) Q + 1/4 n D1 + 1/4 (n.d) d D2
+ *                   (weights: force rows then torque rows)
  *   BLTC_POLY       f (3) -> u (3): u_c = sum (poly_c + x.y)^poly_p f_c, a
  *                   polynomial test kernel; FP64 only
  * with d = x - y and the regularisation eps.  When eps = 0 a pair at zero
@@ -29,9 +33,10 @@
  * Conventions for every entry point:
  *   - Point, weight and output arrays are HIP DEVICE pointers unless the
  *     name or comment says "host".  Points are three separate FP64 arrays
- *     (x, y, z).  Weights are FP64 [3][n], component-major; outputs are
- *     FP64 [odim][m], component-major, in the caller's target order
- *     (odim = 3, or 6 for the rotlet: u rows then w rows).
+ *     (x, y, z).  Weights are FP64 [wdim][n], component-major (wdim = 3,
+ *     or 6 for BLTC_FULL); outputs are FP64 [odim][m], component-major, in
+ *     the caller's target order (odim = 3, or 6 for the rotlet and
+ *     BLTC_FULL: u rows then w rows).
  *   - The caller owns every buffer it passes; the library owns its handles
  *     and the device memory inside them, freed by the matching destroy call.
  *   - `stream` is a hipStream_t (NULL = the default stream).  Work is queued
@@ -63,7 +68,7 @@ typedef enum {
   BLTC_EMODEL = 5    /* a selector model file is missing or malformed */
 } bltc_status;
 
-enum { BLTC_STOKESLET = 0, BLTC_ROTLET = 1, BLTC_POLY = 100 };
+enum { BLTC_STOKESLET = 0, BLTC_ROTLET = 1, BLTC_FULL = 2, BLTC_POLY = 100 };
 
 enum {
   BLTC_FP64 = 0,          /* FP64 everywhere */
@@ -128,17 +133,18 @@ int bltc_tree_export(bltc_tree t, int64_t* perm, double* box, double* center,
                      int64_t* pbegin, int64_t* pend, int32_t* level);
 
 /* Upward pass (eq. modified_weights, Algorithm 1): gathers the weights w
- * (FP64 [3][n], caller order) into tree order and computes, for every
+ * (FP64 [wdim][n], caller order; wdim 3, or 6 for BLTC_FULL) into tree
+ * order and computes, for every
  * cluster, its Chebyshev grid (degree+1 points per axis mapped to the box)
  * and modified weights fhat_k = sum_{j in C} L_k1(y_j1) L_k2(y_j2) L_k3(y_j3) f_j,
  * the Lagrange values taken in barycentric form with the exact-hit rule of
  * Algorithm 1 (a coordinate equal to a grid point gets the Kronecker delta).
  * Computed in FP64; kept in FP64 and FP32 for the evaluation.  Calling again
  * replaces the weights and drops modified weights of other degrees. */
-int bltc_compute_modified_weights(bltc_tree t, const double* w, int32_t degree,
-                                  void* stream);
+int bltc_compute_modified_weights(bltc_tree t, const double* w, int32_t wdim,
+                                  int32_t degree, void* stream);
 /* Host copy of the modified weights of one degree (synchronises):
- * fhat[nn][3][degree+1][degree+1][degree+1] (k3 fastest) and, if grid is
+ * fhat[nn][wdim][degree+1][degree+1][degree+1] (k3 fastest) and, if grid is
  * not NULL, grid[nn][3][degree+1]. */
 int bltc_modified_weights_export(bltc_tree t, int32_t degree, double* fhat,
                                  double* grid);
@@ -180,8 +186,9 @@ int bltc_host_batches(const double* hx, const double* hy, const double* hz,
  * interaction lists), then evaluates the far field against the Chebyshev
  * grid points and modified weights of `degree` and the near field against
  * leaf particles, and writes out[odim][m] in caller order.  The modified
- * weights of `degree` must have been computed (else BLTC_ESTATE).  The list
- * sizes are read back once (synchronises on `stream`). */
+ * weights of `degree` must have been computed with the kernel's wdim (else
+ * BLTC_ESTATE).  The list sizes are read back once (synchronises on
+ * `stream`). */
 int bltc_evaluate_tree(bltc_tree t, bltc_targets g, int32_t kernel, double eps,
                        int32_t degree, double theta, const bltc_options* opt,
                        double* out, void* stream);
@@ -293,13 +300,15 @@ int bltc_selector_info(bltc_selector sel, int32_t* k, int32_t* cand_n,
 
 /* Evaluation with a learned (n, theta) per batch, aiming at a relative L2
  * error tol over all targets (the paper's eq. error).  Not in the paper,
- * which fixes (theta, n) for a run (Section 6).
+ * which fixes (theta, n) for a run (Section 6).  Kernels BLTC_STOKESLET and
+ * BLTC_ROTLET (the kernels the network's features describe).
  *  1. The network predicts e_b(j), the relative error of batch b under each
  *     candidate j; bltc_batch_costs gives its modelled wave cost with the
  *     model's cost weights, under the model's separation rule (deg_min).
- *  2. The judge: one target per batch is evaluated with the fallback
- *     treecode (fb_degree, fb_theta); w_b = targets_b |u_fb|^2 estimates the
- *     batch's share of the reference norm.
+ *  2. The judge: one target in every second batch is evaluated with the
+ *     fallback treecode (fb_degree, fb_theta); w_b = targets_b |u_fb|^2
+ *     (the sample of b's pair of batches) estimates the batch's share of the
+ *     reference norm.
  *  3. mode BLTC_SELECT_BATCH: the batches share the error budget: the
  *     choice minimises the total cost subject to
  *     sum_b w_b e_b^2 <= tau^2 sum_b w_b, tau = tol 10^-margin, through the
@@ -311,9 +320,11 @@ int bltc_selector_info(bltc_selector sel, int32_t* k, int32_t* cand_n,
  *     modified weights of every degree in use, for the clusters that use it
  *     only; evaluation grouped by the batches' degrees, the groups running
  *     concurrently.
- *  5. The judge's estimate E^2 = sum_b targets_b |u - u_fb|^2 / sum_b w_b at
- *     the samples; if E > tol, every batch whose term exceeds tol^2 sum w / nb
- *     is evaluated again with the fallback.
+ *  5. The judge's estimate E^2 = sum_i G_i |u - u_fb|^2 / sum_i G_i |u_fb|^2
+ *     over the samples (G_i the targets the sample stands for); when it
+ *     exceeds tol^2, the samples with the largest terms, just enough of
+ *     them to bring the estimate to (0.8 tol)^2, have their batches evaluated
+ *     again with the fallback.
  * choice (host int32 [nb], may be NULL): candidate index, or -2 for a batch
  * the judge sent to the fallback.  stats (host int64 [4], may be NULL):
  * batches, distinct degrees, batches re-evaluated, 0.  judge (host double

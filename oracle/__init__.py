@@ -19,8 +19,9 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "liboracle.so")
 _SOURCES = ["kernels.c", "direct.c", "tree.c", "bary.c", "treecode.c"]
-KERNELS = {"stokeslet": 0, "rotlet": 1, "poly": 100}
-ODIM = {"stokeslet": 3, "rotlet": 6, "poly": 3}
+KERNELS = {"stokeslet": 0, "rotlet": 1, "full": 2, "poly": 100}
+ODIM = {"stokeslet": 3, "rotlet": 6, "full": 6, "poly": 3}
+WDIM = {"stokeslet": 3, "rotlet": 3, "full": 6, "poly": 3}
 
 _lib = None
 

@@ -15,11 +15,12 @@
 static void direct_one(int kernel, double eps, int poly_p, double poly_c,
                        const double x[3], const double* sx, const double* sy,
                        const double* sz, int64_t n, const double* w,
-                       int compensated, double* acc, int odim) {
+                       int compensated, double* acc, int wdim, int odim) {
   double sum[6] = {0}, comp[6] = {0};
   for (int64_t j = 0; j < n; ++j) {
     double y[3] = {sx[j], sy[j], sz[j]};
-    double f[3] = {w[j], w[n + j], w[2 * n + j]};
+    double f[6];
+    for (int k = 0; k < wdim; ++k) f[k] = w[k * n + j];
     double term[6] = {0};
     orc_pair(kernel, eps, poly_p, poly_c, x, y, f, term);
     for (int c = 0; c < odim; ++c) {
@@ -49,7 +50,7 @@ int orc_direct(int kernel, double eps, int poly_p, double poly_c,
     double x[3] = {tx[i], ty[i], tz[i]};
     double acc[6];
     direct_one(kernel, eps, poly_p, poly_c, x, sx, sy, sz, n, w, compensated,
-               acc, odim);
+               acc, wdim, odim);
     for (int c = 0; c < odim; ++c) out[c * m + i] = acc[c];
   }
   return 0;
@@ -67,7 +68,7 @@ int orc_direct_subset(int kernel, double eps, int poly_p, double poly_c,
     int64_t i = idx[q];
     double x[3] = {tx[i], ty[i], tz[i]};
     double acc[6];
-    direct_one(kernel, eps, poly_p, poly_c, x, sx, sy, sz, n, w, 0, acc, odim);
+    direct_one(kernel, eps, poly_p, poly_c, x, sx, sy, sz, n, w, 0, acc, wdim, odim);
     for (int c = 0; c < odim; ++c) out[c * k + q] = acc[c];
   }
   return 0;

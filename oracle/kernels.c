@@ -15,6 +15,10 @@
  *   rotlet (torque terms of eq. MRS_2 with zero force):
  *                                   u += 1/2 (n x d) Q
  *                                   w += 1/4 n D1 + 1/4 (n.d) d D2
+ *   Stokeslet + rotlet (eq. MRS_2, weights (f, n), outputs (u, w)):
+ *                                   u += f H1 + (f.d) d H2 + 1/2 (n x d) Q
+ *                                   w += 1/2 (f x d) Q + 1/4 n D1
+ *                                        + 1/4 (n.d) d D2
  *   polynomial test kernel:          u_c += (poly_c + x.y)^poly_p f_c
  * When eps = 0 and r = 0 the singular self term is omitted (Section 1: the
  * i = j term is dropped only for a singular kernel).
@@ -43,6 +47,7 @@ int orc_kernel_dims(int kernel, int* wdim, int* odim) {
   switch (kernel) {
     case ORC_STOKESLET: *wdim = 3; *odim = 3; return 0;
     case ORC_ROTLET:    *wdim = 3; *odim = 6; return 0;
+    case ORC_FULL:      *wdim = 6; *odim = 6; return 0;
     case ORC_POLY:      *wdim = 3; *odim = 3; return 0;
     default: return -1;
   }
@@ -69,6 +74,21 @@ void orc_pair(int kernel, double eps, int poly_p, double poly_c,
   if (kernel == ORC_STOKESLET) {
     double fd = f[0] * d[0] + f[1] * d[1] + f[2] * d[2];
     for (int a = 0; a < 3; ++a) out[a] += f[a] * m[0] + fd * d[a] * m[1];
+  } else if (kernel == ORC_FULL) { /* f[0:3] force, f[3:6] torque */
+    const double* fo = f;
+    const double* to = f + 3;
+    double fd = fo[0] * d[0] + fo[1] * d[1] + fo[2] * d[2];
+    double nd = to[0] * d[0] + to[1] * d[1] + to[2] * d[2];
+    double nxd[3] = {to[1] * d[2] - to[2] * d[1],
+                     to[2] * d[0] - to[0] * d[2],
+                     to[0] * d[1] - to[1] * d[0]};
+    double fxd[3] = {fo[1] * d[2] - fo[2] * d[1],
+                     fo[2] * d[0] - fo[0] * d[2],
+                     fo[0] * d[1] - fo[1] * d[0]};
+    for (int a = 0; a < 3; ++a)
+      out[a] += fo[a] * m[0] + fd * d[a] * m[1] + 0.5 * nxd[a] * m[2];
+    for (int a = 0; a < 3; ++a)
+      out[3 + a] += 0.5 * fxd[a] * m[2] + 0.25 * to[a] * m[3] + 0.25 * nd * d[a] * m[4];
   } else { /* ORC_ROTLET: f holds the torque n */
     double nxd[3] = {f[1] * d[2] - f[2] * d[1],
                      f[2] * d[0] - f[0] * d[2],

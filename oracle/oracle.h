@@ -31,7 +31,7 @@
 extern "C" {
 #endif
 
-enum { ORC_STOKESLET = 0, ORC_ROTLET = 1, ORC_POLY = 100 };
+enum { ORC_STOKESLET = 0, ORC_ROTLET = 1, ORC_FULL = 2, ORC_POLY = 100 };
 
 /* ---- kernels.c ---------------------------------------------------------- */
 /* H1, H2, Q, D1, D2 at squared distance r2 (eq. MRS_kernels). */
@@ -110,7 +110,7 @@ int orc_modified_weights(const orc_tree* t, const double* x, const double* y,
 /* ---- treecode.c --------------------------------------------------------- */
 #define ORC_MAX_DEGREE 16
 typedef struct {
-  int kernel;          /* ORC_STOKESLET, ORC_ROTLET, ORC_POLY */
+  int kernel;          /* ORC_STOKESLET, ORC_ROTLET, ORC_FULL, ORC_POLY */
   double eps;          /* MRS regularisation */
   int poly_p;          /* polynomial kernel degree */
   double poly_c;       /* polynomial kernel constant */

@@ -105,14 +105,16 @@ static void compute_velocity(const walk_ctx* c, const double x[3],
         for (int k3 = 0; k3 < n1; ++k3) {
           int64_t kk = ((int64_t)k1 * n1 + k2) * n1 + k3;
           double s[3] = {g[k1], g[n1 + k2], g[2 * n1 + k3]};
-          double f[3] = {fq[kk], fq[nk + kk], fq[2 * nk + kk]};
+          double f[6];
+          for (int k = 0; k < c->wdim; ++k) f[k] = fq[k * nk + kk];
           orc_pair(p->kernel, p->eps, p->poly_p, p->poly_c, x, s, f, acc);
         }
     *np += nk;
   } else if (c->child_count[q] == 0) {
     for (int64_t j = c->pbegin[q]; j < c->pend[q]; ++j) {
       double y[3] = {c->ys[j], c->ys[c->n + j], c->ys[2 * c->n + j]};
-      double f[3] = {c->ws[j], c->ws[c->n + j], c->ws[2 * c->n + j]};
+      double f[6];
+      for (int k = 0; k < c->wdim; ++k) f[k] = c->ws[k * c->n + j];
       orc_pair(p->kernel, p->eps, p->poly_p, p->poly_c, x, y, f, acc);
     }
     *nd += c->pend[q] - c->pbegin[q];

@@ -19,8 +19,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "lib", "libbltc.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "bltc.h")
 
-KERNELS = {"stokeslet": 0, "rotlet": 1, "poly": 100}
-ODIM = {"stokeslet": 3, "rotlet": 6, "poly": 3}
+KERNELS = {"stokeslet": 0, "rotlet": 1, "full": 2, "poly": 100}
+ODIM = {"stokeslet": 3, "rotlet": 6, "full": 6, "poly": 3}
+WDIM = {"stokeslet": 3, "rotlet": 3, "full": 6, "poly": 3}
 PRECISIONS = {"fp64": 0, "fp32_fp64acc": 1, "fp32_kahan": 2}
 STATUS = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "ESTATE", 5: "EMODEL"}
 
@@ -69,7 +70,7 @@ def load():
         "bltc_tree_destroy": (ctypes.c_int, [P]),
         "bltc_tree_info": (ctypes.c_int, [P, P, P]),
         "bltc_tree_export": (ctypes.c_int, [P] * 10),
-        "bltc_compute_modified_weights": (ctypes.c_int, [P, P, I32, P]),
+        "bltc_compute_modified_weights": (ctypes.c_int, [P, P, I32, I32, P]),
         "bltc_modified_weights_export": (ctypes.c_int, [P, I32, P, P]),
         "bltc_build_targets": (ctypes.c_int, [P, P, P, I64, I32, I32, I64, P, P]),
         "bltc_targets_destroy": (ctypes.c_int, [P]),
@@ -184,12 +185,15 @@ class Tree:
         self.nnodes, self.depth = nn.value, dep.value
 
     def compute_weights(self, w, degree):
-        _dev(w, "w", 3)
-        if w.shape[1] != self.n:
-            raise ValueError("weights must match the source count")
+        """w: (3, n), or (6, n) force and torque rows for the full kernel."""
+        _dev(w, "w")
+        if w.dim() != 2 or w.shape[0] not in (3, 6) or w.shape[1] != self.n:
+            raise ValueError("weights must have shape (3, n) or (6, n) for the n sources")
         ptr = ctypes.c_void_p(w.data_ptr()) if self.n else None
-        _check(load().bltc_compute_modified_weights(self._h, ptr, int(degree), _stream()))
+        _check(load().bltc_compute_modified_weights(self._h, ptr, int(w.shape[0]), int(degree),
+                                                    _stream()))
         self._w = w
+        self.wdim = int(w.shape[0])
 
     def export(self):
         nn = self.nnodes
@@ -205,7 +209,7 @@ class Tree:
 
     def weights_export(self, degree):
         n1 = degree + 1
-        f = np.zeros((self.nnodes, 3, n1, n1, n1))
+        f = np.zeros((self.nnodes, getattr(self, "wdim", 3), n1, n1, n1))
         g = np.zeros((self.nnodes, 3, n1))
         _check(load().bltc_modified_weights_export(self._h, int(degree), _hp(f), _hp(g)))
         return f, g
@@ -280,7 +284,7 @@ def evaluate(tgt, src, w, kernel, eps, degree, theta, leaf_max, precision="fp64"
     torch = _torch()
     tx, ty, tz, m = _rows(tgt, "tgt")
     sx, sy, sz, n = _rows(src, "src")
-    _dev(w, "w", 3)
+    _dev(w, "w", WDIM[kernel])
     od = ODIM[kernel]
     if out is None:
         out = torch.empty((od, m), dtype=torch.float64, device="cuda")
@@ -323,7 +327,7 @@ def direct(tgt, src, w, kernel, eps, idx=None, precision="fp64", poly_p=2, poly_
     torch = _torch()
     tx, ty, tz, m = _rows(tgt, "tgt")
     sx, sy, sz, n = _rows(src, "src")
-    _dev(w, "w", 3)
+    _dev(w, "w", WDIM[kernel])
     if idx is not None:
         if idx.dtype != torch.int64 or not idx.is_cuda or not idx.is_contiguous():
             raise TypeError("idx must be a contiguous int64 CUDA tensor")

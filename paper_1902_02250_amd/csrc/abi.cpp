@@ -12,6 +12,7 @@
 #include <mutex>
 #include <utility>
 #include <new>
+#include <numeric>
 #include <string>
 #include <vector>
 
@@ -119,10 +120,11 @@ void fetch(std::vector<double>& dst, const double* src, int64_t n,
            "hipMemcpyAsync");
 }
 
-int odim_of(int kernel) { return kernel == BLTC_ROTLET ? 6 : 3; }
+int odim_of(int kernel) { return kernel == BLTC_ROTLET || kernel == BLTC_FULL ? 6 : 3; }
+int wdim_of(int kernel) { return kernel == BLTC_FULL ? 6 : 3; }
 
 bool valid_kernel(int k) {
-  return k == BLTC_STOKESLET || k == BLTC_ROTLET || k == BLTC_POLY;
+  return k == BLTC_STOKESLET || k == BLTC_ROTLET || k == BLTC_FULL || k == BLTC_POLY;
 }
 
 int check_points(const double* x, const double* y, const double* z,
@@ -164,7 +166,7 @@ int check_eval(int kernel, double eps, int degree, double theta) {
 
 void kernel_scales(int kernel, double* su, double* sw) {
   const double c = 1.0 / (8.0 * 3.14159265358979323846);
-  if (kernel == BLTC_STOKESLET) { *su = c; *sw = c; }
+  if (kernel == BLTC_STOKESLET || kernel == BLTC_FULL) { *su = c; *sw = c; }
   else if (kernel == BLTC_ROTLET) { *su = 0.5 * c; *sw = 0.25 * c; }
   else { *su = 1.0; *sw = 1.0; }
 }
@@ -302,27 +304,28 @@ void ensure_degree(bltc_tree t, int degree, hipStream_t s, const uint8_t* need =
   const int64_t nk = (int64_t)n1 * n1 * n1;
   bltc_degree_data d;
   try {
+    const int wd = t->wdim;
     d.grid = dalloc<double>(nn * 3 * n1);
-    d.fhat64 = dalloc<double>(nn * 3 * nk);
-    d.p2p64 = dalloc<double>(nn * 3 * nk);
-    d.p2p32 = dalloc<float>(nn * 3 * nk);
+    d.fhat64 = dalloc<double>(nn * wd * nk);
+    d.p2p64 = dalloc<double>(nn * wd * nk);
+    d.p2p32 = dalloc<float>(nn * wd * nk);
     d.partial = need != nullptr;
     double tk[bltc::kMaxDegree + 1];
     bltc::cheb_points(degree, tk);
     StageTimer prep(BLTC_STAGE_PREP, s);
     hipchk(bltc::launch_grids(t->d_box, nn, degree, tk, d.grid, s), "grids");
     prep.stop();
-    const size_t want = (size_t)t->nchunks * 3 * nk;
+    const size_t want = (size_t)t->nchunks * wd * nk;
     if (want > t->partial_cap) {
       dfree(t->d_partial);
       t->d_partial = dalloc<double>(want);
       t->partial_cap = want;
     }
     StageTimer up(BLTC_STAGE_UPWARD, s);
-    hipchk(bltc::launch_upward(t->d_y, t->d_w64, t->n, t->d_chunks,
+    hipchk(bltc::launch_upward(t->d_y, t->d_w64, t->n, wd, t->d_chunks,
                                t->nchunks, d.grid, degree, need, t->d_partial, s),
            "upward");
-    hipchk(bltc::launch_upward_reduce(t->d_chunk_ptr, nn, t->d_partial, degree, need,
+    hipchk(bltc::launch_upward_reduce(t->d_chunk_ptr, nn, t->d_partial, degree, wd, need,
                                       d.fhat64, d.p2p64, d.p2p32, s),
            "upward reduce");
     up.stop();
@@ -333,15 +336,23 @@ void ensure_degree(bltc_tree t, int degree, hipStream_t s, const uint8_t* need =
   t->deg[degree] = d;
 }
 
-void set_weights(bltc_tree t, const double* w, hipStream_t s) {
+void set_weights(bltc_tree t, const double* w, int wdim, hipStream_t s) {
   for (auto& kv : t->deg) destroy_degree(kv.second);
   t->deg.clear();
+  t->has_w = false;
+  if (t->d_w64 && t->wdim != wdim) {
+    dfree(t->d_w64);
+    dfree(t->d_w32);
+    t->d_w64 = nullptr;
+    t->d_w32 = nullptr;
+  }
+  t->wdim = wdim;
   if (!t->d_w64) {
-    t->d_w64 = dalloc<double>(3 * t->n);
-    t->d_w32 = dalloc<float>(3 * t->n);
+    t->d_w64 = dalloc<double>(wdim * t->n);
+    t->d_w32 = dalloc<float>(wdim * t->n);
   }
   StageTimer prep(BLTC_STAGE_PREP, s);
-  hipchk(bltc::launch_gather_weights(w, t->d_perm, t->n, t->d_w64, t->d_w32, s),
+  hipchk(bltc::launch_gather_weights(w, t->d_perm, t->n, wdim, t->d_w64, t->d_w32, s),
          "gather weights");
   prep.stop();
   t->has_w = true;
@@ -358,7 +369,7 @@ void destroy_targets(bltc_targets g) {
   dfree(g->d_feat); dfree(g->d_Y); dfree(g->d_pc); dfree(g->d_sc);
   dfree(g->d_choice); dfree(g->d_bmap); dfree(g->d_theta_b); dfree(g->d_spos);
   dfree(g->d_sbatch); dfree(g->d_gflag); dfree(g->d_ufb);
-  dfree(g->d_wt); dfree(g->d_contrib); dfree(g->d_part); dfree(g->d_sums); dfree(g->d_lam);
+  dfree(g->d_wt); dfree(g->d_usq); dfree(g->d_contrib); dfree(g->d_part); dfree(g->d_sums); dfree(g->d_lam);
   dfree(g->d_cost); dfree(g->d_e2); dfree(g->d_candT); dfree(g->d_candn);
   delete g;
 }
@@ -653,18 +664,23 @@ void ensure_selection_scratch(bltc_targets g, int64_t k, int64_t nth) {
     g->d_part = dalloc<double>(bltc::alloc_blocks(nb) * kLamGrid * 2);
     g->d_sums = dalloc<double>(2 * std::max(kLamGrid, bltc::kMlpMaxOut));
     g->d_lam = dalloc<double>(kLamGrid);
-    // one judge sample per batch at a hashed position inside the batch
-    std::vector<int32_t> sp(nb), sb(nb);
-    for (int64_t b = 0; b < nb; ++b) {
+    // one judge sample per kJudgeStride batches, at a hashed position inside
+    // the first batch of its group
+    const int64_t ns = (nb + bltc::kJudgeStride - 1) / bltc::kJudgeStride;
+    g->nsamp = (int32_t)ns;
+    g->d_usq = dalloc<double>(ns);
+    std::vector<int32_t> sp(ns), sb(ns);
+    for (int64_t i = 0; i < ns; ++i) {
+      const int64_t b = i * bltc::kJudgeStride;
       const int32_t b0 = g->host.bptr[b], cnt = g->host.bptr[b + 1] - b0;
       const uint32_t h = (uint32_t)(b * 2654435761ull >> 7);
-      sp[b] = b0 + (int32_t)(h % (uint32_t)cnt);
-      sb[b] = (int32_t)b;
+      sp[i] = b0 + (int32_t)(h % (uint32_t)cnt);
+      sb[i] = (int32_t)b;
     }
-    g->d_spos = dalloc<int32_t>(nb);
-    g->d_sbatch = dalloc<int32_t>(nb);
-    h2d(g->d_spos, sp.data(), nb, nullptr);
-    h2d(g->d_sbatch, sb.data(), nb, nullptr);
+    g->d_spos = dalloc<int32_t>(ns);
+    g->d_sbatch = dalloc<int32_t>(ns);
+    h2d(g->d_spos, sp.data(), ns, nullptr);
+    h2d(g->d_sbatch, sb.data(), ns, nullptr);
     sync(nullptr);
   }
   if (nb * k > g->ycap) {
@@ -690,9 +706,9 @@ void ensure_selection_scratch(bltc_targets g, int64_t k, int64_t nth) {
 // sample per batch; `out` NULL gives the weights only.
 void judge_sums(bltc_targets g, int kernel, const double* out, double sums[2],
                 hipStream_t s) {
-  hipchk(bltc::launch_judge((int)g->nb, g->d_bptr, g->d_spos, g->d_tperm, out, g->m,
-                            odim_of(kernel), g->d_ufb, g->d_wt, g->d_contrib, g->d_part,
-                            g->d_sums, s),
+  hipchk(bltc::launch_judge(g->nsamp, bltc::kJudgeStride, g->nb, g->d_bptr, g->d_spos,
+                            g->d_tperm, out, g->m, odim_of(kernel), g->d_ufb, g->d_usq,
+                            g->d_contrib, g->d_part, g->d_sums, s),
          "judge");
   d2h(sums, g->d_sums, 2, s);
   sync(s);
@@ -733,7 +749,7 @@ void evaluate_adaptive(bltc_tree t, bltc_targets g, int kernel, double eps,
   bltc::GuardArgs ga;
   ga.spos = g->d_spos;
   ga.sbatch = g->d_sbatch;
-  ga.ns = (int)nb;
+  ga.ns = g->nsamp;
   ga.tx = g->d_x;
   ga.m = g->m;
   ga.pptr = g->ls[1].ptr;
@@ -752,6 +768,8 @@ void evaluate_adaptive(bltc_tree t, bltc_targets g, int kernel, double eps,
   hipchk(bltc::launch_guard(kernel, fb_degree, ga, s), "judge samples");
   double ws[2];
   judge_sums(g, kernel, nullptr, ws, s);
+  hipchk(bltc::launch_batch_weights(nb, bltc::kJudgeStride, g->d_bptr, g->d_usq, g->d_wt, s),
+         "batch weights");
   const double wsum = ws[0];
 
   if (mode == BLTC_SELECT_RUN) {
@@ -894,25 +912,36 @@ void evaluate_adaptive(bltc_tree t, bltc_targets g, int kernel, double eps,
     for (hipEvent_t e : done) hipchk(hipStreamWaitEvent(s, e, 0), "hipStreamWaitEvent");
   }
 
-  // 5. the judge's estimate of the global error; when it exceeds tol, every
-  //    batch above an equal share of the budget is evaluated again with the
-  //    fallback, which brings the estimate within tol
+  // 5. the judge's estimate of the global error; when it exceeds tol, the
+  //    batches with the largest sampled errors are evaluated again with the
+  //    fallback until the estimate is at most 0.8 tol (the sampled estimate
+  //    reads up to about 15% low where the error sits in a few clustered
+  //    batches)
   double js[2];
   judge_sums(g, kernel, out, js, s);
   jd[0] = jd[1] = wsum > 0.0 ? std::sqrt(js[1] / wsum) : 0.0;
   if (js[1] > tol * tol * wsum) {
-    hipchk(bltc::launch_flag((int)nb, g->d_contrib, tol * tol * wsum / (double)nb, g->d_gflag,
-                             s),
-           "judge flags");
-    std::vector<int32_t> flag(nb);
-    d2h(flag.data(), g->d_gflag, nb, s);
+    // the fewest samples, largest terms first, whose removal brings the
+    // estimate to (0.8 tol)^2; their batches go to the fallback
+    const int ns = g->nsamp;
+    std::vector<double> c(ns);
+    d2h(c.data(), g->d_contrib, ns, s);
     sync(s);
+    std::vector<int32_t> ord(ns);
+    std::iota(ord.begin(), ord.end(), 0);
+    std::stable_sort(ord.begin(), ord.end(), [&](int32_t a, int32_t b) { return c[a] > c[b]; });
+    double rest = js[1];
     std::vector<int32_t> redo;
-    for (int64_t b = 0; b < nb; ++b)
-      if (flag[b]) {
+    for (int32_t i : ord) {
+      if (rest <= 0.64 * tol * tol * wsum) break;
+      rest -= c[i];
+      for (int64_t b = (int64_t)i * bltc::kJudgeStride;
+           b < std::min<int64_t>(nb, (int64_t)(i + 1) * bltc::kJudgeStride); ++b) {
         redo.push_back((int32_t)b);
         choice[b] = -2;
       }
+    }
+    std::sort(redo.begin(), redo.end());
     st[2] = (int64_t)redo.size();
     if (!redo.empty()) {
       h2d(g->d_bmap, redo.data(), redo.size(), s);
@@ -1097,16 +1126,17 @@ int bltc_tree_export(bltc_tree t, int64_t* perm, double* box, double* center,
   return BLTC_OK;
 }
 
-int bltc_compute_modified_weights(bltc_tree t, const double* w, int32_t degree,
-                                  void* stream) {
+int bltc_compute_modified_weights(bltc_tree t, const double* w, int32_t wdim,
+                                  int32_t degree, void* stream) {
   if (!t) return fail(BLTC_EINVAL, "NULL tree");
+  if (wdim != 3 && wdim != 6) return fail(BLTC_EINVAL, "wdim must be 3 or 6");
   if (degree < 1 || degree > bltc::kMaxDegree)
     return fail(BLTC_EINVAL, "degree must be in [1, 12]");
   if (t->n > 0 && !device_ptr(w))
     return fail(BLTC_EINVAL, "weights must be a device pointer");
   return guarded([&] {
     hipStream_t s = (hipStream_t)stream;
-    set_weights(t, w, s);
+    set_weights(t, w, wdim, s);
     ensure_degree(t, degree, s);
     return (int)BLTC_OK;
   });
@@ -1123,7 +1153,8 @@ int bltc_modified_weights_export(bltc_tree t, int32_t degree, double* fhat,
     const int n1 = degree + 1;
     hipchk(hipDeviceSynchronize(), "hipDeviceSynchronize");
     if (fhat)
-      hipchk(hipMemcpy(fhat, it->second.fhat64, sizeof(double) * nn * 3 * n1 * n1 * n1,
+      hipchk(hipMemcpy(fhat, it->second.fhat64,
+                       sizeof(double) * nn * t->wdim * n1 * n1 * n1,
                        hipMemcpyDeviceToHost), "hipMemcpy");
     if (grid)
       hipchk(hipMemcpy(grid, it->second.grid, sizeof(double) * nn * 3 * n1,
@@ -1224,6 +1255,8 @@ int bltc_evaluate_tree(bltc_tree t, bltc_targets g, int32_t kernel, double eps,
   if (int rc = check_options(&o, kernel)) return rc;
   if (g->m > 0 && !device_ptr(out)) return fail(BLTC_EINVAL, "out must be a device pointer");
   if (!t->has_w) return fail(BLTC_ESTATE, "no weights: call bltc_compute_modified_weights first");
+  if (t->wdim != wdim_of(kernel))
+    return fail(BLTC_ESTATE, "the tree's weights have the wrong number of components for this kernel");
   if (!t->deg.count(degree))
     return fail(BLTC_ESTATE, "modified weights of this degree are not computed");
   return guarded([&] {
@@ -1258,7 +1291,7 @@ int bltc_evaluate(const double* tx, const double* ty, const double* tz,
       build_tree(sx, sy, sz, n, leaf_max, s, t);
       g = new bltc_targets_s;
       build_targets(tx, ty, tz, m, o.batch_size, o.order_leaf, o.group_max, s, g);
-      set_weights(t, w, s);
+      set_weights(t, w, wdim_of(kernel), s);
       evaluate_tree(t, g, kernel, eps, degree, theta, o, out, s);
       sync(s);
     } catch (...) {
@@ -1510,6 +1543,8 @@ int bltc_evaluate_adaptive(bltc_tree t, bltc_targets g, int32_t kernel, double e
   if (int rc = check_options(&o, kernel)) return rc;
   if (g->m > 0 && !device_ptr(out)) return fail(BLTC_EINVAL, "out must be a device pointer");
   if (!t->has_w) return fail(BLTC_ESTATE, "no weights: call bltc_compute_modified_weights first");
+  if (t->wdim != wdim_of(kernel))
+    return fail(BLTC_ESTATE, "the tree's weights have the wrong number of components for this kernel");
   return guarded([&] {
     evaluate_adaptive(t, g, kernel, eps, sel, tol, mode, fb_degree, fb_theta, o, out, choice,
                       stats, judge, (hipStream_t)stream);

@@ -18,6 +18,7 @@ constexpr int kUpwardChunk = 2048;   // particles per upward-pass work group
 constexpr int kMlpIn = 12;           // selector network: features
 constexpr int kMlpHidden = 64;       // selector network: hidden width
 constexpr int kMlpMaxOut = 128;      // selector network: most candidates
+constexpr int kJudgeStride = 2;      // batches per judge sample
 // A proxy-list entry holds the cluster id in its low kDegShift bits and,
 // under the separation rule, the cluster's degree above them (0: the
 // evaluation's degree).
@@ -204,10 +205,12 @@ hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
 hipError_t launch_choose(const double* e2, int k, int64_t nb, const float* cost,
                          const double* wt, double inv_wsum, double lam, int32_t* choice,
                          hipStream_t s);
-hipError_t launch_judge(int ns, const int32_t* bptr, const int32_t* spos,
-                        const int32_t* tperm, const double* out, int64_t m, int od,
-                        const double* ufb, double* wt, double* contrib, double* partial,
-                        double* sums, hipStream_t s);
+hipError_t launch_judge(int ns, int stride, int64_t nb, const int32_t* bptr,
+                        const int32_t* spos, const int32_t* tperm, const double* out,
+                        int64_t m, int od, const double* ufb, double* usq, double* contrib,
+                        double* partial, double* sums, hipStream_t s);
+hipError_t launch_batch_weights(int64_t nb, int stride, const int32_t* bptr,
+                                const double* usq, double* wt, hipStream_t s);
 hipError_t launch_flag(int ns, const double* contrib, double thr, int32_t* flag,
                        hipStream_t s);
 hipError_t launch_need(const int32_t* bsel, int64_t nsel, const int32_t* pptr,
@@ -219,16 +222,16 @@ hipError_t launch_gather_points(const double* x, const double* y,
                                 const double* z, const int32_t* perm,
                                 int64_t n, double* out3, hipStream_t s);
 hipError_t launch_gather_weights(const double* w, const int32_t* perm,
-                                 int64_t n, double* w64, float* w32,
+                                 int64_t n, int wd, double* w64, float* w32,
                                  hipStream_t s);
 hipError_t launch_grids(const double* box, int64_t nn, int degree,
                         const double* unit_nodes, double* grid, hipStream_t s);
-hipError_t launch_upward(const double* ys, const double* w64, int64_t n,
+hipError_t launch_upward(const double* ys, const double* w64, int64_t n, int wd,
                          const int4* chunks, int64_t nchunks,
                          const double* grid, int degree, const uint8_t* need,
                          double* partial, hipStream_t s);
 hipError_t launch_upward_reduce(const int32_t* chunk_ptr, int64_t nn,
-                                const double* partial, int degree,
+                                const double* partial, int degree, int wd,
                                 const uint8_t* need, double* fhat64, double* p2p64,
                                 float* p2p32, hipStream_t s);
 hipError_t launch_lists(const ListArgs& a, bool fill, hipStream_t s);
@@ -282,7 +285,8 @@ struct bltc_tree_s {
   int2* d_kids = nullptr;
   // weights
   bool has_w = false;
-  double* d_w64 = nullptr;     // tree-ordered [3][n]
+  int32_t wdim = 3;            // weight components: 3, or 6 for force and torque
+  double* d_w64 = nullptr;     // tree-ordered [wdim][n]
   float* d_w32 = nullptr;
   std::map<int, bltc_degree_data> deg;
   // upward-pass chunks
@@ -331,8 +335,10 @@ struct bltc_targets_s {
   int32_t* d_sbatch = nullptr;
   int32_t* d_gflag = nullptr;  // [nb]
   double* d_ufb = nullptr;     // [nb][6]
-  double* d_wt = nullptr;      // [nb] judge weights
-  double* d_contrib = nullptr; // [nb] judge error contributions
+  int32_t nsamp = 0;           // judge samples (one per kJudgeStride batches)
+  double* d_usq = nullptr;     // [nsamp] |u_fb|^2 at the samples
+  double* d_wt = nullptr;      // [nb] batch weights targets_b |u_fb|^2
+  double* d_contrib = nullptr; // [nsamp] judge error contributions
   double* d_part = nullptr;    // [blocks][G][2] partial sums
   double* d_sums = nullptr;    // [G][2]
   double* d_lam = nullptr;     // [G]

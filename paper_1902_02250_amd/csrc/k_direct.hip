@@ -26,9 +26,10 @@ __global__ __launch_bounds__(kTile) void k_direct(
     double eps, int poly_p, double poly_c, double su, double sw,
     double* __restrict__ out) {
   constexpr int OD = Dims<KERN>::OD;
+  constexpr int WD = Dims<KERN>::WD;
   constexpr bool F64 = PREC == BLTC_FP64;
   using T = typename std::conditional<F64, double, float>::type;
-  __shared__ double sh[6][kTile];
+  __shared__ double sh[3 + WD][kTile];
   const int64_t i = (int64_t)blockIdx.x * kTile + threadIdx.x;
   const bool active = i < k;
   const int64_t ti = active ? (idx ? idx[i] : i) : 0;
@@ -44,9 +45,8 @@ __global__ __launch_bounds__(kTile) void k_direct(
       sh[0][threadIdx.x] = sx[j];
       sh[1][threadIdx.x] = sy[j];
       sh[2][threadIdx.x] = sz[j];
-      sh[3][threadIdx.x] = w[j];
-      sh[4][threadIdx.x] = w[n + j];
-      sh[5][threadIdx.x] = w[2 * n + j];
+#pragma unroll
+      for (int c = 0; c < WD; ++c) sh[3 + c][threadIdx.x] = w[c * n + j];
     }
     __syncthreads();
     const int cnt = (int)(n - s0 < kTile ? n - s0 : kTile);
@@ -69,8 +69,12 @@ __global__ __launch_bounds__(kTile) void k_direct(
         const T dy = (T)(y - sh[1][jj]);
         const T dz = (T)(z - sh[2][jj]);
         const T r2 = dz * dz + (dy * dy + (dx * dx + e2));
-        pair<KERN, ZEPS, T>(dx, dy, dz, r2, e2, (T)sh[3][jj], (T)sh[4][jj],
-                            (T)sh[5][jj], p);
+        if constexpr (KERN == KFULL)
+          pair_full<ZEPS, T>(dx, dy, dz, r2, e2, (T)sh[3][jj], (T)sh[4][jj], (T)sh[5][jj],
+                             (T)sh[6][jj], (T)sh[7][jj], (T)sh[8][jj], p);
+        else
+          pair<KERN, ZEPS, T>(dx, dy, dz, r2, e2, (T)sh[3][jj], (T)sh[4][jj],
+                              (T)sh[5][jj], p);
       }
     }
 #pragma unroll
@@ -121,6 +125,12 @@ hipError_t launch_direct(int kernel, int precision, const double* tx,
                : run<KSTOKES, BLTC_FP32_FP64ACC>(tx, ty, tz, idx, k, sx, sy,
                                                  sz, n, w, eps, poly_p, poly_c,
                                                  su, sw, out, s);
+  if (kernel == KFULL)
+    return f64 ? run<KFULL, BLTC_FP64>(tx, ty, tz, idx, k, sx, sy, sz, n, w,
+                                        eps, poly_p, poly_c, su, sw, out, s)
+               : run<KFULL, BLTC_FP32_FP64ACC>(tx, ty, tz, idx, k, sx, sy,
+                                               sz, n, w, eps, poly_p, poly_c,
+                                               su, sw, out, s);
   return f64 ? run<KROT, BLTC_FP64>(tx, ty, tz, idx, k, sx, sy, sz, n, w, eps,
                                      poly_p, poly_c, su, sw, out, s)
              : run<KROT, BLTC_FP32_FP64ACC>(tx, ty, tz, idx, k, sx, sy, sz, n,

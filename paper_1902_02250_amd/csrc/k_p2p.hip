@@ -78,7 +78,7 @@ __device__ __forceinline__ void proxies(double x, double y, double z,
       for (int k2 = 0; k2 < N1; ++k2) {
         const T dy = (T)(y - g[N1 + k2]);
         const T dxy2 = dy * dy + dx2e;
-        const F* __restrict__ R = fh + (k1 * N1 + k2) * 3 * N1;
+        const F* __restrict__ R = fh + (k1 * N1 + k2) * 3 * N1;   // [c][k3], c < 3
         T S = 0, ax = 0, ay = 0, az = 0;
 #pragma unroll
         for (int k3 = 0; k3 < N1; ++k3) {
@@ -100,6 +100,75 @@ __device__ __forceinline__ void proxies(double x, double y, double z,
     }
 #pragma unroll
     for (int k = 0; k < N1; ++k) p[2] = dz[k] * cz[k] + p[2];
+  } else if constexpr (KERN == KFULL) {
+    // u = sum f H1 + (f.d) H2 d + Q/2 (n x d),
+    // w = sum Q/2 (f x d) + D1/4 n + D2/4 (n.d) d
+    T cz[N1], cqx[N1], cqy[N1], cfx[N1], cfy[N1], cg[N1];   // column sums
+#pragma unroll
+    for (int k = 0; k < N1; ++k) cz[k] = cqx[k] = cqy[k] = cfx[k] = cfy[k] = cg[k] = 0;
+    const T qa = T(1.5) * e2, d2a = T(3.75) * e2, d1a = T(3.75) * e2 * e2, d1b = T(-0.75) * e2;
+    for (int k1 = 0; k1 < N1; ++k1) {
+      const T dx = (T)(x - g[k1]);
+      const T dx2e = dx * dx + e2;
+      for (int k2 = 0; k2 < N1; ++k2) {
+        const T dy = (T)(y - g[N1 + k2]);
+        const T dxy2 = dy * dy + dx2e;
+        const F* __restrict__ R = fh + (k1 * N1 + k2) * 6 * N1;   // [c][k3], c < 6
+        T ax = 0, ay = 0, az = 0, S = 0, Qx = 0, Qy = 0, Qz = 0;
+        T Fx = 0, Fy = 0, Fz = 0, Wx = 0, Wy = 0, Wz = 0, G = 0;
+#pragma unroll
+        for (int k3 = 0; k3 < N1; ++k3) {
+          const T fx = (T)R[k3], fy = (T)R[N1 + k3], fz = (T)R[2 * N1 + k3];
+          const T nx = (T)R[3 * N1 + k3], ny = (T)R[4 * N1 + k3], nz = (T)R[5 * N1 + k3];
+          const T inv = inv_rho<ZEPS>(dxy2 + dz2[k3]);
+          const T inv2 = inv * inv;
+          const T inv3 = inv2 * inv;
+          const T inv5 = inv3 * inv2;
+          const T h1 = e2 * inv3 + inv;                                 // H1
+          const T qh = (qa * inv2 + T(1)) * inv3;                       // Q/2
+          const T d1q = (inv2 * (d1a * inv2 + d1b) + T(-0.5)) * inv3;   // D1/4
+          const T d2q = (d2a * inv2 + T(1.5)) * inv5;                   // D2/4
+          const T fd = fz * dz[k3] + (fy * dy + fx * dx);
+          const T nd = nz * dz[k3] + (ny * dy + nx * dx);
+          ax = fx * h1 + ax;
+          ay = fy * h1 + ay;
+          az = fz * h1 + az;
+          S = fmat(fd, inv3, S);
+          cz[k3] = fmat(fd, inv3, cz[k3]);
+          Qx = fmat(qh, nx, Qx);
+          Qy = fmat(qh, ny, Qy);
+          Qz = fmat(qh, nz, Qz);
+          cqx[k3] = fmat(qh, nx, cqx[k3]);
+          cqy[k3] = fmat(qh, ny, cqy[k3]);
+          Fx = fmat(qh, fx, Fx);
+          Fy = fmat(qh, fy, Fy);
+          Fz = fmat(qh, fz, Fz);
+          cfx[k3] = fmat(qh, fx, cfx[k3]);
+          cfy[k3] = fmat(qh, fy, cfy[k3]);
+          Wx = d1q * nx + Wx;
+          Wy = d1q * ny + Wy;
+          Wz = d1q * nz + Wz;
+          G = fmat(d2q, nd, G);
+          cg[k3] = fmat(d2q, nd, cg[k3]);
+        }
+        // f x d and n x d split into the row's dx, dy and the column's dz
+        p[0] += (dx * S + ax) - dy * Qz;
+        p[1] += (dy * S + ay) + dx * Qz;
+        p[2] += (dy * Qx + az) - dx * Qy;
+        p[3] += (dx * G + Wx) - dy * Fz;
+        p[4] += (dy * G + Wy) + dx * Fz;
+        p[5] += (dy * Fx + Wz) - dx * Fy;
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < N1; ++k) {
+      p[0] = dz[k] * cqy[k] + p[0];
+      p[1] = -dz[k] * cqx[k] + p[1];
+      p[2] = dz[k] * cz[k] + p[2];
+      p[3] = dz[k] * cfy[k] + p[3];
+      p[4] = -dz[k] * cfx[k] + p[4];
+      p[5] = dz[k] * cg[k] + p[5];
+    }
   } else {
     // u = sum Q (n x d),  w = sum D1 n + sum D2 (n.d) d
     T cqx[N1], cqy[N1], cg[N1];   // column sums of Q nx, Q ny, D2 (n.d)
@@ -302,11 +371,12 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void k_p2p(
     double eps, int poly_p, double poly_c, double su, double sw,
     double* __restrict__ out, DegTables dt) {
   constexpr int OD = Dims<KERN>::OD;
+  constexpr int WD = Dims<KERN>::WD;
   constexpr int NK = N1 * N1 * N1;
   constexpr bool F64 = PREC == BLTC_FP64;
   using T = typename std::conditional<F64, double, float>::type;
-  __shared__ T sA[kWavesPerBlock][4][64];
-  __shared__ T sB[kWavesPerBlock][2][64];
+  __shared__ T sA[kWavesPerBlock][4][64];        // source x, y, z, weight 0
+  __shared__ T sB[kWavesPerBlock][WD - 1][64];   // weights 1 .. WD-1
 
   // the wave index is uniform across the wave; readfirstlane tells the
   // compiler so, which keeps everything derived from it in scalar registers
@@ -344,12 +414,12 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void k_p2p(
       if constexpr (KERN == KPOLY)
         proxies_poly<N1>(x, y, z, g, fh64 + (int64_t)q * 3 * NK, poly_p, poly_c, p);
       else if constexpr (F64)
-        proxies<KERN, N1, ZEPS, T, double>(x, y, z, g, fh64 + (int64_t)q * 3 * NK, e2, p);
+        proxies<KERN, N1, ZEPS, T, double>(x, y, z, g, fh64 + (int64_t)q * WD * NK, e2, p);
       else
-        proxies<KERN, N1, ZEPS, T, float>(x, y, z, g, fh32 + (int64_t)q * 3 * NK, e2, p);
+        proxies<KERN, N1, ZEPS, T, float>(x, y, z, g, fh32 + (int64_t)q * WD * NK, e2, p);
     } else if (RULE && n1 >= 2 && n1 < N1) {
       const double* __restrict__ g = dt.grid[n1 - 1] + (int64_t)q * 3 * n1;
-      const int64_t o = (int64_t)q * 3 * n1 * n1 * n1;
+      const int64_t o = (int64_t)q * WD * n1 * n1 * n1;
       if constexpr (KERN == KPOLY)
         proxies_poly_low<N1 - 1>(n1, x, y, z, g, (const double*)dt.fh[n1 - 1] + o, poly_p,
                                  poly_c, p);
@@ -373,21 +443,19 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void k_p2p(
   bool have = it.next();
   int s0 = it.rb, re = it.re;
   double py0 = 0, py1 = 0, py2 = 0;   // prefetched source (FP64 position)
-  T pf0 = 0, pf1 = 0, pf2 = 0;        // and weights
+  T pf[WD];                           // and weights
+#pragma unroll
+  for (int c = 0; c < WD; ++c) pf[c] = 0;
   auto fetch = [&](int start, int end) {
     const int j = start + lane;
     if (j < end) {
       py0 = ys[j];
       py1 = ys[n + j];
       py2 = ys[2 * n + j];
-      if constexpr (F64) {
-        pf0 = w64[j];
-        pf1 = w64[n + j];
-        pf2 = w64[2 * n + j];
-      } else {
-        pf0 = w32[j];
-        pf1 = w32[n + j];
-        pf2 = w32[2 * n + j];
+#pragma unroll
+      for (int c = 0; c < WD; ++c) {
+        if constexpr (F64) pf[c] = w64[c * n + j];
+        else pf[c] = w32[c * n + j];
       }
     }
   };
@@ -404,9 +472,9 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void k_p2p(
         A[1][lane] = (T)(py1 - cb.y);
         A[2][lane] = (T)(py2 - cb.z);
       }
-      A[3][lane] = pf0;
-      B[0][lane] = pf1;
-      B[1][lane] = pf2;
+      A[3][lane] = pf[0];
+#pragma unroll
+      for (int c = 1; c < WD; ++c) B[c - 1][lane] = pf[c];
     }
     wave_lds_sync();
     int ns0 = s0 + 64, nre = re;
@@ -439,7 +507,11 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void k_p2p(
         const T dy = yr - A[1][jj];
         const T dz = zr - A[2][jj];
         const T r2 = dz * dz + (dy * dy + (dx * dx + e2));
-        pair<KERN, ZEPS, T>(dx, dy, dz, r2, e2, A[3][jj], B[0][jj], B[1][jj], p);
+        if constexpr (KERN == KFULL)
+          pair_full<ZEPS, T>(dx, dy, dz, r2, e2, A[3][jj], B[0][jj], B[1][jj], B[2][jj],
+                             B[3][jj], B[4][jj], p);
+        else
+          pair<KERN, ZEPS, T>(dx, dy, dz, r2, e2, A[3][jj], B[0][jj], B[1][jj], p);
       }
     }
     acc.fold(p);
@@ -625,6 +697,11 @@ hipError_t launch_p2p(int kernel, int precision, int degree, const P2PArgs& a,
     if (precision == BLTC_FP64) return dispatch_degree<KSTOKES, BLTC_FP64>(degree, a, s);
     if (precision == BLTC_FP32_FP64ACC) return dispatch_degree<KSTOKES, BLTC_FP32_FP64ACC>(degree, a, s);
     return dispatch_degree<KSTOKES, BLTC_FP32_KAHAN>(degree, a, s);
+  }
+  if (kernel == KFULL) {
+    if (precision == BLTC_FP64) return dispatch_degree<KFULL, BLTC_FP64>(degree, a, s);
+    if (precision == BLTC_FP32_FP64ACC) return dispatch_degree<KFULL, BLTC_FP32_FP64ACC>(degree, a, s);
+    return dispatch_degree<KFULL, BLTC_FP32_KAHAN>(degree, a, s);
   }
   if (precision == BLTC_FP64) return dispatch_degree<KROT, BLTC_FP64>(degree, a, s);
   if (precision == BLTC_FP32_FP64ACC) return dispatch_degree<KROT, BLTC_FP32_FP64ACC>(degree, a, s);

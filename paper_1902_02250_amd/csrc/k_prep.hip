@@ -24,13 +24,13 @@ __global__ void k_gather_points(const double* __restrict__ x,
 }
 
 __global__ void k_gather_weights(const double* __restrict__ w,
-                                 const int32_t* __restrict__ perm, int64_t n,
+                                 const int32_t* __restrict__ perm, int64_t n, int wd,
                                  double* __restrict__ w64,
                                  float* __restrict__ w32) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int32_t j = perm[i];
-  for (int c = 0; c < 3; ++c) {
+  for (int c = 0; c < wd; ++c) {
     const double v = w[c * n + j];
     w64[c * n + i] = v;
     w32[c * n + i] = (float)v;
@@ -105,11 +105,11 @@ hipError_t launch_gather_points(const double* x, const double* y,
 }
 
 hipError_t launch_gather_weights(const double* w, const int32_t* perm,
-                                 int64_t n, double* w64, float* w32,
+                                 int64_t n, int wd, double* w64, float* w32,
                                  hipStream_t s) {
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_gather_weights, dim3(blocks(n, 256)), dim3(256), 0, s,
-                     w, perm, n, w64, w32);
+                     w, perm, n, wd, w64, w32);
   return hipGetLastError();
 }
 

@@ -244,20 +244,23 @@ __global__ void k_choose(const double* __restrict__ E2, int k, int64_t nb,
   choice[b] = best_candidate(E2, k, nb, b, costs, lam * wt[b] * inv_wsum, &cost, &e2);
 }
 
-// Judge sums over the sampled targets (one per batch, sample i of batch i):
-//   wt[i]      = cnt_i |u_fb|^2
-//   contrib[i] = cnt_i |u - u_fb|^2   (when out is given, else 0)
+// Judge sums over the sampled targets: sample i lies in batch i * stride and
+// stands for the group of batches [i * stride, (i + 1) * stride), which
+// holds G_i targets:
+//   usq[i]     = |u_fb|^2
+//   contrib[i] = G_i |u - u_fb|^2   (when out is given, else 0)
 // with u_fb the fallback treecode at the sample; partial[blk] = the work
-// group's sums of (wt, contrib).
+// group's sums of (G_i |u_fb|^2, contrib).
 __global__ __launch_bounds__(kSelThreads) void k_judge(
-    int ns, const int32_t* __restrict__ bptr, const int32_t* __restrict__ spos,
-    const int32_t* __restrict__ tperm, const double* __restrict__ out, int64_t m, int od,
-    const double* __restrict__ ufb, double* __restrict__ wt,
-    double* __restrict__ contrib, double* __restrict__ partial) {
+    int ns, int stride, int64_t nb, const int32_t* __restrict__ bptr,
+    const int32_t* __restrict__ spos, const int32_t* __restrict__ tperm,
+    const double* __restrict__ out, int64_t m, int od, const double* __restrict__ ufb,
+    double* __restrict__ usq, double* __restrict__ contrib, double* __restrict__ partial) {
   const int i = blockIdx.x * kSelThreads + threadIdx.x;
   double wv = 0.0, cv = 0.0;
   if (i < ns) {
-    const double cnt = (double)(bptr[i + 1] - bptr[i]);
+    const int64_t g0 = (int64_t)i * stride, g1 = g0 + stride < nb ? g0 + stride : nb;
+    const double cnt = (double)(bptr[g1] - bptr[g0]);
     const int64_t o = out ? tperm[spos[i]] : 0;
     double num = 0.0, den = 0.0;
     for (int c = 0; c < od; ++c) {
@@ -270,10 +273,18 @@ __global__ __launch_bounds__(kSelThreads) void k_judge(
     }
     wv = cnt * den;
     cv = cnt * num;
-    wt[i] = wv;
+    usq[i] = den;
     contrib[i] = cv;
   }
   block_sum2<kSelThreads>(wv, cv, partial + (int64_t)blockIdx.x * 2);
+}
+
+// wt[b] = targets_b |u_fb|^2 of the sample standing for batch b.
+__global__ void k_batch_weights(int64_t nb, int stride, const int32_t* __restrict__ bptr,
+                                const double* __restrict__ usq, double* __restrict__ wt) {
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nb) return;
+  wt[b] = (double)(bptr[b + 1] - bptr[b]) * usq[b / stride];
 }
 
 // out[c] = sum over blk of partial[blk][c], in work-group order.
@@ -371,15 +382,23 @@ hipError_t launch_choose(const double* e2, int k, int64_t nb, const float* cost,
   return hipGetLastError();
 }
 
-hipError_t launch_judge(int ns, const int32_t* bptr, const int32_t* spos,
-                        const int32_t* tperm, const double* out, int64_t m, int od,
-                        const double* ufb, double* wt, double* contrib, double* partial,
-                        double* sums, hipStream_t s) {
+hipError_t launch_judge(int ns, int stride, int64_t nb, const int32_t* bptr,
+                        const int32_t* spos, const int32_t* tperm, const double* out,
+                        int64_t m, int od, const double* ufb, double* usq, double* contrib,
+                        double* partial, double* sums, hipStream_t s) {
   if (ns == 0) return hipSuccess;
   const int nblk = (int)alloc_blocks(ns);
-  hipLaunchKernelGGL(k_judge, dim3(nblk), dim3(kSelThreads), 0, s, ns, bptr, spos, tperm, out,
-                     m, od, ufb, wt, contrib, partial);
+  hipLaunchKernelGGL(k_judge, dim3(nblk), dim3(kSelThreads), 0, s, ns, stride, nb, bptr, spos,
+                     tperm, out, m, od, ufb, usq, contrib, partial);
   hipLaunchKernelGGL(k_sum_columns, dim3(1), dim3(64), 0, s, partial, nblk, 2, sums);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_weights(int64_t nb, int stride, const int32_t* bptr,
+                                const double* usq, double* wt, hipStream_t s) {
+  if (nb == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_batch_weights, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, s, nb,
+                     stride, bptr, usq, wt);
   return hipGetLastError();
 }
 

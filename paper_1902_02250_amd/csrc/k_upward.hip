@@ -11,7 +11,8 @@
 // particles, 3 x 64 threads first compute the 1D values L_k for one
 // (particle, axis) each into LDS; then every thread accumulates the n1
 // values k3 of its (k1, k2, c) items, a tensor-product contraction of
-// (n1^2 x 3) by n1 over the chunk's particles.  Chunk partial sums land in
+// (n1^2 x WD) by n1 over the chunk's particles (WD = 3 weight components, or
+// 6 for force and torque).  Chunk partial sums land in
 // a scratch array and a second kernel adds them per cluster in chunk order,
 // so the result is deterministic.  FP64 throughout.  An optional need mask
 // (one byte per cluster) restricts both kernels to the flagged clusters.
@@ -27,16 +28,16 @@ namespace {
 constexpr int kSub = 64;        // particles per sub-block
 constexpr int kThreads = 256;
 
-template <int N1>
+template <int N1, int WD>
 __global__ __launch_bounds__(kThreads) void k_upward(
     const double* __restrict__ ys, const double* __restrict__ w64, int64_t n,
     const int4* __restrict__ chunks, const double* __restrict__ grid,
     const uint8_t* __restrict__ need, double* __restrict__ partial) {
   constexpr int NK = N1 * N1 * N1;
-  constexpr int NITEM = N1 * N1 * 3;                       // (k1, k2, c)
+  constexpr int NITEM = N1 * N1 * WD;                      // (k1, k2, c)
   constexpr int IPT = (NITEM + kThreads - 1) / kThreads;   // items per thread
   __shared__ double sL[3][N1][kSub];
-  __shared__ double sF[3][kSub];
+  __shared__ double sF[WD][kSub];
   __shared__ double sS[3][N1];
 
   const int4 ch = chunks[blockIdx.x];
@@ -82,12 +83,12 @@ __global__ __launch_bounds__(kThreads) void k_upward(
           for (int k = 0; k < N1; ++k) L[k] = L[k] / sum;
         }
         if (ax == 0)
-          for (int c = 0; c < 3; ++c) sF[c][p] = w64[(int64_t)c * n + j];
+          for (int c = 0; c < WD; ++c) sF[c][p] = w64[(int64_t)c * n + j];
       } else {
 #pragma unroll
         for (int k = 0; k < N1; ++k) L[k] = 0.0;
         if (ax == 0)
-          for (int c = 0; c < 3; ++c) sF[c][p] = 0.0;
+          for (int c = 0; c < WD; ++c) sF[c][p] = 0.0;
       }
 #pragma unroll
       for (int k = 0; k < N1; ++k) sL[ax][k][p] = L[k];
@@ -98,9 +99,9 @@ __global__ __launch_bounds__(kThreads) void k_upward(
     for (int i = 0; i < IPT; ++i) {
       const int it = t + i * kThreads;
       if (it < NITEM) {
-        const int c = it % 3;
-        const int k2 = (it / 3) % N1;
-        const int k1 = it / (3 * N1);
+        const int c = it % WD;
+        const int k2 = (it / WD) % N1;
+        const int k1 = it / (WD * N1);
         for (int p = 0; p < cnt; ++p) {
           const double a = sL[0][k1][p] * sL[1][k2][p] * sF[c][p];
 #pragma unroll
@@ -110,14 +111,14 @@ __global__ __launch_bounds__(kThreads) void k_upward(
     }
     __syncthreads();
   }
-  double* out = partial + (int64_t)blockIdx.x * 3 * NK;
+  double* out = partial + (int64_t)blockIdx.x * WD * NK;
 #pragma unroll
   for (int i = 0; i < IPT; ++i) {
     const int it = t + i * kThreads;
     if (it < NITEM) {
-      const int c = it % 3;
-      const int k2 = (it / 3) % N1;
-      const int k1 = it / (3 * N1);
+      const int c = it % WD;
+      const int k2 = (it / WD) % N1;
+      const int k1 = it / (WD * N1);
 #pragma unroll
       for (int k3 = 0; k3 < N1; ++k3)
         out[(int64_t)c * NK + (k1 * N1 + k2) * N1 + k3] = acc[i][k3];
@@ -126,42 +127,46 @@ __global__ __launch_bounds__(kThreads) void k_upward(
 }
 
 // fhat64[q][c][k1][k2][k3] = sum of the chunk partials of cluster q, and the
-// evaluation layout p2p[q][k1][k2][c][k3] in FP64 and FP32.
+// evaluation layout p2p[q][k1][k2][c][k3] in FP64 and FP32 (c < wd).
 __global__ void k_upward_reduce(const int32_t* __restrict__ chunk_ptr,
                                 int64_t nn, const double* __restrict__ partial,
-                                int n1, const uint8_t* __restrict__ need,
+                                int n1, int wd, const uint8_t* __restrict__ need,
                                 double* __restrict__ fhat64,
                                 double* __restrict__ p2p64,
                                 float* __restrict__ p2p32) {
   const int nk = n1 * n1 * n1;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nn * 3 * nk) return;
-  const int64_t q = i / (3 * nk);
+  if (i >= nn * wd * nk) return;
+  const int64_t q = i / (wd * nk);
   if (need && !need[q]) return;
-  const int r = (int)(i % (3 * nk));
+  const int r = (int)(i % (wd * nk));
   double s = 0.0;
   for (int32_t c = chunk_ptr[q]; c < chunk_ptr[q + 1]; ++c)
-    s += partial[(int64_t)c * 3 * nk + r];
+    s += partial[(int64_t)c * wd * nk + r];
   fhat64[i] = s;
   const int comp = r / nk, kk = r % nk;
   const int k3 = kk % n1, k12 = kk / n1;
-  const int64_t o = q * 3 * nk + ((int64_t)k12 * 3 + comp) * n1 + k3;
+  const int64_t o = q * wd * nk + ((int64_t)k12 * wd + comp) * n1 + k3;
   p2p64[o] = s;
   p2p32[o] = (float)s;
 }
 
 template <int N1>
-hipError_t run_upward(const double* ys, const double* w64, int64_t n,
+hipError_t run_upward(const double* ys, const double* w64, int64_t n, int wd,
                       const int4* chunks, int64_t nchunks, const double* grid,
                       const uint8_t* need, double* partial, hipStream_t s) {
-  hipLaunchKernelGGL(k_upward<N1>, dim3((unsigned)nchunks), dim3(kThreads), 0,
-                     s, ys, w64, n, chunks, grid, need, partial);
+  if (wd == 6)
+    hipLaunchKernelGGL((k_upward<N1, 6>), dim3((unsigned)nchunks), dim3(kThreads), 0,
+                       s, ys, w64, n, chunks, grid, need, partial);
+  else
+    hipLaunchKernelGGL((k_upward<N1, 3>), dim3((unsigned)nchunks), dim3(kThreads), 0,
+                       s, ys, w64, n, chunks, grid, need, partial);
   return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_upward(const double* ys, const double* w64, int64_t n,
+hipError_t launch_upward(const double* ys, const double* w64, int64_t n, int wd,
                          const int4* chunks, int64_t nchunks,
                          const double* grid, int degree, const uint8_t* need,
                          double* partial, hipStream_t s) {
@@ -169,7 +174,7 @@ hipError_t launch_upward(const double* ys, const double* w64, int64_t n,
   switch (degree + 1) {
 #define BLTC_UP(N) \
   case N:          \
-    return run_upward<N>(ys, w64, n, chunks, nchunks, grid, need, partial, s);
+    return run_upward<N>(ys, w64, n, wd, chunks, nchunks, grid, need, partial, s);
     BLTC_UP(2) BLTC_UP(3) BLTC_UP(4) BLTC_UP(5) BLTC_UP(6) BLTC_UP(7)
     BLTC_UP(8) BLTC_UP(9) BLTC_UP(10) BLTC_UP(11) BLTC_UP(12) BLTC_UP(13)
 #undef BLTC_UP
@@ -179,14 +184,14 @@ hipError_t launch_upward(const double* ys, const double* w64, int64_t n,
 }
 
 hipError_t launch_upward_reduce(const int32_t* chunk_ptr, int64_t nn,
-                                const double* partial, int degree,
+                                const double* partial, int degree, int wd,
                                 const uint8_t* need, double* fhat64, double* p2p64,
                                 float* p2p32, hipStream_t s) {
   if (nn == 0) return hipSuccess;
   const int n1 = degree + 1;
-  const int64_t tot = nn * 3 * n1 * n1 * n1;
+  const int64_t tot = nn * wd * n1 * n1 * n1;
   hipLaunchKernelGGL(k_upward_reduce, dim3((unsigned)((tot + 255) / 256)),
-                     dim3(256), 0, s, chunk_ptr, nn, partial, n1, need, fhat64,
+                     dim3(256), 0, s, chunk_ptr, nn, partial, n1, wd, need, fhat64,
                      p2p64, p2p32);
   return hipGetLastError();
 }

@@ -10,16 +10,21 @@
 //   Stokeslet: u += f H1 + (f.d) d H2                       (eq. Velocity_1)
 //   rotlet:    u += Q (n x d),  w += D1 n + D2 (n.d) d      (eq. MRS_2)
 // (the 1/2 and 1/4 of the rotlet are applied with the 1/(8 pi) at the end).
+// pair_full() adds both parts of eq. MRS_2 for a force f and a torque n:
+//   u += f H1 + (f.d) d H2 + Q/2 (n x d)
+//   w += Q/2 (f x d) + D1/4 n + D2/4 (n.d) d
+// with the 1/2 and 1/4 folded into the coefficients.
 #pragma once
 #include <hip/hip_runtime.h>
 
 namespace bltc {
 
-enum { KSTOKES = 0, KROT = 1, KPOLY = 100 };
+enum { KSTOKES = 0, KROT = 1, KFULL = 2, KPOLY = 100 };
 
 template <int KERN>
 struct Dims {
-  static constexpr int OD = KERN == KROT ? 6 : 3;
+  static constexpr int OD = (KERN == KROT || KERN == KFULL) ? 6 : 3;   // outputs
+  static constexpr int WD = KERN == KFULL ? 6 : 3;                     // weights
 };
 
 __device__ __forceinline__ float rsq(float v) { return __builtin_amdgcn_rsqf(v); }
@@ -69,6 +74,41 @@ __device__ __forceinline__ void pair(T dx, T dy, T dz, T r2, T e2, T fx, T fy,
     u[5] = d1 * fz + u[5];
     u[5] = g * dz + u[5];
   }
+}
+
+// Both parts of eq. MRS_2 for one pair: force (fx, fy, fz), torque
+// (nx, ny, nz); u[0..2] velocity, u[3..5] angular velocity.
+template <bool ZEPS, typename T>
+__device__ __forceinline__ void pair_full(T dx, T dy, T dz, T r2, T e2, T fx, T fy,
+                                          T fz, T nx, T ny, T nz, T* u) {
+  const T inv = inv_rho<ZEPS>(r2);
+  const T inv2 = inv * inv;
+  const T inv3 = inv2 * inv;
+  const T inv5 = inv3 * inv2;
+  const T h1 = e2 * inv3 + inv;
+  const T qh = (T(1.5) * e2 * inv2 + T(1)) * inv3;                              // Q/2
+  const T d1q = (inv2 * (T(3.75) * e2 * e2 * inv2 + T(-0.75) * e2) + T(-0.5)) * inv3;  // D1/4
+  const T d2q = (T(3.75) * e2 * inv2 + T(1.5)) * inv5;                          // D2/4
+  const T s = (fz * dz + (fy * dy + fx * dx)) * inv3;
+  const T g = (nz * dz + (ny * dy + nx * dx)) * d2q;
+  u[0] = fx * h1 + u[0];
+  u[0] = dx * s + u[0];
+  u[0] = qh * (ny * dz - nz * dy) + u[0];
+  u[1] = fy * h1 + u[1];
+  u[1] = dy * s + u[1];
+  u[1] = qh * (nz * dx - nx * dz) + u[1];
+  u[2] = fz * h1 + u[2];
+  u[2] = dz * s + u[2];
+  u[2] = qh * (nx * dy - ny * dx) + u[2];
+  u[3] = qh * (fy * dz - fz * dy) + u[3];
+  u[3] = d1q * nx + u[3];
+  u[3] = g * dx + u[3];
+  u[4] = qh * (fz * dx - fx * dz) + u[4];
+  u[4] = d1q * ny + u[4];
+  u[4] = g * dy + u[4];
+  u[5] = qh * (fx * dy - fy * dx) + u[5];
+  u[5] = d1q * nz + u[5];
+  u[5] = g * dz + u[5];
 }
 
 }  // namespace bltc

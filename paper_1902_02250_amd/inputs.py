@@ -19,6 +19,13 @@ Workloads (particle positions are (3, n) float64, weights (3, n) float64):
               flagellum particle at distance 0.02 along a direction uniform on
               the sphere; the two exert unit forces in opposite directions
               along that direction (body +u, flagellum -u)
+  rods      - the helical rods of the paper's second example (Section 8.2):
+              rods of M = 150 segments (151 particles) at
+              (x0 + 0.3 cos 2z, y0 + 0.3 sin 2z, z), z = 9 m / M, with base
+              points (x0, y0) at the centers of a square grid of spacing
+              16/15 centred on the origin (15 x 15 rods fill [-8, 8]^2), the
+              grid widening with the rod count at constant density; weights
+              are a force and a torque per particle (6 rows)
 Weights (forces or torques) are i.i.d. uniform in [-1, 1] per component and
 come from their own stream of the same seed, except for `pairs`, whose forces
 follow from the orientations.
@@ -60,9 +67,12 @@ def weights(n, seed, wdim=3):
 
 
 def weights_for(dist, n, seed):
-    """The weights of a workload: the pair forces for `pairs`, else weights()."""
+    """The weights of a workload: the pair forces for `pairs`, a force and a
+    torque per particle for `rods`, else weights()."""
     if dist == "pairs":
         return _pairs(n, seed)[1]
+    if dist == "rods":
+        return weights(n, seed, 6)
     return weights(n, seed)
 
 
@@ -149,9 +159,35 @@ def _pairs(n, seed, side=10.0, length=0.02):
     return np.ascontiguousarray(pos[:n].T), np.ascontiguousarray(frc[:n].T)
 
 
+ROD_SEGMENTS = 150
+ROD_SPACING = 16.0 / 15.0
+
+
+def rods(n, segments=ROD_SEGMENTS, spacing=ROD_SPACING, height=9.0, radius=0.3):
+    """Particles of ceil(n / (segments + 1)) helical rods, rod after rod, cut
+    to n.  The rods take the first places, row by row, of the smallest square
+    grid that holds them; no draw is random."""
+    per = segments + 1
+    nr = -(-n // per)
+    side = int(np.ceil(np.sqrt(nr))) if nr else 0
+    while side * side < nr:
+        side += 1
+    r = np.arange(nr)
+    c = (np.arange(side) - 0.5 * (side - 1)) * spacing
+    x0, y0 = c[r % side], c[r // side]
+    z = height * np.arange(per) / segments
+    px = x0[:, None] + radius * np.cos(2.0 * z)[None, :]
+    py = y0[:, None] + radius * np.sin(2.0 * z)[None, :]
+    pz = np.broadcast_to(z[None, :], px.shape)
+    pts = np.stack([px.ravel(), py.ravel(), pz.ravel()])[:, :n]
+    return np.ascontiguousarray(pts)
+
+
 def points(dist, n, seed):
     if dist == "pairs":
         return _pairs(n, seed)[0]
+    if dist == "rods":
+        return rods(n)
     if dist == "uniform":
         return uniform_points(n, seed)
     if dist == "mixture":
@@ -189,6 +225,10 @@ CONFIGS = {
     # the paper's first example at its 640K size (Section 8.1, Tables 1 and 4)
     "e1": dict(n=640000, dist="pairs", kernel="stokeslet", eps=0.02, degree=7,
                theta=0.7, leaf=2000, seed=SEED_BASE + 11, error_sample=10000),
+    # the paper's second example with 80 x 80 rods (Section 8.2, Table 5):
+    # Stokeslets and rotlets together, eps = 5 L / M = 0.3
+    "e2": dict(n=966400, dist="rods", kernel="full", eps=0.3, degree=7,
+               theta=0.7, leaf=1000, seed=SEED_BASE + 12, error_sample=10000),
 }
 
 

@@ -78,6 +78,19 @@ def test_modified_weights(torch, orc, degree, dist, n, leaf):
         assert np.abs(f[q] - ref[q]).max() <= FP64_TOL * scale, q
 
 
+@pytest.mark.parametrize("degree", [2, 9])
+def test_modified_weights_force_and_torque(torch, orc, degree):
+    """Six weight components (force and torque rows) in one upward pass."""
+    p = inputs.points("mixture", 7000, 6)
+    w = inputs.weights(7000, 6, 6)
+    T = _gpu_tree(torch, p, w, 90, degree)
+    f, _ = T.weights_export(degree)
+    assert f.shape[1] == 6
+    ref = orc.Tree(p, 90).modified_weights(w, degree)
+    for q in range(ref.shape[0]):
+        assert np.abs(f[q] - ref[q]).max() <= FP64_TOL * np.abs(ref[q]).max(), q
+
+
 def test_modified_weights_exact_hits(torch, orc):
     """Particles on grid points and box faces take the exact-hit branch."""
     n = 4
@@ -127,10 +140,10 @@ def test_lists_rule_bit_exact(torch, orc, theta, degree, deg_min):
         assert np.any(L["prox_deg"] < degree)
 
 
-@pytest.mark.parametrize("kernel", ["stokeslet", "rotlet"])
+@pytest.mark.parametrize("kernel", ["stokeslet", "rotlet", "full"])
 def test_direct_fp64(torch, orc, kernel):
     src = inputs.points("uniform", 5003, 3)
-    w = inputs.weights(5003, 3)
+    w = inputs.weights(5003, 3, bltc.WDIM[kernel])
     tgt = inputs.points("mixture", 777, 4)
     got = bltc.direct(_d(torch, tgt), _d(torch, src), _d(torch, w), kernel, 0.01).cpu().numpy()
     ref = orc.direct(kernel, tgt, src, w, eps=0.01)
@@ -178,10 +191,11 @@ def test_treecode_fp64_c1(torch, orc, kernel):
 
 @pytest.mark.parametrize("kernel,degree,theta,bs,ol", [
     ("stokeslet", 1, 0.9, 100, 30), ("stokeslet", 12, 0.5, 1024, 500),
-    ("rotlet", 7, 0.7, 64, 16), ("stokeslet", 6, 1.0, 1, 64), ("rotlet", 3, 0.0, 64, 64)])
+    ("rotlet", 7, 0.7, 64, 16), ("stokeslet", 6, 1.0, 1, 64), ("rotlet", 3, 0.0, 64, 64),
+    ("full", 5, 0.7, 64, 32), ("full", 12, 0.6, 100, 64), ("full", 1, 0.9, 1, 64)])
 def test_treecode_fp64_ragged(torch, orc, kernel, degree, theta, bs, ol):
     src = inputs.points("mixture", 10007, 12)
-    w = inputs.weights(10007, 12)
+    w = inputs.weights(10007, 12, bltc.WDIM[kernel])
     tgt = inputs.points("union", 3001 if bs > 1 else 700, 13) * 1.1
     got, ref = _tree_case(torch, orc, kernel, src, tgt, w, 0.02, degree, theta, 200, bs, ol)
     assert orc.rel_l2(ref, got) <= FP64_TOL
@@ -207,9 +221,11 @@ def test_treecode_poly(torch, orc):
 
 
 @pytest.mark.parametrize("precision", ["fp32_fp64acc", "fp32_kahan"])
-@pytest.mark.parametrize("kernel", ["stokeslet", "rotlet"])
+@pytest.mark.parametrize("kernel", ["stokeslet", "rotlet", "full"])
 def test_treecode_mixed(torch, orc, precision, kernel):
     src, w, cfg = inputs.workload("c1", n=20000)
+    if kernel == "full":
+        w = inputs.weights(20000, 1, 6)
     got, ref = _tree_case(torch, orc, kernel, src, src, w, 0.005, 6, 0.7, 500, 64, 64,
                           precision=precision)
     assert orc.rel_l2(ref, got) <= MIXED_TOL
@@ -267,22 +283,22 @@ def test_errors_on_device(torch):
         bltc.Tree(torch.zeros((3, 10), dtype=torch.float32, device="cuda"), 5)
 
 
-@pytest.mark.parametrize("kernel", ["stokeslet", "rotlet"])
+@pytest.mark.parametrize("kernel", ["stokeslet", "rotlet", "full"])
 @pytest.mark.parametrize("theta,degree,deg_min", [(0.7, 8, 1), (0.6, 6, 2)])
 def test_treecode_rule_fp64(torch, orc, kernel, theta, degree, deg_min):
     """Separation rule: every accepted cluster at its own degree, FP64."""
     src = inputs.points("mixture", 9000, 51)
-    w = inputs.weights(9000, 51)
+    w = inputs.weights(9000, 51, bltc.WDIM[kernel])
     got, ref = _tree_case(torch, orc, kernel, src, src, w, 0.01, degree, theta, 300, 64, 32,
                           deg_min=deg_min)
     assert orc.rel_l2(ref, got) <= FP64_TOL
 
 
 @pytest.mark.parametrize("precision", ["fp32_fp64acc", "fp32_kahan"])
-@pytest.mark.parametrize("kernel", ["stokeslet", "rotlet"])
+@pytest.mark.parametrize("kernel", ["stokeslet", "rotlet", "full"])
 def test_treecode_rule_mixed(torch, orc, kernel, precision):
     src = inputs.points("uniform", 9000, 52)
-    w = inputs.weights(9000, 52)
+    w = inputs.weights(9000, 52, bltc.WDIM[kernel])
     got, ref = _tree_case(torch, orc, kernel, src, src, w, 0.005, 9, 0.7, 300, 64, 32,
                           precision=precision, deg_min=1)
     assert orc.rel_l2(ref, got) <= MIXED_TOL
@@ -308,3 +324,48 @@ def test_rule_off_when_deg_min_reaches_degree(torch, orc):
     b = bltc.evaluate_tree(T, G, "stokeslet", 0.01, 6, 0.7, precision="fp32_fp64acc",
                            deg_min=6)
     assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", FP64_TOL), ("fp32_fp64acc", MIXED_TOL)])
+def test_full_is_stokeslet_plus_rotlet(torch, precision, tol):
+    """The full kernel is linear in (f, n): on the same tree and batches, its
+    velocity is the Stokeslet's of f plus the rotlet's of n, and its angular
+    velocity the rotlet's of n plus the force part 1/2 (f x d) Q, which is
+    the rotlet's velocity for the weights f."""
+    src = inputs.points("union", 30011, 61)
+    w6 = inputs.weights(30011, 61, 6)
+    f, n = w6[:3], w6[3:]
+    T = bltc.Tree(_d(torch, src), 250)
+    G = bltc.Targets(_d(torch, src), 64, 32, 512)
+    run = {}
+    for name, w, kern in (("full", w6, "full"), ("sf", f, "stokeslet"), ("rn", n, "rotlet"),
+                          ("rf", f, "rotlet")):
+        T.compute_weights(_d(torch, w), 7)
+        run[name] = bltc.evaluate_tree(T, G, kern, 0.004, 7, 0.7,
+                                       precision=precision).cpu().numpy()
+    # u = Stokeslet(f) + rotlet_u(n); rotlet_u(f) = 1/2 Q (f x d) = w's force part
+    u = run["sf"] + run["rn"][:3]
+    wv = run["rf"][:3] + run["rn"][3:]
+    ref = np.concatenate([u, wv])
+    got = run["full"]
+    for c in range(6):
+        assert np.linalg.norm(got[c] - ref[c]) <= tol * np.linalg.norm(ref[c]), c
+
+
+def test_full_edge_cases(torch, orc):
+    """eps = 0 with coincident targets and sources, and weights with the wrong
+    number of components for the kernel."""
+    src = inputs.points("mixture", 3000, 62)
+    w = inputs.weights(3000, 62, 6)
+    got, ref = _tree_case(torch, orc, "full", src, src, w, 0.0, 6, 0.7, 60, 64, 64)
+    assert np.all(np.isfinite(got)) and orc.rel_l2(ref, got) <= FP64_TOL
+    T = _gpu_tree(torch, src, inputs.weights(3000, 62), 60, 4)
+    G = bltc.Targets(_d(torch, src), 64, 64)
+    with pytest.raises(bltc.BltcError) as e:
+        bltc.evaluate_tree(T, G, "full", 0.01, 4, 0.7)
+    assert e.value.status == 4   # the tree holds three weight rows
+    T.compute_weights(_d(torch, w), 4)
+    with pytest.raises(bltc.BltcError) as e:
+        bltc.evaluate_tree(T, G, "stokeslet", 0.01, 4, 0.7)
+    assert e.value.status == 4   # and now six
+    assert bltc.evaluate_tree(T, G, "full", 0.01, 4, 0.7).shape == (6, 3000)

@@ -95,7 +95,7 @@ def test_argument_validation_before_device_work():
     assert _status(L.bltc_build_targets(None, None, None, 0, 0, 64, 256, None, ctypes.byref(h))) == "EINVAL"
     assert _status(L.bltc_build_targets(None, None, None, 0, 64, 64, 0, None, ctypes.byref(h))) == "EINVAL"
     assert _status(L.bltc_evaluate_tree(None, None, 0, 0.01, 4, 0.7, ok, None, None)) == "EINVAL"
-    assert _status(L.bltc_compute_modified_weights(None, None, 4, None)) == "EINVAL"
+    assert _status(L.bltc_compute_modified_weights(None, None, 3, 4, None)) == "EINVAL"
     assert _status(L.bltc_direct(None, None, None, 0, None, 0, None, None, None, 0, None, 5, 0.0,
                                  ok, None, None)) == "EINVAL"
     assert _status(L.bltc_direct(None, None, None, 0, None, 3, None, None, None, 0, None, 0, 0.0,
