@@ -18,7 +18,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "liboracle.so")
-_SOURCES = ["kernels.c", "direct.c", "tree.c", "bary.c", "treecode.c"]
+_SOURCES = ["kernels.c", "direct.c", "tree.c", "bary.c", "treecode.c", "dual.c"]
 KERNELS = {"stokeslet": 0, "rotlet": 1, "full": 2, "poly": 100}
 ODIM = {"stokeslet": 3, "rotlet": 6, "full": 6, "poly": 3}
 WDIM = {"stokeslet": 3, "rotlet": 3, "full": 6, "poly": 3}
@@ -70,6 +70,7 @@ def _load():
                                        ctypes.c_int, ctypes.c_int, P]
     L.orc_treecode.argtypes = [P, P, P, P, I64, P, P, P, I64, P, P, I64, P,
                                P, P]
+    L.orc_dual_treecode.argtypes = [P, I64, P, P, P, I64, P, P, P, I64, P, P, P]
     L.orc_lists_new.argtypes = [P, P, P, I64, I64, P, P, P, I64, D, I64, I64,
                                 I64, ctypes.c_int, ctypes.c_int]
     L.orc_lists_new.restype = P
@@ -272,6 +273,24 @@ def treecode(kernel, tgt, src, w, eps, degree, theta, leaf_max, mac_mode=0,
                               ctypes.byref(npx), ctypes.byref(ndr))
     assert rc == 0, "oracle treecode rejected its parameters"
     return out, npx.value, ndr.value
+
+
+def dual_treecode(kernel, tgt, src, w, eps, degree, theta, leaf_max, leaf_t, poly_p=0,
+                  poly_c=0.0):
+    """The cluster-cluster variant (dual.c).  Returns (out (odim, m), counts)
+    with counts = kernel evaluations of the CC, PC, CP and PP interactions
+    and the downward (target, grid point) terms."""
+    tgt, src, w = _c(tgt), _c(src), _c(w)
+    m, n = tgt.shape[1], src.shape[1]
+    prm = _Params(KERNELS[kernel], float(eps), int(poly_p), float(poly_c),
+                  int(degree), float(theta), int(leaf_max), 0, 1, 1, 1, 0)
+    out = np.zeros((ODIM[kernel], m))
+    cnt = np.zeros(5, np.int64)
+    rc = _load().orc_dual_treecode(ctypes.byref(prm), int(leaf_t), _p(tgt[0]), _p(tgt[1]),
+                                   _p(tgt[2]), m, _p(src[0]), _p(src[1]), _p(src[2]), n,
+                                   _p(w), _p(out), _p(cnt))
+    assert rc == 0, "oracle dual treecode rejected its parameters"
+    return out, cnt
 
 
 def lists(src, leaf_max, tgt, theta, batch_size, order_leaf, group_max=512, degree=1,

@@ -20,6 +20,8 @@
  *                 the modified weights of Algorithm 1
  *   treecode.c  - Algorithm 2 (per-target MAC, or the shared batch MAC),
  *                 interaction-list export and interaction counts
+ *   dual.c      - the cluster-cluster variant (interpolation in the target
+ *                 variable too), named as future work in Section 9
  * All arithmetic is FP64; the library is compiled with -ffp-contract=off so
  * that no multiply-add is fused behind the reader's back.
  */
@@ -159,6 +161,18 @@ void orc_lists_export(const orc_lists* L, int64_t* tperm, int64_t* bptr,
                       int64_t* prox_ptr, int32_t* prox_ids, int64_t* dir_ptr,
                       int32_t* dir_ids);
 void orc_lists_free(orc_lists* L);
+
+/* ---- dual.c ------------------------------------------------------------- */
+/* Cluster-cluster variant (Section 9's next step; rules in dual.c): target
+ * tree of leaf size leaf_t, potentials at target-cluster grid points,
+ * interpolated down to the targets.  Uses p->kernel, eps, poly_p, poly_c,
+ * degree, theta, leaf_max (sources).  out[odim][m] in input order;
+ * counts (may be NULL): kernel evaluations of the CC, PC, CP and PP
+ * interactions and the downward (target, grid point) terms. */
+int orc_dual_treecode(const orc_params* p, int64_t leaf_t,
+                      const double* tx, const double* ty, const double* tz, int64_t m,
+                      const double* sx, const double* sy, const double* sz, int64_t n,
+                      const double* w, double* out, int64_t counts[5]);
 
 /* Relative L2 error of eq. error over all components. */
 double orc_rel_l2(const double* ref, const double* approx, int64_t count);
