@@ -101,6 +101,8 @@ def main():
     ap.add_argument("--degree", type=int, default=None)
     ap.add_argument("--kernel", default=None, choices=["stokeslet", "rotlet", "full"])
     ap.add_argument("--theta", type=float, default=None)
+    ap.add_argument("--eps", type=float, default=None,
+                    help="override eps (the pairs workload also sets its pair length to eps)")
     ap.add_argument("--batch-size", type=int, default=64)
     ap.add_argument("--order-leaf", type=int, default=32)
     ap.add_argument("--group-max", type=int, default=512)
@@ -110,6 +112,9 @@ def main():
     ap.add_argument("--tol-settings", default="9,0.7,0;10,0.7,1",
                     help="n,theta,deg_min;... settings also timed, with their error, "
                          "beside the headline configuration ('' for none)")
+    ap.add_argument("--dual-settings", default="",
+                    help="cluster-cluster variant settings 'n,theta,target_leaf;...' timed "
+                         "after the headline")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first run one device-to-device copy of MIB MiB, the reference "
                          "for scaling HBM byte counters")
@@ -146,12 +151,16 @@ def main():
         cfg["theta"] = args.theta
     if args.kernel:
         cfg["kernel"] = args.kernel
+    if args.eps is not None:
+        cfg["eps"] = args.eps
+        if cfg["dist"] == "pairs":
+            cfg["pair_length"] = args.eps
     kernel, eps, degree, theta = cfg["kernel"], cfg["eps"], cfg["degree"], cfg["theta"]
     n = cfg["n"]
     log(f"[bench] generating {args.workload}: n={n} {cfg['dist']} {kernel} eps={eps} "
         f"degree={degree} theta={theta} leaf={cfg['leaf']} precision={args.precision}")
-    src = inputs.points(cfg["dist"], n, cfg["seed"])
-    w = inputs.weights_for(cfg["dist"], n, cfg["seed"])
+    src = inputs.points(cfg["dist"], n, cfg["seed"], **inputs.shape_args(cfg))
+    w = inputs.weights_for(cfg["dist"], n, cfg["seed"], **inputs.shape_args(cfg))
     wd = bltc.WDIM[kernel]
     if w.shape[0] != wd:   # a kernel other than the workload's own
         w = w[:wd] if w.shape[0] > wd else inputs.weights(n, cfg["seed"], wd)
@@ -281,6 +290,39 @@ def main():
                       "interactions_per_s": (xp + xd) / (xms * 1e-3)})
         log(f"[bench] n={dn} theta={th} deg_min={dm}: {xms:.3f} ms/step, E={xerr:.3e}")
     res["settings"] = extra
+    # the cluster-cluster variant on the same workload (targets = sources)
+    dual = []
+    for item in [t for t in args.dual_settings.split(";") if t.strip()]:
+        dn, th, lt = item.split(",")
+        dn, th, lt = int(dn), float(th), int(lt)
+        ttree = bltc.Tree(d_src, lt)
+
+        def dstep(dn=dn, th=th):
+            tree.compute_weights(d_w, dn)
+            return bltc.evaluate_dual(tree, ttree, kernel, eps, dn, th, precision=args.precision,
+                                      out=out)[1]
+        cnt = dstep()
+        torch.cuda.synchronize()
+        xs = max(2, args.steps // 2)
+        bltc.profile_read(reset=True)
+        bltc.profile_enable(True)
+        e0.record()
+        for i in range(xs):
+            dstep()
+        e1.record()
+        torch.cuda.synchronize()
+        bltc.profile_enable(False)
+        dprof = bltc.profile_read(reset=True)
+        xms = e0.elapsed_time(e1) / xs
+        xerrs = errors(out[:, d_idx])
+        dual.append({"degree": dn, "theta": th, "target_leaf": lt, "steps": xs,
+                     "ms_per_step": round(xms, 4), **xerrs,
+                     "evaluations": {"cc": int(cnt[0]), "pc": int(cnt[1]), "cp": int(cnt[2]),
+                                     "pp": int(cnt[3]), "downward": int(cnt[4])},
+                     "stage_ms": {s: round(v[0] / max(v[1], 1), 4) for s, v in dprof.items()}})
+        log(f"[bench] dual n={dn} theta={th} target leaf={lt}: {xms:.3f} ms/step, "
+            f"E={xerrs['rel_l2_err']:.3e}, evaluations {cnt.tolist()}")
+    res["dual"] = dual
     if not args.no_cpu_baseline:
         log(f"[bench] CPU oracle baseline on {args.cpu_sample} targets ...")
         res["cpu_baseline"] = cpu_baseline(cfg, src, w, args.cpu_sample, args.precision)

@@ -193,6 +193,33 @@ int bltc_evaluate_tree(bltc_tree t, bltc_targets g, int32_t kernel, double eps,
                        int32_t degree, double theta, const bltc_options* opt,
                        double* out, void* stream);
 
+/* Cluster-cluster variant (the interpolation in the target variable that
+ * Section 9 names as the next step; not in the paper's method).  tgt is a
+ * tree built with bltc_build_tree on the TARGET points (its leaf size is the
+ * target leaf size; it needs no weights); src holds the sources with the
+ * modified weights of `degree` (wdim of the kernel, else BLTC_ESTATE).  A
+ * target cluster gets Chebyshev grid points like a source cluster.  The two
+ * trees are traversed together from their roots; for a pair (A, C) with
+ * P = (degree+1)^3:
+ *   MAC R2 > 0 and (r_A + r_C)^2 <= theta^2 R2 (eq. MAC with the target
+ *   cluster's radius added): CC (potentials at A's grid points from C's
+ *   proxies) if both hold more than P particles; PC (eq.
+ *   pc_approximation_3D at A's targets) if only C does; CP (potentials at
+ *   A's grid points from C's particles) if only A does; else PP (eq.
+ *   pc_interaction_3D);
+ *   no MAC: PP if both are leaves, else the pair is refined, A's children if
+ *   C is a leaf or A is not a leaf with r_A >= r_C, else C's children.
+ * Every target then adds sum_m L_m(x) g_A[m] over the clusters A holding it,
+ * with the tensor-product Lagrange basis on A's grid (barycentric form,
+ * exact-hit rule of Algorithm 1).  out: FP64 [odim][m] in the target tree's
+ * caller order.  counts (host int64 [5], may be NULL): kernel evaluations of
+ * the CC, PC, CP and PP interactions and the downward (target, grid point)
+ * terms.  opt->deg_min must be 0.  The traversal and its lists are built on
+ * the host; synchronises on stream. */
+int bltc_evaluate_dual(bltc_tree src, bltc_tree tgt, int32_t kernel, double eps,
+                       int32_t degree, double theta, const bltc_options* opt, double* out,
+                       int64_t* counts, void* stream);
+
 /* One call: build the source tree (leaf_max), the target batches, the
  * modified weights of `degree`, evaluate, free everything.  opt may be NULL
  * (defaults). */

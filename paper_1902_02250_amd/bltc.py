@@ -81,6 +81,7 @@ def load():
         "bltc_evaluate": (ctypes.c_int, [P, P, P, I64, P, P, P, I64, P, I32, D,
                                          I32, D, I64, P, P, P]),
         "bltc_lists_export": (ctypes.c_int, [P, P, D, I32, I32] + [P] * 8),
+        "bltc_evaluate_dual": (ctypes.c_int, [P, P, I32, D, I32, D, P, P, P, P]),
         "bltc_counts": (ctypes.c_int, [P, P, I32, D, I32, P, P]),
         "bltc_batch_costs": (ctypes.c_int, [P, P, I32, P, P, I32, P, P, P]),
         "bltc_mlp_params": (ctypes.c_int, [I32, P]),
@@ -296,6 +297,25 @@ def evaluate(tgt, src, w, kernel, eps, degree, theta, leaf_max, precision="fp64"
                                 int(leaf_max), ctypes.byref(o),
                                 ctypes.c_void_p(out.data_ptr()) if m else None, _stream()))
     return out
+
+
+def evaluate_dual(src_tree, tgt_tree, kernel, eps, degree, theta, precision="fp32_fp64acc",
+                  poly_p=2, poly_c=1.0, out=None):
+    """Cluster-cluster variant: src_tree with modified weights of `degree`,
+    tgt_tree built on the targets.  Returns (out (odim, m), counts[5])."""
+    torch = _torch()
+    od = ODIM[kernel]
+    m = tgt_tree.n
+    if out is None:
+        out = torch.empty((od, m), dtype=torch.float64, device="cuda")
+    _dev(out, "out", od)
+    o = options(precision, 64, 32, poly_p, poly_c)
+    cnt = np.zeros(5, np.int64)
+    _check(load().bltc_evaluate_dual(src_tree._h, tgt_tree._h, KERNELS[kernel], float(eps),
+                                     int(degree), float(theta), ctypes.byref(o),
+                                     ctypes.c_void_p(out.data_ptr()) if m else None, _hp(cnt),
+                                     _stream()))
+    return out, cnt
 
 
 def lists(tree, targets, theta, degree=1, deg_min=0):

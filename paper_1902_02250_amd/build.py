@@ -20,8 +20,9 @@ LIB = os.path.join(LIBDIR, "libbltc.so")
 BUILD = os.path.join(HERE, "_build")
 
 SOURCES = ["abi.cpp", "tree_host.cpp", "k_prep.hip", "k_lists.hip",
-           "k_upward.hip", "k_p2p.hip", "k_direct.hip", "k_mlp.hip", "k_select.hip"]
-EXACT = {"abi.cpp", "tree_host.cpp", "k_prep.hip", "k_lists.hip"}
+           "k_upward.hip", "k_p2p.hip", "k_direct.hip", "k_mlp.hip", "k_select.hip",
+           "k_tree.hip", "k_dual.hip"]
+EXACT = {"abi.cpp", "tree_host.cpp", "k_prep.hip", "k_lists.hip", "k_tree.hip"}
 
 COMMON = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -230,26 +230,168 @@ void destroy_tree(bltc_tree t) {
   delete t;
 }
 
+// Device buffers freed on scope exit unless released; owned by exactly one
+// holder (no copies).
+template <typename T>
+struct DevBuf {
+  T* p = nullptr;
+  size_t cap = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  void reserve(size_t n) {
+    if (n <= cap) return;
+    dfree(p);
+    p = dalloc<T>(n);
+    cap = n;
+  }
+  T* release() {
+    T* q = p;
+    p = nullptr;
+    cap = 0;
+    return q;
+  }
+  ~DevBuf() { dfree(p); }
+};
+
+// The cluster tree built on the device, level by level (Section 6 rules, the
+// same results as bltc::build_host_tree bit for bit).  The host keeps the
+// node ranges and numbers the children breadth first from one histogram per
+// chunk; boxes, centers and radii come back with it.  Returns the
+// tree-ordered coordinates [3][n] and the permutation in device memory.
+void build_device_tree(const double* x, const double* y, const double* z, int64_t n,
+                       int64_t leaf_max, hipStream_t s, bltc::HostTree& t, double** coords,
+                       int32_t** perm) {
+  t = bltc::HostTree();
+  t.n = n;
+  DevBuf<double> ca, cb, cmm;
+  DevBuf<int32_t> pa, pb, dcptr, dhist, dpos;
+  DevBuf<int4> dchunks;
+  DevBuf<int2> drange;
+  DevBuf<bltc::TreeLevelNode> dnodes;
+  ca.reserve(3 * n);
+  pa.reserve(n);
+  hipchk(bltc::launch_tree_init(x, y, z, n, ca.p, pa.p, s), "tree init");
+  if (n > 0) {
+    cb.reserve(3 * n);
+    pb.reserve(n);
+    auto add = [&](int32_t b, int32_t e, int32_t lev) {
+      t.begin.push_back(b);
+      t.end.push_back(e);
+      t.level.push_back(lev);
+      t.first.push_back(-1);
+      t.count.push_back(0);
+      if (lev > t.depth) t.depth = lev;
+    };
+    add(0, (int32_t)n, 0);
+    std::vector<int4> chunks;
+    std::vector<int32_t> cptr, hist, pos;
+    std::vector<int2> range;
+    std::vector<bltc::TreeLevelNode> nodes;
+    size_t lev_begin = 0;
+    while (lev_begin < t.begin.size()) {
+      const size_t lev_end = t.begin.size();
+      const int nl = (int)(lev_end - lev_begin);
+      chunks.clear();
+      cptr.resize(nl + 1);
+      range.resize(nl);
+      for (int k = 0; k < nl; ++k) {
+        const size_t q = lev_begin + k;
+        cptr[k] = (int32_t)chunks.size();
+        range[k] = make_int2(t.begin[q], t.end[q]);
+        for (int64_t b = t.begin[q]; b < t.end[q]; b += bltc::kTreeChunk)
+          chunks.push_back(make_int4(k, (int)b, (int)std::min<int64_t>(t.end[q], b + bltc::kTreeChunk), 0));
+      }
+      cptr[nl] = (int32_t)chunks.size();
+      const int64_t nch = (int64_t)chunks.size();
+      dchunks.reserve(nch);
+      dcptr.reserve(nl + 1);
+      drange.reserve(nl);
+      cmm.reserve(6 * nch);
+      dnodes.reserve(nl);
+      dhist.reserve(8 * nch);
+      dpos.reserve(9 * nch);
+      h2d(dchunks.p, chunks.data(), nch, s);
+      h2d(dcptr.p, cptr.data(), nl + 1, s);
+      h2d(drange.p, range.data(), nl, s);
+      hipchk(bltc::launch_tree_level(dchunks.p, nch, dcptr.p, drange.p, nl, ca.p, n, leaf_max,
+                                     cmm.p, dnodes.p, dhist.p, s), "tree level");
+      hist.resize(8 * nch);
+      nodes.resize(nl);
+      d2h(hist.data(), dhist.p, 8 * nch, s);
+      d2h(nodes.data(), dnodes.p, nl, s);
+      sync(s);
+      // split decisions, child offsets and per-chunk positions (stable)
+      pos.assign(9 * nch, 0);
+      bool any = false;
+      std::vector<std::array<int32_t, 8>> off(nl), tot(nl);
+      std::vector<char> split(nl, 0);
+      for (int k = 0; k < nl; ++k) {
+        const size_t q = lev_begin + k;
+        const bltc::TreeLevelNode& o = nodes[k];   // box, center, radius, split axes
+        for (int a = 0; a < 3; ++a) t.box.push_back(o.lo[a]);
+        for (int a = 0; a < 3; ++a) t.box.push_back(o.hi[a]);
+        for (int a = 0; a < 3; ++a) t.ctr.push_back(o.ctr[a]);
+        t.rad.push_back(o.rad);
+        tot[k].fill(0);
+        for (int c = cptr[k]; c < cptr[k + 1]; ++c)
+          for (int k8 = 0; k8 < 8; ++k8) tot[k][k8] += hist[8 * c + k8];
+        int used = 0;
+        for (int k8 = 0; k8 < 8; ++k8) used += tot[k][k8] != 0;
+        split[k] = o.mask != 0 && used >= 2;
+        if (!split[k]) {
+          for (int c = cptr[k]; c < cptr[k + 1]; ++c) pos[9 * c] = chunks[c].y;
+          continue;
+        }
+        any = true;
+        int32_t acc = t.begin[q];
+        for (int k8 = 0; k8 < 8; ++k8) {
+          off[k][k8] = acc;
+          acc += tot[k][k8];
+        }
+        for (int k8 = 0; k8 < 8; ++k8) {
+          int32_t p = off[k][k8];
+          for (int c = cptr[k]; c < cptr[k + 1]; ++c) {
+            pos[9 * c + k8] = p;
+            p += hist[8 * c + k8];
+          }
+        }
+        for (int c = cptr[k]; c < cptr[k + 1]; ++c) pos[9 * c + 8] = 1;
+      }
+      if (any) {
+        h2d(dpos.p, pos.data(), 9 * nch, s);
+        hipchk(bltc::launch_tree_scatter(dchunks.p, nch, dpos.p, n, dnodes.p, ca.p, pa.p, cb.p,
+                                         pb.p, s), "tree scatter");
+      }
+      for (int k = 0; k < nl; ++k) {
+        if (!split[k]) continue;
+        const size_t q = lev_begin + k;
+        t.first[q] = (int32_t)t.begin.size();
+        int nch8 = 0;
+        for (int k8 = 0; k8 < 8; ++k8) {
+          if (!tot[k][k8]) continue;
+          add(off[k][k8], off[k][k8] + tot[k][k8], t.level[q] + 1);
+          ++nch8;
+        }
+        t.count[q] = nch8;
+      }
+      lev_begin = lev_end;
+    }
+    t.perm.resize(n);
+    d2h(t.perm.data(), pa.p, n, s);
+    sync(s);
+  }
+  *coords = ca.release();
+  *perm = pa.release();
+}
+
 void build_tree(const double* x, const double* y, const double* z, int64_t n,
                 int64_t leaf_max, hipStream_t s, bltc_tree t) {
-  std::vector<double> hx, hy, hz;
-  fetch(hx, x, n, s);
-  fetch(hy, y, n, s);
-  fetch(hz, z, n, s);
-  sync(s);
-  bltc::build_host_tree(hx.data(), hy.data(), hz.data(), n, leaf_max, t->host);
+  build_device_tree(x, y, z, n, leaf_max, s, t->host, &t->d_y, &t->d_perm);
   const bltc::HostTree& H = t->host;
   if (7 * (int64_t)H.depth + 1 > bltc::kStackMax)
     throw HipError{BLTC_EINVAL, "tree deeper than the list walk supports"};
   const int64_t nn = H.nnodes();
-  // tree-ordered coordinates
-  std::vector<double> ys(3 * n);
-  for (int64_t i = 0; i < n; ++i) {
-    const int32_t j = H.perm[i];
-    ys[i] = hx[j];
-    ys[n + i] = hy[j];
-    ys[2 * n + i] = hz[j];
-  }
   std::vector<double4> geo(nn);
   std::vector<int2> range(nn), kids(nn);
   for (int64_t q = 0; q < nn; ++q) {
@@ -268,16 +410,12 @@ void build_tree(const double* x, const double* y, const double* z, int64_t n,
   cptr[nn] = (int32_t)chunks.size();
   t->nchunks = (int64_t)chunks.size();
 
-  t->d_perm = dalloc<int32_t>(n);
-  t->d_y = dalloc<double>(3 * n);
   t->d_box = dalloc<double>(6 * nn);
   t->d_geo = dalloc<double4>(nn);
   t->d_range = dalloc<int2>(nn);
   t->d_kids = dalloc<int2>(nn);
   t->d_chunks = dalloc<int4>(chunks.size());
   t->d_chunk_ptr = dalloc<int32_t>(nn + 1);
-  h2d(t->d_perm, H.perm.data(), n, s);
-  h2d(t->d_y, ys.data(), 3 * n, s);
   h2d(t->d_box, H.box.data(), 6 * nn, s);
   h2d(t->d_geo, geo.data(), nn, s);
   h2d(t->d_range, range.data(), nn, s);
@@ -377,28 +515,21 @@ void destroy_targets(bltc_targets g) {
 void build_targets(const double* x, const double* y, const double* z,
                    int64_t m, int32_t bs, int32_t leaf, int64_t gmax,
                    hipStream_t s, bltc_targets g) {
-  std::vector<double> hx, hy, hz;
-  fetch(hx, x, m, s);
-  fetch(hy, y, m, s);
-  fetch(hz, z, m, s);
-  sync(s);
-  bltc::build_host_batches(hx.data(), hy.data(), hz.data(), m, bs, leaf, gmax, g->host);
-  const bltc::HostBatches& B = g->host;
+  // the order tree on the device; groups and batch bounds on the host;
+  // batch geometry on the device
+  bltc::HostTree order;
+  build_device_tree(x, y, z, m, leaf, s, order, &g->d_x, &g->d_tperm);
+  bltc::HostBatches& B = g->host;
+  B = bltc::HostBatches();
+  B.perm.swap(order.perm);
+  std::vector<int32_t> bend;
+  bltc::batch_bounds(order, bs, gmax, B.bptr, bend);
   g->m = m;
   g->nb = (int64_t)B.bptr.size() - 1;
   g->batch_size = bs;
   g->order_leaf = leaf;
   g->group_max = gmax;
-  std::vector<double> xs(3 * m);
-  for (int64_t i = 0; i < m; ++i) {
-    const int32_t j = B.perm[i];
-    xs[i] = hx[j];
-    xs[m + i] = hy[j];
-    xs[2 * m + i] = hz[j];
-  }
   const int64_t nb = g->nb;
-  g->d_tperm = dalloc<int32_t>(m);
-  g->d_x = dalloc<double>(3 * m);
   g->d_bptr = dalloc<int32_t>(nb + 1);
   g->d_bgeo = dalloc<double4>(nb);
   for (auto& L : g->ls) {
@@ -406,10 +537,22 @@ void build_targets(const double* x, const double* y, const double* z,
     L.ptr = dalloc<int32_t>(2 * (nb + 1));
   }
   g->d_flags = dalloc<int32_t>(4);
-  h2d(g->d_tperm, B.perm.data(), m, s);
-  h2d(g->d_x, xs.data(), 3 * m, s);
   h2d(g->d_bptr, B.bptr.data(), nb + 1, s);
-  h2d(g->d_bgeo, reinterpret_cast<const double4*>(B.geo.data()), nb, s);
+  {
+    int32_t* d_bend = dalloc<int32_t>(nb);
+    try {
+      h2d(d_bend, bend.data(), nb, s);
+      hipchk(bltc::launch_batch_geo(g->d_x, m, g->d_bptr, d_bend, nb, g->d_bgeo, s),
+             "batch geometry");
+      B.geo.resize(4 * nb);
+      d2h(reinterpret_cast<double4*>(B.geo.data()), g->d_bgeo, nb, s);
+      sync(s);
+    } catch (...) {
+      dfree(d_bend);
+      throw;
+    }
+    dfree(d_bend);
+  }
   const int32_t zero[4] = {0, 0, 0, 0};
   h2d(g->d_flags, zero, 4, s);
   sync(s);
@@ -715,6 +858,236 @@ void judge_sums(bltc_targets g, int kernel, const double* out, double sums[2],
 }
 
 // Evaluation with (n, theta) chosen per batch (see bltc_evaluate_adaptive).
+// ---- cluster-cluster variant -------------------------------------------------
+// Dual traversal of the target tree T and the source tree S (the target
+// variable is interpolated too, Section 9).  For a pair (A, C):
+//   MAC (R2 > 0 and (r_A + r_C)^2 <= theta^2 R2): CC if both hold more than
+//   P = (n+1)^3 particles, PC if only C does, CP if only A does, else PP;
+//   no MAC and both leaves: PP; otherwise refine A if C is a leaf or
+//   (A is not a leaf and r_A >= r_C), else refine C.
+struct DualPlan {
+  std::vector<std::vector<int32_t>> cc, cp, pc, pp;   // source nodes, by target node
+  int64_t cnt[5] = {0, 0, 0, 0, 0};                    // CC, PC, CP, PP evaluations, downward terms
+};
+
+void dual_traverse(const bltc::HostTree& T, const bltc::HostTree& S, int n1, double theta,
+                   DualPlan& D) {
+  const int64_t ntn = T.nnodes();
+  D.cc.assign(ntn, {});
+  D.cp.assign(ntn, {});
+  D.pc.assign(ntn, {});
+  D.pp.assign(ntn, {});
+  if (T.n == 0 || S.n == 0) return;
+  const int64_t P = (int64_t)n1 * n1 * n1;
+  std::vector<std::pair<int32_t, int32_t>> st{{0, 0}};
+  while (!st.empty()) {
+    const int32_t A = st.back().first, C = st.back().second;
+    st.pop_back();
+    const int64_t na = T.end[A] - T.begin[A], nc = S.end[C] - S.begin[C];
+    const double dx = T.ctr[3 * A] - S.ctr[3 * C];
+    const double dy = T.ctr[3 * A + 1] - S.ctr[3 * C + 1];
+    const double dz = T.ctr[3 * A + 2] - S.ctr[3 * C + 2];
+    const double R2 = dx * dx + dy * dy + dz * dz;
+    const double rr = T.rad[A] + S.rad[C];
+    const bool mac = R2 > 0.0 && rr * rr <= (theta * theta) * R2;
+    const bool leafA = T.count[A] == 0, leafC = S.count[C] == 0;
+    if (mac && na > P && nc > P) {
+      D.cc[A].push_back(C);
+      D.cnt[0] += P * P;
+    } else if (mac && nc > P) {
+      D.pc[A].push_back(C);
+      D.cnt[1] += na * P;
+    } else if (mac && na > P) {
+      D.cp[A].push_back(C);
+      D.cnt[2] += P * nc;
+    } else if (mac || (leafA && leafC)) {
+      D.pp[A].push_back(C);
+      D.cnt[3] += na * nc;
+    } else if (leafC || (!leafA && T.rad[A] >= S.rad[C])) {
+      for (int32_t k = T.count[A] - 1; k >= 0; --k) st.push_back({T.first[A] + k, C});
+    } else {
+      for (int32_t k = S.count[C] - 1; k >= 0; --k) st.push_back({A, S.first[C] + k});
+    }
+  }
+}
+
+void evaluate_dual(bltc_tree src, bltc_tree tgt, int kernel, double eps, int degree,
+                   double theta, const bltc_options& o, double* out, int64_t* counts,
+                   hipStream_t s) {
+  const bltc::HostTree& T = tgt->host;
+  const bltc::HostTree& S = src->host;
+  const int64_t m = tgt->n, ntn = T.nnodes();
+  if (m == 0) return;
+  ensure_degree(src, degree, s);
+  const bltc_degree_data& d = src->deg.at(degree);
+  const int n1 = degree + 1;
+  const int64_t P = (int64_t)n1 * n1 * n1;
+  const int odim = odim_of(kernel);
+
+  StageTimer lt(BLTC_STAGE_LISTS, s);
+  DualPlan D;
+  dual_traverse(T, S, n1, theta, D);
+  // grid slots: target clusters with CC or CP work
+  std::vector<int32_t> slot(ntn, -1), gnode;
+  std::vector<int32_t> ccptr{0}, ccids, cpptr{0}, cpids;
+  std::vector<int4> items;
+  for (int64_t A = 0; A < ntn; ++A) {
+    if (D.cc[A].empty() && D.cp[A].empty()) continue;
+    const int32_t gi = (int32_t)gnode.size();
+    slot[A] = gi;
+    gnode.push_back((int32_t)A);
+    ccids.insert(ccids.end(), D.cc[A].begin(), D.cc[A].end());
+    cpids.insert(cpids.end(), D.cp[A].begin(), D.cp[A].end());
+    ccptr.push_back((int32_t)ccids.size());
+    cpptr.push_back((int32_t)cpids.size());
+    for (int64_t m0 = 0; m0 < P; m0 += 256) items.push_back(make_int4(gi, (int)A, (int)m0, 0));
+    D.cnt[4] += (int64_t)(T.end[A] - T.begin[A]) * P;
+  }
+  const int64_t ng = (int64_t)gnode.size();
+  // batches of at most 64 targets inside each target leaf, leaves in
+  // position order; a batch takes the PC and PP entries and the grid slots
+  // of its leaf and all the leaf's ancestors
+  std::vector<int32_t> parent(ntn, -1), leaves;
+  for (int64_t q = 0; q < ntn; ++q) {
+    for (int32_t k = 0; k < T.count[q]; ++k) parent[T.first[q] + k] = (int32_t)q;
+    if (T.count[q] == 0) leaves.push_back((int32_t)q);
+  }
+  std::sort(leaves.begin(), leaves.end(),
+            [&](int32_t a, int32_t b) { return T.begin[a] < T.begin[b]; });
+  std::vector<int32_t> bptr, pptr{0}, pids, dptr{0}, dids, xptr{0}, xgi, xnode, path;
+  std::vector<double4> bgeo;
+  std::vector<int32_t> lpc, lpp, lgi, lnode;
+  for (int32_t L : leaves) {
+    path.clear();
+    for (int32_t q = L; q >= 0; q = parent[q]) path.push_back(q);
+    std::reverse(path.begin(), path.end());
+    lpc.clear();
+    lpp.clear();
+    lgi.clear();
+    lnode.clear();
+    for (int32_t q : path) {
+      lpc.insert(lpc.end(), D.pc[q].begin(), D.pc[q].end());
+      lpp.insert(lpp.end(), D.pp[q].begin(), D.pp[q].end());
+      if (slot[q] >= 0) {
+        lgi.push_back(slot[q]);
+        lnode.push_back(q);
+      }
+    }
+    for (int64_t b0 = T.begin[L]; b0 < T.end[L]; b0 += bltc::kWave) {
+      bptr.push_back((int32_t)b0);
+      bgeo.push_back(make_double4(T.ctr[3 * L], T.ctr[3 * L + 1], T.ctr[3 * L + 2], T.rad[L]));
+      pids.insert(pids.end(), lpc.begin(), lpc.end());
+      pptr.push_back((int32_t)pids.size());
+      dids.insert(dids.end(), lpp.begin(), lpp.end());
+      dptr.push_back((int32_t)dids.size());
+      xgi.insert(xgi.end(), lgi.begin(), lgi.end());
+      xnode.insert(xnode.end(), lnode.begin(), lnode.end());
+      xptr.push_back((int32_t)xgi.size());
+    }
+  }
+  const int64_t nb = (int64_t)bgeo.size();
+  bptr.push_back((int32_t)m);
+  if (pids.size() > (size_t)INT32_MAX || dids.size() > (size_t)INT32_MAX)
+    throw HipError{BLTC_EINVAL, "cluster-cluster lists exceed 2^31 entries"};
+
+  DevBuf<int32_t> d_ccptr, d_ccids, d_cpptr, d_cpids, d_bptr, d_pptr, d_pids, d_dptr, d_dids,
+      d_xptr, d_xgi, d_xnode;
+  DevBuf<int4> d_items;
+  DevBuf<double4> d_bgeo;
+  DevBuf<double> d_tgrid, d_g;
+  auto up = [&](auto& buf, const auto& v) {
+    buf.reserve(v.size());
+    h2d(buf.p, v.data(), v.size(), s);
+  };
+  up(d_ccptr, ccptr);
+  up(d_ccids, ccids);
+  up(d_cpptr, cpptr);
+  up(d_cpids, cpids);
+  up(d_items, items);
+  up(d_bptr, bptr);
+  up(d_pptr, pptr);
+  up(d_pids, pids);
+  up(d_dptr, dptr);
+  up(d_dids, dids);
+  up(d_xptr, xptr);
+  up(d_xgi, xgi);
+  up(d_xnode, xnode);
+  up(d_bgeo, bgeo);
+  d_tgrid.reserve(ntn * 3 * n1);
+  d_g.reserve(ng * odim * P);
+  double tk[bltc::kMaxDegree + 1];
+  bltc::cheb_points(degree, tk);
+  hipchk(bltc::launch_grids(tgt->d_box, ntn, degree, tk, d_tgrid.p, s), "target grids");
+  lt.stop();
+
+  StageTimer ev(BLTC_STAGE_EVAL, s);
+  bltc::DualGridArgs ga;
+  ga.items = d_items.p;
+  ga.nitems = (int64_t)items.size();
+  ga.n1 = n1;
+  ga.tgrid = d_tgrid.p;
+  ga.tgeo = tgt->d_geo;
+  ga.ccptr = d_ccptr.p;
+  ga.ccids = d_ccids.p;
+  ga.cpptr = d_cpptr.p;
+  ga.cpids = d_cpids.p;
+  ga.sgrid = d.grid;
+  ga.fhat = d.fhat64;
+  ga.srange = src->d_range;
+  ga.ys = src->d_y;
+  ga.w64 = src->d_w64;
+  ga.n = src->n;
+  ga.eps = eps;
+  ga.poly_p = o.poly_p;
+  ga.poly_c = o.poly_c;
+  kernel_scales(kernel, &ga.scale_u, &ga.scale_w);
+  ga.g = d_g.p;
+  hipchk(bltc::launch_dual_grid(kernel, o.precision, ga, s), "dual grid");
+
+  bltc::P2PArgs a;
+  a.tx = tgt->d_y;
+  a.m = m;
+  a.tperm = tgt->d_perm;
+  a.bptr = d_bptr.p;
+  a.bgeo = d_bgeo.p;
+  a.nb = nb;
+  a.wpb = 1;
+  a.pptr = d_pptr.p;
+  a.pids = d_pids.p;
+  a.dptr = d_dptr.p;
+  a.dids = d_dids.p;
+  a.range = src->d_range;
+  a.grid = d.grid;
+  a.fhat = o.precision == BLTC_FP64 ? (const void*)d.p2p64 : (const void*)d.p2p32;
+  a.ys = src->d_y;
+  a.w64 = src->d_w64;
+  a.w32 = src->d_w32;
+  a.n = src->n;
+  a.eps = eps;
+  a.poly_p = o.poly_p;
+  a.poly_c = o.poly_c;
+  kernel_scales(kernel, &a.scale_u, &a.scale_w);
+  a.out = out;
+  hipchk(bltc::launch_p2p(kernel, o.precision, degree, a, s), "p2p");
+
+  bltc::DualDownArgs da;
+  da.bptr = d_bptr.p;
+  da.nb = nb;
+  da.tx = tgt->d_y;
+  da.m = m;
+  da.tperm = tgt->d_perm;
+  da.dptr = d_xptr.p;
+  da.dgi = d_xgi.p;
+  da.dnode = d_xnode.p;
+  da.tgrid = d_tgrid.p;
+  da.g = d_g.p;
+  da.out = out;
+  if (ng > 0) hipchk(bltc::launch_dual_down(odim, n1, da, s), "dual down");
+  ev.stop();
+  if (counts) std::memcpy(counts, D.cnt, sizeof D.cnt);
+  sync(s);   // the device lists go out of scope
+}
+
 void evaluate_adaptive(bltc_tree t, bltc_targets g, int kernel, double eps,
                        bltc_selector sel, double tol, int mode, int fb_degree, double fb_theta,
                        const bltc_options& o, double* out, int32_t* choice_out,
@@ -1261,6 +1634,30 @@ int bltc_evaluate_tree(bltc_tree t, bltc_targets g, int32_t kernel, double eps,
     return fail(BLTC_ESTATE, "modified weights of this degree are not computed");
   return guarded([&] {
     evaluate_tree(t, g, kernel, eps, degree, theta, o, out, (hipStream_t)stream);
+    return (int)BLTC_OK;
+  });
+}
+
+int bltc_evaluate_dual(bltc_tree src, bltc_tree tgt, int32_t kernel, double eps,
+                       int32_t degree, double theta, const bltc_options* opt, double* out,
+                       int64_t* counts, void* stream) {
+  if (counts) std::memset(counts, 0, 5 * sizeof(int64_t));
+  if (!src || !tgt) return fail(BLTC_EINVAL, "NULL source or target tree");
+  if (int rc = check_eval(kernel, eps, degree, theta)) return rc;
+  bltc_options o;
+  bltc_options_default(&o);
+  if (opt) o = *opt;
+  if (int rc = check_options(&o, kernel)) return rc;
+  if (o.deg_min != 0)
+    return fail(BLTC_EINVAL, "the cluster-cluster variant has no separation rule (deg_min 0)");
+  if (tgt->n > 0 && !device_ptr(out)) return fail(BLTC_EINVAL, "out must be a device pointer");
+  if (!src->has_w) return fail(BLTC_ESTATE, "no weights: call bltc_compute_modified_weights first");
+  if (src->wdim != wdim_of(kernel))
+    return fail(BLTC_ESTATE, "the tree's weights have the wrong number of components for this kernel");
+  if (!src->deg.count(degree))
+    return fail(BLTC_ESTATE, "modified weights of this degree are not computed");
+  return guarded([&] {
+    evaluate_dual(src, tgt, kernel, eps, degree, theta, o, out, counts, (hipStream_t)stream);
     return (int)BLTC_OK;
   });
 }

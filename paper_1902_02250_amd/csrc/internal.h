@@ -51,9 +51,22 @@ struct HostBatches {
 void build_host_batches(const double* x, const double* y, const double* z,
                         int64_t m, int32_t batch_size, int32_t order_leaf,
                         int64_t group_max, HostBatches& b);
+// Batch starts bptr[nb+1] and ends bend[nb] over an order tree: the group
+// nodes in tree order, each cut into consecutive pieces of batch_size.
+void batch_bounds(const HostTree& order, int32_t batch_size, int64_t group_max,
+                  std::vector<int32_t>& bptr, std::vector<int32_t>& bend);
+
 
 // Unit Chebyshev points of the 2nd kind, descending.
 void cheb_points(int degree, double* t);
+
+// One cluster of a tree level as the device builder computes it.
+struct TreeLevelNode {
+  double lo[3], hi[3], ctr[3], rad;
+  int32_t mask;      // axes to bisect (bit a); 0 = no split attempted
+  int32_t pad;
+};
+constexpr int kTreeChunk = 8192;   // particles per work group in the tree build
 
 // ---- kernel launch arguments ----------------------------------------------
 struct Nodes {                 // device node arrays
@@ -123,6 +136,45 @@ struct P2PArgs {
   double poly_c;
   double scale_u, scale_w;     // constant factors applied at the end
   double* out;                 // [odim][m] caller order
+};
+
+// Cluster-cluster variant: potentials at target-cluster grid points.
+struct DualGridArgs {
+  const int4* items;           // (grid slot gi, target node A, first grid point, 0)
+  int64_t nitems;
+  int32_t n1;                  // degree + 1
+  const double* tgrid;         // target grids [nn_t][3][n1]
+  const double4* tgeo;         // target node centers and radii
+  const int32_t* ccptr;        // per grid slot: CC source nodes
+  const int32_t* ccids;
+  const int32_t* cpptr;        // per grid slot: CP source nodes
+  const int32_t* cpids;
+  const double* sgrid;         // source grids [nn_s][3][n1]
+  const double* fhat;          // source modified weights [nn_s][wd][n1^3], FP64
+  const int2* srange;          // source node particle ranges
+  const double* ys;            // tree-ordered sources [3][n]
+  const double* w64;           // tree-ordered weights [wd][n]
+  int64_t n;
+  double eps;
+  int32_t poly_p;
+  double poly_c;
+  double scale_u, scale_w;
+  double* g;                   // [n_slots][odim][n1^3]
+};
+
+// Cluster-cluster variant: interpolation of the grid potentials to targets.
+struct DualDownArgs {
+  const int32_t* bptr;         // target batches [nb+1] in target tree order
+  int64_t nb;
+  const double* tx;            // tree-ordered targets [3][m]
+  int64_t m;
+  const int32_t* tperm;        // target position -> caller index
+  const int32_t* dptr;         // per batch: entries (grid slot, target node)
+  const int32_t* dgi;
+  const int32_t* dnode;
+  const double* tgrid;
+  const double* g;
+  double* out;                 // [odim][m] caller order, added to
 };
 
 struct GuardArgs {
@@ -218,6 +270,22 @@ hipError_t launch_need(const int32_t* bsel, int64_t nsel, const int32_t* pptr,
 hipError_t launch_cand_costs(const CostArgs& a, hipStream_t s);
 hipError_t launch_need_degree(int64_t nb, const int32_t* pptr, const int32_t* pids, int d,
                               uint8_t* need, int64_t nn, hipStream_t s);
+hipError_t launch_dual_grid(int kernel, int precision, const DualGridArgs& a, hipStream_t s);
+hipError_t launch_dual_down(int odim, int n1, const DualDownArgs& a, hipStream_t s);
+hipError_t launch_tree_init(const double* x, const double* y, const double* z, int64_t n,
+                            double* c, int32_t* perm, hipStream_t s);
+hipError_t launch_tree_level(const int4* chunks, int64_t nch, const int32_t* cptr,
+                             const int2* range, int nl, const double* c, int64_t n,
+                             int64_t leaf_max, double* cmm, TreeLevelNode* nodes,
+                             int32_t* hist, hipStream_t s);
+// Partitions the chunks of splitting clusters (pos[c][8] != 0) of the
+// current order (c, perm) through the scratch buffers (tc, tperm); (c, perm)
+// hold the new order afterwards.
+hipError_t launch_tree_scatter(const int4* chunks, int64_t nch, const int32_t* pos, int64_t n,
+                               const TreeLevelNode* nodes, double* c, int32_t* perm,
+                               double* tc, int32_t* tperm, hipStream_t s);
+hipError_t launch_batch_geo(const double* c, int64_t m, const int32_t* bptr, const int32_t* bend,
+                            int64_t nb, double4* geo, hipStream_t s);
 hipError_t launch_gather_points(const double* x, const double* y,
                                 const double* z, const int32_t* perm,
                                 int64_t n, double* out3, hipStream_t s);

@@ -256,6 +256,25 @@ void groups_of(const HostTree& t, int32_t q, int64_t group_max,
 
 }  // namespace
 
+void batch_bounds(const HostTree& order, int32_t batch_size, int64_t group_max,
+                  std::vector<int32_t>& bptr, std::vector<int32_t>& bend) {
+  bptr.clear();
+  bend.clear();
+  if (order.n == 0) {
+    bptr.push_back(0);
+    return;
+  }
+  std::vector<std::pair<int32_t, int32_t>> groups;
+  groups_of(order, 0, group_max, groups);
+  // every batch ends at the next batch's start or at its group's end
+  for (const auto& g : groups)
+    for (int64_t s = g.first; s < g.second; s += batch_size) {
+      bptr.push_back((int32_t)s);
+      bend.push_back((int32_t)std::min<int64_t>(g.second, s + batch_size));
+    }
+  bptr.push_back((int32_t)order.n);
+}
+
 void build_host_batches(const double* x, const double* y, const double* z,
                         int64_t m, int32_t batch_size, int32_t order_leaf,
                         int64_t group_max, HostBatches& out) {
@@ -265,22 +284,10 @@ void build_host_batches(const double* x, const double* y, const double* z,
   HostTree order;
   build_host_tree(x, y, z, m, order_leaf, order);
   out.perm.swap(order.perm);
-  std::vector<std::pair<int32_t, int32_t>> groups;
-  groups_of(order, 0, group_max, groups);
-  out.bptr.clear();
+  std::vector<int32_t> bend;
+  batch_bounds(order, batch_size, group_max, out.bptr, bend);
+  const int64_t nb = (int64_t)bend.size();
   const double* src[3] = {x, y, z};
-  for (const auto& g : groups)
-    for (int64_t s = g.first; s < g.second; s += batch_size) out.bptr.push_back((int32_t)s);
-  const int64_t nb = (int64_t)out.bptr.size();
-  out.bptr.push_back((int32_t)m);
-  // every batch ends at the next batch's start or at its group's end
-  std::vector<int32_t> bend(nb);
-  {
-    int64_t b = 0;
-    for (const auto& g : groups)
-      for (int64_t s = g.first; s < g.second; s += batch_size)
-        bend[b++] = (int32_t)std::min<int64_t>(g.second, s + batch_size);
-  }
   out.geo.resize(4 * nb);
   parallel_for(nb, [&](int64_t b) {
     const int64_t s = out.bptr[b], e = bend[b];

@@ -66,11 +66,16 @@ def weights(n, seed, wdim=3):
     return np.ascontiguousarray(-1.0 + 2.0 * u)
 
 
-def weights_for(dist, n, seed):
+def shape_args(cfg):
+    """Keyword arguments of points() / weights_for() that a config sets."""
+    return {"pair_length": cfg["pair_length"]} if "pair_length" in cfg else {}
+
+
+def weights_for(dist, n, seed, pair_length=0.02):
     """The weights of a workload: the pair forces for `pairs`, a force and a
     torque per particle for `rods`, else weights()."""
     if dist == "pairs":
-        return _pairs(n, seed)[1]
+        return _pairs(n, seed, length=pair_length)[1]
     if dist == "rods":
         return weights(n, seed, 6)
     return weights(n, seed)
@@ -183,9 +188,9 @@ def rods(n, segments=ROD_SEGMENTS, spacing=ROD_SPACING, height=9.0, radius=0.3):
     return np.ascontiguousarray(pts)
 
 
-def points(dist, n, seed):
+def points(dist, n, seed, pair_length=0.02):
     if dist == "pairs":
-        return _pairs(n, seed)[0]
+        return _pairs(n, seed, length=pair_length)[0]
     if dist == "rods":
         return rods(n)
     if dist == "uniform":
@@ -238,6 +243,6 @@ def workload(name, n=None):
     cfg = dict(CONFIGS[name])
     if n is not None:
         cfg["n"] = n
-    pts = points(cfg["dist"], cfg["n"], cfg["seed"])
-    w = weights_for(cfg["dist"], cfg["n"], cfg["seed"])
+    pts = points(cfg["dist"], cfg["n"], cfg["seed"], **shape_args(cfg))
+    w = weights_for(cfg["dist"], cfg["n"], cfg["seed"], **shape_args(cfg))
     return pts, w, cfg

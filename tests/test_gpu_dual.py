@@ -1,0 +1,106 @@
+"""GPU parity of the cluster-cluster variant (interpolation in the target
+variable too) against the oracle's dual traversal, through the C ABI.
+
+The traversal decides every pair's interaction type from FP64 comparisons
+of the two trees, which are bit-identical on both sides, so the per-type
+kernel-evaluation counts must match exactly.  FP64 results agree to 1e-12
+relative L2; FP32 evaluation (FP64 accumulation) to the bound of the
+particle-cluster path."""
+import ctypes
+
+import numpy as np
+import pytest
+
+from paper_1902_02250_amd import bltc, inputs
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-12
+MIXED_TOL = 1e-6
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available()
+    bltc.load()
+    return t
+
+
+def _d(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def _run(torch, kernel, src, tgt, w, eps, n, theta, leaf, leaf_t, precision="fp64", **kw):
+    S = bltc.Tree(_d(torch, src), leaf)
+    S.compute_weights(_d(torch, w), n)
+    T = bltc.Tree(_d(torch, tgt), leaf_t)
+    out, cnt = bltc.evaluate_dual(S, T, kernel, eps, n, theta, precision=precision, **kw)
+    return out.cpu().numpy(), cnt
+
+
+@pytest.mark.parametrize("kernel", ["stokeslet", "rotlet", "full"])
+def test_dual_fp64_matches_oracle(torch, orc, kernel):
+    src = inputs.points("mixture", 20000, 91)
+    tgt = inputs.points("uniform", 15001, 92)
+    w = inputs.weights(20000, 91, bltc.WDIM[kernel])
+    got, cnt = _run(torch, kernel, src, tgt, w, 0.01, 4, 0.8, 40, 40)
+    ref, rcnt = orc.dual_treecode(kernel, tgt, src, w, 0.01, 4, 0.8, 40, 40)
+    assert np.array_equal(cnt, rcnt), (cnt, rcnt)
+    assert np.all(cnt[:4] > 0)
+    assert orc.rel_l2(ref, got) <= FP64_TOL
+
+
+@pytest.mark.parametrize("precision", ["fp32_fp64acc", "fp32_kahan"])
+def test_dual_mixed(torch, orc, precision):
+    src = inputs.points("union", 20000, 93)
+    w = inputs.weights(20000, 93)
+    got, cnt = _run(torch, "stokeslet", src, src, w, 0.005, 5, 0.7, 60, 60, precision)
+    ref, rcnt = orc.dual_treecode("stokeslet", src, src, w, 0.005, 5, 0.7, 60, 60)
+    assert np.array_equal(cnt, rcnt) and cnt[0] > 0
+    assert orc.rel_l2(ref, got) <= MIXED_TOL
+
+
+def test_dual_poly_exact(torch, orc):
+    """(c + x.y)^3 at n = 4: exact in both variables, so the variant equals
+    the direct sum."""
+    src = inputs.points("mixture", 20000, 94)
+    tgt = inputs.points("uniform", 19000, 95)
+    w = inputs.weights(20000, 94)
+    got, cnt = _run(torch, "poly", src, tgt, w, 0.0, 4, 0.8, 40, 40, poly_p=3, poly_c=1.5)
+    assert np.all(cnt[:4] > 0)
+    d = orc.direct("poly", tgt, src, w, poly_p=3, poly_c=1.5)
+    assert orc.rel_l2(d, got) <= FP64_TOL
+
+
+def test_dual_edges(torch, orc):
+    src = inputs.points("mixture", 3000, 96)
+    w = inputs.weights(3000, 96)
+    # coincident targets and sources with eps = 0 (the self term is dropped)
+    got, cnt = _run(torch, "stokeslet", src, src, w, 0.0, 3, 0.9, 20, 20)
+    ref, rcnt = orc.dual_treecode("stokeslet", src, src, w, 0.0, 3, 0.9, 20, 20)
+    assert np.array_equal(cnt, rcnt)
+    assert np.all(np.isfinite(got)) and orc.rel_l2(ref, got) <= FP64_TOL
+    # no targets; one target; theta = 0 (only direct pairs)
+    S = bltc.Tree(_d(torch, src), 20)
+    S.compute_weights(_d(torch, w), 3)
+    T0 = bltc.Tree(_d(torch, np.zeros((3, 0))), 20)
+    out, cnt = bltc.evaluate_dual(S, T0, "stokeslet", 0.01, 3, 0.7)
+    assert out.shape == (3, 0) and not cnt.any()
+    one = src[:, 5:6] + 3.0
+    got, _ = _run(torch, "rotlet", src, one, w, 0.01, 3, 0.7, 20, 20)
+    ref, _ = orc.dual_treecode("rotlet", one, src, w, 0.01, 3, 0.7, 20, 20)
+    assert orc.rel_l2(ref, got) <= FP64_TOL
+    got, cnt = _run(torch, "stokeslet", src, src, w, 0.01, 3, 0.0, 20, 20)
+    assert cnt[0] == cnt[1] == cnt[2] == 0
+    assert orc.rel_l2(orc.direct("stokeslet", src, src, w, eps=0.01), got) <= FP64_TOL
+    # the separation rule is not part of this variant; weights must fit
+    T = bltc.Tree(_d(torch, src), 20)
+    o = bltc.options("fp64", deg_min=2)
+    buf = torch.empty((3, 3000), dtype=torch.float64, device="cuda")
+    rc = bltc.load().bltc_evaluate_dual(S._h, T._h, 0, 0.01, 3, 0.7, ctypes.byref(o),
+                                        ctypes.c_void_p(buf.data_ptr()), None, None)
+    assert bltc.STATUS[rc] == "EINVAL"
+    with pytest.raises(bltc.BltcError) as e:
+        bltc.evaluate_dual(S, T, "full", 0.01, 3, 0.7)
+    assert e.value.status == 4

@@ -63,6 +63,49 @@ def test_tree_and_batches_bit_exact(torch, orc, dist, n, leaf):
             assert np.array_equal(x, y)
 
 
+def _device_vs_host(torch, orc, p, leaf):
+    T = bltc.Tree(_d(torch, p), leaf)
+    a = T.export()
+    h = bltc.host_tree(p, leaf)
+    R = orc.Tree(p, leaf)
+    assert T.depth == h["depth"] == R.depth and T.nnodes == R.nnodes
+    for k in TREE_KEYS:
+        assert np.array_equal(a[k], h[k]), k
+        assert np.array_equal(a[k], getattr(R, k)), k
+    return T
+
+
+def test_device_tree_degenerate(torch, orc):
+    """The device builder on the cases that take the degenerate rules: equal
+    points (l_max = 0), a box one ulp wide whose midpoint rounds onto an
+    endpoint (every particle in one child), coordinates on midpoints, one
+    point, and a line."""
+    one = np.nextafter(1.0, 2.0)
+    cases = [np.zeros((3, 40)),
+             np.concatenate([np.zeros((3, 30)), np.ones((3, 31))], axis=1),
+             np.array([[1.0] * 10 + [one] * 10, [0.0] * 20, [5.0] * 20]),
+             np.stack([np.linspace(-1, 1, 300), np.zeros(300), np.zeros(300)]),
+             np.array([[0.5], [0.25], [-1.0]]),
+             np.stack(np.meshgrid(np.arange(9.0), np.arange(9.0), np.arange(9.0))).reshape(3, -1)]
+    for p in cases:
+        _device_vs_host(torch, orc, np.ascontiguousarray(p), 4)
+
+
+@pytest.mark.parametrize("dist,n,leaf", [("mixture", 50001, 40), ("union", 70000, 3000),
+                                         ("rods", 30000, 1000), ("pairs", 20001, 64)])
+def test_device_tree_many_chunks(torch, orc, dist, n, leaf):
+    """Clusters larger than one build work group (8192 particles), ragged
+    chunk tails, slab and pair geometries; the batches built from the device
+    order tree match the oracle's."""
+    p = inputs.points(dist, n, 19)
+    _device_vs_host(torch, orc, p, leaf)
+    for bs, ol, gm in [(64, 32, 512), (100, 9000, 10 ** 9), (1, 64, 256)]:
+        g = bltc.Targets(_d(torch, p), bs, ol, gm).export()
+        ob = orc.batches(p, bs, ol, gm)
+        for x, y in zip([g["tperm"], g["bptr"], g["bcenter"], g["bradius"]], ob):
+            assert np.array_equal(x, y)
+
+
 @pytest.mark.parametrize("degree", [1, 4, 8, 12])
 @pytest.mark.parametrize("dist,n,leaf", [("uniform", 9000, 700), ("mixture", 7000, 60)])
 def test_modified_weights(torch, orc, degree, dist, n, leaf):
