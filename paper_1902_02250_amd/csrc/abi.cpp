@@ -649,9 +649,13 @@ void build_lists(bltc_tree t, bltc_targets g, double theta, const double* theta_
 // lists L and the modified weights of `degree`.
 void run_p2p(bltc_tree t, bltc_targets g, const bltc::ListSet& L, int kernel,
              double eps, int degree, const bltc_options& o, const int32_t* bmap,
-             int64_t nmap, double* out, hipStream_t s) {
+             int64_t nmap, double* out, hipStream_t s, const int4* split = nullptr,
+             int64_t nsplit = 0, double* partial = nullptr) {
   const bltc_degree_data& d = t->deg.at(degree);
   bltc::P2PArgs a;
+  a.split = split;
+  a.nsplit = nsplit;
+  a.partial = partial;
   a.bmap = bmap;
   a.nmap = nmap;
   a.tx = g->d_x;
@@ -765,9 +769,25 @@ void candidate_costs(bltc_tree t, bltc_targets g, int k, const int32_t* cand_n,
   }
   h2d(g->d_candT, T.data(), T.size(), s);
   h2d(g->d_candn, cand_n, k, s);
+  // candidates grouped by theta (at most kMaxPerTheta per group), up to
+  // kMaxThetaGroups groups per launch
+  std::vector<bltc::CostGroup> groups;
   std::vector<bool> done(k, false);
   for (int j0 = 0; j0 < k; ++j0) {
     if (done[j0]) continue;
+    bltc::CostGroup gr;
+    std::memset(&gr, 0, sizeof gr);
+    gr.theta = cand_theta[j0];
+    for (int j = j0; j < k && gr.nc < bltc::kMaxPerTheta; ++j) {
+      if (done[j] || cand_theta[j] != cand_theta[j0]) continue;
+      done[j] = true;
+      gr.deg[gr.nc] = cand_n[j];
+      gr.row[gr.nc] = j;
+      ++gr.nc;
+    }
+    groups.push_back(gr);
+  }
+  for (size_t g0 = 0; g0 < groups.size(); g0 += bltc::kMaxThetaGroups) {
     bltc::CostArgs a;
     std::memset(&a, 0, sizeof a);
     a.bgeo = g->d_bgeo;
@@ -776,19 +796,13 @@ void candidate_costs(bltc_tree t, bltc_targets g, int k, const int32_t* cand_n,
     a.nodes.range = t->d_range;
     a.nodes.kids = t->d_kids;
     a.nodes.nn = t->host.nnodes();
-    a.theta = cand_theta[j0];
+    a.ngroups = (int32_t)std::min<size_t>(bltc::kMaxThetaGroups, groups.size() - g0);
+    for (int i = 0; i < a.ngroups; ++i) a.grp[i] = groups[g0 + i];
     a.deg_min = deg_min;
     a.T = g->d_candT;
     a.w = w;
     a.cost = cost;
     a.err = g->d_flags;
-    for (int j = j0; j < k && a.nc < bltc::kMaxPerTheta; ++j) {
-      if (done[j] || cand_theta[j] != cand_theta[j0]) continue;
-      done[j] = true;
-      a.deg[a.nc] = cand_n[j];
-      a.row[a.nc] = j;
-      ++a.nc;
-    }
     hipchk(bltc::launch_cand_costs(a, s), "candidate costs");
   }
 }
@@ -928,22 +942,32 @@ void evaluate_dual(bltc_tree src, bltc_tree tgt, int kernel, double eps, int deg
   DualPlan D;
   dual_traverse(T, S, n1, theta, D);
   // grid slots: target clusters with CC or CP work
+  // (their grid points are evaluated as targets in batches of 64: CC
+  // clusters on the proxy list, CP clusters on the direct list)
   std::vector<int32_t> slot(ntn, -1), gnode;
-  std::vector<int32_t> ccptr{0}, ccids, cpptr{0}, cpids;
-  std::vector<int4> items;
+  std::vector<int32_t> gbptr, gpptr{0}, gpids, gdptr{0}, gdids;
+  std::vector<double4> gbgeo;
   for (int64_t A = 0; A < ntn; ++A) {
     if (D.cc[A].empty() && D.cp[A].empty()) continue;
     const int32_t gi = (int32_t)gnode.size();
     slot[A] = gi;
     gnode.push_back((int32_t)A);
-    ccids.insert(ccids.end(), D.cc[A].begin(), D.cc[A].end());
-    cpids.insert(cpids.end(), D.cp[A].begin(), D.cp[A].end());
-    ccptr.push_back((int32_t)ccids.size());
-    cpptr.push_back((int32_t)cpids.size());
-    for (int64_t m0 = 0; m0 < P; m0 += 256) items.push_back(make_int4(gi, (int)A, (int)m0, 0));
+    for (int64_t m0 = 0; m0 < P; m0 += bltc::kWave) {
+      gbptr.push_back((int32_t)(gi * P + m0));
+      gbgeo.push_back(make_double4(T.ctr[3 * A], T.ctr[3 * A + 1], T.ctr[3 * A + 2], T.rad[A]));
+      gpids.insert(gpids.end(), D.cc[A].begin(), D.cc[A].end());
+      gpptr.push_back((int32_t)gpids.size());
+      gdids.insert(gdids.end(), D.cp[A].begin(), D.cp[A].end());
+      gdptr.push_back((int32_t)gdids.size());
+    }
     D.cnt[4] += (int64_t)(T.end[A] - T.begin[A]) * P;
   }
-  const int64_t ng = (int64_t)gnode.size();
+  const int64_t ng = (int64_t)gnode.size(), M = ng * P, gnb = (int64_t)gbgeo.size();
+  if (M > (int64_t)INT32_MAX || gpids.size() > (size_t)INT32_MAX)
+    throw HipError{BLTC_EINVAL, "cluster-cluster grid pass exceeds 2^31 entries"};
+  gbptr.push_back((int32_t)M);
+  std::vector<int32_t> giota(M);
+  std::iota(giota.begin(), giota.end(), 0);
   // batches of at most 64 targets inside each target leaf, leaves in
   // position order; a batch takes the PC and PP entries and the grid slots
   // of its leaf and all the leaf's ancestors
@@ -990,20 +1014,22 @@ void evaluate_dual(bltc_tree src, bltc_tree tgt, int kernel, double eps, int deg
   if (pids.size() > (size_t)INT32_MAX || dids.size() > (size_t)INT32_MAX)
     throw HipError{BLTC_EINVAL, "cluster-cluster lists exceed 2^31 entries"};
 
-  DevBuf<int32_t> d_ccptr, d_ccids, d_cpptr, d_cpids, d_bptr, d_pptr, d_pids, d_dptr, d_dids,
-      d_xptr, d_xgi, d_xnode;
-  DevBuf<int4> d_items;
-  DevBuf<double4> d_bgeo;
-  DevBuf<double> d_tgrid, d_g;
+  DevBuf<int32_t> d_gnode, d_gbptr, d_gpptr, d_gpids, d_gdptr, d_gdids, d_giota, d_bptr, d_pptr,
+      d_pids, d_dptr, d_dids, d_xptr, d_xgi, d_xnode;
+  DevBuf<double4> d_bgeo, d_gbgeo;
+  DevBuf<double> d_tgrid, d_g, d_gpts;
   auto up = [&](auto& buf, const auto& v) {
     buf.reserve(v.size());
     h2d(buf.p, v.data(), v.size(), s);
   };
-  up(d_ccptr, ccptr);
-  up(d_ccids, ccids);
-  up(d_cpptr, cpptr);
-  up(d_cpids, cpids);
-  up(d_items, items);
+  up(d_gnode, gnode);
+  up(d_gbptr, gbptr);
+  up(d_gpptr, gpptr);
+  up(d_gpids, gpids);
+  up(d_gdptr, gdptr);
+  up(d_gdids, gdids);
+  up(d_gbgeo, gbgeo);
+  up(d_giota, giota);
   up(d_bptr, bptr);
   up(d_pptr, pptr);
   up(d_pids, pids);
@@ -1014,61 +1040,53 @@ void evaluate_dual(bltc_tree src, bltc_tree tgt, int kernel, double eps, int deg
   up(d_xnode, xnode);
   up(d_bgeo, bgeo);
   d_tgrid.reserve(ntn * 3 * n1);
-  d_g.reserve(ng * odim * P);
+  d_g.reserve(odim * M);
+  d_gpts.reserve(3 * M);
   double tk[bltc::kMaxDegree + 1];
   bltc::cheb_points(degree, tk);
   hipchk(bltc::launch_grids(tgt->d_box, ntn, degree, tk, d_tgrid.p, s), "target grids");
+  hipchk(bltc::launch_dual_points(d_gnode.p, ng, n1, d_tgrid.p, d_gpts.p, s), "grid points");
   lt.stop();
 
   StageTimer ev(BLTC_STAGE_EVAL, s);
-  bltc::DualGridArgs ga;
-  ga.items = d_items.p;
-  ga.nitems = (int64_t)items.size();
-  ga.n1 = n1;
-  ga.tgrid = d_tgrid.p;
-  ga.tgeo = tgt->d_geo;
-  ga.ccptr = d_ccptr.p;
-  ga.ccids = d_ccids.p;
-  ga.cpptr = d_cpptr.p;
-  ga.cpids = d_cpids.p;
-  ga.sgrid = d.grid;
-  ga.fhat = d.fhat64;
-  ga.srange = src->d_range;
-  ga.ys = src->d_y;
-  ga.w64 = src->d_w64;
-  ga.n = src->n;
-  ga.eps = eps;
-  ga.poly_p = o.poly_p;
-  ga.poly_c = o.poly_c;
-  kernel_scales(kernel, &ga.scale_u, &ga.scale_w);
-  ga.g = d_g.p;
-  hipchk(bltc::launch_dual_grid(kernel, o.precision, ga, s), "dual grid");
-
-  bltc::P2PArgs a;
-  a.tx = tgt->d_y;
-  a.m = m;
-  a.tperm = tgt->d_perm;
-  a.bptr = d_bptr.p;
-  a.bgeo = d_bgeo.p;
-  a.nb = nb;
-  a.wpb = 1;
-  a.pptr = d_pptr.p;
-  a.pids = d_pids.p;
-  a.dptr = d_dptr.p;
-  a.dids = d_dids.p;
-  a.range = src->d_range;
-  a.grid = d.grid;
-  a.fhat = o.precision == BLTC_FP64 ? (const void*)d.p2p64 : (const void*)d.p2p32;
-  a.ys = src->d_y;
-  a.w64 = src->d_w64;
-  a.w32 = src->d_w32;
-  a.n = src->n;
-  a.eps = eps;
-  a.poly_p = o.poly_p;
-  a.poly_c = o.poly_c;
-  kernel_scales(kernel, &a.scale_u, &a.scale_w);
-  a.out = out;
-  hipchk(bltc::launch_p2p(kernel, o.precision, degree, a, s), "p2p");
+  // the particle-cluster kernel over a point set: batches bp/bg, proxy
+  // lists pp/pi, direct lists dp/di, output dst [odim][mm] via tperm
+  auto p2p = [&](const double* tx, int64_t mm, const int32_t* tperm, const int32_t* bp,
+                 const double4* bg, int64_t nbb, const int32_t* pp, const int32_t* pi,
+                 const int32_t* dp, const int32_t* di, double* dst) {
+    bltc::P2PArgs a;
+    a.tx = tx;
+    a.m = mm;
+    a.tperm = tperm;
+    a.bptr = bp;
+    a.bgeo = bg;
+    a.nb = nbb;
+    a.wpb = 1;
+    a.pptr = pp;
+    a.pids = pi;
+    a.dptr = dp;
+    a.dids = di;
+    a.range = src->d_range;
+    a.grid = d.grid;
+    a.fhat = o.precision == BLTC_FP64 ? (const void*)d.p2p64 : (const void*)d.p2p32;
+    a.ys = src->d_y;
+    a.w64 = src->d_w64;
+    a.w32 = src->d_w32;
+    a.n = src->n;
+    a.eps = eps;
+    a.poly_p = o.poly_p;
+    a.poly_c = o.poly_c;
+    kernel_scales(kernel, &a.scale_u, &a.scale_w);
+    a.out = dst;
+    hipchk(bltc::launch_p2p(kernel, o.precision, degree, a, s), "p2p");
+  };
+  // grid potentials g_A at the target clusters' grid points (CC and CP)
+  if (gnb > 0)
+    p2p(d_gpts.p, M, d_giota.p, d_gbptr.p, d_gbgeo.p, gnb, d_gpptr.p, d_gpids.p, d_gdptr.p,
+        d_gdids.p, d_g.p);
+  // targets: PC and PP of their leaf and its ancestors
+  p2p(tgt->d_y, m, tgt->d_perm, d_bptr.p, d_bgeo.p, nb, d_pptr.p, d_pids.p, d_dptr.p, d_dids.p,
+      out);
 
   bltc::DualDownArgs da;
   da.bptr = d_bptr.p;
@@ -1081,6 +1099,7 @@ void evaluate_dual(bltc_tree src, bltc_tree tgt, int kernel, double eps, int deg
   da.dnode = d_xnode.p;
   da.tgrid = d_tgrid.p;
   da.g = d_g.p;
+  da.gstride = M;
   da.out = out;
   if (ng > 0) hipchk(bltc::launch_dual_down(odim, n1, da, s), "dual down");
   ev.stop();
@@ -1318,9 +1337,48 @@ void evaluate_adaptive(bltc_tree t, bltc_targets g, int kernel, double eps,
     st[2] = (int64_t)redo.size();
     if (!redo.empty()) {
       h2d(g->d_bmap, redo.data(), redo.size(), s);
-      run_p2p(t, g, g->ls[1], kernel, eps, fb_degree, o, g->d_bmap, (int64_t)redo.size(),
-              out, s);
-      judge_sums(g, kernel, out, js, s);
+      if (g->batch_size <= bltc::kWave) {
+        // few batches: each batch's proxy list is cut into slices that run
+        // as separate waves (the direct list goes with the first slice);
+        // the slices' FP64 sums are added in slice order
+        std::vector<int32_t> lp(nb + 1);
+        d2h(lp.data(), g->ls[1].ptr, nb + 1, s);
+        sync(s);
+        int64_t tot = 0;
+        for (int32_t b : redo) tot += lp[b + 1] - lp[b];
+        const int64_t len = std::max<int64_t>(16, (tot + 4095) / 4096);
+        std::vector<int4> sl;
+        std::vector<int32_t> sptr{0};
+        for (int32_t b : redo) {
+          const int32_t p0 = lp[b], p1 = lp[b + 1];
+          if (p0 == p1) sl.push_back(make_int4(b, p0, p0, 1));
+          for (int64_t q = p0; q < p1; q += len)
+            sl.push_back(make_int4(b, (int)q, (int)std::min<int64_t>(p1, q + len), q == p0));
+          sptr.push_back((int32_t)sl.size());
+        }
+        const int odim = odim_of(kernel);
+        DevBuf<int4> d_sl;
+        DevBuf<int32_t> d_sptr;
+        DevBuf<double> d_part;
+        d_sl.reserve(sl.size());
+        d_sptr.reserve(sptr.size());
+        d_part.reserve(sl.size() * odim * bltc::kWave);
+        h2d(d_sl.p, sl.data(), sl.size(), s);
+        h2d(d_sptr.p, sptr.data(), sptr.size(), s);
+        run_p2p(t, g, g->ls[1], kernel, eps, fb_degree, o, g->d_bmap, (int64_t)redo.size(),
+                out, s, d_sl.p, (int64_t)sl.size(), d_part.p);
+        double su, sw;
+        kernel_scales(kernel, &su, &sw);
+        hipchk(bltc::launch_split_reduce(d_sptr.p, g->d_bmap, (int64_t)redo.size(), g->d_bptr,
+                                         g->d_tperm, d_part.p, odim, su, sw, g->m, out, s),
+               "split reduce");
+        judge_sums(g, kernel, out, js, s);
+        sync(s);   // the slice buffers go out of scope
+      } else {
+        run_p2p(t, g, g->ls[1], kernel, eps, fb_degree, o, g->d_bmap, (int64_t)redo.size(),
+                out, s);
+        judge_sums(g, kernel, out, js, s);
+      }
       jd[1] = std::sqrt(js[1] / wsum);
     }
   }

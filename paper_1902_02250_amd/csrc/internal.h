@@ -136,30 +136,12 @@ struct P2PArgs {
   double poly_c;
   double scale_u, scale_w;     // constant factors applied at the end
   double* out;                 // [odim][m] caller order
-};
-
-// Cluster-cluster variant: potentials at target-cluster grid points.
-struct DualGridArgs {
-  const int4* items;           // (grid slot gi, target node A, first grid point, 0)
-  int64_t nitems;
-  int32_t n1;                  // degree + 1
-  const double* tgrid;         // target grids [nn_t][3][n1]
-  const double4* tgeo;         // target node centers and radii
-  const int32_t* ccptr;        // per grid slot: CC source nodes
-  const int32_t* ccids;
-  const int32_t* cpptr;        // per grid slot: CP source nodes
-  const int32_t* cpids;
-  const double* sgrid;         // source grids [nn_s][3][n1]
-  const double* fhat;          // source modified weights [nn_s][wd][n1^3], FP64
-  const int2* srange;          // source node particle ranges
-  const double* ys;            // tree-ordered sources [3][n]
-  const double* w64;           // tree-ordered weights [wd][n]
-  int64_t n;
-  double eps;
-  int32_t poly_p;
-  double poly_c;
-  double scale_u, scale_w;
-  double* g;                   // [n_slots][odim][n1^3]
+  // split mode (split != NULL): wave w evaluates batch split[w].x over the
+  // proxy entries [split[w].y, split[w].z), plus the batch's direct list if
+  // split[w].w != 0, and writes unscaled FP64 sums to partial[w][odim][64]
+  const int4* split = nullptr;
+  int64_t nsplit = 0;
+  double* partial = nullptr;
 };
 
 // Cluster-cluster variant: interpolation of the grid potentials to targets.
@@ -173,7 +155,8 @@ struct DualDownArgs {
   const int32_t* dgi;
   const int32_t* dnode;
   const double* tgrid;
-  const double* g;
+  const double* g;             // grid potentials [odim][gstride], slot gi at gi (n+1)^3
+  int64_t gstride;
   double* out;                 // [odim][m] caller order, added to
 };
 
@@ -228,17 +211,24 @@ struct Costs {
 // (far n1 + row) n1^2 + clu with n1 - 1 its degree (the candidate's, or the
 // separation rule's), a near-field source costs nearf.
 constexpr int kMaxPerTheta = 16;
+// The candidates sharing one theta.
+struct CostGroup {
+  double theta;
+  int32_t nc;                          // candidates with this theta
+  int32_t deg[kMaxPerTheta];           // their degrees
+  int32_t row[kMaxPerTheta];           // output row (and T row) of each candidate
+};
+constexpr int kMaxThetaGroups = 8;     // theta groups per launch (grid y)
+
 struct CostArgs {
   const double4* bgeo;
   int64_t nb;
   Nodes nodes;
-  double theta;
-  int32_t nc;                          // candidates with this theta
-  int32_t deg[kMaxPerTheta];           // their degrees
+  int32_t ngroups;
+  CostGroup grp[kMaxThetaGroups];
   int32_t deg_min;                     // separation rule (0: off)
   const double* T;                     // [rows][kMaxDegree + 1] rule thresholds (device)
   Costs w;
-  int32_t row[kMaxPerTheta];           // output row (and T row) of each candidate
   float* cost;                         // [rows][nb]
   int32_t* err;
 };
@@ -270,7 +260,8 @@ hipError_t launch_need(const int32_t* bsel, int64_t nsel, const int32_t* pptr,
 hipError_t launch_cand_costs(const CostArgs& a, hipStream_t s);
 hipError_t launch_need_degree(int64_t nb, const int32_t* pptr, const int32_t* pids, int d,
                               uint8_t* need, int64_t nn, hipStream_t s);
-hipError_t launch_dual_grid(int kernel, int precision, const DualGridArgs& a, hipStream_t s);
+hipError_t launch_dual_points(const int32_t* gnode, int64_t ng, int n1, const double* tgrid,
+                              double* pts, hipStream_t s);
 hipError_t launch_dual_down(int odim, int n1, const DualDownArgs& a, hipStream_t s);
 hipError_t launch_tree_init(const double* x, const double* y, const double* z, int64_t n,
                             double* c, int32_t* perm, hipStream_t s);
@@ -305,6 +296,12 @@ hipError_t launch_upward_reduce(const int32_t* chunk_ptr, int64_t nn,
 hipError_t launch_lists(const ListArgs& a, bool fill, hipStream_t s);
 hipError_t launch_exclusive_scan(const int32_t* in, int64_t n, int32_t* out,
                                  int32_t* overflow, hipStream_t s);
+// out[c][tperm[t]] = scale * (sum of the slices sptr[r] .. sptr[r+1] of
+// partial) for every target t of batch bmap[r].
+hipError_t launch_split_reduce(const int32_t* sptr, const int32_t* bmap, int64_t nr,
+                               const int32_t* bptr, const int32_t* tperm, const double* partial,
+                               int odim, double su, double sw, int64_t m, double* out,
+                               hipStream_t s);
 hipError_t launch_p2p(int kernel, int precision, int degree,
                       const P2PArgs& a, hipStream_t s);
 hipError_t launch_direct(int kernel, int precision, const double* tx,

@@ -369,7 +369,8 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void k_p2p(
     const double* __restrict__ fh64, const double* __restrict__ ys,
     const float* __restrict__ w32, const double* __restrict__ w64, int64_t n,
     double eps, int poly_p, double poly_c, double su, double sw,
-    double* __restrict__ out, DegTables dt) {
+    double* __restrict__ out, DegTables dt, const int4* __restrict__ split,
+    double* __restrict__ partial) {
   constexpr int OD = Dims<KERN>::OD;
   constexpr int WD = Dims<KERN>::WD;
   constexpr int NK = N1 * N1 * N1;
@@ -384,8 +385,21 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void k_p2p(
   const int lane = threadIdx.x & 63;
   const int gw = xcd_block(blockIdx.x, nblk) * kWavesPerBlock + wid;
   if (gw >= nwaves) return;
-  const int b = bmap ? bmap[gw / wpb] : gw / wpb;
-  const int wv = gw % wpb;
+  int b, wv, pbeg, pend;
+  bool near = true;
+  if (split) {   // one slice of a batch's proxy list (and maybe its direct list)
+    const int4 sp = split[gw];
+    b = sp.x;
+    wv = 0;
+    pbeg = sp.y;
+    pend = sp.z;
+    near = sp.w != 0;
+  } else {
+    b = bmap ? bmap[gw / wpb] : gw / wpb;
+    wv = gw % wpb;
+    pbeg = pptr[b];
+    pend = pptr[b + 1];
+  }
   const int t0 = bptr[b] + wv * 64, t1 = bptr[b + 1];
   if (t0 >= t1) return;
   const int ti = t0 + lane;
@@ -401,7 +415,7 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void k_p2p(
   acc.init();
 
   // far field
-  for (int li = pptr[b]; li < pptr[b + 1]; ++li) {
+  for (int li = pbeg; li < pend; ++li) {
     const int e = pids[li];
     const int q = e & kIdMask;
     const int dd = e >> kDegShift;
@@ -439,7 +453,7 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void k_p2p(
   const T xr = F64 ? (T)x : (T)(x - cb.x);
   const T yr = F64 ? (T)y : (T)(y - cb.y);
   const T zr = F64 ? (T)z : (T)(z - cb.z);
-  Runs it{dids, range, dptr[b], dptr[b + 1], 0, 0};
+  Runs it{dids, range, near ? dptr[b] : 0, near ? dptr[b + 1] : 0, 0, 0};
   bool have = it.next();
   int s0 = it.rb, re = it.re;
   double py0 = 0, py1 = 0, py2 = 0;   // prefetched source (FP64 position)
@@ -522,15 +536,40 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void k_p2p(
   }
 
   if (active) {
-    const int64_t o = tperm[ti];
+    if (split) {
 #pragma unroll
-    for (int c = 0; c < OD; ++c) out[c * m + o] = acc.get(c) * (c < 3 ? su : sw);
+      for (int c = 0; c < OD; ++c) partial[((int64_t)gw * OD + c) * 64 + lane] = acc.get(c);
+    } else {
+      const int64_t o = tperm[ti];
+#pragma unroll
+      for (int c = 0; c < OD; ++c) out[c * m + o] = acc.get(c) * (c < 3 ? su : sw);
+    }
+  }
+}
+
+// Sums the slices of each split batch in slice order and scatters.
+__global__ void k_split_reduce(const int32_t* __restrict__ sptr, const int32_t* __restrict__ bmap,
+                               int64_t nr, const int32_t* __restrict__ bptr,
+                               const int32_t* __restrict__ tperm, const double* __restrict__ partial,
+                               int od, double su, double sw, int64_t m, double* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nr * 64) return;
+  const int64_t r = i / 64;
+  const int lane = (int)(i % 64);
+  const int b = bmap[r];
+  const int t = bptr[b] + lane;
+  if (t >= bptr[b + 1]) return;
+  const int64_t o = tperm[t];
+  for (int c = 0; c < od; ++c) {
+    double v = 0.0;
+    for (int sl = sptr[r]; sl < sptr[r + 1]; ++sl) v += partial[((int64_t)sl * od + c) * 64 + lane];
+    out[c * m + o] = v * (c < 3 ? su : sw);
   }
 }
 
 template <int KERN, int PREC, int N1>
 hipError_t run_p2p(const P2PArgs& a, hipStream_t s) {
-  const int64_t nw64 = (a.bmap ? a.nmap : a.nb) * (int64_t)a.wpb;
+  const int64_t nw64 = a.split ? a.nsplit : (a.bmap ? a.nmap : a.nb) * (int64_t)a.wpb;
   if (nw64 == 0) return hipSuccess;
   if (nw64 > 0x7fffffff - kWavesPerBlock) return hipErrorInvalidValue;
   const int nwaves = (int)nw64;
@@ -548,7 +587,7 @@ hipError_t run_p2p(const P2PArgs& a, hipStream_t s) {
                        a.tperm, a.bptr, a.bgeo, nblk, nwaves, a.wpb, a.bmap, a.pptr, a.pids,
                        a.dptr, a.dids, a.range, a.grid, (const float*)a.fhat,
                        (const double*)a.fhat, a.ys, a.w32, a.w64, a.n, a.eps,
-                       a.poly_p, a.poly_c, a.scale_u, a.scale_w, a.out, dt);
+                       a.poly_p, a.poly_c, a.scale_u, a.scale_w, a.out, dt, a.split, a.partial);
   };
   if (rule) {
     if (zeps)
@@ -679,6 +718,16 @@ hipError_t dispatch_degree(int degree, const P2PArgs& a, hipStream_t s) {
 }
 
 }  // namespace
+
+hipError_t launch_split_reduce(const int32_t* sptr, const int32_t* bmap, int64_t nr,
+                               const int32_t* bptr, const int32_t* tperm, const double* partial,
+                               int odim, double su, double sw, int64_t m, double* out,
+                               hipStream_t s) {
+  if (nr == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_split_reduce, dim3((unsigned)((nr * 64 + 255) / 256)), dim3(256), 0, s,
+                     sptr, bmap, nr, bptr, tperm, partial, odim, su, sw, m, out);
+  return hipGetLastError();
+}
 
 hipError_t launch_guard(int kernel, int degree, const GuardArgs& a, hipStream_t s) {
   if (kernel == KSTOKES) return dispatch_guard<KSTOKES>(degree, a, s);

@@ -79,16 +79,18 @@ __global__ __launch_bounds__(128) void k_features(FeatArgs a) {
   }
 }
 
-// Modelled wave costs of the candidates sharing one theta (CostArgs): one
-// walk per batch; an accepted cluster at ratio^2 qq costs
+// Modelled wave costs of the candidates (CostArgs): one walk per batch and
+// theta group (grid y); an accepted cluster at ratio^2 qq costs
 // (far n1 + row) n1^2 + clu with n1 - 1 the candidate's degree, or under the
 // separation rule the first d >= deg_min with qq <= T[d].  The candidate
-// loop is unrolled to kMaxPerTheta so the sums stay in registers.
+// loop is unrolled to kMaxPerTheta so the sums stay in registers; the theta
+// groups run in one launch so their walks overlap.
 __global__ __launch_bounds__(128) void k_cand_costs(CostArgs a) {
   const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= a.nb) return;
+  const CostGroup& gr = a.grp[blockIdx.y];
   const double4 g = a.bgeo[b];
-  const double th2 = a.theta * a.theta;
+  const double th2 = gr.theta * gr.theta;
   float far[kMaxPerTheta];
 #pragma unroll
   for (int i = 0; i < kMaxPerTheta; ++i) far[i] = 0.f;
@@ -108,11 +110,11 @@ __global__ __launch_bounds__(128) void k_cand_costs(CostArgs a) {
       const double qq = (rr * rr) / R2;
 #pragma unroll
       for (int i = 0; i < kMaxPerTheta; ++i) {
-        if (i < a.nc) {
-          const int n = a.deg[i];
+        if (i < gr.nc) {
+          const int n = gr.deg[i];
           int d = n;
           if (a.deg_min > 0 && a.deg_min < n) {
-            const double* __restrict__ T = a.T + (int64_t)a.row[i] * (kMaxDegree + 1);
+            const double* __restrict__ T = a.T + (int64_t)gr.row[i] * (kMaxDegree + 1);
             d = a.deg_min;
             while (d < n && !(qq <= T[d])) ++d;
           }
@@ -136,7 +138,7 @@ __global__ __launch_bounds__(128) void k_cand_costs(CostArgs a) {
   }
 #pragma unroll
   for (int i = 0; i < kMaxPerTheta; ++i)
-    if (i < a.nc) a.cost[(int64_t)a.row[i] * a.nb + b] = far[i] + (float)S * a.w.nearf;
+    if (i < gr.nc) a.cost[(int64_t)gr.row[i] * a.nb + b] = far[i] + (float)S * a.w.nearf;
 }
 
 // e2[j][b] = 10^(2 Y[b][j]): the predicted squared relative errors.
@@ -422,7 +424,9 @@ hipError_t launch_need(const int32_t* bsel, int64_t nsel, const int32_t* pptr,
 
 hipError_t launch_cand_costs(const CostArgs& a, hipStream_t s) {
   if (a.nb == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_cand_costs, dim3((unsigned)((a.nb + 127) / 128)), dim3(128), 0, s, a);
+  if (a.ngroups < 1 || a.ngroups > kMaxThetaGroups) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_cand_costs, dim3((unsigned)((a.nb + 127) / 128), (unsigned)a.ngroups),
+                     dim3(128), 0, s, a);
   return hipGetLastError();
 }
 

@@ -1,7 +1,8 @@
 """GPU checks of the learned (n, theta) path through the C ABI: batch
 features and counts against the oracle's tree and lists, and the adaptive
-evaluation composed exactly of per-candidate fixed evaluations (including
-the batches the judge sends to the fallback)."""
+evaluation composed exactly of per-candidate fixed evaluations (the batches
+the judge sends to the fallback agree with the fallback evaluation up to the
+order of its FP64 accumulation)."""
 import numpy as np
 import pytest
 
@@ -127,6 +128,13 @@ def test_adaptive_constant_choice(torch, tmp_path, case):
     assert np.array_equal(out.cpu().numpy(), _fixed(torch, case, 6, 0.7))
 
 
+def _same_sums(a, b):
+    """Batches the judge re-evaluates run their proxy lists in slices on
+    separate waves, which changes only the order of the FP64 accumulation of
+    the per-cluster FP32 sums: equal to the one-wave evaluation to ~1e-16."""
+    return np.allclose(a, b, rtol=1e-12, atol=1e-12 * np.abs(b).max())
+
+
 def test_adaptive_judge_fallback(torch, tmp_path, case):
     """With a tolerance below FP32 rounding every batch fails the judge and is
     evaluated again with the fallback treecode."""
@@ -136,7 +144,7 @@ def test_adaptive_judge_fallback(torch, tmp_path, case):
                                                        sel, 1e-12, 10, 0.6)
     assert np.all(choice == -2) and stats[2] == case["G"].nb
     assert judge[1] < judge[0]
-    assert np.array_equal(out.cpu().numpy(), _fixed(torch, case, 10, 0.6, deg_min=0))
+    assert _same_sums(out.cpu().numpy(), _fixed(torch, case, 10, 0.6, deg_min=0))
     # every candidate predicted far above the budget: the cheapest is taken;
     # the judge sends the batches with the largest errors to the fallback, as
     # many as bring its estimate within the tolerance
@@ -151,7 +159,10 @@ def test_adaptive_judge_fallback(torch, tmp_path, case):
         ref = _fixed(torch, case, n, th, deg_min=selector.DEG_MIN if u >= 0 else 0)
         for b in np.where(choice2 == u)[0]:
             t = _targets_of(case["G"], b)
-            assert np.array_equal(out2[:, t], ref[:, t]), (u, b)
+            if u >= 0:
+                assert np.array_equal(out2[:, t], ref[:, t]), (u, b)
+            else:
+                assert _same_sums(out2[:, t], ref[:, t]), (u, b)
 
 
 def test_adaptive_is_per_batch_composition(torch, tmp_path, case):
@@ -176,7 +187,10 @@ def test_adaptive_is_per_batch_composition(torch, tmp_path, case):
                      deg_min=selector.DEG_MIN if u >= 0 else 0)
         for b in np.where(choice == u)[0]:
             t = _targets_of(case["G"], b)
-            assert np.array_equal(out[:, t], ref[:, t]), (u, b)
+            if u >= 0:
+                assert np.array_equal(out[:, t], ref[:, t]), (u, b)
+            else:
+                assert _same_sums(out[:, t], ref[:, t]), (u, b)
 
 
 @pytest.mark.parametrize("dist,kernel,tol", [("mixture", "stokeslet", 1e-5),
