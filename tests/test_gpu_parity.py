@@ -412,3 +412,18 @@ def test_full_edge_cases(torch, orc):
         bltc.evaluate_tree(T, G, "stokeslet", 0.01, 4, 0.7)
     assert e.value.status == 4   # and now six
     assert bltc.evaluate_tree(T, G, "full", 0.01, 4, 0.7).shape == (6, 3000)
+
+
+@pytest.mark.parametrize("name,n", [("e1", 12001), ("e2", 9060)])
+def test_paper_workloads_fp64(torch, orc, name, n):
+    """The paper's two workloads at small sizes: Example 1's pairs (Stokeslet)
+    and Example 2's helical rods (full kernel, a slab of 2- and 4-child
+    splits), FP64 and FP32 evaluation against the oracle."""
+    src, w, cfg = inputs.workload(name, n=n)
+    leaf = 300
+    got, ref = _tree_case(torch, orc, cfg["kernel"], src, src, w, cfg["eps"], cfg["degree"],
+                          cfg["theta"], leaf, 64, 32)
+    assert orc.rel_l2(ref, got) <= FP64_TOL
+    got32, _ = _tree_case(torch, orc, cfg["kernel"], src, src, w, cfg["eps"], cfg["degree"],
+                          cfg["theta"], leaf, 64, 32, precision="fp32_fp64acc")
+    assert orc.rel_l2(ref, got32) <= MIXED_TOL
