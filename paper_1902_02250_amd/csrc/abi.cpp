@@ -224,7 +224,7 @@ void destroy_tree(bltc_tree t) {
   if (!t) return;
   for (auto& kv : t->deg) destroy_degree(kv.second);
   dfree(t->d_perm); dfree(t->d_y); dfree(t->d_box); dfree(t->d_geo);
-  dfree(t->d_range); dfree(t->d_kids); dfree(t->d_w64); dfree(t->d_w32);
+  dfree(t->d_range); dfree(t->d_kids); dfree(t->d_skip); dfree(t->d_w64); dfree(t->d_w32);
   dfree(t->d_chunks); dfree(t->d_chunk_ptr); dfree(t->d_partial);
   dfree(t->d_need);
   delete t;
@@ -389,8 +389,6 @@ void build_tree(const double* x, const double* y, const double* z, int64_t n,
                 int64_t leaf_max, hipStream_t s, bltc_tree t) {
   build_device_tree(x, y, z, n, leaf_max, s, t->host, &t->d_y, &t->d_perm);
   const bltc::HostTree& H = t->host;
-  if (7 * (int64_t)H.depth + 1 > bltc::kStackMax)
-    throw HipError{BLTC_EINVAL, "tree deeper than the list walk supports"};
   const int64_t nn = H.nnodes();
   std::vector<double4> geo(nn);
   std::vector<int2> range(nn), kids(nn);
@@ -399,6 +397,12 @@ void build_tree(const double* x, const double* y, const double* z, int64_t n,
     range[q] = make_int2(H.begin[q], H.end[q]);
     kids[q] = make_int2(H.first[q], H.count[q]);
   }
+  // depth-first successor past each subtree: the next sibling, else the
+  // parent's successor (nodes are numbered breadth first, parents first)
+  std::vector<int32_t> skip(nn, -1);
+  for (int64_t q = 0; q < nn; ++q)
+    for (int32_t k = 0; k < H.count[q]; ++k)
+      skip[H.first[q] + k] = k + 1 < H.count[q] ? H.first[q] + k + 1 : skip[q];
   // upward-pass chunks: consecutive pieces of each cluster's particle range
   std::vector<int4> chunks;
   std::vector<int32_t> cptr(nn + 1);
@@ -414,12 +418,14 @@ void build_tree(const double* x, const double* y, const double* z, int64_t n,
   t->d_geo = dalloc<double4>(nn);
   t->d_range = dalloc<int2>(nn);
   t->d_kids = dalloc<int2>(nn);
+  t->d_skip = dalloc<int32_t>(nn);
   t->d_chunks = dalloc<int4>(chunks.size());
   t->d_chunk_ptr = dalloc<int32_t>(nn + 1);
   h2d(t->d_box, H.box.data(), 6 * nn, s);
   h2d(t->d_geo, geo.data(), nn, s);
   h2d(t->d_range, range.data(), nn, s);
   h2d(t->d_kids, kids.data(), nn, s);
+  h2d(t->d_skip, skip.data(), nn, s);
   h2d(t->d_chunks, chunks.data(), chunks.size(), s);
   h2d(t->d_chunk_ptr, cptr.data(), nn + 1, s);
   sync(s);   // the host staging vectors go out of scope
@@ -585,6 +591,7 @@ bltc::ListArgs list_args(bltc_tree t, bltc_targets g, double theta,
   a.nodes.geo = t->d_geo;
   a.nodes.range = t->d_range;
   a.nodes.kids = t->d_kids;
+  a.nodes.skip = t->d_skip;
   a.nodes.nn = t->host.nnodes();
   a.theta = theta;
   a.theta_b = theta_b;
@@ -727,6 +734,7 @@ void compute_features(bltc_tree t, bltc_targets g, int kernel, double eps,
   a.nodes.geo = t->d_geo;
   a.nodes.range = t->d_range;
   a.nodes.kids = t->d_kids;
+  a.nodes.skip = t->d_skip;
   a.nodes.nn = t->host.nnodes();
   a.box = t->d_box;
   a.theta_ref = theta_ref;
@@ -795,6 +803,7 @@ void candidate_costs(bltc_tree t, bltc_targets g, int k, const int32_t* cand_n,
     a.nodes.geo = t->d_geo;
     a.nodes.range = t->d_range;
     a.nodes.kids = t->d_kids;
+  a.nodes.skip = t->d_skip;
     a.nodes.nn = t->host.nnodes();
     a.ngroups = (int32_t)std::min<size_t>(bltc::kMaxThetaGroups, groups.size() - g0);
     for (int i = 0; i < a.ngroups; ++i) a.grp[i] = groups[g0 + i];

@@ -13,7 +13,6 @@ namespace bltc {
 
 constexpr int kMaxDegree = 12;
 constexpr int kWave = 64;
-constexpr int kStackMax = 512;       // depth-first stack of the list walk
 constexpr int kUpwardChunk = 2048;   // particles per upward-pass work group
 constexpr int kMlpIn = 12;           // selector network: features
 constexpr int kMlpHidden = 64;       // selector network: hidden width
@@ -73,6 +72,7 @@ struct Nodes {                 // device node arrays
   const double4* geo;          // center xyz, radius
   const int2* range;           // particle range [begin, end) in tree order
   const int2* kids;            // first child, child count
+  const int32_t* skip;         // next node in depth-first order after the subtree (-1: end)
   int64_t nn;
 };
 
@@ -105,7 +105,7 @@ struct ListArgs {
   const int32_t* dptr;
   int32_t* pids;
   int32_t* dids;
-  int32_t* err;                // set to 1 if a stack overflows
+  int32_t* err;                // error flag (unused by the stackless walk)
 };
 
 struct P2PArgs {
@@ -348,6 +348,7 @@ struct bltc_tree_s {
   double4* d_geo = nullptr;
   int2* d_range = nullptr;
   int2* d_kids = nullptr;
+  int32_t* d_skip = nullptr;   // depth-first successor past each subtree
   // weights
   bool has_w = false;
   int32_t wdim = 3;            // weight components: 3, or 6 for force and torque
@@ -384,7 +385,7 @@ struct bltc_targets_s {
   double* d_x = nullptr;       // tree-ordered [3][m]
   int32_t* d_bptr = nullptr;
   double4* d_bgeo = nullptr;
-  int32_t* d_flags = nullptr;  // [4]: stack overflow, scan overflow x2
+  int32_t* d_flags = nullptr;  // [4]: walk error, scan overflow x2
   bltc::ListSet ls[2];         // [0] evaluation lists, [1] guard lists
   // per-batch selection scratch (allocated on first adaptive call)
   float* d_feat = nullptr;     // [nb][12]

@@ -1,6 +1,7 @@
 // Interaction lists of the batch walk (Algorithm 2 shared by the targets of
 // a batch).  One thread walks the tree for one batch depth first, children
-// in their stored order, with an explicit stack:
+// in their stored order, following each node's first child or, past its
+// subtree, its depth-first successor (no stack):
 //   MAC holds          -> the cluster goes on the proxy list,
 //   else leaf          -> the cluster goes on the direct list,
 //   else               -> visit the children.
@@ -39,8 +40,6 @@ __global__ __launch_bounds__(128) void k_lists(ListArgs a) {
     rT = a.cand_T + (int64_t)j * (kMaxDegree + 1);
   }
   const double th2 = th * th;
-  int32_t stack[kStackMax];
-  int sp = 0;
   int32_t np = 0, nd = 0;
   int64_t ns = 0;   // near-field sources
   int32_t* pout = nullptr;
@@ -49,9 +48,8 @@ __global__ __launch_bounds__(128) void k_lists(ListArgs a) {
     pout = a.pids + a.pptr[b];
     dout = a.dids + a.dptr[b];
   }
-  if (a.nodes.nn > 0) stack[sp++] = 0;
-  while (sp > 0) {
-    const int32_t q = stack[--sp];
+  int32_t q = a.nodes.nn > 0 ? 0 : -1;
+  while (q >= 0) {
     const double4 c = a.nodes.geo[q];
     const double dx = g.x - c.x;
     const double dy = g.y - c.y;
@@ -70,6 +68,7 @@ __global__ __launch_bounds__(128) void k_lists(ListArgs a) {
         pout[np] = e;
       }
       ++np;
+      q = a.nodes.skip[q];
       continue;
     }
     const int2 kd = a.nodes.kids[q];
@@ -78,13 +77,10 @@ __global__ __launch_bounds__(128) void k_lists(ListArgs a) {
       ++nd;
       const int2 rg = a.nodes.range[q];
       ns += rg.y - rg.x;
+      q = a.nodes.skip[q];
       continue;
     }
-    if (sp + kd.y > kStackMax) {   // cannot happen for depth <= 70; guarded
-      *a.err = 1;
-      break;
-    }
-    for (int k = kd.y - 1; k >= 0; --k) stack[sp++] = kd.x + k;
+    q = kd.x;
   }
   if (!FILL) {
     a.pcnt[b] = np;

@@ -27,12 +27,9 @@ __global__ __launch_bounds__(128) void k_features(FeatArgs a) {
   const double R0 = root.w > 0.0 ? root.w : 1.0;
   const double tiny = 1e-12 * R0;
   const double th2 = a.theta_ref * a.theta_ref;
-  int32_t stack[kStackMax];
-  int sp = 0;
   double P = 0, L = 0, D = 0, slr = 0, stight = 0, vol = 0;
-  if (a.nodes.nn > 0) stack[sp++] = 0;
-  while (sp > 0) {
-    const int32_t q = stack[--sp];
+  int32_t q = a.nodes.nn > 0 ? 0 : -1;
+  while (q >= 0) {
     const double4 c = a.nodes.geo[q];
     const double dx = g.x - c.x, dy = g.y - c.y, dz = g.z - c.z;
     const double R2 = dx * dx + dy * dy + dz * dz;
@@ -41,6 +38,7 @@ __global__ __launch_bounds__(128) void k_features(FeatArgs a) {
       P += 1;
       slr += log10((c.w + tiny) / R0);
       stight += rr / (a.theta_ref * sqrt(R2));
+      q = a.nodes.skip[q];
       continue;
     }
     const int2 kd = a.nodes.kids[q];
@@ -50,10 +48,10 @@ __global__ __launch_bounds__(128) void k_features(FeatArgs a) {
       D += rg.y - rg.x;
       const double* bx = a.box + 6 * (int64_t)q;
       vol += (bx[3] - bx[0] + tiny) * (bx[4] - bx[1] + tiny) * (bx[5] - bx[2] + tiny);
+      q = a.nodes.skip[q];
       continue;
     }
-    if (sp + kd.y > kStackMax) break;
-    for (int k = kd.y - 1; k >= 0; --k) stack[sp++] = kd.x + k;
+    q = kd.x;
   }
   const double* rb = a.box;
   const double vroot = (rb[3] - rb[0] + tiny) * (rb[4] - rb[1] + tiny) * (rb[5] - rb[2] + tiny);
@@ -82,24 +80,29 @@ __global__ __launch_bounds__(128) void k_features(FeatArgs a) {
 // Modelled wave costs of the candidates (CostArgs): one walk per batch and
 // theta group (grid y); an accepted cluster at ratio^2 qq costs
 // (far n1 + row) n1^2 + clu with n1 - 1 the candidate's degree, or under the
-// separation rule the first d >= deg_min with qq <= T[d].  The candidate
-// loop is unrolled to kMaxPerTheta so the sums stay in registers; the theta
-// groups run in one launch so their walks overlap.
+// separation rule the first d >= deg_min with qq <= T[d] (binary search on
+// the thresholds, which grow with d, staged in LDS).  The candidate loop is
+// unrolled to kMaxPerTheta so the sums stay in registers; the theta groups
+// run in one launch so their walks overlap.
 __global__ __launch_bounds__(128) void k_cand_costs(CostArgs a) {
   const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= a.nb) return;
   const CostGroup& gr = a.grp[blockIdx.y];
+  // the group's rule thresholds, one row per candidate
+  __shared__ double sT[kMaxPerTheta][kMaxDegree + 1];
+  for (int i = threadIdx.x; i < kMaxPerTheta * (kMaxDegree + 1); i += blockDim.x) {
+    const int c = i / (kMaxDegree + 1), d = i % (kMaxDegree + 1);
+    sT[c][d] = c < gr.nc ? a.T[(int64_t)gr.row[c] * (kMaxDegree + 1) + d] : 0.0;
+  }
+  __syncthreads();
+  if (b >= a.nb) return;
   const double4 g = a.bgeo[b];
   const double th2 = gr.theta * gr.theta;
   float far[kMaxPerTheta];
 #pragma unroll
   for (int i = 0; i < kMaxPerTheta; ++i) far[i] = 0.f;
   double S = 0.0;
-  int32_t stack[kStackMax];
-  int sp = 0;
-  if (a.nodes.nn > 0) stack[sp++] = 0;
-  while (sp > 0) {
-    const int32_t q = stack[--sp];
+  int32_t q = a.nodes.nn > 0 ? 0 : -1;
+  while (q >= 0) {
     const double4 c = a.nodes.geo[q];
     const double dx = g.x - c.x;
     const double dy = g.y - c.y;
@@ -114,27 +117,30 @@ __global__ __launch_bounds__(128) void k_cand_costs(CostArgs a) {
           const int n = gr.deg[i];
           int d = n;
           if (a.deg_min > 0 && a.deg_min < n) {
-            const double* __restrict__ T = a.T + (int64_t)gr.row[i] * (kMaxDegree + 1);
-            d = a.deg_min;
-            while (d < n && !(qq <= T[d])) ++d;
+            // the first d in [deg_min, n) with qq <= T[d], else n (T grows with d)
+            int lo = a.deg_min, hi = n;
+            while (lo < hi) {
+              const int mid = (lo + hi) >> 1;
+              if (qq <= sT[i][mid]) hi = mid;
+              else lo = mid + 1;
+            }
+            d = lo;
           }
           const float n1 = (float)(d + 1);
           far[i] += (a.w.far * n1 + a.w.row) * n1 * n1 + a.w.clu;
         }
       }
+      q = a.nodes.skip[q];
       continue;
     }
     const int2 kd = a.nodes.kids[q];
     if (kd.y == 0) {
       const int2 rg = a.nodes.range[q];
       S += rg.y - rg.x;
+      q = a.nodes.skip[q];
       continue;
     }
-    if (sp + kd.y > kStackMax) {
-      *a.err = 1;
-      break;
-    }
-    for (int k = kd.y - 1; k >= 0; --k) stack[sp++] = kd.x + k;
+    q = kd.x;
   }
 #pragma unroll
   for (int i = 0; i < kMaxPerTheta; ++i)
