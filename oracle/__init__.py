@@ -276,14 +276,15 @@ def treecode(kernel, tgt, src, w, eps, degree, theta, leaf_max, mac_mode=0,
 
 
 def dual_treecode(kernel, tgt, src, w, eps, degree, theta, leaf_max, leaf_t, poly_p=0,
-                  poly_c=0.0):
+                  poly_c=0.0, deg_min=0):
     """The cluster-cluster variant (dual.c).  Returns (out (odim, m), counts)
     with counts = kernel evaluations of the CC, PC, CP and PP interactions
-    and the downward (target, grid point) terms."""
+    and the downward (target, grid point) terms.  deg_min >= 1 applies the
+    separation rule to the source side of CC and PC pairs."""
     tgt, src, w = _c(tgt), _c(src), _c(w)
     m, n = tgt.shape[1], src.shape[1]
     prm = _Params(KERNELS[kernel], float(eps), int(poly_p), float(poly_c),
-                  int(degree), float(theta), int(leaf_max), 0, 1, 1, 1, 0)
+                  int(degree), float(theta), int(leaf_max), 0, 1, 1, 1, int(deg_min))
     out = np.zeros((ODIM[kernel], m))
     cnt = np.zeros(5, np.int64)
     rc = _load().orc_dual_treecode(ctypes.byref(prm), int(leaf_t), _p(tgt[0]), _p(tgt[1]),

@@ -26,6 +26,11 @@
  * Algorithm 1 (the interpolation of eq. pc_approximation_3D applied to the
  * target variable).
  *
+ * With the separation rule (p->deg_min >= 1, see treecode.c) the source
+ * side of a CC or PC pair uses the degree orc_rule_degree gives the pair's
+ * ratio (r_A + r_C)/R; target grids, the size tests and the downward
+ * interpolation keep the degree n.
+ *
  * Summation order: pairs in traversal order; grid points and proxies with k3
  * fastest; particles in tree order; then the clusters holding a target, in
  * node order.
@@ -54,7 +59,9 @@ typedef struct {
   int64_t P;
   side_t s, t;
   double* ws;     /* tree-ordered source weights [wdim][n] */
-  double* fhat;   /* [nn_s][wdim][P] */
+  double T[ORC_MAX_DEGREE + 1];       /* separation-rule thresholds */
+  double* sgrid[ORC_MAX_DEGREE + 1];  /* per degree d: source grids [nn_s][3][d+1] */
+  double* fhat[ORC_MAX_DEGREE + 1];   /* per degree d: [nn_s][wdim][(d+1)^3] */
   double* g;      /* [nn_t][P][odim] */
   char* has_g;    /* [nn_t] */
   double* u;      /* [nt][odim], target tree order */
@@ -113,9 +120,15 @@ static void source_point(const dual_ctx* c, int64_t j, double y[3], double f[6])
   for (int k = 0; k < c->wdim; ++k) f[k] = c->ws[k * n + j];
 }
 
-static void proxy(const dual_ctx* c, int64_t q, int64_t k, double s[3], double f[6]) {
-  grid_point(&c->s, c->n1, q, k, s);
-  for (int a = 0; a < c->wdim; ++a) f[a] = c->fhat[(q * c->wdim + a) * c->P + k];
+/* proxy k of source cluster q at degree d */
+static void proxy(const dual_ctx* c, int d, int64_t q, int64_t k, double s[3], double f[6]) {
+  const int n1 = d + 1;
+  const int64_t nk = (int64_t)n1 * n1 * n1;
+  const double* g = c->sgrid[d] + q * 3 * n1;
+  s[0] = g[k / (n1 * n1)];
+  s[1] = g[n1 + (k / n1) % n1];
+  s[2] = g[2 * n1 + k % n1];
+  for (int a = 0; a < c->wdim; ++a) f[a] = c->fhat[d][(q * c->wdim + a) * nk + k];
 }
 
 static void target_point(const dual_ctx* c, int64_t i, double x[3]) {
@@ -142,27 +155,30 @@ static void interact(dual_ctx* c, int64_t A, int64_t C) {
   const double th = c->p->theta;
   const int mac = R2 > 0.0 && rr * rr <= (th * th) * R2;
   const int leafA = T->count[A] == 0, leafC = S->count[C] == 0;
+  /* the source side's degree under the separation rule (n when it is off) */
+  const int d = mac ? orc_rule_degree(c->p, c->T, rr, R2) : c->n1 - 1;
+  const int64_t Pd = (int64_t)(d + 1) * (d + 1) * (d + 1);
   double x[3], y[3], f[6];
   if (mac && na > c->P && nc > c->P) {                 /* CC */
     for (int64_t m = 0; m < c->P; ++m) {
       grid_point(T, c->n1, A, m, x);
       double* gm = c->g + (A * c->P + m) * c->odim;
-      for (int64_t k = 0; k < c->P; ++k) {
-        proxy(c, C, k, y, f);
+      for (int64_t k = 0; k < Pd; ++k) {
+        proxy(c, d, C, k, y, f);
         add_pair(c, x, y, f, gm);
       }
     }
     c->has_g[A] = 1;
-    c->cnt[0] += c->P * c->P;
+    c->cnt[0] += c->P * Pd;
   } else if (mac && nc > c->P) {                       /* PC */
     for (int64_t i = T->pb[A]; i < T->pe[A]; ++i) {
       target_point(c, i, x);
-      for (int64_t k = 0; k < c->P; ++k) {
-        proxy(c, C, k, y, f);
+      for (int64_t k = 0; k < Pd; ++k) {
+        proxy(c, d, C, k, y, f);
         add_pair(c, x, y, f, c->u + i * c->odim);
       }
     }
-    c->cnt[1] += na * c->P;
+    c->cnt[1] += na * Pd;
   } else if (mac && na > c->P) {                       /* CP */
     for (int64_t m = 0; m < c->P; ++m) {
       grid_point(T, c->n1, A, m, x);
@@ -226,6 +242,7 @@ int orc_dual_treecode(const orc_params* p, int64_t leaf_t,
   c.n1 = p->degree + 1;
   c.P = (int64_t)c.n1 * c.n1 * c.n1;
   if (orc_kernel_dims(p->kernel, &c.wdim, &c.odim)) return -1;
+  orc_rule_table(p, c.T);
   int rc = side_init(&c.s, sx, sy, sz, n, p->leaf_max, c.n1);
   if (!rc) rc = side_init(&c.t, tx, ty, tz, m, leaf_t, c.n1);
   if (!rc) {
@@ -234,12 +251,21 @@ int orc_dual_treecode(const orc_params* p, int64_t leaf_t,
     c.ws = malloc(sizeof(double) * c.wdim * n_1);
     for (int64_t i = 0; i < n; ++i)
       for (int k = 0; k < c.wdim; ++k) c.ws[k * n + i] = w[k * n + c.s.perm[i]];
-    c.fhat = calloc((size_t)(nn_s * c.wdim * c.P), sizeof(double));
     c.g = calloc((size_t)(nn_t * c.P * c.odim), sizeof(double));
     c.has_g = calloc((size_t)nn_t, 1);
     c.u = calloc((size_t)(m_1 * c.odim), sizeof(double));
+    /* source grids and modified weights of every degree the rule can give */
     orc_tree* st = orc_tree_new(sx, sy, sz, n, p->leaf_max);
-    if (n > 0) rc = orc_modified_weights(st, sx, sy, sz, w, c.wdim, p->degree, 0, c.fhat);
+    const int dlo = p->deg_min >= 1 && p->deg_min < p->degree ? p->deg_min : p->degree;
+    for (int d = dlo; d <= p->degree && !rc; ++d) {
+      const int64_t n1 = d + 1;
+      c.sgrid[d] = calloc((size_t)(nn_s * 3 * n1), sizeof(double));
+      c.fhat[d] = calloc((size_t)(nn_s * c.wdim * n1 * n1 * n1), sizeof(double));
+      if (n > 0) {
+        orc_cluster_grids(st, d, c.sgrid[d]);
+        rc = orc_modified_weights(st, sx, sy, sz, w, c.wdim, d, 0, c.fhat[d]);
+      }
+    }
     orc_tree_free(st);
     if (!rc && n > 0 && m > 0) {
       interact(&c, 0, 0);
@@ -249,7 +275,8 @@ int orc_dual_treecode(const orc_params* p, int64_t leaf_t,
       for (int k = 0; k < c.odim; ++k) out[k * m + c.t.perm[i]] = c.u[i * c.odim + k];
     if (counts) memcpy(counts, c.cnt, sizeof c.cnt);
   }
-  free(c.ws); free(c.fhat); free(c.g); free(c.has_g); free(c.u);
+  free(c.ws); free(c.g); free(c.has_g); free(c.u);
+  for (int d = 0; d <= ORC_MAX_DEGREE; ++d) { free(c.sgrid[d]); free(c.fhat[d]); }
   side_free(&c.s);
   side_free(&c.t);
   return rc;

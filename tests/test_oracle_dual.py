@@ -67,3 +67,21 @@ def test_dual_full_is_sum_of_parts(orc):
     rf, _ = run("rotlet", np.ascontiguousarray(w6[:3]))
     ref = np.concatenate([sf + rn[:3], rf[:3] + rn[3:]])
     assert orc.rel_l2(ref, full) <= 1e-13
+
+
+def test_dual_rule_poly_exact(orc):
+    """Separation rule on the source side: every degree used is at least
+    deg_min = p, so (c + x.y)^p stays exact, while the evaluation counts of
+    the CC and PC parts fall below those of the fixed degree."""
+    src = inputs.points("mixture", 20000, 86)
+    tgt = inputs.points("uniform", 19000, 87)
+    w = inputs.weights(20000, 86)
+    got, cnt = orc.dual_treecode("poly", tgt, src, w, 0.0, 5, 0.8, 40, 40, poly_p=2,
+                                 poly_c=0.5, deg_min=2)
+    fixed, cnt0 = orc.dual_treecode("poly", tgt, src, w, 0.0, 5, 0.8, 40, 40, poly_p=2,
+                                    poly_c=0.5)
+    assert cnt[0] > 0 and cnt[1] > 0
+    assert cnt[0] < cnt0[0] and cnt[1] < cnt0[1]
+    assert cnt[2] == cnt0[2] and cnt[3] == cnt0[3] and cnt[4] == cnt0[4]
+    d = orc.direct("poly", tgt, src, w, poly_p=2, poly_c=0.5)
+    assert orc.rel_l2(d, got) <= 1e-12
