@@ -1,0 +1,44 @@
+"""Parity at the full sizes of the workloads, in the launch configuration
+the benchmark times (batches of 64 targets, order leaf 32, groups of 512):
+the GPU treecode's outputs at 2,000 sampled targets against the oracle's
+treecode evaluated at the same targets one by one (same tree, same batch
+MAC).  FP64 to 1e-12; FP32 evaluation with FP64 accumulation to 1e-6."""
+import numpy as np
+import pytest
+
+from paper_1902_02250_amd import bltc, inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available()
+    bltc.load()
+    return t
+
+
+@pytest.mark.parametrize("name", ["c3", "c4", "e2"])
+def test_full_size_sampled(torch, orc, name):
+    src, w, cfg = inputs.workload(name)
+    n = src.shape[1]
+    print(f"[fullsize] {name}: n={n} {cfg['kernel']} degree={cfg['degree']} "
+          f"theta={cfg['theta']} leaf={cfg['leaf']}", flush=True)
+    d_src = torch.from_numpy(src).cuda()
+    d_w = torch.from_numpy(w).cuda()
+    T = bltc.Tree(d_src, cfg["leaf"])
+    T.compute_weights(d_w, cfg["degree"])
+    G = bltc.Targets(d_src, 64, 32, 512)
+    idx = inputs.sample_indices(n, 2000, 3)
+    ref, _, _ = orc.treecode(cfg["kernel"], src, src, w, cfg["eps"], cfg["degree"],
+                             cfg["theta"], cfg["leaf"], mac_mode=1, batch_size=64, order_leaf=32,
+                             group_max=512, sample=idx)
+    d_idx = torch.from_numpy(idx).cuda()
+    for precision, tol in (("fp64", 1e-12), ("fp32_fp64acc", 1e-6)):
+        out = bltc.evaluate_tree(T, G, cfg["kernel"], cfg["eps"], cfg["degree"], cfg["theta"],
+                                 precision=precision)
+        got = out[:, d_idx].cpu().numpy()
+        err = orc.rel_l2(ref, got)
+        print(f"[fullsize] {name} {precision}: rel L2 vs oracle {err:.3e}", flush=True)
+        assert err <= tol, (precision, err)
