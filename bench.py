@@ -113,8 +113,8 @@ def main():
                     help="n,theta,deg_min;... settings also timed, with their error, "
                          "beside the headline configuration ('' for none)")
     ap.add_argument("--dual-settings", default="",
-                    help="cluster-cluster variant settings 'n,theta,target_leaf;...' timed "
-                         "after the headline")
+                    help="cluster-cluster variant settings 'n,theta,target_leaf[,deg_min];...' "
+                         "timed after the headline")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first run one device-to-device copy of MIB MiB, the reference "
                          "for scaling HBM byte counters")
@@ -293,14 +293,15 @@ def main():
     # the cluster-cluster variant on the same workload (targets = sources)
     dual = []
     for item in [t for t in args.dual_settings.split(";") if t.strip()]:
-        dn, th, lt = item.split(",")
-        dn, th, lt = int(dn), float(th), int(lt)
+        f = item.split(",")
+        dn, th, lt = int(f[0]), float(f[1]), int(f[2])
+        dm = int(f[3]) if len(f) > 3 else 0
         ttree = bltc.Tree(d_src, lt)
 
-        def dstep(dn=dn, th=th):
+        def dstep(dn=dn, th=th, dm=dm):
             tree.compute_weights(d_w, dn)
             return bltc.evaluate_dual(tree, ttree, kernel, eps, dn, th, precision=args.precision,
-                                      out=out)[1]
+                                      out=out, deg_min=dm)[1]
         cnt = dstep()
         torch.cuda.synchronize()
         xs = max(2, args.steps // 2)
@@ -315,12 +316,12 @@ def main():
         dprof = bltc.profile_read(reset=True)
         xms = e0.elapsed_time(e1) / xs
         xerrs = errors(out[:, d_idx])
-        dual.append({"degree": dn, "theta": th, "target_leaf": lt, "steps": xs,
+        dual.append({"degree": dn, "theta": th, "target_leaf": lt, "deg_min": dm, "steps": xs,
                      "ms_per_step": round(xms, 4), **xerrs,
                      "evaluations": {"cc": int(cnt[0]), "pc": int(cnt[1]), "cp": int(cnt[2]),
                                      "pp": int(cnt[3]), "downward": int(cnt[4])},
                      "stage_ms": {s: round(v[0] / max(v[1], 1), 4) for s, v in dprof.items()}})
-        log(f"[bench] dual n={dn} theta={th} target leaf={lt}: {xms:.3f} ms/step, "
+        log(f"[bench] dual n={dn} theta={th} target leaf={lt} deg_min={dm}: {xms:.3f} ms/step, "
             f"E={xerrs['rel_l2_err']:.3e}, evaluations {cnt.tolist()}")
     res["dual"] = dual
     if not args.no_cpu_baseline:

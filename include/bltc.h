@@ -214,8 +214,11 @@ int bltc_evaluate_tree(bltc_tree t, bltc_targets g, int32_t kernel, double eps,
  * exact-hit rule of Algorithm 1).  out: FP64 [odim][m] in the target tree's
  * caller order.  counts (host int64 [5], may be NULL): kernel evaluations of
  * the CC, PC, CP and PP interactions and the downward (target, grid point)
- * terms.  opt->deg_min must be 0.  The traversal and its lists are built on
- * the host; synchronises on stream. */
+ * terms.  With opt->deg_min >= 1 the separation rule (see bltc_options)
+ * picks the degree of the source side of each CC and PC pair from the
+ * pair's ratio (r_A + r_C)/R; target grids and the downward interpolation
+ * keep `degree`.  The traversal and its lists are built on the host;
+ * synchronises on stream. */
 int bltc_evaluate_dual(bltc_tree src, bltc_tree tgt, int32_t kernel, double eps,
                        int32_t degree, double theta, const bltc_options* opt, double* out,
                        int64_t* counts, void* stream);

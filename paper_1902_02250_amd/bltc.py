@@ -300,16 +300,17 @@ def evaluate(tgt, src, w, kernel, eps, degree, theta, leaf_max, precision="fp64"
 
 
 def evaluate_dual(src_tree, tgt_tree, kernel, eps, degree, theta, precision="fp32_fp64acc",
-                  poly_p=2, poly_c=1.0, out=None):
+                  poly_p=2, poly_c=1.0, out=None, deg_min=0):
     """Cluster-cluster variant: src_tree with modified weights of `degree`,
-    tgt_tree built on the targets.  Returns (out (odim, m), counts[5])."""
+    tgt_tree built on the targets.  Returns (out (odim, m), counts[5]).
+    deg_min >= 1 applies the separation rule to the source side."""
     torch = _torch()
     od = ODIM[kernel]
     m = tgt_tree.n
     if out is None:
         out = torch.empty((od, m), dtype=torch.float64, device="cuda")
     _dev(out, "out", od)
-    o = options(precision, 64, 32, poly_p, poly_c)
+    o = options(precision, 64, 32, poly_p, poly_c, deg_min=deg_min)
     cnt = np.zeros(5, np.int64)
     _check(load().bltc_evaluate_dual(src_tree._h, tgt_tree._h, KERNELS[kernel], float(eps),
                                      int(degree), float(theta), ctypes.byref(o),

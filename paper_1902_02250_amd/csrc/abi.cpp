@@ -894,7 +894,7 @@ struct DualPlan {
 };
 
 void dual_traverse(const bltc::HostTree& T, const bltc::HostTree& S, int n1, double theta,
-                   DualPlan& D) {
+                   const bltc::Rule& rule, DualPlan& D) {
   const int64_t ntn = T.nnodes();
   D.cc.assign(ntn, {});
   D.cp.assign(ntn, {});
@@ -914,12 +914,22 @@ void dual_traverse(const bltc::HostTree& T, const bltc::HostTree& S, int n1, dou
     const double rr = T.rad[A] + S.rad[C];
     const bool mac = R2 > 0.0 && rr * rr <= (theta * theta) * R2;
     const bool leafA = T.count[A] == 0, leafC = S.count[C] == 0;
+    // the source side's degree under the separation rule (n - 1 when off):
+    // the entry carries it above kDegShift
+    int d = n1 - 1;
+    if (mac && rule.deg_min > 0) {
+      const double qq = (rr * rr) / R2;
+      d = rule.deg_min;
+      while (d < rule.degree && !(qq <= rule.T[d])) ++d;
+    }
+    const int64_t Pd = (int64_t)(d + 1) * (d + 1) * (d + 1);
+    const int32_t e = rule.deg_min > 0 ? (C | (d << bltc::kDegShift)) : C;
     if (mac && na > P && nc > P) {
-      D.cc[A].push_back(C);
-      D.cnt[0] += P * P;
+      D.cc[A].push_back(e);
+      D.cnt[0] += P * Pd;
     } else if (mac && nc > P) {
-      D.pc[A].push_back(C);
-      D.cnt[1] += na * P;
+      D.pc[A].push_back(e);
+      D.cnt[1] += na * Pd;
     } else if (mac && na > P) {
       D.cp[A].push_back(C);
       D.cnt[2] += P * nc;
@@ -949,7 +959,10 @@ void evaluate_dual(bltc_tree src, bltc_tree tgt, int kernel, double eps, int deg
 
   StageTimer lt(BLTC_STAGE_LISTS, s);
   DualPlan D;
-  dual_traverse(T, S, n1, theta, D);
+  const bltc::Rule rule = make_rule(theta, degree, o.deg_min);
+  if (rule.deg_min > 0 && S.nnodes() > bltc::kIdMask)
+    throw HipError{BLTC_EINVAL, "too many source clusters for the separation rule's encoding"};
+  dual_traverse(T, S, n1, theta, rule, D);
   // grid slots: target clusters with CC or CP work
   // (their grid points are evaluated as targets in batches of 64: CC
   // clusters on the proxy list, CP clusters on the direct list)
@@ -1056,6 +1069,22 @@ void evaluate_dual(bltc_tree src, bltc_tree tgt, int kernel, double eps, int deg
   hipchk(bltc::launch_grids(tgt->d_box, ntn, degree, tk, d_tgrid.p, s), "target grids");
   hipchk(bltc::launch_dual_points(d_gnode.p, ng, n1, d_tgrid.p, d_gpts.p, s), "grid points");
   lt.stop();
+  // the rule's lower degrees, for the source clusters that use them
+  if (rule.deg_min > 0) {
+    const int64_t nns = S.nnodes();
+    std::vector<std::vector<uint8_t>> need(degree, std::vector<uint8_t>(nns, 0));
+    for (int64_t A = 0; A < ntn; ++A)
+      for (const auto* lst : {&D.cc[A], &D.pc[A]})
+        for (int32_t e : *lst) {
+          const int dd = e >> bltc::kDegShift;
+          if (dd < degree) need[dd][e & bltc::kIdMask] = 1;
+        }
+    if (!src->d_need) src->d_need = dalloc<uint8_t>(nns);
+    for (int dd = rule.deg_min; dd < degree; ++dd) {
+      h2d(src->d_need, need[dd].data(), nns, s);
+      ensure_degree(src, dd, s, src->d_need);
+    }
+  }
 
   StageTimer ev(BLTC_STAGE_EVAL, s);
   // the particle-cluster kernel over a point set: batches bp/bg, proxy
@@ -1078,6 +1107,13 @@ void evaluate_dual(bltc_tree src, bltc_tree tgt, int kernel, double eps, int deg
     a.range = src->d_range;
     a.grid = d.grid;
     a.fhat = o.precision == BLTC_FP64 ? (const void*)d.p2p64 : (const void*)d.p2p32;
+    if (rule.deg_min > 0) {
+      for (int dd = rule.deg_min; dd <= degree; ++dd) {
+        const bltc_degree_data& e = src->deg.at(dd);
+        a.grid_d[dd] = e.grid;
+        a.fhat_d[dd] = o.precision == BLTC_FP64 ? (const void*)e.p2p64 : (const void*)e.p2p32;
+      }
+    }
     a.ys = src->d_y;
     a.w64 = src->d_w64;
     a.w32 = src->d_w32;
@@ -1715,8 +1751,6 @@ int bltc_evaluate_dual(bltc_tree src, bltc_tree tgt, int32_t kernel, double eps,
   bltc_options_default(&o);
   if (opt) o = *opt;
   if (int rc = check_options(&o, kernel)) return rc;
-  if (o.deg_min != 0)
-    return fail(BLTC_EINVAL, "the cluster-cluster variant has no separation rule (deg_min 0)");
   if (tgt->n > 0 && !device_ptr(out)) return fail(BLTC_EINVAL, "out must be a device pointer");
   if (!src->has_w) return fail(BLTC_ESTATE, "no weights: call bltc_compute_modified_weights first");
   if (src->wdim != wdim_of(kernel))

@@ -94,13 +94,40 @@ def test_dual_edges(torch, orc):
     got, cnt = _run(torch, "stokeslet", src, src, w, 0.01, 3, 0.0, 20, 20)
     assert cnt[0] == cnt[1] == cnt[2] == 0
     assert orc.rel_l2(orc.direct("stokeslet", src, src, w, eps=0.01), got) <= FP64_TOL
-    # the separation rule is not part of this variant; weights must fit
+    # weights must fit the kernel
     T = bltc.Tree(_d(torch, src), 20)
-    o = bltc.options("fp64", deg_min=2)
+    o = bltc.options("fp64", deg_min=13)
     buf = torch.empty((3, 3000), dtype=torch.float64, device="cuda")
     rc = bltc.load().bltc_evaluate_dual(S._h, T._h, 0, 0.01, 3, 0.7, ctypes.byref(o),
                                         ctypes.c_void_p(buf.data_ptr()), None, None)
-    assert bltc.STATUS[rc] == "EINVAL"
+    assert bltc.STATUS[rc] == "EINVAL"   # deg_min out of range
     with pytest.raises(bltc.BltcError) as e:
         bltc.evaluate_dual(S, T, "full", 0.01, 3, 0.7)
     assert e.value.status == 4
+
+
+@pytest.mark.parametrize("kernel,precision,tol", [("stokeslet", "fp64", FP64_TOL),
+                                                  ("full", "fp64", FP64_TOL),
+                                                  ("rotlet", "fp32_fp64acc", MIXED_TOL)])
+def test_dual_rule_matches_oracle(torch, orc, kernel, precision, tol):
+    """The separation rule on the source side of CC and PC pairs: the same
+    degrees as the oracle (counts exact) and the same results."""
+    src = inputs.points("mixture", 20000, 97)
+    tgt = inputs.points("uniform", 15001, 98)
+    w = inputs.weights(20000, 97, bltc.WDIM[kernel])
+    got, cnt = _run(torch, kernel, src, tgt, w, 0.01, 5, 0.8, 40, 40, precision, deg_min=2)
+    ref, rcnt = orc.dual_treecode(kernel, tgt, src, w, 0.01, 5, 0.8, 40, 40, deg_min=2)
+    assert np.array_equal(cnt, rcnt), (cnt, rcnt)
+    _, cnt0 = orc.dual_treecode(kernel, tgt, src, w, 0.01, 5, 0.8, 40, 40)
+    assert cnt[0] < cnt0[0] and cnt[1] < cnt0[1]
+    assert orc.rel_l2(ref, got) <= tol
+
+
+def test_dual_rule_poly_exact(torch, orc):
+    src = inputs.points("mixture", 20000, 99)
+    tgt = inputs.points("uniform", 19000, 100)
+    w = inputs.weights(20000, 99)
+    got, cnt = _run(torch, "poly", src, tgt, w, 0.0, 5, 0.8, 40, 40, poly_p=2, poly_c=0.5,
+                    deg_min=2)
+    d = orc.direct("poly", tgt, src, w, poly_p=2, poly_c=0.5)
+    assert orc.rel_l2(d, got) <= FP64_TOL
