@@ -1,6 +1,6 @@
 """Parity at the full sizes of the workloads, in the launch configuration
 the benchmark times (batches of 64 targets, order leaf 32, groups of 512):
-the GPU treecode's outputs at 2,000 sampled targets against the oracle's
+the GPU treecode's outputs at 2,000 (1,000 for 4e6) sampled targets against the oracle's
 treecode evaluated at the same targets one by one (same tree, same batch
 MAC).  FP64 to 1e-12; FP32 evaluation with FP64 accumulation to 1e-6."""
 import numpy as np
@@ -19,9 +19,14 @@ def torch():
     return t
 
 
-@pytest.mark.parametrize("name", ["c3", "c4", "e2"])
-def test_full_size_sampled(torch, orc, name):
+@pytest.mark.parametrize("name,kernel", [("c3", None), ("c4", None), ("e2", None),
+                                         ("c5", None), ("c2", "stokeslet"), ("c2", "rotlet")])
+def test_full_size_sampled(torch, orc, name, kernel):
+    """c5 is the 4e6 union at the fallback setting (n = 10, theta = 0.6); c2
+    the 100K uniform set at n = 6, theta = 0.7 for both kernels."""
     src, w, cfg = inputs.workload(name)
+    if kernel:
+        cfg["kernel"] = kernel
     n = src.shape[1]
     print(f"[fullsize] {name}: n={n} {cfg['kernel']} degree={cfg['degree']} "
           f"theta={cfg['theta']} leaf={cfg['leaf']}", flush=True)
@@ -30,7 +35,7 @@ def test_full_size_sampled(torch, orc, name):
     T = bltc.Tree(d_src, cfg["leaf"])
     T.compute_weights(d_w, cfg["degree"])
     G = bltc.Targets(d_src, 64, 32, 512)
-    idx = inputs.sample_indices(n, 2000, 3)
+    idx = inputs.sample_indices(n, 1000 if n > 2000000 else 2000, 3)
     ref, _, _ = orc.treecode(cfg["kernel"], src, src, w, cfg["eps"], cfg["degree"],
                              cfg["theta"], cfg["leaf"], mac_mode=1, batch_size=64, order_leaf=32,
                              group_max=512, sample=idx)
