@@ -964,8 +964,9 @@ void evaluate_dual(bltc_tree src, bltc_tree tgt, int kernel, double eps, int deg
     throw HipError{BLTC_EINVAL, "too many source clusters for the separation rule's encoding"};
   dual_traverse(T, S, n1, theta, rule, D);
   // grid slots: target clusters with CC or CP work
-  // (their grid points are evaluated as targets in batches of 64: CC
-  // clusters on the proxy list, CP clusters on the direct list)
+  // (their grid points are evaluated as targets, one batch per cluster run
+  // by several waves: CC clusters on the proxy list, CP clusters on the
+  // direct list)
   std::vector<int32_t> slot(ntn, -1), gnode;
   std::vector<int32_t> gbptr, gpptr{0}, gpids, gdptr{0}, gdids;
   std::vector<double4> gbgeo;
@@ -974,14 +975,12 @@ void evaluate_dual(bltc_tree src, bltc_tree tgt, int kernel, double eps, int deg
     const int32_t gi = (int32_t)gnode.size();
     slot[A] = gi;
     gnode.push_back((int32_t)A);
-    for (int64_t m0 = 0; m0 < P; m0 += bltc::kWave) {
-      gbptr.push_back((int32_t)(gi * P + m0));
-      gbgeo.push_back(make_double4(T.ctr[3 * A], T.ctr[3 * A + 1], T.ctr[3 * A + 2], T.rad[A]));
-      gpids.insert(gpids.end(), D.cc[A].begin(), D.cc[A].end());
-      gpptr.push_back((int32_t)gpids.size());
-      gdids.insert(gdids.end(), D.cp[A].begin(), D.cp[A].end());
-      gdptr.push_back((int32_t)gdids.size());
-    }
+    gbptr.push_back((int32_t)(gi * P));
+    gbgeo.push_back(make_double4(T.ctr[3 * A], T.ctr[3 * A + 1], T.ctr[3 * A + 2], T.rad[A]));
+    gpids.insert(gpids.end(), D.cc[A].begin(), D.cc[A].end());
+    gpptr.push_back((int32_t)gpids.size());
+    gdids.insert(gdids.end(), D.cp[A].begin(), D.cp[A].end());
+    gdptr.push_back((int32_t)gdids.size());
     D.cnt[4] += (int64_t)(T.end[A] - T.begin[A]) * P;
   }
   const int64_t ng = (int64_t)gnode.size(), M = ng * P, gnb = (int64_t)gbgeo.size();
@@ -990,9 +989,9 @@ void evaluate_dual(bltc_tree src, bltc_tree tgt, int kernel, double eps, int deg
   gbptr.push_back((int32_t)M);
   std::vector<int32_t> giota(M);
   std::iota(giota.begin(), giota.end(), 0);
-  // batches of at most 64 targets inside each target leaf, leaves in
-  // position order; a batch takes the PC and PP entries and the grid slots
-  // of its leaf and all the leaf's ancestors
+  // one batch per target leaf (run by several waves of 64 targets), leaves
+  // in position order; it takes the PC and PP entries and the grid slots of
+  // the leaf and all its ancestors
   std::vector<int32_t> parent(ntn, -1), leaves;
   for (int64_t q = 0; q < ntn; ++q) {
     for (int32_t k = 0; k < T.count[q]; ++k) parent[T.first[q] + k] = (int32_t)q;
@@ -1003,6 +1002,7 @@ void evaluate_dual(bltc_tree src, bltc_tree tgt, int kernel, double eps, int deg
   std::vector<int32_t> bptr, pptr{0}, pids, dptr{0}, dids, xptr{0}, xgi, xnode, path;
   std::vector<double4> bgeo;
   std::vector<int32_t> lpc, lpp, lgi, lnode;
+  int64_t lmax = 1;
   for (int32_t L : leaves) {
     path.clear();
     for (int32_t q = L; q >= 0; q = parent[q]) path.push_back(q);
@@ -1019,19 +1019,20 @@ void evaluate_dual(bltc_tree src, bltc_tree tgt, int kernel, double eps, int deg
         lnode.push_back(q);
       }
     }
-    for (int64_t b0 = T.begin[L]; b0 < T.end[L]; b0 += bltc::kWave) {
-      bptr.push_back((int32_t)b0);
-      bgeo.push_back(make_double4(T.ctr[3 * L], T.ctr[3 * L + 1], T.ctr[3 * L + 2], T.rad[L]));
-      pids.insert(pids.end(), lpc.begin(), lpc.end());
-      pptr.push_back((int32_t)pids.size());
-      dids.insert(dids.end(), lpp.begin(), lpp.end());
-      dptr.push_back((int32_t)dids.size());
-      xgi.insert(xgi.end(), lgi.begin(), lgi.end());
-      xnode.insert(xnode.end(), lnode.begin(), lnode.end());
-      xptr.push_back((int32_t)xgi.size());
-    }
+    bptr.push_back(T.begin[L]);
+    bgeo.push_back(make_double4(T.ctr[3 * L], T.ctr[3 * L + 1], T.ctr[3 * L + 2], T.rad[L]));
+    pids.insert(pids.end(), lpc.begin(), lpc.end());
+    pptr.push_back((int32_t)pids.size());
+    dids.insert(dids.end(), lpp.begin(), lpp.end());
+    dptr.push_back((int32_t)dids.size());
+    xgi.insert(xgi.end(), lgi.begin(), lgi.end());
+    xnode.insert(xnode.end(), lnode.begin(), lnode.end());
+    xptr.push_back((int32_t)xgi.size());
+    lmax = std::max<int64_t>(lmax, T.end[L] - T.begin[L]);
   }
   const int64_t nb = (int64_t)bgeo.size();
+  const int wpb_t = (int)((lmax + bltc::kWave - 1) / bltc::kWave);
+  const int wpb_g = (int)((P + bltc::kWave - 1) / bltc::kWave);
   bptr.push_back((int32_t)m);
   if (pids.size() > (size_t)INT32_MAX || dids.size() > (size_t)INT32_MAX)
     throw HipError{BLTC_EINVAL, "cluster-cluster lists exceed 2^31 entries"};
@@ -1090,7 +1091,7 @@ void evaluate_dual(bltc_tree src, bltc_tree tgt, int kernel, double eps, int deg
   // the particle-cluster kernel over a point set: batches bp/bg, proxy
   // lists pp/pi, direct lists dp/di, output dst [odim][mm] via tperm
   auto p2p = [&](const double* tx, int64_t mm, const int32_t* tperm, const int32_t* bp,
-                 const double4* bg, int64_t nbb, const int32_t* pp, const int32_t* pi,
+                 const double4* bg, int64_t nbb, int wpb, const int32_t* pp, const int32_t* pi,
                  const int32_t* dp, const int32_t* di, double* dst) {
     bltc::P2PArgs a;
     a.tx = tx;
@@ -1099,7 +1100,7 @@ void evaluate_dual(bltc_tree src, bltc_tree tgt, int kernel, double eps, int deg
     a.bptr = bp;
     a.bgeo = bg;
     a.nb = nbb;
-    a.wpb = 1;
+    a.wpb = wpb;
     a.pptr = pp;
     a.pids = pi;
     a.dptr = dp;
@@ -1127,15 +1128,16 @@ void evaluate_dual(bltc_tree src, bltc_tree tgt, int kernel, double eps, int deg
   };
   // grid potentials g_A at the target clusters' grid points (CC and CP)
   if (gnb > 0)
-    p2p(d_gpts.p, M, d_giota.p, d_gbptr.p, d_gbgeo.p, gnb, d_gpptr.p, d_gpids.p, d_gdptr.p,
-        d_gdids.p, d_g.p);
+    p2p(d_gpts.p, M, d_giota.p, d_gbptr.p, d_gbgeo.p, gnb, wpb_g, d_gpptr.p, d_gpids.p,
+        d_gdptr.p, d_gdids.p, d_g.p);
   // targets: PC and PP of their leaf and its ancestors
-  p2p(tgt->d_y, m, tgt->d_perm, d_bptr.p, d_bgeo.p, nb, d_pptr.p, d_pids.p, d_dptr.p, d_dids.p,
-      out);
+  p2p(tgt->d_y, m, tgt->d_perm, d_bptr.p, d_bgeo.p, nb, wpb_t, d_pptr.p, d_pids.p, d_dptr.p,
+      d_dids.p, out);
 
   bltc::DualDownArgs da;
   da.bptr = d_bptr.p;
   da.nb = nb;
+  da.wpb = wpb_t;
   da.tx = tgt->d_y;
   da.m = m;
   da.tperm = tgt->d_perm;

@@ -148,6 +148,7 @@ struct P2PArgs {
 struct DualDownArgs {
   const int32_t* bptr;         // target batches [nb+1] in target tree order
   int64_t nb;
+  int32_t wpb = 1;             // waves of 64 targets per batch
   const double* tx;            // tree-ordered targets [3][m]
   int64_t m;
   const int32_t* tperm;        // target position -> caller index

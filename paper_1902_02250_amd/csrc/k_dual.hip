@@ -63,13 +63,14 @@ __device__ __forceinline__ void lagrange(const double* __restrict__ s, double v,
   }
 }
 
-// One lane per target of a batch: out += sum over the batch's down list.
+// One lane per target of a batch (wave wv of batch b serves its targets
+// 64 wv ..): out += sum over the batch's down list.
 template <int N1, int OD>
 __global__ __launch_bounds__(64) void k_dual_down(DualDownArgs a) {
   constexpr int P = N1 * N1 * N1;
-  const int b = blockIdx.x;
+  const int b = blockIdx.x / a.wpb, wv = blockIdx.x % a.wpb;
   const int t0 = a.bptr[b], t1 = a.bptr[b + 1];
-  const int ti = t0 + (int)threadIdx.x;
+  const int ti = t0 + wv * 64 + (int)threadIdx.x;
   if (ti >= t1) return;
   const double x = a.tx[ti], y = a.tx[a.m + ti], z = a.tx[2 * a.m + ti];
   double u[OD];
@@ -105,7 +106,7 @@ hipError_t down_kern(const DualDownArgs& a, int n1, hipStream_t s) {
   switch (n1) {
 #define BLTC_DN(N)                                                                        \
   case N:                                                                                 \
-    hipLaunchKernelGGL((k_dual_down<N, OD>), dim3((unsigned)a.nb), dim3(64), 0, s, a);   \
+    hipLaunchKernelGGL((k_dual_down<N, OD>), dim3((unsigned)(a.nb * a.wpb)), dim3(64), 0, s, a); \
     break;
     BLTC_DN(2) BLTC_DN(3) BLTC_DN(4) BLTC_DN(5) BLTC_DN(6) BLTC_DN(7)
     BLTC_DN(8) BLTC_DN(9) BLTC_DN(10) BLTC_DN(11) BLTC_DN(12) BLTC_DN(13)
