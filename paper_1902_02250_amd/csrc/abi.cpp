@@ -225,8 +225,7 @@ void destroy_tree(bltc_tree t) {
   for (auto& kv : t->deg) destroy_degree(kv.second);
   dfree(t->d_perm); dfree(t->d_y); dfree(t->d_box); dfree(t->d_geo);
   dfree(t->d_range); dfree(t->d_kids); dfree(t->d_skip); dfree(t->d_w64); dfree(t->d_w32);
-  dfree(t->d_chunks); dfree(t->d_chunk_ptr); dfree(t->d_partial);
-  dfree(t->d_need);
+  dfree(t->d_chunks); dfree(t->d_chunk_ptr); dfree(t->d_partial); dfree(t->d_parents);
   delete t;
 }
 
@@ -403,16 +402,28 @@ void build_tree(const double* x, const double* y, const double* z, int64_t n,
   for (int64_t q = 0; q < nn; ++q)
     for (int32_t k = 0; k < H.count[q]; ++k)
       skip[H.first[q] + k] = k + 1 < H.count[q] ? H.first[q] + k + 1 : skip[q];
-  // upward-pass chunks: consecutive pieces of each cluster's particle range
+  // upward-pass chunks: consecutive pieces of each leaf's particle range
   std::vector<int4> chunks;
   std::vector<int32_t> cptr(nn + 1);
   for (int64_t q = 0; q < nn; ++q) {
     cptr[q] = (int32_t)chunks.size();
+    if (H.count[q] > 0) continue;
     for (int32_t b = H.begin[q]; b < H.end[q]; b += bltc::kUpwardChunk)
       chunks.push_back(make_int4((int)q, b, std::min(H.end[q], b + bltc::kUpwardChunk), 0));
   }
   cptr[nn] = (int32_t)chunks.size();
   t->nchunks = (int64_t)chunks.size();
+  // parents by level, deepest first: their children are done before them
+  int32_t maxlev = 0;
+  for (int64_t q = 0; q < nn; ++q) maxlev = std::max(maxlev, H.level[q]);
+  std::vector<int32_t> parents;
+  t->parent_levels.clear();
+  for (int32_t l = maxlev; l >= 0; --l) {
+    const int64_t off = (int64_t)parents.size();
+    for (int64_t q = 0; q < nn; ++q)
+      if (H.level[q] == l && H.count[q] > 0) parents.push_back((int32_t)q);
+    if ((int64_t)parents.size() > off) t->parent_levels.push_back({off, (int64_t)parents.size() - off});
+  }
 
   t->d_box = dalloc<double>(6 * nn);
   t->d_geo = dalloc<double4>(nn);
@@ -421,6 +432,7 @@ void build_tree(const double* x, const double* y, const double* z, int64_t n,
   t->d_skip = dalloc<int32_t>(nn);
   t->d_chunks = dalloc<int4>(chunks.size());
   t->d_chunk_ptr = dalloc<int32_t>(nn + 1);
+  if (!parents.empty()) t->d_parents = dalloc<int32_t>(parents.size());
   h2d(t->d_box, H.box.data(), 6 * nn, s);
   h2d(t->d_geo, geo.data(), nn, s);
   h2d(t->d_range, range.data(), nn, s);
@@ -428,21 +440,15 @@ void build_tree(const double* x, const double* y, const double* z, int64_t n,
   h2d(t->d_skip, skip.data(), nn, s);
   h2d(t->d_chunks, chunks.data(), chunks.size(), s);
   h2d(t->d_chunk_ptr, cptr.data(), nn + 1, s);
+  if (!parents.empty()) h2d(t->d_parents, parents.data(), parents.size(), s);
   sync(s);   // the host staging vectors go out of scope
 }
 
 // Grid and modified weights of one degree from the stored tree-ordered
-// weights.
-// Modified weights at `degree`, cached per degree until the weights change.
-// With a need mask (device bytes per cluster) only the flagged clusters get
-// weights; such a partial set is never reused.
-void ensure_degree(bltc_tree t, int degree, hipStream_t s, const uint8_t* need = nullptr) {
-  auto it = t->deg.find(degree);
-  if (it != t->deg.end()) {
-    if (!it->second.partial) return;
-    destroy_degree(it->second);
-    t->deg.erase(it);
-  }
+// weights, cached per degree until the weights change: the leaves from
+// their particles, then the parents level by level from their children.
+void ensure_degree(bltc_tree t, int degree, hipStream_t s) {
+  if (t->deg.count(degree)) return;
   const int64_t nn = t->host.nnodes();
   const int n1 = degree + 1;
   const int64_t nk = (int64_t)n1 * n1 * n1;
@@ -453,7 +459,6 @@ void ensure_degree(bltc_tree t, int degree, hipStream_t s, const uint8_t* need =
     d.fhat64 = dalloc<double>(nn * wd * nk);
     d.p2p64 = dalloc<double>(nn * wd * nk);
     d.p2p32 = dalloc<float>(nn * wd * nk);
-    d.partial = need != nullptr;
     double tk[bltc::kMaxDegree + 1];
     bltc::cheb_points(degree, tk);
     StageTimer prep(BLTC_STAGE_PREP, s);
@@ -467,11 +472,15 @@ void ensure_degree(bltc_tree t, int degree, hipStream_t s, const uint8_t* need =
     }
     StageTimer up(BLTC_STAGE_UPWARD, s);
     hipchk(bltc::launch_upward(t->d_y, t->d_w64, t->n, wd, t->d_chunks,
-                               t->nchunks, d.grid, degree, need, t->d_partial, s),
+                               t->nchunks, d.grid, degree, t->d_partial, s),
            "upward");
-    hipchk(bltc::launch_upward_reduce(t->d_chunk_ptr, nn, t->d_partial, degree, wd, need,
+    hipchk(bltc::launch_upward_reduce(t->d_chunk_ptr, nn, t->d_partial, degree, wd,
                                       d.fhat64, d.p2p64, d.p2p32, s),
            "upward reduce");
+    for (const auto& lv : t->parent_levels)
+      hipchk(bltc::launch_m2m(t->d_parents + lv.first, lv.second, t->d_kids, degree, wd, d.grid,
+                              d.fhat64, d.p2p64, d.p2p32, s),
+             "upward transfer");
     up.stop();
   } catch (...) {
     destroy_degree(d);
@@ -652,6 +661,19 @@ void build_lists(bltc_tree t, bltc_targets g, double theta, const double* theta_
   *nd = tot[1];
 }
 
+// Weights for every degree that the proxy lists of nb batches carry (the
+// separation rule's degree field).
+void ensure_list_degrees(bltc_tree t, bltc_targets g, const bltc::ListSet& L, int64_t nb,
+                         hipStream_t s) {
+  hipchk(bltc::launch_degree_mask(nb, L.ptr, L.pids, (uint32_t*)(g->d_flags + 3), s),
+         "degree mask");
+  uint32_t mask = 0;
+  d2h(&mask, (uint32_t*)(g->d_flags + 3), 1, s);
+  sync(s);
+  for (int d = 1; d <= bltc::kMaxDegree; ++d)
+    if (mask >> d & 1u) ensure_degree(t, d, s);
+}
+
 // The particle-cluster evaluation of the batches in bmap (all if NULL) with
 // lists L and the modified weights of `degree`.
 void run_p2p(bltc_tree t, bltc_targets g, const bltc::ListSet& L, int kernel,
@@ -680,10 +702,12 @@ void run_p2p(bltc_tree t, bltc_targets g, const bltc::ListSet& L, int kernel,
   a.grid = d.grid;
   a.fhat = o.precision == BLTC_FP64 ? (const void*)d.p2p64 : (const void*)d.p2p32;
   if (o.deg_min >= 1 && o.deg_min < degree) {
-    for (int dd = o.deg_min; dd <= degree; ++dd) {
-      const bltc_degree_data& e = t->deg.at(dd);
-      a.grid_d[dd] = e.grid;
-      a.fhat_d[dd] = o.precision == BLTC_FP64 ? (const void*)e.p2p64 : (const void*)e.p2p32;
+    for (int dd = o.deg_min; dd <= degree; ++dd) {   // the degrees the lists carry
+      const auto it = t->deg.find(dd);
+      if (it == t->deg.end()) continue;
+      a.grid_d[dd] = it->second.grid;
+      a.fhat_d[dd] = o.precision == BLTC_FP64 ? (const void*)it->second.p2p64
+                                               : (const void*)it->second.p2p32;
     }
   }
   a.ys = t->d_y;
@@ -708,18 +732,7 @@ void evaluate_tree(bltc_tree t, bltc_targets g, int kernel, double eps,
   int64_t np = 0, nd = 0;
   const bltc::Rule rule = make_rule(theta, degree, o.deg_min);
   build_lists(t, g, theta, nullptr, g->ls[0], s, &np, &nd, &rule);
-  if (rule.deg_min > 0) {
-    // the lower degrees, for the clusters the rule gives them
-    const int64_t nn = t->host.nnodes();
-    if (!t->d_need) t->d_need = dalloc<uint8_t>(nn);
-    for (int d = rule.deg_min; d < degree; ++d) {
-      const auto it = t->deg.find(d);
-      if (it != t->deg.end() && !it->second.partial) continue;
-      hipchk(bltc::launch_need_degree(g->nb, g->ls[0].ptr, g->ls[0].pids, d, t->d_need, nn, s),
-             "need mask");
-      ensure_degree(t, d, s, t->d_need);
-    }
-  }
+  if (rule.deg_min > 0) ensure_list_degrees(t, g, g->ls[0], g->nb, s);   // the rule's lower degrees
   run_p2p(t, g, g->ls[0], kernel, eps, degree, o, nullptr, 0, out, s);
 }
 
@@ -1070,21 +1083,17 @@ void evaluate_dual(bltc_tree src, bltc_tree tgt, int kernel, double eps, int deg
   hipchk(bltc::launch_grids(tgt->d_box, ntn, degree, tk, d_tgrid.p, s), "target grids");
   hipchk(bltc::launch_dual_points(d_gnode.p, ng, n1, d_tgrid.p, d_gpts.p, s), "grid points");
   lt.stop();
-  // the rule's lower degrees, for the source clusters that use them
+  // the rule's lower degrees that the source side uses
   if (rule.deg_min > 0) {
-    const int64_t nns = S.nnodes();
-    std::vector<std::vector<uint8_t>> need(degree, std::vector<uint8_t>(nns, 0));
+    std::vector<bool> used(degree, false);
     for (int64_t A = 0; A < ntn; ++A)
       for (const auto* lst : {&D.cc[A], &D.pc[A]})
         for (int32_t e : *lst) {
           const int dd = e >> bltc::kDegShift;
-          if (dd < degree) need[dd][e & bltc::kIdMask] = 1;
+          if (dd < degree) used[dd] = true;
         }
-    if (!src->d_need) src->d_need = dalloc<uint8_t>(nns);
-    for (int dd = rule.deg_min; dd < degree; ++dd) {
-      h2d(src->d_need, need[dd].data(), nns, s);
-      ensure_degree(src, dd, s, src->d_need);
-    }
+    for (int dd = rule.deg_min; dd < degree; ++dd)
+      if (used[dd]) ensure_degree(src, dd, s);
   }
 
   StageTimer ev(BLTC_STAGE_EVAL, s);
@@ -1109,10 +1118,12 @@ void evaluate_dual(bltc_tree src, bltc_tree tgt, int kernel, double eps, int deg
     a.grid = d.grid;
     a.fhat = o.precision == BLTC_FP64 ? (const void*)d.p2p64 : (const void*)d.p2p32;
     if (rule.deg_min > 0) {
-      for (int dd = rule.deg_min; dd <= degree; ++dd) {
-        const bltc_degree_data& e = src->deg.at(dd);
-        a.grid_d[dd] = e.grid;
-        a.fhat_d[dd] = o.precision == BLTC_FP64 ? (const void*)e.p2p64 : (const void*)e.p2p32;
+      for (int dd = rule.deg_min; dd <= degree; ++dd) {   // the degrees the lists carry
+        const auto it = src->deg.find(dd);
+        if (it == src->deg.end()) continue;
+        a.grid_d[dd] = it->second.grid;
+        a.fhat_d[dd] = o.precision == BLTC_FP64 ? (const void*)it->second.p2p64
+                                                 : (const void*)it->second.p2p32;
       }
     }
     a.ys = src->d_y;
@@ -1298,29 +1309,9 @@ void evaluate_adaptive(bltc_tree t, bltc_targets g, int kernel, double eps,
     order.insert(order.end(), kv.second.begin(), kv.second.end());
   }
   h2d(g->d_bmap, order.data(), nb, s);
-  const int64_t nn = t->host.nnodes();
-  if (!t->d_need) t->d_need = dalloc<uint8_t>(nn);
-  if (rule_min > 0) {
-    // every entry carries its degree: one need mask per degree over all batches
-    const int top = std::max(by_degree.rbegin()->first, rule_min);
-    for (int d = rule_min; d <= top; ++d) {
-      const auto it = t->deg.find(d);
-      if (it != t->deg.end() && !it->second.partial) continue;
-      hipchk(bltc::launch_need_degree(nb, g->ls[0].ptr, g->ls[0].pids, d, t->d_need, nn, s),
-             "need mask");
-      ensure_degree(t, d, s, t->d_need);
-    }
-  } else {
-    for (auto& sp : spans) {   // upward passes in turn: they share scratch
-      const auto it = t->deg.find(sp.first);
-      if (it == t->deg.end() || it->second.partial) {
-        hipchk(bltc::launch_need(g->d_bmap + sp.second.first, sp.second.second, g->ls[0].ptr,
-                                 g->ls[0].pids, t->d_need, nn, s),
-               "need mask");
-        ensure_degree(t, sp.first, s, t->d_need);
-      }
-    }
-  }
+  // each group's top degree, and with the rule every degree an entry carries
+  for (auto& sp : spans) ensure_degree(t, sp.first, s);
+  if (rule_min > 0) ensure_list_degrees(t, g, g->ls[0], nb, s);
   bltc_options og = o;
   og.deg_min = rule_min;
   // the degree groups write disjoint targets: with more than one, they run

@@ -256,11 +256,11 @@ hipError_t launch_batch_weights(int64_t nb, int stride, const int32_t* bptr,
                                 const double* usq, double* wt, hipStream_t s);
 hipError_t launch_flag(int ns, const double* contrib, double thr, int32_t* flag,
                        hipStream_t s);
-hipError_t launch_need(const int32_t* bsel, int64_t nsel, const int32_t* pptr,
-                       const int32_t* pids, uint8_t* need, int64_t nn, hipStream_t s);
 hipError_t launch_cand_costs(const CostArgs& a, hipStream_t s);
-hipError_t launch_need_degree(int64_t nb, const int32_t* pptr, const int32_t* pids, int d,
-                              uint8_t* need, int64_t nn, hipStream_t s);
+// mask[0] = the bits 1 << d of the degrees d carried by the proxy lists of
+// nb batches (entries with the separation rule's degree field).
+hipError_t launch_degree_mask(int64_t nb, const int32_t* pptr, const int32_t* pids,
+                              uint32_t* mask, hipStream_t s);
 hipError_t launch_dual_points(const int32_t* gnode, int64_t ng, int n1, const double* tgrid,
                               double* pts, hipStream_t s);
 hipError_t launch_dual_down(int odim, int n1, const DualDownArgs& a, hipStream_t s);
@@ -288,12 +288,14 @@ hipError_t launch_grids(const double* box, int64_t nn, int degree,
                         const double* unit_nodes, double* grid, hipStream_t s);
 hipError_t launch_upward(const double* ys, const double* w64, int64_t n, int wd,
                          const int4* chunks, int64_t nchunks,
-                         const double* grid, int degree, const uint8_t* need,
-                         double* partial, hipStream_t s);
+                         const double* grid, int degree, double* partial, hipStream_t s);
 hipError_t launch_upward_reduce(const int32_t* chunk_ptr, int64_t nn,
                                 const double* partial, int degree, int wd,
-                                const uint8_t* need, double* fhat64, double* p2p64,
-                                float* p2p32, hipStream_t s);
+                                double* fhat64, double* p2p64, float* p2p32, hipStream_t s);
+// Parents nodes[0..count) from their children's weights (one tree level).
+hipError_t launch_m2m(const int32_t* nodes, int64_t count, const int2* kids, int degree, int wd,
+                      const double* grid, double* fhat64, double* p2p64, float* p2p32,
+                      hipStream_t s);
 hipError_t launch_lists(const ListArgs& a, bool fill, hipStream_t s);
 hipError_t launch_exclusive_scan(const int32_t* in, int64_t n, int32_t* out,
                                  int32_t* overflow, hipStream_t s);
@@ -336,7 +338,6 @@ struct bltc_degree_data {
   double* fhat64 = nullptr;    // [nn][3][nk] (k3 fastest)
   double* p2p64 = nullptr;     // [nn][n1][n1][3][n1]
   float* p2p32 = nullptr;
-  bool partial = false;        // weights only for the clusters of a need mask
 };
 
 struct bltc_tree_s {
@@ -356,13 +357,15 @@ struct bltc_tree_s {
   double* d_w64 = nullptr;     // tree-ordered [wdim][n]
   float* d_w32 = nullptr;
   std::map<int, bltc_degree_data> deg;
-  // upward-pass chunks
+  // upward pass: chunks of the leaves' particle ranges, and the parents by
+  // level, deepest level first
   int64_t nchunks = 0;
   int4* d_chunks = nullptr;    // node, begin, end, 0
   int32_t* d_chunk_ptr = nullptr;  // [nn+1]
+  int32_t* d_parents = nullptr;    // parents, deepest level first
+  std::vector<std::pair<int64_t, int64_t>> parent_levels;   // (offset, count) per level
   double* d_partial = nullptr;
   size_t partial_cap = 0;      // doubles
-  uint8_t* d_need = nullptr;   // [nn] clusters a degree must provide
 };
 
 namespace bltc {
@@ -386,7 +389,7 @@ struct bltc_targets_s {
   double* d_x = nullptr;       // tree-ordered [3][m]
   int32_t* d_bptr = nullptr;
   double4* d_bgeo = nullptr;
-  int32_t* d_flags = nullptr;  // [4]: walk error, scan overflow x2
+  int32_t* d_flags = nullptr;  // [4]: walk error, scan overflow x2, degree mask
   bltc::ListSet ls[2];         // [0] evaluation lists, [1] guard lists
   // per-batch selection scratch (allocated on first adaptive call)
   float* d_feat = nullptr;     // [nb][12]

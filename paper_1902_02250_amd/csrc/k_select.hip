@@ -311,34 +311,18 @@ __global__ void k_flag(int ns, const double* __restrict__ contrib, double thr,
   if (i < ns) flag[i] = contrib[i] > thr ? 1 : 0;
 }
 
-// need[q] = 1 for every proxy cluster q on the lists of the batches bsel[0..nsel).
-__global__ void k_need(const int32_t* __restrict__ bsel, int64_t nsel,
-                       const int32_t* __restrict__ pptr, const int32_t* __restrict__ pids,
-                       uint8_t* __restrict__ need) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nsel) return;
-  const int b = bsel[i];
-  for (int l = pptr[b]; l < pptr[b + 1]; ++l) need[pids[l] & kIdMask] = 1;
-}
-
-// need[q] = 1 for every proxy entry of degree d (separation rule).
-__global__ void k_need_degree(int64_t nb, const int32_t* __restrict__ pptr,
-                              const int32_t* __restrict__ pids, int d,
-                              uint8_t* __restrict__ need) {
+// mask[0] |= 1 << d for every degree d that the proxy lists carry
+// (separation rule); mask[0] starts at zero.
+__global__ void k_degree_mask(int64_t nb, const int32_t* __restrict__ pptr,
+                              const int32_t* __restrict__ pids, uint32_t* __restrict__ mask) {
   const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= nb) return;
-  for (int l = pptr[b]; l < pptr[b + 1]; ++l) {
-    const int e = pids[l];
-    if ((e >> kDegShift) == d) need[e & kIdMask] = 1;
-  }
+  uint32_t m = 0;
+  for (int l = pptr[b]; l < pptr[b + 1]; ++l) m |= 1u << (pids[l] >> kDegShift);
+  if (m) atomicOr(mask, m);
 }
 
 __global__ void k_fill_i32(int32_t* __restrict__ p, int64_t n, int32_t v) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = v;
-}
-
-__global__ void k_fill_u8(uint8_t* __restrict__ p, int64_t n, uint8_t v) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
 }
@@ -417,17 +401,6 @@ hipError_t launch_flag(int ns, const double* contrib, double thr, int32_t* flag,
   return hipGetLastError();
 }
 
-hipError_t launch_need(const int32_t* bsel, int64_t nsel, const int32_t* pptr,
-                       const int32_t* pids, uint8_t* need, int64_t nn, hipStream_t s) {
-  if (nn > 0)
-    hipLaunchKernelGGL(k_fill_u8, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, s, need,
-                       nn, (uint8_t)0);
-  if (nsel > 0)
-    hipLaunchKernelGGL(k_need, dim3((unsigned)((nsel + 127) / 128)), dim3(128), 0, s, bsel,
-                       nsel, pptr, pids, need);
-  return hipGetLastError();
-}
-
 hipError_t launch_cand_costs(const CostArgs& a, hipStream_t s) {
   if (a.nb == 0) return hipSuccess;
   if (a.ngroups < 1 || a.ngroups > kMaxThetaGroups) return hipErrorInvalidValue;
@@ -442,14 +415,12 @@ hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_need_degree(int64_t nb, const int32_t* pptr, const int32_t* pids, int d,
-                              uint8_t* need, int64_t nn, hipStream_t s) {
-  if (nn > 0)
-    hipLaunchKernelGGL(k_fill_u8, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, s, need,
-                       nn, (uint8_t)0);
+hipError_t launch_degree_mask(int64_t nb, const int32_t* pptr, const int32_t* pids,
+                              uint32_t* mask, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, (int32_t*)mask, (int64_t)1, 0);
   if (nb > 0)
-    hipLaunchKernelGGL(k_need_degree, dim3((unsigned)((nb + 127) / 128)), dim3(128), 0, s, nb,
-                       pptr, pids, d, need);
+    hipLaunchKernelGGL(k_degree_mask, dim3((unsigned)((nb + 127) / 128)), dim3(128), 0, s, nb,
+                       pptr, pids, mask);
   return hipGetLastError();
 }
 
