@@ -223,6 +223,7 @@ void destroy_degree(bltc_degree_data& d) {
 void destroy_tree(bltc_tree t) {
   if (!t) return;
   for (auto& kv : t->deg) destroy_degree(kv.second);
+  for (auto& kv : t->spare) destroy_degree(kv.second);
   dfree(t->d_perm); dfree(t->d_y); dfree(t->d_box); dfree(t->d_geo);
   dfree(t->d_range); dfree(t->d_kids); dfree(t->d_skip); dfree(t->d_w64); dfree(t->d_w32);
   dfree(t->d_chunks); dfree(t->d_chunk_ptr); dfree(t->d_partial); dfree(t->d_parents);
@@ -455,10 +456,16 @@ void ensure_degree(bltc_tree t, int degree, hipStream_t s) {
   bltc_degree_data d;
   try {
     const int wd = t->wdim;
-    d.grid = dalloc<double>(nn * 3 * n1);
-    d.fhat64 = dalloc<double>(nn * wd * nk);
-    d.p2p64 = dalloc<double>(nn * wd * nk);
-    d.p2p32 = dalloc<float>(nn * wd * nk);
+    const auto sp = t->spare.find(degree);
+    if (sp != t->spare.end()) {   // buffers of a stale table of this degree
+      d = sp->second;
+      t->spare.erase(sp);
+    } else {
+      d.grid = dalloc<double>(nn * 3 * n1);
+      d.fhat64 = dalloc<double>(nn * wd * nk);
+      d.p2p64 = dalloc<double>(nn * wd * nk);
+      d.p2p32 = dalloc<float>(nn * wd * nk);
+    }
     double tk[bltc::kMaxDegree + 1];
     bltc::cheb_points(degree, tk);
     StageTimer prep(BLTC_STAGE_PREP, s);
@@ -490,9 +497,19 @@ void ensure_degree(bltc_tree t, int degree, hipStream_t s) {
 }
 
 void set_weights(bltc_tree t, const double* w, int wdim, hipStream_t s) {
-  for (auto& kv : t->deg) destroy_degree(kv.second);
+  // the cached tables go stale; their buffers are kept for the next tables
+  // of the same degree and width (no free or allocation per call)
+  for (auto& kv : t->deg) {
+    auto it = t->spare.find(kv.first);
+    if (it != t->spare.end()) destroy_degree(it->second);
+    t->spare[kv.first] = kv.second;
+  }
   t->deg.clear();
   t->has_w = false;
+  if (t->wdim != wdim) {
+    for (auto& kv : t->spare) destroy_degree(kv.second);
+    t->spare.clear();
+  }
   if (t->d_w64 && t->wdim != wdim) {
     dfree(t->d_w64);
     dfree(t->d_w32);

@@ -13,7 +13,7 @@ namespace bltc {
 
 constexpr int kMaxDegree = 12;
 constexpr int kWave = 64;
-constexpr int kUpwardChunk = 2048;   // particles per upward-pass work group
+constexpr int kUpwardChunk = 512;    // particles per upward-pass work group
 constexpr int kMlpIn = 12;           // selector network: features
 constexpr int kMlpHidden = 64;       // selector network: hidden width
 constexpr int kMlpMaxOut = 128;      // selector network: most candidates
@@ -357,6 +357,7 @@ struct bltc_tree_s {
   double* d_w64 = nullptr;     // tree-ordered [wdim][n]
   float* d_w32 = nullptr;
   std::map<int, bltc_degree_data> deg;
+  std::map<int, bltc_degree_data> spare;   // buffers of stale tables, by degree
   // upward pass: chunks of the leaves' particle ranges, and the parents by
   // level, deepest level first
   int64_t nchunks = 0;

@@ -24,9 +24,9 @@
 // 6 for force and torque).  Chunk partial sums land in a scratch array and a
 // second kernel adds them per cluster in chunk order.  The child-to-parent
 // step (k_m2m) runs one tree level at a time, deepest first, one work group
-// per parent, as three separable contractions per child through LDS, the
-// children in order.  Every sum has a fixed order, so the result is
-// deterministic.  FP64 throughout.
+// per (parent, weight component), as three separable contractions per child
+// through LDS, the children in order.  Every sum has a fixed order, so the
+// result is deterministic.  FP64 throughout.
 #include <float.h>
 #include <hip/hip_runtime.h>
 
@@ -165,12 +165,12 @@ __global__ void k_upward_reduce(const int32_t* __restrict__ chunk_ptr,
 }
 
 // One work group per parent q = nodes[blockIdx.x], whose children all have
-// their weights: per weight component and child, T_ax[k][m] = L^P_k(s_m) on
-// each axis, then
+// their weights, and weight component c = blockIdx.y: per child,
+// T_ax[k][m] = L^P_k(s_m) on each axis, then
 //   A[k1][m2][m3] = sum_m1 T_0[k1][m1] F[m1][m2][m3]
 //   B[k1][k2][m3] = sum_m2 T_1[k2][m2] A[k1][m2][m3]
 //   fhat_P[k1][k2][k3] += sum_m3 T_2[k3][m3] B[k1][k2][m3]
-// per weight component, with F the child's weights.
+// with F the child's weights of component c.
 template <int N1, int WD>
 __global__ __launch_bounds__(kThreads) void k_m2m(const int32_t* __restrict__ nodes,
                                                   const int2* __restrict__ kids,
@@ -191,61 +191,59 @@ __global__ __launch_bounds__(kThreads) void k_m2m(const int32_t* __restrict__ no
   const int t = threadIdx.x;
   if (t < 3 * N1) sP[t / N1][t % N1] = grid[(int64_t)q * 3 * N1 + t];
 
-#pragma unroll 1
-  for (int c = 0; c < WD; ++c) {
-    double acc[IPT];
+  const int c = blockIdx.y;   // weight component
+  double acc[IPT];
 #pragma unroll
-    for (int i = 0; i < IPT; ++i) acc[i] = 0.0;
-    for (int ch = kd.x; ch < kd.x + kd.y; ++ch) {
-      __syncthreads();   // sP written; the previous child's sT and sF read
-      if (t < 3 * N1) {
-        const int ax = t / N1, m = t % N1;
-        double L[N1];
-        bary_row<N1>(sP[ax], grid[((int64_t)ch * 3 + ax) * N1 + m], L);
+  for (int i = 0; i < IPT; ++i) acc[i] = 0.0;
+  for (int ch = kd.x; ch < kd.x + kd.y; ++ch) {
+    __syncthreads();   // sP written; the previous child's sT and sF read
+    if (t < 3 * N1) {
+      const int ax = t / N1, m = t % N1;
+      double L[N1];
+      bary_row<N1>(sP[ax], grid[((int64_t)ch * 3 + ax) * N1 + m], L);
 #pragma unroll
-        for (int k = 0; k < N1; ++k) sT[ax][k][m] = L[k];
-      }
-      const double* __restrict__ F = fhat64 + ((int64_t)ch * WD + c) * NK;
-      for (int i = t; i < NK; i += kThreads) sF[i] = F[i];
-      __syncthreads();
-      for (int i = t; i < NK; i += kThreads) {
-        const int k1 = i / N2, r = i % N2;
-        double s = 0.0;
-#pragma unroll
-        for (int m = 0; m < N1; ++m) s = fma(sT[0][k1][m], sF[m * N2 + r], s);
-        sA[i] = s;
-      }
-      __syncthreads();
-      for (int i = t; i < NK; i += kThreads) {
-        const int k1 = i / N2, k2 = (i / N1) % N1, m3 = i % N1;
-        double s = 0.0;
-#pragma unroll
-        for (int m = 0; m < N1; ++m) s = fma(sT[1][k2][m], sA[(k1 * N1 + m) * N1 + m3], s);
-        sF[i] = s;
-      }
-      __syncthreads();
-#pragma unroll
-      for (int it = 0; it < IPT; ++it) {
-        const int i = t + it * kThreads;
-        if (i < NK) {
-          const int k12 = i / N1, k3 = i % N1;
-          double s = 0.0;
-#pragma unroll
-          for (int m = 0; m < N1; ++m) s = fma(sT[2][k3][m], sF[k12 * N1 + m], s);
-          acc[it] += s;
-        }
-      }
+      for (int k = 0; k < N1; ++k) sT[ax][k][m] = L[k];
     }
+    const double* __restrict__ F = fhat64 + ((int64_t)ch * WD + c) * NK;
+    for (int i = t; i < NK; i += kThreads) sF[i] = F[i];
+    __syncthreads();
+    for (int i = t; i < NK; i += kThreads) {
+      const int k1 = i / N2, r = i % N2;
+      double s = 0.0;
+#pragma unroll
+      for (int m = 0; m < N1; ++m) s = fma(sT[0][k1][m], sF[m * N2 + r], s);
+      sA[i] = s;
+    }
+    __syncthreads();
+    for (int i = t; i < NK; i += kThreads) {
+      const int k1 = i / N2, k2 = (i / N1) % N1, m3 = i % N1;
+      double s = 0.0;
+#pragma unroll
+      for (int m = 0; m < N1; ++m) s = fma(sT[1][k2][m], sA[(k1 * N1 + m) * N1 + m3], s);
+      sF[i] = s;
+    }
+    __syncthreads();
 #pragma unroll
     for (int it = 0; it < IPT; ++it) {
       const int i = t + it * kThreads;
       if (i < NK) {
         const int k12 = i / N1, k3 = i % N1;
-        fhat64[((int64_t)q * WD + c) * NK + i] = acc[it];
-        const int64_t o = (int64_t)q * WD * NK + ((int64_t)k12 * WD + c) * N1 + k3;
-        p2p64[o] = acc[it];
-        p2p32[o] = (float)acc[it];
+        double s = 0.0;
+#pragma unroll
+        for (int m = 0; m < N1; ++m) s = fma(sT[2][k3][m], sF[k12 * N1 + m], s);
+        acc[it] += s;
       }
+    }
+  }
+#pragma unroll
+  for (int it = 0; it < IPT; ++it) {
+    const int i = t + it * kThreads;
+    if (i < NK) {
+      const int k12 = i / N1, k3 = i % N1;
+      fhat64[((int64_t)q * WD + c) * NK + i] = acc[it];
+      const int64_t o = (int64_t)q * WD * NK + ((int64_t)k12 * WD + c) * N1 + k3;
+      p2p64[o] = acc[it];
+      p2p32[o] = (float)acc[it];
     }
   }
 }
@@ -268,11 +266,11 @@ hipError_t run_m2m(const int32_t* nodes, int64_t count, const int2* kids, int wd
                    const double* grid, double* fhat64, double* p2p64, float* p2p32,
                    hipStream_t s) {
   if (wd == 6)
-    hipLaunchKernelGGL((k_m2m<N1, 6>), dim3((unsigned)count), dim3(kThreads), 0, s, nodes, kids,
-                       grid, fhat64, p2p64, p2p32);
+    hipLaunchKernelGGL((k_m2m<N1, 6>), dim3((unsigned)count, 6), dim3(kThreads), 0, s, nodes,
+                       kids, grid, fhat64, p2p64, p2p32);
   else
-    hipLaunchKernelGGL((k_m2m<N1, 3>), dim3((unsigned)count), dim3(kThreads), 0, s, nodes, kids,
-                       grid, fhat64, p2p64, p2p32);
+    hipLaunchKernelGGL((k_m2m<N1, 3>), dim3((unsigned)count, 3), dim3(kThreads), 0, s, nodes,
+                       kids, grid, fhat64, p2p64, p2p32);
   return hipGetLastError();
 }
 
