@@ -112,13 +112,16 @@ def main():
     ap.add_argument("--tol-settings", default="9,0.7,0;10,0.7,1",
                     help="n,theta,deg_min;... settings also timed, with their error, "
                          "beside the headline configuration ('' for none)")
-    ap.add_argument("--dual-settings", default="",
+    ap.add_argument("--dual-settings", default=None,
                     help="cluster-cluster variant settings 'n,theta,target_leaf[,deg_min];...' "
-                         "timed after the headline")
+                         "timed after the headline (default: two settings at E <= 1e-6 on the "
+                         "1e6 uniform workload, none on the others)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first run one device-to-device copy of MIB MiB, the reference "
                          "for scaling HBM byte counters")
     args = ap.parse_args()
+    if args.dual_settings is None:
+        args.dual_settings = "7,0.7,400;9,0.8,700" if args.workload == "c3" and not args.n else ""
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:

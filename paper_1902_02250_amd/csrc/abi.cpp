@@ -220,6 +220,8 @@ void destroy_degree(bltc_degree_data& d) {
   dfree(d.p2p32);
 }
 
+void destroy_dual_cache(bltc_dual_cache* c);
+
 void destroy_tree(bltc_tree t) {
   if (!t) return;
   for (auto& kv : t->deg) destroy_degree(kv.second);
@@ -227,6 +229,7 @@ void destroy_tree(bltc_tree t) {
   dfree(t->d_perm); dfree(t->d_y); dfree(t->d_box); dfree(t->d_geo);
   dfree(t->d_range); dfree(t->d_kids); dfree(t->d_skip); dfree(t->d_w64); dfree(t->d_w32);
   dfree(t->d_chunks); dfree(t->d_chunk_ptr); dfree(t->d_partial); dfree(t->d_parents);
+  destroy_dual_cache(t->dual);
   delete t;
 }
 
@@ -253,6 +256,27 @@ struct DevBuf {
   }
   ~DevBuf() { dfree(p); }
 };
+
+}  // namespace
+
+// Device buffers that the cluster-cluster path (on the target tree) and the
+// judge's repair pass (on the targets) keep between calls, grown on demand,
+// so a repeated call allocates nothing.
+struct bltc_dual_cache {
+  DevBuf<int32_t> gnode, gbptr, gpptr, gpids, gdptr, gdids, giota, bptr, pptr, pids, dptr, dids,
+      xptr, xgi, xnode;
+  DevBuf<double4> bgeo, gbgeo;
+  DevBuf<double> tgrid, g, gpts;
+};
+struct bltc_split_cache {
+  DevBuf<int4> sl;
+  DevBuf<int32_t> sptr;
+  DevBuf<double> part;
+};
+
+namespace {
+
+void destroy_dual_cache(bltc_dual_cache* c) { delete c; }
 
 // The cluster tree built on the device, level by level (Section 6 rules, the
 // same results as bltc::build_host_tree bit for bit).  The host keeps the
@@ -541,6 +565,7 @@ void destroy_targets(bltc_targets g) {
   dfree(g->d_sbatch); dfree(g->d_gflag); dfree(g->d_ufb);
   dfree(g->d_wt); dfree(g->d_usq); dfree(g->d_contrib); dfree(g->d_part); dfree(g->d_sums); dfree(g->d_lam);
   dfree(g->d_cost); dfree(g->d_e2); dfree(g->d_candT); dfree(g->d_candn);
+  delete g->split;
   delete g;
 }
 
@@ -1067,10 +1092,14 @@ void evaluate_dual(bltc_tree src, bltc_tree tgt, int kernel, double eps, int deg
   if (pids.size() > (size_t)INT32_MAX || dids.size() > (size_t)INT32_MAX)
     throw HipError{BLTC_EINVAL, "cluster-cluster lists exceed 2^31 entries"};
 
-  DevBuf<int32_t> d_gnode, d_gbptr, d_gpptr, d_gpids, d_gdptr, d_gdids, d_giota, d_bptr, d_pptr,
-      d_pids, d_dptr, d_dids, d_xptr, d_xgi, d_xnode;
-  DevBuf<double4> d_bgeo, d_gbgeo;
-  DevBuf<double> d_tgrid, d_g, d_gpts;
+  if (!tgt->dual) tgt->dual = new bltc_dual_cache;
+  bltc_dual_cache& C = *tgt->dual;
+  DevBuf<int32_t>&d_gnode = C.gnode, &d_gbptr = C.gbptr, &d_gpptr = C.gpptr, &d_gpids = C.gpids,
+      &d_gdptr = C.gdptr, &d_gdids = C.gdids, &d_giota = C.giota, &d_bptr = C.bptr,
+      &d_pptr = C.pptr, &d_pids = C.pids, &d_dptr = C.dptr, &d_dids = C.dids, &d_xptr = C.xptr,
+      &d_xgi = C.xgi, &d_xnode = C.xnode;
+  DevBuf<double4>&d_bgeo = C.bgeo, &d_gbgeo = C.gbgeo;
+  DevBuf<double>&d_tgrid = C.tgrid, &d_g = C.g, &d_gpts = C.gpts;
   auto up = [&](auto& buf, const auto& v) {
     buf.reserve(v.size());
     h2d(buf.p, v.data(), v.size(), s);
@@ -1412,9 +1441,10 @@ void evaluate_adaptive(bltc_tree t, bltc_targets g, int kernel, double eps,
           sptr.push_back((int32_t)sl.size());
         }
         const int odim = odim_of(kernel);
-        DevBuf<int4> d_sl;
-        DevBuf<int32_t> d_sptr;
-        DevBuf<double> d_part;
+        if (!g->split) g->split = new bltc_split_cache;
+        DevBuf<int4>& d_sl = g->split->sl;
+        DevBuf<int32_t>& d_sptr = g->split->sptr;
+        DevBuf<double>& d_part = g->split->part;
         d_sl.reserve(sl.size());
         d_sptr.reserve(sptr.size());
         d_part.reserve(sl.size() * odim * bltc::kWave);
@@ -1428,7 +1458,6 @@ void evaluate_adaptive(bltc_tree t, bltc_targets g, int kernel, double eps,
                                          g->d_tperm, d_part.p, odim, su, sw, g->m, out, s),
                "split reduce");
         judge_sums(g, kernel, out, js, s);
-        sync(s);   // the slice buffers go out of scope
       } else {
         run_p2p(t, g, g->ls[1], kernel, eps, fb_degree, o, g->d_bmap, (int64_t)redo.size(),
                 out, s);

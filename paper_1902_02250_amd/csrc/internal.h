@@ -340,6 +340,9 @@ struct bltc_degree_data {
   float* p2p32 = nullptr;
 };
 
+struct bltc_dual_cache;
+struct bltc_split_cache;
+
 struct bltc_tree_s {
   int device = 0;
   int64_t n = 0, leaf_max = 0;
@@ -358,6 +361,7 @@ struct bltc_tree_s {
   float* d_w32 = nullptr;
   std::map<int, bltc_degree_data> deg;
   std::map<int, bltc_degree_data> spare;   // buffers of stale tables, by degree
+  bltc_dual_cache* dual = nullptr;   // cluster-cluster buffers (as the target tree)
   // upward pass: chunks of the leaves' particle ranges, and the parents by
   // level, deepest level first
   int64_t nchunks = 0;
@@ -382,6 +386,7 @@ struct ListSet {
 
 struct bltc_targets_s {
   int device = 0;
+  bltc_split_cache* split = nullptr;   // the judge's repair slices (grown on demand)
   int64_t m = 0, nb = 0;
   int32_t batch_size = 0, order_leaf = 0;
   int64_t group_max = 0;
