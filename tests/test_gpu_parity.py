@@ -134,8 +134,11 @@ def test_modified_weights_force_and_torque(torch, orc, degree):
         assert np.abs(f[q] - ref[q]).max() <= FP64_TOL * np.abs(ref[q]).max(), q
 
 
-def test_modified_weights_exact_hits(torch, orc):
-    """Particles on grid points and box faces take the exact-hit branch."""
+@pytest.mark.parametrize("leaf", [1000, 12])
+def test_modified_weights_exact_hits(torch, orc, leaf):
+    """Particles on grid points and box faces take the exact-hit branch; with
+    small leaves the parents come from their children's weights, whose grid
+    points then meet the parents' exact hits too."""
     n = 4
     lo, hi = np.array([-1.0, -0.5, 0.25]), np.array([1.0, 1.5, 2.25])
     t = orc.cheb_points(n)
@@ -146,10 +149,35 @@ def test_modified_weights_exact_hits(torch, orc):
                          s[2, rng.integers(0, n + 1, 50)]])
     p = np.concatenate([lo[:, None], hi[:, None], on_nodes, inner], axis=1)
     w = inputs.weights(p.shape[1], 9)
-    T = _gpu_tree(torch, p, w, 1000, n)
+    T = _gpu_tree(torch, p, w, leaf, n)
     f, _ = T.weights_export(n)
-    ref = orc.Tree(p, 1000).modified_weights(w, n)
-    assert np.abs(f - ref).max() <= FP64_TOL * np.abs(ref).max()
+    ref = orc.Tree(p, leaf).modified_weights(w, n)
+    for q in range(ref.shape[0]):
+        assert np.abs(f[q] - ref[q]).max() <= FP64_TOL * np.abs(ref[q]).max(), q
+
+
+@pytest.mark.parametrize("degree", [3, 7])
+@pytest.mark.parametrize("wdim", [3, 6])
+def test_modified_weights_flat_and_coincident(torch, orc, degree, wdim):
+    """Clusters with flat sides (a plane, a line) and clusters of coincident
+    points, deep in a tree of small leaves: a flat child's grid collapses onto
+    the particles' common coordinate, and its parent's weights must still
+    equal the sum over the parent's particles."""
+    rng = np.random.default_rng(8)
+    plane = np.stack([rng.uniform(-1, 1, 300), rng.uniform(-1, 1, 300), np.full(300, 0.3)])
+    line = np.stack([np.full(100, -0.5), np.full(100, 0.2), rng.uniform(-1, 1, 100)])
+    spots = rng.uniform(-1, 1, (3, 5))
+    dup = np.repeat(spots, 20, axis=1)
+    free = rng.uniform(-1, 1, (3, 400))
+    p = np.concatenate([plane, line, dup, free], axis=1)
+    w = inputs.weights(p.shape[1], 12, wdim)
+    T = _gpu_tree(torch, p, w, 8, degree)
+    f, _ = T.weights_export(degree)
+    R = orc.Tree(p, 8)
+    assert R.nnodes > 100
+    ref = R.modified_weights(w, degree)
+    for q in range(R.nnodes):
+        assert np.abs(f[q] - ref[q]).max() <= FP64_TOL * np.abs(ref[q]).max(), q
 
 
 @pytest.mark.parametrize("theta", [0.0, 0.3, 0.7, 1.0])
