@@ -604,9 +604,12 @@ hipError_t run_p2p(const P2PArgs& a, hipStream_t s) {
 }
 
 // Guard evaluation: one wave per sampled target; the lanes share the
-// target's list (far field by (k1, k2) rows, near field by sources) and the
-// FP64 lane totals are added by a butterfly, so the sum is deterministic.
-// FP32 evaluation with the differences formed in FP64.
+// target's list (far field by (k2, k3) columns, near field by sources) and
+// the FP64 lane totals are added by a butterfly, so the sum is deterministic.
+// In the far field each lane walks k1 down its column: for a fixed k1 the
+// lanes read consecutive k3 of the weight layout, and dx (uniform over the
+// wave) comes from a per-cluster table.  FP32 evaluation with the
+// differences formed in FP64.
 template <int KERN, int N1, bool ZEPS>
 __global__ __launch_bounds__(64) void k_guard(
     const int32_t* __restrict__ spos, const int32_t* __restrict__ sbatch, int ns,
@@ -634,17 +637,20 @@ __global__ __launch_bounds__(64) void k_guard(
     float p[OD];
 #pragma unroll
     for (int c = 0; c < OD; ++c) p[c] = 0.f;
-    for (int r = lane; r < N1 * N1; r += 64) {
-      const int k1 = r / N1, k2 = r % N1;
-      const float dx = (float)(x - g[k1]);
-      const float dy = (float)(y - g[N1 + k2]);
-      const float* __restrict__ row = F + r * 3 * N1;
+    float dxs[N1];
 #pragma unroll
-      for (int k3 = 0; k3 < N1; ++k3) {
-        const float dz = (float)(z - g[2 * N1 + k3]);
-        const float r2 = dz * dz + (dy * dy + (dx * dx + e2));
-        pair<KERN, ZEPS, float>(dx, dy, dz, r2, e2, row[k3], row[N1 + k3],
-                                row[2 * N1 + k3], p);
+    for (int k1 = 0; k1 < N1; ++k1) dxs[k1] = (float)(x - g[k1]);
+    for (int r = lane; r < N1 * N1; r += 64) {
+      const int k2 = r / N1, k3 = r % N1;
+      const float dy = (float)(y - g[N1 + k2]);
+      const float dz = (float)(z - g[2 * N1 + k3]);
+      const float a = dz * dz + (dy * dy + e2);
+      const float* __restrict__ col = F + k2 * 3 * N1 + k3;
+#pragma unroll
+      for (int k1 = 0; k1 < N1; ++k1) {
+        const float dx = dxs[k1];
+        const float* __restrict__ f = col + k1 * N1 * 3 * N1;
+        pair<KERN, ZEPS, float>(dx, dy, dz, dx * dx + a, e2, f[0], f[N1], f[2 * N1], p);
       }
     }
 #pragma unroll
