@@ -139,8 +139,13 @@ int bltc_tree_export(bltc_tree t, int64_t* perm, double* box, double* center,
  * and modified weights fhat_k = sum_{j in C} L_k1(y_j1) L_k2(y_j2) L_k3(y_j3) f_j,
  * the Lagrange values taken in barycentric form with the exact-hit rule of
  * Algorithm 1 (a coordinate equal to a grid point gets the Kronecker delta).
+ * The leaves sum over their particles; every parent takes its children's
+ * weights through the degree-n Lagrange basis of its own grid evaluated at
+ * the children's grid points, which equals the sum over its particles in
+ * exact arithmetic (degree-n interpolation reproduces the parent's basis).
  * Computed in FP64; kept in FP64 and FP32 for the evaluation.  Calling again
- * replaces the weights and drops modified weights of other degrees. */
+ * replaces the weights and drops modified weights of other degrees (their
+ * device buffers are kept for reuse). */
 int bltc_compute_modified_weights(bltc_tree t, const double* w, int32_t wdim,
                                   int32_t degree, void* stream);
 /* Host copy of the modified weights of one degree (synchronises):

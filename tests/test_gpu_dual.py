@@ -131,3 +131,22 @@ def test_dual_rule_poly_exact(torch, orc):
                     deg_min=2)
     d = orc.direct("poly", tgt, src, w, poly_p=2, poly_c=0.5)
     assert orc.rel_l2(d, got) <= FP64_TOL
+
+
+def test_dual_repeated_calls_reuse_buffers(torch, orc):
+    """The cluster-cluster path keeps its device buffers with the target tree
+    and grows them on demand: calls on the same trees with a small, a larger
+    and again the small degree (and new weights in between) must each give
+    the result of the oracle for that call."""
+    src = inputs.points("mixture", 12000, 97)
+    tgt = inputs.points("uniform", 9001, 98)
+    S = bltc.Tree(_d(torch, src), 50)
+    T = bltc.Tree(_d(torch, tgt), 50)
+    for i, (n, theta, seed) in enumerate([(3, 0.8, 1), (6, 0.7, 2), (3, 0.8, 3)]):
+        w = inputs.weights(12000, seed)
+        S.compute_weights(_d(torch, w), n)
+        out, cnt = bltc.evaluate_dual(S, T, "stokeslet", 0.01, n, theta, precision="fp64")
+        ref, rcnt = orc.dual_treecode("stokeslet", tgt, src, w, 0.01, n, theta, 50, 50)
+        assert np.array_equal(cnt, rcnt), (i, cnt, rcnt)
+        assert cnt[0] > 0, (i, cnt)
+        assert orc.rel_l2(ref, out.cpu().numpy()) <= FP64_TOL, i

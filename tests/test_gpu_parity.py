@@ -460,3 +460,21 @@ def test_paper_workloads_fp64(torch, orc, name, n):
     # about (2 + 1.41) / 0.59 = 5.8 times over MIXED_TOL's analysis
     tol32 = 10 * MIXED_TOL if name == "e1" else MIXED_TOL
     assert orc.rel_l2(ref, got32) <= tol32
+
+
+def test_modified_weights_after_weight_and_width_changes(torch, orc):
+    """Stale tables keep their device buffers for the next table of the same
+    degree; a change of the weight width drops them.  A sequence of weight
+    updates over degrees and widths must give the oracle's weights each time."""
+    p = inputs.points("mixture", 6000, 71)
+    T = bltc.Tree(_d(torch, p), 60)
+    R = orc.Tree(p, 60)
+    for i, (degree, wdim, seed) in enumerate([(4, 3, 1), (6, 3, 2), (4, 3, 3), (4, 6, 4),
+                                              (6, 6, 5), (4, 3, 6)]):
+        w = inputs.weights(6000, seed, wdim)
+        T.compute_weights(_d(torch, w), degree)
+        f, _ = T.weights_export(degree)
+        assert f.shape[1] == wdim, i
+        ref = R.modified_weights(w, degree)
+        for q in range(R.nnodes):
+            assert np.abs(f[q] - ref[q]).max() <= FP64_TOL * np.abs(ref[q]).max(), (i, q)
