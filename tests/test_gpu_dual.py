@@ -148,5 +148,5 @@ def test_dual_repeated_calls_reuse_buffers(torch, orc):
         out, cnt = bltc.evaluate_dual(S, T, "stokeslet", 0.01, n, theta, precision="fp64")
         ref, rcnt = orc.dual_treecode("stokeslet", tgt, src, w, 0.01, n, theta, 50, 50)
         assert np.array_equal(cnt, rcnt), (i, cnt, rcnt)
-        assert cnt[0] > 0, (i, cnt)
+        assert cnt[4] > 0, (i, cnt)   # grid slots: the buffers of the grid pass are used
         assert orc.rel_l2(ref, out.cpu().numpy()) <= FP64_TOL, i
