@@ -352,9 +352,10 @@ int bltc_selector_info(bltc_selector sel, int32_t* k, int32_t* cand_n,
  *     the cheapest whose predicted global error is within
  *     tol 10^-margin_global (else the one predicted most accurate).
  *  4. Lists at each batch's theta (and the separation rule's degrees);
- *     modified weights of every degree in use, for the clusters that use it
- *     only; evaluation grouped by the batches' degrees, the groups running
- *     concurrently.
+ *     modified weights of every top degree in use and, under the rule, of
+ *     the lower degrees derived from each top degree's (so a batch's result
+ *     equals the fixed evaluation at its candidate); evaluation grouped by
+ *     the batches' top degrees, the groups running concurrently.
  *  5. The judge's estimate E^2 = sum_i G_i |u - u_fb|^2 / sum_i G_i |u_fb|^2
  *     over the samples (G_i the targets the sample stands for); when it
  *     exceeds tol^2, the samples with the largest terms, just enough of
@@ -364,7 +365,9 @@ int bltc_selector_info(bltc_selector sel, int32_t* k, int32_t* cand_n,
  * the judge sent to the fallback.  stats (host int64 [4], may be NULL):
  * batches, distinct degrees, batches re-evaluated, 0.  judge (host double
  * [2], may be NULL): the judge's error estimate before and after its
- * re-evaluation.  Synchronises on stream. */
+ * re-evaluation.  opt supplies the precision; its deg_min is ignored (the
+ * candidates take the model's rule, the fallback none).  Synchronises on
+ * stream. */
 enum { BLTC_SELECT_BATCH = 0, BLTC_SELECT_RUN = 1 };
 int bltc_evaluate_adaptive(bltc_tree t, bltc_targets g, int32_t kernel, double eps,
                            bltc_selector sel, double tol, int32_t mode, int32_t fb_degree,

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
+#include <cfloat>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -226,6 +227,8 @@ void destroy_tree(bltc_tree t) {
   if (!t) return;
   for (auto& kv : t->deg) destroy_degree(kv.second);
   for (auto& kv : t->spare) destroy_degree(kv.second);
+  for (auto& kv : t->derived) destroy_degree(kv.second);
+  for (auto& kv : t->spare_derived) destroy_degree(kv.second);
   dfree(t->d_perm); dfree(t->d_y); dfree(t->d_box); dfree(t->d_geo);
   dfree(t->d_range); dfree(t->d_kids); dfree(t->d_skip); dfree(t->d_w64); dfree(t->d_w32);
   dfree(t->d_chunks); dfree(t->d_chunk_ptr); dfree(t->d_partial); dfree(t->d_parents);
@@ -520,6 +523,75 @@ void ensure_degree(bltc_tree t, int degree, hipStream_t s) {
   t->deg[degree] = d;
 }
 
+// L^d_k(t^n_m) on the reference Chebyshev nodes, in barycentric form with
+// the exact-hit rule of Algorithm 1.
+void restrict_matrix(int d, int n, double* R) {
+  double td[bltc::kMaxDegree + 1], tn[bltc::kMaxDegree + 1];
+  bltc::cheb_points(d, td);
+  bltc::cheb_points(n, tn);
+  for (int m = 0; m <= n; ++m) {
+    double L[bltc::kMaxDegree + 1], sum = 0.0;
+    int flag = -1;
+    for (int k = 0; k <= d; ++k) {
+      const double wk = (k == 0 || k == d) ? ((k & 1) ? -0.5 : 0.5) : ((k & 1) ? -1.0 : 1.0);
+      const double diff = tn[m] - td[k];
+      if (std::fabs(diff) <= DBL_MIN) {
+        flag = k;
+        L[k] = 0.0;
+      } else {
+        L[k] = wk / diff;
+        sum += L[k];
+      }
+    }
+    for (int k = 0; k <= d; ++k)
+      R[k * (n + 1) + m] = flag >= 0 ? (k == flag ? 1.0 : 0.0) : L[k] / sum;
+  }
+}
+
+// Weights of degree d < n derived from those of degree n (which must
+// exist), cached under (d, n) until the weights change.  Lower degrees of
+// the separation rule take these, so a batch's result depends only on its
+// own top degree n, whichever other degrees a call uses.
+const bltc_degree_data& ensure_derived(bltc_tree t, int d, int n, hipStream_t s) {
+  if (d == n) return t->deg.at(n);
+  const auto key = std::make_pair(d, n);
+  auto it = t->derived.find(key);
+  if (it != t->derived.end()) return it->second;
+  const bltc_degree_data& src = t->deg.at(n);
+  const int64_t nn = t->host.nnodes();
+  const int d1 = d + 1;
+  const int64_t nk = (int64_t)d1 * d1 * d1;
+  bltc_degree_data e;
+  try {
+    const int wd = t->wdim;
+    const auto sp = t->spare_derived.find(key);
+    if (sp != t->spare_derived.end()) {
+      e = sp->second;
+      t->spare_derived.erase(sp);
+    } else {
+      e.grid = dalloc<double>(nn * 3 * d1);
+      e.fhat64 = dalloc<double>(nn * wd * nk);
+      e.p2p64 = dalloc<double>(nn * wd * nk);
+      e.p2p32 = dalloc<float>(nn * wd * nk);
+    }
+    double tk[bltc::kMaxDegree + 1];
+    bltc::cheb_points(d, tk);
+    StageTimer up(BLTC_STAGE_UPWARD, s);
+    hipchk(bltc::launch_grids(t->d_box, nn, d, tk, e.grid, s), "grids");
+    bltc::RestrictArgs ra;
+    ra.d1 = d1;
+    ra.n1 = n + 1;
+    restrict_matrix(d, n, ra.R);
+    hipchk(bltc::launch_restrict(ra, nn, wd, src.fhat64, e.fhat64, e.p2p64, e.p2p32, s),
+           "restrict");
+    up.stop();
+  } catch (...) {
+    destroy_degree(e);
+    throw;
+  }
+  return t->derived[key] = e;
+}
+
 void set_weights(bltc_tree t, const double* w, int wdim, hipStream_t s) {
   // the cached tables go stale; their buffers are kept for the next tables
   // of the same degree and width (no free or allocation per call)
@@ -529,10 +601,18 @@ void set_weights(bltc_tree t, const double* w, int wdim, hipStream_t s) {
     t->spare[kv.first] = kv.second;
   }
   t->deg.clear();
+  for (auto& kv : t->derived) {
+    auto it = t->spare_derived.find(kv.first);
+    if (it != t->spare_derived.end()) destroy_degree(it->second);
+    t->spare_derived[kv.first] = kv.second;
+  }
+  t->derived.clear();
   t->has_w = false;
   if (t->wdim != wdim) {
     for (auto& kv : t->spare) destroy_degree(kv.second);
     t->spare.clear();
+    for (auto& kv : t->spare_derived) destroy_degree(kv.second);
+    t->spare_derived.clear();
   }
   if (t->d_w64 && t->wdim != wdim) {
     dfree(t->d_w64);
@@ -703,19 +783,6 @@ void build_lists(bltc_tree t, bltc_targets g, double theta, const double* theta_
   *nd = tot[1];
 }
 
-// Weights for every degree that the proxy lists of nb batches carry (the
-// separation rule's degree field).
-void ensure_list_degrees(bltc_tree t, bltc_targets g, const bltc::ListSet& L, int64_t nb,
-                         hipStream_t s) {
-  hipchk(bltc::launch_degree_mask(nb, L.ptr, L.pids, (uint32_t*)(g->d_flags + 3), s),
-         "degree mask");
-  uint32_t mask = 0;
-  d2h(&mask, (uint32_t*)(g->d_flags + 3), 1, s);
-  sync(s);
-  for (int d = 1; d <= bltc::kMaxDegree; ++d)
-    if (mask >> d & 1u) ensure_degree(t, d, s);
-}
-
 // The particle-cluster evaluation of the batches in bmap (all if NULL) with
 // lists L and the modified weights of `degree`.
 void run_p2p(bltc_tree t, bltc_targets g, const bltc::ListSet& L, int kernel,
@@ -744,12 +811,10 @@ void run_p2p(bltc_tree t, bltc_targets g, const bltc::ListSet& L, int kernel,
   a.grid = d.grid;
   a.fhat = o.precision == BLTC_FP64 ? (const void*)d.p2p64 : (const void*)d.p2p32;
   if (o.deg_min >= 1 && o.deg_min < degree) {
-    for (int dd = o.deg_min; dd <= degree; ++dd) {   // the degrees the lists carry
-      const auto it = t->deg.find(dd);
-      if (it == t->deg.end()) continue;
-      a.grid_d[dd] = it->second.grid;
-      a.fhat_d[dd] = o.precision == BLTC_FP64 ? (const void*)it->second.p2p64
-                                               : (const void*)it->second.p2p32;
+    for (int dd = o.deg_min; dd <= degree; ++dd) {   // lower degrees derived from the top
+      const bltc_degree_data& e = dd == degree ? d : t->derived.at({dd, degree});
+      a.grid_d[dd] = e.grid;
+      a.fhat_d[dd] = o.precision == BLTC_FP64 ? (const void*)e.p2p64 : (const void*)e.p2p32;
     }
   }
   a.ys = t->d_y;
@@ -774,7 +839,8 @@ void evaluate_tree(bltc_tree t, bltc_targets g, int kernel, double eps,
   int64_t np = 0, nd = 0;
   const bltc::Rule rule = make_rule(theta, degree, o.deg_min);
   build_lists(t, g, theta, nullptr, g->ls[0], s, &np, &nd, &rule);
-  if (rule.deg_min > 0) ensure_list_degrees(t, g, g->ls[0], g->nb, s);   // the rule's lower degrees
+  for (int dd = std::max(rule.deg_min, 1); dd < degree && rule.deg_min > 0; ++dd)
+    ensure_derived(t, dd, degree, s);   // the rule's lower degrees
   run_p2p(t, g, g->ls[0], kernel, eps, degree, o, nullptr, 0, out, s);
 }
 
@@ -1129,18 +1195,9 @@ void evaluate_dual(bltc_tree src, bltc_tree tgt, int kernel, double eps, int deg
   hipchk(bltc::launch_grids(tgt->d_box, ntn, degree, tk, d_tgrid.p, s), "target grids");
   hipchk(bltc::launch_dual_points(d_gnode.p, ng, n1, d_tgrid.p, d_gpts.p, s), "grid points");
   lt.stop();
-  // the rule's lower degrees that the source side uses
-  if (rule.deg_min > 0) {
-    std::vector<bool> used(degree, false);
-    for (int64_t A = 0; A < ntn; ++A)
-      for (const auto* lst : {&D.cc[A], &D.pc[A]})
-        for (int32_t e : *lst) {
-          const int dd = e >> bltc::kDegShift;
-          if (dd < degree) used[dd] = true;
-        }
-    for (int dd = rule.deg_min; dd < degree; ++dd)
-      if (used[dd]) ensure_degree(src, dd, s);
-  }
+  // the rule's lower degrees, derived from the top degree's weights
+  for (int dd = rule.deg_min; dd < degree && rule.deg_min > 0; ++dd)
+    ensure_derived(src, dd, degree, s);
 
   StageTimer ev(BLTC_STAGE_EVAL, s);
   // the particle-cluster kernel over a point set: batches bp/bg, proxy
@@ -1164,12 +1221,10 @@ void evaluate_dual(bltc_tree src, bltc_tree tgt, int kernel, double eps, int deg
     a.grid = d.grid;
     a.fhat = o.precision == BLTC_FP64 ? (const void*)d.p2p64 : (const void*)d.p2p32;
     if (rule.deg_min > 0) {
-      for (int dd = rule.deg_min; dd <= degree; ++dd) {   // the degrees the lists carry
-        const auto it = src->deg.find(dd);
-        if (it == src->deg.end()) continue;
-        a.grid_d[dd] = it->second.grid;
-        a.fhat_d[dd] = o.precision == BLTC_FP64 ? (const void*)it->second.p2p64
-                                                 : (const void*)it->second.p2p32;
+      for (int dd = rule.deg_min; dd <= degree; ++dd) {   // lower degrees derived from the top
+        const bltc_degree_data& e = dd == degree ? d : src->derived.at({dd, degree});
+        a.grid_d[dd] = e.grid;
+        a.fhat_d[dd] = o.precision == BLTC_FP64 ? (const void*)e.p2p64 : (const void*)e.p2p32;
       }
     }
     a.ys = src->d_y;
@@ -1355,9 +1410,13 @@ void evaluate_adaptive(bltc_tree t, bltc_targets g, int kernel, double eps,
     order.insert(order.end(), kv.second.begin(), kv.second.end());
   }
   h2d(g->d_bmap, order.data(), nb, s);
-  // each group's top degree, and with the rule every degree an entry carries
-  for (auto& sp : spans) ensure_degree(t, sp.first, s);
-  if (rule_min > 0) ensure_list_degrees(t, g, g->ls[0], nb, s);
+  // each group's top degree and, with the rule, the lower degrees derived
+  // from it (a batch's result then depends on its own top degree only)
+  for (auto& sp : spans) {
+    ensure_degree(t, sp.first, s);
+    for (int dd = rule_min; dd < sp.first && rule_min > 0; ++dd)
+      ensure_derived(t, dd, sp.first, s);
+  }
   bltc_options og = o;
   og.deg_min = rule_min;
   // the degree groups write disjoint targets: with more than one, they run
@@ -2077,6 +2136,7 @@ int bltc_evaluate_adaptive(bltc_tree t, bltc_targets g, int32_t kernel, double e
   bltc_options o;
   bltc_options_default(&o);
   if (opt) o = *opt;
+  o.deg_min = 0;   // the candidates take the model's rule, the fallback none
   if (int rc = check_options(&o, kernel)) return rc;
   if (g->m > 0 && !device_ptr(out)) return fail(BLTC_EINVAL, "out must be a device pointer");
   if (!t->has_w) return fail(BLTC_ESTATE, "no weights: call bltc_compute_modified_weights first");

@@ -257,10 +257,6 @@ hipError_t launch_batch_weights(int64_t nb, int stride, const int32_t* bptr,
 hipError_t launch_flag(int ns, const double* contrib, double thr, int32_t* flag,
                        hipStream_t s);
 hipError_t launch_cand_costs(const CostArgs& a, hipStream_t s);
-// mask[0] = the bits 1 << d of the degrees d carried by the proxy lists of
-// nb batches (entries with the separation rule's degree field).
-hipError_t launch_degree_mask(int64_t nb, const int32_t* pptr, const int32_t* pids,
-                              uint32_t* mask, hipStream_t s);
 hipError_t launch_dual_points(const int32_t* gnode, int64_t ng, int n1, const double* tgrid,
                               double* pts, hipStream_t s);
 hipError_t launch_dual_down(int odim, int n1, const DualDownArgs& a, hipStream_t s);
@@ -292,6 +288,14 @@ hipError_t launch_upward(const double* ys, const double* w64, int64_t n, int wd,
 hipError_t launch_upward_reduce(const int32_t* chunk_ptr, int64_t nn,
                                 const double* partial, int degree, int wd,
                                 double* fhat64, double* p2p64, float* p2p32, hipStream_t s);
+// Lower-degree weights from a higher degree's of the same clusters:
+// R[k * n1 + m] = L^d_k(t^n_m) on the reference nodes, d1 = d + 1 <= n1 = n + 1.
+struct RestrictArgs {
+  double R[(kMaxDegree + 1) * (kMaxDegree + 1)];
+  int32_t d1 = 0, n1 = 0;
+};
+hipError_t launch_restrict(const RestrictArgs& a, int64_t nn, int wd, const double* src,
+                           double* fhat64, double* p2p64, float* p2p32, hipStream_t s);
 // Parents nodes[0..count) from their children's weights (one tree level).
 hipError_t launch_m2m(const int32_t* nodes, int64_t count, const int2* kids, int degree, int wd,
                       const double* grid, double* fhat64, double* p2p64, float* p2p32,
@@ -361,6 +365,9 @@ struct bltc_tree_s {
   float* d_w32 = nullptr;
   std::map<int, bltc_degree_data> deg;
   std::map<int, bltc_degree_data> spare;   // buffers of stale tables, by degree
+  // separation rule: degree d derived from the weights of degree n > d,
+  // keyed (d, n), and the buffers of stale ones
+  std::map<std::pair<int, int>, bltc_degree_data> derived, spare_derived;
   bltc_dual_cache* dual = nullptr;   // cluster-cluster buffers (as the target tree)
   // upward pass: chunks of the leaves' particle ranges, and the parents by
   // level, deepest level first
@@ -395,7 +402,7 @@ struct bltc_targets_s {
   double* d_x = nullptr;       // tree-ordered [3][m]
   int32_t* d_bptr = nullptr;
   double4* d_bgeo = nullptr;
-  int32_t* d_flags = nullptr;  // [4]: walk error, scan overflow x2, degree mask
+  int32_t* d_flags = nullptr;  // [4]: walk error, scan overflow x2, unused
   bltc::ListSet ls[2];         // [0] evaluation lists, [1] guard lists
   // per-batch selection scratch (allocated on first adaptive call)
   float* d_feat = nullptr;     // [nb][12]

@@ -311,17 +311,6 @@ __global__ void k_flag(int ns, const double* __restrict__ contrib, double thr,
   if (i < ns) flag[i] = contrib[i] > thr ? 1 : 0;
 }
 
-// mask[0] |= 1 << d for every degree d that the proxy lists carry
-// (separation rule); mask[0] starts at zero.
-__global__ void k_degree_mask(int64_t nb, const int32_t* __restrict__ pptr,
-                              const int32_t* __restrict__ pids, uint32_t* __restrict__ mask) {
-  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= nb) return;
-  uint32_t m = 0;
-  for (int l = pptr[b]; l < pptr[b + 1]; ++l) m |= 1u << (pids[l] >> kDegShift);
-  if (m) atomicOr(mask, m);
-}
-
 __global__ void k_fill_i32(int32_t* __restrict__ p, int64_t n, int32_t v) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
@@ -412,15 +401,6 @@ hipError_t launch_cand_costs(const CostArgs& a, hipStream_t s) {
 hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s) {
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n, v);
-  return hipGetLastError();
-}
-
-hipError_t launch_degree_mask(int64_t nb, const int32_t* pptr, const int32_t* pids,
-                              uint32_t* mask, hipStream_t s) {
-  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, (int32_t*)mask, (int64_t)1, 0);
-  if (nb > 0)
-    hipLaunchKernelGGL(k_degree_mask, dim3((unsigned)((nb + 127) / 128)), dim3(128), 0, s, nb,
-                       pptr, pids, mask);
   return hipGetLastError();
 }
 

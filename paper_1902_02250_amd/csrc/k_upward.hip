@@ -248,6 +248,55 @@ __global__ __launch_bounds__(kThreads) void k_m2m(const int32_t* __restrict__ no
   }
 }
 
+// Weights of a lower degree d from those of degree n of the same cluster
+// (separation rule): every L^d_k is a polynomial of degree d <= n, which
+// degree-n interpolation reproduces, so
+//   fhat^d[k] = sum_m R[k1][m1] R[k2][m2] R[k3][m3] fhat^n[m],  R[k][m] = L^d_k(t^n_m)
+// on the reference nodes (the same for every cluster and axis).  One work
+// group per (cluster, weight row c = blockIdx.y); three separable
+// contractions through LDS in a fixed order.
+__global__ __launch_bounds__(kThreads) void k_restrict(RestrictArgs a, int wd,
+                                                       const double* __restrict__ src,
+                                                       double* __restrict__ fhat64,
+                                                       double* __restrict__ p2p64,
+                                                       float* __restrict__ p2p32) {
+  constexpr int M = kMaxDegree + 1;
+  __shared__ double sR[M * M];
+  __shared__ double sF[M * M * M];
+  __shared__ double sA[M * M * M];
+  const int64_t q = blockIdx.x;
+  const int c = blockIdx.y, t = threadIdx.x;
+  const int d1 = a.d1, n1 = a.n1;
+  const int ns = n1 * n1 * n1, nd = d1 * d1 * d1;
+  for (int i = t; i < d1 * n1; i += kThreads) sR[i] = a.R[i];
+  const double* __restrict__ F = src + (q * wd + c) * ns;
+  for (int i = t; i < ns; i += kThreads) sF[i] = F[i];
+  __syncthreads();
+  for (int i = t; i < d1 * n1 * n1; i += kThreads) {   // A[k1][m2][m3]
+    const int k1 = i / (n1 * n1), r = i % (n1 * n1);
+    double s = 0.0;
+    for (int m = 0; m < n1; ++m) s = fma(sR[k1 * n1 + m], sF[m * n1 * n1 + r], s);
+    sA[i] = s;
+  }
+  __syncthreads();
+  for (int i = t; i < d1 * d1 * n1; i += kThreads) {   // B[k1][k2][m3], into sF
+    const int k1 = i / (d1 * n1), k2 = (i / n1) % d1, m3 = i % n1;
+    double s = 0.0;
+    for (int m = 0; m < n1; ++m) s = fma(sR[k2 * n1 + m], sA[(k1 * n1 + m) * n1 + m3], s);
+    sF[i] = s;
+  }
+  __syncthreads();
+  for (int i = t; i < nd; i += kThreads) {             // fhat^d[k1][k2][k3]
+    const int k12 = i / d1, k3 = i % d1;
+    double s = 0.0;
+    for (int m = 0; m < n1; ++m) s = fma(sR[k3 * n1 + m], sF[k12 * n1 + m], s);
+    fhat64[(q * wd + c) * nd + i] = s;
+    const int64_t o = q * wd * nd + ((int64_t)k12 * wd + c) * d1 + k3;
+    p2p64[o] = s;
+    p2p32[o] = (float)s;
+  }
+}
+
 template <int N1>
 hipError_t run_upward(const double* ys, const double* w64, int64_t n, int wd,
                       const int4* chunks, int64_t nchunks, const double* grid,
@@ -318,6 +367,15 @@ hipError_t launch_m2m(const int32_t* nodes, int64_t count, const int2* kids, int
     default:
       return hipErrorInvalidValue;
   }
+}
+
+hipError_t launch_restrict(const RestrictArgs& a, int64_t nn, int wd, const double* src,
+                           double* fhat64, double* p2p64, float* p2p32, hipStream_t s) {
+  if (nn == 0) return hipSuccess;
+  if (a.d1 < 1 || a.n1 < a.d1 || a.n1 > kMaxDegree + 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_restrict, dim3((unsigned)nn, (unsigned)wd), dim3(kThreads), 0, s, a, wd,
+                     src, fhat64, p2p64, p2p32);
+  return hipGetLastError();
 }
 
 }  // namespace bltc
