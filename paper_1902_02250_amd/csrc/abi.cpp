@@ -646,6 +646,7 @@ void destroy_targets(bltc_targets g) {
   dfree(g->d_wt); dfree(g->d_usq); dfree(g->d_contrib); dfree(g->d_part); dfree(g->d_sums); dfree(g->d_lam);
   dfree(g->d_cost); dfree(g->d_e2); dfree(g->d_candT); dfree(g->d_candn);
   delete g->split;
+  dfree(g->d_dmask);
   delete g;
 }
 
@@ -674,6 +675,7 @@ void build_targets(const double* x, const double* y, const double* z,
     L.ptr = dalloc<int32_t>(2 * (nb + 1));
   }
   g->d_flags = dalloc<int32_t>(4);
+  g->d_dmask = dalloc<uint32_t>(bltc::kMaxDegree + 1);
   h2d(g->d_bptr, B.bptr.data(), nb + 1, s);
   {
     int32_t* d_bend = dalloc<int32_t>(nb);
@@ -783,6 +785,25 @@ void build_lists(bltc_tree t, bltc_targets g, double theta, const double* theta_
   *nd = tot[1];
 }
 
+// The separation rule's lower degrees that each evaluation group uses, derived
+// from the group's top degree: groups (top degree, batches bsel[0..count)),
+// bsel NULL for all batches.
+void derive_used_degrees(bltc_tree t, bltc_targets g, const bltc::ListSet& L, int rule_min,
+                         const std::vector<std::pair<int, std::pair<const int32_t*, int64_t>>>& grp,
+                         hipStream_t s) {
+  if (rule_min <= 0 || grp.empty()) return;
+  for (size_t i = 0; i < grp.size(); ++i)
+    hipchk(bltc::launch_degree_mask(grp[i].second.first, grp[i].second.second, L.ptr, L.pids,
+                                    g->d_dmask + i, s),
+           "degree mask");
+  std::vector<uint32_t> mask(grp.size());
+  d2h(mask.data(), g->d_dmask, grp.size(), s);
+  sync(s);
+  for (size_t i = 0; i < grp.size(); ++i)
+    for (int dd = rule_min; dd < grp[i].first; ++dd)
+      if (mask[i] >> dd & 1u) ensure_derived(t, dd, grp[i].first, s);
+}
+
 // The particle-cluster evaluation of the batches in bmap (all if NULL) with
 // lists L and the modified weights of `degree`.
 void run_p2p(bltc_tree t, bltc_targets g, const bltc::ListSet& L, int kernel,
@@ -812,9 +833,14 @@ void run_p2p(bltc_tree t, bltc_targets g, const bltc::ListSet& L, int kernel,
   a.fhat = o.precision == BLTC_FP64 ? (const void*)d.p2p64 : (const void*)d.p2p32;
   if (o.deg_min >= 1 && o.deg_min < degree) {
     for (int dd = o.deg_min; dd <= degree; ++dd) {   // lower degrees derived from the top
-      const bltc_degree_data& e = dd == degree ? d : t->derived.at({dd, degree});
-      a.grid_d[dd] = e.grid;
-      a.fhat_d[dd] = o.precision == BLTC_FP64 ? (const void*)e.p2p64 : (const void*)e.p2p32;
+      const bltc_degree_data* e = &d;
+      if (dd < degree) {
+        const auto it = t->derived.find({dd, degree});
+        if (it == t->derived.end()) continue;   // a degree no list entry carries
+        e = &it->second;
+      }
+      a.grid_d[dd] = e->grid;
+      a.fhat_d[dd] = o.precision == BLTC_FP64 ? (const void*)e->p2p64 : (const void*)e->p2p32;
     }
   }
   a.ys = t->d_y;
@@ -839,8 +865,7 @@ void evaluate_tree(bltc_tree t, bltc_targets g, int kernel, double eps,
   int64_t np = 0, nd = 0;
   const bltc::Rule rule = make_rule(theta, degree, o.deg_min);
   build_lists(t, g, theta, nullptr, g->ls[0], s, &np, &nd, &rule);
-  for (int dd = std::max(rule.deg_min, 1); dd < degree && rule.deg_min > 0; ++dd)
-    ensure_derived(t, dd, degree, s);   // the rule's lower degrees
+  derive_used_degrees(t, g, g->ls[0], rule.deg_min, {{degree, {nullptr, g->nb}}}, s);
   run_p2p(t, g, g->ls[0], kernel, eps, degree, o, nullptr, 0, out, s);
 }
 
@@ -1195,9 +1220,19 @@ void evaluate_dual(bltc_tree src, bltc_tree tgt, int kernel, double eps, int deg
   hipchk(bltc::launch_grids(tgt->d_box, ntn, degree, tk, d_tgrid.p, s), "target grids");
   hipchk(bltc::launch_dual_points(d_gnode.p, ng, n1, d_tgrid.p, d_gpts.p, s), "grid points");
   lt.stop();
-  // the rule's lower degrees, derived from the top degree's weights
-  for (int dd = rule.deg_min; dd < degree && rule.deg_min > 0; ++dd)
-    ensure_derived(src, dd, degree, s);
+  // the rule's lower degrees that the source side uses, derived from the top
+  // degree's weights
+  if (rule.deg_min > 0) {
+    std::vector<bool> used(degree, false);
+    for (int64_t A = 0; A < ntn; ++A)
+      for (const auto* lst : {&D.cc[A], &D.pc[A]})
+        for (int32_t e : *lst) {
+          const int dd = e >> bltc::kDegShift;
+          if (dd < degree) used[dd] = true;
+        }
+    for (int dd = rule.deg_min; dd < degree; ++dd)
+      if (used[dd]) ensure_derived(src, dd, degree, s);
+  }
 
   StageTimer ev(BLTC_STAGE_EVAL, s);
   // the particle-cluster kernel over a point set: batches bp/bg, proxy
@@ -1222,9 +1257,14 @@ void evaluate_dual(bltc_tree src, bltc_tree tgt, int kernel, double eps, int deg
     a.fhat = o.precision == BLTC_FP64 ? (const void*)d.p2p64 : (const void*)d.p2p32;
     if (rule.deg_min > 0) {
       for (int dd = rule.deg_min; dd <= degree; ++dd) {   // lower degrees derived from the top
-        const bltc_degree_data& e = dd == degree ? d : src->derived.at({dd, degree});
-        a.grid_d[dd] = e.grid;
-        a.fhat_d[dd] = o.precision == BLTC_FP64 ? (const void*)e.p2p64 : (const void*)e.p2p32;
+        const bltc_degree_data* e = &d;
+        if (dd < degree) {
+          const auto it = src->derived.find({dd, degree});
+          if (it == src->derived.end()) continue;   // a degree no list entry carries
+          e = &it->second;
+        }
+        a.grid_d[dd] = e->grid;
+        a.fhat_d[dd] = o.precision == BLTC_FP64 ? (const void*)e->p2p64 : (const void*)e->p2p32;
       }
     }
     a.ys = src->d_y;
@@ -1412,11 +1452,12 @@ void evaluate_adaptive(bltc_tree t, bltc_targets g, int kernel, double eps,
   h2d(g->d_bmap, order.data(), nb, s);
   // each group's top degree and, with the rule, the lower degrees derived
   // from it (a batch's result then depends on its own top degree only)
+  std::vector<std::pair<int, std::pair<const int32_t*, int64_t>>> grp;
   for (auto& sp : spans) {
     ensure_degree(t, sp.first, s);
-    for (int dd = rule_min; dd < sp.first && rule_min > 0; ++dd)
-      ensure_derived(t, dd, sp.first, s);
+    grp.push_back({sp.first, {g->d_bmap + sp.second.first, sp.second.second}});
   }
+  derive_used_degrees(t, g, g->ls[0], rule_min, grp, s);
   bltc_options og = o;
   og.deg_min = rule_min;
   // the degree groups write disjoint targets: with more than one, they run

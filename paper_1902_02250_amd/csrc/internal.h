@@ -257,6 +257,10 @@ hipError_t launch_batch_weights(int64_t nb, int stride, const int32_t* bptr,
 hipError_t launch_flag(int ns, const double* contrib, double thr, int32_t* flag,
                        hipStream_t s);
 hipError_t launch_cand_costs(const CostArgs& a, hipStream_t s);
+// mask[0] = the bits 1 << d of the degrees d that the proxy lists of the
+// batches bsel[0..nsel) carry (all nsel batches when bsel is NULL).
+hipError_t launch_degree_mask(const int32_t* bsel, int64_t nsel, const int32_t* pptr,
+                              const int32_t* pids, uint32_t* mask, hipStream_t s);
 hipError_t launch_dual_points(const int32_t* gnode, int64_t ng, int n1, const double* tgrid,
                               double* pts, hipStream_t s);
 hipError_t launch_dual_down(int odim, int n1, const DualDownArgs& a, hipStream_t s);
@@ -394,6 +398,7 @@ struct ListSet {
 struct bltc_targets_s {
   int device = 0;
   bltc_split_cache* split = nullptr;   // the judge's repair slices (grown on demand)
+  uint32_t* d_dmask = nullptr;   // [kMaxDegree + 1] degrees used per evaluation group
   int64_t m = 0, nb = 0;
   int32_t batch_size = 0, order_leaf = 0;
   int64_t group_max = 0;

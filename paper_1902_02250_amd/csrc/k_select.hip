@@ -311,6 +311,19 @@ __global__ void k_flag(int ns, const double* __restrict__ contrib, double thr,
   if (i < ns) flag[i] = contrib[i] > thr ? 1 : 0;
 }
 
+// mask[0] |= 1 << d for every degree d that the proxy lists of the batches
+// bsel[0..nsel) carry (all batches when bsel is NULL); mask[0] starts at 0.
+__global__ void k_degree_mask(const int32_t* __restrict__ bsel, int64_t nsel,
+                              const int32_t* __restrict__ pptr,
+                              const int32_t* __restrict__ pids, uint32_t* __restrict__ mask) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nsel) return;
+  const int64_t b = bsel ? bsel[i] : i;
+  uint32_t m = 0;
+  for (int l = pptr[b]; l < pptr[b + 1]; ++l) m |= 1u << (pids[l] >> kDegShift);
+  if (m) atomicOr(mask, m);
+}
+
 __global__ void k_fill_i32(int32_t* __restrict__ p, int64_t n, int32_t v) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
@@ -401,6 +414,15 @@ hipError_t launch_cand_costs(const CostArgs& a, hipStream_t s) {
 hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s) {
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_degree_mask(const int32_t* bsel, int64_t nsel, const int32_t* pptr,
+                              const int32_t* pids, uint32_t* mask, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, (int32_t*)mask, (int64_t)1, 0);
+  if (nsel > 0)
+    hipLaunchKernelGGL(k_degree_mask, dim3((unsigned)((nsel + 127) / 128)), dim3(128), 0, s,
+                       bsel, nsel, pptr, pids, mask);
   return hipGetLastError();
 }
 
