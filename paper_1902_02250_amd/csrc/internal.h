@@ -407,7 +407,7 @@ struct bltc_targets_s {
   double* d_x = nullptr;       // tree-ordered [3][m]
   int32_t* d_bptr = nullptr;
   double4* d_bgeo = nullptr;
-  int32_t* d_flags = nullptr;  // [4]: walk error, scan overflow x2, unused
+  int32_t* d_flags = nullptr;  // [4]: walk error, scan overflow x2, spare
   bltc::ListSet ls[2];         // [0] evaluation lists, [1] guard lists
   // per-batch selection scratch (allocated on first adaptive call)
   float* d_feat = nullptr;     // [nb][12]
