@@ -95,9 +95,12 @@ typedef struct {
                           (Chebyshev interpolation converges like kappa^d for
                           a singularity at ratio r); tested as
                           rho^2 <= (2k/(1+k^2))^2, k = kappa(theta)^((n+1)/(d+1)).
-                          The modified weights of the lower degrees are
-                          computed by the evaluation for the clusters that
-                          need them. */
+                          The evaluation derives the weights of each lower
+                          degree the lists use from the degree-n weights
+                          (degree-n interpolation reproduces the degree-d
+                          Lagrange basis, so this equals the sum over the
+                          particles up to rounding); they are cached until
+                          the weights change. */
 } bltc_options;
 
 typedef struct bltc_tree_s* bltc_tree;       /* sources: tree, weights */
