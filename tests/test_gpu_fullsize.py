@@ -47,3 +47,30 @@ def test_full_size_sampled(torch, orc, name, kernel):
         err = orc.rel_l2(ref, got)
         print(f"[fullsize] {name} {precision}: rel L2 vs oracle {err:.3e}", flush=True)
         assert err <= tol, (precision, err)
+
+
+def test_full_size_separation_rule(torch, orc):
+    """The 1e6 uniform workload at the separation rule's setting for E <= 1e-6
+    (n = 10, theta = 0.7, deg_min = 1): the library derives the lower degrees'
+    weights from the degree-10 weights, the oracle sums every degree over the
+    particles (Algorithm 1)."""
+    src, w, cfg = inputs.workload("c3")
+    n, degree, theta = src.shape[1], 10, 0.7
+    print(f"[fullsize] c3 rule: n={n} degree={degree} theta={theta} deg_min=1", flush=True)
+    d_src = torch.from_numpy(src).cuda()
+    d_w = torch.from_numpy(w).cuda()
+    T = bltc.Tree(d_src, cfg["leaf"])
+    T.compute_weights(d_w, degree)
+    G = bltc.Targets(d_src, 64, 32, 512)
+    idx = inputs.sample_indices(n, 2000, 5)
+    ref, _, _ = orc.treecode(cfg["kernel"], src, src, w, cfg["eps"], degree, theta, cfg["leaf"],
+                             mac_mode=1, batch_size=64, order_leaf=32, group_max=512,
+                             sample=idx, deg_min=1)
+    d_idx = torch.from_numpy(idx).cuda()
+    for precision, tol in (("fp64", 1e-12), ("fp32_fp64acc", 1e-6)):
+        out = bltc.evaluate_tree(T, G, cfg["kernel"], cfg["eps"], degree, theta,
+                                 precision=precision, deg_min=1)
+        got = out[:, d_idx].cpu().numpy()
+        err = orc.rel_l2(ref, got)
+        print(f"[fullsize] c3 rule {precision}: rel L2 vs oracle {err:.3e}", flush=True)
+        assert err <= tol, (precision, err)
