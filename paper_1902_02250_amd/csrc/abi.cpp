@@ -112,15 +112,6 @@ bool device_ptr(const void* p) {
   return attr.type == hipMemoryTypeDevice || attr.type == hipMemoryTypeManaged;
 }
 
-// Copies n doubles from a device (or host) array to the host.
-void fetch(std::vector<double>& dst, const double* src, int64_t n,
-           hipStream_t s) {
-  dst.resize(n);
-  if (n)
-    hipchk(hipMemcpyAsync(dst.data(), src, sizeof(double) * n, hipMemcpyDefault, s),
-           "hipMemcpyAsync");
-}
-
 int odim_of(int kernel) { return kernel == BLTC_ROTLET || kernel == BLTC_FULL ? 6 : 3; }
 int wdim_of(int kernel) { return kernel == BLTC_FULL ? 6 : 3; }
 

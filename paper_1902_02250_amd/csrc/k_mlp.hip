@@ -95,7 +95,7 @@ __global__ __launch_bounds__(kThreads) void k_mlp_loss(
   red[threadIdx.x] = sq;
   __syncthreads();
   for (int s = kThreads / 2; s > 0; s >>= 1) {
-    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
     __syncthreads();
   }
   if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
