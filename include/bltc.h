@@ -120,8 +120,11 @@ const char* bltc_version(void);
  * the code bx + 2 by + 4 bz; empty children are dropped; a cluster
  * with l_max = 0 or whose bisection would separate nothing stays a leaf.
  * Center = box midpoint, radius = half the box diagonal.  The tree is built
- * on the host from a copy of the coordinates (synchronises on `stream`);
- * tree-ordered coordinates and the node arrays are kept on the device. */
+ * on the device one level at a time (per-chunk min/max, split tests, code
+ * histograms, a stable scatter); the host numbers the children from one
+ * read-back per level and keeps a copy of the node arrays (synchronises on
+ * `stream`).  Tree-ordered coordinates and the node arrays stay on the
+ * device. */
 int bltc_build_tree(const double* x, const double* y, const double* z,
                     int64_t n, int64_t leaf_max, void* stream, bltc_tree* out);
 int bltc_tree_destroy(bltc_tree t);
@@ -163,8 +166,10 @@ int bltc_modified_weights_export(bltc_tree t, int32_t degree, double* fhat,
  * (and any larger degenerate leaf) are the groups; each group is cut into
  * consecutive batches of batch_size targets, so a batch never spans two
  * groups and its radius is bounded by its group's.  Each batch gets its
- * tight box, center and radius like a cluster.  Built on the host
- * (synchronises); the order and batches live on the device. */
+ * tight box, center and radius like a cluster.  The order tree is built on
+ * the device as in bltc_build_tree, the group and batch bounds on the host
+ * from its node arrays, the batch boxes on the device (synchronises); the
+ * order and batches live on the device. */
 int bltc_build_targets(const double* x, const double* y, const double* z,
                        int64_t m, int32_t batch_size, int32_t order_leaf,
                        int64_t group_max, void* stream, bltc_targets* out);
@@ -377,6 +382,13 @@ int bltc_evaluate_adaptive(bltc_tree t, bltc_targets g, int32_t kernel, double e
                            double fb_theta, const bltc_options* opt, double* out,
                            int32_t* choice, int64_t* stats, double* judge,
                            void* stream);
+
+/* ---- testing ---------------------------------------------------------------
+ * Failure injection for tests of the error paths: the after-th device
+ * allocation the library makes from now on fails as if the device were out
+ * of memory (the call returns BLTC_ENOMEM with no output written); 0
+ * disarms.  Process wide; not thread safe. */
+int bltc_test_fail_alloc(int32_t after);
 
 /* ---- measurement ---------------------------------------------------------
  * Stage timing with HIP events recorded on the evaluation stream around each

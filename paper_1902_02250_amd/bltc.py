@@ -97,6 +97,7 @@ def load():
         "bltc_batch_features": (ctypes.c_int, [P, P, I32, D, D, P, P]),
         "bltc_batch_counts": (ctypes.c_int, [P, P, D, P, P, P]),
         "bltc_evaluate_adaptive": (ctypes.c_int, [P, P, I32, D, P, D, I32, I32, D, P, P, P, P, P, P]),
+        "bltc_test_fail_alloc": (ctypes.c_int, [I32]),
         "bltc_profile_enable": (ctypes.c_int, [I32]),
         "bltc_profile_read": (ctypes.c_int, [P, P, I32]),
         "bltc_direct": (ctypes.c_int, [P, P, P, I64, P, I64, P, P, P, I64, P, I32,
@@ -234,6 +235,8 @@ class Targets:
         x, y, z, m = _rows(tgt, "tgt")
         self.m = m
         self.batch_size = batch_size
+        self.order_leaf = order_leaf
+        self.group_max = group_max
         h = ctypes.c_void_p()
         _check(L.bltc_build_targets(x, y, z, m, int(batch_size), int(order_leaf),
                                     int(group_max), _stream(), ctypes.byref(h)))
@@ -270,7 +273,8 @@ def evaluate_tree(tree, targets, kernel, eps, degree, theta, precision="fp64",
     if out is None:
         out = torch.empty((od, targets.m), dtype=torch.float64, device="cuda")
     _dev(out, "out", od)
-    o = options(precision, targets.batch_size, 32, poly_p, poly_c, deg_min=deg_min)
+    o = options(precision, targets.batch_size, targets.order_leaf, poly_p, poly_c,
+                targets.group_max, deg_min)
     ptr = ctypes.c_void_p(out.data_ptr()) if targets.m else None
     _check(load().bltc_evaluate_tree(tree._h, targets._h, KERNELS[kernel], float(eps),
                                      int(degree), float(theta), ctypes.byref(o), ptr,
@@ -553,7 +557,7 @@ def evaluate_adaptive(tree, targets, kernel, eps, selector, tol, fb_degree, fb_t
     if out is None:
         out = torch.empty((od, targets.m), dtype=torch.float64, device="cuda")
     _dev(out, "out", od)
-    o = options(precision, targets.batch_size, 32)
+    o = options(precision, targets.batch_size, targets.order_leaf, group_max=targets.group_max)
     choice = np.zeros(max(targets.nb, 1), np.int32)
     stats = np.zeros(4, np.int64)
     judge = np.zeros(2, np.float64)
@@ -564,3 +568,9 @@ def evaluate_adaptive(tree, targets, kernel, eps, selector, tol, fb_degree, fb_t
                                          ctypes.c_void_p(out.data_ptr()) if targets.m else None,
                                          _hp(choice), _hp(stats), _hp(judge), _stream()))
     return out, choice[:targets.nb], stats, judge
+
+
+def inject_alloc_failure(after):
+    """Failure injection (bltc_test_fail_alloc): the after-th device
+    allocation from now fails with BLTC_ENOMEM; 0 disarms."""
+    _check(load().bltc_test_fail_alloc(int(after)))

@@ -19,10 +19,11 @@ LIBDIR = os.path.join(HERE, "lib")
 LIB = os.path.join(LIBDIR, "libbltc.so")
 BUILD = os.path.join(HERE, "_build")
 
-SOURCES = ["abi.cpp", "tree_host.cpp", "k_prep.hip", "k_lists.hip",
-           "k_upward.hip", "k_p2p.hip", "k_direct.hip", "k_mlp.hip", "k_select.hip",
-           "k_tree.hip", "k_dual.hip"]
-EXACT = {"abi.cpp", "tree_host.cpp", "k_prep.hip", "k_lists.hip", "k_tree.hip"}
+HOST_UNITS = ["host.cpp", "api_tree.cpp", "api_eval.cpp", "api_select.cpp", "api_dual.cpp",
+              "tree_host.cpp"]
+SOURCES = HOST_UNITS + ["k_prep.hip", "k_lists.hip", "k_upward.hip", "k_p2p.hip",
+                        "k_direct.hip", "k_mlp.hip", "k_select.hip", "k_tree.hip", "k_dual.hip"]
+EXACT = set(HOST_UNITS) | {"k_prep.hip", "k_lists.hip", "k_tree.hip", "k_select.hip"}
 
 COMMON = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -9,6 +9,7 @@ tiles, ragged tails and the parameter limits.
 import numpy as np
 import pytest
 
+from closeness import close
 from paper_1902_02250_amd import bltc, inputs
 
 pytestmark = pytest.mark.gpu
@@ -218,14 +219,14 @@ def test_direct_fp64(torch, orc, kernel):
     tgt = inputs.points("mixture", 777, 4)
     got = bltc.direct(_d(torch, tgt), _d(torch, src), _d(torch, w), kernel, 0.01).cpu().numpy()
     ref = orc.direct(kernel, tgt, src, w, eps=0.01)
-    assert orc.rel_l2(ref, got) <= FP64_TOL
+    close(orc, ref, got, FP64_TOL)
     idx = inputs.sample_indices(777, 50, 1)
     sub = bltc.direct(_d(torch, tgt), _d(torch, src), _d(torch, w), kernel, 0.01,
                       idx=torch.from_numpy(idx).cuda()).cpu().numpy()
     assert np.array_equal(sub, got[:, idx])
     m32 = bltc.direct(_d(torch, tgt), _d(torch, src), _d(torch, w), kernel, 0.01,
                       precision="fp32_fp64acc").cpu().numpy()
-    assert orc.rel_l2(ref, m32) <= MIXED_TOL
+    close(orc, ref, m32, MIXED_TOL)
 
 
 def test_direct_poly_integer_bit_exact(torch, orc):
@@ -257,7 +258,7 @@ def test_treecode_fp64_c1(torch, orc, kernel):
     src, w, cfg = inputs.workload("c1")
     got, ref = _tree_case(torch, orc, kernel, src, src, w, cfg["eps"], cfg["degree"],
                           cfg["theta"], cfg["leaf"], 64, 64)
-    assert orc.rel_l2(ref, got) <= FP64_TOL
+    close(orc, ref, got, FP64_TOL)
 
 
 @pytest.mark.parametrize("kernel,degree,theta,bs,ol", [
@@ -269,7 +270,7 @@ def test_treecode_fp64_ragged(torch, orc, kernel, degree, theta, bs, ol):
     w = inputs.weights(10007, 12, bltc.WDIM[kernel])
     tgt = inputs.points("union", 3001 if bs > 1 else 700, 13) * 1.1
     got, ref = _tree_case(torch, orc, kernel, src, tgt, w, 0.02, degree, theta, 200, bs, ol)
-    assert orc.rel_l2(ref, got) <= FP64_TOL
+    close(orc, ref, got, FP64_TOL)
 
 
 def test_treecode_poly(torch, orc):
@@ -280,9 +281,9 @@ def test_treecode_poly(torch, orc):
     w = inputs.weights(6000, 2)
     got, ref = _tree_case(torch, orc, "poly", src, src, w, 0.0, 4, 0.7, 150, 64, 64,
                           poly_p=4, poly_c=1.5)
-    assert orc.rel_l2(ref, got) <= FP64_TOL
+    close(orc, ref, got, FP64_TOL)
     d = orc.direct("poly", src, src, w, poly_p=4, poly_c=1.5)
-    assert orc.rel_l2(d, got) <= FP64_TOL
+    close(orc, d, got, FP64_TOL)
     rng = np.random.default_rng(3)
     isrc = rng.integers(-3, 4, (3, 2000)).astype(np.float64)
     iw = rng.integers(-5, 6, (3, 2000)).astype(np.float64)
@@ -299,7 +300,7 @@ def test_treecode_mixed(torch, orc, precision, kernel):
         w = inputs.weights(20000, 1, 6)
     got, ref = _tree_case(torch, orc, kernel, src, src, w, 0.005, 6, 0.7, 500, 64, 64,
                           precision=precision)
-    assert orc.rel_l2(ref, got) <= MIXED_TOL
+    close(orc, ref, got, MIXED_TOL)
 
 
 def test_edge_cases(torch, orc):
@@ -319,13 +320,15 @@ def test_edge_cases(torch, orc):
         ws = w[:, :s.shape[1]]
         for tg in (far, src):
             got, ref = _tree_case(torch, orc, "stokeslet", s, tg, ws, 0.01, 5, 0.7, 30, 64, 64)
-            assert orc.rel_l2(ref, got) <= FP64_TOL
+            close(orc, ref, got, FP64_TOL)
     # eps = 0 with coincident targets and sources: the self term is dropped
     got, ref = _tree_case(torch, orc, "stokeslet", src, src, w, 0.0, 5, 0.7, 50, 64, 64)
-    assert np.all(np.isfinite(got)) and orc.rel_l2(ref, got) <= FP64_TOL
+    assert np.all(np.isfinite(got))
+    close(orc, ref, got, FP64_TOL)
     got, ref = _tree_case(torch, orc, "rotlet", src, src, w, 0.0, 5, 0.7, 50, 64, 64,
                           precision="fp32_fp64acc")
-    assert np.all(np.isfinite(got)) and orc.rel_l2(ref, got) <= SINGULAR_MIXED_TOL
+    assert np.all(np.isfinite(got))
+    close(orc, ref, got, SINGULAR_MIXED_TOL)
 
 
 def test_one_call_evaluate(torch, orc):
@@ -336,7 +339,7 @@ def test_one_call_evaluate(torch, orc):
                         300, batch_size=128, order_leaf=32).cpu().numpy()
     ref, _, _ = orc.treecode("rotlet", tgt, src, w, 0.03, 5, 0.8, 300, mac_mode=1,
                              batch_size=128, order_leaf=32)
-    assert orc.rel_l2(ref, got) <= FP64_TOL
+    close(orc, ref, got, FP64_TOL)
 
 
 def test_errors_on_device(torch):
@@ -362,7 +365,7 @@ def test_treecode_rule_fp64(torch, orc, kernel, theta, degree, deg_min):
     w = inputs.weights(9000, 51, bltc.WDIM[kernel])
     got, ref = _tree_case(torch, orc, kernel, src, src, w, 0.01, degree, theta, 300, 64, 32,
                           deg_min=deg_min)
-    assert orc.rel_l2(ref, got) <= FP64_TOL
+    close(orc, ref, got, FP64_TOL)
 
 
 @pytest.mark.parametrize("precision", ["fp32_fp64acc", "fp32_kahan"])
@@ -372,7 +375,7 @@ def test_treecode_rule_mixed(torch, orc, kernel, precision):
     w = inputs.weights(9000, 52, bltc.WDIM[kernel])
     got, ref = _tree_case(torch, orc, kernel, src, src, w, 0.005, 9, 0.7, 300, 64, 32,
                           precision=precision, deg_min=1)
-    assert orc.rel_l2(ref, got) <= MIXED_TOL
+    close(orc, ref, got, MIXED_TOL)
 
 
 def test_treecode_rule_poly_exact(torch, orc):
@@ -382,8 +385,8 @@ def test_treecode_rule_poly_exact(torch, orc):
     got, ref = _tree_case(torch, orc, "poly", pts, pts, w, 0.0, 9, 0.8, 100, 64, 32,
                           poly_p=3, poly_c=1.5, deg_min=3)
     d = orc.direct("poly", pts, pts, w, poly_p=3, poly_c=1.5)
-    assert orc.rel_l2(ref, got) <= FP64_TOL
-    assert orc.rel_l2(d, got) <= FP64_TOL
+    close(orc, ref, got, FP64_TOL)
+    close(orc, d, got, FP64_TOL)
 
 
 def test_rule_off_when_deg_min_reaches_degree(torch, orc):
@@ -429,7 +432,8 @@ def test_full_edge_cases(torch, orc):
     src = inputs.points("mixture", 3000, 62)
     w = inputs.weights(3000, 62, 6)
     got, ref = _tree_case(torch, orc, "full", src, src, w, 0.0, 6, 0.7, 60, 64, 64)
-    assert np.all(np.isfinite(got)) and orc.rel_l2(ref, got) <= FP64_TOL
+    assert np.all(np.isfinite(got))
+    close(orc, ref, got, FP64_TOL)
     T = _gpu_tree(torch, src, inputs.weights(3000, 62), 60, 4)
     G = bltc.Targets(_d(torch, src), 64, 64)
     with pytest.raises(bltc.BltcError) as e:
@@ -451,7 +455,7 @@ def test_paper_workloads_fp64(torch, orc, name, n):
     leaf = 300
     got, ref = _tree_case(torch, orc, cfg["kernel"], src, src, w, cfg["eps"], cfg["degree"],
                           cfg["theta"], leaf, 64, 32)
-    assert orc.rel_l2(ref, got) <= FP64_TOL
+    close(orc, ref, got, FP64_TOL)
     got32, _ = _tree_case(torch, orc, cfg["kernel"], src, src, w, cfg["eps"], cfg["degree"],
                           cfg["theta"], leaf, 64, 32, precision="fp32_fp64acc")
     # Example 1's pairs: at a body, its own term f H1(0) (2/eps) and its
@@ -459,7 +463,7 @@ def test_paper_workloads_fp64(torch, orc, name, n):
     # cancel, leaving 0.59/eps: FP32 rounding of the two terms is amplified
     # about (2 + 1.41) / 0.59 = 5.8 times over MIXED_TOL's analysis
     tol32 = 10 * MIXED_TOL if name == "e1" else MIXED_TOL
-    assert orc.rel_l2(ref, got32) <= tol32
+    close(orc, ref, got32, tol32)
 
 
 def test_modified_weights_after_weight_and_width_changes(torch, orc):
