@@ -206,6 +206,27 @@ int bltc_evaluate_tree(bltc_tree t, bltc_targets g, int32_t kernel, double eps,
                        int32_t degree, double theta, const bltc_options* opt,
                        double* out, void* stream);
 
+/* Allocation-free bltc_evaluate_tree, for callers that cannot allocate
+ * device memory (code under stream capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same arguments, checks and result as
+ * bltc_evaluate_tree, bit for bit; the interaction lists, the walk flags and
+ * the separation rule's degree mask live in a fixed device array of the
+ * library (bltc_noalloc_scratch_bytes: 32 MiB, one copy per device the
+ * library runs on, held until the process ends) instead of the targets
+ * handle.  The call allocates nothing: the modified weights of `degree` must
+ * exist (else BLTC_ESTATE) and, with opt->deg_min >= 1, so must every lower
+ * degree the lists use (derived by an earlier bltc_evaluate_tree with the
+ * same options; else BLTC_ESTATE).  Lists larger than the array give
+ * BLTC_EINVAL with the size needed, before anything is written to out.
+ * Every call on a device shares that device's array: calls that overlap on
+ * one device (other threads, other streams) race and must be serialised by
+ * the caller.  Reads the list sizes back once (synchronises on `stream`). */
+int bltc_evaluate_tree_noalloc(bltc_tree t, bltc_targets g, int32_t kernel, double eps,
+                               int32_t degree, double theta, const bltc_options* opt,
+                               double* out, void* stream);
+/* Size in bytes of the fixed array bltc_evaluate_tree_noalloc uses. */
+int bltc_noalloc_scratch_bytes(int64_t* bytes);
+
 /* Cluster-cluster variant (the interpolation in the target variable that
  * Section 9 names as the next step; not in the paper's method).  tgt is a
  * tree built with bltc_build_tree on the TARGET points (its leaf size is the

@@ -98,6 +98,8 @@ def load():
         "bltc_batch_counts": (ctypes.c_int, [P, P, D, P, P, P]),
         "bltc_evaluate_adaptive": (ctypes.c_int, [P, P, I32, D, P, D, I32, I32, D, P, P, P, P, P, P]),
         "bltc_test_fail_alloc": (ctypes.c_int, [I32]),
+        "bltc_evaluate_tree_noalloc": (ctypes.c_int, [P, P, I32, D, I32, D, P, P, P]),
+        "bltc_noalloc_scratch_bytes": (ctypes.c_int, [P]),
         "bltc_profile_enable": (ctypes.c_int, [I32]),
         "bltc_profile_read": (ctypes.c_int, [P, P, I32]),
         "bltc_direct": (ctypes.c_int, [P, P, P, I64, P, I64, P, P, P, I64, P, I32,
@@ -280,6 +282,27 @@ def evaluate_tree(tree, targets, kernel, eps, degree, theta, precision="fp64",
                                      int(degree), float(theta), ctypes.byref(o), ptr,
                                      _stream()))
     return out
+
+
+def evaluate_tree_noalloc(tree, targets, kernel, eps, degree, theta, out, precision="fp64",
+                          poly_p=2, poly_c=1.0, deg_min=0):
+    """bltc_evaluate_tree_noalloc: as evaluate_tree, with the caller's
+    output and the library's fixed scratch array; nothing is allocated."""
+    od = ODIM[kernel]
+    _dev(out, "out", od)
+    o = options(precision, targets.batch_size, targets.order_leaf, poly_p, poly_c,
+                targets.group_max, deg_min)
+    ptr = ctypes.c_void_p(out.data_ptr()) if targets.m else None
+    _check(load().bltc_evaluate_tree_noalloc(tree._h, targets._h, KERNELS[kernel], float(eps),
+                                             int(degree), float(theta), ctypes.byref(o), ptr,
+                                             _stream()))
+    return out
+
+
+def noalloc_scratch_bytes():
+    b = ctypes.c_int64()
+    _check(load().bltc_noalloc_scratch_bytes(ctypes.byref(b)))
+    return b.value
 
 
 def evaluate(tgt, src, w, kernel, eps, degree, theta, leaf_max, precision="fp64",

@@ -20,7 +20,7 @@ LIB = os.path.join(LIBDIR, "libbltc.so")
 BUILD = os.path.join(HERE, "_build")
 
 HOST_UNITS = ["host.cpp", "api_tree.cpp", "api_eval.cpp", "api_select.cpp", "api_dual.cpp",
-              "tree_host.cpp"]
+              "api_noalloc.cpp", "tree_host.cpp"]
 SOURCES = HOST_UNITS + ["k_prep.hip", "k_lists.hip", "k_upward.hip", "k_p2p.hip",
                         "k_direct.hip", "k_mlp.hip", "k_select.hip", "k_tree.hip", "k_dual.hip"]
 EXACT = set(HOST_UNITS) | {"k_prep.hip", "k_lists.hip", "k_tree.hip", "k_select.hip"}

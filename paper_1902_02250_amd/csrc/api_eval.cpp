@@ -70,7 +70,8 @@ void build_lists(bltc_tree t, bltc_targets g, double theta, const double* theta_
     a.rule_deg_min = per_batch->rule_deg_min;
   }
   StageTimer lt(BLTC_STAGE_LISTS, s);
-  int32_t* fl = g->d_flags;
+  int32_t* fl = L.flags ? L.flags : g->d_flags;
+  if (L.flags) a.err = L.flags;
   hipchk(bltc::launch_lists(a, false, s), "list count");
   hipchk(bltc::launch_exclusive_scan(a.pcnt, nb, L.ptr, fl + 1, s), "scan");
   hipchk(bltc::launch_exclusive_scan(a.dcnt, nb, L.ptr + nb + 1, fl + 2, s), "scan");
@@ -81,13 +82,21 @@ void build_lists(bltc_tree t, bltc_targets g, double theta, const double* theta_
   sync(s);
   if (flags[0] || flags[1] || flags[2])
     throw HipError{BLTC_EDEVICE, "interaction lists overflowed"};
-  if (tot[0] > L.pcap) {
+  if (L.fixed) {
+    const int64_t off = ((int64_t)tot[0] + 63) / 64 * 64;
+    if (off + tot[1] > L.pcap)
+      throw HipError{BLTC_EINVAL,
+                     "the interaction lists need " + std::to_string(4 * (off + tot[1])) +
+                         " bytes, more than the " + std::to_string(4 * L.pcap) +
+                         " bytes of fixed scratch left for them"};
+    L.dids = L.pids + off;
+  } else if (tot[0] > L.pcap) {
     dfree(L.pids);
     L.pcap = 0;
     L.pids = dalloc<int32_t>(tot[0]);
     L.pcap = tot[0];
   }
-  if (tot[1] > L.dcap) {
+  if (!L.fixed && tot[1] > L.dcap) {
     dfree(L.dids);
     L.dcap = 0;
     L.dids = dalloc<int32_t>(tot[1]);

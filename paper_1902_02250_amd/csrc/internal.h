@@ -392,6 +392,11 @@ struct ListSet {
   int32_t* pids = nullptr;
   int32_t* dids = nullptr;
   int64_t pcap = 0, dcap = 0;
+  // Storage owned elsewhere and never grown: pids heads a region of pcap
+  // int32 that holds the proxy list and then the leaf list (at pids plus
+  // the proxy total rounded up to 64 entries).
+  bool fixed = false;
+  int32_t* flags = nullptr;    // [4] walk and scan flags, or NULL: the targets' own
 };
 }  // namespace bltc
 
