@@ -104,7 +104,8 @@ def main():
     ap.add_argument("--eps", type=float, default=None,
                     help="override eps (the pairs workload also sets its pair length to eps)")
     ap.add_argument("--batch-size", type=int, default=64)
-    ap.add_argument("--order-leaf", type=int, default=32)
+    ap.add_argument("--order-leaf", type=int, default=0,
+                    help="0: balanced k-d batches; >= 1: batches of an order tree's groups")
     ap.add_argument("--group-max", type=int, default=512)
     ap.add_argument("--err-sample", type=int, default=10000)
     ap.add_argument("--cpu-sample", type=int, default=65536)

@@ -48,7 +48,7 @@
  *   - Handles are not thread safe; different handles may be used from
  *     different threads.
  *   - Sizes: n, m < 2^31; degree 1..12; leaf_max >= 1; batch_size 1..1024;
- *     order_leaf >= 1; group_max >= 1;
+ *     order_leaf >= 0 (0: balanced k-d batches); group_max >= 1;
  *     0 <= theta <= 1; eps >= 0.  n = 0 or m = 0 is a valid no-op.
  */
 #ifndef BLTC_H
@@ -81,7 +81,8 @@ typedef struct {
   int32_t size;        /* sizeof(bltc_options) */
   int32_t precision;   /* BLTC_FP64 (default) or a mixed mode */
   int32_t batch_size;  /* targets sharing one walk, default 64 */
-  int32_t order_leaf;  /* leaf size of the tree that orders the targets, default 32 */
+  int32_t order_leaf;  /* leaf size of the tree that orders the targets; 0
+                          (default): balanced k-d batches (bltc_build_targets) */
   int32_t poly_p;      /* BLTC_POLY exponent, default 2 */
   double poly_c;       /* BLTC_POLY constant, default 1 */
   int64_t group_max;   /* batches never span two target groups, default 512 */
@@ -161,15 +162,26 @@ int bltc_modified_weights_export(bltc_tree t, int32_t degree, double* fhat,
                                  double* grid);
 
 /* ---- targets -------------------------------------------------------------
- * Orders the m targets by a tree built with the same rules and leaf size
- * order_leaf.  The maximal nodes of that tree with at most group_max targets
- * (and any larger degenerate leaf) are the groups; each group is cut into
- * consecutive batches of batch_size targets, so a batch never spans two
- * groups and its radius is bounded by its group's.  Each batch gets its
- * tight box, center and radius like a cluster.  The order tree is built on
- * the device as in bltc_build_tree, the group and batch bounds on the host
- * from its node arrays, the batch boxes on the device (synchronises); the
- * order and batches live on the device. */
+ * Groups the m targets into batches of at most batch_size that share one
+ * walk (the batch MAC).  Two rules:
+ *  - order_leaf = 0, balanced k-d batches: a set of c > batch_size targets is
+ *    cut along the longest side of its tight box (the first of equal sides),
+ *    the first part taking the batch_size floor(nb / 2) targets with the
+ *    smallest coordinates on that axis, nb = ceil(c / batch_size), ties
+ *    ordered by target index; sets of at most batch_size targets are the
+ *    batches, in cut order (first part first), their targets in increasing
+ *    index.  Every batch is full except the last, and the boxes stay
+ *    compact.  group_max is not used.
+ *  - order_leaf >= 1: the targets are ordered by a tree built with the same
+ *    rules as the sources and leaf size order_leaf; the maximal nodes of that
+ *    tree with at most group_max targets (and any larger degenerate leaf) are
+ *    the groups, each cut into consecutive batches of batch_size targets, so
+ *    a batch never spans two groups and its radius is bounded by its group's.
+ * Each batch gets its tight box, center and radius like a cluster.  The k-d
+ * cut runs on the host from a copy of the coordinates; the order tree is
+ * built on the device as in bltc_build_tree, the group and batch bounds on
+ * the host from its node arrays; the batch boxes on the device
+ * (synchronises).  The order and batches live on the device. */
 int bltc_build_targets(const double* x, const double* y, const double* z,
                        int64_t m, int32_t batch_size, int32_t order_leaf,
                        int64_t group_max, void* stream, bltc_targets* out);
@@ -362,6 +374,20 @@ int bltc_selector_destroy(bltc_selector sel);
 int bltc_selector_info(bltc_selector sel, int32_t* k, int32_t* cand_n,
                        double* cand_theta);
 
+/* The judge's samples (the a11 step of bltc_evaluate_adaptive, exposed for
+ * checks): the fixed treecode of Algorithm 2 with degree fb_degree and the
+ * paper's per-target MAC r/R <= fb_theta (eq. MAC), each sample target
+ * walked on its own from the root, FP32 kernel evaluation with FP64 sums.
+ * The samples are one target per two batches, at a hashed position inside
+ * the first batch of each pair (fixed by the targets handle).  Computes the
+ * modified weights of fb_degree when missing.  *n_samples receives their
+ * number; target_idx (host int64 [n_samples], caller's target order) and
+ * ufb (host FP64 [n_samples][odim]) may be NULL (then nothing is
+ * evaluated).  Kernels BLTC_STOKESLET and BLTC_ROTLET.  Synchronises. */
+int bltc_judge_samples(bltc_tree t, bltc_targets g, int32_t kernel, double eps,
+                       int32_t fb_degree, double fb_theta, int64_t* n_samples,
+                       int64_t* target_idx, double* ufb, void* stream);
+
 /* Evaluation with a learned (n, theta) per batch, aiming at a relative L2
  * error tol over all targets (the paper's eq. error).  Not in the paper,
  * which fixes (theta, n) for a run (Section 6).  Kernels BLTC_STOKESLET and
@@ -370,8 +396,9 @@ int bltc_selector_info(bltc_selector sel, int32_t* k, int32_t* cand_n,
  *     candidate j; bltc_batch_costs gives its modelled wave cost with the
  *     model's cost weights, under the model's separation rule (deg_min).
  *  2. The judge: one target in every second batch is evaluated with the
- *     fallback treecode (fb_degree, fb_theta); w_b = targets_b |u_fb|^2
- *     (the sample of b's pair of batches) estimates the batch's share of the
+ *     fallback treecode (fb_degree, fb_theta) as bltc_judge_samples does
+ *     (Algorithm 2 with the per-target MAC); w_b = targets_b |u_fb|^2 (the
+ *     sample of b's pair of batches) estimates the batch's share of the
  *     reference norm.
  *  3. mode BLTC_SELECT_BATCH: the batches share the error budget: the
  *     choice minimises the total cost subject to
@@ -389,7 +416,7 @@ int bltc_selector_info(bltc_selector sel, int32_t* k, int32_t* cand_n,
  *     over the samples (G_i the targets the sample stands for); when it
  *     exceeds tol^2, the samples with the largest terms, just enough of
  *     them to bring the estimate to (0.8 tol)^2, have their batches evaluated
- *     again with the fallback.
+ *     again with the fallback (its batch walk at fb_theta).
  * choice (host int32 [nb], may be NULL): candidate index, or -2 for a batch
  * the judge sent to the fallback.  stats (host int64 [4], may be NULL):
  * batches, distinct degrees, batches re-evaluated, 0.  judge (host double

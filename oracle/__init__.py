@@ -205,7 +205,8 @@ class Tree:
 
 
 def batches(tgt, batch_size, order_leaf, group_max=512):
-    """Target batches: (tperm, bptr, bcenter, bradius)."""
+    """Target batches: (tperm, bptr, bcenter, bradius); order_leaf = 0 gives
+    the balanced k-d batches."""
     tgt = _c(tgt)
     m = tgt.shape[1]
     L = _load()

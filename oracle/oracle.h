@@ -80,9 +80,10 @@ void orc_tree_export(const orc_tree* t, int64_t* perm, double* box,
 
 /* Target batches: targets ordered by a tree of leaf size order_leaf; the
  * maximal nodes of that tree holding at most group_max targets ("groups")
- * are cut into consecutive chunks of batch_size.  Returns the number of
- * batches nb; fills tperm[m], bptr[nb+1], bcenter[nb][3], bradius[nb] (pass
- * NULL arrays first to get nb). */
+ * are cut into consecutive chunks of batch_size.  order_leaf = 0 instead
+ * cuts the targets into balanced k-d batches (tree.c).  Returns the number
+ * of batches nb; fills tperm[m], bptr[nb+1], bcenter[nb][3], bradius[nb]
+ * (pass NULL arrays first to get nb). */
 int64_t orc_batches(const double* tx, const double* ty, const double* tz,
                     int64_t m, int64_t batch_size, int64_t order_leaf,
                     int64_t group_max, int64_t* tperm, int64_t* bptr,

@@ -198,6 +198,73 @@ static void collect_groups(const orc_tree* t, int64_t q, int64_t group_max,
     collect_groups(t, t->child_first[q] + c, group_max, gb, ge, ng);
 }
 
+/* Balanced k-d batches (order_leaf = 0).  A set of c targets with c <=
+ * batch_size is one batch.  A larger set is cut in two along the longest
+ * side of its tight box (the first of equal sides), the first part taking
+ * the batch_size * floor(nb / 2) targets with the smallest coordinates on
+ * that axis, nb = ceil(c / batch_size) (ties ordered by target index), so
+ * every batch is full except at most one.  Parts are emitted first part
+ * first; inside a batch the targets are in increasing index. */
+static int64_t kd_less(const double* key, int64_t i, int64_t j) {
+  return key[i] < key[j] || (key[i] == key[j] && i < j);
+}
+
+/* Reorders idx[0..c) so that its first k entries are the k smallest by
+ * (key, index) (quickselect; the set is unique because the order is total). */
+static void kd_select(int64_t* idx, int64_t c, int64_t k, const double* key) {
+  int64_t lo = 0, hi = c - 1;
+  while (lo < hi) {
+    const int64_t pv = idx[lo + (hi - lo) / 2];
+    int64_t i = lo, j = hi;
+    while (i <= j) {
+      while (kd_less(key, idx[i], pv)) ++i;
+      while (kd_less(key, pv, idx[j])) --j;
+      if (i <= j) {
+        const int64_t tmp = idx[i];
+        idx[i] = idx[j];
+        idx[j] = tmp;
+        ++i;
+        --j;
+      }
+    }
+    if (k - 1 <= j) hi = j;
+    else if (k - 1 >= i) lo = i;
+    else return;
+  }
+}
+
+static int cmp_i64(const void* a, const void* b) {
+  const int64_t u = *(const int64_t*)a, v = *(const int64_t*)b;
+  return (u > v) - (u < v);
+}
+
+static void kd_split(int64_t* idx, int64_t c, int64_t bs, const double* xyz[3],
+                     int64_t base, int64_t* bptr, int64_t* nb) {
+  if (c <= bs) {
+    qsort(idx, (size_t)c, sizeof(int64_t), cmp_i64);
+    if (bptr) bptr[*nb] = base;
+    (*nb)++;
+    return;
+  }
+  double lo[3], hi[3];
+  for (int a = 0; a < 3; ++a) {
+    lo[a] = hi[a] = xyz[a][idx[0]];
+    for (int64_t i = 1; i < c; ++i) {
+      const double v = xyz[a][idx[i]];
+      if (v < lo[a]) lo[a] = v;
+      if (v > hi[a]) hi[a] = v;
+    }
+  }
+  int ax = 0;
+  for (int a = 1; a < 3; ++a)
+    if (hi[a] - lo[a] > hi[ax] - lo[ax]) ax = a;
+  const int64_t nbc = (c + bs - 1) / bs;
+  const int64_t left = bs * (nbc / 2);
+  kd_select(idx, c, left, xyz[ax]);
+  kd_split(idx, left, bs, xyz, base, bptr, nb);
+  kd_split(idx + left, c - left, bs, xyz, base + left, bptr, nb);
+}
+
 int64_t orc_batches(const double* tx, const double* ty, const double* tz,
                     int64_t m, int64_t batch_size, int64_t order_leaf,
                     int64_t group_max, int64_t* tperm, int64_t* bptr,
@@ -205,6 +272,29 @@ int64_t orc_batches(const double* tx, const double* ty, const double* tz,
   if (m == 0) {
     if (bptr) bptr[0] = 0;
     return 0;
+  }
+  if (order_leaf == 0) {
+    const double* xyz[3] = {tx, ty, tz};
+    if (!bptr) return (m + batch_size - 1) / batch_size;
+    for (int64_t i = 0; i < m; ++i) tperm[i] = i;
+    int64_t nb = 0;
+    kd_split(tperm, m, batch_size, xyz, 0, bptr, &nb);
+    bptr[nb] = m;
+    for (int64_t b = 0; b < nb; ++b) {
+      double h[3];
+      for (int a = 0; a < 3; ++a) {
+        double lo = xyz[a][tperm[bptr[b]]], hi = lo;
+        for (int64_t i = bptr[b] + 1; i < bptr[b + 1]; ++i) {
+          const double v = xyz[a][tperm[i]];
+          if (v < lo) lo = v;
+          if (v > hi) hi = v;
+        }
+        bcenter[3 * b + a] = 0.5 * (lo + hi);
+        h[a] = 0.5 * (hi - lo);
+      }
+      bradius[b] = sqrt(h[0] * h[0] + h[1] * h[1] + h[2] * h[2]);
+    }
+    return nb;
   }
   orc_tree* t = orc_tree_new(tx, ty, tz, m, order_leaf);
   const double* xyz[3] = {tx, ty, tz};

@@ -98,6 +98,7 @@ def load():
         "bltc_batch_counts": (ctypes.c_int, [P, P, D, P, P, P]),
         "bltc_evaluate_adaptive": (ctypes.c_int, [P, P, I32, D, P, D, I32, I32, D, P, P, P, P, P, P]),
         "bltc_test_fail_alloc": (ctypes.c_int, [I32]),
+        "bltc_judge_samples": (ctypes.c_int, [P, P, I32, D, I32, D, P, P, P, P]),
         "bltc_evaluate_tree_noalloc": (ctypes.c_int, [P, P, I32, D, I32, D, P, P, P]),
         "bltc_noalloc_scratch_bytes": (ctypes.c_int, [P]),
         "bltc_profile_enable": (ctypes.c_int, [I32]),
@@ -118,7 +119,7 @@ def _check(rc):
         raise BltcError(rc, load().bltc_last_error().decode())
 
 
-def options(precision="fp64", batch_size=64, order_leaf=32, poly_p=2,
+def options(precision="fp64", batch_size=64, order_leaf=0, poly_p=2,
             poly_c=1.0, group_max=512, deg_min=0):
     o = Options()
     load().bltc_options_default(ctypes.byref(o))
@@ -232,7 +233,9 @@ class Tree:
 class Targets:
     """Target order and batches (bltc_build_targets)."""
 
-    def __init__(self, tgt, batch_size=64, order_leaf=32, group_max=512):
+    def __init__(self, tgt, batch_size=64, order_leaf=0, group_max=512):
+        """order_leaf 0: balanced k-d batches; >= 1: batches of an order
+        tree's groups of at most group_max targets."""
         L = load()
         x, y, z, m = _rows(tgt, "tgt")
         self.m = m
@@ -306,7 +309,7 @@ def noalloc_scratch_bytes():
 
 
 def evaluate(tgt, src, w, kernel, eps, degree, theta, leaf_max, precision="fp64",
-             batch_size=64, order_leaf=32, group_max=512, poly_p=2, poly_c=1.0,
+             batch_size=64, order_leaf=0, group_max=512, poly_p=2, poly_c=1.0,
              out=None, deg_min=0):
     """One call: tree, batches, modified weights and evaluation."""
     torch = _torch()
@@ -337,7 +340,7 @@ def evaluate_dual(src_tree, tgt_tree, kernel, eps, degree, theta, precision="fp3
     if out is None:
         out = torch.empty((od, m), dtype=torch.float64, device="cuda")
     _dev(out, "out", od)
-    o = options(precision, 64, 32, poly_p, poly_c, deg_min=deg_min)
+    o = options(precision, 64, 0, poly_p, poly_c, deg_min=deg_min)
     cnt = np.zeros(5, np.int64)
     _check(load().bltc_evaluate_dual(src_tree._h, tgt_tree._h, KERNELS[kernel], float(eps),
                                      int(degree), float(theta), ctypes.byref(o),
@@ -591,6 +594,20 @@ def evaluate_adaptive(tree, targets, kernel, eps, selector, tol, fb_degree, fb_t
                                          ctypes.c_void_p(out.data_ptr()) if targets.m else None,
                                          _hp(choice), _hp(stats), _hp(judge), _stream()))
     return out, choice[:targets.nb], stats, judge
+
+
+def judge_samples(tree, targets, kernel, eps, fb_degree, fb_theta):
+    """bltc_judge_samples: (caller-order target indices, fallback values
+    (odim, n_samples)) of the judge's samples."""
+    L = load()
+    ns = ctypes.c_int64()
+    _check(L.bltc_judge_samples(tree._h, targets._h, KERNELS[kernel], float(eps), int(fb_degree),
+                                float(fb_theta), ctypes.byref(ns), None, None, _stream()))
+    idx = np.zeros(ns.value, np.int64)
+    u = np.zeros((ns.value, ODIM[kernel]))
+    _check(L.bltc_judge_samples(tree._h, targets._h, KERNELS[kernel], float(eps), int(fb_degree),
+                                float(fb_theta), ctypes.byref(ns), _hp(idx), _hp(u), _stream()))
+    return idx, np.ascontiguousarray(u.T)
 
 
 def inject_alloc_failure(after):

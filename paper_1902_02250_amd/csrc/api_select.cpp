@@ -107,40 +107,71 @@ void candidate_costs(bltc_tree t, bltc_targets g, int k, const int32_t* cand_n,
   }
 }
 
+// The judge's sample targets: one per kJudgeStride batches, at a hashed
+// position inside the first batch of its group; their fallback values go
+// to g->d_ufb.
+void ensure_judge_samples(bltc_targets g) {
+  if (g->nsamp > 0) return;
+  const int64_t nb = g->nb;
+  const int64_t ns = (nb + bltc::kJudgeStride - 1) / bltc::kJudgeStride;
+  ensure_alloc(g->d_ufb, 6 * ns);
+  ensure_alloc(g->d_spos, ns);
+  std::vector<int32_t> sp(ns);
+  for (int64_t i = 0; i < ns; ++i) {
+    const int64_t b = i * bltc::kJudgeStride;
+    const int32_t b0 = g->host.bptr[b], cnt = g->host.bptr[b + 1] - b0;
+    const uint32_t h = (uint32_t)(b * 2654435761ull >> 7);
+    sp[i] = b0 + (int32_t)(h % (uint32_t)cnt);
+  }
+  h2d(g->d_spos, sp.data(), ns, nullptr);
+  sync(nullptr);
+  g->nsamp = (int32_t)ns;   // last: a failed allocation leaves it 0
+}
+
+// The fallback treecode (fb_degree, fb_theta) at the judge's samples, into
+// g->d_ufb [nsamp][odim].
+void fallback_samples(bltc_tree t, bltc_targets g, int kernel, double eps, int fb_degree,
+                      double fb_theta, hipStream_t s) {
+  ensure_judge_samples(g);
+  ensure_degree(t, fb_degree, s);
+  const bltc_degree_data& fd = t->deg.at(fb_degree);
+  bltc::SampleArgs a;
+  a.spos = g->d_spos;
+  a.ns = g->nsamp;
+  a.tx = g->d_x;
+  a.m = g->m;
+  a.nodes.geo = t->d_geo;
+  a.nodes.range = t->d_range;
+  a.nodes.kids = t->d_kids;
+  a.nodes.skip = t->d_skip;
+  a.nodes.nn = t->host.nnodes();
+  a.theta = fb_theta;
+  a.grid = fd.grid;
+  a.fh32 = fd.p2p32;
+  a.ys = t->d_y;
+  a.w32 = t->d_w32;
+  a.n = t->n;
+  a.eps = eps;
+  kernel_scales(kernel, &a.scale_u, &a.scale_w);
+  a.ufb = g->d_ufb;
+  hipchk(bltc::launch_fallback_samples(kernel, fb_degree, a, s), "judge samples");
+}
+
 void ensure_selection_scratch(bltc_targets g, int64_t k) {
   const int64_t nb = g->nb;
-  if (g->nsamp == 0) {   // set last: a failed allocation leaves it 0, and a
-                         // later call allocates what is still missing
+  if (!g->d_lam) {   // allocated last: a failed call leaves it NULL
     ensure_alloc(g->d_feat, nb * bltc::kMlpIn);
     ensure_alloc(g->d_choice, nb);
     ensure_alloc(g->d_bmap, nb);
     ensure_alloc(g->d_theta_b, nb);
-    ensure_alloc(g->d_gflag, nb);
-    ensure_alloc(g->d_ufb, 6 * nb);
     ensure_alloc(g->d_wt, nb);
     ensure_alloc(g->d_contrib, nb);
+    ensure_alloc(g->d_usq, nb);
     ensure_alloc(g->d_part, bltc::alloc_blocks(nb) * kLamGrid * 2);
     ensure_alloc(g->d_sums, 2 * std::max(kLamGrid, bltc::kMlpMaxOut));
     ensure_alloc(g->d_lam, kLamGrid);
-    // one judge sample per kJudgeStride batches, at a hashed position inside
-    // the first batch of its group
-    const int64_t ns = (nb + bltc::kJudgeStride - 1) / bltc::kJudgeStride;
-    ensure_alloc(g->d_usq, ns);
-    std::vector<int32_t> sp(ns), sb(ns);
-    for (int64_t i = 0; i < ns; ++i) {
-      const int64_t b = i * bltc::kJudgeStride;
-      const int32_t b0 = g->host.bptr[b], cnt = g->host.bptr[b + 1] - b0;
-      const uint32_t h = (uint32_t)(b * 2654435761ull >> 7);
-      sp[i] = b0 + (int32_t)(h % (uint32_t)cnt);
-      sb[i] = (int32_t)b;
-    }
-    ensure_alloc(g->d_spos, ns);
-    ensure_alloc(g->d_sbatch, ns);
-    h2d(g->d_spos, sp.data(), ns, nullptr);
-    h2d(g->d_sbatch, sb.data(), ns, nullptr);
-    sync(nullptr);
-    g->nsamp = (int32_t)ns;
   }
+  ensure_judge_samples(g);
   if (nb * k > g->ycap) {
     dfree(g->d_Y);
     g->ycap = 0;
@@ -189,6 +220,18 @@ void evaluate_adaptive(bltc_tree t, bltc_targets g, int kernel, double eps,
                           (float)sel->cost_near};
   ensure_selection_scratch(g, k);
 
+  // 2. (first, on a library stream, concurrent with step 1: the two are
+  //    independent) the judge: the fallback treecode (Algorithm 2 with the
+  //    per-target MAC) at one sample per pair of batches
+  Events evs;
+  hipEvent_t start = evs.make();
+  hipchk(hipEventRecord(start, s), "hipEventRecord");
+  hipStream_t jstream = side_stream(0);
+  hipchk(hipStreamWaitEvent(jstream, start, 0), "hipStreamWaitEvent");
+  fallback_samples(t, g, kernel, eps, fb_degree, fb_theta, jstream);
+  hipEvent_t judged = evs.make();
+  hipchk(hipEventRecord(judged, jstream), "hipEventRecord");
+
   // 1. predicted log10 errors of every candidate, and their modelled costs
   compute_features(t, g, kernel, eps, sel->theta_ref, sel->d_mean, sel->d_std, g->d_feat, s);
   hipchk(bltc::launch_mlp_forward(sel->d_params, g->d_feat, nb, k, g->d_Y, nullptr, s),
@@ -196,32 +239,8 @@ void evaluate_adaptive(bltc_tree t, bltc_targets g, int kernel, double eps,
   candidate_costs(t, g, k, sel->cand_n.data(), sel->cand_theta.data(), rule_min, costs,
                   g->d_cost, s);
   hipchk(bltc::launch_pred_err2(g->d_Y, k, nb, g->d_e2, s), "predicted errors");
+  hipchk(hipStreamWaitEvent(s, judged, 0), "hipStreamWaitEvent");
 
-  // 2. the judge: the fallback treecode at one sample per batch
-  ensure_degree(t, fb_degree, s);
-  int64_t np = 0, nd = 0;
-  build_lists(t, g, fb_theta, nullptr, g->ls[1], s, &np, &nd);
-  const bltc_degree_data& fd = t->deg.at(fb_degree);
-  bltc::GuardArgs ga;
-  ga.spos = g->d_spos;
-  ga.sbatch = g->d_sbatch;
-  ga.ns = g->nsamp;
-  ga.tx = g->d_x;
-  ga.m = g->m;
-  ga.pptr = g->ls[1].ptr;
-  ga.pids = g->ls[1].pids;
-  ga.dptr = g->ls[1].ptr + nb + 1;
-  ga.dids = g->ls[1].dids;
-  ga.range = t->d_range;
-  ga.grid = fd.grid;
-  ga.fh32 = fd.p2p32;
-  ga.ys = t->d_y;
-  ga.w32 = t->d_w32;
-  ga.n = t->n;
-  ga.eps = eps;
-  kernel_scales(kernel, &ga.scale_u, &ga.scale_w);
-  ga.ufb = g->d_ufb;
-  hipchk(bltc::launch_guard(kernel, fb_degree, ga, s), "judge samples");
   double ws[2];
   judge_sums(g, kernel, nullptr, ws, s);
   hipchk(bltc::launch_batch_weights(nb, bltc::kJudgeStride, g->d_bptr, g->d_usq, g->d_wt, s),
@@ -306,6 +325,7 @@ void evaluate_adaptive(bltc_tree t, bltc_targets g, int kernel, double eps,
     extra.cand_T = g->d_candT;
     extra.cand_deg = g->d_candn;
     extra.rule_deg_min = rule_min;
+    int64_t np = 0, nd = 0;
     build_lists(t, g, 0.0, g->d_theta_b, g->ls[0], s, &np, &nd, nullptr, &extra);
   }
   std::vector<int32_t> order;
@@ -327,7 +347,6 @@ void evaluate_adaptive(bltc_tree t, bltc_targets g, int kernel, double eps,
   og.deg_min = rule_min;
   // the degree groups write disjoint targets: with more than one, they run
   // concurrently on side streams, largest first
-  Events evs;
   if (spans.size() == 1) {
     run_p2p(t, g, g->ls[0], kernel, eps, spans[0].first, og, g->d_bmap, nb, out, s);
   } else {
@@ -385,6 +404,8 @@ void evaluate_adaptive(bltc_tree t, bltc_targets g, int kernel, double eps,
     std::sort(redo.begin(), redo.end());
     st[2] = (int64_t)redo.size();
     if (!redo.empty()) {
+      int64_t np = 0, nd = 0;   // the fallback's batch lists
+      build_lists(t, g, fb_theta, nullptr, g->ls[1], s, &np, &nd);
       h2d(g->d_bmap, redo.data(), redo.size(), s);
       if (g->batch_size <= bltc::kWave) {
         // few batches: each batch's proxy list is cut into slices that run
@@ -646,6 +667,35 @@ int bltc_evaluate_adaptive(bltc_tree t, bltc_targets g, int32_t kernel, double e
   return guarded([&] {
     evaluate_adaptive(t, g, kernel, eps, sel, tol, mode, fb_degree, fb_theta, o, out, choice,
                       stats, judge, (hipStream_t)stream);
+    return (int)BLTC_OK;
+  });
+}
+
+int bltc_judge_samples(bltc_tree t, bltc_targets g, int32_t kernel, double eps,
+                       int32_t fb_degree, double fb_theta, int64_t* n_samples,
+                       int64_t* target_idx, double* ufb, void* stream) {
+  if (!t || !g || !n_samples) return fail(BLTC_EINVAL, "NULL tree, targets or n_samples");
+  if (kernel != BLTC_STOKESLET && kernel != BLTC_ROTLET)
+    return fail(BLTC_EINVAL, "the judge serves the Stokeslet and rotlet kernels");
+  if (int rc = check_eval(kernel, eps, fb_degree, fb_theta)) return rc;
+  if (!t->has_w) return fail(BLTC_ESTATE, "no weights: call bltc_compute_modified_weights first");
+  if (t->wdim != wdim_of(kernel))
+    return fail(BLTC_ESTATE, "the tree's weights have the wrong number of components for this kernel");
+  *n_samples = g->m > 0 ? (g->nb + bltc::kJudgeStride - 1) / bltc::kJudgeStride : 0;
+  if (!target_idx && !ufb) return BLTC_OK;
+  if (g->m == 0) return BLTC_OK;
+  return guarded([&] {
+    hipStream_t s = (hipStream_t)stream;
+    fallback_samples(t, g, kernel, eps, fb_degree, fb_theta, s);
+    const int64_t ns = g->nsamp;
+    std::vector<int32_t> sp(ns);
+    std::vector<double> u((size_t)ns * odim_of(kernel));
+    d2h(sp.data(), g->d_spos, ns, s);
+    d2h(u.data(), g->d_ufb, u.size(), s);
+    sync(s);
+    for (int64_t i = 0; i < ns; ++i)
+      if (target_idx) target_idx[i] = g->host.perm[sp[i]];
+    if (ufb) std::memcpy(ufb, u.data(), sizeof(double) * u.size());
     return (int)BLTC_OK;
   });
 }

@@ -401,7 +401,7 @@ void destroy_targets(bltc_targets g) {
   }
   dfree(g->d_feat); dfree(g->d_Y); dfree(g->d_pc); dfree(g->d_sc);
   dfree(g->d_choice); dfree(g->d_bmap); dfree(g->d_theta_b); dfree(g->d_spos);
-  dfree(g->d_sbatch); dfree(g->d_gflag); dfree(g->d_ufb);
+  dfree(g->d_ufb);
   dfree(g->d_wt); dfree(g->d_usq); dfree(g->d_contrib); dfree(g->d_part); dfree(g->d_sums); dfree(g->d_lam);
   dfree(g->d_cost); dfree(g->d_e2); dfree(g->d_candT); dfree(g->d_candn);
   delete g->split;
@@ -412,15 +412,31 @@ void destroy_targets(bltc_targets g) {
 void build_targets(const double* x, const double* y, const double* z,
                    int64_t m, int32_t bs, int32_t leaf, int64_t gmax,
                    hipStream_t s, bltc_targets g) {
-  // the order tree on the device; groups and batch bounds on the host;
-  // batch geometry on the device
-  bltc::HostTree order;
-  build_device_tree(x, y, z, m, leaf, s, order, &g->d_x, &g->d_tperm);
   bltc::HostBatches& B = g->host;
   B = bltc::HostBatches();
-  B.perm.swap(order.perm);
   std::vector<int32_t> bend;
-  bltc::batch_bounds(order, bs, gmax, B.bptr, bend);
+  if (leaf == 0) {
+    // balanced k-d batches: the cut on the host from a copy of the
+    // coordinates; the tree-ordered copy gathered on the device
+    std::vector<double> h(3 * (size_t)m);
+    d2h(h.data(), x, m, s);
+    d2h(h.data() + m, y, m, s);
+    d2h(h.data() + 2 * m, z, m, s);
+    sync(s);
+    bltc::kd_batches(h.data(), h.data() + m, h.data() + 2 * m, m, bs, B.perm, B.bptr);
+    bend.assign(B.bptr.begin() + 1, B.bptr.end());
+    g->d_tperm = dalloc<int32_t>(m);
+    g->d_x = dalloc<double>(3 * m);
+    h2d(g->d_tperm, B.perm.data(), m, s);
+    hipchk(bltc::launch_gather_points(x, y, z, g->d_tperm, m, g->d_x, s), "gather targets");
+  } else {
+    // the order tree on the device; groups and batch bounds on the host;
+    // batch geometry on the device
+    bltc::HostTree order;
+    build_device_tree(x, y, z, m, leaf, s, order, &g->d_x, &g->d_tperm);
+    B.perm.swap(order.perm);
+    bltc::batch_bounds(order, bs, gmax, B.bptr, bend);
+  }
   g->m = m;
   g->nb = (int64_t)B.bptr.size() - 1;
   g->batch_size = bs;
@@ -561,7 +577,7 @@ int bltc_build_targets(const double* x, const double* y, const double* z,
   if (int rc = check_points(x, y, z, m, "targets")) return rc;
   if (batch_size < 1 || batch_size > 1024)
     return fail(BLTC_EINVAL, "batch_size must be in [1, 1024]");
-  if (order_leaf < 1) return fail(BLTC_EINVAL, "order_leaf must be >= 1");
+  if (order_leaf < 0) return fail(BLTC_EINVAL, "order_leaf must be >= 0 (0: balanced k-d batches)");
   if (group_max < 1) return fail(BLTC_EINVAL, "group_max must be >= 1");
   return guarded([&] {
     bltc_targets g = new bltc_targets_s;
@@ -623,7 +639,7 @@ int bltc_host_batches(const double* hx, const double* hy, const double* hz,
   if (m > 0 && (!hx || !hy || !hz)) return fail(BLTC_EINVAL, "NULL coordinate array");
   if (batch_size < 1 || batch_size > 1024)
     return fail(BLTC_EINVAL, "batch_size must be in [1, 1024]");
-  if (order_leaf < 1) return fail(BLTC_EINVAL, "order_leaf must be >= 1");
+  if (order_leaf < 0) return fail(BLTC_EINVAL, "order_leaf must be >= 0 (0: balanced k-d batches)");
   if (group_max < 1) return fail(BLTC_EINVAL, "group_max must be >= 1");
   return guarded([&] {
     bltc_targets_s g;

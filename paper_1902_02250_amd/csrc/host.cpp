@@ -118,7 +118,7 @@ int check_options(const bltc_options* o, int kernel) {
     return fail(BLTC_EINVAL, "the polynomial test kernel runs in FP64 only");
   if (o->batch_size < 1 || o->batch_size > 1024)
     return fail(BLTC_EINVAL, "batch_size must be in [1, 1024]");
-  if (o->order_leaf < 1) return fail(BLTC_EINVAL, "order_leaf must be >= 1");
+  if (o->order_leaf < 0) return fail(BLTC_EINVAL, "order_leaf must be >= 0 (0: balanced k-d batches)");
   if (o->group_max < 1) return fail(BLTC_EINVAL, "group_max must be >= 1");
   if (o->poly_p < 0 || o->poly_p > 64) return fail(BLTC_EINVAL, "poly_p must be in [0, 64]");
   if (o->deg_min < 0 || o->deg_min > bltc::kMaxDegree)
@@ -169,7 +169,7 @@ void bltc_options_default(bltc_options* o) {
   o->size = (int32_t)sizeof(bltc_options);
   o->precision = BLTC_FP64;
   o->batch_size = 64;
-  o->order_leaf = 32;
+  o->order_leaf = 0;   // balanced k-d batches
   o->group_max = 512;
   o->poly_p = 2;
   o->poly_c = 1.0;

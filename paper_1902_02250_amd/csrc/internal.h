@@ -54,6 +54,15 @@ void build_host_batches(const double* x, const double* y, const double* z,
 // nodes in tree order, each cut into consecutive pieces of batch_size.
 void batch_bounds(const HostTree& order, int32_t batch_size, int64_t group_max,
                   std::vector<int32_t>& bptr, std::vector<int32_t>& bend);
+// Balanced k-d batches (order_leaf = 0): a part of c > batch_size targets is
+// cut along the longest side of its tight box (the first of equal sides),
+// the first part taking the batch_size floor(nb / 2) targets with the
+// smallest coordinates on that axis (ties by index), nb = ceil(c /
+// batch_size); parts of at most batch_size targets are batches, in cut
+// order, their targets in increasing index.  Every batch is full except at
+// most one.  perm[m] (position -> index), bptr[nb + 1].
+void kd_batches(const double* x, const double* y, const double* z, int64_t m, int32_t bs,
+                std::vector<int32_t>& perm, std::vector<int32_t>& bptr);
 
 
 // Unit Chebyshev points of the 2nd kind, descending.
@@ -161,20 +170,18 @@ struct DualDownArgs {
   double* out;                 // [odim][m] caller order, added to
 };
 
-struct GuardArgs {
+// The judge's samples: the fixed treecode of Algorithm 2 at single targets
+// (one wave each), walked with the per-target MAC.
+struct SampleArgs {
   const int32_t* spos;         // [ns] sampled target positions (tree order)
-  const int32_t* sbatch;       // [ns] their batches
   int ns;
-  const double* tx;
+  const double* tx;            // tree-ordered targets [3][m]
   int64_t m;
-  const int32_t* pptr;
-  const int32_t* pids;
-  const int32_t* dptr;
-  const int32_t* dids;
-  const int2* range;
-  const double* grid;
-  const float* fh32;
-  const double* ys;
+  Nodes nodes;
+  double theta;
+  const double* grid;          // [nn][3][n1] of the fallback degree
+  const float* fh32;           // its modified weights, evaluation layout
+  const double* ys;            // tree-ordered sources [3][n]
   const float* w32;
   int64_t n;
   double eps, scale_u, scale_w;
@@ -235,7 +242,8 @@ struct CostArgs {
 };
 
 // ---- launchers (defined in the .hip files) --------------------------------
-hipError_t launch_guard(int kernel, int degree, const GuardArgs& a, hipStream_t s);
+hipError_t launch_fallback_samples(int kernel, int degree, const SampleArgs& a,
+                                   hipStream_t s);
 hipError_t launch_features(const FeatArgs& a, hipStream_t s);
 int64_t alloc_blocks(int64_t nb);
 hipError_t launch_pred_err2(const float* Y, int k, int64_t nb, double* e2, hipStream_t s);
@@ -413,7 +421,7 @@ struct bltc_targets_s {
   int32_t* d_bptr = nullptr;
   double4* d_bgeo = nullptr;
   int32_t* d_flags = nullptr;  // [4]: walk error, scan overflow x2, spare
-  bltc::ListSet ls[2];         // [0] evaluation lists, [1] guard lists
+  bltc::ListSet ls[2];         // [0] evaluation lists, [1] the fallback's lists (repairs)
   // per-batch selection scratch (allocated on first adaptive call)
   float* d_feat = nullptr;     // [nb][12]
   float* d_Y = nullptr;        // [nb][k]
@@ -424,9 +432,7 @@ struct bltc_targets_s {
   int32_t* d_choice = nullptr; // [nb]
   int32_t* d_bmap = nullptr;   // [nb]
   double* d_theta_b = nullptr; // [nb]
-  int32_t* d_spos = nullptr;   // guard samples, one per batch
-  int32_t* d_sbatch = nullptr;
-  int32_t* d_gflag = nullptr;  // [nb]
+  int32_t* d_spos = nullptr;   // judge samples, one per kJudgeStride batches (tree order)
   double* d_ufb = nullptr;     // [nb][6]
   int32_t nsamp = 0;           // judge samples (one per kJudgeStride batches)
   double* d_usq = nullptr;     // [nsamp] |u_fb|^2 at the samples

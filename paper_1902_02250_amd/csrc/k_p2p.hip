@@ -603,112 +603,6 @@ hipError_t run_p2p(const P2PArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-// Guard evaluation: one wave per sampled target; the lanes share the
-// target's list (far field by (k2, k3) columns, near field by sources) and
-// the FP64 lane totals are added by a butterfly, so the sum is deterministic.
-// In the far field each lane walks k1 down its column: for a fixed k1 the
-// lanes read consecutive k3 of the weight layout, and dx (uniform over the
-// wave) comes from a per-cluster table.  FP32 evaluation with the
-// differences formed in FP64.
-template <int KERN, int N1, bool ZEPS>
-__global__ __launch_bounds__(64) void k_guard(
-    const int32_t* __restrict__ spos, const int32_t* __restrict__ sbatch, int ns,
-    const double* __restrict__ tx, int64_t m, const int32_t* __restrict__ pptr,
-    const int32_t* __restrict__ pids, const int32_t* __restrict__ dptr,
-    const int32_t* __restrict__ dids, const int2* __restrict__ range,
-    const double* __restrict__ grid, const float* __restrict__ fh32,
-    const double* __restrict__ ys, const float* __restrict__ w32, int64_t n,
-    double eps, double su, double sw, double* __restrict__ ufb) {
-  constexpr int OD = Dims<KERN>::OD;
-  constexpr int NK = N1 * N1 * N1;
-  const int si = blockIdx.x;
-  if (si >= ns) return;
-  const int lane = threadIdx.x;
-  const int pos = spos[si], b = sbatch[si];
-  const double x = tx[pos], y = tx[m + pos], z = tx[2 * m + pos];
-  const float e2 = (float)(eps * eps);
-  double acc[OD];
-#pragma unroll
-  for (int c = 0; c < OD; ++c) acc[c] = 0.0;
-  for (int li = pptr[b]; li < pptr[b + 1]; ++li) {
-    const int q = pids[li];
-    const double* __restrict__ g = grid + (int64_t)q * 3 * N1;
-    const float* __restrict__ F = fh32 + (int64_t)q * 3 * NK;
-    float p[OD];
-#pragma unroll
-    for (int c = 0; c < OD; ++c) p[c] = 0.f;
-    float dxs[N1];
-#pragma unroll
-    for (int k1 = 0; k1 < N1; ++k1) dxs[k1] = (float)(x - g[k1]);
-    for (int r = lane; r < N1 * N1; r += 64) {
-      const int k2 = r / N1, k3 = r % N1;
-      const float dy = (float)(y - g[N1 + k2]);
-      const float dz = (float)(z - g[2 * N1 + k3]);
-      const float a = dz * dz + (dy * dy + e2);
-      const float* __restrict__ col = F + k2 * 3 * N1 + k3;
-#pragma unroll
-      for (int k1 = 0; k1 < N1; ++k1) {
-        const float dx = dxs[k1];
-        const float* __restrict__ f = col + k1 * N1 * 3 * N1;
-        pair<KERN, ZEPS, float>(dx, dy, dz, dx * dx + a, e2, f[0], f[N1], f[2 * N1], p);
-      }
-    }
-#pragma unroll
-    for (int c = 0; c < OD; ++c) acc[c] += (double)p[c];
-  }
-  for (int li = dptr[b]; li < dptr[b + 1]; ++li) {
-    const int2 rg = range[dids[li]];
-    float p[OD];
-#pragma unroll
-    for (int c = 0; c < OD; ++c) p[c] = 0.f;
-    for (int j = rg.x + lane; j < rg.y; j += 64) {
-      const float dx = (float)(x - ys[j]);
-      const float dy = (float)(y - ys[n + j]);
-      const float dz = (float)(z - ys[2 * n + j]);
-      const float r2 = dz * dz + (dy * dy + (dx * dx + e2));
-      pair<KERN, ZEPS, float>(dx, dy, dz, r2, e2, w32[j], w32[n + j], w32[2 * n + j], p);
-    }
-#pragma unroll
-    for (int c = 0; c < OD; ++c) acc[c] += (double)p[c];
-  }
-#pragma unroll
-  for (int c = 0; c < OD; ++c)
-    for (int off = 32; off > 0; off >>= 1) acc[c] += __shfl_xor(acc[c], off);
-  if (lane == 0) {
-#pragma unroll
-    for (int c = 0; c < OD; ++c) ufb[(int64_t)si * OD + c] = acc[c] * (c < 3 ? su : sw);
-  }
-}
-
-template <int KERN, int N1>
-hipError_t run_guard(const GuardArgs& a, hipStream_t s) {
-  if (a.ns == 0) return hipSuccess;
-  auto go = [&](auto kern) {
-    hipLaunchKernelGGL(kern, dim3(a.ns), dim3(64), 0, s, a.spos, a.sbatch, a.ns, a.tx,
-                       a.m, a.pptr, a.pids, a.dptr, a.dids, a.range, a.grid, a.fh32,
-                       a.ys, a.w32, a.n, a.eps, a.scale_u, a.scale_w, a.ufb);
-  };
-  if (a.eps == 0.0)
-    go(k_guard<KERN, N1, true>);
-  else
-    go(k_guard<KERN, N1, false>);
-  return hipGetLastError();
-}
-
-template <int KERN>
-hipError_t dispatch_guard(int degree, const GuardArgs& a, hipStream_t s) {
-  switch (degree + 1) {
-#define BLTC_G(N) \
-  case N:         \
-    return run_guard<KERN, N>(a, s);
-    BLTC_G(2) BLTC_G(3) BLTC_G(4) BLTC_G(5) BLTC_G(6) BLTC_G(7)
-    BLTC_G(8) BLTC_G(9) BLTC_G(10) BLTC_G(11) BLTC_G(12) BLTC_G(13)
-#undef BLTC_G
-    default:
-      return hipErrorInvalidValue;
-  }
-}
-
 template <int KERN, int PREC>
 hipError_t dispatch_degree(int degree, const P2PArgs& a, hipStream_t s) {
   switch (degree + 1) {
@@ -733,12 +627,6 @@ hipError_t launch_split_reduce(const int32_t* sptr, const int32_t* bmap, int64_t
   hipLaunchKernelGGL(k_split_reduce, dim3((unsigned)((nr * 64 + 255) / 256)), dim3(256), 0, s,
                      sptr, bmap, nr, bptr, tperm, partial, odim, su, sw, m, out);
   return hipGetLastError();
-}
-
-hipError_t launch_guard(int kernel, int degree, const GuardArgs& a, hipStream_t s) {
-  if (kernel == KSTOKES) return dispatch_guard<KSTOKES>(degree, a, s);
-  if (kernel == KROT) return dispatch_guard<KROT>(degree, a, s);
-  return hipErrorInvalidValue;
 }
 
 hipError_t launch_p2p(int kernel, int precision, int degree, const P2PArgs& a,

@@ -275,17 +275,79 @@ void batch_bounds(const HostTree& order, int32_t batch_size, int64_t group_max,
   bptr.push_back((int32_t)order.n);
 }
 
+namespace {
+
+// One part of the balanced k-d cut: idx[0, c) holds the part's targets and
+// `base` its first position in the final order.
+void kd_part(int32_t* idx, int64_t c, int32_t bs, const double* const xyz[3], int64_t base,
+             int depth, std::vector<int64_t>& starts) {
+  if (c <= bs) {
+    std::sort(idx, idx + c);
+    starts.push_back(base);
+    return;
+  }
+  double lo[3], hi[3];
+  for (int a = 0; a < 3; ++a) {
+    lo[a] = hi[a] = xyz[a][idx[0]];
+    for (int64_t i = 1; i < c; ++i) {
+      const double v = xyz[a][idx[i]];
+      if (v < lo[a]) lo[a] = v;
+      if (v > hi[a]) hi[a] = v;
+    }
+  }
+  int ax = 0;
+  for (int a = 1; a < 3; ++a)
+    if (hi[a] - lo[a] > hi[ax] - lo[ax]) ax = a;
+  const double* key = xyz[ax];
+  const int64_t nb = (c + bs - 1) / bs;
+  const int64_t left = (int64_t)bs * (nb / 2);
+  // the `left` smallest by (coordinate, index): a strict total order, so
+  // the set is unique whatever the selection algorithm
+  std::nth_element(idx, idx + left, idx + c, [key](int32_t i, int32_t j) {
+    return key[i] < key[j] || (key[i] == key[j] && i < j);
+  });
+  if (depth < 4 && c > (1 << 17)) {   // large parts: the two halves in parallel
+    std::vector<int64_t> other;
+    std::thread th([&] { kd_part(idx, left, bs, xyz, base, depth + 1, other); });
+    kd_part(idx + left, c - left, bs, xyz, base + left, depth + 1, starts);
+    th.join();
+    starts.insert(starts.end(), other.begin(), other.end());
+  } else {
+    kd_part(idx, left, bs, xyz, base, depth + 1, starts);
+    kd_part(idx + left, c - left, bs, xyz, base + left, depth + 1, starts);
+  }
+}
+
+}  // namespace
+
+void kd_batches(const double* x, const double* y, const double* z, int64_t m, int32_t bs,
+                std::vector<int32_t>& perm, std::vector<int32_t>& bptr) {
+  perm.resize(m);
+  std::iota(perm.begin(), perm.end(), 0);
+  std::vector<int64_t> starts;
+  const double* const xyz[3] = {x, y, z};
+  if (m > 0) kd_part(perm.data(), m, bs, xyz, 0, 0, starts);
+  std::sort(starts.begin(), starts.end());   // parts in cut order, first part first
+  bptr.assign(starts.begin(), starts.end());
+  bptr.push_back((int32_t)m);
+}
+
 void build_host_batches(const double* x, const double* y, const double* z,
                         int64_t m, int32_t batch_size, int32_t order_leaf,
                         int64_t group_max, HostBatches& out) {
   out = HostBatches();
   out.bptr.push_back(0);
   if (m == 0) return;
-  HostTree order;
-  build_host_tree(x, y, z, m, order_leaf, order);
-  out.perm.swap(order.perm);
   std::vector<int32_t> bend;
-  batch_bounds(order, batch_size, group_max, out.bptr, bend);
+  if (order_leaf == 0) {
+    kd_batches(x, y, z, m, batch_size, out.perm, out.bptr);
+    bend.assign(out.bptr.begin() + 1, out.bptr.end());
+  } else {
+    HostTree order;
+    build_host_tree(x, y, z, m, order_leaf, order);
+    out.perm.swap(order.perm);
+    batch_bounds(order, batch_size, group_max, out.bptr, bend);
+  }
   const int64_t nb = (int64_t)bend.size();
   const double* src[3] = {x, y, z};
   out.geo.resize(4 * nb);

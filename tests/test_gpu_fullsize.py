@@ -1,5 +1,5 @@
 """Parity at the full sizes of the workloads, in the launch configuration
-the benchmark times (batches of 64 targets, order leaf 32, groups of 512):
+the benchmark times (balanced k-d batches of 64 targets):
 the GPU treecode's outputs at 2,000 (1,000 for 4e6) sampled targets against the oracle's
 treecode evaluated at the same targets one by one (same tree, same batch
 MAC).  FP64 to 1e-12; FP32 evaluation with FP64 accumulation (and, on the
@@ -37,11 +37,11 @@ def test_full_size_sampled(torch, orc, name, kernel):
     d_w = torch.from_numpy(w).cuda()
     T = bltc.Tree(d_src, cfg["leaf"])
     T.compute_weights(d_w, cfg["degree"])
-    G = bltc.Targets(d_src, 64, 32, 512)
+    G = bltc.Targets(d_src, 64, 0)
     idx = inputs.sample_indices(n, 1000 if n > 2000000 else 2000, 3)
     ref, _, _ = orc.treecode(cfg["kernel"], src, src, w, cfg["eps"], cfg["degree"],
-                             cfg["theta"], cfg["leaf"], mac_mode=1, batch_size=64, order_leaf=32,
-                             group_max=512, sample=idx)
+                             cfg["theta"], cfg["leaf"], mac_mode=1, batch_size=64, order_leaf=0,
+                             sample=idx)
     d_idx = torch.from_numpy(idx).cuda()
     modes = [("fp64", 1e-12), ("fp32_fp64acc", 1e-6)]
     if name == "c3":
@@ -65,11 +65,10 @@ def test_full_size_separation_rule(torch, orc):
     d_w = torch.from_numpy(w).cuda()
     T = bltc.Tree(d_src, cfg["leaf"])
     T.compute_weights(d_w, degree)
-    G = bltc.Targets(d_src, 64, 32, 512)
+    G = bltc.Targets(d_src, 64, 0)
     idx = inputs.sample_indices(n, 2000, 5)
     ref, _, _ = orc.treecode(cfg["kernel"], src, src, w, cfg["eps"], degree, theta, cfg["leaf"],
-                             mac_mode=1, batch_size=64, order_leaf=32, group_max=512,
-                             sample=idx, deg_min=1)
+                             mac_mode=1, batch_size=64, order_leaf=0, sample=idx, deg_min=1)
     d_idx = torch.from_numpy(idx).cuda()
     for precision, tol in (("fp64", 1e-12), ("fp32_fp64acc", 1e-6)):
         out = bltc.evaluate_tree(T, G, cfg["kernel"], cfg["eps"], degree, theta,

@@ -57,7 +57,8 @@ def test_tree_and_batches_bit_exact(torch, orc, dist, n, leaf):
     assert T.depth == R.depth and T.nnodes == R.nnodes
     for k in TREE_KEYS:
         assert np.array_equal(a[k], getattr(R, k)), k
-    for bs, ol, gm in [(64, 64, 256), (100, 40, 150), (1, 64, 256), (64, 16, 10 ** 9)]:
+    for bs, ol, gm in [(64, 64, 256), (100, 40, 150), (1, 64, 256), (64, 16, 10 ** 9),
+                       (64, 0, 512), (100, 0, 512), (1, 0, 512)]:
         g = bltc.Targets(_d(torch, p), bs, ol, gm).export()
         ob = orc.batches(p, bs, ol, gm)
         for x, y in zip([g["tperm"], g["bptr"], g["bcenter"], g["bradius"]], ob):
@@ -182,15 +183,15 @@ def test_modified_weights_flat_and_coincident(torch, orc, degree, wdim):
 
 
 @pytest.mark.parametrize("theta", [0.0, 0.3, 0.7, 1.0])
-@pytest.mark.parametrize("bs", [1, 64, 100])
-def test_lists_bit_exact(torch, orc, theta, bs):
+@pytest.mark.parametrize("bs,ol", [(1, 64), (64, 64), (100, 64), (64, 0), (100, 0)])
+def test_lists_bit_exact(torch, orc, theta, bs, ol):
     src = inputs.points("mixture", 12000, 41)
     tgt = inputs.points("uniform", 3001, 42) * 1.2
     w = inputs.weights(12000, 41)
     T = _gpu_tree(torch, src, w, 120, 3)
-    G = bltc.Targets(_d(torch, tgt), bs, 64)
+    G = bltc.Targets(_d(torch, tgt), bs, ol)
     L = bltc.lists(T, G, theta)
-    R = orc.lists(src, 120, tgt, theta, bs, 64)
+    R = orc.lists(src, 120, tgt, theta, bs, ol)
     for k in ["prox_ptr", "prox_ids", "dir_ptr", "dir_ids"]:
         assert np.array_equal(L[k], R[k]), k
 

@@ -64,7 +64,7 @@ def test_one_call_enomem_at_every_allocation(torch, orc):
     print(f"[robust] one-call evaluation: {failures} allocations failed in turn", flush=True)
     assert failures >= 10
     ref, _, _ = orc.treecode("stokeslet", src, src, w, 0.01, 4, 0.7, 300, mac_mode=1,
-                             batch_size=64, order_leaf=32)
+                             batch_size=64, order_leaf=0)
     close(orc, ref, out.cpu().numpy(), 1e-12, what="after the injected failures")
 
 

@@ -48,7 +48,8 @@ def test_host_tree_degenerate(orc):
 
 
 @pytest.mark.parametrize("bs,leaf,group", [(64, 64, 256), (1, 64, 256), (100, 30, 90),
-                                            (1024, 200, 10 ** 9), (256, 256, 300), (64, 16, 1)])
+                                            (1024, 200, 10 ** 9), (256, 256, 300), (64, 16, 1),
+                                            (64, 0, 512), (1, 0, 512), (1000, 0, 512)])
 def test_host_batches_bit_exact(orc, bs, leaf, group):
     p = inputs.points("mixture", 7777, 3)
     b = bltc.host_batches(p, bs, leaf, group)

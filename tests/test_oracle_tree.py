@@ -151,3 +151,72 @@ def test_batches_bound_the_radius(orc):
     _, bptr, _, br = orc.batches(pts, 64, 32, 256)
     _, bptr2, _, br2 = orc.batches(pts, 64, 32, 10 ** 9)
     assert br.max() < 0.5 * br2.max()
+
+
+def _kd_reference(pts, bs):
+    """The balanced k-d rule written out with full sorts: a set larger than
+    bs is cut along the longest side of its tight box (first of equal
+    sides), the first part taking the bs * floor(ceil(c / bs) / 2) smallest
+    by (coordinate, index); smaller sets are batches in increasing index."""
+    out = []
+
+    def rec(idx):
+        if idx.size <= bs:
+            out.append(np.sort(idx))
+            return
+        p = pts[:, idx]
+        side = p.max(axis=1) - p.min(axis=1)
+        ax = int(np.argmax(side))            # the first of equal sides
+        order = idx[np.lexsort((idx, pts[ax, idx]))]
+        left = bs * (((idx.size + bs - 1) // bs) // 2)
+        rec(order[:left])
+        rec(order[left:])
+
+    rec(np.arange(pts.shape[1]))
+    return out
+
+
+@pytest.mark.parametrize("dist,m,bs", [("uniform", 3000, 64), ("mixture", 2001, 64),
+                                       ("union", 777, 10), ("uniform", 64, 64),
+                                       ("uniform", 65, 64), ("mixture", 5, 64)])
+def test_kd_batches(orc, dist, m, bs):
+    pts = inputs.points(dist, m, 8)
+    tperm, bptr, bc, br = orc.batches(pts, bs, 0)
+    ref = _kd_reference(pts, bs)
+    assert bptr.size - 1 == len(ref) == (m + bs - 1) // bs
+    for b, r in enumerate(ref):
+        assert np.array_equal(tperm[bptr[b]:bptr[b + 1]], r), b
+    # full batches except the last
+    cnt = np.diff(bptr)
+    assert np.all(cnt[:-1] == bs) and 0 < cnt[-1] <= bs
+    assert sorted(tperm.tolist()) == list(range(m))
+    for b in range(bc.shape[0]):
+        p = pts[:, tperm[bptr[b]:bptr[b + 1]]]
+        lo, hi = p.min(axis=1), p.max(axis=1)
+        assert np.array_equal(bc[b], 0.5 * (lo + hi))
+        h = 0.5 * (hi - lo)
+        assert br[b] == np.sqrt(h[0] * h[0] + h[1] * h[1] + h[2] * h[2])
+
+
+def test_kd_batches_ties_and_coincident_points(orc):
+    """Equal coordinates (a small integer lattice with repeats, and a set of
+    identical points) are ordered by target index."""
+    rng = np.random.default_rng(9)
+    pts = rng.integers(0, 3, size=(3, 500)).astype(np.float64)
+    tperm, bptr, _, _ = orc.batches(pts, 16, 0)
+    ref = _kd_reference(pts, 16)
+    for b, r in enumerate(ref):
+        assert np.array_equal(tperm[bptr[b]:bptr[b + 1]], r), b
+    same = np.ones((3, 100))
+    tperm, bptr, bc, br = orc.batches(same, 8, 0)
+    assert np.array_equal(tperm, np.arange(100)) and np.all(br == 0.0)
+
+
+def test_kd_batches_are_compact(orc):
+    """On uniform points the k-d batches are no wider than the batches of
+    the order tree's groups, and they are full."""
+    pts = inputs.points("uniform", 20000, 6)
+    _, bptr_t, _, br_t = orc.batches(pts, 64, 32, 512)
+    _, bptr_k, _, br_k = orc.batches(pts, 64, 0)
+    assert bptr_k.size - 1 == 313 < bptr_t.size - 1
+    assert br_k.mean() < br_t.mean()

@@ -161,14 +161,16 @@ def test_translation(orc):
         assert orc.rel_l2(a, b) < 1e-4
 
 
-def test_batch_mac_soundness_and_counts(orc):
+@pytest.mark.parametrize("order_leaf", [64, 0])
+def test_batch_mac_soundness_and_counts(orc, order_leaf):
     """P13: every cluster accepted for a batch passes the per-target MAC for
-    each target of the batch; one target per batch reproduces mode 0."""
+    each target of the batch; one target per batch reproduces mode 0.  Both
+    batch rules (order-tree groups, balanced k-d)."""
     src = inputs.points("mixture", 4000, 8)
     tgt = inputs.points("uniform", 1500, 9)
     w = inputs.weights(4000, 8)
     theta = 0.7
-    L = orc.lists(src, 100, tgt, theta, 64, 64)
+    L = orc.lists(src, 100, tgt, theta, 64, order_leaf)
     T = orc.Tree(src, 100)
     for b in range(L["bptr"].size - 1):
         xs = tgt[:, L["tperm"][L["bptr"][b]:L["bptr"][b + 1]]]
@@ -183,11 +185,11 @@ def test_batch_mac_soundness_and_counts(orc):
         assert np.all(cover == 1)
     a, npa, nda = orc.treecode("stokeslet", tgt, src, w, 0.01, 5, theta, 100, mac_mode=0)
     b, npb, ndb = orc.treecode("stokeslet", tgt, src, w, 0.01, 5, theta, 100, mac_mode=1,
-                               batch_size=1, order_leaf=64)
+                               batch_size=1, order_leaf=order_leaf)
     assert np.array_equal(a, b) and npa == npb and nda == ndb
     # interaction counts from the lists
     c, npc, ndc = orc.treecode("stokeslet", tgt, src, w, 0.01, 5, theta, 100, mac_mode=1,
-                               batch_size=64, order_leaf=64)
+                               batch_size=64, order_leaf=order_leaf)
     cnt = np.diff(L["bptr"])
     per_b_p = np.array([L["prox_ptr"][b + 1] - L["prox_ptr"][b] for b in range(cnt.size)])
     sizes = T.pend - T.pbegin
