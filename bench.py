@@ -15,8 +15,12 @@ timing (their build time is reported in "build_ms").
 Printed on stdout: one JSON line.  value = kernel evaluations performed per
 second (far-field proxy evaluations plus near-field pair evaluations, summed
 over targets).  Also reported: the relative L2 error against the FP64 direct
-sum on a 10,000-target sample, the per-stage device times from the library's
-HIP events, the roofline of the evaluation kernel and the CPU oracle's rate.
+sum on a 10,000-target sample (the library's GPU direct sum) and on 2,000
+targets against the oracle's CPU direct sum, the headline in the other
+accumulation modes, the learned (n, theta) against the best fixed settings at
+an error target (a sweep of the candidate grid), the per-stage device times
+from the library's HIP events, the roofline of the evaluation kernel and the
+CPU oracle's rate.
 """
 import argparse
 import json
@@ -41,35 +45,38 @@ def log(*a):
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_p2p_stokeslet_n1e6_hbm_traffic.md")
+COUNTER_FILE = os.path.join(ROOT, "profiles", "k_p2p_stokeslet_n1e6_valu_counters.md")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1902_02250_amd", "csrc", f)
                   for f in ("k_p2p.hip", "kmath.h")]
 
 
-def measured_traffic(args, cfg):
-    """HBM bytes per launch of the evaluation kernel from the committed
-    rocprofv3 FETCH_SIZE / WRITE_SIZE summary, or None when that summary is
-    for another workload or the kernel sources changed since it was taken."""
+def profile_record(path, key, args, cfg):
+    """A per-launch figure of the evaluation kernel from a committed rocprofv3
+    summary, or None when that summary is for another workload or launch
+    configuration, or the kernel sources changed since it was taken."""
     import hashlib
-    if (args.workload, cfg["n"], cfg["degree"], args.precision, args.batch_size) != \
-            ("c3", 1000000, 8, "fp32_fp64acc", 64) or not os.path.exists(TRAFFIC_FILE):
+    if (args.workload, cfg["n"], cfg["degree"], args.precision, args.batch_size,
+            args.order_leaf) != ("c3", 1000000, 8, "fp32_fp64acc", 64, 0) \
+            or not os.path.exists(path):
         return None
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
         h.update(open(f, "rb").read())
     rec = {}
-    for line in open(TRAFFIC_FILE):
-        if ":" in line and line.split(":")[0] in ("traffic_bytes_per_launch",
-                                                   "kernel_source_sha256"):
+    for line in open(path):
+        if ":" in line and line.split(":")[0] in (key, "kernel_source_sha256"):
             k, v = line.split(":", 1)
             rec[k] = v.strip()
-    if rec.get("kernel_source_sha256") != h.hexdigest():
+    if rec.get("kernel_source_sha256") != h.hexdigest() or key not in rec:
         return None
-    return float(rec["traffic_bytes_per_launch"])
+    return float(rec[key])
 
 
-def cpu_baseline(cfg, src, w, sample_k, precision_label):
+def cpu_baseline(cfg, src, w, sample_k, args, osamp, head_at_osamp):
     """The FP64 oracle treecode (tree, Algorithm 1 weights for all sources,
-    batch walk for a target sample) timed on the host cores."""
+    batch walk for a target sample) timed on the host cores.  The same leg
+    evaluates the oracle's FP64 direct sum (eq. N-body) at the osamp targets
+    and reports the headline's error against it."""
     import oracle
     from paper_1902_02250_amd import inputs
     oracle._load()
@@ -77,16 +84,25 @@ def cpu_baseline(cfg, src, w, sample_k, precision_label):
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     t0 = time.perf_counter()
     _, npx, ndr = oracle.treecode(cfg["kernel"], src, src, w, cfg["eps"], cfg["degree"],
-                                  cfg["theta"], cfg["leaf"], mac_mode=1, batch_size=64,
-                                  order_leaf=32, group_max=512, sample=idx)
+                                  cfg["theta"], cfg["leaf"], mac_mode=1,
+                                  batch_size=args.batch_size, order_leaf=args.order_leaf,
+                                  group_max=args.group_max, sample=idx)
     dt = time.perf_counter() - t0
+    t1 = time.perf_counter()
+    ref = oracle.direct_subset(cfg["kernel"], src, osamp, src, w, cfg["eps"])
+    dt_direct = time.perf_counter() - t1
+    e_oracle = float(np.linalg.norm(head_at_osamp - ref) / np.linalg.norm(ref))
     return {"value": (npx + ndr) / dt, "unit": "interactions/s", "cores": threads,
             "kind": "oracle",
             "sample": (f"FP64 oracle treecode from scratch (tree, Algorithm 1 weights for all "
                        f"{src.shape[1]} sources, shared-batch walk) evaluated for {sample_k} "
                        f"seeded targets of the same workload: {npx + ndr} kernel evaluations "
                        f"in {dt:.2f} s on {threads} OpenMP threads"),
-            "seconds": dt}
+            "seconds": dt,
+            "rel_l2_err_oracle": e_oracle,
+            "oracle_direct": (f"oracle FP64 direct sum at {osamp.size} seeded targets "
+                              f"({dt_direct:.2f} s): the headline's relative L2 error "
+                              f"against it")}
 
 
 def main():
@@ -110,9 +126,23 @@ def main():
     ap.add_argument("--err-sample", type=int, default=10000)
     ap.add_argument("--cpu-sample", type=int, default=65536)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tol", type=float, default=1e-6,
+                    help="error target of the learned-vs-fixed comparison")
+    ap.add_argument("--fallback", default="10,0.6",
+                    help="the learned path's fallback and judge (n, theta)")
+    ap.add_argument("--sweep", type=int, default=None,
+                    help="1: time every candidate (n, theta) of the selector, plain and with "
+                         "the separation rule, to find the best fixed settings at --tol "
+                         "(default on for the 1e6 uniform workload); 0: only --tol-settings")
     ap.add_argument("--tol-settings", default="9,0.7,0;10,0.7,1",
-                    help="n,theta,deg_min;... settings also timed, with their error, "
-                         "beside the headline configuration ('' for none)")
+                    help="n,theta,deg_min;... fixed settings timed when --sweep 0")
+    ap.add_argument("--no-learned", dest="learned", action="store_false",
+                    help="skip the learned (n, theta) legs")
+    ap.add_argument("--precision-legs", default="fp64,fp32_kahan",
+                    help="other accumulation modes timed at the headline setting")
+    ap.add_argument("--oracle-sample", type=int, default=2000,
+                    help="targets at which the CPU leg checks the headline against the oracle's "
+                         "FP64 direct sum")
     ap.add_argument("--dual-settings", default=None,
                     help="cluster-cluster variant settings 'n,theta,target_leaf[,deg_min];...' "
                          "timed after the headline (default: two settings at E <= 1e-6 on the "
@@ -121,6 +151,9 @@ def main():
                     help="first run one device-to-device copy of MIB MiB, the reference "
                          "for scaling HBM byte counters")
     args = ap.parse_args()
+    args.fallback = (int(args.fallback.split(",")[0]), float(args.fallback.split(",")[1]))
+    if args.sweep is None:
+        args.sweep = 1 if args.workload == "c3" and not args.n else 0
     if args.dual_settings is None:
         args.dual_settings = "7,0.7,400;9,0.8,700" if args.workload == "c3" and not args.n else ""
 
@@ -235,10 +268,21 @@ def main():
     achieved = flops / (ev_ms * 1e-3) / 1e12
     pk = PEAK["fp64" if args.precision == "fp64" else "fp32"]
     roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": pk, "unit": "TFLOP/s",
-            "frac": round(achieved / pk, 4), "traffic": measured_traffic(args, cfg),
+            "frac": round(achieved / pk, 4),
+            "traffic": profile_record(TRAFFIC_FILE, "traffic_bytes_per_launch", args, cfg),
             "kernel": f"k_p2p ({kernel}, {args.precision}, n={degree})",
+            "achieved_kind": "algorithmic: kernel evaluations x flop per evaluation "
+                             "(FMA = 2, rsqrt = 1) / launch time",
             "per_launch": f"{inter} kernel evaluations x {FLOPS.get(kernel, 32)} flop",
             "avg_launch_ms": round(ev_ms, 4)}
+    executed = profile_record(COUNTER_FILE, "executed_fp32_flops_per_launch", args, cfg)
+    if executed is not None:
+        roof["executed"] = {"achieved": round(executed / (ev_ms * 1e-3) / 1e12, 3),
+                            "frac": round(executed / (ev_ms * 1e-3) / 1e12 / pk, 4),
+                            "unit": "TFLOP/s",
+                            "kind": "counter-derived: 64 x SQ_INSTS_VALU_FLOPS_FP32 per launch "
+                                    "(committed rocprofv3 summary of the same kernel source) "
+                                    "/ launch time"}
 
     res = {
         "metric": "eval time & interactions/s at N=1e6, rel L2 err vs FP64 direct; "
@@ -266,34 +310,112 @@ def main():
         "roofline": roof,
         "cpu_baseline": None,
     }
-    # further settings of the same workload: fixed degree and separation rule
-    extra = []
-    for item in [t for t in args.tol_settings.split(";") if t.strip()]:
-        dn, th, dm = item.split(",")
-        dn, th, dm = int(dn), float(th), int(dm)
+    # the headline's output at the oracle's sample targets (for the CPU leg)
+    osamp = inputs.sample_indices(n, min(args.oracle_sample, n), cfg["seed"] + 13)
+    head_at_osamp = out[:, torch.from_numpy(osamp).to(dev)].cpu().numpy()
 
+    def timed(xstep, reps):
+        xstep()
+        torch.cuda.synchronize()
+        e0.record()
+        for i in range(reps):
+            r = xstep()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps, r
+
+    # the headline in the other accumulation modes (same n, theta)
+    legs = []
+    for prec in [p for p in args.precision_legs.split(",") if p and p != args.precision]:
+        def pstep(prec=prec):
+            tree.compute_weights(d_w, degree)
+            bltc.evaluate_tree(tree, tg, kernel, eps, degree, theta, precision=prec, out=out)
+        xs = max(2, args.steps // 2)
+        xms, _ = timed(pstep, xs)
+        legs.append({"precision": prec, "steps": xs, "ms_per_step": round(xms, 4),
+                     **errors(out[:, d_idx]), "interactions_per_s": inter / (xms * 1e-3)})
+        log(f"[bench] headline in {prec}: {xms:.3f} ms/step, E={legs[-1]['rel_l2_err']:.3e}")
+    res["precision_legs"] = legs
+
+    # fixed settings at the error target: the listed ones, or the sweep of
+    # the selector's whole candidate grid with and without the separation rule
+    from paper_1902_02250_amd import selector
+    if args.sweep:
+        grid = [(c[0], c[1], dm) for dm in (0, selector.DEG_MIN) for c in selector.CANDIDATES]
+    else:
+        grid = []
+        for item in [t for t in args.tol_settings.split(";") if t.strip()]:
+            dn, th, dm = item.split(",")
+            grid.append((int(dn), float(th), int(dm)))
+    fixed = []
+    for (dn, th, dm) in grid:
         def xstep(dn=dn, th=th, dm=dm):
             tree.compute_weights(d_w, dn)
             bltc.evaluate_tree(tree, tg, kernel, eps, dn, th, precision=args.precision,
                                out=out, deg_min=dm)
-        xstep()
-        torch.cuda.synchronize()
-        xs = max(2, args.steps // 2)
-        e0.record()
-        for i in range(xs):
-            xstep()
-        e1.record()
-        torch.cuda.synchronize()
-        xms = e0.elapsed_time(e1) / xs
+        xms, _ = timed(xstep, 1 if args.sweep else max(2, args.steps // 2))
         xerrs = errors(out[:, d_idx])
-        xerr = xerrs["rel_l2_err"]
-        xp, xd = bltc.counts(tree, tg, dn, th, dm)
-        extra.append({"degree": dn, "theta": th, "deg_min": dm, "steps": xs,
-                      "ms_per_step": round(xms, 4), **xerrs,
-                      "interactions_per_step": xp + xd,
-                      "interactions_per_s": (xp + xd) / (xms * 1e-3)})
-        log(f"[bench] n={dn} theta={th} deg_min={dm}: {xms:.3f} ms/step, E={xerr:.3e}")
-    res["settings"] = extra
+        fixed.append({"degree": dn, "theta": th, "deg_min": dm, "ms_per_step": round(xms, 4),
+                      **xerrs})
+    def best_of(rows, dm_set):
+        ok = [r for r in rows if r["deg_min"] in dm_set and r["rel_l2_err"] <= args.tol]
+        return min(ok, key=lambda r: r["ms_per_step"]) if ok else None
+    best = {"plain": best_of(fixed, (0,)), "rule": best_of(fixed, tuple(
+        sorted({r["deg_min"] for r in fixed if r["deg_min"] > 0})))}
+    # the winners again, with more steps
+    for key, row in best.items():
+        if row is None:
+            continue
+        def bstep(row=row):
+            tree.compute_weights(d_w, row["degree"])
+            bltc.evaluate_tree(tree, tg, kernel, eps, row["degree"], row["theta"],
+                               precision=args.precision, out=out, deg_min=row["deg_min"])
+        xs = max(3, args.steps // 2)
+        xms, _ = timed(bstep, xs)
+        p_, d_ = bltc.counts(tree, tg, row["degree"], row["theta"], row["deg_min"])
+        best[key] = dict(row, ms_per_step=round(xms, 4), steps=xs, **errors(out[:, d_idx]),
+                         interactions_per_step=p_ + d_,
+                         interactions_per_s=(p_ + d_) / (xms * 1e-3))
+        log(f"[bench] best fixed ({key}) at E <= {args.tol:g}: n={row['degree']} "
+            f"theta={row['theta']} deg_min={row['deg_min']}: {xms:.3f} ms/step, "
+            f"E={best[key]['rel_l2_err']:.3e}")
+    overall = [b for b in best.values() if b is not None]
+    overall = min(overall, key=lambda r: r["ms_per_step"]) if overall else None
+    # the learned (n, theta): per batch and one per run, with the fallback's
+    # weights, the judge and any repair inside the timed step
+    learned = []
+    if args.learned and kernel in ("stokeslet", "rotlet"):
+        sel = bltc.Selector(selector.MODEL_PATH)
+        for mode in ("batch", "run"):
+            def lstep(mode=mode):
+                tree.compute_weights(d_w, args.fallback[0])
+                return bltc.evaluate_adaptive(tree, tg, kernel, eps, sel, args.tol,
+                                              args.fallback[0], args.fallback[1],
+                                              precision=args.precision, out=out, mode=mode)
+            xs = max(3, args.steps // 2)
+            xms, (_, choice, stats, judge) = timed(lstep, xs)
+            used = np.bincount(choice[choice >= 0], minlength=selector.K)
+            row = {"mode": mode, "steps": xs, "ms_per_step": round(xms, 4),
+                   **errors(out[:, d_idx]),
+                   "judge_estimate": [float(judge[0]), float(judge[1])],
+                   "batches_repaired": int(stats[2]), "degrees": int(stats[1]),
+                   "top_choices": [[list(selector.CANDIDATES[j]), int(used[j])]
+                                   for j in np.argsort(-used)[:4] if used[j]]}
+            for key, b in (("best_fixed", overall), ("best_fixed_plain", best["plain"]),
+                           ("best_fixed_rule", best["rule"])):
+                if b is not None:
+                    row[f"speedup_vs_{key}"] = round(b["ms_per_step"] / xms, 4)
+            learned.append(row)
+            log(f"[bench] learned ({mode}) at tol {args.tol:g}: {xms:.3f} ms/step, "
+                f"E={row['rel_l2_err']:.3e}, judge {judge[0]:.2e} -> {judge[1]:.2e}, "
+                f"{int(stats[2])} batches repaired, top {row['top_choices'][:2]}")
+    res["learned_vs_fixed"] = {
+        "tol": args.tol, "fallback": list(args.fallback),
+        "grid": "selector candidates, plain and with the separation rule" if args.sweep
+                else "listed settings",
+        "best_fixed": overall, "best_fixed_plain": best["plain"], "best_fixed_rule": best["rule"],
+        "learned": learned,
+        "fixed": fixed}
     # the cluster-cluster variant on the same workload (targets = sources)
     dual = []
     for item in [t for t in args.dual_settings.split(";") if t.strip()]:
@@ -330,9 +452,13 @@ def main():
     res["dual"] = dual
     if not args.no_cpu_baseline:
         log(f"[bench] CPU oracle baseline on {args.cpu_sample} targets ...")
-        res["cpu_baseline"] = cpu_baseline(cfg, src, w, args.cpu_sample, args.precision)
+        res["cpu_baseline"] = cpu_baseline(cfg, src, w, args.cpu_sample, args, osamp,
+                                           head_at_osamp)
+        res["rel_l2_err_oracle"] = res["cpu_baseline"]["rel_l2_err_oracle"]
+        res["err_sample_oracle"] = int(osamp.size)
         log(f"[bench] CPU oracle: {res['cpu_baseline']['value']:.3e} interactions/s "
-            f"({res['cpu_baseline']['seconds']:.1f} s)")
+            f"({res['cpu_baseline']['seconds']:.1f} s); headline E vs the oracle's direct sum "
+            f"on {osamp.size} targets {res['rel_l2_err_oracle']:.3e}")
     print(json.dumps(res), flush=True)
 
 

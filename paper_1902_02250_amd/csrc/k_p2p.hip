@@ -55,17 +55,27 @@ __device__ __forceinline__ T fmat(T a, T b, T c) {
 // shares dz.  A term c_k d_k (c a scalar per proxy) is therefore summed as
 //   dx * (row sum of c),  dy * (row sum of c),  sum_k3 dz_k3 * (column sum of c),
 // so the d-weighted parts of the kernels cost one multiply-add per proxy and
-// marginal instead of a product and a multiply-add per component.
+// marginal instead of a product and a multiply-add per component.  Every
+// sum runs over a grid row first (n+1 terms) and then over the rows, which
+// keeps the FP32 rounding of a cluster's sum near that of n+1 + (n+1)^2
+// additions instead of (n+1)^3.  The per-axis differences are
+// formed once per (target, cluster): dz and dz^2 in registers (the k3 loop
+// is unrolled), dy and dy^2 in this lane's entries of an LDS table
+// (sd[k2 * 128 + 0/1]) because the k2 loop is not, so a grid row costs
+// one LDS read instead of an FP64 difference, a conversion and a square.
 template <int KERN, int N1, bool ZEPS, typename T, typename F>
 __device__ __forceinline__ void proxies(double x, double y, double z,
                                         const double* __restrict__ g,
                                         const F* __restrict__ fh, T e2,
-                                        T* p) {
+                                        T* __restrict__ sd, T* p) {
   T dz[N1], dz2[N1];
 #pragma unroll
   for (int k = 0; k < N1; ++k) {
     dz[k] = (T)(z - g[2 * N1 + k]);
     dz2[k] = dz[k] * dz[k];
+    const T d = (T)(y - g[N1 + k]);
+    sd[k * 128] = d;
+    sd[k * 128 + 1] = d * d;
   }
   if constexpr (KERN == KSTOKES) {
     // u = sum f H1 + sum (f.d) H2 d,  H2 = inv^3
@@ -76,8 +86,8 @@ __device__ __forceinline__ void proxies(double x, double y, double z,
       const T dx = (T)(x - g[k1]);
       const T dx2e = dx * dx + e2;
       for (int k2 = 0; k2 < N1; ++k2) {
-        const T dy = (T)(y - g[N1 + k2]);
-        const T dxy2 = dy * dy + dx2e;
+        const T dy = sd[k2 * 128];
+        const T dxy2 = sd[k2 * 128 + 1] + dx2e;
         const F* __restrict__ R = fh + (k1 * N1 + k2) * 3 * N1;   // [c][k3], c < 3
         T S = 0, ax = 0, ay = 0, az = 0;
 #pragma unroll
@@ -87,14 +97,15 @@ __device__ __forceinline__ void proxies(double x, double y, double z,
           const T inv3 = (inv * inv) * inv;
           const T fd = fz * dz[k3] + (fy * dy + fx * dx);
           const T h1 = e2 * inv3 + inv;
-          ax = fx * h1 + ax;
-          ay = fy * h1 + ay;
-          az = fz * h1 + az;
+          ax = fmat(fx, h1, ax);
+          ay = fmat(fy, h1, ay);
+          az = fmat(fz, h1, az);
           S = fmat(fd, inv3, S);
           cz[k3] = fmat(fd, inv3, cz[k3]);
         }
-        p[0] += dx * S + ax;
-        p[1] += dy * S + ay;
+        // row sums first: FP32 partials of (n+1) terms, then (n+1)^2 rows
+        p[0] += fmat(dx, S, ax);
+        p[1] += fmat(dy, S, ay);
         p[2] += az;
       }
     }
@@ -111,8 +122,8 @@ __device__ __forceinline__ void proxies(double x, double y, double z,
       const T dx = (T)(x - g[k1]);
       const T dx2e = dx * dx + e2;
       for (int k2 = 0; k2 < N1; ++k2) {
-        const T dy = (T)(y - g[N1 + k2]);
-        const T dxy2 = dy * dy + dx2e;
+        const T dy = sd[k2 * 128];
+        const T dxy2 = sd[k2 * 128 + 1] + dx2e;
         const F* __restrict__ R = fh + (k1 * N1 + k2) * 6 * N1;   // [c][k3], c < 6
         T ax = 0, ay = 0, az = 0, S = 0, Qx = 0, Qy = 0, Qz = 0;
         T Fx = 0, Fy = 0, Fz = 0, Wx = 0, Wy = 0, Wz = 0, G = 0;
@@ -130,9 +141,9 @@ __device__ __forceinline__ void proxies(double x, double y, double z,
           const T d2q = (d2a * inv2 + T(1.5)) * inv5;                   // D2/4
           const T fd = fz * dz[k3] + (fy * dy + fx * dx);
           const T nd = nz * dz[k3] + (ny * dy + nx * dx);
-          ax = fx * h1 + ax;
-          ay = fy * h1 + ay;
-          az = fz * h1 + az;
+          ax = fmat(fx, h1, ax);
+          ay = fmat(fy, h1, ay);
+          az = fmat(fz, h1, az);
           S = fmat(fd, inv3, S);
           cz[k3] = fmat(fd, inv3, cz[k3]);
           Qx = fmat(qh, nx, Qx);
@@ -145,19 +156,19 @@ __device__ __forceinline__ void proxies(double x, double y, double z,
           Fz = fmat(qh, fz, Fz);
           cfx[k3] = fmat(qh, fx, cfx[k3]);
           cfy[k3] = fmat(qh, fy, cfy[k3]);
-          Wx = d1q * nx + Wx;
-          Wy = d1q * ny + Wy;
-          Wz = d1q * nz + Wz;
+          Wx = fmat(d1q, nx, Wx);
+          Wy = fmat(d1q, ny, Wy);
+          Wz = fmat(d1q, nz, Wz);
           G = fmat(d2q, nd, G);
           cg[k3] = fmat(d2q, nd, cg[k3]);
         }
         // f x d and n x d split into the row's dx, dy and the column's dz
-        p[0] += (dx * S + ax) - dy * Qz;
-        p[1] += (dy * S + ay) + dx * Qz;
-        p[2] += (dy * Qx + az) - dx * Qy;
-        p[3] += (dx * G + Wx) - dy * Fz;
-        p[4] += (dy * G + Wy) + dx * Fz;
-        p[5] += (dy * Fx + Wz) - dx * Fy;
+        p[0] += fmat(dx, S, ax) - dy * Qz;
+        p[1] += fmat(dy, S, ay) + dx * Qz;
+        p[2] += fmat(dy, Qx, az) - dx * Qy;
+        p[3] += fmat(dx, G, Wx) - dy * Fz;
+        p[4] += fmat(dy, G, Wy) + dx * Fz;
+        p[5] += fmat(dy, Fx, Wz) - dx * Fy;
       }
     }
 #pragma unroll
@@ -179,8 +190,8 @@ __device__ __forceinline__ void proxies(double x, double y, double z,
       const T dx = (T)(x - g[k1]);
       const T dx2e = dx * dx + e2;
       for (int k2 = 0; k2 < N1; ++k2) {
-        const T dy = (T)(y - g[N1 + k2]);
-        const T dxy2 = dy * dy + dx2e;
+        const T dy = sd[k2 * 128];
+        const T dxy2 = sd[k2 * 128 + 1] + dx2e;
         const F* __restrict__ R = fh + (k1 * N1 + k2) * 3 * N1;
         T qx = 0, qy = 0, qz = 0, G = 0, wx = 0, wy = 0, wz = 0;
 #pragma unroll
@@ -199,9 +210,9 @@ __device__ __forceinline__ void proxies(double x, double y, double z,
           qz = fmat(q, nz, qz);
           cqx[k3] = fmat(q, nx, cqx[k3]);
           cqy[k3] = fmat(q, ny, cqy[k3]);
-          wx = d1 * nx + wx;
-          wy = d1 * ny + wy;
-          wz = d1 * nz + wz;
+          wx = fmat(d1, nx, wx);
+          wy = fmat(d1, ny, wy);
+          wz = fmat(d1, nz, wz);
           G = fmat(d2, nd, G);
           cg[k3] = fmat(d2, nd, cg[k3]);
         }
@@ -209,8 +220,8 @@ __device__ __forceinline__ void proxies(double x, double y, double z,
         p[0] = -dy * qz + p[0];
         p[1] = dx * qz + p[1];
         p[2] += dy * qx - dx * qy;
-        p[3] += dx * G + wx;
-        p[4] += dy * G + wy;
+        p[3] += fmat(dx, G, wx);
+        p[4] += fmat(dy, G, wy);
         p[5] += wz;
       }
     }
@@ -253,13 +264,14 @@ __device__ __forceinline__ void proxies_poly(double x, double y, double z,
 template <int KERN, int M, bool ZEPS, typename T, typename F>
 __device__ __forceinline__ void proxies_low(int n1, double x, double y, double z,
                                             const double* __restrict__ g,
-                                            const F* __restrict__ fh, T e2, T* p) {
+                                            const F* __restrict__ fh, T e2,
+                                            T* __restrict__ sd, T* p) {
   if constexpr (M >= 2) {
     if (n1 == M) {
-      proxies<KERN, M, ZEPS, T, F>(x, y, z, g, fh, e2, p);
+      proxies<KERN, M, ZEPS, T, F>(x, y, z, g, fh, e2, sd, p);
       return;
     }
-    proxies_low<KERN, M - 1, ZEPS, T, F>(n1, x, y, z, g, fh, e2, p);
+    proxies_low<KERN, M - 1, ZEPS, T, F>(n1, x, y, z, g, fh, e2, sd, p);
   }
 }
 
@@ -378,6 +390,7 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void k_p2p(
   using T = typename std::conditional<F64, double, float>::type;
   __shared__ T sA[kWavesPerBlock][4][64];        // source x, y, z, weight 0
   __shared__ T sB[kWavesPerBlock][WD - 1][64];   // weights 1 .. WD-1
+  __shared__ T sY[kWavesPerBlock][N1][64][2];    // far field: each lane's dy, dy^2 per grid row
 
   // the wave index is uniform across the wave; readfirstlane tells the
   // compiler so, which keeps everything derived from it in scalar registers
@@ -410,6 +423,7 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void k_p2p(
   const T e2 = (T)(eps * eps);
   T (*A)[64] = sA[wid];
   T (*B)[64] = sB[wid];
+  T* sd = &sY[wid][0][lane][0];
 
   Acc<PREC, OD> acc;
   acc.init();
@@ -428,9 +442,9 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void k_p2p(
       if constexpr (KERN == KPOLY)
         proxies_poly<N1>(x, y, z, g, fh64 + (int64_t)q * 3 * NK, poly_p, poly_c, p);
       else if constexpr (F64)
-        proxies<KERN, N1, ZEPS, T, double>(x, y, z, g, fh64 + (int64_t)q * WD * NK, e2, p);
+        proxies<KERN, N1, ZEPS, T, double>(x, y, z, g, fh64 + (int64_t)q * WD * NK, e2, sd, p);
       else
-        proxies<KERN, N1, ZEPS, T, float>(x, y, z, g, fh32 + (int64_t)q * WD * NK, e2, p);
+        proxies<KERN, N1, ZEPS, T, float>(x, y, z, g, fh32 + (int64_t)q * WD * NK, e2, sd, p);
     } else if (RULE && n1 >= 2 && n1 < N1) {
       const double* __restrict__ g = dt.grid[n1 - 1] + (int64_t)q * 3 * n1;
       const int64_t o = (int64_t)q * WD * n1 * n1 * n1;
@@ -439,10 +453,10 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void k_p2p(
                                  poly_c, p);
       else if constexpr (F64)
         proxies_low<KERN, N1 - 1, ZEPS, T, double>(n1, x, y, z, g,
-                                                   (const double*)dt.fh[n1 - 1] + o, e2, p);
+                                                   (const double*)dt.fh[n1 - 1] + o, e2, sd, p);
       else
         proxies_low<KERN, N1 - 1, ZEPS, T, float>(n1, x, y, z, g,
-                                                  (const float*)dt.fh[n1 - 1] + o, e2, p);
+                                                  (const float*)dt.fh[n1 - 1] + o, e2, sd, p);
     }
     acc.fold(p);
   }
