@@ -165,7 +165,8 @@ void orc_tree_export(const orc_tree* t, int64_t* perm, double* box,
                      int32_t* child_count, int64_t* pbegin, int64_t* pend,
                      int32_t* level, int32_t* parent) {
   int64_t nn = t->nn;
-  if (perm) memcpy(perm, t->perm, sizeof(int64_t) * t->n);
+  if (perm && t->n) memcpy(perm, t->perm, sizeof(int64_t) * t->n);
+  if (nn == 0) return;   /* an empty set has no nodes (and no arrays) */
   if (box) memcpy(box, t->box, sizeof(double) * 6 * nn);
   if (center) memcpy(center, t->center, sizeof(double) * 3 * nn);
   if (radius) memcpy(radius, t->radius, sizeof(double) * nn);
