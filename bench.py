@@ -147,6 +147,10 @@ def main():
                     help="cluster-cluster variant settings 'n,theta,target_leaf[,deg_min];...' "
                          "timed after the headline (default: two settings at E <= 1e-6 on the "
                          "1e6 uniform workload, none on the others)")
+    ap.add_argument("--grid-sweep", type=int, default=None,
+                    help="1: time the workload's (n, theta) grid for the Stokeslet and the "
+                         "rotlet, FP64 and FP32 evaluation, E over all targets (default on for "
+                         "the 100K workload c2)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first run one device-to-device copy of MIB MiB, the reference "
                          "for scaling HBM byte counters")
@@ -154,6 +158,8 @@ def main():
     args.fallback = (int(args.fallback.split(",")[0]), float(args.fallback.split(",")[1]))
     if args.sweep is None:
         args.sweep = 1 if args.workload == "c3" and not args.n else 0
+    if args.grid_sweep is None:
+        args.grid_sweep = 1 if args.workload == "c2" else 0
     if args.dual_settings is None:
         args.dual_settings = "7,0.7,400;9,0.8,700" if args.workload == "c3" and not args.n else ""
 
@@ -450,6 +456,33 @@ def main():
         log(f"[bench] dual n={dn} theta={th} target leaf={lt} deg_min={dm}: {xms:.3f} ms/step, "
             f"E={xerrs['rel_l2_err']:.3e}, evaluations {cnt.tolist()}")
     res["dual"] = dual
+    # the (n, theta) grid of the 100K workload, both kernels, FP64 against
+    # FP32 evaluation with FP64 sums, E over every target
+    if args.grid_sweep:
+        gs = []
+        for gk in ("stokeslet", "rotlet"):
+            gref = bltc.direct(d_src, d_src, d_w, gk, eps, precision="fp64")
+            gout = torch.empty((bltc.ODIM[gk], n), dtype=torch.float64, device=dev)
+            for dn in cfg.get("degrees", (2, 4, 6, 8, 10)):
+                for th in cfg.get("thetas", (0.5, 0.7, 0.9)):
+                    row = {"kernel": gk, "degree": dn, "theta": th}
+                    for prec in ("fp64", "fp32_fp64acc"):
+                        def gstep(dn=dn, th=th, prec=prec, gk=gk):
+                            tree.compute_weights(d_w, dn)
+                            bltc.evaluate_tree(tree, tg, gk, eps, dn, th, precision=prec,
+                                               out=gout)
+                        gms, _ = timed(gstep, 3)
+                        gE = (torch.linalg.norm(gout - gref) / torch.linalg.norm(gref)).item()
+                        row[prec] = {"ms_per_step": round(gms, 4), "rel_l2_err": gE}
+                    p_, d_ = bltc.counts(tree, tg, dn, th)
+                    row["interactions_per_step"] = p_ + d_
+                    gs.append(row)
+                    log(f"[bench] grid {gk} n={dn} theta={th}: FP64 "
+                        f"{row['fp64']['ms_per_step']:.2f} ms E={row['fp64']['rel_l2_err']:.2e}; "
+                        f"FP32 {row['fp32_fp64acc']['ms_per_step']:.2f} ms "
+                        f"E={row['fp32_fp64acc']['rel_l2_err']:.2e}")
+        res["grid_sweep"] = {"targets": n, "err": "all targets against the FP64 direct sum",
+                             "rows": gs}
     if not args.no_cpu_baseline:
         log(f"[bench] CPU oracle baseline on {args.cpu_sample} targets ...")
         res["cpu_baseline"] = cpu_baseline(cfg, src, w, args.cpu_sample, args, osamp,

@@ -34,11 +34,7 @@ bltc::ListArgs list_args(bltc_tree t, bltc_targets g, double theta,
   bltc::ListArgs a;
   a.bgeo = g->d_bgeo;
   a.nb = nb;
-  a.nodes.geo = t->d_geo;
-  a.nodes.range = t->d_range;
-  a.nodes.kids = t->d_kids;
-  a.nodes.skip = t->d_skip;
-  a.nodes.nn = t->host.nnodes();
+  a.nodes = tree_nodes(t);
   a.theta = theta;
   a.theta_b = theta_b;
   a.pcnt = L.cnt;

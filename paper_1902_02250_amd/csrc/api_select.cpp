@@ -24,11 +24,7 @@ void compute_features(bltc_tree t, bltc_targets g, int kernel, double eps,
   a.bgeo = g->d_bgeo;
   a.bptr = g->d_bptr;
   a.nb = g->nb;
-  a.nodes.geo = t->d_geo;
-  a.nodes.range = t->d_range;
-  a.nodes.kids = t->d_kids;
-  a.nodes.skip = t->d_skip;
-  a.nodes.nn = t->host.nnodes();
+  a.nodes = tree_nodes(t);
   a.box = t->d_box;
   a.theta_ref = theta_ref;
   a.eps = eps;
@@ -91,11 +87,7 @@ void candidate_costs(bltc_tree t, bltc_targets g, int k, const int32_t* cand_n,
     std::memset(&a, 0, sizeof a);
     a.bgeo = g->d_bgeo;
     a.nb = g->nb;
-    a.nodes.geo = t->d_geo;
-    a.nodes.range = t->d_range;
-    a.nodes.kids = t->d_kids;
-  a.nodes.skip = t->d_skip;
-    a.nodes.nn = t->host.nnodes();
+    a.nodes = tree_nodes(t);
     a.ngroups = (int32_t)std::min<size_t>(bltc::kMaxThetaGroups, groups.size() - g0);
     for (int i = 0; i < a.ngroups; ++i) a.grp[i] = groups[g0 + i];
     a.deg_min = deg_min;
@@ -140,11 +132,7 @@ void fallback_samples(bltc_tree t, bltc_targets g, int kernel, double eps, int f
   a.ns = g->nsamp;
   a.tx = g->d_x;
   a.m = g->m;
-  a.nodes.geo = t->d_geo;
-  a.nodes.range = t->d_range;
-  a.nodes.kids = t->d_kids;
-  a.nodes.skip = t->d_skip;
-  a.nodes.nn = t->host.nnodes();
+  a.nodes = tree_nodes(t);
   a.theta = fb_theta;
   a.grid = fd.grid;
   a.fh32 = fd.p2p32;

@@ -28,6 +28,7 @@ void destroy_tree(bltc_tree t) {
   for (auto& kv : t->spare_derived) destroy_degree(kv.second);
   dfree(t->d_perm); dfree(t->d_y); dfree(t->d_box); dfree(t->d_geo);
   dfree(t->d_range); dfree(t->d_kids); dfree(t->d_skip); dfree(t->d_w64); dfree(t->d_w32);
+  dfree(t->d_cut); dfree(t->d_cut_anc); dfree(t->d_cut_first);
   dfree(t->d_chunks); dfree(t->d_chunk_ptr); dfree(t->d_partial); dfree(t->d_parents);
   delete t->dual;
   delete t;
@@ -205,6 +206,55 @@ void build_tree(const double* x, const double* y, const double* z, int64_t n,
     if ((int64_t)parents.size() > off) t->parent_levels.push_back({off, (int64_t)parents.size() - off});
   }
 
+  // the cut for lane-shared walks: the shallowest depth (up to
+  // kCutMaxDepth) with at least 64 cut nodes, cut nodes in depth-first order
+  int32_t cut_depth = 0;
+  std::vector<int32_t> cut;
+  {
+    std::vector<int32_t> parent(nn, -1);
+    for (int64_t q = 0; q < nn; ++q)
+      for (int32_t k = 0; k < H.count[q]; ++k) parent[H.first[q] + k] = (int32_t)q;
+    auto collect = [&](int32_t L, std::vector<int32_t>& out) {
+      out.clear();
+      if (nn == 0) return;
+      std::vector<int32_t> st{0};
+      while (!st.empty()) {
+        const int32_t q = st.back();
+        st.pop_back();
+        if (H.level[q] == L || H.count[q] == 0) {
+          out.push_back(q);
+          continue;
+        }
+        for (int32_t k = H.count[q] - 1; k >= 0; --k) st.push_back(H.first[q] + k);
+      }
+    };
+    for (cut_depth = 0; cut_depth <= bltc::kCutMaxDepth; ++cut_depth) {
+      collect(cut_depth, cut);
+      if ((int64_t)cut.size() >= 64 || cut_depth >= H.depth || cut_depth == bltc::kCutMaxDepth)
+        break;
+    }
+    const int64_t nc = (int64_t)cut.size();
+    std::vector<int32_t> anc(nc * bltc::kCutMaxDepth, -1);
+    std::vector<uint32_t> first(nc, 0);
+    for (int64_t c = 0; c < nc; ++c) {
+      std::vector<int32_t> chain;
+      for (int32_t a = parent[cut[c]]; a >= 0; a = parent[a]) chain.push_back(a);
+      std::reverse(chain.begin(), chain.end());   // root first; depth = index
+      for (size_t j = 0; j < chain.size(); ++j) anc[c * bltc::kCutMaxDepth + j] = chain[j];
+      for (size_t j = 0; j < chain.size(); ++j) {
+        const bool prev_under = c > 0 && anc[(c - 1) * bltc::kCutMaxDepth + j] == chain[j];
+        if (!prev_under) first[c] |= 1u << j;
+      }
+    }
+    t->ncut = (int32_t)nc;
+    t->d_cut = dalloc<int32_t>(nc);
+    t->d_cut_anc = dalloc<int32_t>(nc * bltc::kCutMaxDepth);
+    t->d_cut_first = dalloc<uint32_t>(nc);
+    h2d(t->d_cut, cut.data(), nc, s);
+    h2d(t->d_cut_anc, anc.data(), anc.size(), s);
+    h2d(t->d_cut_first, first.data(), nc, s);
+  }
+
   t->d_box = dalloc<double>(6 * nn);
   t->d_geo = dalloc<double4>(nn);
   t->d_range = dalloc<int2>(nn);
@@ -347,6 +397,20 @@ const bltc_degree_data& ensure_derived(bltc_tree t, int d, int n, hipStream_t s)
     throw;
   }
   return t->derived[key] = e;
+}
+
+bltc::Nodes tree_nodes(bltc_tree t) {
+  bltc::Nodes n;
+  n.geo = t->d_geo;
+  n.range = t->d_range;
+  n.kids = t->d_kids;
+  n.skip = t->d_skip;
+  n.nn = t->host.nnodes();
+  n.cut = t->d_cut;
+  n.cut_anc = t->d_cut_anc;
+  n.cut_first = t->d_cut_first;
+  n.ncut = t->ncut;
+  return n;
 }
 
 void set_weights(bltc_tree t, const double* w, int wdim, hipStream_t s) {

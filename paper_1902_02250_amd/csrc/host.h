@@ -160,6 +160,8 @@ void build_tree(const double* x, const double* y, const double* z, int64_t n,
 void build_targets(const double* x, const double* y, const double* z, int64_t m, int32_t bs,
                    int32_t leaf, int64_t gmax, hipStream_t s, bltc_targets g);
 void set_weights(bltc_tree t, const double* w, int wdim, hipStream_t s);
+// The device node arrays of a tree, with its cut, for the walk kernels.
+bltc::Nodes tree_nodes(bltc_tree t);
 // Grid and modified weights of one degree, cached until the weights change.
 void ensure_degree(bltc_tree t, int degree, hipStream_t s);
 // Weights of degree d < n derived from those of degree n, cached under (d, n).

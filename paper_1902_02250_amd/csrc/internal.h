@@ -77,12 +77,23 @@ struct TreeLevelNode {
 constexpr int kTreeChunk = 8192;   // particles per work group in the tree build
 
 // ---- kernel launch arguments ----------------------------------------------
+// The cut of a tree for walks shared by a wave's lanes (walk.h): the
+// clusters at the cut depth and the shallower leaves, in depth-first order,
+// with each one's ancestors root first (at most kCutMaxDepth, -1 padded)
+// and, in bit j of cut_first, whether it is the first cut node under its
+// ancestor j.
+constexpr int kCutMaxDepth = 8;
+
 struct Nodes {                 // device node arrays
   const double4* geo;          // center xyz, radius
   const int2* range;           // particle range [begin, end) in tree order
   const int2* kids;            // first child, child count
   const int32_t* skip;         // next node in depth-first order after the subtree (-1: end)
   int64_t nn;
+  const int32_t* cut = nullptr;        // [ncut]
+  const int32_t* cut_anc = nullptr;    // [ncut][kCutMaxDepth]
+  const uint32_t* cut_first = nullptr; // [ncut]
+  int32_t ncut = 0;
 };
 
 // Separation rule for the degree of an accepted cluster: the smallest d in
@@ -370,6 +381,10 @@ struct bltc_tree_s {
   int2* d_range = nullptr;
   int2* d_kids = nullptr;
   int32_t* d_skip = nullptr;   // depth-first successor past each subtree
+  int32_t* d_cut = nullptr;    // the cut for lane-shared walks (see Nodes)
+  int32_t* d_cut_anc = nullptr;
+  uint32_t* d_cut_first = nullptr;
+  int32_t ncut = 0;
   // weights
   bool has_w = false;
   int32_t wdim = 3;            // weight components: 3, or 6 for force and torque

@@ -5,12 +5,21 @@
 
 #include "bltc.h"
 #include "internal.h"
+#include "walk.h"
 
 namespace bltc {
 
 namespace {
 
-// Features of batch b, from its geometry and one walk at theta_ref:
+constexpr int kSelWaves = 4;   // batches (waves) per work group of the walk kernels
+
+__device__ __forceinline__ double wave_sumd(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
+// Features of batch b, from its geometry and one walk at theta_ref (one
+// wave-shared walk, walk.h; the lanes' sums are added across the wave):
 //  0 log2 targets             1 log10 r_B / R0         2 log10 eps / R0
 //  3 log10 eps / r_B          4 log10(1 + proxy clusters)
 //  5 log10(1 + near sources)  6 log10(1 + near leaves)
@@ -19,8 +28,9 @@ namespace {
 //  9 log10 near-field density relative to the mean density
 // 10 kernel (0 Stokeslet, 1 rotlet)  11 log10 n
 // R0 is the root radius; lengths below 1e-12 R0 are floored.
-__global__ __launch_bounds__(128) void k_features(FeatArgs a) {
-  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(64 * kSelWaves) void k_features(FeatArgs a) {
+  const int lane = threadIdx.x & 63;
+  const int64_t b = (int64_t)blockIdx.x * kSelWaves + (threadIdx.x >> 6);
   if (b >= a.nb) return;
   const double4 g = a.bgeo[b];
   const double4 root = a.nodes.geo[0];
@@ -28,31 +38,26 @@ __global__ __launch_bounds__(128) void k_features(FeatArgs a) {
   const double tiny = 1e-12 * R0;
   const double th2 = a.theta_ref * a.theta_ref;
   double P = 0, L = 0, D = 0, slr = 0, stight = 0, vol = 0;
-  int32_t q = a.nodes.nn > 0 ? 0 : -1;
-  while (q >= 0) {
-    const double4 c = a.nodes.geo[q];
-    const double dx = g.x - c.x, dy = g.y - c.y, dz = g.z - c.z;
-    const double R2 = dx * dx + dy * dy + dz * dz;
-    const double rr = g.w + c.w;
-    if (R2 > 0.0 && rr * rr <= th2 * R2) {
-      P += 1;
-      slr += log10((c.w + tiny) / R0);
-      stight += rr / (a.theta_ref * sqrt(R2));
-      q = a.nodes.skip[q];
-      continue;
-    }
-    const int2 kd = a.nodes.kids[q];
-    if (kd.y == 0) {
-      const int2 rg = a.nodes.range[q];
-      L += 1;
-      D += rg.y - rg.x;
-      const double* bx = a.box + 6 * (int64_t)q;
-      vol += (bx[3] - bx[0] + tiny) * (bx[4] - bx[1] + tiny) * (bx[5] - bx[2] + tiny);
-      q = a.nodes.skip[q];
-      continue;
-    }
-    q = kd.x;
-  }
+  cut_walk(a.nodes, g, th2, lane,
+           [&](int32_t q, double R2, double rr) {
+             P += 1;
+             slr += log10((a.nodes.geo[q].w + tiny) / R0);
+             stight += rr / (a.theta_ref * sqrt(R2));
+           },
+           [&](int32_t q) {
+             const int2 rg = a.nodes.range[q];
+             L += 1;
+             D += rg.y - rg.x;
+             const double* bx = a.box + 6 * (int64_t)q;
+             vol += (bx[3] - bx[0] + tiny) * (bx[4] - bx[1] + tiny) * (bx[5] - bx[2] + tiny);
+           });
+  P = wave_sumd(P);
+  L = wave_sumd(L);
+  D = wave_sumd(D);
+  slr = wave_sumd(slr);
+  stight = wave_sumd(stight);
+  vol = wave_sumd(vol);
+  if (lane != 0) return;
   const double* rb = a.box;
   const double vroot = (rb[3] - rb[0] + tiny) * (rb[4] - rb[1] + tiny) * (rb[5] - rb[2] + tiny);
   const double mean_density = (double)(a.n_src > 0 ? a.n_src : 1) / vroot;
@@ -77,15 +82,16 @@ __global__ __launch_bounds__(128) void k_features(FeatArgs a) {
   }
 }
 
-// Modelled wave costs of the candidates (CostArgs): one walk per batch and
-// theta group (grid y); an accepted cluster at ratio^2 qq costs
+// Modelled wave costs of the candidates (CostArgs): one wave-shared walk
+// (walk.h) per batch and theta group (grid y); an accepted cluster at ratio^2 qq costs
 // (far n1 + row) n1^2 + clu with n1 - 1 the candidate's degree, or under the
 // separation rule the first d >= deg_min with qq <= T[d] (binary search on
 // the thresholds, which grow with d, staged in LDS).  The candidate loop is
 // unrolled to kMaxPerTheta so the sums stay in registers; the theta groups
 // run in one launch so their walks overlap.
-__global__ __launch_bounds__(128) void k_cand_costs(CostArgs a) {
-  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(64 * kSelWaves) void k_cand_costs(CostArgs a) {
+  const int lane = threadIdx.x & 63;
+  const int64_t b = (int64_t)blockIdx.x * kSelWaves + (threadIdx.x >> 6);
   const CostGroup& gr = a.grp[blockIdx.y];
   // the group's rule thresholds, one row per candidate
   __shared__ double sT[kMaxPerTheta][kMaxDegree + 1];
@@ -101,50 +107,42 @@ __global__ __launch_bounds__(128) void k_cand_costs(CostArgs a) {
 #pragma unroll
   for (int i = 0; i < kMaxPerTheta; ++i) far[i] = 0.f;
   double S = 0.0;
-  int32_t q = a.nodes.nn > 0 ? 0 : -1;
-  while (q >= 0) {
-    const double4 c = a.nodes.geo[q];
-    const double dx = g.x - c.x;
-    const double dy = g.y - c.y;
-    const double dz = g.z - c.z;
-    const double R2 = dx * dx + dy * dy + dz * dz;
-    const double rr = g.w + c.w;
-    if (R2 > 0.0 && rr * rr <= th2 * R2) {
-      const double qq = (rr * rr) / R2;
+  cut_walk(a.nodes, g, th2, lane,
+           [&](int32_t, double R2, double rr) {
+             const double qq = (rr * rr) / R2;
 #pragma unroll
-      for (int i = 0; i < kMaxPerTheta; ++i) {
-        if (i < gr.nc) {
-          const int n = gr.deg[i];
-          int d = n;
-          if (a.deg_min > 0 && a.deg_min < n) {
-            // the first d in [deg_min, n) with qq <= T[d], else n (T grows with d)
-            int lo = a.deg_min, hi = n;
-            while (lo < hi) {
-              const int mid = (lo + hi) >> 1;
-              if (qq <= sT[i][mid]) hi = mid;
-              else lo = mid + 1;
-            }
-            d = lo;
-          }
-          const float n1 = (float)(d + 1);
-          far[i] += (a.w.far * n1 + a.w.row) * n1 * n1 + a.w.clu;
-        }
-      }
-      q = a.nodes.skip[q];
-      continue;
-    }
-    const int2 kd = a.nodes.kids[q];
-    if (kd.y == 0) {
-      const int2 rg = a.nodes.range[q];
-      S += rg.y - rg.x;
-      q = a.nodes.skip[q];
-      continue;
-    }
-    q = kd.x;
-  }
+             for (int i = 0; i < kMaxPerTheta; ++i) {
+               if (i < gr.nc) {
+                 const int n = gr.deg[i];
+                 int d = n;
+                 if (a.deg_min > 0 && a.deg_min < n) {
+                   // the first d in [deg_min, n) with qq <= T[d], else n (T grows with d)
+                   int lo = a.deg_min, hi = n;
+                   while (lo < hi) {
+                     const int mid = (lo + hi) >> 1;
+                     if (qq <= sT[i][mid]) hi = mid;
+                     else lo = mid + 1;
+                   }
+                   d = lo;
+                 }
+                 const float n1 = (float)(d + 1);
+                 far[i] += (a.w.far * n1 + a.w.row) * n1 * n1 + a.w.clu;
+               }
+             }
+           },
+           [&](int32_t q) {
+             const int2 rg = a.nodes.range[q];
+             S += rg.y - rg.x;
+           });
+  S = wave_sumd(S);
 #pragma unroll
   for (int i = 0; i < kMaxPerTheta; ++i)
-    if (i < gr.nc) a.cost[(int64_t)gr.row[i] * a.nb + b] = far[i] + (float)S * a.w.nearf;
+    for (int off = 32; off > 0; off >>= 1) far[i] += __shfl_xor(far[i], off);
+  if (lane == 0) {
+#pragma unroll
+    for (int i = 0; i < kMaxPerTheta; ++i)
+      if (i < gr.nc) a.cost[(int64_t)gr.row[i] * a.nb + b] = far[i] + (float)S * a.w.nearf;
+  }
 }
 
 // e2[j][b] = 10^(2 Y[b][j]): the predicted squared relative errors.
@@ -333,7 +331,8 @@ __global__ void k_fill_i32(int32_t* __restrict__ p, int64_t n, int32_t v) {
 
 hipError_t launch_features(const FeatArgs& a, hipStream_t s) {
   if (a.nb == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_features, dim3((unsigned)((a.nb + 127) / 128)), dim3(128), 0, s, a);
+  hipLaunchKernelGGL(k_features, dim3((unsigned)((a.nb + kSelWaves - 1) / kSelWaves)),
+                     dim3(64 * kSelWaves), 0, s, a);
   return hipGetLastError();
 }
 
@@ -406,8 +405,9 @@ hipError_t launch_flag(int ns, const double* contrib, double thr, int32_t* flag,
 hipError_t launch_cand_costs(const CostArgs& a, hipStream_t s) {
   if (a.nb == 0) return hipSuccess;
   if (a.ngroups < 1 || a.ngroups > kMaxThetaGroups) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_cand_costs, dim3((unsigned)((a.nb + 127) / 128), (unsigned)a.ngroups),
-                     dim3(128), 0, s, a);
+  hipLaunchKernelGGL(k_cand_costs,
+                     dim3((unsigned)((a.nb + kSelWaves - 1) / kSelWaves), (unsigned)a.ngroups),
+                     dim3(64 * kSelWaves), 0, s, a);
   return hipGetLastError();
 }
 

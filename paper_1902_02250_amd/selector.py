@@ -27,7 +27,7 @@ import numpy as np
 from . import bltc, inputs
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-MODEL_PATH = os.path.join(HERE, "data", "selector_v1.bin")
+MODEL_PATH = os.path.join(HERE, "data", "selector_v2.bin")
 
 CAND_N = tuple(range(2, 13))
 CAND_THETA = (0.4, 0.5, 0.6, 0.7, 0.8, 0.9)
@@ -44,6 +44,7 @@ DEG_MIN = 1                # the candidates are evaluated with the separation ru
 LOG_FLOOR = -12.0          # labels are log10(max(error, 1e-12))
 SAMPLES_PER_BATCH = 8
 TRAIN_SEEDS = range(0, 200)
+ORDER_LEAF = 0             # target batches: balanced k-d (bltc_build_targets)
 
 
 # ---- model file -------------------------------------------------------------------
@@ -111,7 +112,7 @@ def label_run(cfg, log=print):
     d_src = torch.from_numpy(src).to(dev)
     d_w = torch.from_numpy(w).to(dev)
     tree = bltc.Tree(d_src, cfg["leaf"])
-    tg = bltc.Targets(d_src, 64, 32, 512)
+    tg = bltc.Targets(d_src, 64, ORDER_LEAF, 512)
     kernel, eps = cfg["kernel"], cfg["eps"]
     X = bltc.batch_features(tree, tg, kernel, eps, THETA_REF).cpu().numpy()
     ex = tg.export()
@@ -357,7 +358,7 @@ def compare(workload, model=MODEL_PATH, tol=None, fb=(10, 0.6), reps=2, n=None, 
     w = inputs.weights_for(cfg["dist"], cfg["n"], cfg["seed"])
     d_src, d_w = torch.from_numpy(src).to(dev), torch.from_numpy(w).to(dev)
     tree = bltc.Tree(d_src, cfg["leaf"])
-    tg = bltc.Targets(d_src, 64, 32, 512)
+    tg = bltc.Targets(d_src, 64, ORDER_LEAF, 512)
     kernel, eps = cfg["kernel"], cfg["eps"]
     idx = inputs.sample_indices(cfg["n"], min(10000, cfg["n"]), cfg["seed"] + 11)
     d_idx = torch.from_numpy(idx).to(dev)
@@ -441,7 +442,7 @@ def main(argv=None):
     ap = argparse.ArgumentParser(description="train the selector, or compare it with fixed "
                                              "(n, theta) on a workload")
     ap.add_argument("--data", default="gpurun_out/selector_runs.npz")
-    ap.add_argument("--model", default="gpurun_out/selector_v1.bin")
+    ap.add_argument("--model", default="gpurun_out/selector_v2.bin")
     ap.add_argument("--runs", type=int, default=200)
     ap.add_argument("--seeds", default=None, help="first:last training seeds to label")
     ap.add_argument("--label-only", action="store_true", help="label and save, no training")
