@@ -378,8 +378,8 @@ int bltc_selector_info(bltc_selector sel, int32_t* k, int32_t* cand_n,
  * checks): the fixed treecode of Algorithm 2 with degree fb_degree and the
  * paper's per-target MAC r/R <= fb_theta (eq. MAC), each sample target
  * walked on its own from the root, FP32 kernel evaluation with FP64 sums.
- * The samples are one target per two batches, at a hashed position inside
- * the first batch of each pair (fixed by the targets handle).  Computes the
+ * The samples are one target per batch, at a hashed position inside the
+ * batch (fixed by the targets handle).  Computes the
  * modified weights of fb_degree when missing.  *n_samples receives their
  * number; target_idx (host int64 [n_samples], caller's target order) and
  * ufb (host FP64 [n_samples][odim]) may be NULL (then nothing is
@@ -395,11 +395,10 @@ int bltc_judge_samples(bltc_tree t, bltc_targets g, int32_t kernel, double eps,
  *  1. The network predicts e_b(j), the relative error of batch b under each
  *     candidate j; bltc_batch_costs gives its modelled wave cost with the
  *     model's cost weights, under the model's separation rule (deg_min).
- *  2. The judge: one target in every second batch is evaluated with the
- *     fallback treecode (fb_degree, fb_theta) as bltc_judge_samples does
- *     (Algorithm 2 with the per-target MAC); w_b = targets_b |u_fb|^2 (the
- *     sample of b's pair of batches) estimates the batch's share of the
- *     reference norm.
+ *  2. The judge: one target in every batch is evaluated with the fallback
+ *     treecode (fb_degree, fb_theta) as bltc_judge_samples does (Algorithm 2
+ *     with the per-target MAC); w_b = targets_b |u_fb|^2 (at b's sample)
+ *     estimates the batch's share of the reference norm.
  *  3. mode BLTC_SELECT_BATCH: the batches share the error budget: the
  *     choice minimises the total cost subject to
  *     sum_b w_b e_b^2 <= tau^2 sum_b w_b, tau = tol 10^-margin, through the
@@ -413,10 +412,12 @@ int bltc_judge_samples(bltc_tree t, bltc_targets g, int32_t kernel, double eps,
  *     equals the fixed evaluation at its candidate); evaluation grouped by
  *     the batches' top degrees, the groups running concurrently.
  *  5. The judge's estimate E^2 = sum_i G_i |u - u_fb|^2 / sum_i G_i |u_fb|^2
- *     over the samples (G_i the targets the sample stands for); when it
- *     exceeds tol^2, the samples with the largest terms, just enough of
- *     them to bring the estimate to (0.8 tol)^2, have their batches evaluated
- *     again with the fallback (its batch walk at fb_theta).
+ *     over the samples (G_i the targets of sample i's batch); when it
+ *     exceeds (0.8 tol)^2, the samples with the largest terms, just enough
+ *     of them to bring the estimate to (0.6 tol)^2, have their batches
+ *     evaluated again with the fallback (its batch walk at fb_theta).  The
+ *     estimate is a sample: the margins make a result above tol unlikely,
+ *     not impossible.
  * choice (host int32 [nb], may be NULL): candidate index, or -2 for a batch
  * the judge sent to the fallback.  stats (host int64 [4], may be NULL):
  * batches, distinct degrees, batches re-evaluated, 0.  judge (host double

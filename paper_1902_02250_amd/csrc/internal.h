@@ -17,7 +17,7 @@ constexpr int kUpwardChunk = 512;    // particles per upward-pass work group
 constexpr int kMlpIn = 12;           // selector network: features
 constexpr int kMlpHidden = 64;       // selector network: hidden width
 constexpr int kMlpMaxOut = 128;      // selector network: most candidates
-constexpr int kJudgeStride = 2;      // batches per judge sample
+constexpr int kJudgeStride = 1;      // batches per judge sample
 // A proxy-list entry holds the cluster id in its low kDegShift bits and,
 // under the separation rule, the cluster's degree above them (0: the
 // evaluation's degree).

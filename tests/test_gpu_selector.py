@@ -27,20 +27,23 @@ def _d(torch, a):
     return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
 
 
-@pytest.fixture(scope="module")
-def case(torch):
+@pytest.fixture(scope="module", params=[0, 32], ids=["kd", "leaf32"])
+def case(torch, request):
+    """Clustered points, batched by the balanced k-d rule (the default) and
+    by an order tree with leaves of 32."""
+    ol = request.param
     src = inputs.points("mixture", 30000, 71)
     w = inputs.weights(30000, 71)
     T = bltc.Tree(_d(torch, src), 300)
     T.compute_weights(_d(torch, w), 4)
-    G = bltc.Targets(_d(torch, src), 64, 32, 512)
-    return dict(src=src, w=w, T=T, G=G, d_w=_d(torch, w))
+    G = bltc.Targets(_d(torch, src), 64, ol, 512)
+    return dict(src=src, w=w, T=T, G=G, d_w=_d(torch, w), ol=ol)
 
 
 def test_counts_match_oracle_lists(torch, orc, case):
     for theta in (0.4, 0.7, 0.9):
         pc, sc = bltc.batch_counts(case["T"], case["G"], theta)
-        L = orc.lists(case["src"], 300, case["src"], theta, 64, 32, 512)
+        L = orc.lists(case["src"], 300, case["src"], theta, 64, case["ol"], 512)
         R = orc.Tree(case["src"], 300)
         np_ = np.diff(L["prox_ptr"])
         sizes = R.pend - R.pbegin
@@ -55,8 +58,8 @@ def test_features_match_oracle(torch, orc, case):
     f = bltc.batch_features(case["T"], case["G"], "rotlet", eps, th).cpu().numpy()
     src = case["src"]
     R = orc.Tree(src, 300)
-    L = orc.lists(src, 300, src, th, 64, 32, 512)
-    tperm, bptr, bc, br = orc.batches(src, 64, 32, 512)
+    L = orc.lists(src, 300, src, th, 64, case["ol"], 512)
+    tperm, bptr, bc, br = orc.batches(src, 64, case["ol"], 512)
     R0 = R.radius[0]
     tiny = 1e-12 * R0
     lo, hi = R.box[0, :3], R.box[0, 3:]
@@ -85,7 +88,7 @@ def test_batch_costs_match_oracle_lists(torch, orc, case, deg_min):
     R = orc.Tree(case["src"], 300)
     sizes = R.pend - R.pbegin
     for j, (n, th) in enumerate(cands):
-        L = orc.lists(case["src"], 300, case["src"], th, 64, 32, 512, degree=n,
+        L = orc.lists(case["src"], 300, case["src"], th, 64, case["ol"], 512, degree=n,
                       deg_min=deg_min)
         pp, dp = L["prox_ptr"], L["dir_ptr"]
         n1 = (L["prox_deg"] + 1).astype(np.float64)
@@ -204,14 +207,15 @@ def test_trained_selector_gain(torch, dist, kernel, tol):
     workload outside its training runs, the learned evaluation meets the
     requested global error against the FP64 direct sum, at a modelled cost
     well below that of the fixed fallback that would otherwise be used to be
-    safe at this tolerance (n = 10, theta = 0.6)."""
+    safe at this tolerance (n = 10, theta = 0.6).  The targets are batched
+    by the balanced k-d rule, the batching the network was trained on."""
     n = 150000
     src = inputs.points(dist, n, 4242)
     w = inputs.weights(n, 4242)
     d_src, d_w = _d(torch, src), _d(torch, w)
     T = bltc.Tree(d_src, 1000)
     T.compute_weights(d_w, 10)
-    G = bltc.Targets(d_src, 64, 32, 512)
+    G = bltc.Targets(d_src)
     sel = bltc.Selector(selector.MODEL_PATH)
     out, choice, stats, judge = bltc.evaluate_adaptive(T, G, kernel, 0.005, sel, tol, 10, 0.6)
     idx = torch.from_numpy(inputs.sample_indices(n, 3000, 7)).cuda()
@@ -227,10 +231,10 @@ def test_trained_selector_gain(torch, dist, kernel, tol):
     assert learned < 0.6 * c_fb.sum(), (learned, c_fb.sum())
 
 
-@pytest.mark.parametrize("kernel,dist,fb", [("stokeslet", "mixture", (10, 0.6)),
-                                            ("rotlet", "union", (8, 0.7)),
-                                            ("stokeslet", "uniform", (12, 0.5))])
-def test_judge_samples_match_oracle(torch, orc, kernel, dist, fb):
+@pytest.mark.parametrize("kernel,dist,fb,ol", [("stokeslet", "mixture", (10, 0.6), 0),
+                                               ("rotlet", "union", (8, 0.7), 32),
+                                               ("stokeslet", "uniform", (12, 0.5), 0)])
+def test_judge_samples_match_oracle(torch, orc, kernel, dist, fb, ol):
     """The judge is the fixed treecode of Algorithm 2: every sampled value
     against the oracle's treecode with the paper's per-target MAC at the same
     target (FP32 evaluation: 1e-6 relative L2, 1e-5 per target)."""
@@ -239,9 +243,9 @@ def test_judge_samples_match_oracle(torch, orc, kernel, dist, fb):
     w = inputs.weights(n, 81)
     T = bltc.Tree(_d(torch, src), leaf)
     T.compute_weights(_d(torch, w), 4)
-    G = bltc.Targets(_d(torch, src), 64, 32, 512)
+    G = bltc.Targets(_d(torch, src), 64, ol, 512)
     idx, u = bltc.judge_samples(T, G, kernel, eps, fb[0], fb[1])
-    assert idx.size == (G.nb + 1) // 2 and np.unique(idx).size == idx.size
+    assert idx.size == G.nb and np.unique(idx).size == idx.size
     ref, _, _ = orc.treecode(kernel, src, src, w, eps, fb[0], fb[1], leaf, mac_mode=0,
                              sample=idx)
     close(orc, ref, u, 1e-6, elem_tol=1e-5, what=f"judge {kernel} {dist} {fb}")
@@ -252,8 +256,15 @@ def test_adaptive_matches_oracle_per_candidate(torch, orc, tmp_path, case):
     at 30,000 points) at a tolerance that mixes candidates: the targets of
     every batch are compared with the oracle's treecode at that batch's
     chosen (n, theta) under the model's separation rule, or at the fallback
-    for batches the judge re-evaluated (FP32 evaluation: 1e-6 relative L2,
-    1e-4 per target)."""
+    for batches the judge re-evaluated.  The comparison runs in FP64 (1e-12
+    relative L2, 1e-10 per target), which shows every batch's lists, degrees
+    and modified weights are its candidate's; the FP32 evaluation of the
+    same choices is then held to the FP32 bar against it over all targets
+    (1e-6 relative L2).  FP32 is not compared batch by batch: inside the
+    dense clusters the rotlet sums of an isotropic neighbourhood cancel, so
+    the rounding of x - y relative to a batch's centre, up to 2^-24 times the
+    batch radius over max(r, eps) of each term, reaches about 1e-6 of the
+    cancelled sum there (4e-7 over all targets)."""
     k = selector.K
     p = selector.glorot(k, seed=4)
     p[-k:] = np.random.default_rng(5).uniform(-6.0, -4.0, k)
@@ -264,14 +275,23 @@ def test_adaptive_matches_oracle_per_candidate(torch, orc, tmp_path, case):
     fb = (8, 0.6)
     for tol in (1e-5, 1e-6, 1e-4):
         out, choice, stats, judge = bltc.evaluate_adaptive(case["T"], case["G"], "rotlet",
-                                                           0.01, sel, tol, fb[0], fb[1])
+                                                           0.01, sel, tol, fb[0], fb[1],
+                                                           precision="fp64")
         used = sorted(set(choice.tolist()))
         if len([u for u in used if u >= 0]) >= 2:
             break
     assert len([u for u in used if u >= 0]) >= 2, used
     out = out.cpu().numpy()
+    o32, c32, _, _ = bltc.evaluate_adaptive(case["T"], case["G"], "rotlet", 0.01, sel, tol,
+                                            fb[0], fb[1])
     src, w = case["src"], case["w"]
     ex = case["G"].export()
+    # the judge's choice of batches to re-evaluate reads the evaluation, so a
+    # batch at its threshold may go either way: compare where the two agree
+    same = np.where(c32 == choice)[0]
+    assert same.size >= 0.9 * choice.size
+    ts = np.concatenate([ex["tperm"][ex["bptr"][b]:ex["bptr"][b + 1]] for b in same])
+    close(orc, out[:, ts], o32.cpu().numpy()[:, ts], 1e-6, what="adaptive FP32 against FP64")
     counts = {u: int(np.sum(choice == u)) for u in used}
     # the most used candidates, the least used one and the fallback's batches
     picks = sorted([u for u in used if u >= 0], key=lambda u: -counts[u])[:4]
@@ -285,7 +305,7 @@ def test_adaptive_matches_oracle_per_candidate(torch, orc, tmp_path, case):
         n_u, th_u = selector.CANDIDATES[u] if u >= 0 else fb
         dm = selector.DEG_MIN if u >= 0 else 0
         ref, _, _ = orc.treecode("rotlet", src, src, w, 0.01, n_u, th_u, 300, mac_mode=1,
-                                 batch_size=64, order_leaf=32, group_max=512, sample=idx,
+                                 batch_size=64, order_leaf=case["ol"], group_max=512, sample=idx,
                                  deg_min=dm)
-        close(orc, ref, out[:, idx], 1e-6, what=f"adaptive candidate {u} ({n_u}, {th_u}) "
-                                                f"deg_min {dm}, {bs.size} batches")
+        close(orc, ref, out[:, idx], 1e-12, elem_tol=1e-10,
+              what=f"adaptive candidate {u} ({n_u}, {th_u}) deg_min {dm}, {bs.size} batches")
