@@ -379,7 +379,8 @@ int bltc_selector_info(bltc_selector sel, int32_t* k, int32_t* cand_n,
  * paper's per-target MAC r/R <= fb_theta (eq. MAC), each sample target
  * walked on its own from the root, FP32 kernel evaluation with FP64 sums.
  * The samples are one target per batch, at a hashed position inside the
- * batch (fixed by the targets handle).  Computes the
+ * batch (fixed by the targets handle); from 32,768 batches on, one per
+ * floor(nb / 16384) consecutive batches, in the first of them.  Computes the
  * modified weights of fb_degree when missing.  *n_samples receives their
  * number; target_idx (host int64 [n_samples], caller's target order) and
  * ufb (host FP64 [n_samples][odim]) may be NULL (then nothing is
@@ -395,9 +396,10 @@ int bltc_judge_samples(bltc_tree t, bltc_targets g, int32_t kernel, double eps,
  *  1. The network predicts e_b(j), the relative error of batch b under each
  *     candidate j; bltc_batch_costs gives its modelled wave cost with the
  *     model's cost weights, under the model's separation rule (deg_min).
- *  2. The judge: one target in every batch is evaluated with the fallback
- *     treecode (fb_degree, fb_theta) as bltc_judge_samples does (Algorithm 2
- *     with the per-target MAC); w_b = targets_b |u_fb|^2 (at b's sample)
+ *  2. The judge: the samples of bltc_judge_samples (one target per batch,
+ *     or per group of batches when there are many) are evaluated with the
+ *     fallback treecode (fb_degree, fb_theta) (Algorithm 2 with the
+ *     per-target MAC); w_b = targets_b |u_fb|^2 (at the sample of b's group)
  *     estimates the batch's share of the reference norm.
  *  3. mode BLTC_SELECT_BATCH: the batches share the error budget: the
  *     choice minimises the total cost subject to
@@ -412,7 +414,7 @@ int bltc_judge_samples(bltc_tree t, bltc_targets g, int32_t kernel, double eps,
  *     equals the fixed evaluation at its candidate); evaluation grouped by
  *     the batches' top degrees, the groups running concurrently.
  *  5. The judge's estimate E^2 = sum_i G_i |u - u_fb|^2 / sum_i G_i |u_fb|^2
- *     over the samples (G_i the targets of sample i's batch); when it
+ *     over the samples (G_i the targets of sample i's group); when it
  *     exceeds (0.8 tol)^2, the samples with the largest terms, just enough
  *     of them to bring the estimate to (0.6 tol)^2, have their batches
  *     evaluated again with the fallback (its batch walk at fb_theta).  The

@@ -82,6 +82,52 @@ void candidate_costs(bltc_tree t, bltc_targets g, int k, const int32_t* cand_n,
     }
     groups.push_back(gr);
   }
+  // each group's distinct thresholds U (sorted) and bucket costs C[i][k]:
+  // candidate i's degree for qq in bucket k (U[k-1] < qq <= U[k]) is the
+  // first d in [deg_min, n_i) with T_i[d] >= U[k] (qq <= T_i[d] exactly
+  // then), else n_i; bucket nu (qq above every threshold) takes n_i
+  std::vector<double> U;
+  std::vector<float> C;
+  for (bltc::CostGroup& gr : groups) {
+    std::vector<bltc::Rule> rules(gr.nc);
+    std::vector<double> u;
+    for (int i = 0; i < gr.nc; ++i) {
+      rules[i] = make_rule(gr.theta, gr.deg[i], deg_min);
+      for (int d = rules[i].deg_min; d < rules[i].degree; ++d) u.push_back(rules[i].T[d]);
+    }
+    std::sort(u.begin(), u.end());
+    u.erase(std::unique(u.begin(), u.end()), u.end());
+    gr.nu = (int32_t)u.size();
+    gr.u_off = (int32_t)U.size();
+    gr.c_off = (int32_t)C.size();
+    U.insert(U.end(), u.begin(), u.end());
+    for (int i = 0; i < gr.nc; ++i) {
+      for (int kb = 0; kb <= gr.nu; ++kb) {
+        int d = gr.deg[i];
+        if (kb < gr.nu) {
+          for (int dd = rules[i].deg_min; dd < rules[i].degree; ++dd)
+            if (rules[i].T[dd] >= u[kb]) {
+              d = dd;
+              break;
+            }
+        }
+        const float n1 = (float)(d + 1);
+        C.push_back((w.far * n1 + w.row) * n1 * n1 + w.clu);
+      }
+    }
+  }
+  const size_t ub = (U.size() * sizeof(double) + 255) / 256 * 256;
+  const size_t need = ub + C.size() * sizeof(float);
+  if ((int64_t)need > g->costtab_cap) {
+    dfree(g->d_costtab);
+    g->costtab_cap = 0;
+    g->d_costtab = dalloc_bytes(need);
+    g->costtab_cap = (int64_t)need;
+  }
+  double* dU = static_cast<double*>(g->d_costtab);
+  float* dC = reinterpret_cast<float*>(static_cast<char*>(g->d_costtab) + ub);
+  h2d(dU, U.data(), U.size(), s);
+  h2d(dC, C.data(), C.size(), s);
   for (size_t g0 = 0; g0 < groups.size(); g0 += bltc::kMaxThetaGroups) {
     bltc::CostArgs a;
     std::memset(&a, 0, sizeof a);
@@ -90,34 +136,89 @@ void candidate_costs(bltc_tree t, bltc_targets g, int k, const int32_t* cand_n,
     a.nodes = tree_nodes(t);
     a.ngroups = (int32_t)std::min<size_t>(bltc::kMaxThetaGroups, groups.size() - g0);
     for (int i = 0; i < a.ngroups; ++i) a.grp[i] = groups[g0 + i];
-    a.deg_min = deg_min;
-    a.T = g->d_candT;
-    a.w = w;
+    a.U = dU;
+    a.C = dC;
+    a.nearf = w.nearf;
     a.cost = cost;
     a.err = g->d_flags;
     hipchk(bltc::launch_cand_costs(a, s), "candidate costs");
   }
 }
 
-// The judge's sample targets: one per kJudgeStride batches, at a hashed
-// position inside the first batch of its group; their fallback values go
-// to g->d_ufb.
+// The judge's sample targets: one per judge_stride(nb) batches, at a hashed
+// position inside the first batch of its group, and their geometry as
+// batches of one target; their fallback values go to g->d_ufb.
 void ensure_judge_samples(bltc_targets g) {
   if (g->nsamp > 0) return;
   const int64_t nb = g->nb;
-  const int64_t ns = (nb + bltc::kJudgeStride - 1) / bltc::kJudgeStride;
+  const int st = bltc::judge_stride(nb);
+  const int64_t ns = (nb + st - 1) / st;
   ensure_alloc(g->d_ufb, 6 * ns);
   ensure_alloc(g->d_spos, ns);
+  ensure_alloc(g->d_sgeo, ns);
+  ensure_alloc(g->d_sflags, 4);
+  bltc::ListSet& L = g->ls_samp;
+  ensure_alloc(L.cnt, 3 * ns);
+  ensure_alloc(L.ptr, 2 * (ns + 1));
   std::vector<int32_t> sp(ns);
   for (int64_t i = 0; i < ns; ++i) {
-    const int64_t b = i * bltc::kJudgeStride;
+    const int64_t b = i * st;
     const int32_t b0 = g->host.bptr[b], cnt = g->host.bptr[b + 1] - b0;
     const uint32_t h = (uint32_t)(b * 2654435761ull >> 7);
     sp[i] = b0 + (int32_t)(h % (uint32_t)cnt);
   }
   h2d(g->d_spos, sp.data(), ns, nullptr);
+  hipchk(bltc::launch_sample_geo(g->d_spos, (int)ns, g->d_x, g->m, g->d_sgeo, nullptr),
+         "sample geometry");
+  hipchk(bltc::launch_fill_i32(g->d_sflags, 4, 0, nullptr), "clear flags");
   sync(nullptr);
+  g->sstride = st;
   g->nsamp = (int32_t)ns;   // last: a failed allocation leaves it 0
+}
+
+// The samples' lists: the batch walk of every sample (a batch of one target
+// at radius 0, so the batch MAC is the per-target MAC) at fb_theta.
+void sample_lists(bltc_tree t, bltc_targets g, double fb_theta, hipStream_t s) {
+  const int64_t ns = g->nsamp;
+  bltc::ListSet& L = g->ls_samp;
+  bltc::ListArgs a;
+  a.bgeo = g->d_sgeo;
+  a.nb = ns;
+  a.nodes = tree_nodes(t);
+  a.theta = fb_theta;
+  a.pcnt = L.cnt;
+  a.dcnt = L.cnt + ns;
+  a.scnt = L.cnt + 2 * ns;
+  a.pptr = L.ptr;
+  a.dptr = L.ptr + ns + 1;
+  a.pids = nullptr;
+  a.dids = nullptr;
+  a.err = g->d_sflags;
+  hipchk(bltc::launch_lists(a, false, s), "sample list count");
+  hipchk(bltc::launch_exclusive_scan(a.pcnt, ns, L.ptr, g->d_sflags + 1, s), "scan");
+  hipchk(bltc::launch_exclusive_scan(a.dcnt, ns, L.ptr + ns + 1, g->d_sflags + 2, s), "scan");
+  int32_t tot[2], flags[4];
+  d2h(&tot[0], L.ptr + ns, 1, s);
+  d2h(&tot[1], L.ptr + 2 * ns + 1, 1, s);
+  d2h(flags, g->d_sflags, 4, s);
+  sync(s);
+  if (flags[0] || flags[1] || flags[2])
+    throw HipError{BLTC_EDEVICE, "the judge samples' lists overflowed"};
+  if (tot[0] > L.pcap) {
+    dfree(L.pids);
+    L.pcap = 0;
+    L.pids = dalloc<int32_t>(tot[0]);
+    L.pcap = tot[0];
+  }
+  if (tot[1] > L.dcap) {
+    dfree(L.dids);
+    L.dcap = 0;
+    L.dids = dalloc<int32_t>(tot[1]);
+    L.dcap = tot[1];
+  }
+  a.pids = L.pids;
+  a.dids = L.dids;
+  hipchk(bltc::launch_lists(a, true, s), "sample list fill");
 }
 
 // The fallback treecode (fb_degree, fb_theta) at the judge's samples, into
@@ -126,14 +227,19 @@ void fallback_samples(bltc_tree t, bltc_targets g, int kernel, double eps, int f
                       double fb_theta, hipStream_t s) {
   ensure_judge_samples(g);
   ensure_degree(t, fb_degree, s);
+  sample_lists(t, g, fb_theta, s);
   const bltc_degree_data& fd = t->deg.at(fb_degree);
+  const int64_t ns = g->nsamp;
   bltc::SampleArgs a;
   a.spos = g->d_spos;
   a.ns = g->nsamp;
   a.tx = g->d_x;
   a.m = g->m;
-  a.nodes = tree_nodes(t);
-  a.theta = fb_theta;
+  a.range = tree_nodes(t).range;
+  a.pptr = g->ls_samp.ptr;
+  a.pids = g->ls_samp.pids;
+  a.dptr = g->ls_samp.ptr + ns + 1;
+  a.dids = g->ls_samp.dids;
   a.grid = fd.grid;
   a.fh32 = fd.p2p32;
   a.ys = t->d_y;
@@ -182,7 +288,7 @@ void ensure_selection_scratch(bltc_targets g, int64_t k) {
 // sample per batch; `out` NULL gives the weights only.
 void judge_sums(bltc_targets g, int kernel, const double* out, double sums[2],
                 hipStream_t s) {
-  hipchk(bltc::launch_judge(g->nsamp, bltc::kJudgeStride, g->nb, g->d_bptr, g->d_spos,
+  hipchk(bltc::launch_judge(g->nsamp, g->sstride, g->nb, g->d_bptr, g->d_spos,
                             g->d_tperm, out, g->m, odim_of(kernel), g->d_ufb, g->d_usq,
                             g->d_contrib, g->d_part, g->d_sums, s),
          "judge");
@@ -208,17 +314,9 @@ void evaluate_adaptive(bltc_tree t, bltc_targets g, int kernel, double eps,
                           (float)sel->cost_near};
   ensure_selection_scratch(g, k);
 
-  // 2. (first, on a library stream, concurrent with step 1: the two are
-  //    independent) the judge: the fallback treecode (Algorithm 2 with the
-  //    per-target MAC) at one sample per pair of batches
   Events evs;
   hipEvent_t start = evs.make();
   hipchk(hipEventRecord(start, s), "hipEventRecord");
-  hipStream_t jstream = side_stream(0);
-  hipchk(hipStreamWaitEvent(jstream, start, 0), "hipStreamWaitEvent");
-  fallback_samples(t, g, kernel, eps, fb_degree, fb_theta, jstream);
-  hipEvent_t judged = evs.make();
-  hipchk(hipEventRecord(judged, jstream), "hipEventRecord");
 
   // 1. predicted log10 errors of every candidate, and their modelled costs
   compute_features(t, g, kernel, eps, sel->theta_ref, sel->d_mean, sel->d_std, g->d_feat, s);
@@ -227,11 +325,21 @@ void evaluate_adaptive(bltc_tree t, bltc_targets g, int kernel, double eps,
   candidate_costs(t, g, k, sel->cand_n.data(), sel->cand_theta.data(), rule_min, costs,
                   g->d_cost, s);
   hipchk(bltc::launch_pred_err2(g->d_Y, k, nb, g->d_e2, s), "predicted errors");
+
+  // 2. on a library stream, concurrent with step 1 (the two are independent;
+  //    enqueued second because sizing the samples' lists waits on the host),
+  //    the judge: the fallback treecode (Algorithm 2 with the per-target MAC)
+  //    at one sample per judge_stride(nb) batches
+  hipStream_t jstream = side_stream(0);
+  hipchk(hipStreamWaitEvent(jstream, start, 0), "hipStreamWaitEvent");
+  fallback_samples(t, g, kernel, eps, fb_degree, fb_theta, jstream);
+  hipEvent_t judged = evs.make();
+  hipchk(hipEventRecord(judged, jstream), "hipEventRecord");
   hipchk(hipStreamWaitEvent(s, judged, 0), "hipStreamWaitEvent");
 
   double ws[2];
   judge_sums(g, kernel, nullptr, ws, s);
-  hipchk(bltc::launch_batch_weights(nb, bltc::kJudgeStride, g->d_bptr, g->d_usq, g->d_wt, s),
+  hipchk(bltc::launch_batch_weights(nb, g->sstride, g->d_bptr, g->d_usq, g->d_wt, s),
          "batch weights");
   const double wsum = ws[0];
 
@@ -387,8 +495,8 @@ void evaluate_adaptive(bltc_tree t, bltc_targets g, int kernel, double eps,
     for (int32_t i : ord) {
       if (rest <= 0.36 * tol * tol * wsum) break;
       rest -= c[i];
-      for (int64_t b = (int64_t)i * bltc::kJudgeStride;
-           b < std::min<int64_t>(nb, (int64_t)(i + 1) * bltc::kJudgeStride); ++b) {
+      for (int64_t b = (int64_t)i * g->sstride;
+           b < std::min<int64_t>(nb, (int64_t)(i + 1) * g->sstride); ++b) {
         redo.push_back((int32_t)b);
         choice[b] = -2;
       }
@@ -400,22 +508,45 @@ void evaluate_adaptive(bltc_tree t, bltc_targets g, int kernel, double eps,
       build_lists(t, g, fb_theta, nullptr, g->ls[1], s, &np, &nd);
       h2d(g->d_bmap, redo.data(), redo.size(), s);
       if (g->batch_size <= bltc::kWave) {
-        // few batches: each batch's proxy list is cut into slices that run
-        // as separate waves (the direct list goes with the first slice);
-        // the slices' FP64 sums are added in slice order
-        std::vector<int32_t> lp(nb + 1);
-        d2h(lp.data(), g->ls[1].ptr, nb + 1, s);
+        // few batches: each batch's proxy list and its direct list are cut
+        // into slices that run as separate waves (about 4096 of each over
+        // all batches); the slices' FP64 sums are added in slice order.  A
+        // direct slice starts only where a new run of contiguous leaf
+        // particles starts, so the near field's 64-source chunks, and their
+        // FP32 sums, are those of the uncut list.
+        std::vector<int32_t> lp(2 * (nb + 1));
+        std::vector<int32_t> dl(nd);
+        d2h(lp.data(), g->ls[1].ptr, 2 * (nb + 1), s);
+        d2h(dl.data(), g->ls[1].dids, nd, s);
         sync(s);
-        int64_t tot = 0;
-        for (int32_t b : redo) tot += lp[b + 1] - lp[b];
+        const int32_t* ld = lp.data() + nb + 1;
+        const std::vector<int32_t>& lb = t->host.begin;
+        const std::vector<int32_t>& le = t->host.end;
+        int64_t tot = 0, tsrc = 0;
+        for (int32_t b : redo) {
+          tot += lp[b + 1] - lp[b];
+          for (int32_t e = ld[b]; e < ld[b + 1]; ++e) tsrc += le[dl[e]] - lb[dl[e]];
+        }
         const int64_t len = std::max<int64_t>(16, (tot + 4095) / 4096);
-        std::vector<int4> sl;
+        const int64_t srcs = std::max<int64_t>(1024, (tsrc + 4095) / 4096);
+        std::vector<int4> sl;   // (batch, begin, end, 0: proxy entries / 1: direct entries)
         std::vector<int32_t> sptr{0};
         for (int32_t b : redo) {
-          const int32_t p0 = lp[b], p1 = lp[b + 1];
-          if (p0 == p1) sl.push_back(make_int4(b, p0, p0, 1));
+          const int32_t p0 = lp[b], p1 = lp[b + 1], d0 = ld[b], d1 = ld[b + 1];
           for (int64_t q = p0; q < p1; q += len)
-            sl.push_back(make_int4(b, (int)q, (int)std::min<int64_t>(p1, q + len), q == p0));
+            sl.push_back(make_int4(b, (int)q, (int)std::min<int64_t>(p1, q + len), 0));
+          int32_t q = d0;
+          int64_t acc = 0;
+          for (int32_t e = d0; e < d1; ++e) {
+            if (e > q && acc >= srcs && lb[dl[e]] != le[dl[e - 1]]) {
+              sl.push_back(make_int4(b, q, e, 1));
+              q = e;
+              acc = 0;
+            }
+            acc += le[dl[e]] - lb[dl[e]];
+          }
+          if (q < d1) sl.push_back(make_int4(b, q, d1, 1));
+          if (p0 == p1 && d0 == d1) sl.push_back(make_int4(b, p0, p0, 0));
           sptr.push_back((int32_t)sl.size());
         }
         const int odim = odim_of(kernel);
@@ -673,7 +804,8 @@ int bltc_judge_samples(bltc_tree t, bltc_targets g, int32_t kernel, double eps,
   if (!t->has_w) return fail(BLTC_ESTATE, "no weights: call bltc_compute_modified_weights first");
   if (t->wdim != wdim_of(kernel))
     return fail(BLTC_ESTATE, "the tree's weights have the wrong number of components for this kernel");
-  *n_samples = g->m > 0 ? (g->nb + bltc::kJudgeStride - 1) / bltc::kJudgeStride : 0;
+  const int st = bltc::judge_stride(g->nb);
+  *n_samples = g->m > 0 ? (g->nb + st - 1) / st : 0;
   if (!target_idx && !ufb) return BLTC_OK;
   if (g->m == 0) return BLTC_OK;
   return guarded([&] {

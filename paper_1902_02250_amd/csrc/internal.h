@@ -17,7 +17,12 @@ constexpr int kUpwardChunk = 512;    // particles per upward-pass work group
 constexpr int kMlpIn = 12;           // selector network: features
 constexpr int kMlpHidden = 64;       // selector network: hidden width
 constexpr int kMlpMaxOut = 128;      // selector network: most candidates
-constexpr int kJudgeStride = 1;      // batches per judge sample
+// The judge samples one target in every batch up to 2 kJudgeMinSamples
+// batches, above that one in every nb / kJudgeMinSamples consecutive batches.
+constexpr int64_t kJudgeMinSamples = 16384;
+inline int judge_stride(int64_t nb) {
+  return (int)(nb / kJudgeMinSamples > 1 ? nb / kJudgeMinSamples : 1);
+}
 // A proxy-list entry holds the cluster id in its low kDegShift bits and,
 // under the separation rule, the cluster's degree above them (0: the
 // evaluation's degree).
@@ -157,8 +162,9 @@ struct P2PArgs {
   double scale_u, scale_w;     // constant factors applied at the end
   double* out;                 // [odim][m] caller order
   // split mode (split != NULL): wave w evaluates batch split[w].x over the
-  // proxy entries [split[w].y, split[w].z), plus the batch's direct list if
-  // split[w].w != 0, and writes unscaled FP64 sums to partial[w][odim][64]
+  // entries [split[w].y, split[w].z) of its proxy list (split[w].w == 0) or
+  // of its direct list (split[w].w != 0), and writes unscaled FP64 sums to
+  // partial[w][odim][64]
   const int4* split = nullptr;
   int64_t nsplit = 0;
   double* partial = nullptr;
@@ -188,8 +194,12 @@ struct SampleArgs {
   int ns;
   const double* tx;            // tree-ordered targets [3][m]
   int64_t m;
-  Nodes nodes;
-  double theta;
+  const int2* range;           // [nn] cluster source ranges
+  // each sample's lists: its walk of Algorithm 2 with the per-target MAC
+  const int32_t* pptr;         // [ns+1] proxy (accepted cluster) lists
+  const int32_t* pids;
+  const int32_t* dptr;         // [ns+1] direct (leaf) lists
+  const int32_t* dids;
   const double* grid;          // [nn][3][n1] of the fallback degree
   const float* fh32;           // its modified weights, evaluation layout
   const double* ys;            // tree-ordered sources [3][n]
@@ -235,9 +245,16 @@ struct CostGroup {
   double theta;
   int32_t nc;                          // candidates with this theta
   int32_t deg[kMaxPerTheta];           // their degrees
-  int32_t row[kMaxPerTheta];           // output row (and T row) of each candidate
+  int32_t row[kMaxPerTheta];           // output row of each candidate
+  // The rule's degree of an accepted cluster depends on its qq = (rr/R)^2
+  // only through the bucket k = #{U[j] < qq} of the group's sorted distinct
+  // thresholds U[0..nu); C[i][k] (i < nc, k <= nu) is the cost of a cluster
+  // in bucket k for candidate i.
+  int32_t nu;
+  int32_t u_off, c_off;                // offsets into CostArgs::U and ::C
 };
 constexpr int kMaxThetaGroups = 8;     // theta groups per launch (grid y)
+constexpr int kMaxBuckets = kMaxPerTheta * kMaxDegree;   // most thresholds per group
 
 struct CostArgs {
   const double4* bgeo;
@@ -245,14 +262,18 @@ struct CostArgs {
   Nodes nodes;
   int32_t ngroups;
   CostGroup grp[kMaxThetaGroups];
-  int32_t deg_min;                     // separation rule (0: off)
-  const double* T;                     // [rows][kMaxDegree + 1] rule thresholds (device)
-  Costs w;
+  const double* U;                     // the groups' thresholds (device)
+  const float* C;                      // the groups' bucket costs [nc][nu + 1] (device)
+  float nearf;                         // cost of one near-field source
   float* cost;                         // [rows][nb]
   int32_t* err;
 };
 
 // ---- launchers (defined in the .hip files) --------------------------------
+// sgeo[i] = (target spos[i], radius 0): a sample as a batch of one target,
+// whose batch MAC is the per-target MAC.
+hipError_t launch_sample_geo(const int32_t* spos, int ns, const double* tx, int64_t m,
+                             double4* sgeo, hipStream_t s);
 hipError_t launch_fallback_samples(int kernel, int degree, const SampleArgs& a,
                                    hipStream_t s);
 hipError_t launch_features(const FeatArgs& a, hipStream_t s);
@@ -447,9 +468,13 @@ struct bltc_targets_s {
   int32_t* d_choice = nullptr; // [nb]
   int32_t* d_bmap = nullptr;   // [nb]
   double* d_theta_b = nullptr; // [nb]
-  int32_t* d_spos = nullptr;   // judge samples, one per kJudgeStride batches (tree order)
+  int32_t* d_spos = nullptr;   // judge samples, one per sstride batches (tree order)
+  double4* d_sgeo = nullptr;   // [nsamp] the samples as batches of one target
+  int32_t* d_sflags = nullptr; // [4] walk and scan flags of the samples' lists
+  bltc::ListSet ls_samp;       // the samples' lists (per-target MAC, fallback theta)
   double* d_ufb = nullptr;     // [nb][6]
-  int32_t nsamp = 0;           // judge samples (one per kJudgeStride batches)
+  int32_t nsamp = 0;           // judge samples (one per sstride batches)
+  int32_t sstride = 1;         // batches per judge sample (judge_stride)
   double* d_usq = nullptr;     // [nsamp] |u_fb|^2 at the samples
   double* d_wt = nullptr;      // [nb] batch weights targets_b |u_fb|^2
   double* d_contrib = nullptr; // [nsamp] judge error contributions
@@ -460,6 +485,8 @@ struct bltc_targets_s {
   double* d_e2 = nullptr;      // [k][nb] predicted squared errors
   int64_t costcap = 0;
   double* d_candT = nullptr;   // [k][kMaxDegree+1] rule thresholds
+  void* d_costtab = nullptr;   // the cost groups' thresholds and bucket costs
+  int64_t costtab_cap = 0;     // bytes
   int32_t* d_candn = nullptr;  // [k] candidate degrees
 };
 

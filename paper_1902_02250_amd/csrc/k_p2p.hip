@@ -398,20 +398,23 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void k_p2p(
   const int lane = threadIdx.x & 63;
   const int gw = xcd_block(blockIdx.x, nblk) * kWavesPerBlock + wid;
   if (gw >= nwaves) return;
-  int b, wv, pbeg, pend;
-  bool near = true;
-  if (split) {   // one slice of a batch's proxy list (and maybe its direct list)
+  int b, wv, pbeg, pend, dbeg, dend;
+  if (split) {   // a slice of a batch's proxy list or of its direct list
     const int4 sp = split[gw];
     b = sp.x;
     wv = 0;
-    pbeg = sp.y;
-    pend = sp.z;
-    near = sp.w != 0;
+    const bool far = sp.w == 0;
+    pbeg = far ? sp.y : 0;
+    pend = far ? sp.z : 0;
+    dbeg = far ? 0 : sp.y;
+    dend = far ? 0 : sp.z;
   } else {
     b = bmap ? bmap[gw / wpb] : gw / wpb;
     wv = gw % wpb;
     pbeg = pptr[b];
     pend = pptr[b + 1];
+    dbeg = dptr[b];
+    dend = dptr[b + 1];
   }
   const int t0 = bptr[b] + wv * 64, t1 = bptr[b + 1];
   if (t0 >= t1) return;
@@ -467,7 +470,7 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void k_p2p(
   const T xr = F64 ? (T)x : (T)(x - cb.x);
   const T yr = F64 ? (T)y : (T)(y - cb.y);
   const T zr = F64 ? (T)z : (T)(z - cb.z);
-  Runs it{dids, range, near ? dptr[b] : 0, near ? dptr[b + 1] : 0, 0, 0};
+  Runs it{dids, range, dbeg, dend, 0, 0};
   bool have = it.next();
   int s0 = it.rb, re = it.re;
   double py0 = 0, py1 = 0, py2 = 0;   // prefetched source (FP64 position)

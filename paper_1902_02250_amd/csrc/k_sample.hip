@@ -1,23 +1,25 @@
 // The judge's samples: the fixed-(n, theta) treecode of Algorithm 2 at a
-// set of single targets, each walked on its own from the root with the
-// paper's per-target MAC r/R <= theta (eq. MAC), so every sample is exactly
-// the paper's treecode at that target.
+// set of single targets, each with the paper's per-target MAC r/R <= theta
+// (eq. MAC), so every sample is exactly the paper's treecode at that target.
 //
-// One 64-lane wave per sampled target.  The wave walks the tree (uniform
-// control flow: every lane holds the same target) depth first without a
-// stack, following each node's first child or its depth-first successor:
-//   MAC holds -> the cluster's far field (eq. pc_approximation_3D), the
-//                lanes spread over the (k2, k3) columns of its grid, each
-//                walking k1 (for a fixed k1 the lanes read consecutive k3 of
-//                the evaluation layout of the modified weights);
-//   leaf      -> the direct sum (eq. pc_interaction_3D), the lanes spread
-//                over the leaf's particles.
+// A sample is walked as a batch of one target: center the target, radius 0,
+// where the batch MAC (r_B + r_C)^2 <= theta^2 R^2 is the per-target MAC
+// rounded the same way (0 + r_C is exact).  The walks are the list walks of
+// every batch (k_lists: one wave per sample, the lanes sharing the tree's
+// cut), so no wave waits on a serial chain of node loads; this file holds the
+// samples' geometry and the evaluation of their lists.
+//
+// Evaluation: one 64-lane wave per sample, its lists read wave-uniformly:
+//   proxy list -> each cluster's far field (eq. pc_approximation_3D), the
+//                 lanes spread over the (k2, k3) columns of its grid, each
+//                 walking k1 (for a fixed k1 the lanes read consecutive k3 of
+//                 the evaluation layout of the modified weights);
+//   direct list -> the direct sum (eq. pc_interaction_3D), the lanes spread
+//                 over the leaf's particles.
 // FP32 kernel evaluation with the differences x - s and x - y formed in
 // FP64; every cluster's lane partial is folded into an FP64 lane sum and
 // the lane sums are added by a butterfly at the end, so the result is
-// deterministic.  The MAC is R2 > 0 and r r <= (theta theta) R2 with
-// R2 = dx dx + dy dy + dz dz evaluated left to right without fused
-// multiply-adds, the oracle's test bit for bit.
+// deterministic.
 #include <hip/hip_runtime.h>
 
 #include "bltc.h"
@@ -28,16 +30,13 @@ namespace bltc {
 
 namespace {
 
-// The per-target MAC in FP64, rounded exactly as written.
-__device__ __forceinline__ bool mac_target(double x, double y, double z, const double4& c,
-                                           double th2) {
-#pragma clang fp contract(off)
-  const double dx = x - c.x;
-  const double dy = y - c.y;
-  const double dz = z - c.z;
-  const double R2 = dx * dx + dy * dy + dz * dz;
-  const double r2 = c.w * c.w;
-  return R2 > 0.0 && r2 <= th2 * R2;
+__global__ void k_sample_geo(const int32_t* __restrict__ spos, int ns,
+                             const double* __restrict__ tx, int64_t m,
+                             double4* __restrict__ sgeo) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ns) return;
+  const int p = spos[i];
+  sgeo[i] = make_double4(tx[p], tx[m + p], tx[2 * m + p], 0.0);
 }
 
 template <int KERN, int N1, bool ZEPS>
@@ -50,58 +49,55 @@ __global__ __launch_bounds__(64) void k_fallback_samples(SampleArgs a) {
   const int pos = a.spos[si];
   const double x = a.tx[pos], y = a.tx[a.m + pos], z = a.tx[2 * a.m + pos];
   const float e2 = (float)(a.eps * a.eps);
-  const double th2 = a.theta * a.theta;
   double acc[OD];
 #pragma unroll
   for (int c = 0; c < OD; ++c) acc[c] = 0.0;
-  int q = a.nodes.nn > 0 ? 0 : -1;
-  while (q >= 0) {
-    q = __builtin_amdgcn_readfirstlane(q);
-    const double4 cg = a.nodes.geo[q];
+  // far field of the accepted clusters
+  const int p0 = a.pptr[si], p1 = a.pptr[si + 1];
+  for (int e = p0; e < p1; ++e) {
+    const int q = __builtin_amdgcn_readfirstlane(a.pids[e]);
+    const double* __restrict__ g = a.grid + (int64_t)q * 3 * N1;
+    const float* __restrict__ F = a.fh32 + (int64_t)q * 3 * NK;
     float p[OD];
 #pragma unroll
     for (int c = 0; c < OD; ++c) p[c] = 0.f;
-    if (mac_target(x, y, z, cg, th2)) {
-      const double* __restrict__ g = a.grid + (int64_t)q * 3 * N1;
-      const float* __restrict__ F = a.fh32 + (int64_t)q * 3 * NK;
-      float dxs[N1];
+    float dxs[N1];
 #pragma unroll
-      for (int k1 = 0; k1 < N1; ++k1) dxs[k1] = (float)(x - g[k1]);
-      for (int r = lane; r < N1 * N1; r += 64) {
-        const int k2 = r / N1, k3 = r % N1;
-        const float dy = (float)(y - g[N1 + k2]);
-        const float dz = (float)(z - g[2 * N1 + k3]);
-        const float rest = dz * dz + (dy * dy + e2);
-        const float* __restrict__ col = F + k2 * 3 * N1 + k3;
+    for (int k1 = 0; k1 < N1; ++k1) dxs[k1] = (float)(x - g[k1]);
+    for (int r = lane; r < N1 * N1; r += 64) {
+      const int k2 = r / N1, k3 = r % N1;
+      const float dy = (float)(y - g[N1 + k2]);
+      const float dz = (float)(z - g[2 * N1 + k3]);
+      const float rest = dz * dz + (dy * dy + e2);
+      const float* __restrict__ col = F + k2 * 3 * N1 + k3;
 #pragma unroll
-        for (int k1 = 0; k1 < N1; ++k1) {
-          const float dx = dxs[k1];
-          const float* __restrict__ f = col + k1 * N1 * 3 * N1;
-          pair<KERN, ZEPS, float>(dx, dy, dz, dx * dx + rest, e2, f[0], f[N1], f[2 * N1], p);
-        }
+      for (int k1 = 0; k1 < N1; ++k1) {
+        const float dx = dxs[k1];
+        const float* __restrict__ f = col + k1 * N1 * 3 * N1;
+        pair<KERN, ZEPS, float>(dx, dy, dz, dx * dx + rest, e2, f[0], f[N1], f[2 * N1], p);
       }
-#pragma unroll
-      for (int c = 0; c < OD; ++c) acc[c] += (double)p[c];
-      q = a.nodes.skip[q];
-      continue;
     }
-    const int2 kd = a.nodes.kids[q];
-    if (kd.y == 0) {
-      const int2 rg = a.nodes.range[q];
-      for (int j = rg.x + lane; j < rg.y; j += 64) {
-        const float dx = (float)(x - a.ys[j]);
-        const float dy = (float)(y - a.ys[a.n + j]);
-        const float dz = (float)(z - a.ys[2 * a.n + j]);
-        const float r2 = dz * dz + (dy * dy + (dx * dx + e2));
-        pair<KERN, ZEPS, float>(dx, dy, dz, r2, e2, a.w32[j], a.w32[a.n + j],
-                                a.w32[2 * a.n + j], p);
-      }
 #pragma unroll
-      for (int c = 0; c < OD; ++c) acc[c] += (double)p[c];
-      q = a.nodes.skip[q];
-      continue;
+    for (int c = 0; c < OD; ++c) acc[c] += (double)p[c];
+  }
+  // direct sums over the leaves that failed the MAC
+  const int d0 = a.dptr[si], d1 = a.dptr[si + 1];
+  for (int e = d0; e < d1; ++e) {
+    const int q = __builtin_amdgcn_readfirstlane(a.dids[e]);
+    const int2 rg = a.range[q];
+    float p[OD];
+#pragma unroll
+    for (int c = 0; c < OD; ++c) p[c] = 0.f;
+    for (int j = rg.x + lane; j < rg.y; j += 64) {
+      const float dx = (float)(x - a.ys[j]);
+      const float dy = (float)(y - a.ys[a.n + j]);
+      const float dz = (float)(z - a.ys[2 * a.n + j]);
+      const float r2 = dz * dz + (dy * dy + (dx * dx + e2));
+      pair<KERN, ZEPS, float>(dx, dy, dz, r2, e2, a.w32[j], a.w32[a.n + j],
+                              a.w32[2 * a.n + j], p);
     }
-    q = kd.x;
+#pragma unroll
+    for (int c = 0; c < OD; ++c) acc[c] += (double)p[c];
   }
 #pragma unroll
   for (int c = 0; c < OD; ++c)
@@ -138,6 +134,14 @@ hipError_t dispatch_samples(int degree, const SampleArgs& a, hipStream_t s) {
 }
 
 }  // namespace
+
+hipError_t launch_sample_geo(const int32_t* spos, int ns, const double* tx, int64_t m,
+                             double4* sgeo, hipStream_t s) {
+  if (ns == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sample_geo, dim3((ns + 255) / 256), dim3(256), 0, s, spos, ns, tx, m,
+                     sgeo);
+  return hipGetLastError();
+}
 
 hipError_t launch_fallback_samples(int kernel, int degree, const SampleArgs& a, hipStream_t s) {
   if (kernel == KSTOKES) return dispatch_samples<KSTOKES>(degree, a, s);

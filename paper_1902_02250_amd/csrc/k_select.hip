@@ -83,22 +83,25 @@ __global__ __launch_bounds__(64 * kSelWaves) void k_features(FeatArgs a) {
 }
 
 // Modelled wave costs of the candidates (CostArgs): one wave-shared walk
-// (walk.h) per batch and theta group (grid y); an accepted cluster at ratio^2 qq costs
-// (far n1 + row) n1^2 + clu with n1 - 1 the candidate's degree, or under the
-// separation rule the first d >= deg_min with qq <= T[d] (binary search on
-// the thresholds, which grow with d, staged in LDS).  The candidate loop is
+// (walk.h) per batch and theta group (grid y).  An accepted cluster at
+// ratio^2 qq = (rr/R)^2 costs (far n1 + row) n1^2 + clu with n1 - 1 the
+// candidate's degree, or under the separation rule the first d >= deg_min
+// with qq <= T[d].  Which degree every candidate of the group takes depends
+// on qq only through its bucket among the group's distinct thresholds, so a
+// cluster costs one binary search over them (staged in LDS) and one table
+// row read per candidate; the host fills the table.  The candidate loop is
 // unrolled to kMaxPerTheta so the sums stay in registers; the theta groups
 // run in one launch so their walks overlap.
 __global__ __launch_bounds__(64 * kSelWaves) void k_cand_costs(CostArgs a) {
   const int lane = threadIdx.x & 63;
   const int64_t b = (int64_t)blockIdx.x * kSelWaves + (threadIdx.x >> 6);
   const CostGroup& gr = a.grp[blockIdx.y];
-  // the group's rule thresholds, one row per candidate
-  __shared__ double sT[kMaxPerTheta][kMaxDegree + 1];
-  for (int i = threadIdx.x; i < kMaxPerTheta * (kMaxDegree + 1); i += blockDim.x) {
-    const int c = i / (kMaxDegree + 1), d = i % (kMaxDegree + 1);
-    sT[c][d] = c < gr.nc ? a.T[(int64_t)gr.row[c] * (kMaxDegree + 1) + d] : 0.0;
-  }
+  __shared__ double sU[kMaxBuckets];
+  __shared__ float sC[kMaxPerTheta][kMaxBuckets + 1];
+  const int nu = gr.nu;
+  for (int i = threadIdx.x; i < nu; i += blockDim.x) sU[i] = a.U[gr.u_off + i];
+  for (int i = threadIdx.x; i < gr.nc * (nu + 1); i += blockDim.x)
+    sC[i / (nu + 1)][i % (nu + 1)] = a.C[gr.c_off + i];
   __syncthreads();
   if (b >= a.nb) return;
   const double4 g = a.bgeo[b];
@@ -109,26 +112,20 @@ __global__ __launch_bounds__(64 * kSelWaves) void k_cand_costs(CostArgs a) {
   double S = 0.0;
   cut_walk(a.nodes, g, th2, lane,
            [&](int32_t, double R2, double rr) {
-             const double qq = (rr * rr) / R2;
-#pragma unroll
-             for (int i = 0; i < kMaxPerTheta; ++i) {
-               if (i < gr.nc) {
-                 const int n = gr.deg[i];
-                 int d = n;
-                 if (a.deg_min > 0 && a.deg_min < n) {
-                   // the first d in [deg_min, n) with qq <= T[d], else n (T grows with d)
-                   int lo = a.deg_min, hi = n;
-                   while (lo < hi) {
-                     const int mid = (lo + hi) >> 1;
-                     if (qq <= sT[i][mid]) hi = mid;
-                     else lo = mid + 1;
-                   }
-                   d = lo;
-                 }
-                 const float n1 = (float)(d + 1);
-                 far[i] += (a.w.far * n1 + a.w.row) * n1 * n1 + a.w.clu;
+             int k = 0;
+             if (nu > 0) {
+               // the number of thresholds below qq
+               const double qq = (rr * rr) / R2;
+               int hi = nu;
+               while (k < hi) {
+                 const int mid = (k + hi) >> 1;
+                 if (sU[mid] < qq) k = mid + 1;
+                 else hi = mid;
                }
              }
+#pragma unroll
+             for (int i = 0; i < kMaxPerTheta; ++i)
+               if (i < gr.nc) far[i] += sC[i][k];
            },
            [&](int32_t q) {
              const int2 rg = a.nodes.range[q];
@@ -141,7 +138,7 @@ __global__ __launch_bounds__(64 * kSelWaves) void k_cand_costs(CostArgs a) {
   if (lane == 0) {
 #pragma unroll
     for (int i = 0; i < kMaxPerTheta; ++i)
-      if (i < gr.nc) a.cost[(int64_t)gr.row[i] * a.nb + b] = far[i] + (float)S * a.w.nearf;
+      if (i < gr.nc) a.cost[(int64_t)gr.row[i] * a.nb + b] = far[i] + (float)S * a.nearf;
   }
 }
 

@@ -251,6 +251,32 @@ def test_judge_samples_match_oracle(torch, orc, kernel, dist, fb, ol):
     close(orc, ref, u, 1e-6, elem_tol=1e-5, what=f"judge {kernel} {dist} {fb}")
 
 
+def test_judge_samples_grouped(torch, orc):
+    """From 32,768 batches on, the judge samples one target per group of
+    floor(nb / 16384) consecutive batches, inside the group's first batch:
+    2.2e6 uniform points give 34,375 batches in groups of two.  A spread of
+    the samples is checked against the oracle's treecode (per-target MAC)."""
+    n, leaf, eps, fb = 2200000, 2000, 0.005, (6, 0.7)
+    src = inputs.points("uniform", n, 83)
+    w = inputs.weights(n, 83)
+    T = bltc.Tree(_d(torch, src), leaf)
+    T.compute_weights(_d(torch, w), fb[0])
+    G = bltc.Targets(_d(torch, src))
+    st = G.nb // 16384
+    assert st == 2
+    idx, u = bltc.judge_samples(T, G, "stokeslet", eps, fb[0], fb[1])
+    assert idx.size == (G.nb + st - 1) // st and np.unique(idx).size == idx.size
+    ex = G.export()
+    where = np.empty(n, np.int64)
+    where[ex["tperm"]] = np.arange(n)
+    b = np.searchsorted(ex["bptr"], where[idx], side="right") - 1
+    assert np.array_equal(b, np.arange(idx.size) * st)
+    pick = np.linspace(0, idx.size - 1, 24).astype(np.int64)
+    ref, _, _ = orc.treecode("stokeslet", src, src, w, eps, fb[0], fb[1], leaf, mac_mode=0,
+                             sample=idx[pick])
+    close(orc, ref, u[:, pick], 1e-6, elem_tol=1e-5, what="judge samples in groups of two")
+
+
 def test_adaptive_matches_oracle_per_candidate(torch, orc, tmp_path, case):
     """Rotlets on clustered points (the shape of the 1e6 mixture workload,
     at 30,000 points) at a tolerance that mixes candidates: the targets of
