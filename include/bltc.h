@@ -403,11 +403,12 @@ int bltc_judge_samples(bltc_tree t, bltc_targets g, int32_t kernel, double eps,
  *     estimates the batch's share of the reference norm.
  *  3. mode BLTC_SELECT_BATCH: the batches share the error budget: the
  *     choice minimises the total cost subject to
- *     sum_b w_b e_b^2 <= tau^2 sum_b w_b, tau = tol 10^-margin, through the
- *     Lagrange multiplier of cost + lam w_b e_b^2 (searched on a log grid in
- *     two passes).  mode BLTC_SELECT_RUN: one candidate for every batch,
- *     the cheapest whose predicted global error is within
- *     tol 10^-margin_global (else the one predicted most accurate).
+ *     sum_b w_b e_b^2 <= tau^2 sum_b w_b, tau = 0.8 tol 10^-margin (0.8
+ *     tol: the judge's trigger, step 5), through the Lagrange multiplier of
+ *     cost + lam w_b e_b^2 (searched on a log grid in two passes).  mode
+ *     BLTC_SELECT_RUN: one candidate for every batch, the cheapest whose
+ *     predicted global error is within 0.8 tol 10^-margin_global (else the
+ *     one predicted most accurate).
  *  4. Lists at each batch's theta (and the separation rule's degrees);
  *     modified weights of every top degree in use and, under the rule, of
  *     the lower degrees derived from each top degree's (so a batch's result

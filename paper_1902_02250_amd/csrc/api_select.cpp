@@ -48,6 +48,10 @@ void batch_counts(bltc_tree t, bltc_targets g, double theta, int32_t* pc,
 
 constexpr int kLamGrid = 64;   // multipliers per allocation pass
 
+// The judge re-evaluates batches when its estimate exceeds kJudgeTrigger tol,
+// down to kJudgeTarget tol; the choices aim below the trigger.
+constexpr double kJudgeTrigger = 0.8, kJudgeTarget = 0.6;
+
 // Modelled wave cost of every batch under each of the k candidates
 // (cand_n[j], cand_theta[j]) into cost[j][nb] (device), with the separation
 // rule when deg_min >= 1: one walk per distinct theta.
@@ -345,8 +349,10 @@ void evaluate_adaptive(bltc_tree t, bltc_targets g, int kernel, double eps,
 
   if (mode == BLTC_SELECT_RUN) {
     // 3. one candidate for the whole run: the cheapest whose predicted global
-    //    error sqrt(sum_b wn_b e_b^2) is within tau = tol 10^-margin_global
-    const double tau = tol * std::pow(10.0, -sel->margin_global);
+    //    error sqrt(sum_b wn_b e_b^2) is within tau = kJudgeTrigger tol
+    //    10^-margin_global (the judge's trigger, so a choice as predicted is
+    //    not re-evaluated)
+    const double tau = kJudgeTrigger * tol * std::pow(10.0, -sel->margin_global);
     const double inv_w = wsum > 0.0 ? 1.0 / (wsum * tau * tau) : 0.0;
     hipchk(bltc::launch_cand_totals(g->d_e2, k, nb, g->d_cost, g->d_wt, inv_w, g->d_sums, s),
            "candidate totals");
@@ -361,9 +367,10 @@ void evaluate_adaptive(bltc_tree t, bltc_targets g, int kernel, double eps,
     hipchk(bltc::launch_fill_i32(g->d_choice, nb, best >= 0 ? best : most, s), "choice");
   } else {
   // 3. error budget: minimise the modelled cost subject to
-  //    sum_b wn_b e_b^2 <= tau^2,  wn_b = w_b / sum w,  tau = tol 10^-margin,
+  //    sum_b wn_b e_b^2 <= tau^2,  wn_b = w_b / sum w,
+  //    tau = kJudgeTrigger tol 10^-margin,
   //    by the multiplier lam of cost + lam wn e^2 / tau^2 (two grid passes)
-  const double tau = tol * std::pow(10.0, -sel->margin);
+  const double tau = kJudgeTrigger * tol * std::pow(10.0, -sel->margin);
   const double inv_w = wsum > 0.0 ? 1.0 / (wsum * tau * tau) : 0.0;
   double lam_star = 0.0;
   if (inv_w > 0.0) {
@@ -468,9 +475,10 @@ void evaluate_adaptive(bltc_tree t, bltc_targets g, int kernel, double eps,
     for (hipEvent_t e : done) hipchk(hipStreamWaitEvent(s, e, 0), "hipStreamWaitEvent");
   }
 
-  // 5. the judge's estimate of the global error; when it exceeds 0.8 tol,
-  //    the batches with the largest sampled errors are evaluated again with
-  //    the fallback until the estimate is at most 0.6 tol.  The margins
+  // 5. the judge's estimate of the global error; when it exceeds
+  //    kJudgeTrigger tol, the batches with the largest sampled errors are
+  //    evaluated again with the fallback until the estimate is at most
+  //    kJudgeTarget tol.  The margins
   //    cover the sampled estimate's spread: the per-target errors are heavy
   //    tailed (a few targets next to accepted clusters of a dense region
   //    carry much of the sum), so one sample per batch reads low more often
@@ -480,9 +488,9 @@ void evaluate_adaptive(bltc_tree t, bltc_targets g, int kernel, double eps,
   double js[2];
   judge_sums(g, kernel, out, js, s);
   jd[0] = jd[1] = wsum > 0.0 ? std::sqrt(js[1] / wsum) : 0.0;
-  if (js[1] > 0.64 * tol * tol * wsum) {
+  if (js[1] > kJudgeTrigger * kJudgeTrigger * tol * tol * wsum) {
     // the fewest samples, largest terms first, whose removal brings the
-    // estimate to (0.6 tol)^2; their batches go to the fallback
+    // estimate to (kJudgeTarget tol)^2; their batches go to the fallback
     const int ns = g->nsamp;
     std::vector<double> c(ns);
     d2h(c.data(), g->d_contrib, ns, s);
@@ -493,7 +501,7 @@ void evaluate_adaptive(bltc_tree t, bltc_targets g, int kernel, double eps,
     double rest = js[1];
     std::vector<int32_t> redo;
     for (int32_t i : ord) {
-      if (rest <= 0.36 * tol * tol * wsum) break;
+      if (rest <= kJudgeTarget * kJudgeTarget * tol * tol * wsum) break;
       rest -= c[i];
       for (int64_t b = (int64_t)i * g->sstride;
            b < std::min<int64_t>(nb, (int64_t)(i + 1) * g->sstride); ++b) {
