@@ -128,8 +128,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tol", type=float, default=1e-6,
                     help="error target of the learned-vs-fixed comparison")
-    ap.add_argument("--fallback", default="10,0.6",
-                    help="the learned path's fallback and judge (n, theta)")
+    ap.add_argument("--fallback", default=None,
+                    help="the learned path's fallback and judge (n, theta) (default: "
+                         "selector.fallback_for(tol))")
     ap.add_argument("--sweep", type=int, default=None,
                     help="1: time every candidate (n, theta) of the selector, plain and with "
                          "the separation rule, to find the best fixed settings at --tol "
@@ -155,7 +156,8 @@ def main():
                     help="first run one device-to-device copy of MIB MiB, the reference "
                          "for scaling HBM byte counters")
     args = ap.parse_args()
-    args.fallback = (int(args.fallback.split(",")[0]), float(args.fallback.split(",")[1]))
+    if args.fallback:
+        args.fallback = (int(args.fallback.split(",")[0]), float(args.fallback.split(",")[1]))
     if args.sweep is None:
         args.sweep = 1 if args.workload == "c3" and not args.n else 0
     if args.grid_sweep is None:
@@ -390,6 +392,8 @@ def main():
     # the learned (n, theta): per batch and one per run, with the fallback's
     # weights, the judge and any repair inside the timed step
     learned = []
+    if not args.fallback:
+        args.fallback = selector.fallback_for(args.tol)
     if args.learned and kernel in ("stokeslet", "rotlet"):
         sel = bltc.Selector(selector.MODEL_PATH)
         for mode in ("batch", "run"):

@@ -344,7 +344,20 @@ def calibrate_margin(val_runs, Ys, tols=(1e-4, 1e-5, 1e-6), grid=None):
     return float(grid[-1])
 
 
-def compare(workload, model=MODEL_PATH, tol=None, fb=(10, 0.6), reps=2, n=None, log=print):
+def fallback_for(tol):
+    """The judge's fallback (n, 0.6) for a requested error tol: the lowest
+    degree whose error at theta = 0.6 is about 2% of tol or less, so the
+    fallback is a reference for the judge and a safe re-evaluation.  The
+    errors of the fixed grid at theta = 0.6 on the workloads here fall about
+    fivefold per degree from 5e-3 at n = 2; from n = 10 on, FP32 rounding
+    (2-4e-7) dominates, so n stays in [6, 10]."""
+    n = 2
+    while n < 10 and 5e-3 * 0.21 ** (n - 2) > 0.02 * tol:
+        n += 1
+    return (max(6, n), 0.6)
+
+
+def compare(workload, model=MODEL_PATH, tol=None, fb=None, reps=2, n=None, log=print):
     """Learned (n, theta) against every fixed candidate on one workload:
     step time (modified weights + evaluation, HIP events) and relative L2
     error against the FP64 direct sum on 10,000 sampled targets.  tol=None
@@ -392,6 +405,8 @@ def compare(workload, model=MODEL_PATH, tol=None, fb=(10, 0.6), reps=2, n=None, 
                     for t in CAND_THETA))
     if tol is None:
         tol = cfg.get("tol") or fixed[(cfg["degree"], cfg["theta"])][1]
+    if fb is None:
+        fb = fallback_for(tol)
     ok = [c for c in CANDIDATES if fixed[c][1] <= tol]
     best = min(ok, key=lambda c: fixed[c][0]) if ok else None
     okr = [c for c in CANDIDATES if ruled[c][1] <= tol]
