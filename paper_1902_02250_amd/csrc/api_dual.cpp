@@ -13,69 +13,16 @@ namespace api {
 
 namespace {
 
-// Evaluation with (n, theta) chosen per batch (see bltc_evaluate_adaptive).
 // ---- cluster-cluster variant -------------------------------------------------
-// Dual traversal of the target tree T and the source tree S (the target
-// variable is interpolated too, Section 9).  For a pair (A, C):
-//   MAC (R2 > 0 and (r_A + r_C)^2 <= theta^2 R2): CC if both hold more than
-//   P = (n+1)^3 particles, PC if only C does, CP if only A does, else PP;
-//   no MAC and both leaves: PP; otherwise refine A if C is a leaf or
-//   (A is not a leaf and r_A >= r_C), else refine C.
-struct DualPlan {
-  std::vector<std::vector<int32_t>> cc, cp, pc, pp;   // source nodes, by target node
-  int64_t cnt[5] = {0, 0, 0, 0, 0};                    // CC, PC, CP, PP evaluations, downward terms
-};
-
-void dual_traverse(const bltc::HostTree& T, const bltc::HostTree& S, int n1, double theta,
-                   const bltc::Rule& rule, DualPlan& D) {
-  const int64_t ntn = T.nnodes();
-  D.cc.assign(ntn, {});
-  D.cp.assign(ntn, {});
-  D.pc.assign(ntn, {});
-  D.pp.assign(ntn, {});
-  if (T.n == 0 || S.n == 0) return;
-  const int64_t P = (int64_t)n1 * n1 * n1;
-  std::vector<std::pair<int32_t, int32_t>> st{{0, 0}};
-  while (!st.empty()) {
-    const int32_t A = st.back().first, C = st.back().second;
-    st.pop_back();
-    const int64_t na = T.end[A] - T.begin[A], nc = S.end[C] - S.begin[C];
-    const double dx = T.ctr[3 * A] - S.ctr[3 * C];
-    const double dy = T.ctr[3 * A + 1] - S.ctr[3 * C + 1];
-    const double dz = T.ctr[3 * A + 2] - S.ctr[3 * C + 2];
-    const double R2 = dx * dx + dy * dy + dz * dz;
-    const double rr = T.rad[A] + S.rad[C];
-    const bool mac = R2 > 0.0 && rr * rr <= (theta * theta) * R2;
-    const bool leafA = T.count[A] == 0, leafC = S.count[C] == 0;
-    // the source side's degree under the separation rule (n - 1 when off):
-    // the entry carries it above kDegShift
-    int d = n1 - 1;
-    if (mac && rule.deg_min > 0) {
-      const double qq = (rr * rr) / R2;
-      d = rule.deg_min;
-      while (d < rule.degree && !(qq <= rule.T[d])) ++d;
-    }
-    const int64_t Pd = (int64_t)(d + 1) * (d + 1) * (d + 1);
-    const int32_t e = rule.deg_min > 0 ? (C | (d << bltc::kDegShift)) : C;
-    if (mac && na > P && nc > P) {
-      D.cc[A].push_back(e);
-      D.cnt[0] += P * Pd;
-    } else if (mac && nc > P) {
-      D.pc[A].push_back(e);
-      D.cnt[1] += na * Pd;
-    } else if (mac && na > P) {
-      D.cp[A].push_back(C);
-      D.cnt[2] += P * nc;
-    } else if (mac || (leafA && leafC)) {
-      D.pp[A].push_back(C);
-      D.cnt[3] += na * nc;
-    } else if (leafC || (!leafA && T.rad[A] >= S.rad[C])) {
-      for (int32_t k = T.count[A] - 1; k >= 0; --k) st.push_back({T.first[A] + k, C});
-    } else {
-      for (int32_t k = S.count[C] - 1; k >= 0; --k) st.push_back({A, S.first[C] + k});
-    }
-  }
-}
+// The dual traversal of the target tree T and the source tree S (the target
+// variable is interpolated too, Section 9) runs on the device
+// (k_dual_walk.hip): per target node its CC and CP lists and the evaluation
+// counts, per target leaf the PC and PP entries of the leaf and its
+// ancestors.  Each target cluster with CC or CP work gets a grid slot: its
+// grid points are evaluated as targets (one batch per cluster run by several
+// waves: CC clusters on the proxy list, CP clusters on the direct list), and
+// every target adds the interpolated grid potentials of the slots on its
+// root path.
 
 void evaluate_dual(bltc_tree src, bltc_tree tgt, int kernel, double eps, int degree,
                    double theta, const bltc_options& o, double* out, int64_t* counts,
@@ -84,121 +31,150 @@ void evaluate_dual(bltc_tree src, bltc_tree tgt, int kernel, double eps, int deg
   const bltc::HostTree& S = src->host;
   const int64_t m = tgt->n, ntn = T.nnodes();
   if (m == 0) return;
+  if (T.depth + 1 > bltc::kDualMaxDepth || S.depth + 2 > bltc::kDualMaxDepth)
+    throw HipError{BLTC_EINVAL, "the cluster-cluster traversal supports trees of at most " +
+                                    std::to_string(bltc::kDualMaxDepth - 2) + " levels"};
   ensure_degree(src, degree, s);
   const bltc_degree_data& d = src->deg.at(degree);
   const int n1 = degree + 1;
   const int64_t P = (int64_t)n1 * n1 * n1;
   const int odim = odim_of(kernel);
-
-  StageTimer lt(BLTC_STAGE_LISTS, s);
-  DualPlan D;
   const bltc::Rule rule = make_rule(theta, degree, o.deg_min);
   if (rule.deg_min > 0 && S.nnodes() > bltc::kIdMask)
     throw HipError{BLTC_EINVAL, "too many source clusters for the separation rule's encoding"};
-  dual_traverse(T, S, n1, theta, rule, D);
-  // grid slots: target clusters with CC or CP work
-  // (their grid points are evaluated as targets, one batch per cluster run
-  // by several waves: CC clusters on the proxy list, CP clusters on the
-  // direct list)
-  std::vector<int32_t> slot(ntn, -1), gnode;
-  std::vector<int32_t> gbptr, gpptr{0}, gpids, gdptr{0}, gdids;
-  std::vector<double4> gbgeo;
-  for (int64_t A = 0; A < ntn; ++A) {
-    if (D.cc[A].empty() && D.cp[A].empty()) continue;
-    const int32_t gi = (int32_t)gnode.size();
-    slot[A] = gi;
-    gnode.push_back((int32_t)A);
-    gbptr.push_back((int32_t)(gi * P));
-    gbgeo.push_back(make_double4(T.ctr[3 * A], T.ctr[3 * A + 1], T.ctr[3 * A + 2], T.rad[A]));
-    gpids.insert(gpids.end(), D.cc[A].begin(), D.cc[A].end());
-    gpptr.push_back((int32_t)gpids.size());
-    gdids.insert(gdids.end(), D.cp[A].begin(), D.cp[A].end());
-    gdptr.push_back((int32_t)gdids.size());
-    D.cnt[4] += (int64_t)(T.end[A] - T.begin[A]) * P;
-  }
-  const int64_t ng = (int64_t)gnode.size(), M = ng * P, gnb = (int64_t)gbgeo.size();
-  if (M > (int64_t)INT32_MAX || gpids.size() > (size_t)INT32_MAX)
-    throw HipError{BLTC_EINVAL, "cluster-cluster grid pass exceeds 2^31 entries"};
-  gbptr.push_back((int32_t)M);
-  std::vector<int32_t> giota(M);
-  std::iota(giota.begin(), giota.end(), 0);
-  // one batch per target leaf (run by several waves of 64 targets), leaves
-  // in position order; it takes the PC and PP entries and the grid slots of
-  // the leaf and all its ancestors
-  std::vector<int32_t> parent(ntn, -1), leaves;
-  for (int64_t q = 0; q < ntn; ++q) {
-    for (int32_t k = 0; k < T.count[q]; ++k) parent[T.first[q] + k] = (int32_t)q;
-    if (T.count[q] == 0) leaves.push_back((int32_t)q);
-  }
-  std::sort(leaves.begin(), leaves.end(),
-            [&](int32_t a, int32_t b) { return T.begin[a] < T.begin[b]; });
-  std::vector<int32_t> bptr, pptr{0}, pids, dptr{0}, dids, xptr{0}, xgi, xnode, path;
-  std::vector<double4> bgeo;
-  std::vector<int32_t> lpc, lpp, lgi, lnode;
-  int64_t lmax = 1;
-  for (int32_t L : leaves) {
-    path.clear();
-    for (int32_t q = L; q >= 0; q = parent[q]) path.push_back(q);
-    std::reverse(path.begin(), path.end());
-    lpc.clear();
-    lpp.clear();
-    lgi.clear();
-    lnode.clear();
-    for (int32_t q : path) {
-      lpc.insert(lpc.end(), D.pc[q].begin(), D.pc[q].end());
-      lpp.insert(lpp.end(), D.pp[q].begin(), D.pp[q].end());
-      if (slot[q] >= 0) {
-        lgi.push_back(slot[q]);
-        lnode.push_back(q);
-      }
-    }
-    bptr.push_back(T.begin[L]);
-    bgeo.push_back(make_double4(T.ctr[3 * L], T.ctr[3 * L + 1], T.ctr[3 * L + 2], T.rad[L]));
-    pids.insert(pids.end(), lpc.begin(), lpc.end());
-    pptr.push_back((int32_t)pids.size());
-    dids.insert(dids.end(), lpp.begin(), lpp.end());
-    dptr.push_back((int32_t)dids.size());
-    xgi.insert(xgi.end(), lgi.begin(), lgi.end());
-    xnode.insert(xnode.end(), lnode.begin(), lnode.end());
-    xptr.push_back((int32_t)xgi.size());
-    lmax = std::max<int64_t>(lmax, T.end[L] - T.begin[L]);
-  }
-  const int64_t nb = (int64_t)bgeo.size();
-  const int wpb_t = (int)((lmax + bltc::kWave - 1) / bltc::kWave);
-  const int wpb_g = (int)((P + bltc::kWave - 1) / bltc::kWave);
-  bptr.push_back((int32_t)m);
-  if (pids.size() > (size_t)INT32_MAX || dids.size() > (size_t)INT32_MAX)
-    throw HipError{BLTC_EINVAL, "cluster-cluster lists exceed 2^31 entries"};
 
   if (!tgt->dual) tgt->dual = new bltc_dual_cache;
   bltc_dual_cache& C = *tgt->dual;
+  StageTimer lt(BLTC_STAGE_LISTS, s);
+  // the target leaves in position order: one batch each
+  std::vector<int32_t> leaves, bptr;
+  std::vector<double4> bgeo;
+  int64_t lmax = 1;
+  for (int64_t q = 0; q < ntn; ++q)
+    if (T.count[q] == 0) leaves.push_back((int32_t)q);
+  std::sort(leaves.begin(), leaves.end(),
+            [&](int32_t a, int32_t b) { return T.begin[a] < T.begin[b]; });
+  for (int32_t L : leaves) {
+    bptr.push_back(T.begin[L]);
+    bgeo.push_back(make_double4(T.ctr[3 * L], T.ctr[3 * L + 1], T.ctr[3 * L + 2], T.rad[L]));
+    lmax = std::max<int64_t>(lmax, T.end[L] - T.begin[L]);
+  }
+  bptr.push_back((int32_t)m);
+  const int64_t nl = (int64_t)leaves.size(), nb = nl;
+  auto up = [&](auto& buf, const auto& v) {
+    buf.reserve(v.size());
+    h2d(buf.p, v.data(), v.size(), s);
+  };
+  up(C.leaves, leaves);
+  up(C.bptr, bptr);
+  up(C.bgeo, bgeo);
+  C.ncc.reserve(ntn);
+  C.ncp.reserve(ntn);
+  C.ccptr.reserve(ntn + 1);
+  C.cpptr.reserve(ntn + 1);
+  C.flag.reserve(ntn);
+  C.slot.reserve(ntn + 1);
+  C.npc.reserve(nl);
+  C.npp.reserve(nl);
+  C.xcnt.reserve(nl);
+  C.pptr.reserve(nl + 1);
+  C.dptr.reserve(nl + 1);
+  C.xptr.reserve(nl + 1);
+  C.work.reserve(5);
+  C.ovf.reserve(8);
+  hipchk(bltc::launch_fill_i32(reinterpret_cast<int32_t*>(C.work.p), 10, 0, s), "clear");
+  hipchk(bltc::launch_fill_i32(C.ovf.p, 8, 0, s), "clear");
+
+  bltc::DualArgs a;
+  a.src = tree_nodes(src);
+  a.slevel = src->d_level;
+  a.tgeo = tgt->d_geo;
+  a.trange = tgt->d_range;
+  a.tkids = tgt->d_kids;
+  a.tparent = tgt->d_parent;
+  a.th2 = theta * theta;
+  a.P = P;
+  a.n1 = n1;
+  a.rule = rule;
+  a.work = C.work.p;
+  // per target node: CC and CP lists, counts, grid slots
+  a.items = nullptr;
+  a.nitems = ntn;
+  a.cnt0 = C.ncc.p;
+  a.cnt1 = C.ncp.p;
+  hipchk(bltc::launch_dual_walk(a, false, false, s), "dual walk (nodes)");
+  hipchk(bltc::launch_exclusive_scan(C.ncc.p, ntn, C.ccptr.p, C.ovf.p, s), "scan");
+  hipchk(bltc::launch_exclusive_scan(C.ncp.p, ntn, C.cpptr.p, C.ovf.p + 1, s), "scan");
+  hipchk(bltc::launch_dual_flags(C.ncc.p, C.ncp.p, ntn, C.flag.p, s), "grid slots");
+  hipchk(bltc::launch_exclusive_scan(C.flag.p, ntn, C.slot.p, C.ovf.p + 2, s), "scan");
+  // per target leaf: PC and PP entries of its path, and its path's slots
+  a.items = C.leaves.p;
+  a.nitems = nl;
+  a.cnt0 = C.npc.p;
+  a.cnt1 = C.npp.p;
+  hipchk(bltc::launch_dual_walk(a, true, false, s), "dual walk (leaves)");
+  hipchk(bltc::launch_exclusive_scan(C.npc.p, nl, C.pptr.p, C.ovf.p + 3, s), "scan");
+  hipchk(bltc::launch_exclusive_scan(C.npp.p, nl, C.dptr.p, C.ovf.p + 4, s), "scan");
+  hipchk(bltc::launch_dual_xlists(C.leaves.p, nl, tgt->d_parent, C.flag.p, C.slot.p, C.xcnt.p,
+                                  nullptr, nullptr, nullptr, false, s),
+         "slot lists");
+  hipchk(bltc::launch_exclusive_scan(C.xcnt.p, nl, C.xptr.p, C.ovf.p + 5, s), "scan");
+  int32_t tot[6], ovf[8];
+  d2h(&tot[0], C.ccptr.p + ntn, 1, s);
+  d2h(&tot[1], C.cpptr.p + ntn, 1, s);
+  d2h(&tot[2], C.slot.p + ntn, 1, s);
+  d2h(&tot[3], C.pptr.p + nl, 1, s);
+  d2h(&tot[4], C.dptr.p + nl, 1, s);
+  d2h(&tot[5], C.xptr.p + nl, 1, s);
+  d2h(ovf, C.ovf.p, 8, s);
+  sync(s);
+  for (int q = 0; q < 6; ++q)
+    if (ovf[q]) throw HipError{BLTC_EINVAL, "cluster-cluster lists exceed 2^31 entries"};
+  const int64_t ng = tot[2], M = ng * P, gnb = ng;
+  if (M > (int64_t)INT32_MAX)
+    throw HipError{BLTC_EINVAL, "cluster-cluster grid pass exceeds 2^31 entries"};
   DevBuf<int32_t>&d_gnode = C.gnode, &d_gbptr = C.gbptr, &d_gpptr = C.gpptr, &d_gpids = C.gpids,
       &d_gdptr = C.gdptr, &d_gdids = C.gdids, &d_giota = C.giota, &d_bptr = C.bptr,
       &d_pptr = C.pptr, &d_pids = C.pids, &d_dptr = C.dptr, &d_dids = C.dids, &d_xptr = C.xptr,
       &d_xgi = C.xgi, &d_xnode = C.xnode;
   DevBuf<double4>&d_bgeo = C.bgeo, &d_gbgeo = C.gbgeo;
   DevBuf<double>&d_tgrid = C.tgrid, &d_g = C.g, &d_gpts = C.gpts;
-  auto up = [&](auto& buf, const auto& v) {
-    buf.reserve(v.size());
-    h2d(buf.p, v.data(), v.size(), s);
-  };
-  up(d_gnode, gnode);
-  up(d_gbptr, gbptr);
-  up(d_gpptr, gpptr);
-  up(d_gpids, gpids);
-  up(d_gdptr, gdptr);
-  up(d_gdids, gdids);
-  up(d_gbgeo, gbgeo);
-  up(d_giota, giota);
-  up(d_bptr, bptr);
-  up(d_pptr, pptr);
-  up(d_pids, pids);
-  up(d_dptr, dptr);
-  up(d_dids, dids);
-  up(d_xptr, xptr);
-  up(d_xgi, xgi);
-  up(d_xnode, xnode);
-  up(d_bgeo, bgeo);
+  d_gpids.reserve(tot[0]);
+  d_gdids.reserve(tot[1]);
+  d_gnode.reserve(ng);
+  d_gbgeo.reserve(ng);
+  d_gbptr.reserve(ng + 1);
+  d_gpptr.reserve(ng + 1);
+  d_gdptr.reserve(ng + 1);
+  d_pids.reserve(tot[3]);
+  d_dids.reserve(tot[4]);
+  d_xgi.reserve(tot[5]);
+  d_xnode.reserve(tot[5]);
+  d_giota.reserve(M);
+  a.items = nullptr;
+  a.nitems = ntn;
+  a.ptr0 = C.ccptr.p;
+  a.ptr1 = C.cpptr.p;
+  a.ids0 = d_gpids.p;
+  a.ids1 = d_gdids.p;
+  hipchk(bltc::launch_dual_walk(a, false, true, s), "dual walk (nodes)");
+  hipchk(bltc::launch_dual_slots(C.flag.p, C.slot.p, ntn, ng, P, tgt->d_geo, tgt->d_range,
+                                 C.ccptr.p, C.cpptr.p, d_gnode.p, d_gbgeo.p, d_gbptr.p,
+                                 d_gpptr.p, d_gdptr.p, C.work.p, s),
+         "grid slots");
+  a.items = C.leaves.p;
+  a.nitems = nl;
+  a.ptr0 = d_pptr.p;
+  a.ptr1 = d_dptr.p;
+  a.ids0 = d_pids.p;
+  a.ids1 = d_dids.p;
+  hipchk(bltc::launch_dual_walk(a, true, true, s), "dual walk (leaves)");
+  hipchk(bltc::launch_dual_xlists(C.leaves.p, nl, tgt->d_parent, C.flag.p, C.slot.p, C.xcnt.p,
+                                  d_xptr.p, d_xgi.p, d_xnode.p, true, s),
+         "slot lists");
+  hipchk(bltc::launch_iota(d_giota.p, M, s), "grid point order");
+  const int wpb_t = (int)((lmax + bltc::kWave - 1) / bltc::kWave);
+  const int wpb_g = (int)((P + bltc::kWave - 1) / bltc::kWave);
   d_tgrid.reserve(ntn * 3 * n1);
   d_g.reserve(odim * M);
   d_gpts.reserve(3 * M);
@@ -210,15 +186,15 @@ void evaluate_dual(bltc_tree src, bltc_tree tgt, int kernel, double eps, int deg
   // the rule's lower degrees that the source side uses, derived from the top
   // degree's weights
   if (rule.deg_min > 0) {
-    std::vector<bool> used(degree, false);
-    for (int64_t A = 0; A < ntn; ++A)
-      for (const auto* lst : {&D.cc[A], &D.pc[A]})
-        for (int32_t e : *lst) {
-          const int dd = e >> bltc::kDegShift;
-          if (dd < degree) used[dd] = true;
-        }
+    uint32_t mk[2] = {0, 0};
+    C.mask.reserve(2);
+    hipchk(bltc::launch_degree_mask(nullptr, ng, d_gpptr.p, d_gpids.p, C.mask.p, s), "degrees");
+    hipchk(bltc::launch_degree_mask(nullptr, nl, d_pptr.p, d_pids.p, C.mask.p + 1, s),
+           "degrees");
+    d2h(mk, C.mask.p, 2, s);
+    sync(s);
     for (int dd = rule.deg_min; dd < degree; ++dd)
-      if (used[dd]) ensure_derived(src, dd, degree, s);
+      if ((mk[0] | mk[1]) >> dd & 1u) ensure_derived(src, dd, degree, s);
   }
 
   StageTimer ev(BLTC_STAGE_EVAL, s);
@@ -289,8 +265,13 @@ void evaluate_dual(bltc_tree src, bltc_tree tgt, int kernel, double eps, int deg
   da.out = out;
   if (ng > 0) hipchk(bltc::launch_dual_down(odim, n1, da, s), "dual down");
   ev.stop();
-  if (counts) std::memcpy(counts, D.cnt, sizeof D.cnt);
-  sync(s);   // the device lists go out of scope
+  if (counts) {
+    unsigned long long w[5];
+    d2h(w, C.work.p, 5, s);
+    sync(s);
+    for (int q = 0; q < 5; ++q) counts[q] = (int64_t)w[q];
+  }
+  sync(s);
 }
 
 }  // namespace

@@ -28,6 +28,7 @@ void destroy_tree(bltc_tree t) {
   for (auto& kv : t->spare_derived) destroy_degree(kv.second);
   dfree(t->d_perm); dfree(t->d_y); dfree(t->d_box); dfree(t->d_geo);
   dfree(t->d_range); dfree(t->d_kids); dfree(t->d_skip); dfree(t->d_w64); dfree(t->d_w32);
+  dfree(t->d_level); dfree(t->d_parent);
   dfree(t->d_cut); dfree(t->d_cut_anc); dfree(t->d_cut_first);
   dfree(t->d_chunks); dfree(t->d_chunk_ptr); dfree(t->d_partial); dfree(t->d_parents);
   delete t->dual;
@@ -260,6 +261,8 @@ void build_tree(const double* x, const double* y, const double* z, int64_t n,
   t->d_range = dalloc<int2>(nn);
   t->d_kids = dalloc<int2>(nn);
   t->d_skip = dalloc<int32_t>(nn);
+  t->d_level = dalloc<int32_t>(nn);
+  t->d_parent = dalloc<int32_t>(nn);
   t->d_chunks = dalloc<int4>(chunks.size());
   t->d_chunk_ptr = dalloc<int32_t>(nn + 1);
   if (!parents.empty()) t->d_parents = dalloc<int32_t>(parents.size());
@@ -268,6 +271,14 @@ void build_tree(const double* x, const double* y, const double* z, int64_t n,
   h2d(t->d_range, range.data(), nn, s);
   h2d(t->d_kids, kids.data(), nn, s);
   h2d(t->d_skip, skip.data(), nn, s);
+  h2d(t->d_level, H.level.data(), nn, s);
+  {
+    std::vector<int32_t> par(nn, -1);
+    for (int64_t q = 0; q < nn; ++q)
+      for (int32_t k = 0; k < H.count[q]; ++k) par[H.first[q] + k] = (int32_t)q;
+    h2d(t->d_parent, par.data(), nn, s);
+    sync(s);   // par goes out of scope
+  }
   h2d(t->d_chunks, chunks.data(), chunks.size(), s);
   h2d(t->d_chunk_ptr, cptr.data(), nn + 1, s);
   if (!parents.empty()) h2d(t->d_parents, parents.data(), parents.size(), s);

@@ -204,6 +204,10 @@ int check_tree_eval(bltc_tree t, int64_t m, int kernel, double eps, int degree, 
 struct bltc_dual_cache {
   bltc::api::DevBuf<int32_t> gnode, gbptr, gpptr, gpids, gdptr, gdids, giota, bptr, pptr, pids,
       dptr, dids, xptr, xgi, xnode;
+  // the device traversal's counts, offsets, slots and flags
+  bltc::api::DevBuf<int32_t> leaves, ncc, ncp, ccptr, cpptr, flag, slot, npc, npp, xcnt, ovf;
+  bltc::api::DevBuf<unsigned long long> work;
+  bltc::api::DevBuf<uint32_t> mask;
   bltc::api::DevBuf<double4> bgeo, gbgeo;
   bltc::api::DevBuf<double> tgrid, g, gpts;
 };

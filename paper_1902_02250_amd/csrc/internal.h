@@ -269,6 +269,54 @@ struct CostArgs {
   int32_t* err;
 };
 
+// The dual traversal of the cluster-cluster variant on the device: one wave
+// per target node (per-node mode: that node's CC and CP lists and the
+// evaluation counts) or per target leaf (per-leaf mode: the PC and PP
+// entries of the leaf and of all its ancestors).  The waves walk the source
+// tree over its cut (walk.h) with the target's level along its root path as
+// state; the decisions are the host traversal's, FP64 without contraction.
+constexpr int kDualMaxDepth = 32;      // most levels of either tree
+struct DualArgs {
+  Nodes src;                           // the source tree with its cut
+  const int32_t* slevel;               // [snn] source node depth
+  const double4* tgeo;                 // target tree: center, radius
+  const int2* trange;
+  const int2* tkids;
+  const int32_t* tparent;              // [tnn], -1 at the root
+  const int32_t* items;                // per-leaf mode: the leaves; per-node mode: NULL
+  int64_t nitems;
+  double th2;                          // theta theta
+  int64_t P;                           // (n + 1)^3
+  int32_t n1;
+  Rule rule;
+  int32_t* cnt0;                       // count pass: CC (per node) or PC (per leaf) entries
+  int32_t* cnt1;                       // CP (per node) or PP (per leaf) entries
+  unsigned long long* work;            // per-node count pass: [5] evaluations CC, PC, CP, PP, downward
+  const int32_t* ptr0;                 // fill pass: offsets [nitems + 1]
+  const int32_t* ptr1;
+  int32_t* ids0;
+  int32_t* ids1;
+};
+hipError_t launch_dual_walk(const DualArgs& a, bool per_leaf, bool fill, hipStream_t s);
+// Grid slots of the target nodes with CC or CP work: flag[q] = 1 for them.
+hipError_t launch_dual_flags(const int32_t* ncc, const int32_t* ncp, int64_t nn, int32_t* flag,
+                             hipStream_t s);
+// For every flagged node q: slot gi = slot[q], gnode[gi] = q, gbgeo[gi] = its
+// geometry, gbptr[gi] = gi P, gpptr[gi] = ccptr[q], gdptr[gi] = cpptr[q], and
+// work[4] += |q| P; entry ng of gbptr, gpptr, gdptr closes the arrays.
+hipError_t launch_dual_slots(const int32_t* flag, const int32_t* slot, int64_t nn, int64_t ng,
+                             int64_t P, const double4* tgeo, const int2* trange,
+                             const int32_t* ccptr, const int32_t* cpptr, int32_t* gnode,
+                             double4* gbgeo, int32_t* gbptr, int32_t* gpptr, int32_t* gdptr,
+                             unsigned long long* work, hipStream_t s);
+// Per leaf (leaves[l]): the slots of the flagged nodes on its root path, root
+// first (count pass: xcnt[l]; fill pass: xgi and xnode at xptr[l]).
+hipError_t launch_dual_xlists(const int32_t* leaves, int64_t nl, const int32_t* tparent,
+                              const int32_t* flag, const int32_t* slot, int32_t* xcnt,
+                              const int32_t* xptr, int32_t* xgi, int32_t* xnode, bool fill,
+                              hipStream_t s);
+hipError_t launch_iota(int32_t* p, int64_t n, hipStream_t s);
+
 // ---- launchers (defined in the .hip files) --------------------------------
 // sgeo[i] = (target spos[i], radius 0): a sample as a batch of one target,
 // whose batch MAC is the per-target MAC.
@@ -402,6 +450,8 @@ struct bltc_tree_s {
   int2* d_range = nullptr;
   int2* d_kids = nullptr;
   int32_t* d_skip = nullptr;   // depth-first successor past each subtree
+  int32_t* d_level = nullptr;  // node depth
+  int32_t* d_parent = nullptr; // parent node, -1 at the root
   int32_t* d_cut = nullptr;    // the cut for lane-shared walks (see Nodes)
   int32_t* d_cut_anc = nullptr;
   uint32_t* d_cut_first = nullptr;

@@ -125,6 +125,20 @@ def test_dual_rule_matches_oracle(torch, orc, kernel, precision, tol):
     close(orc, ref, got, tol)
 
 
+def test_dual_deep_union_counts(torch, orc):
+    """The device traversal on a deeper, uneven pair of trees: 120,000 points
+    of the union workload as sources and targets, source leaves of 300 and
+    target leaves of 100, with the separation rule: every type's count
+    equals the oracle's traversal and the FP64 result its sum."""
+    src = inputs.points("union", 120000, 97)
+    w = inputs.weights(120000, 97)
+    got, cnt = _run(torch, "stokeslet", src, src, w, 0.002, 3, 0.85, 300, 100, deg_min=1)
+    ref, rcnt = orc.dual_treecode("stokeslet", src, src, w, 0.002, 3, 0.85, 300, 100, deg_min=1)
+    assert np.array_equal(cnt, rcnt), (cnt, rcnt)
+    assert np.all(cnt[:4] > 0)
+    close(orc, ref, got, FP64_TOL, elem_tol=1e-10)
+
+
 def test_dual_rule_poly_exact(torch, orc):
     src = inputs.points("mixture", 20000, 99)
     tgt = inputs.points("uniform", 19000, 100)
