@@ -119,7 +119,7 @@ def test_enomem_leaves_handles_usable(torch, orc):
     # the learned path's scratch
     sel = bltc.Selector(selector.MODEL_PATH)
     T.compute_weights(d_w, 10)
-    for k in (1, 4, 9, 15):
+    for k in range(1, 40, 2):
         out = _sentinel(torch, (3, n))
         bltc.inject_alloc_failure(k)
         try:
@@ -136,6 +136,45 @@ def test_enomem_leaves_handles_usable(torch, orc):
     a, ca, _, _ = bltc.evaluate_adaptive(T, G, "stokeslet", 0.01, sel, 1e-5, 10, 0.6)
     b, cb, _, _ = bltc.evaluate_adaptive(T, G, "stokeslet", 0.01, sel, 1e-5, 10, 0.6)
     assert np.array_equal(ca, cb) and torch.equal(a, b)
+
+
+def test_dual_enomem_and_determinism(torch, orc):
+    """The cluster-cluster variant's device traversal and buffers: a failure
+    at each of its allocations in turn (on a fresh target tree) returns
+    BLTC_ENOMEM with no output written, the next call gives the oracle's
+    result, and two calls are bit-identical."""
+    n = 12000
+    src = inputs.points("mixture", n, 94)
+    w = inputs.weights(n, 94)
+    d_src, d_w = _d(torch, src), _d(torch, w)
+    S = bltc.Tree(d_src, 200)
+    S.compute_weights(d_w, 4)
+    T = bltc.Tree(d_src, 60)
+    failures = 0
+    for k in range(1, 80):
+        out = _sentinel(torch, (3, n))
+        bltc.inject_alloc_failure(k)
+        try:
+            bltc.evaluate_dual(S, T, "stokeslet", 0.01, 4, 0.8, precision="fp64", out=out,
+                               deg_min=1)
+        except bltc.BltcError as e:
+            assert e.status == 2, e
+            torch.cuda.synchronize()
+            assert _untouched(out), k
+            failures += 1
+            continue
+        finally:
+            bltc.inject_alloc_failure(0)
+        break
+    else:
+        raise AssertionError("the dual evaluation never completed")
+    assert failures >= 10
+    ref, rcnt = orc.dual_treecode("stokeslet", src, src, w, 0.01, 4, 0.8, 200, 60, deg_min=1)
+    a, ca = bltc.evaluate_dual(S, T, "stokeslet", 0.01, 4, 0.8, precision="fp64", deg_min=1)
+    b, cb = bltc.evaluate_dual(S, T, "stokeslet", 0.01, 4, 0.8, precision="fp64", deg_min=1)
+    assert np.array_equal(ca, rcnt) and np.array_equal(ca, cb)
+    assert torch.equal(a, b)
+    close(orc, ref, a.cpu().numpy(), 1e-12, what="dual after the injected failures")
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32_fp64acc", "fp32_kahan"])
