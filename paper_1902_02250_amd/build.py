@@ -23,9 +23,9 @@ HOST_UNITS = ["host.cpp", "api_tree.cpp", "api_eval.cpp", "api_select.cpp", "api
               "api_noalloc.cpp", "tree_host.cpp"]
 SOURCES = HOST_UNITS + ["k_prep.hip", "k_lists.hip", "k_upward.hip", "k_p2p.hip",
                         "k_direct.hip", "k_mlp.hip", "k_select.hip", "k_tree.hip", "k_dual.hip",
-                        "k_sample.hip", "k_dual_walk.hip"]
+                        "k_sample.hip", "k_dual_walk.hip", "k_kd.hip"]
 EXACT = set(HOST_UNITS) | {"k_prep.hip", "k_lists.hip", "k_tree.hip", "k_select.hip",
-                           "k_dual_walk.hip"}
+                           "k_dual_walk.hip", "k_kd.hip"}
 
 COMMON = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

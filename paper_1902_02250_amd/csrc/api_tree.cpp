@@ -486,6 +486,99 @@ void destroy_targets(bltc_targets g) {
   delete g;
 }
 
+namespace {
+
+// The starts of the balanced k-d batches of m targets in position order: a
+// part of c > bs targets has a first part of bs floor(nb/2), nb = ceil(c/bs).
+void kd_batch_starts(int64_t m, int32_t bs, std::vector<int32_t>& bptr) {
+  bptr.clear();
+  std::vector<std::pair<int64_t, int64_t>> st;
+  if (m > 0) st.push_back({0, m});
+  while (!st.empty()) {
+    const auto [b, c] = st.back();
+    st.pop_back();
+    if (c <= bs) {
+      bptr.push_back((int32_t)b);
+      continue;
+    }
+    const int64_t nb = (c + bs - 1) / bs, left = (int64_t)bs * (nb / 2);
+    st.push_back({b + left, c - left});
+    st.push_back({b, left});
+  }
+  bptr.push_back((int32_t)m);
+}
+
+// perm (device, m): the balanced k-d order (k_kd.hip).
+void kd_batches_device(const double* x, const double* y, const double* z, int64_t m,
+                       int32_t bs, int32_t* perm, hipStream_t s) {
+  if (m == 0) return;
+  std::vector<std::pair<int64_t, int64_t>> segs{{0, m}};
+  int64_t n2 = 2048;
+  while (n2 < m) n2 <<= 1;
+  DevBuf<uint64_t> hi, lo;
+  hi.reserve(n2);
+  lo.reserve(n2);
+  hipchk(bltc::launch_kd_init(hi.p, lo.p, m, n2, s), "k-d keys");
+  DevBuf<int4> d_chunks;
+  DevBuf<int32_t> d_cut, d_cfirst, d_axis;
+  DevBuf<double> d_part;
+  auto large = [&] {
+    for (const auto& sg : segs)
+      if (sg.second > bltc::kKdLocal) return true;
+    return false;
+  };
+  while (large()) {
+    if (segs.size() >= (size_t)(1 << 20))
+      throw HipError{BLTC_EINVAL, "too many targets for the k-d batches"};
+    std::vector<int4> chunks;
+    std::vector<int32_t> cut(segs.size()), cfirst(segs.size() + 1);
+    for (size_t q = 0; q < segs.size(); ++q) {
+      const int64_t b = segs[q].first, c = segs[q].second;
+      cut[q] = c > bltc::kKdLocal ? 1 : 0;
+      cfirst[q] = (int32_t)chunks.size();
+      for (int64_t p = b; p < b + c; p += bltc::kKdChunk)
+        chunks.push_back(make_int4((int)q, (int)p, (int)std::min(b + c, p + bltc::kKdChunk), 0));
+    }
+    cfirst[segs.size()] = (int32_t)chunks.size();
+    d_chunks.reserve(chunks.size());
+    d_cut.reserve(cut.size());
+    d_cfirst.reserve(cfirst.size());
+    d_axis.reserve(segs.size());
+    d_part.reserve(6 * chunks.size());
+    h2d(d_chunks.p, chunks.data(), chunks.size(), s);
+    h2d(d_cut.p, cut.data(), cut.size(), s);
+    h2d(d_cfirst.p, cfirst.data(), cfirst.size(), s);
+    hipchk(bltc::launch_kd_level(d_chunks.p, (int32_t)chunks.size(), d_cut.p, d_cfirst.p,
+                                 (int32_t)segs.size(), x, y, z, d_part.p, d_axis.p, hi.p, lo.p,
+                                 n2, s),
+           "k-d level");
+    sync(s);   // the staged layout goes out of scope
+    std::vector<std::pair<int64_t, int64_t>> next;
+    for (const auto& sg : segs) {
+      const int64_t b = sg.first, c = sg.second;
+      if (c <= bltc::kKdLocal) {
+        next.push_back(sg);
+        continue;
+      }
+      const int64_t nb = (c + bs - 1) / bs, left = (int64_t)bs * (nb / 2);
+      next.push_back({b, left});
+      next.push_back({b + left, c - left});
+    }
+    segs.swap(next);
+  }
+  std::vector<int2> parts(segs.size());
+  for (size_t q = 0; q < segs.size(); ++q)
+    parts[q] = make_int2((int)segs[q].first, (int)segs[q].second);
+  DevBuf<int2> d_parts;
+  d_parts.reserve(parts.size());
+  h2d(d_parts.p, parts.data(), parts.size(), s);
+  hipchk(bltc::launch_kd_local(d_parts.p, (int32_t)parts.size(), lo.p, x, y, z, bs, perm, s),
+         "k-d parts");
+  sync(s);
+}
+
+}  // namespace
+
 void build_targets(const double* x, const double* y, const double* z,
                    int64_t m, int32_t bs, int32_t leaf, int64_t gmax,
                    hipStream_t s, bltc_targets g) {
@@ -493,19 +586,17 @@ void build_targets(const double* x, const double* y, const double* z,
   B = bltc::HostBatches();
   std::vector<int32_t> bend;
   if (leaf == 0) {
-    // balanced k-d batches: the cut on the host from a copy of the
-    // coordinates; the tree-ordered copy gathered on the device
-    std::vector<double> h(3 * (size_t)m);
-    d2h(h.data(), x, m, s);
-    d2h(h.data() + m, y, m, s);
-    d2h(h.data() + 2 * m, z, m, s);
-    sync(s);
-    bltc::kd_batches(h.data(), h.data() + m, h.data() + 2 * m, m, bs, B.perm, B.bptr);
-    bend.assign(B.bptr.begin() + 1, B.bptr.end());
+    // balanced k-d batches, cut on the device; the part sizes follow from m
+    // and bs alone, so the layout of every level comes from the host
     g->d_tperm = dalloc<int32_t>(m);
     g->d_x = dalloc<double>(3 * m);
-    h2d(g->d_tperm, B.perm.data(), m, s);
+    kd_batches_device(x, y, z, m, bs, g->d_tperm, s);
+    B.perm.resize(m);
+    d2h(B.perm.data(), g->d_tperm, m, s);
+    kd_batch_starts(m, bs, B.bptr);
+    bend.assign(B.bptr.begin() + 1, B.bptr.end());
     hipchk(bltc::launch_gather_points(x, y, z, g->d_tperm, m, g->d_x, s), "gather targets");
+    sync(s);
   } else {
     // the order tree on the device; groups and batch bounds on the host;
     // batch geometry on the device

@@ -317,6 +317,24 @@ hipError_t launch_dual_xlists(const int32_t* leaves, int64_t nl, const int32_t* 
                               hipStream_t s);
 hipError_t launch_iota(int32_t* p, int64_t n, hipStream_t s);
 
+// Balanced k-d target batches on the device (k_kd.hip).  Parts above
+// kKdLocal targets are cut level by level over all of them: chunks (part,
+// begin, end) of at most kKdChunk positions, each part's chunks consecutive
+// from cfirst[part]; keys (part, coordinate, index) in hi/lo (n2, a power of
+// two >= 2048, padded with all-ones keys), lo's low 44 bits the index.
+// Parts of at most kKdLocal targets finish in one work group each and write
+// perm.
+constexpr int kKdLocal = 4096;
+constexpr int kKdChunk = 4096;
+hipError_t launch_kd_init(uint64_t* hi, uint64_t* lo, int64_t m, int64_t n2, hipStream_t s);
+hipError_t launch_kd_level(const int4* chunks, int32_t nchunks, const int32_t* cut,
+                           const int32_t* cfirst, int32_t nseg, const double* x,
+                           const double* y, const double* z, double* part, int32_t* axis,
+                           uint64_t* hi, uint64_t* lo, int64_t n2, hipStream_t s);
+hipError_t launch_kd_local(const int2* parts, int32_t nparts, const uint64_t* lo,
+                           const double* x, const double* y, const double* z, int32_t bs,
+                           int32_t* perm, hipStream_t s);
+
 // ---- launchers (defined in the .hip files) --------------------------------
 // sgeo[i] = (target spos[i], radius 0): a sample as a batch of one target,
 // whose batch MAC is the per-target MAC.

@@ -98,10 +98,12 @@ def test_device_tree_degenerate(torch, orc):
 def test_device_tree_many_chunks(torch, orc, dist, n, leaf):
     """Clusters larger than one build work group (8192 particles), ragged
     chunk tails, slab and pair geometries; the batches built from the device
-    order tree match the oracle's."""
+    order tree, and the balanced k-d batches (several levels of device-wide
+    cuts before the per-work-group recursion), match the oracle's."""
     p = inputs.points(dist, n, 19)
     _device_vs_host(torch, orc, p, leaf)
-    for bs, ol, gm in [(64, 32, 512), (100, 9000, 10 ** 9), (1, 64, 256)]:
+    for bs, ol, gm in [(64, 32, 512), (100, 9000, 10 ** 9), (1, 64, 256), (64, 0, 512),
+                       (100, 0, 512)]:
         g = bltc.Targets(_d(torch, p), bs, ol, gm).export()
         ob = orc.batches(p, bs, ol, gm)
         for x, y in zip([g["tperm"], g["bptr"], g["bcenter"], g["bradius"]], ob):
