@@ -178,10 +178,12 @@ int bltc_modified_weights_export(bltc_tree t, int32_t degree, double* fhat,
  *    the groups, each cut into consecutive batches of batch_size targets, so
  *    a batch never spans two groups and its radius is bounded by its group's.
  * Each batch gets its tight box, center and radius like a cluster.  The k-d
- * cut runs on the host from a copy of the coordinates; the order tree is
- * built on the device as in bltc_build_tree, the group and batch bounds on
- * the host from its node arrays; the batch boxes on the device
- * (synchronises).  The order and batches live on the device. */
+ * cut runs on the device (the part sizes, which depend on m and batch_size
+ * only, are laid out on the host); the order tree is built on the device as
+ * in bltc_build_tree, the group and batch bounds on the host from its node
+ * arrays; the batch boxes on the device (synchronises).  The order and
+ * batches live on the device; a host copy of the order is kept for
+ * bltc_targets_export. */
 int bltc_build_targets(const double* x, const double* y, const double* z,
                        int64_t m, int32_t batch_size, int32_t order_leaf,
                        int64_t group_max, void* stream, bltc_targets* out);
@@ -263,8 +265,10 @@ int bltc_noalloc_scratch_bytes(int64_t* bytes);
  * terms.  With opt->deg_min >= 1 the separation rule (see bltc_options)
  * picks the degree of the source side of each CC and PC pair from the
  * pair's ratio (r_A + r_C)/R; target grids and the downward interpolation
- * keep `degree`.  The traversal and its lists are built on the host;
- * synchronises on stream. */
+ * keep `degree`.  The traversal runs on the device: per target node its CC
+ * and CP lists, per target leaf the PC and PP entries of its root path; the
+ * trees may have at most 30 (source) and 31 (target) levels below the root
+ * (BLTC_EINVAL beyond).  Synchronises on stream. */
 int bltc_evaluate_dual(bltc_tree src, bltc_tree tgt, int32_t kernel, double eps,
                        int32_t degree, double theta, const bltc_options* opt, double* out,
                        int64_t* counts, void* stream);
