@@ -173,11 +173,16 @@ bltc::P2PArgs p2p_args(bltc_tree t, bltc_targets g, const bltc::ListSet& L, int 
 
 void run_p2p(bltc_tree t, bltc_targets g, const bltc::ListSet& L, int kernel, double eps,
              int degree, const bltc_options& o, const int32_t* bmap, int64_t nmap,
-             double* out, hipStream_t s, const int4* split, int64_t nsplit, double* partial) {
+             double* out, hipStream_t s, const int4* split, int64_t nsplit, double* partial,
+             const int32_t* xstart, int32_t xmax) {
   bltc::P2PArgs a = p2p_args(t, g, L, kernel, eps, degree, o, bmap, nmap, out);
   a.split = split;
   a.nsplit = nsplit;
   a.partial = partial;
+  if (xstart && xmax > 0 && !bmap && !split) {
+    a.xstart = xstart;
+    a.xmax = xmax;
+  }
   StageTimer ev(BLTC_STAGE_EVAL, s);
   hipchk(bltc::launch_p2p(kernel, o.precision, degree, a, s), "p2p");
   ev.stop();
@@ -192,7 +197,33 @@ void evaluate_tree(bltc_tree t, bltc_targets g, int kernel, double eps,
   const bltc::Rule rule = make_rule(theta, degree, o.deg_min);
   build_lists(t, g, theta, nullptr, g->ls[0], s, &np, &nd, &rule);
   derive_used_degrees(t, g, g->ls[0], rule.deg_min, {{degree, {nullptr, g->nb}}}, s);
-  run_p2p(t, g, g->ls[0], kernel, eps, degree, o, nullptr, 0, out, s);
+  const int32_t xmax = work_ranges(g, g->ls[0], degree, s);
+  run_p2p(t, g, g->ls[0], kernel, eps, degree, o, nullptr, 0, out, s, nullptr, 0, nullptr,
+          g->d_xstart, xmax);
+}
+
+int32_t work_ranges(bltc_targets g, const bltc::ListSet& L, int degree, hipStream_t s) {
+  const int64_t nb = g->nb;
+  if (nb == 0) return 0;
+  ensure_alloc(g->d_xwork, 2 * nb + 6);
+  ensure_alloc(g->d_xstart, 18);
+  const int wpb = (g->batch_size + bltc::kWave - 1) / bltc::kWave;
+  hipchk(bltc::launch_xcd_ranges(L.cnt, L.cnt + 2 * nb, nb, degree, wpb, g->d_xwork,
+                                 g->d_xstart, s),
+         "XCD ranges");
+  int32_t xs[18], ovf = 0;
+  d2h(xs, g->d_xstart, 18, s);
+  d2h(&ovf, g->d_xwork + 2 * nb + 1, 1, s);
+  sync(s);
+  if (ovf) return 0;
+  // the equal-count split is kept unless one XCD would get 3% more than an
+  // eighth of the work
+  int32_t most = 0;
+  for (int x = 0; x < 8; ++x) most = std::max(most, xs[9 + x]);
+  if ((double)most <= 1.03 * (double)xs[17] / 8.0) return 0;
+  int32_t xmax = 0;
+  for (int x = 0; x < 8; ++x) xmax = std::max(xmax, xs[x + 1] - xs[x]);
+  return xmax;
 }
 
 int check_tree_eval(bltc_tree t, int64_t m, int kernel, double eps, int degree, double theta,

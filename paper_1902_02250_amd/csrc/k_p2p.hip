@@ -320,7 +320,8 @@ struct Acc {
 
 // Blocks are dispatched round robin over the 8 XCDs; give each XCD a
 // contiguous range of batches so neighbouring batches, which share most of
-// their lists, share an L2.
+// their lists, share an L2.  (The evaluation passes ranges of equal
+// modelled work instead, xstart, when it has them.)
 __device__ __forceinline__ int xcd_block(int blk, int nblk) {
   const int per = nblk / 8, rem = nblk % 8;
   const int xcd = blk % 8, idx = blk / 8;
@@ -382,7 +383,7 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void k_p2p(
     const float* __restrict__ w32, const double* __restrict__ w64, int64_t n,
     double eps, int poly_p, double poly_c, double su, double sw,
     double* __restrict__ out, DegTables dt, const int4* __restrict__ split,
-    double* __restrict__ partial) {
+    double* __restrict__ partial, const int32_t* __restrict__ xstart) {
   constexpr int OD = Dims<KERN>::OD;
   constexpr int WD = Dims<KERN>::WD;
   constexpr int NK = N1 * N1 * N1;
@@ -396,7 +397,14 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void k_p2p(
   // compiler so, which keeps everything derived from it in scalar registers
   const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  const int gw = xcd_block(blockIdx.x, nblk) * kWavesPerBlock + wid;
+  int gw;
+  if (xstart) {   // XCD x serves the waves [xstart[x], xstart[x + 1])
+    const int xcd = blockIdx.x % 8;
+    gw = xstart[xcd] + (int)(blockIdx.x / 8) * kWavesPerBlock + wid;
+    if (gw >= xstart[xcd + 1]) return;
+  } else {
+    gw = xcd_block(blockIdx.x, nblk) * kWavesPerBlock + wid;
+  }
   if (gw >= nwaves) return;
   int b, wv, pbeg, pend, dbeg, dend;
   if (split) {   // a slice of a batch's proxy list or of its direct list
@@ -590,7 +598,10 @@ hipError_t run_p2p(const P2PArgs& a, hipStream_t s) {
   if (nw64 == 0) return hipSuccess;
   if (nw64 > 0x7fffffff - kWavesPerBlock) return hipErrorInvalidValue;
   const int nwaves = (int)nw64;
-  const int nblk = (nwaves + kWavesPerBlock - 1) / kWavesPerBlock;
+  // with work-balanced XCD ranges: 8 x the longest range's blocks
+  const int nblk = a.xstart ? 8 * ((a.xmax + kWavesPerBlock - 1) / kWavesPerBlock)
+                            : (nwaves + kWavesPerBlock - 1) / kWavesPerBlock;
+  if (nblk == 0) return hipSuccess;
   const bool zeps = a.eps == 0.0;
   DegTables dt;
   bool rule = false;
@@ -604,7 +615,8 @@ hipError_t run_p2p(const P2PArgs& a, hipStream_t s) {
                        a.tperm, a.bptr, a.bgeo, nblk, nwaves, a.wpb, a.bmap, a.pptr, a.pids,
                        a.dptr, a.dids, a.range, a.grid, (const float*)a.fhat,
                        (const double*)a.fhat, a.ys, a.w32, a.w64, a.n, a.eps,
-                       a.poly_p, a.poly_c, a.scale_u, a.scale_w, a.out, dt, a.split, a.partial);
+                       a.poly_p, a.poly_c, a.scale_u, a.scale_w, a.out, dt, a.split, a.partial,
+                       a.xstart);
   };
   if (rule) {
     if (zeps)
