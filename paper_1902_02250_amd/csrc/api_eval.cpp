@@ -179,7 +179,7 @@ void run_p2p(bltc_tree t, bltc_targets g, const bltc::ListSet& L, int kernel, do
   a.split = split;
   a.nsplit = nsplit;
   a.partial = partial;
-  if (xstart && xmax > 0 && !bmap && !split) {
+  if (xstart && xmax > 0 && !split) {
     a.xstart = xstart;
     a.xmax = xmax;
   }
@@ -202,18 +202,20 @@ void evaluate_tree(bltc_tree t, bltc_targets g, int kernel, double eps,
           g->d_xstart, xmax);
 }
 
-int32_t work_ranges(bltc_targets g, const bltc::ListSet& L, int degree, hipStream_t s) {
-  const int64_t nb = g->nb;
-  if (nb == 0) return 0;
+int32_t work_ranges(bltc_targets g, const bltc::ListSet& L, int degree, hipStream_t s,
+                    const int32_t* bmap, int64_t nmap, int slot) {
+  const int64_t nb = g->nb, nw = bmap ? nmap : nb;
+  if (nw == 0) return 0;
   ensure_alloc(g->d_xwork, 2 * nb + 6);
-  ensure_alloc(g->d_xstart, 18);
+  ensure_alloc(g->d_xstart, 18 * (bltc::kMaxDegree + 1));
+  int32_t* xst = g->d_xstart + 18 * slot;
   const int wpb = (g->batch_size + bltc::kWave - 1) / bltc::kWave;
-  hipchk(bltc::launch_xcd_ranges(L.cnt, L.cnt + 2 * nb, nb, degree, wpb, g->d_xwork,
-                                 g->d_xstart, s),
+  hipchk(bltc::launch_xcd_ranges(L.cnt, L.cnt + 2 * nb, bmap, nw, degree, wpb, g->d_xwork, xst,
+                                 s),
          "XCD ranges");
   int32_t xs[18], ovf = 0;
-  d2h(xs, g->d_xstart, 18, s);
-  d2h(&ovf, g->d_xwork + 2 * nb + 1, 1, s);
+  d2h(xs, xst, 18, s);
+  d2h(&ovf, g->d_xwork + 2 * nw + 1, 1, s);
   sync(s);
   if (ovf) return 0;
   // the equal-count split is kept unless one XCD would get 3% more than an

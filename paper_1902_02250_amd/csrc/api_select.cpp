@@ -450,14 +450,21 @@ void evaluate_adaptive(bltc_tree t, bltc_targets g, int kernel, double eps,
   og.deg_min = rule_min;
   // the degree groups write disjoint targets: with more than one, they run
   // concurrently on side streams, largest first
+  // (each group's XCD ranges of equal modelled work, as for a fixed evaluation)
   if (spans.size() == 1) {
-    run_p2p(t, g, g->ls[0], kernel, eps, spans[0].first, og, g->d_bmap, nb, out, s);
+    const int32_t xmax = work_ranges(g, g->ls[0], spans[0].first, s, g->d_bmap, nb, 0);
+    run_p2p(t, g, g->ls[0], kernel, eps, spans[0].first, og, g->d_bmap, nb, out, s, nullptr, 0,
+            nullptr, g->d_xstart, xmax);
   } else {
     std::sort(spans.begin(), spans.end(), [](const auto& a, const auto& b) {
       const double wa = (double)a.second.second * std::pow(a.first + 1.0, 3);
       const double wb = (double)b.second.second * std::pow(b.first + 1.0, 3);
       return wa > wb;
     });
+    std::vector<int32_t> xmax(spans.size());
+    for (size_t i = 0; i < spans.size(); ++i)
+      xmax[i] = work_ranges(g, g->ls[0], spans[i].first, s, g->d_bmap + spans[i].second.first,
+                            spans[i].second.second, (int)i);
     hipEvent_t ready = evs.make();
     hipchk(hipEventRecord(ready, s), "hipEventRecord");
     std::vector<hipEvent_t> done;
@@ -465,7 +472,8 @@ void evaluate_adaptive(bltc_tree t, bltc_targets g, int kernel, double eps,
       hipStream_t ss = side_stream((int)i);
       hipchk(hipStreamWaitEvent(ss, ready, 0), "hipStreamWaitEvent");
       run_p2p(t, g, g->ls[0], kernel, eps, spans[i].first, og,
-              g->d_bmap + spans[i].second.first, spans[i].second.second, out, ss);
+              g->d_bmap + spans[i].second.first, spans[i].second.second, out, ss, nullptr, 0,
+              nullptr, g->d_xstart + 18 * i, xmax[i]);
       if (i + kSideStreams >= spans.size()) {   // last launch on this side stream
         hipEvent_t e = evs.make();
         hipchk(hipEventRecord(e, ss), "hipEventRecord");

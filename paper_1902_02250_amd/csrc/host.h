@@ -188,11 +188,13 @@ void run_p2p(bltc_tree t, bltc_targets g, const bltc::ListSet& L, int kernel, do
              int degree, const bltc_options& o, const int32_t* bmap, int64_t nmap,
              double* out, hipStream_t s, const int4* split = nullptr, int64_t nsplit = 0,
              double* partial = nullptr, const int32_t* xstart = nullptr, int32_t xmax = 0);
-// XCD ranges of equal modelled work for an evaluation of all batches with
-// the lists L (device xstart in g); returns the longest range in waves, or 0
+// XCD ranges of equal modelled work for an evaluation of all batches (or of
+// bmap[0..nmap)) with the lists L (device, g->d_xstart + 18 slot); returns
+// the longest range in waves, or 0
 // when the kernel's own equal-count ranges are within 3% of balanced (then
 // they apply).  Synchronises.
-int32_t work_ranges(bltc_targets g, const bltc::ListSet& L, int degree, hipStream_t s);
+int32_t work_ranges(bltc_targets g, const bltc::ListSet& L, int degree, hipStream_t s,
+                    const int32_t* bmap = nullptr, int64_t nmap = 0, int slot = 0);
 void evaluate_tree(bltc_tree t, bltc_targets g, int kernel, double eps, int degree,
                    double theta, const bltc_options& o, double* out, hipStream_t s);
 // The checks shared by the entry points that evaluate a built tree: handles,

@@ -98,11 +98,13 @@ inline unsigned blocks(int64_t n, int threads) {
 // cluster costs (0.69 n1 + 0.5) n1^2 + 2.5 and a near-field source 1, the
 // weights of the compiled loops (the selector's cost model).
 __global__ void k_batch_work(const int32_t* __restrict__ pcnt, const int32_t* __restrict__ scnt,
-                             int64_t nb, double per_cluster, int32_t* __restrict__ w) {
-  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= nb) return;
+                             const int32_t* __restrict__ bmap, int64_t nb, double per_cluster,
+                             int32_t* __restrict__ w) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nb) return;
+  const int64_t b = bmap ? bmap[i] : i;
   const double v = ((double)pcnt[b] * per_cluster + (double)scnt[b]) / 4096.0 + 1.0;
-  w[b] = v < 2147483647.0 ? (int32_t)v : 0x7fffffff;
+  w[i] = v < 2147483647.0 ? (int32_t)v : 0x7fffffff;
 }
 
 // xstart[x] = wpb times the first batch whose exclusive work prefix reaches
@@ -170,8 +172,9 @@ hipError_t launch_exclusive_scan(const int32_t* in, int64_t n, int32_t* out,
   return hipGetLastError();
 }
 
-hipError_t launch_xcd_ranges(const int32_t* pcnt, const int32_t* scnt, int64_t nb, int degree,
-                             int wpb, int32_t* scratch, int32_t* xstart, hipStream_t s) {
+hipError_t launch_xcd_ranges(const int32_t* pcnt, const int32_t* scnt, const int32_t* bmap,
+                             int64_t nb, int degree, int wpb, int32_t* scratch, int32_t* xstart,
+                             hipStream_t s) {
   if (nb == 0) return hipSuccess;
   const double n1 = degree + 1;
   const double per_cluster = (0.69 * n1 + 0.5) * n1 * n1 + 2.5;
@@ -179,7 +182,7 @@ hipError_t launch_xcd_ranges(const int32_t* pcnt, const int32_t* scnt, int64_t n
   int32_t* pre = scratch + nb;     // [nb + 1]
   int32_t* ovf = pre + nb + 1;     // [1]
   hipLaunchKernelGGL(k_batch_work, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, s, pcnt,
-                     scnt, nb, per_cluster, w);
+                     scnt, bmap, nb, per_cluster, w);
   if (hipError_t e = launch_exclusive_scan(w, nb, pre, ovf, s)) return e;
   hipLaunchKernelGGL(k_xcd_ranges, dim3(1), dim3(64), 0, s, pre, nb, wpb, xstart);
   return hipGetLastError();
