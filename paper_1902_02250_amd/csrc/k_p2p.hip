@@ -648,6 +648,33 @@ hipError_t dispatch_degree(int degree, const P2PArgs& a, hipStream_t s) {
 
 }  // namespace
 
+#if defined(BLTC_P2P_KERN) && defined(BLTC_P2P_PREC)
+// This object holds the kernels of one (kernel, precision) pair: the source
+// is compiled once per pair (with -DBLTC_P2P_KERN and -DBLTC_P2P_PREC) so the
+// template matrix builds in parallel, and once without them for the
+// dispatcher below.
+#define BLTC_P2P_NAME2(k, p) p2p_k##k##_p##p
+#define BLTC_P2P_NAME(k, p) BLTC_P2P_NAME2(k, p)
+hipError_t BLTC_P2P_NAME(BLTC_P2P_KERN, BLTC_P2P_PREC)(int degree, const P2PArgs& a,
+                                                      hipStream_t s) {
+  return dispatch_degree<BLTC_P2P_KERN, BLTC_P2P_PREC>(degree, a, s);
+}
+#else
+// one entry per (kernel, precision) pair, each in its own object
+hipError_t p2p_k0_p0(int degree, const P2PArgs& a, hipStream_t s);
+hipError_t p2p_k0_p1(int degree, const P2PArgs& a, hipStream_t s);
+hipError_t p2p_k0_p2(int degree, const P2PArgs& a, hipStream_t s);
+hipError_t p2p_k1_p0(int degree, const P2PArgs& a, hipStream_t s);
+hipError_t p2p_k1_p1(int degree, const P2PArgs& a, hipStream_t s);
+hipError_t p2p_k1_p2(int degree, const P2PArgs& a, hipStream_t s);
+hipError_t p2p_k2_p0(int degree, const P2PArgs& a, hipStream_t s);
+hipError_t p2p_k2_p1(int degree, const P2PArgs& a, hipStream_t s);
+hipError_t p2p_k2_p2(int degree, const P2PArgs& a, hipStream_t s);
+hipError_t p2p_k100_p0(int degree, const P2PArgs& a, hipStream_t s);
+static_assert(KSTOKES == 0 && KROT == 1 && KFULL == 2 && KPOLY == 100 && BLTC_FP64 == 0 &&
+                  BLTC_FP32_FP64ACC == 1 && BLTC_FP32_KAHAN == 2,
+              "the entry names follow the kernel and precision codes");
+
 hipError_t launch_split_reduce(const int32_t* sptr, const int32_t* bmap, int64_t nr,
                                const int32_t* bptr, const int32_t* tperm, const double* partial,
                                int odim, double su, double sw, int64_t m, double* out,
@@ -663,21 +690,22 @@ hipError_t launch_p2p(int kernel, int precision, int degree, const P2PArgs& a,
   if (a.nb == 0) return hipSuccess;
   if (kernel == KPOLY) {
     if (precision != BLTC_FP64) return hipErrorInvalidValue;
-    return dispatch_degree<KPOLY, BLTC_FP64>(degree, a, s);
+    return p2p_k100_p0(degree, a, s);
   }
   if (kernel == KSTOKES) {
-    if (precision == BLTC_FP64) return dispatch_degree<KSTOKES, BLTC_FP64>(degree, a, s);
-    if (precision == BLTC_FP32_FP64ACC) return dispatch_degree<KSTOKES, BLTC_FP32_FP64ACC>(degree, a, s);
-    return dispatch_degree<KSTOKES, BLTC_FP32_KAHAN>(degree, a, s);
+    if (precision == BLTC_FP64) return p2p_k0_p0(degree, a, s);
+    if (precision == BLTC_FP32_FP64ACC) return p2p_k0_p1(degree, a, s);
+    return p2p_k0_p2(degree, a, s);
   }
   if (kernel == KFULL) {
-    if (precision == BLTC_FP64) return dispatch_degree<KFULL, BLTC_FP64>(degree, a, s);
-    if (precision == BLTC_FP32_FP64ACC) return dispatch_degree<KFULL, BLTC_FP32_FP64ACC>(degree, a, s);
-    return dispatch_degree<KFULL, BLTC_FP32_KAHAN>(degree, a, s);
+    if (precision == BLTC_FP64) return p2p_k2_p0(degree, a, s);
+    if (precision == BLTC_FP32_FP64ACC) return p2p_k2_p1(degree, a, s);
+    return p2p_k2_p2(degree, a, s);
   }
-  if (precision == BLTC_FP64) return dispatch_degree<KROT, BLTC_FP64>(degree, a, s);
-  if (precision == BLTC_FP32_FP64ACC) return dispatch_degree<KROT, BLTC_FP32_FP64ACC>(degree, a, s);
-  return dispatch_degree<KROT, BLTC_FP32_KAHAN>(degree, a, s);
+  if (precision == BLTC_FP64) return p2p_k1_p0(degree, a, s);
+  if (precision == BLTC_FP32_FP64ACC) return p2p_k1_p1(degree, a, s);
+  return p2p_k1_p2(degree, a, s);
 }
+#endif
 
 }  // namespace bltc

@@ -28,7 +28,16 @@ struct Dims {
 };
 
 __device__ __forceinline__ float rsq(float v) { return __builtin_amdgcn_rsqf(v); }
-__device__ __forceinline__ double rsq(double v) { return rsqrt(v); }
+// FP64: the hardware estimate y (about 23 correct bits) and one second-order
+// Newton step for 1/sqrt(v): with e = 1 - v y^2, 1/sqrt(v) = y (1 - e)^(-1/2)
+// = y (1 + e/2 + 3e^2/8 + O(e^3)), and e^3 is below an FP64 ulp.  The
+// argument is rho^2 >= eps^2 > 0, or r^2 > 0 when eps = 0 (inv_rho tests
+// it), always positive and finite, so no special values are handled.
+__device__ __forceinline__ double rsq(double v) {
+  const double y = __builtin_amdgcn_rsq(v);
+  const double e = __builtin_fma(-v * y, y, 1.0);
+  return __builtin_fma(y * e, __builtin_fma(e, 0.375, 0.5), y);
+}
 
 template <bool ZEPS, typename T>
 __device__ __forceinline__ T inv_rho(T r2) {
