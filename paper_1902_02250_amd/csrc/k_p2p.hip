@@ -60,9 +60,24 @@ __device__ __forceinline__ T fmat(T a, T b, T c) {
 // keeps the FP32 rounding of a cluster's sum near that of n+1 + (n+1)^2
 // additions instead of (n+1)^3.  The per-axis differences are
 // formed once per (target, cluster): dz and dz^2 in registers (the k3 loop
-// is unrolled), dy and dy^2 in this lane's entries of an LDS table
-// (sd[k2 * 128 + 0/1]) because the k2 loop is not, so a grid row costs
+// is unrolled), dy and (FP32) dy^2 in this lane's entries of an LDS table
+// (sd[k2 * SdStride<T>]) because the k2 loop is not, so a grid row costs
 // one LDS read instead of an FP64 difference, a conversion and a square.
+// In FP64 the table holds dy alone and a row forms dy^2 + (dx^2 + eps^2)
+// with one fused multiply-add, the same instruction count as the add it
+// replaces: half the LDS per wave, which is what limits FP64 occupancy.
+// LDS stride (elements) between grid rows of a lane's dy table: (dy, dy^2)
+// pairs in FP32, dy alone in FP64, 64 lanes per row.
+template <typename T>
+constexpr int SdStride = sizeof(T) == 8 ? 64 : 128;
+
+// dy^2 + (dx^2 + eps^2) of grid row k2
+template <typename T>
+__device__ __forceinline__ T row_r2(const T* __restrict__ sd, int k2, T dy, T dx2e) {
+  if constexpr (sizeof(T) == 8) return fmat(dy, dy, dx2e);
+  else return sd[k2 * SdStride<T> + 1] + dx2e;
+}
+
 template <int KERN, int N1, bool ZEPS, typename T, typename F>
 __device__ __forceinline__ void proxies(double x, double y, double z,
                                         const double* __restrict__ g,
@@ -74,8 +89,8 @@ __device__ __forceinline__ void proxies(double x, double y, double z,
     dz[k] = (T)(z - g[2 * N1 + k]);
     dz2[k] = dz[k] * dz[k];
     const T d = (T)(y - g[N1 + k]);
-    sd[k * 128] = d;
-    sd[k * 128 + 1] = d * d;
+    sd[k * SdStride<T>] = d;
+    if constexpr (sizeof(T) == 4) sd[k * SdStride<T> + 1] = d * d;
   }
   if constexpr (KERN == KSTOKES) {
     // u = sum f H1 + sum (f.d) H2 d,  H2 = inv^3
@@ -86,8 +101,8 @@ __device__ __forceinline__ void proxies(double x, double y, double z,
       const T dx = (T)(x - g[k1]);
       const T dx2e = dx * dx + e2;
       for (int k2 = 0; k2 < N1; ++k2) {
-        const T dy = sd[k2 * 128];
-        const T dxy2 = sd[k2 * 128 + 1] + dx2e;
+        const T dy = sd[k2 * SdStride<T>];
+        const T dxy2 = row_r2(sd, k2, dy, dx2e);
         const F* __restrict__ R = fh + (k1 * N1 + k2) * 3 * N1;   // [c][k3], c < 3
         T S = 0, ax = 0, ay = 0, az = 0;
 #pragma unroll
@@ -122,8 +137,8 @@ __device__ __forceinline__ void proxies(double x, double y, double z,
       const T dx = (T)(x - g[k1]);
       const T dx2e = dx * dx + e2;
       for (int k2 = 0; k2 < N1; ++k2) {
-        const T dy = sd[k2 * 128];
-        const T dxy2 = sd[k2 * 128 + 1] + dx2e;
+        const T dy = sd[k2 * SdStride<T>];
+        const T dxy2 = row_r2(sd, k2, dy, dx2e);
         const F* __restrict__ R = fh + (k1 * N1 + k2) * 6 * N1;   // [c][k3], c < 6
         T ax = 0, ay = 0, az = 0, S = 0, Qx = 0, Qy = 0, Qz = 0;
         T Fx = 0, Fy = 0, Fz = 0, Wx = 0, Wy = 0, Wz = 0, G = 0;
@@ -190,8 +205,8 @@ __device__ __forceinline__ void proxies(double x, double y, double z,
       const T dx = (T)(x - g[k1]);
       const T dx2e = dx * dx + e2;
       for (int k2 = 0; k2 < N1; ++k2) {
-        const T dy = sd[k2 * 128];
-        const T dxy2 = sd[k2 * 128 + 1] + dx2e;
+        const T dy = sd[k2 * SdStride<T>];
+        const T dxy2 = row_r2(sd, k2, dy, dx2e);
         const F* __restrict__ R = fh + (k1 * N1 + k2) * 3 * N1;
         T qx = 0, qy = 0, qz = 0, G = 0, wx = 0, wy = 0, wz = 0;
 #pragma unroll
@@ -391,7 +406,8 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void k_p2p(
   using T = typename std::conditional<F64, double, float>::type;
   __shared__ T sA[kWavesPerBlock][4][64];        // source x, y, z, weight 0
   __shared__ T sB[kWavesPerBlock][WD - 1][64];   // weights 1 .. WD-1
-  __shared__ T sY[kWavesPerBlock][N1][64][2];    // far field: each lane's dy, dy^2 per grid row
+  // far field: each lane's dy (and, in FP32, dy^2) per grid row
+  __shared__ T sY[kWavesPerBlock][N1][SdStride<T>];
 
   // the wave index is uniform across the wave; readfirstlane tells the
   // compiler so, which keeps everything derived from it in scalar registers
@@ -434,7 +450,7 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void k_p2p(
   const T e2 = (T)(eps * eps);
   T (*A)[64] = sA[wid];
   T (*B)[64] = sB[wid];
-  T* sd = &sY[wid][0][lane][0];
+  T* sd = &sY[wid][0][lane * (SdStride<T> / 64)];
 
   Acc<PREC, OD> acc;
   acc.init();
