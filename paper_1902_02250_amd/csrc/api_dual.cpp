@@ -197,13 +197,60 @@ void evaluate_dual(bltc_tree src, bltc_tree tgt, int kernel, double eps, int deg
       if ((mk[0] | mk[1]) >> dd & 1u) ensure_derived(src, dd, degree, s);
   }
 
+  // Schedules of the two passes: batches by decreasing modelled work, dealt
+  // to the 8 XCDs in turn, each XCD running its share longest first.  List
+  // lengths vary with a cluster's level and place, and in tree order the
+  // longest batches could start last and hold a launch open; every wave's
+  // sums are independent, so the order does not change any result.  A proxy
+  // entry costs its cluster's grid size, a direct entry about half a full
+  // source leaf.
+  const double leaf_half = 0.5 * (double)src->leaf_max;
+  auto schedule = [&](const int32_t* d_pp, const int32_t* d_dp, int64_t nbb, int wpb,
+                      DevBuf<int32_t>& d_map, DevBuf<int32_t>& d_xs) -> int32_t {
+    if (nbb == 0) return 0;
+    std::vector<int32_t> pp(nbb + 1), dp(nbb + 1);
+    d2h(pp.data(), d_pp, nbb + 1, s);
+    d2h(dp.data(), d_dp, nbb + 1, s);
+    sync(s);
+    std::vector<double> w(nbb);
+    for (int64_t i = 0; i < nbb; ++i)
+      w[i] = (double)(pp[i + 1] - pp[i]) * (double)P + (double)(dp[i + 1] - dp[i]) * leaf_half;
+    std::vector<int32_t> ord(nbb);
+    std::iota(ord.begin(), ord.end(), 0);
+    std::stable_sort(ord.begin(), ord.end(), [&](int32_t i, int32_t j) { return w[i] > w[j]; });
+    std::vector<int32_t> bm(nbb), xs(9);
+    int64_t pos = 0;
+    for (int x = 0; x < 8; ++x) {
+      xs[x] = (int32_t)(pos * wpb);
+      for (int64_t r = x; r < nbb; r += 8) bm[pos++] = ord[r];
+    }
+    xs[8] = (int32_t)(pos * wpb);
+    int32_t xmax = 0;
+    for (int x = 0; x < 8; ++x) xmax = std::max(xmax, xs[x + 1] - xs[x]);
+    d_map.reserve(nbb);
+    d_xs.reserve(9);
+    h2d(d_map.p, bm.data(), nbb, s);
+    h2d(d_xs.p, xs.data(), 9, s);
+    return xmax;
+  };
+  const int32_t gxmax = schedule(d_gpptr.p, d_gdptr.p, gnb, wpb_g, C.gbmap, C.gxstart);
+  const int32_t txmax = schedule(d_pptr.p, d_dptr.p, nb, wpb_t, C.tbmap, C.txstart);
+
   StageTimer ev(BLTC_STAGE_EVAL, s);
   // the particle-cluster kernel over a point set: batches bp/bg, proxy
-  // lists pp/pi, direct lists dp/di, output dst [odim][mm] via tperm
+  // lists pp/pi, direct lists dp/di, output dst [odim][mm] via tperm;
+  // optionally batches in the order bmap with XCD ranges xstart
   auto p2p = [&](const double* tx, int64_t mm, const int32_t* tperm, const int32_t* bp,
                  const double4* bg, int64_t nbb, int wpb, const int32_t* pp, const int32_t* pi,
-                 const int32_t* dp, const int32_t* di, double* dst) {
+                 const int32_t* dp, const int32_t* di, double* dst, const int32_t* bmap,
+                 const int32_t* xstart, int32_t xmax) {
     bltc::P2PArgs a;
+    if (bmap) {
+      a.bmap = bmap;
+      a.nmap = nbb;
+      a.xstart = xstart;
+      a.xmax = xmax;
+    }
     a.tx = tx;
     a.m = mm;
     a.tperm = tperm;
@@ -244,10 +291,10 @@ void evaluate_dual(bltc_tree src, bltc_tree tgt, int kernel, double eps, int deg
   // grid potentials g_A at the target clusters' grid points (CC and CP)
   if (gnb > 0)
     p2p(d_gpts.p, M, d_giota.p, d_gbptr.p, d_gbgeo.p, gnb, wpb_g, d_gpptr.p, d_gpids.p,
-        d_gdptr.p, d_gdids.p, d_g.p);
+        d_gdptr.p, d_gdids.p, d_g.p, C.gbmap.p, C.gxstart.p, gxmax);
   // targets: PC and PP of their leaf and its ancestors
   p2p(tgt->d_y, m, tgt->d_perm, d_bptr.p, d_bgeo.p, nb, wpb_t, d_pptr.p, d_pids.p, d_dptr.p,
-      d_dids.p, out);
+      d_dids.p, out, C.tbmap.p, C.txstart.p, txmax);
 
   bltc::DualDownArgs da;
   da.bptr = d_bptr.p;

@@ -211,6 +211,8 @@ int check_tree_eval(bltc_tree t, int64_t m, int kernel, double eps, int degree, 
 struct bltc_dual_cache {
   bltc::api::DevBuf<int32_t> gnode, gbptr, gpptr, gpids, gdptr, gdids, giota, bptr, pptr, pids,
       dptr, dids, xptr, xgi, xnode;
+  // the grid and target passes' batch orders and XCD ranges (in waves)
+  bltc::api::DevBuf<int32_t> gbmap, gxstart, tbmap, txstart;
   // the device traversal's counts, offsets, slots and flags
   bltc::api::DevBuf<int32_t> leaves, ncc, ncp, ccptr, cpptr, flag, slot, npc, npp, xcnt, ovf;
   bltc::api::DevBuf<unsigned long long> work;
