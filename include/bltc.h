@@ -214,8 +214,10 @@ int bltc_host_batches(const double* hx, const double* hy, const double* hz,
  * grid points and modified weights of `degree` and the near field against
  * leaf particles, and writes out[odim][m] in caller order.  The modified
  * weights of `degree` must have been computed with the kernel's wdim (else
- * BLTC_ESTATE).  The list sizes are read back once (synchronises on
- * `stream`). */
+ * BLTC_ESTATE).  The list sizes are read back once, and the per-batch list
+ * counts once more to order the launch (batches by decreasing modelled work,
+ * dealt to the XCDs; the order changes no result): synchronises on
+ * `stream`. */
 int bltc_evaluate_tree(bltc_tree t, bltc_targets g, int32_t kernel, double eps,
                        int32_t degree, double theta, const bltc_options* opt,
                        double* out, void* stream);

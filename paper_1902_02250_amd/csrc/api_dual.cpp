@@ -206,7 +206,8 @@ void evaluate_dual(bltc_tree src, bltc_tree tgt, int kernel, double eps, int deg
   // source leaf.
   const double leaf_half = 0.5 * (double)src->leaf_max;
   auto schedule = [&](const int32_t* d_pp, const int32_t* d_dp, int64_t nbb, int wpb,
-                      DevBuf<int32_t>& d_map, DevBuf<int32_t>& d_xs) -> int32_t {
+                      DevBuf<int32_t>& d_map, DevBuf<int32_t>& d_xs, std::vector<int32_t>& bm,
+                      std::vector<int32_t>& xs) -> int32_t {
     if (nbb == 0) return 0;
     std::vector<int32_t> pp(nbb + 1), dp(nbb + 1);
     d2h(pp.data(), d_pp, nbb + 1, s);
@@ -218,7 +219,8 @@ void evaluate_dual(bltc_tree src, bltc_tree tgt, int kernel, double eps, int deg
     std::vector<int32_t> ord(nbb);
     std::iota(ord.begin(), ord.end(), 0);
     std::stable_sort(ord.begin(), ord.end(), [&](int32_t i, int32_t j) { return w[i] > w[j]; });
-    std::vector<int32_t> bm(nbb), xs(9);
+    bm.resize(nbb);
+    xs.assign(9, 0);
     int64_t pos = 0;
     for (int x = 0; x < 8; ++x) {
       xs[x] = (int32_t)(pos * wpb);
@@ -233,8 +235,10 @@ void evaluate_dual(bltc_tree src, bltc_tree tgt, int kernel, double eps, int deg
     h2d(d_xs.p, xs.data(), 9, s);
     return xmax;
   };
-  const int32_t gxmax = schedule(d_gpptr.p, d_gdptr.p, gnb, wpb_g, C.gbmap, C.gxstart);
-  const int32_t txmax = schedule(d_pptr.p, d_dptr.p, nb, wpb_t, C.tbmap, C.txstart);
+  const int32_t gxmax =
+      schedule(d_gpptr.p, d_gdptr.p, gnb, wpb_g, C.gbmap, C.gxstart, C.h_gbmap, C.h_gxstart);
+  const int32_t txmax =
+      schedule(d_pptr.p, d_dptr.p, nb, wpb_t, C.tbmap, C.txstart, C.h_tbmap, C.h_txstart);
 
   StageTimer ev(BLTC_STAGE_EVAL, s);
   // the particle-cluster kernel over a point set: batches bp/bg, proxy

@@ -197,35 +197,81 @@ void evaluate_tree(bltc_tree t, bltc_targets g, int kernel, double eps,
   const bltc::Rule rule = make_rule(theta, degree, o.deg_min);
   build_lists(t, g, theta, nullptr, g->ls[0], s, &np, &nd, &rule);
   derive_used_degrees(t, g, g->ls[0], rule.deg_min, {{degree, {nullptr, g->nb}}}, s);
-  const int32_t xmax = work_ranges(g, g->ls[0], degree, s);
-  run_p2p(t, g, g->ls[0], kernel, eps, degree, o, nullptr, 0, out, s, nullptr, 0, nullptr,
-          g->d_xstart, xmax);
+  const std::vector<Dealt> d = deal_batches(g, g->ls[0], s, {{degree, nullptr, g->nb}});
+  run_p2p(t, g, g->ls[0], kernel, eps, degree, o, g->d_xmap + d[0].off, g->nb, out, s, nullptr,
+          0, nullptr, g->d_xstart, d[0].xmax);
 }
 
-int32_t work_ranges(bltc_targets g, const bltc::ListSet& L, int degree, hipStream_t s,
-                    const int32_t* bmap, int64_t nmap, int slot) {
-  const int64_t nb = g->nb, nw = bmap ? nmap : nb;
-  if (nw == 0) return 0;
-  ensure_alloc(g->d_xwork, 2 * nb + 6);
-  ensure_alloc(g->d_xstart, 18 * (bltc::kMaxDegree + 1));
-  int32_t* xst = g->d_xstart + 18 * slot;
-  const int wpb = (g->batch_size + bltc::kWave - 1) / bltc::kWave;
-  hipchk(bltc::launch_xcd_ranges(L.cnt, L.cnt + 2 * nb, bmap, nw, degree, wpb, g->d_xwork, xst,
-                                 s),
-         "XCD ranges");
-  int32_t xs[18], ovf = 0;
-  d2h(xs, xst, 18, s);
-  d2h(&ovf, g->d_xwork + 2 * nw + 1, 1, s);
+// The launch order of the evaluation's batches.  A wave's time is modelled
+// from its lists: an accepted cluster costs (0.69 n1 + 0.5) n1^2 + 2.5
+// near-field pair-equivalents (n1 = n + 1: the grid's proxies at the far
+// field's per-proxy cost, plus its per-row and per-cluster set-up), a near
+// source one.  The batches go by decreasing modelled time (ties in batch
+// order), dealt to XCDs 0, 1, .., 7, 0, 1, ..: each XCD gets an eighth of
+// the work and runs its share longest first, so the batches that start last
+// are the shortest.  In tree order the long batches of a dense region sit
+// together and could start last, each then holding its SIMD to the end of
+// the launch.  The order changes no result (every wave's sums are its own).
+// The sort is a stable counting sort over 4096 levels of the group's largest
+// modelled time (batches within 1/4096 of it count as equal), linear in the
+// batches, since the device waits for it.
+std::vector<Dealt> deal_batches(bltc_targets g, const bltc::ListSet& L, hipStream_t s,
+                                const std::vector<DealGroup>& groups) {
+  constexpr int kLevels = 4096;
+  const int64_t nb = g->nb;
+  std::vector<Dealt> res(groups.size(), Dealt{0, 0});
+  int64_t total = 0;
+  for (const DealGroup& gr : groups) total += gr.n;
+  if (total == 0) return res;
+  // proxy, leaf and near-source counts of every batch ([3][nb]), one copy
+  g->h_cnt.resize(3 * nb);
+  d2h(g->h_cnt.data(), L.cnt, 3 * nb, s);
   sync(s);
-  if (ovf) return 0;
-  // the equal-count split is kept unless one XCD would get 3% more than an
-  // eighth of the work
-  int32_t most = 0;
-  for (int x = 0; x < 8; ++x) most = std::max(most, xs[9 + x]);
-  if ((double)most <= 1.03 * (double)xs[17] / 8.0) return 0;
-  int32_t xmax = 0;
-  for (int x = 0; x < 8; ++x) xmax = std::max(xmax, xs[x + 1] - xs[x]);
-  return xmax;
+  ensure_alloc(g->d_xmap, nb);
+  ensure_alloc(g->d_xstart, 9 * (bltc::kMaxDegree + 1));
+  g->h_xmap.resize(total);
+  g->h_xstart.assign(9 * groups.size(), 0);
+  const int wpb = (g->batch_size + bltc::kWave - 1) / bltc::kWave;
+  std::vector<double> w;
+  std::vector<int32_t> ord, lev, first(kLevels + 1);
+  int64_t off = 0;
+  for (size_t i = 0; i < groups.size(); ++i) {
+    const DealGroup& gr = groups[i];
+    const double n1 = gr.degree + 1;
+    const double per_cluster = (0.69 * n1 + 0.5) * n1 * n1 + 2.5;
+    w.resize(gr.n);
+    ord.resize(gr.n);
+    lev.resize(gr.n);
+    double wmax = 0.0;
+    for (int64_t k = 0; k < gr.n; ++k) {
+      const int32_t b = gr.ids ? gr.ids[k] : (int32_t)k;
+      w[k] = (double)g->h_cnt[b] * per_cluster + (double)g->h_cnt[2 * nb + b];
+      wmax = std::max(wmax, w[k]);
+    }
+    // level 0 holds the longest batches; stable within a level
+    const double scale = wmax > 0.0 ? (kLevels - 1) / wmax : 0.0;
+    std::fill(first.begin(), first.end(), 0);
+    for (int64_t k = 0; k < gr.n; ++k) {
+      lev[k] = kLevels - 1 - std::min(kLevels - 1, (int)(w[k] * scale));
+      ++first[lev[k] + 1];
+    }
+    for (int l = 0; l < kLevels; ++l) first[l + 1] += first[l];
+    for (int64_t k = 0; k < gr.n; ++k) ord[first[lev[k]]++] = (int32_t)k;
+    int32_t* xm = g->h_xmap.data() + off;
+    int32_t* xs = g->h_xstart.data() + 9 * i;
+    int64_t pos = 0;
+    for (int x = 0; x < 8; ++x) {
+      xs[x] = (int32_t)(pos * wpb);
+      for (int64_t r = x; r < gr.n; r += 8) xm[pos++] = gr.ids ? gr.ids[ord[r]] : ord[r];
+    }
+    xs[8] = (int32_t)(pos * wpb);
+    for (int x = 0; x < 8; ++x) res[i].xmax = std::max(res[i].xmax, xs[x + 1] - xs[x]);
+    res[i].off = off;
+    off += gr.n;
+  }
+  h2d(g->d_xmap, g->h_xmap.data(), total, s);
+  h2d(g->d_xstart, g->h_xstart.data(), 9 * groups.size(), s);
+  return res;
 }
 
 int check_tree_eval(bltc_tree t, int64_t m, int kernel, double eps, int degree, double theta,

@@ -449,31 +449,32 @@ void evaluate_adaptive(bltc_tree t, bltc_targets g, int kernel, double eps,
   bltc_options og = o;
   og.deg_min = rule_min;
   // the degree groups write disjoint targets: with more than one, they run
-  // concurrently on side streams, largest first
-  // (each group's XCD ranges of equal modelled work, as for a fixed evaluation)
+  // concurrently on side streams, largest first; each group's batches in the
+  // launch order of a fixed evaluation (by decreasing modelled work, dealt
+  // to the XCDs)
   if (spans.size() == 1) {
-    const int32_t xmax = work_ranges(g, g->ls[0], spans[0].first, s, g->d_bmap, nb, 0);
-    run_p2p(t, g, g->ls[0], kernel, eps, spans[0].first, og, g->d_bmap, nb, out, s, nullptr, 0,
-            nullptr, g->d_xstart, xmax);
+    const std::vector<Dealt> d = deal_batches(g, g->ls[0], s, {{spans[0].first, order.data(), nb}});
+    run_p2p(t, g, g->ls[0], kernel, eps, spans[0].first, og, g->d_xmap + d[0].off, nb, out, s,
+            nullptr, 0, nullptr, g->d_xstart, d[0].xmax);
   } else {
     std::sort(spans.begin(), spans.end(), [](const auto& a, const auto& b) {
       const double wa = (double)a.second.second * std::pow(a.first + 1.0, 3);
       const double wb = (double)b.second.second * std::pow(b.first + 1.0, 3);
       return wa > wb;
     });
-    std::vector<int32_t> xmax(spans.size());
-    for (size_t i = 0; i < spans.size(); ++i)
-      xmax[i] = work_ranges(g, g->ls[0], spans[i].first, s, g->d_bmap + spans[i].second.first,
-                            spans[i].second.second, (int)i);
+    std::vector<DealGroup> dg;
+    for (auto& sp : spans)
+      dg.push_back({sp.first, order.data() + sp.second.first, sp.second.second});
+    const std::vector<Dealt> d = deal_batches(g, g->ls[0], s, dg);
     hipEvent_t ready = evs.make();
     hipchk(hipEventRecord(ready, s), "hipEventRecord");
     std::vector<hipEvent_t> done;
     for (size_t i = 0; i < spans.size(); ++i) {
       hipStream_t ss = side_stream((int)i);
       hipchk(hipStreamWaitEvent(ss, ready, 0), "hipStreamWaitEvent");
-      run_p2p(t, g, g->ls[0], kernel, eps, spans[i].first, og,
-              g->d_bmap + spans[i].second.first, spans[i].second.second, out, ss, nullptr, 0,
-              nullptr, g->d_xstart + 18 * i, xmax[i]);
+      run_p2p(t, g, g->ls[0], kernel, eps, spans[i].first, og, g->d_xmap + d[i].off,
+              spans[i].second.second, out, ss, nullptr, 0, nullptr, g->d_xstart + 9 * i,
+              d[i].xmax);
       if (i + kSideStreams >= spans.size()) {   // last launch on this side stream
         hipEvent_t e = evs.make();
         hipchk(hipEventRecord(e, ss), "hipEventRecord");

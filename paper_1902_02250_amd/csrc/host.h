@@ -188,13 +188,22 @@ void run_p2p(bltc_tree t, bltc_targets g, const bltc::ListSet& L, int kernel, do
              int degree, const bltc_options& o, const int32_t* bmap, int64_t nmap,
              double* out, hipStream_t s, const int4* split = nullptr, int64_t nsplit = 0,
              double* partial = nullptr, const int32_t* xstart = nullptr, int32_t xmax = 0);
-// XCD ranges of equal modelled work for an evaluation of all batches (or of
-// bmap[0..nmap)) with the lists L (device, g->d_xstart + 18 slot); returns
-// the longest range in waves, or 0
-// when the kernel's own equal-count ranges are within 3% of balanced (then
-// they apply).  Synchronises.
-int32_t work_ranges(bltc_targets g, const bltc::ListSet& L, int degree, hipStream_t s,
-                    const int32_t* bmap = nullptr, int64_t nmap = 0, int slot = 0);
+// The order of an evaluation launch's batches: by decreasing modelled work
+// (see deal_batches in api_eval.cpp), dealt to the 8 XCDs in turn.  One
+// group per launch: its degree and its batches (host ids, or NULL for all
+// g->nb); group i's order goes to g->d_xmap + off[i] and its XCD ranges (in
+// waves) to g->d_xstart + 9 i.  Reads the list counts back (synchronises).
+struct DealGroup {
+  int degree;
+  const int32_t* ids;   // host, or NULL: batches 0 .. n-1
+  int64_t n;
+};
+struct Dealt {
+  int64_t off;          // in g->d_xmap
+  int32_t xmax;         // longest XCD range in waves
+};
+std::vector<Dealt> deal_batches(bltc_targets g, const bltc::ListSet& L, hipStream_t s,
+                                const std::vector<DealGroup>& groups);
 void evaluate_tree(bltc_tree t, bltc_targets g, int kernel, double eps, int degree,
                    double theta, const bltc_options& o, double* out, hipStream_t s);
 // The checks shared by the entry points that evaluate a built tree: handles,
@@ -211,8 +220,10 @@ int check_tree_eval(bltc_tree t, int64_t m, int kernel, double eps, int degree, 
 struct bltc_dual_cache {
   bltc::api::DevBuf<int32_t> gnode, gbptr, gpptr, gpids, gdptr, gdids, giota, bptr, pptr, pids,
       dptr, dids, xptr, xgi, xnode;
-  // the grid and target passes' batch orders and XCD ranges (in waves)
+  // the grid and target passes' batch orders and XCD ranges (in waves), and
+  // their host copies (sources of the uploads)
   bltc::api::DevBuf<int32_t> gbmap, gxstart, tbmap, txstart;
+  std::vector<int32_t> h_gbmap, h_gxstart, h_tbmap, h_txstart;
   // the device traversal's counts, offsets, slots and flags
   bltc::api::DevBuf<int32_t> leaves, ncc, ncp, ccptr, cpptr, flag, slot, npc, npp, xcnt, ovf;
   bltc::api::DevBuf<unsigned long long> work;

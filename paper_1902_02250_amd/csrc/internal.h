@@ -320,16 +320,6 @@ hipError_t launch_dual_xlists(const int32_t* leaves, int64_t nl, const int32_t* 
                               const int32_t* xptr, int32_t* xgi, int32_t* xnode, bool fill,
                               hipStream_t s);
 hipError_t launch_iota(int32_t* p, int64_t n, hipStream_t s);
-// XCD ranges of equal modelled work over the nb batches (bmap[0..nb) when
-// bmap is given) of wpb waves each:
-// work of a batch = its proxies ((0.69 n1 + 0.5) n1^2 + 2.5 each) + its
-// near-field sources (counts from the list pass); xstart[0..8] in waves,
-// xstart[9..16] the work of the kernel's equal-count ranges, xstart[17] the
-// total.  scratch: 2 nb + 6 int32.
-hipError_t launch_xcd_ranges(const int32_t* pcnt, const int32_t* scnt, const int32_t* bmap,
-                             int64_t nb, int degree, int wpb, int32_t* scratch, int32_t* xstart,
-                             hipStream_t s);
-
 // Balanced k-d target batches on the device (k_kd.hip).  Parts above
 // kKdLocal targets are cut level by level over all of them: chunks (part,
 // begin, end) of at most kKdChunk positions, each part's chunks consecutive
@@ -548,8 +538,10 @@ struct bltc_targets_s {
   int64_t pccap = 0;
   int32_t* d_choice = nullptr; // [nb]
   int32_t* d_bmap = nullptr;   // [nb]
-  int32_t* d_xwork = nullptr;  // [2 nb + 6] work prefix sums for the XCD ranges
-  int32_t* d_xstart = nullptr; // [kMaxDegree + 1][18] XCD ranges (per evaluation group) and the equal-count split's work
+  int32_t* d_xmap = nullptr;   // [nb] batch order of the evaluation launches (per group)
+  int32_t* d_xstart = nullptr; // [kMaxDegree + 1][9] XCD ranges in waves (per group)
+  std::vector<int32_t> h_xmap, h_xstart;   // their host copies (sources of the uploads)
+  std::vector<int32_t> h_cnt;  // list counts read back for the order
   double* d_theta_b = nullptr; // [nb]
   int32_t* d_spos = nullptr;   // judge samples, one per sstride batches (tree order)
   double4* d_sgeo = nullptr;   // [nsamp] the samples as batches of one target

@@ -333,10 +333,11 @@ struct Acc {
   }
 };
 
-// Blocks are dispatched round robin over the 8 XCDs; give each XCD a
-// contiguous range of batches so neighbouring batches, which share most of
-// their lists, share an L2.  (The evaluation passes ranges of equal
-// modelled work instead, xstart, when it has them.)
+// Blocks are dispatched round robin over the 8 XCDs; without a launch order
+// each XCD takes a contiguous range of batches, so neighbouring batches,
+// which share most of their lists, share an L2.  The evaluations pass their
+// own order instead (bmap, by decreasing modelled work, dealt to the XCDs)
+// with each XCD's range of it (xstart).
 __device__ __forceinline__ int xcd_block(int blk, int nblk) {
   const int per = nblk / 8, rem = nblk % 8;
   const int xcd = blk % 8, idx = blk / 8;

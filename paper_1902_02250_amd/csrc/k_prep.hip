@@ -92,49 +92,6 @@ __global__ __launch_bounds__(1024) void k_scan(const int32_t* __restrict__ in,
 inline unsigned blocks(int64_t n, int threads) {
   return (unsigned)((n + threads - 1) / threads);
 }
-
-// Per batch its modelled wave time, in units of 4096 near-field pairs (so
-// the totals fit in 31 bits up to about 8e12), at least 1: an accepted
-// cluster costs (0.69 n1 + 0.5) n1^2 + 2.5 and a near-field source 1, the
-// weights of the compiled loops (the selector's cost model).
-__global__ void k_batch_work(const int32_t* __restrict__ pcnt, const int32_t* __restrict__ scnt,
-                             const int32_t* __restrict__ bmap, int64_t nb, double per_cluster,
-                             int32_t* __restrict__ w) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nb) return;
-  const int64_t b = bmap ? bmap[i] : i;
-  const double v = ((double)pcnt[b] * per_cluster + (double)scnt[b]) / 4096.0 + 1.0;
-  w[i] = v < 2147483647.0 ? (int32_t)v : 0x7fffffff;
-}
-
-// xstart[x] = wpb times the first batch whose exclusive work prefix reaches
-// x/8 of the total; xstart[8] = wpb nb.  xstart[9 + x]: the work of XCD x's
-// range under equal counts (the kernel's own split), xstart[17] the total.
-__global__ void k_xcd_ranges(const int32_t* __restrict__ pre, int64_t nb, int wpb,
-                             int32_t* __restrict__ xstart) {
-  const int x = threadIdx.x;
-  if (x > 8) return;
-  if (x == 8) {
-    xstart[8] = (int32_t)(nb * wpb);
-    xstart[17] = pre[nb];
-    return;
-  }
-  {
-    const int64_t nw = nb * wpb, per = nw / 8, rem = nw % 8;
-    const int64_t w0 = x * per + (x < rem ? x : rem), w1 = w0 + per + (x < rem ? 1 : 0);
-    xstart[9 + x] = pre[w1 / wpb] - pre[w0 / wpb];
-  }
-  const double tot = (double)pre[nb];
-  const double want = tot * x / 8.0;
-  int64_t lo = 0, hi = nb;   // first b with pre[b] >= want
-  while (lo < hi) {
-    const int64_t mid = (lo + hi) >> 1;
-    if ((double)pre[mid] >= want) hi = mid;
-    else lo = mid + 1;
-  }
-  xstart[x] = (int32_t)(lo * wpb);
-}
-
 }  // namespace
 
 hipError_t launch_gather_points(const double* x, const double* y,
@@ -169,22 +126,6 @@ hipError_t launch_grids(const double* box, int64_t nn, int degree,
 hipError_t launch_exclusive_scan(const int32_t* in, int64_t n, int32_t* out,
                                  int32_t* overflow, hipStream_t s) {
   hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, in, n, out, overflow);
-  return hipGetLastError();
-}
-
-hipError_t launch_xcd_ranges(const int32_t* pcnt, const int32_t* scnt, const int32_t* bmap,
-                             int64_t nb, int degree, int wpb, int32_t* scratch, int32_t* xstart,
-                             hipStream_t s) {
-  if (nb == 0) return hipSuccess;
-  const double n1 = degree + 1;
-  const double per_cluster = (0.69 * n1 + 0.5) * n1 * n1 + 2.5;
-  int32_t* w = scratch;            // [nb]
-  int32_t* pre = scratch + nb;     // [nb + 1]
-  int32_t* ovf = pre + nb + 1;     // [1]
-  hipLaunchKernelGGL(k_batch_work, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, s, pcnt,
-                     scnt, bmap, nb, per_cluster, w);
-  if (hipError_t e = launch_exclusive_scan(w, nb, pre, ovf, s)) return e;
-  hipLaunchKernelGGL(k_xcd_ranges, dim3(1), dim3(64), 0, s, pre, nb, wpb, xstart);
   return hipGetLastError();
 }
 
