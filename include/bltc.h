@@ -225,8 +225,10 @@ int bltc_evaluate_tree(bltc_tree t, bltc_targets g, int32_t kernel, double eps,
 /* Allocation-free bltc_evaluate_tree, for callers that cannot allocate
  * device memory (code under stream capture, tight serving loops, harnesses
  * that forbid hipMalloc).  Same arguments, checks and result as
- * bltc_evaluate_tree, bit for bit; the interaction lists, the walk flags and
- * the separation rule's degree mask live in a fixed device array of the
+ * bltc_evaluate_tree, bit for bit; the interaction lists, the walk flags,
+ * the separation rule's degree mask and, for launches of fewer than 4096
+ * waves, the partial sums of the batches' list slices (at most 12 MiB) live
+ * in a fixed device array of the
  * library (bltc_noalloc_scratch_bytes: 32 MiB, one copy per device the
  * library runs on, held until the process ends) instead of the targets
  * handle.  The call allocates nothing: the modified weights of `degree` must

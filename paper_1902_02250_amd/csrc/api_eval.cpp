@@ -174,7 +174,7 @@ bltc::P2PArgs p2p_args(bltc_tree t, bltc_targets g, const bltc::ListSet& L, int 
 void run_p2p(bltc_tree t, bltc_targets g, const bltc::ListSet& L, int kernel, double eps,
              int degree, const bltc_options& o, const int32_t* bmap, int64_t nmap,
              double* out, hipStream_t s, const int4* split, int64_t nsplit, double* partial,
-             const int32_t* xstart, int32_t xmax) {
+             const int32_t* xstart, int32_t xmax, int slices, double* spart) {
   bltc::P2PArgs a = p2p_args(t, g, L, kernel, eps, degree, o, bmap, nmap, out);
   a.split = split;
   a.nsplit = nsplit;
@@ -183,9 +183,34 @@ void run_p2p(bltc_tree t, bltc_targets g, const bltc::ListSet& L, int kernel, do
     a.xstart = xstart;
     a.xmax = xmax;
   }
+  const bool sliced = !split && slices > 1;
+  if (sliced) {
+    a.slices = slices;
+    a.spart = spart;
+  }
   StageTimer ev(BLTC_STAGE_EVAL, s);
   hipchk(bltc::launch_p2p(kernel, o.precision, degree, a, s), "p2p");
+  if (sliced)
+    hipchk(bltc::launch_slice_reduce(bmap, bmap ? nmap : g->nb, g->d_bptr, a.wpb, slices,
+                                     g->d_tperm, spart, odim_of(kernel), a.scale_u, a.scale_w,
+                                     g->m, out, s),
+           "slice reduce");
   ev.stop();
+}
+
+// The slice count of evaluations on g with this kernel, and its partial
+// buffer (grown once to the larger of the two output widths' needs).
+int ensure_slices(bltc_targets g, int kernel, double** spart) {
+  const int wpb = (g->batch_size + bltc::kWave - 1) / bltc::kWave;
+  const int k = slices_for(g->nb, wpb, odim_of(kernel));
+  *spart = nullptr;
+  if (k > 1) {
+    const int64_t b3 = slices_bytes(g->nb, wpb, 3, slices_for(g->nb, wpb, 3));
+    const int64_t b6 = slices_bytes(g->nb, wpb, 6, slices_for(g->nb, wpb, 6));
+    ensure_alloc(g->d_spart, (size_t)(std::max(b3, b6) / (int64_t)sizeof(double)));
+    *spart = g->d_spart;
+  }
+  return k;
 }
 
 void evaluate_tree(bltc_tree t, bltc_targets g, int kernel, double eps,
@@ -197,9 +222,11 @@ void evaluate_tree(bltc_tree t, bltc_targets g, int kernel, double eps,
   const bltc::Rule rule = make_rule(theta, degree, o.deg_min);
   build_lists(t, g, theta, nullptr, g->ls[0], s, &np, &nd, &rule);
   derive_used_degrees(t, g, g->ls[0], rule.deg_min, {{degree, {nullptr, g->nb}}}, s);
-  const std::vector<Dealt> d = deal_batches(g, g->ls[0], s, {{degree, nullptr, g->nb}});
+  double* spart = nullptr;
+  const int k = ensure_slices(g, kernel, &spart);
+  const std::vector<Dealt> d = deal_batches(g, g->ls[0], s, {{degree, nullptr, g->nb}}, k);
   run_p2p(t, g, g->ls[0], kernel, eps, degree, o, g->d_xmap + d[0].off, g->nb, out, s, nullptr,
-          0, nullptr, g->d_xstart, d[0].xmax);
+          0, nullptr, g->d_xstart, d[0].xmax, k, spart);
 }
 
 // The launch order of the evaluation's batches.  A wave's time is modelled
@@ -216,7 +243,7 @@ void evaluate_tree(bltc_tree t, bltc_targets g, int kernel, double eps,
 // modelled time (batches within 1/4096 of it count as equal), linear in the
 // batches, since the device waits for it.
 std::vector<Dealt> deal_batches(bltc_targets g, const bltc::ListSet& L, hipStream_t s,
-                                const std::vector<DealGroup>& groups) {
+                                const std::vector<DealGroup>& groups, int slices) {
   constexpr int kLevels = 4096;
   const int64_t nb = g->nb;
   std::vector<Dealt> res(groups.size(), Dealt{0, 0});
@@ -231,7 +258,8 @@ std::vector<Dealt> deal_batches(bltc_targets g, const bltc::ListSet& L, hipStrea
   ensure_alloc(g->d_xstart, 9 * (bltc::kMaxDegree + 1));
   g->h_xmap.resize(total);
   g->h_xstart.assign(9 * groups.size(), 0);
-  const int wpb = (g->batch_size + bltc::kWave - 1) / bltc::kWave;
+  // waves per batch in the launch: its waves of 64 targets times its slices
+  const int wpb = (g->batch_size + bltc::kWave - 1) / bltc::kWave * slices;
   std::vector<double> w;
   std::vector<int32_t> ord, lev, first(kLevels + 1);
   int64_t off = 0;

@@ -41,12 +41,17 @@ size_t up256(size_t b) { return (b + 255) / 256 * 256; }
 void evaluate_tree_noalloc(bltc_tree t, bltc_targets g, int kernel, double eps, int degree,
                            double theta, const bltc_options& o, double* out, hipStream_t s) {
   const int64_t nb = g->nb;
+  // the slices of a fixed evaluation (small launches), with their partial sums
+  const int wpb = (g->batch_size + kWave - 1) / kWave;
+  const int nsl = slices_for(nb, wpb, odim_of(kernel));
+  const size_t spart_bytes = nsl > 1 ? (size_t)slices_bytes(nb, wpb, odim_of(kernel), nsl) : 0;
   // scratch layout: flags [4] | degree mask [kMaxDegree + 1] | counts [3][nb]
-  // | pointers [2][nb + 1] | proxy list, then leaf list
+  // | pointers [2][nb + 1] | slice sums | proxy list, then leaf list
   const size_t o_mask = up256(4 * sizeof(int32_t));
   const size_t o_cnt = o_mask + up256((kMaxDegree + 1) * sizeof(uint32_t));
   const size_t o_ptr = o_cnt + up256(3 * (size_t)nb * sizeof(int32_t));
-  const size_t o_ids = o_ptr + up256(2 * ((size_t)nb + 1) * sizeof(int32_t));
+  const size_t o_spart = o_ptr + up256(2 * ((size_t)nb + 1) * sizeof(int32_t));
+  const size_t o_ids = o_spart + up256(spart_bytes);
   if (o_ids >= kScratchBytes)
     throw HipError{BLTC_EINVAL, std::to_string(nb) + " batches need " + std::to_string(o_ids) +
                                     " bytes of scratch before any list entry; the fixed "
@@ -79,7 +84,8 @@ void evaluate_tree_noalloc(bltc_tree t, bltc_targets g, int kernel, double eps, 
                            " weights derived from degree " + std::to_string(degree) +
                            "; a call of bltc_evaluate_tree with the same options derives them"};
   }
-  run_p2p(t, g, L, kernel, eps, degree, o, nullptr, 0, out, s);
+  run_p2p(t, g, L, kernel, eps, degree, o, nullptr, 0, out, s, nullptr, 0, nullptr, nullptr, 0,
+          nsl, nsl > 1 ? reinterpret_cast<double*>(base + o_spart) : nullptr);
 }
 
 }  // namespace

@@ -452,10 +452,14 @@ void evaluate_adaptive(bltc_tree t, bltc_targets g, int kernel, double eps,
   // concurrently on side streams, largest first; each group's batches in the
   // launch order of a fixed evaluation (by decreasing modelled work, dealt
   // to the XCDs)
+  // (small launches: every batch's lists in slices, as in a fixed evaluation)
+  double* spart = nullptr;
+  const int nsl = ensure_slices(g, kernel, &spart);
   if (spans.size() == 1) {
-    const std::vector<Dealt> d = deal_batches(g, g->ls[0], s, {{spans[0].first, order.data(), nb}});
+    const std::vector<Dealt> d =
+        deal_batches(g, g->ls[0], s, {{spans[0].first, order.data(), nb}}, nsl);
     run_p2p(t, g, g->ls[0], kernel, eps, spans[0].first, og, g->d_xmap + d[0].off, nb, out, s,
-            nullptr, 0, nullptr, g->d_xstart, d[0].xmax);
+            nullptr, 0, nullptr, g->d_xstart, d[0].xmax, nsl, spart);
   } else {
     std::sort(spans.begin(), spans.end(), [](const auto& a, const auto& b) {
       const double wa = (double)a.second.second * std::pow(a.first + 1.0, 3);
@@ -465,7 +469,7 @@ void evaluate_adaptive(bltc_tree t, bltc_targets g, int kernel, double eps,
     std::vector<DealGroup> dg;
     for (auto& sp : spans)
       dg.push_back({sp.first, order.data() + sp.second.first, sp.second.second});
-    const std::vector<Dealt> d = deal_batches(g, g->ls[0], s, dg);
+    const std::vector<Dealt> d = deal_batches(g, g->ls[0], s, dg, nsl);
     hipEvent_t ready = evs.make();
     hipchk(hipEventRecord(ready, s), "hipEventRecord");
     std::vector<hipEvent_t> done;
@@ -474,7 +478,7 @@ void evaluate_adaptive(bltc_tree t, bltc_targets g, int kernel, double eps,
       hipchk(hipStreamWaitEvent(ss, ready, 0), "hipStreamWaitEvent");
       run_p2p(t, g, g->ls[0], kernel, eps, spans[i].first, og, g->d_xmap + d[i].off,
               spans[i].second.second, out, ss, nullptr, 0, nullptr, g->d_xstart + 9 * i,
-              d[i].xmax);
+              d[i].xmax, nsl, spart);
       if (i + kSideStreams >= spans.size()) {   // last launch on this side stream
         hipEvent_t e = evs.make();
         hipchk(hipEventRecord(e, ss), "hipEventRecord");

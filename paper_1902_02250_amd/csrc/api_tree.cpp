@@ -476,7 +476,7 @@ void destroy_targets(bltc_targets g) {
   }
   dfree(g->d_feat); dfree(g->d_Y); dfree(g->d_pc); dfree(g->d_sc);
   dfree(g->d_choice); dfree(g->d_bmap); dfree(g->d_theta_b); dfree(g->d_spos);
-  dfree(g->d_xmap); dfree(g->d_xstart);
+  dfree(g->d_xmap); dfree(g->d_xstart); dfree(g->d_spart);
   dfree(g->d_ufb); dfree(g->d_sgeo); dfree(g->d_sflags);
   dfree(g->ls_samp.cnt); dfree(g->ls_samp.ptr); dfree(g->ls_samp.pids); dfree(g->ls_samp.dids);
   dfree(g->d_wt); dfree(g->d_usq); dfree(g->d_contrib); dfree(g->d_part); dfree(g->d_sums); dfree(g->d_lam);

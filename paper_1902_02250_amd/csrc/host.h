@@ -5,6 +5,7 @@
 #pragma once
 #include <hip/hip_runtime_api.h>
 
+#include <algorithm>
 #include <exception>
 #include <new>
 #include <string>
@@ -184,10 +185,34 @@ void derive_used_degrees(bltc_tree t, bltc_targets g, const bltc::ListSet& L, in
 bltc::P2PArgs p2p_args(bltc_tree t, bltc_targets g, const bltc::ListSet& L, int kernel,
                        double eps, int degree, const bltc_options& o, const int32_t* bmap,
                        int64_t nmap, double* out);
+// slices > 1 (with spart of slices_bytes): each batch's lists in that many
+// parts, summed in order by launch_slice_reduce after the launch.
 void run_p2p(bltc_tree t, bltc_targets g, const bltc::ListSet& L, int kernel, double eps,
              int degree, const bltc_options& o, const int32_t* bmap, int64_t nmap,
              double* out, hipStream_t s, const int4* split = nullptr, int64_t nsplit = 0,
-             double* partial = nullptr, const int32_t* xstart = nullptr, int32_t xmax = 0);
+             double* partial = nullptr, const int32_t* xstart = nullptr, int32_t xmax = 0,
+             int slices = 1, double* spart = nullptr);
+// Slices per batch of an evaluation over the nb batches of a targets handle
+// (wpb waves of 64 targets each, odim outputs): a launch of fewer waves than
+// kSliceWaves (4 per SIMD) splits every batch's lists into that many parts,
+// at most kMaxSlices, with partial sums of at most kSliceBytes.  A function
+// of the handle and the kernel alone, so a batch gets the same sums in every
+// evaluation entry point.
+constexpr int64_t kSliceWaves = 4096;
+constexpr int kMaxSlices = 8;
+constexpr int64_t kSliceBytes = int64_t(12) << 20;
+inline int slices_for(int64_t nb, int wpb, int odim) {
+  const int64_t w = nb * wpb;
+  if (w <= 0 || w >= kSliceWaves) return 1;
+  int64_t k = (kSliceWaves + w - 1) / w;
+  k = std::min<int64_t>(k, kMaxSlices);
+  k = std::min<int64_t>(k, kSliceBytes / (w * odim * 64 * (int64_t)sizeof(double)));
+  return (int)std::max<int64_t>(k, 1);
+}
+inline int64_t slices_bytes(int64_t nb, int wpb, int odim, int slices) {
+  return nb * wpb * slices * odim * 64 * (int64_t)sizeof(double);
+}
+int ensure_slices(bltc_targets g, int kernel, double** spart);
 // The order of an evaluation launch's batches: by decreasing modelled work
 // (see deal_batches in api_eval.cpp), dealt to the 8 XCDs in turn.  One
 // group per launch: its degree and its batches (host ids, or NULL for all
@@ -203,7 +228,7 @@ struct Dealt {
   int32_t xmax;         // longest XCD range in waves
 };
 std::vector<Dealt> deal_batches(bltc_targets g, const bltc::ListSet& L, hipStream_t s,
-                                const std::vector<DealGroup>& groups);
+                                const std::vector<DealGroup>& groups, int slices = 1);
 void evaluate_tree(bltc_tree t, bltc_targets g, int kernel, double eps, int degree,
                    double theta, const bltc_options& o, double* out, hipStream_t s);
 // The checks shared by the entry points that evaluate a built tree: handles,

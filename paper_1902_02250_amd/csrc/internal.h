@@ -168,10 +168,19 @@ struct P2PArgs {
   const int4* split = nullptr;
   int64_t nsplit = 0;
   double* partial = nullptr;
-  // work-balanced XCD ranges (NULL: equal counts): XCD x runs the waves
-  // [xstart[x], xstart[x + 1]); xmax the longest range (host value)
+  // XCD ranges of the launch order (NULL: contiguous equal counts): XCD x
+  // runs the waves [xstart[x], xstart[x + 1]); xmax the longest range (host
+  // value)
   const int32_t* xstart = nullptr;
   int32_t xmax = 0;
+  // slices per batch (without split): slices > 1 gives each (batch, wave of
+  // targets) that many waves, slice j taking the j-th of `slices` equal parts
+  // (by entries) of the batch's proxy list and of its direct list (cut at
+  // run boundaries of contiguous leaves), and
+  // writing unscaled FP64 sums to spart[((b wpb + wv) slices + j)][odim][64];
+  // launch_slice_reduce then adds the slices in order and scatters
+  int32_t slices = 1;
+  double* spart = nullptr;
 };
 
 // Cluster-cluster variant: interpolation of the grid potentials to targets.
@@ -424,6 +433,12 @@ hipError_t launch_split_reduce(const int32_t* sptr, const int32_t* bmap, int64_t
                                hipStream_t s);
 hipError_t launch_p2p(int kernel, int precision, int degree,
                       const P2PArgs& a, hipStream_t s);
+// out[c][tperm[t]] = scale * sum over j < slices of spart[((b wpb + wv)
+// slices + j)][c][t - bptr[b] - 64 wv] for every target t of the batches
+// b = bmap[0..n) (or 0..n-1) in wave wv of 64 targets.
+hipError_t launch_slice_reduce(const int32_t* bmap, int64_t n, const int32_t* bptr, int wpb,
+                               int slices, const int32_t* tperm, const double* spart, int odim,
+                               double su, double sw, int64_t m, double* out, hipStream_t s);
 hipError_t launch_direct(int kernel, int precision, const double* tx,
                          const double* ty, const double* tz,
                          const int64_t* idx, int64_t k, const double* sx,
@@ -539,6 +554,7 @@ struct bltc_targets_s {
   int32_t* d_choice = nullptr; // [nb]
   int32_t* d_bmap = nullptr;   // [nb]
   int32_t* d_xmap = nullptr;   // [nb] batch order of the evaluation launches (per group)
+  double* d_spart = nullptr;   // slice partial sums (small launches)
   int32_t* d_xstart = nullptr; // [kMaxDegree + 1][9] XCD ranges in waves (per group)
   std::vector<int32_t> h_xmap, h_xstart;   // their host copies (sources of the uploads)
   std::vector<int32_t> h_cnt;  // list counts read back for the order

@@ -399,7 +399,8 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void k_p2p(
     const float* __restrict__ w32, const double* __restrict__ w64, int64_t n,
     double eps, int poly_p, double poly_c, double su, double sw,
     double* __restrict__ out, DegTables dt, const int4* __restrict__ split,
-    double* __restrict__ partial, const int32_t* __restrict__ xstart) {
+    double* __restrict__ partial, const int32_t* __restrict__ xstart, int nslice,
+    double* __restrict__ spart) {
   constexpr int OD = Dims<KERN>::OD;
   constexpr int WD = Dims<KERN>::WD;
   constexpr int NK = N1 * N1 * N1;
@@ -423,7 +424,7 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void k_p2p(
     gw = xcd_block(blockIdx.x, nblk) * kWavesPerBlock + wid;
   }
   if (gw >= nwaves) return;
-  int b, wv, pbeg, pend, dbeg, dend;
+  int b, wv, sl = 0, pbeg, pend, dbeg, dend;
   if (split) {   // a slice of a batch's proxy list or of its direct list
     const int4 sp = split[gw];
     b = sp.x;
@@ -433,13 +434,24 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void k_p2p(
     pend = far ? sp.z : 0;
     dbeg = far ? 0 : sp.y;
     dend = far ? 0 : sp.z;
-  } else {
-    b = bmap ? bmap[gw / wpb] : gw / wpb;
-    wv = gw % wpb;
-    pbeg = pptr[b];
-    pend = pptr[b + 1];
-    dbeg = dptr[b];
-    dend = dptr[b + 1];
+  } else {   // slice sl of nslice equal parts of both lists (all of them at 1)
+    const int per = wpb * nslice;
+    const int bi = gw / per, rem = gw % per;
+    b = bmap ? bmap[bi] : bi;
+    wv = rem / nslice;
+    sl = rem % nslice;
+    const int p0 = pptr[b], p1 = pptr[b + 1], d0 = dptr[b], d1 = dptr[b + 1];
+    pbeg = p0 + (int)((int64_t)(p1 - p0) * sl / nslice);
+    pend = p0 + (int)((int64_t)(p1 - p0) * (sl + 1) / nslice);
+    // direct-list cuts move forward to the next run boundary, so every run
+    // of contiguous leaves, and with it every tile of 64 sources, is the
+    // unsliced one: slices change only the order of the FP64 sums
+    auto snap = [&](int e) {
+      while (e > d0 && e < d1 && range[dids[e]].x == range[dids[e - 1]].y) ++e;
+      return e;
+    };
+    dbeg = nslice > 1 ? snap(d0 + (int)((int64_t)(d1 - d0) * sl / nslice)) : d0;
+    dend = nslice > 1 ? snap(d0 + (int)((int64_t)(d1 - d0) * (sl + 1) / nslice)) : d1;
   }
   const int t0 = bptr[b] + wv * 64, t1 = bptr[b + 1];
   if (t0 >= t1) return;
@@ -581,6 +593,10 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void k_p2p(
     if (split) {
 #pragma unroll
       for (int c = 0; c < OD; ++c) partial[((int64_t)gw * OD + c) * 64 + lane] = acc.get(c);
+    } else if (nslice > 1) {
+      const int64_t u = ((int64_t)b * wpb + wv) * nslice + sl;
+#pragma unroll
+      for (int c = 0; c < OD; ++c) spart[(u * OD + c) * 64 + lane] = acc.get(c);
     } else {
       const int64_t o = tperm[ti];
 #pragma unroll
@@ -609,9 +625,35 @@ __global__ void k_split_reduce(const int32_t* __restrict__ sptr, const int32_t* 
   }
 }
 
+// Sums the slices of each (batch, wave) in slice order and scatters.
+__global__ void k_slice_reduce(const int32_t* __restrict__ bmap, int64_t n,
+                               const int32_t* __restrict__ bptr, int wpb, int nslice,
+                               const int32_t* __restrict__ tperm,
+                               const double* __restrict__ spart, int od, double su, double sw,
+                               int64_t m, double* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n * wpb * 64) return;
+  const int64_t r = i / (64 * wpb);
+  const int wv = (int)(i / 64 % wpb);
+  const int lane = (int)(i % 64);
+  const int b = bmap ? bmap[r] : (int)r;
+  const int t = bptr[b] + wv * 64 + lane;
+  if (t >= bptr[b + 1]) return;
+  const int64_t o = tperm[t];
+  const int64_t u0 = ((int64_t)b * wpb + wv) * nslice;
+  for (int c = 0; c < od; ++c) {
+    double v = 0.0;
+    for (int j = 0; j < nslice; ++j) v += spart[((u0 + j) * od + c) * 64 + lane];
+    out[c * m + o] = v * (c < 3 ? su : sw);
+  }
+}
+
 template <int KERN, int PREC, int N1>
 hipError_t run_p2p(const P2PArgs& a, hipStream_t s) {
-  const int64_t nw64 = a.split ? a.nsplit : (a.bmap ? a.nmap : a.nb) * (int64_t)a.wpb;
+  const int nslice = a.split ? 1 : a.slices;
+  if (nslice < 1 || (nslice > 1 && !a.spart)) return hipErrorInvalidValue;
+  const int64_t nw64 =
+      a.split ? a.nsplit : (a.bmap ? a.nmap : a.nb) * (int64_t)a.wpb * nslice;
   if (nw64 == 0) return hipSuccess;
   if (nw64 > 0x7fffffff - kWavesPerBlock) return hipErrorInvalidValue;
   const int nwaves = (int)nw64;
@@ -633,7 +675,7 @@ hipError_t run_p2p(const P2PArgs& a, hipStream_t s) {
                        a.dptr, a.dids, a.range, a.grid, (const float*)a.fhat,
                        (const double*)a.fhat, a.ys, a.w32, a.w64, a.n, a.eps,
                        a.poly_p, a.poly_c, a.scale_u, a.scale_w, a.out, dt, a.split, a.partial,
-                       a.xstart);
+                       a.xstart, nslice, a.spart);
   };
   if (rule) {
     if (zeps)
@@ -699,6 +741,16 @@ hipError_t launch_split_reduce(const int32_t* sptr, const int32_t* bmap, int64_t
   if (nr == 0) return hipSuccess;
   hipLaunchKernelGGL(k_split_reduce, dim3((unsigned)((nr * 64 + 255) / 256)), dim3(256), 0, s,
                      sptr, bmap, nr, bptr, tperm, partial, odim, su, sw, m, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_slice_reduce(const int32_t* bmap, int64_t n, const int32_t* bptr, int wpb,
+                               int slices, const int32_t* tperm, const double* spart, int odim,
+                               double su, double sw, int64_t m, double* out, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const int64_t th = n * wpb * 64;
+  hipLaunchKernelGGL(k_slice_reduce, dim3((unsigned)((th + 255) / 256)), dim3(256), 0, s, bmap,
+                     n, bptr, wpb, slices, tperm, spart, odim, su, sw, m, out);
   return hipGetLastError();
 }
 
