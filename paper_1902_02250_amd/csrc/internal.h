@@ -175,8 +175,8 @@ struct P2PArgs {
   int32_t xmax = 0;
   // slices per batch (without split): slices > 1 gives each (batch, wave of
   // targets) that many waves, slice j taking the j-th of `slices` equal parts
-  // (by entries) of the batch's proxy list and of its direct list (cut at
-  // run boundaries of contiguous leaves), and
+  // of the batch's proxy list (by entries) and of its near-field tiles (64
+  // sources each, along the runs of contiguous leaves), and
   // writing unscaled FP64 sums to spart[((b wpb + wv) slices + j)][odim][64];
   // launch_slice_reduce then adds the slices in order and scatters
   int32_t slices = 1;

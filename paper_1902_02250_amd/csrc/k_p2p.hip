@@ -443,15 +443,9 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void k_p2p(
     const int p0 = pptr[b], p1 = pptr[b + 1], d0 = dptr[b], d1 = dptr[b + 1];
     pbeg = p0 + (int)((int64_t)(p1 - p0) * sl / nslice);
     pend = p0 + (int)((int64_t)(p1 - p0) * (sl + 1) / nslice);
-    // direct-list cuts move forward to the next run boundary, so every run
-    // of contiguous leaves, and with it every tile of 64 sources, is the
-    // unsliced one: slices change only the order of the FP64 sums
-    auto snap = [&](int e) {
-      while (e > d0 && e < d1 && range[dids[e]].x == range[dids[e - 1]].y) ++e;
-      return e;
-    };
-    dbeg = nslice > 1 ? snap(d0 + (int)((int64_t)(d1 - d0) * sl / nslice)) : d0;
-    dend = nslice > 1 ? snap(d0 + (int)((int64_t)(d1 - d0) * (sl + 1) / nslice)) : d1;
+    // the direct list is sliced by tiles in the near-field loop
+    dbeg = d0;
+    dend = d1;
   }
   const int t0 = bptr[b] + wv * 64, t1 = bptr[b + 1];
   if (t0 >= t1) return;
@@ -510,6 +504,28 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void k_p2p(
   Runs it{dids, range, dbeg, dend, 0, 0};
   bool have = it.next();
   int s0 = it.rb, re = it.re;
+  // slice sl of nslice: the tiles [tl, th) of the batch's tiles (each run of
+  // contiguous leaves cut into tiles of 64 sources from its start), so every
+  // tile is the unsliced one and slices change only the order of the FP64
+  // sums
+  int tiles_left = 0x7fffffff;
+  if (nslice > 1 && !split) {
+    int nt = 0;
+    for (Runs c{dids, range, dbeg, dend, 0, 0}; c.next();) nt += (c.re - c.rb + 63) >> 6;
+    const int tl = (int)((int64_t)nt * sl / nslice);
+    tiles_left = (int)((int64_t)nt * (sl + 1) / nslice) - tl;
+    if (tiles_left == 0) {
+      have = false;
+    } else {
+      int t = 0;   // tiles before the current run
+      while (have && t + ((it.re - it.rb + 63) >> 6) <= tl) {
+        t += (it.re - it.rb + 63) >> 6;
+        have = it.next();
+      }
+      s0 = it.rb + 64 * (tl - t);
+      re = it.re;
+    }
+  }
   double py0 = 0, py1 = 0, py2 = 0;   // prefetched source (FP64 position)
   T pf[WD];                           // and weights
 #pragma unroll
@@ -546,8 +562,8 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void k_p2p(
     }
     wave_lds_sync();
     int ns0 = s0 + 64, nre = re;
-    bool nhave = true;
-    if (ns0 >= re) {
+    bool nhave = --tiles_left > 0;
+    if (nhave && ns0 >= re) {
       nhave = it.next();
       ns0 = it.rb;
       nre = it.re;
