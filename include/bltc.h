@@ -420,8 +420,11 @@ int bltc_judge_samples(bltc_tree t, bltc_targets g, int32_t kernel, double eps,
  *  4. Lists at each batch's theta (and the separation rule's degrees);
  *     modified weights of every top degree in use and, under the rule, of
  *     the lower degrees derived from each top degree's (so a batch's result
- *     equals the fixed evaluation at its candidate); evaluation grouped by
- *     the batches' top degrees, the groups running concurrently.
+ *     equals the fixed evaluation at its candidate: bit for bit when its
+ *     group's launch slices its lists as the fixed one does, else up to the
+ *     order of the FP64 sums); evaluation grouped by the batches' top
+ *     degrees, the groups running concurrently, a group of under 4096 waves
+ *     slicing every batch's lists (more finely than a full evaluation).
  *  5. The judge's estimate E^2 = sum_i G_i |u - u_fb|^2 / sum_i G_i |u_fb|^2
  *     over the samples (G_i the targets of sample i's group); when it
  *     exceeds (0.8 tol)^2, the samples with the largest terms, just enough

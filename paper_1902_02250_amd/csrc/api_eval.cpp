@@ -198,19 +198,14 @@ void run_p2p(bltc_tree t, bltc_targets g, const bltc::ListSet& L, int kernel, do
   ev.stop();
 }
 
-// The slice count of evaluations on g with this kernel, and its partial
-// buffer (grown once to the larger of the two output widths' needs).
-int ensure_slices(bltc_targets g, int kernel, double** spart) {
-  const int wpb = (g->batch_size + bltc::kWave - 1) / bltc::kWave;
-  const int k = slices_for(g->nb, wpb, odim_of(kernel));
-  *spart = nullptr;
-  if (k > 1) {
-    const int64_t b3 = slices_bytes(g->nb, wpb, 3, slices_for(g->nb, wpb, 3));
-    const int64_t b6 = slices_bytes(g->nb, wpb, 6, slices_for(g->nb, wpb, 6));
-    ensure_alloc(g->d_spart, (size_t)(std::max(b3, b6) / (int64_t)sizeof(double)));
-    *spart = g->d_spart;
+double* spart_reserve(bltc_targets g, int64_t doubles) {
+  if (doubles > g->spart_cap) {
+    dfree(g->d_spart);
+    g->spart_cap = 0;
+    g->d_spart = dalloc<double>((size_t)doubles);
+    g->spart_cap = doubles;
   }
-  return k;
+  return g->d_spart;
 }
 
 void evaluate_tree(bltc_tree t, bltc_targets g, int kernel, double eps,
@@ -222,9 +217,11 @@ void evaluate_tree(bltc_tree t, bltc_targets g, int kernel, double eps,
   const bltc::Rule rule = make_rule(theta, degree, o.deg_min);
   build_lists(t, g, theta, nullptr, g->ls[0], s, &np, &nd, &rule);
   derive_used_degrees(t, g, g->ls[0], rule.deg_min, {{degree, {nullptr, g->nb}}}, s);
-  double* spart = nullptr;
-  const int k = ensure_slices(g, kernel, &spart);
-  const std::vector<Dealt> d = deal_batches(g, g->ls[0], s, {{degree, nullptr, g->nb}}, k);
+  const int wpb = (g->batch_size + bltc::kWave - 1) / bltc::kWave;
+  const int k = slices_for(g->nb, wpb, odim_of(kernel));
+  double* spart =
+      k > 1 ? spart_reserve(g, slices_bytes(g->nb, wpb, odim_of(kernel), k) / 8) : nullptr;
+  const std::vector<Dealt> d = deal_batches(g, g->ls[0], s, {{degree, nullptr, g->nb, k}});
   run_p2p(t, g, g->ls[0], kernel, eps, degree, o, g->d_xmap + d[0].off, g->nb, out, s, nullptr,
           0, nullptr, g->d_xstart, d[0].xmax, k, spart);
 }
@@ -243,7 +240,7 @@ void evaluate_tree(bltc_tree t, bltc_targets g, int kernel, double eps,
 // modelled time (batches within 1/4096 of it count as equal), linear in the
 // batches, since the device waits for it.
 std::vector<Dealt> deal_batches(bltc_targets g, const bltc::ListSet& L, hipStream_t s,
-                                const std::vector<DealGroup>& groups, int slices) {
+                                const std::vector<DealGroup>& groups) {
   constexpr int kLevels = 4096;
   const int64_t nb = g->nb;
   std::vector<Dealt> res(groups.size(), Dealt{0, 0});
@@ -258,13 +255,13 @@ std::vector<Dealt> deal_batches(bltc_targets g, const bltc::ListSet& L, hipStrea
   ensure_alloc(g->d_xstart, 9 * (bltc::kMaxDegree + 1));
   g->h_xmap.resize(total);
   g->h_xstart.assign(9 * groups.size(), 0);
-  // waves per batch in the launch: its waves of 64 targets times its slices
-  const int wpb = (g->batch_size + bltc::kWave - 1) / bltc::kWave * slices;
+  const int wpb0 = (g->batch_size + bltc::kWave - 1) / bltc::kWave;
   std::vector<double> w;
   std::vector<int32_t> ord, lev, first(kLevels + 1);
   int64_t off = 0;
   for (size_t i = 0; i < groups.size(); ++i) {
     const DealGroup& gr = groups[i];
+    const int wpb = wpb0 * gr.slices;   // waves per batch: of 64 targets, times slices
     const double n1 = gr.degree + 1;
     const double per_cluster = (0.69 * n1 + 0.5) * n1 * n1 + 2.5;
     w.resize(gr.n);

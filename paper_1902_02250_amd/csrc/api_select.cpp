@@ -452,12 +452,15 @@ void evaluate_adaptive(bltc_tree t, bltc_targets g, int kernel, double eps,
   // concurrently on side streams, largest first; each group's batches in the
   // launch order of a fixed evaluation (by decreasing modelled work, dealt
   // to the XCDs)
-  // (small launches: every batch's lists in slices, as in a fixed evaluation)
-  double* spart = nullptr;
-  const int nsl = ensure_slices(g, kernel, &spart);
+  // (a launch under 4 waves per SIMD slices its batches' lists: a lone group
+  // as a fixed evaluation, bit for bit; a small degree group more finely)
+  const int wpb = (g->batch_size + bltc::kWave - 1) / bltc::kWave;
+  const int od = odim_of(kernel);
   if (spans.size() == 1) {
+    const int nsl = slices_for(nb, wpb, od);
+    double* spart = nsl > 1 ? spart_reserve(g, slices_bytes(nb, wpb, od, nsl) / 8) : nullptr;
     const std::vector<Dealt> d =
-        deal_batches(g, g->ls[0], s, {{spans[0].first, order.data(), nb}}, nsl);
+        deal_batches(g, g->ls[0], s, {{spans[0].first, order.data(), nb, nsl}});
     run_p2p(t, g, g->ls[0], kernel, eps, spans[0].first, og, g->d_xmap + d[0].off, nb, out, s,
             nullptr, 0, nullptr, g->d_xstart, d[0].xmax, nsl, spart);
   } else {
@@ -467,9 +470,16 @@ void evaluate_adaptive(bltc_tree t, bltc_targets g, int kernel, double eps,
       return wa > wb;
     });
     std::vector<DealGroup> dg;
-    for (auto& sp : spans)
-      dg.push_back({sp.first, order.data() + sp.second.first, sp.second.second});
-    const std::vector<Dealt> d = deal_batches(g, g->ls[0], s, dg, nsl);
+    std::vector<int64_t> soff;   // each group's slice sums in the shared buffer
+    int64_t stot = 0;
+    for (auto& sp : spans) {
+      const int k = slices_for(sp.second.second, wpb, od);
+      dg.push_back({sp.first, order.data() + sp.second.first, sp.second.second, k});
+      soff.push_back(stot);
+      if (k > 1) stot += slices_bytes(sp.second.second, wpb, od, k) / 8;
+    }
+    double* spart = stot > 0 ? spart_reserve(g, stot) : nullptr;
+    const std::vector<Dealt> d = deal_batches(g, g->ls[0], s, dg);
     hipEvent_t ready = evs.make();
     hipchk(hipEventRecord(ready, s), "hipEventRecord");
     std::vector<hipEvent_t> done;
@@ -478,7 +488,7 @@ void evaluate_adaptive(bltc_tree t, bltc_targets g, int kernel, double eps,
       hipchk(hipStreamWaitEvent(ss, ready, 0), "hipStreamWaitEvent");
       run_p2p(t, g, g->ls[0], kernel, eps, spans[i].first, og, g->d_xmap + d[i].off,
               spans[i].second.second, out, ss, nullptr, 0, nullptr, g->d_xstart + 9 * i,
-              d[i].xmax, nsl, spart);
+              d[i].xmax, dg[i].slices, dg[i].slices > 1 ? spart + soff[i] : nullptr);
       if (i + kSideStreams >= spans.size()) {   // last launch on this side stream
         hipEvent_t e = evs.make();
         hipchk(hipEventRecord(e, ss), "hipEventRecord");

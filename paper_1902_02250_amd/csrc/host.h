@@ -192,12 +192,14 @@ void run_p2p(bltc_tree t, bltc_targets g, const bltc::ListSet& L, int kernel, do
              double* out, hipStream_t s, const int4* split = nullptr, int64_t nsplit = 0,
              double* partial = nullptr, const int32_t* xstart = nullptr, int32_t xmax = 0,
              int slices = 1, double* spart = nullptr);
-// Slices per batch of an evaluation over the nb batches of a targets handle
-// (wpb waves of 64 targets each, odim outputs): a launch of fewer waves than
-// kSliceWaves (4 per SIMD) splits every batch's lists into that many parts,
-// at most kMaxSlices, with partial sums of at most kSliceBytes.  A function
-// of the handle and the kernel alone, so a batch gets the same sums in every
-// evaluation entry point.
+// Slices per batch of a launch over nb batches (wpb waves of 64 targets
+// each, odim outputs): a launch of fewer waves than kSliceWaves (4 per SIMD)
+// splits every batch's lists into that many parts, at most kMaxSlices, with
+// partial sums of at most kSliceBytes.  A function of the launch's size and
+// the kernel alone: the fixed and allocation-free evaluations of a targets
+// handle slice alike (bit for bit equal); a degree group of the per-batch
+// selection, launched alone, may take more slices than a full evaluation,
+// which changes only the order of its FP64 sums.
 constexpr int64_t kSliceWaves = 4096;
 constexpr int kMaxSlices = 8;
 constexpr int64_t kSliceBytes = int64_t(12) << 20;
@@ -212,7 +214,8 @@ inline int slices_for(int64_t nb, int wpb, int odim) {
 inline int64_t slices_bytes(int64_t nb, int wpb, int odim, int slices) {
   return nb * wpb * slices * odim * 64 * (int64_t)sizeof(double);
 }
-int ensure_slices(bltc_targets g, int kernel, double** spart);
+// The slice partial-sum buffer of g, grown to at least `doubles`.
+double* spart_reserve(bltc_targets g, int64_t doubles);
 // The order of an evaluation launch's batches: by decreasing modelled work
 // (see deal_batches in api_eval.cpp), dealt to the 8 XCDs in turn.  One
 // group per launch: its degree and its batches (host ids, or NULL for all
@@ -222,13 +225,14 @@ struct DealGroup {
   int degree;
   const int32_t* ids;   // host, or NULL: batches 0 .. n-1
   int64_t n;
+  int slices = 1;       // slices per batch of the group's launch
 };
 struct Dealt {
   int64_t off;          // in g->d_xmap
   int32_t xmax;         // longest XCD range in waves
 };
 std::vector<Dealt> deal_batches(bltc_targets g, const bltc::ListSet& L, hipStream_t s,
-                                const std::vector<DealGroup>& groups, int slices = 1);
+                                const std::vector<DealGroup>& groups);
 void evaluate_tree(bltc_tree t, bltc_targets g, int kernel, double eps, int degree,
                    double theta, const bltc_options& o, double* out, hipStream_t s);
 // The checks shared by the entry points that evaluate a built tree: handles,

@@ -177,8 +177,9 @@ struct P2PArgs {
   // targets) that many waves, slice j taking the j-th of `slices` equal parts
   // of the batch's proxy list (by entries) and of its near-field tiles (64
   // sources each, along the runs of contiguous leaves), and
-  // writing unscaled FP64 sums to spart[((b wpb + wv) slices + j)][odim][64];
-  // launch_slice_reduce then adds the slices in order and scatters
+  // writing unscaled FP64 sums to spart[((i wpb + wv) slices + j)][odim][64]
+  // for the batch at launch position i (bmap[i], or i); launch_slice_reduce
+  // then adds the slices in order and scatters
   int32_t slices = 1;
   double* spart = nullptr;
 };
@@ -433,9 +434,9 @@ hipError_t launch_split_reduce(const int32_t* sptr, const int32_t* bmap, int64_t
                                hipStream_t s);
 hipError_t launch_p2p(int kernel, int precision, int degree,
                       const P2PArgs& a, hipStream_t s);
-// out[c][tperm[t]] = scale * sum over j < slices of spart[((b wpb + wv)
+// out[c][tperm[t]] = scale * sum over j < slices of spart[((i wpb + wv)
 // slices + j)][c][t - bptr[b] - 64 wv] for every target t of the batches
-// b = bmap[0..n) (or 0..n-1) in wave wv of 64 targets.
+// b = bmap[i], i < n (or b = i), in wave wv of 64 targets.
 hipError_t launch_slice_reduce(const int32_t* bmap, int64_t n, const int32_t* bptr, int wpb,
                                int slices, const int32_t* tperm, const double* spart, int odim,
                                double su, double sw, int64_t m, double* out, hipStream_t s);
@@ -554,7 +555,8 @@ struct bltc_targets_s {
   int32_t* d_choice = nullptr; // [nb]
   int32_t* d_bmap = nullptr;   // [nb]
   int32_t* d_xmap = nullptr;   // [nb] batch order of the evaluation launches (per group)
-  double* d_spart = nullptr;   // slice partial sums (small launches)
+  double* d_spart = nullptr;   // slice partial sums (small launches), grown on demand
+  int64_t spart_cap = 0;       // doubles
   int32_t* d_xstart = nullptr; // [kMaxDegree + 1][9] XCD ranges in waves (per group)
   std::vector<int32_t> h_xmap, h_xstart;   // their host copies (sources of the uploads)
   std::vector<int32_t> h_cnt;  // list counts read back for the order

@@ -424,7 +424,7 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void k_p2p(
     gw = xcd_block(blockIdx.x, nblk) * kWavesPerBlock + wid;
   }
   if (gw >= nwaves) return;
-  int b, wv, sl = 0, pbeg, pend, dbeg, dend;
+  int b, bi = 0, wv, sl = 0, pbeg, pend, dbeg, dend;
   if (split) {   // a slice of a batch's proxy list or of its direct list
     const int4 sp = split[gw];
     b = sp.x;
@@ -436,7 +436,8 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void k_p2p(
     dend = far ? 0 : sp.z;
   } else {   // slice sl of nslice equal parts of both lists (all of them at 1)
     const int per = wpb * nslice;
-    const int bi = gw / per, rem = gw % per;
+    bi = gw / per;
+    const int rem = gw % per;
     b = bmap ? bmap[bi] : bi;
     wv = rem / nslice;
     sl = rem % nslice;
@@ -610,7 +611,7 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void k_p2p(
 #pragma unroll
       for (int c = 0; c < OD; ++c) partial[((int64_t)gw * OD + c) * 64 + lane] = acc.get(c);
     } else if (nslice > 1) {
-      const int64_t u = ((int64_t)b * wpb + wv) * nslice + sl;
+      const int64_t u = ((int64_t)bi * wpb + wv) * nslice + sl;   // by launch position
 #pragma unroll
       for (int c = 0; c < OD; ++c) spart[(u * OD + c) * 64 + lane] = acc.get(c);
     } else {
@@ -641,7 +642,8 @@ __global__ void k_split_reduce(const int32_t* __restrict__ sptr, const int32_t* 
   }
 }
 
-// Sums the slices of each (batch, wave) in slice order and scatters.
+// Sums the slices of each (launch position, wave) in slice order and
+// scatters to the targets of the batch at that position.
 __global__ void k_slice_reduce(const int32_t* __restrict__ bmap, int64_t n,
                                const int32_t* __restrict__ bptr, int wpb, int nslice,
                                const int32_t* __restrict__ tperm,
@@ -656,7 +658,7 @@ __global__ void k_slice_reduce(const int32_t* __restrict__ bmap, int64_t n,
   const int t = bptr[b] + wv * 64 + lane;
   if (t >= bptr[b + 1]) return;
   const int64_t o = tperm[t];
-  const int64_t u0 = ((int64_t)b * wpb + wv) * nslice;
+  const int64_t u0 = (r * wpb + wv) * nslice;
   for (int c = 0; c < od; ++c) {
     double v = 0.0;
     for (int j = 0; j < nslice; ++j) v += spart[((u0 + j) * od + c) * 64 + lane];
