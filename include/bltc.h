@@ -226,7 +226,7 @@ int bltc_evaluate_tree(bltc_tree t, bltc_targets g, int32_t kernel, double eps,
  * device memory (code under stream capture, tight serving loops, harnesses
  * that forbid hipMalloc).  Same arguments, checks and result as
  * bltc_evaluate_tree, bit for bit; the interaction lists, the walk flags,
- * the separation rule's degree mask and, for launches of fewer than 4096
+ * the separation rule's degree mask and, for launches of fewer than 8192
  * waves, the partial sums of the batches' list slices (at most 12 MiB) live
  * in a fixed device array of the
  * library (bltc_noalloc_scratch_bytes: 32 MiB, one copy per device the
@@ -423,7 +423,7 @@ int bltc_judge_samples(bltc_tree t, bltc_targets g, int32_t kernel, double eps,
  *     equals the fixed evaluation at its candidate: bit for bit when its
  *     group's launch slices its lists as the fixed one does, else up to the
  *     order of the FP64 sums); evaluation grouped by the batches' top
- *     degrees, the groups running concurrently, a group of under 4096 waves
+ *     degrees, the groups running concurrently, a group of under 8192 waves
  *     slicing every batch's lists (more finely than a full evaluation).
  *  5. The judge's estimate E^2 = sum_i G_i |u - u_fb|^2 / sum_i G_i |u_fb|^2
  *     over the samples (G_i the targets of sample i's group); when it

@@ -452,7 +452,7 @@ void evaluate_adaptive(bltc_tree t, bltc_targets g, int kernel, double eps,
   // concurrently on side streams, largest first; each group's batches in the
   // launch order of a fixed evaluation (by decreasing modelled work, dealt
   // to the XCDs)
-  // (a launch under 4 waves per SIMD slices its batches' lists: a lone group
+  // (a launch under 8 waves per SIMD slices its batches' lists: a lone group
   // as a fixed evaluation, bit for bit; a small degree group more finely)
   const int wpb = (g->batch_size + bltc::kWave - 1) / bltc::kWave;
   const int od = odim_of(kernel);

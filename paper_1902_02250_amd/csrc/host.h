@@ -193,15 +193,15 @@ void run_p2p(bltc_tree t, bltc_targets g, const bltc::ListSet& L, int kernel, do
              double* partial = nullptr, const int32_t* xstart = nullptr, int32_t xmax = 0,
              int slices = 1, double* spart = nullptr);
 // Slices per batch of a launch over nb batches (wpb waves of 64 targets
-// each, odim outputs): a launch of fewer waves than kSliceWaves (4 per SIMD)
+// each, odim outputs): a launch of fewer waves than kSliceWaves (8 per SIMD)
 // splits every batch's lists into that many parts, at most kMaxSlices, with
 // partial sums of at most kSliceBytes.  A function of the launch's size and
 // the kernel alone: the fixed and allocation-free evaluations of a targets
 // handle slice alike (bit for bit equal); a degree group of the per-batch
 // selection, launched alone, may take more slices than a full evaluation,
 // which changes only the order of its FP64 sums.
-constexpr int64_t kSliceWaves = 4096;
-constexpr int kMaxSlices = 8;
+constexpr int64_t kSliceWaves = 8192;
+constexpr int kMaxSlices = 16;
 constexpr int64_t kSliceBytes = int64_t(12) << 20;
 inline int slices_for(int64_t nb, int wpb, int odim) {
   const int64_t w = nb * wpb;
