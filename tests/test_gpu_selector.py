@@ -200,6 +200,55 @@ def test_adaptive_is_per_batch_composition(torch, tmp_path, case):
                 assert _same_sums(out[:, t], ref[:, t]), (u, b)
 
 
+def test_adaptive_small_groups_sliced_finer(torch, tmp_path):
+    """200,000 clustered targets (3,125 batches): a full evaluation of this
+    size runs in at most a few slices per batch, while a degree group of the
+    per-batch selection, launched alone with a fraction of the batches,
+    slices its batches more finely.  Slices change only the order of the
+    FP64 sums, so every batch still equals the fixed evaluation at its
+    candidate to 1e-12, and the lone-group run mode stays bit for bit."""
+    n = 200000
+    src = inputs.points("mixture", n, 73)
+    w = inputs.weights(n, 73)
+    d_w = _d(torch, w)
+    T = bltc.Tree(_d(torch, src), 1000)
+    T.compute_weights(d_w, 4)
+    G = bltc.Targets(_d(torch, src))
+    c = dict(src=src, w=w, T=T, G=G, d_w=d_w, ol=0)
+    k = selector.K
+    p = selector.glorot(k, seed=4)
+    p[-k:] = np.random.default_rng(5).uniform(-6.0, -4.0, k)
+    path = str(tmp_path / "rand_large.bin")
+    selector.write_model(path, p, np.zeros(12), np.full(12, 3.0), 0.0)
+    sel = bltc.Selector(path)
+    for tol in (1e-5, 1e-6, 1e-4):   # the first tolerance that mixes degrees
+        out, choice, stats, judge = bltc.evaluate_adaptive(T, G, "rotlet", 0.01, sel, tol, 8,
+                                                           0.6)
+        used = sorted(set(choice.tolist()))
+        if len({selector.CANDIDATES[u][0] for u in used if u >= 0}) >= 2:
+            break
+    degs = [selector.CANDIDATES[u][0] for u in used if u >= 0]
+    assert len(set(degs)) >= 2, used
+    per_deg = {d: int(np.sum([np.sum(choice == u) for u in used
+                              if u >= 0 and selector.CANDIDATES[u][0] == d])) for d in set(degs)}
+    assert min(per_deg.values()) <= G.nb // 2, per_deg   # a group of at most half the batches
+    out = out.cpu().numpy()
+    for u in used:
+        nd, th = selector.CANDIDATES[u] if u >= 0 else (8, 0.6)
+        ref = _fixed(torch, c, nd, th, kernel="rotlet",
+                     deg_min=selector.DEG_MIN if u >= 0 else 0)
+        for b in np.where(choice == u)[0]:
+            t = _targets_of(G, b)
+            assert _same_sums(out[:, t], ref[:, t]), (u, b)
+    # one candidate for every batch: a single group, sliced as a full evaluation
+    out1, choice1, _, _ = bltc.evaluate_adaptive(T, G, "rotlet", 0.01, sel, tol, 8, 0.6,
+                                                 mode="run")
+    u1 = int(choice1[choice1 >= 0][0])
+    if np.all(choice1 == u1):
+        nd, th = selector.CANDIDATES[u1]
+        assert np.array_equal(out1.cpu().numpy(), _fixed(torch, c, nd, th, kernel="rotlet"))
+
+
 @pytest.mark.parametrize("dist,kernel,tol", [("mixture", "stokeslet", 1e-5),
                                              ("union", "rotlet", 1e-4)])
 def test_trained_selector_gain(torch, dist, kernel, tol):
